@@ -1,0 +1,203 @@
+/*
+ * hom.h -- C ABI of the MI355X FFT homogenization library (libhom.so).
+ *
+ * The library solves the thermomechanical cell problem of first-order
+ * homogenization with a microscopically homogeneous temperature (paper
+ * Sec. 2, equation "micro cell problem"): for a prescribed macro strain E and
+ * macro temperature theta, find the periodic strain field with mean E whose
+ * stress is divergence free, for a voxel microstructure whose phases follow
+ * the laws of Sec. 4 (isotropic linear thermoelasticity; the PA66
+ * thermo-viscoelastic / viscoplastic law). The internal variables are
+ * integrated by implicit Euler (Sec. 3.3, condensed incremental potential).
+ * It returns the effective quantities of Sec. 2: stress <sigma>, heat flux
+ * <q> = -<kappa grad theta> for a prescribed macro temperature gradient (the
+ * effective-conductivity problem of Sec. 6), dissipation <D_diss>, coupling
+ * term <D> and heat capacity <c0>.
+ *
+ * Discretization: trigonometric collocation on voxel centres (Moulinec-
+ * Suquet, cited in Sec. 5.2/5.4); for even grid sizes the Nyquist frequency
+ * of an axis gets a zero wave number.
+ *
+ * Conventions
+ *   - Strain / stress tensors cross the ABI as 6 components in the order
+ *     (11, 22, 33, 23, 13, 12) with tensorial (not engineering) shear.
+ *   - Units: MPa, s, K, m. Heat capacity c0 in MPa/K, conductivity in
+ *     W/(m K), temperature gradient in K/m, heat flux in W/m^2,
+ *     dissipation and coupling term in MPa/s.
+ *   - Voxel arrays are x-fastest: index = x + nx (y + ny z).
+ *   - Phase ids are uint8; phase id i follows laws[i].
+ *
+ * Ownership: the caller owns every array passed in or out. Setup copies the
+ * phases and law parameters to the device; a context owns its device memory
+ * until it is destroyed. Calls on one context are not thread safe.
+ *
+ * Errors: every int-returning call returns HOM_OK (0) or a negative code and
+ * keeps a message retrievable with hom_last_error / hom_batch_last_error.
+ * A failed increment does not commit: internal variables and the last
+ * converged strain field are left as they were.
+ */
+#ifndef HOM_H
+#define HOM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define HOM_OK 0
+#define HOM_E_ARG (-1)           /* invalid argument (sizes, ids, parameters) */
+#define HOM_E_OOM (-2)           /* device allocation failed */
+#define HOM_E_NOT_CONVERGED (-3) /* iteration limit reached before the tolerance */
+#define HOM_E_NAN (-4)           /* non-finite residual or breakdown */
+#define HOM_E_DEVICE (-5)        /* HIP runtime error */
+#define HOM_E_UNSUPPORTED (-6)   /* grid size or law combination not supported */
+
+#define HOM_MAX_MAXWELL 16
+#define HOM_MAX_LAWS 8
+
+typedef enum { HOM_LAW_THERMOELASTIC = 1, HOM_LAW_PA66 = 2 } hom_law_kind;
+
+/* Grid: n[0] = nx (fastest), n[1] = ny, n[2] = nz; len = cell edge lengths
+ * (only their ratios matter). Each n must be one of 16, 24, 32, 48, 64, 96,
+ * 128, 256. */
+typedef struct {
+  int32_t n[3];
+  double len[3];
+} hom_grid;
+
+/* Constitutive law of one phase (paper Sec. 4).
+ * Thermoelastic: E, nu, alpha0, kappa0, c0, theta0 (stress-free temperature).
+ * PA66: additionally n_maxwell branches (E_i, log10 of tau_i in s), WLF
+ * constants C1, C2 [K], theta_ref, yield stress sigma_y0, hardening
+ * H = Gamma(theta, beta1) k_h eps_p^n_h, viscosity eta0 and exponent m (>= 1),
+ * softening exponents beta1, beta2. At most one PA66 law per setup. */
+typedef struct {
+  int32_t kind;
+  double E, nu, alpha0, kappa0, c0, theta0;
+  int32_t n_maxwell;
+  double E_i[HOM_MAX_MAXWELL];
+  double log10_tau_i[HOM_MAX_MAXWELL];
+  double C1, C2, theta_ref, sigma_y0, k_h, n_h, eta0, m, beta1, beta2;
+} hom_law;
+
+#define HOM_SCHEME_BASIC 0     /* Moulinec-Suquet fixed point, isotropic reference medium */
+#define HOM_SCHEME_NEWTON_CG 1 /* inexact Newton with CG on the projected tangent system */
+#define HOM_FP64 0             /* all fields in FP64 */
+#define HOM_FP32 1             /* FP32 fields; FP64 reductions, CG scalars, return mapping and state */
+
+typedef struct {
+  int32_t scheme;      /* HOM_SCHEME_* */
+  int32_t precision;   /* HOM_FP64 / HOM_FP32 */
+  double tol;          /* relative residual tolerance (mechanics) */
+  double thermal_tol;  /* relative tolerance of the conduction problem; 0 => tol */
+  int32_t max_iter;    /* basic: iterations; Newton: residual evaluations; 0 => default */
+  int32_t max_krylov;  /* CG iterations per Newton step; 0 => default */
+  int32_t chunk;       /* solver iterations launched between host checks; 0 => default */
+  int32_t use_graph;   /* 1: replay chunks as captured hipGraphs */
+  int32_t profile;     /* 1: time every kernel launch with HIP events */
+  int32_t autotune;    /* 1: time the tile choices of the y/z passes at setup */
+  void* stream;        /* hipStream_t to run on; NULL => a stream owned by the context */
+} hom_options;
+
+/* Macroscopic temperature input: theta [K] and its gradient [K/m]. */
+typedef struct {
+  double theta;
+  double grad[3];
+} hom_macro_temp;
+
+typedef struct {
+  double stress[6];      /* <sigma>, components (11,22,33,23,13,12) */
+  double heat_flux[3];   /* <q> = -<kappa g> */
+  double dissipation;    /* <D_diss> */
+  double coupling;       /* <D> */
+  double heat_capacity;  /* <c0> */
+  double residual;       /* final relative residual (mechanics) */
+  int32_t newton_iters;  /* residual evaluations (Newton) or iterations (basic) */
+  int32_t krylov_iters;  /* CG iterations (mechanics) */
+  int32_t thermal_iters; /* iterations of the conduction problem */
+  int32_t status;        /* HOM_OK or the error code of this problem */
+  double pipelines;      /* FFT pipeline applications (mechanics) */
+  double thermal_pipelines;
+} hom_result;
+
+typedef struct hom_ctx hom_ctx;
+typedef struct hom_batch hom_batch;
+
+/* Fill opts with defaults: Newton-CG, FP32, tol 1e-6, graphs on. */
+void hom_default_options(hom_options* opts);
+
+/* Create a context for one microstructure. phases: nx*ny*nz ids (host).
+ * Returns HOM_OK and *out, or an error code (then *out is NULL). */
+int hom_setup(const hom_grid* grid, const uint8_t* phases, const hom_law* laws, int32_t n_laws,
+              const hom_options* opts, hom_ctx** out);
+
+/* Solve one load increment to (E, theta, grad theta) over dt > 0 and, on
+ * success, commit the internal variables. macro_strain: 6 components. */
+int hom_solve_increment(hom_ctx* ctx, const double macro_strain[6], const hom_macro_temp* temp, double dt,
+                        hom_result* out);
+
+/* Checkpoint of the committed state (internal variables, last converged
+ * strain and gradient fields, macro history). hom_state_size gives the byte
+ * count; get writes it into host_buf, set restores it. */
+size_t hom_state_size(const hom_ctx* ctx);
+int hom_get_state(hom_ctx* ctx, void* host_buf, size_t bytes);
+int hom_set_state(hom_ctx* ctx, const void* host_buf, size_t bytes);
+
+/* Copy a field of the last increment to the host as FP64, voxel arrays of
+ * 6 (Mandel) or 3 components, component-major:
+ *   0 strain (Mandel), 1 stress of the last evaluation (Mandel),
+ *   2 temperature gradient, 3 PA66 internal variables (1 + 6 + 6 n_maxwell). */
+#define HOM_FIELD_STRAIN 0
+#define HOM_FIELD_STRESS 1
+#define HOM_FIELD_GRADIENT 2
+#define HOM_FIELD_STATE 3
+int hom_get_field(hom_ctx* ctx, int32_t which, double* host_buf, size_t count);
+
+/* Per-kernel timing collected with profile = 1: names, launch counts and
+ * accumulated milliseconds. Returns the number of kernel kinds (<= cap). */
+int hom_kernel_stats(const hom_ctx* ctx, const char** names, int64_t* launches, double* ms, int32_t cap);
+
+/* Bytes of device memory held by the context. */
+size_t hom_device_bytes(const hom_ctx* ctx);
+
+const char* hom_last_error(const hom_ctx* ctx);
+void hom_destroy(hom_ctx* ctx);
+
+/* ---- batched microproblems ------------------------------------------------
+ * n_prob independent problems, each with its own grid and phases but a shared
+ * law table and options. Problems with equal grids are solved together: one
+ * launch of every kernel covers all of them, with per-problem solver state on
+ * the device. strain: n_prob x 6; temp, dt, out: n_prob entries. */
+int hom_batch_setup(int32_t n_prob, const hom_grid* grids, const uint8_t* const* phases, const hom_law* laws,
+                    int32_t n_laws, const hom_options* opts, hom_batch** out);
+int hom_batch_solve_increment(hom_batch* b, const double* strain, const hom_macro_temp* temp, const double* dt,
+                              hom_result* out);
+int hom_batch_kernel_stats(const hom_batch* b, const char** names, int64_t* launches, double* ms, int32_t cap);
+const char* hom_batch_last_error(const hom_batch* b);
+void hom_batch_destroy(hom_batch* b);
+
+/* ---- kernel-level entry points (used by the parity tests) ------------------
+ * hom_apply_operator: out = IFFT(Op(n) FFT(in)) on one grid, in/out host FP64
+ * arrays of ncomp x nvox (component-major). ncomp = 6 (Mandel) with op 0 =
+ * projector P(n) of the laminate equation (Sec. 3.2) or op 1 = isotropic
+ * reference Green operator (p0 = lambda0, p1 = mu0); ncomp = 3 with op 2 =
+ * n (n . q) or op 3 = n (n . q) / p0. precision: HOM_FP64 / HOM_FP32. */
+int hom_apply_operator(const hom_grid* grid, int32_t ncomp, int32_t op, double p0, double p1,
+                       int32_t precision, const double* in, double* out);
+
+/* hom_eval_law: evaluate the law of phase 0 of `law` on count points with
+ * strains eps (6 x count Mandel, host FP64), previous strains eps_n, and (PA66)
+ * internal variables state (nstate x count, nstate = 7 + 6 n_maxwell), at
+ * temperature theta over dt. Writes sigma (6 x count), tangent factors
+ * ab (2 x count), direction nd (6 x count), and if commit != 0 also
+ * state_out, dissipation and coupling (count each). FP64 on the device. */
+int hom_eval_law(const hom_law* law, int64_t count, const double* eps, const double* eps_n,
+                 const double* state, double theta, double dt, int32_t commit, double* sigma, double* ab,
+                 double* nd, double* state_out, double* dissipation, double* coupling);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* HOM_H */

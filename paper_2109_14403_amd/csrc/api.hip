@@ -1,0 +1,181 @@
+// extern "C" entry points of libhom.so (declared in include/hom.h).
+#include <cstring>
+#include <new>
+
+#include "runtime.h"
+
+struct hom_ctx {
+  std::unique_ptr<hom::BatchImpl> impl;
+  std::string err;
+};
+struct hom_batch {
+  std::unique_ptr<hom::BatchImpl> impl;
+  std::string err;
+};
+
+namespace {
+thread_local std::string g_setup_error;
+
+template <typename F>
+int guarded(std::string* err, F&& f) {
+  try {
+    f();
+    if (err) err->clear();
+    return HOM_OK;
+  } catch (const hom::Error& e) {
+    if (err) *err = e.msg;
+    return e.code;
+  } catch (const std::bad_alloc&) {
+    if (err) *err = "host allocation failed";
+    return HOM_E_OOM;
+  } catch (const std::exception& e) {
+    if (err) *err = e.what();
+    return HOM_E_DEVICE;
+  }
+}
+
+int worst(const hom_result* r, int n) {
+  int code = HOM_OK;
+  for (int i = 0; i < n; ++i)
+    if (r[i].status != HOM_OK && (code == HOM_OK || r[i].status == HOM_E_NAN)) code = r[i].status;
+  return code;
+}
+
+int stats(const hom::BatchImpl* b, const char** names, int64_t* launches, double* ms, int32_t cap) {
+  if (!b) return HOM_E_ARG;
+  const hom::Profiler& p = b->profiler();
+  const int n = cap < hom::K_COUNT ? cap : hom::K_COUNT;
+  for (int i = 0; i < n; ++i) {
+    if (names) names[i] = hom::kKernelNames[i];
+    if (launches) launches[i] = p.launches[i];
+    if (ms) ms[i] = p.ms[i];
+  }
+  return n;
+}
+}  // namespace
+
+extern "C" {
+
+void hom_default_options(hom_options* o) {
+  if (!o) return;
+  std::memset(o, 0, sizeof(*o));
+  o->scheme = HOM_SCHEME_NEWTON_CG;
+  o->precision = HOM_FP32;
+  o->tol = 1e-6;
+  o->thermal_tol = 0.0;
+  o->use_graph = 1;
+}
+
+int hom_setup(const hom_grid* grid, const uint8_t* phases, const hom_law* laws, int32_t n_laws,
+              const hom_options* opts, hom_ctx** out) {
+  if (!out) return HOM_E_ARG;
+  *out = nullptr;
+  hom_ctx* c = new (std::nothrow) hom_ctx();
+  if (!c) return HOM_E_OOM;
+  int rc = guarded(&g_setup_error, [&] {
+    if (!grid || !phases || !laws || !opts) hom::fail(HOM_E_ARG, "null argument");
+    const uint8_t* ph[1] = {phases};
+    c->impl = hom::make_batch(1, grid, ph, laws, n_laws, *opts);
+  });
+  if (rc != HOM_OK) {
+    delete c;
+    return rc;
+  }
+  *out = c;
+  return HOM_OK;
+}
+
+int hom_solve_increment(hom_ctx* c, const double macro_strain[6], const hom_macro_temp* temp, double dt,
+                        hom_result* out) {
+  if (!c || !c->impl || !macro_strain || !temp || !out) return HOM_E_ARG;
+  int rc = guarded(&c->err, [&] { c->impl->solve(macro_strain, temp, &dt, out); });
+  if (rc != HOM_OK) return rc;
+  rc = worst(out, 1);
+  if (rc != HOM_OK) c->err = "increment did not converge (state not committed)";
+  return rc;
+}
+
+size_t hom_state_size(const hom_ctx* c) { return (c && c->impl) ? c->impl->state_size() : 0; }
+
+int hom_get_state(hom_ctx* c, void* buf, size_t bytes) {
+  if (!c || !c->impl || !buf) return HOM_E_ARG;
+  return guarded(&c->err, [&] {
+    if (bytes != c->impl->state_size()) hom::fail(HOM_E_ARG, "state buffer size mismatch");
+    c->impl->get_state(buf);
+  });
+}
+
+int hom_set_state(hom_ctx* c, const void* buf, size_t bytes) {
+  if (!c || !c->impl || !buf) return HOM_E_ARG;
+  return guarded(&c->err, [&] {
+    if (bytes != c->impl->state_size()) hom::fail(HOM_E_ARG, "state buffer size mismatch");
+    c->impl->set_state(buf);
+  });
+}
+
+int hom_get_field(hom_ctx* c, int32_t which, double* buf, size_t count) {
+  if (!c || !c->impl || !buf) return HOM_E_ARG;
+  return guarded(&c->err, [&] { c->impl->get_field(which, buf, count); });
+}
+
+int hom_kernel_stats(const hom_ctx* c, const char** names, int64_t* launches, double* ms, int32_t cap) {
+  return stats(c ? c->impl.get() : nullptr, names, launches, ms, cap);
+}
+
+size_t hom_device_bytes(const hom_ctx* c) { return (c && c->impl) ? c->impl->device_bytes() : 0; }
+
+const char* hom_last_error(const hom_ctx* c) { return c ? c->err.c_str() : g_setup_error.c_str(); }
+
+void hom_destroy(hom_ctx* c) { delete c; }
+
+int hom_batch_setup(int32_t n_prob, const hom_grid* grids, const uint8_t* const* phases, const hom_law* laws,
+                    int32_t n_laws, const hom_options* opts, hom_batch** out) {
+  if (!out) return HOM_E_ARG;
+  *out = nullptr;
+  hom_batch* b = new (std::nothrow) hom_batch();
+  if (!b) return HOM_E_OOM;
+  int rc = guarded(&g_setup_error, [&] {
+    if (!opts) hom::fail(HOM_E_ARG, "null options");
+    b->impl = hom::make_batch(n_prob, grids, phases, laws, n_laws, *opts);
+  });
+  if (rc != HOM_OK) {
+    delete b;
+    return rc;
+  }
+  *out = b;
+  return HOM_OK;
+}
+
+int hom_batch_solve_increment(hom_batch* b, const double* strain, const hom_macro_temp* temp, const double* dt,
+                              hom_result* out) {
+  if (!b || !b->impl || !strain || !temp || !dt || !out) return HOM_E_ARG;
+  int rc = guarded(&b->err, [&] { b->impl->solve(strain, temp, dt, out); });
+  if (rc != HOM_OK) return rc;
+  return HOM_OK;  // per-problem status is in out[i].status
+}
+
+int hom_batch_kernel_stats(const hom_batch* b, const char** names, int64_t* launches, double* ms, int32_t cap) {
+  return stats(b ? b->impl.get() : nullptr, names, launches, ms, cap);
+}
+
+const char* hom_batch_last_error(const hom_batch* b) { return b ? b->err.c_str() : g_setup_error.c_str(); }
+
+void hom_batch_destroy(hom_batch* b) { delete b; }
+
+int hom_apply_operator(const hom_grid* grid, int32_t ncomp, int32_t op, double p0, double p1, int32_t precision,
+                       const double* in, double* out) {
+  if (!grid || !in || !out) return HOM_E_ARG;
+  return guarded(&g_setup_error, [&] { hom::apply_operator(*grid, ncomp, op, p0, p1, precision, in, out); });
+}
+
+int hom_eval_law(const hom_law* law, int64_t count, const double* eps, const double* eps_n, const double* state,
+                 double theta, double dt, int32_t commit, double* sigma, double* ab, double* nd, double* state_out,
+                 double* dissipation, double* coupling) {
+  if (!law || !eps || !sigma) return HOM_E_ARG;
+  return guarded(&g_setup_error, [&] {
+    hom::eval_law(*law, count, eps, eps_n, state, theta, dt, commit, sigma, ab, nd, state_out, dissipation,
+                  coupling);
+  });
+}
+
+}  // extern "C"

@@ -1,0 +1,156 @@
+// Instantiation of the pipeline kernels for one transform length HOM_N.
+#include "pipe_launch.h"
+#include "pipeline.h"
+
+#ifndef HOM_N
+#error "compile with -DHOM_N=<transform length>"
+#endif
+
+namespace hom {
+
+namespace {
+
+template <typename T, int C, int N, int NL>
+LaunchInfo xfwd_c(const Pipe<T>& a, hipStream_t s, bool dry) {
+  constexpr int G = N / Plan<N>::M;
+  constexpr int L = NL * ((C + 1) / 2);
+  LaunchInfo li;
+  li.threads = G * L;
+  li.blocks = a.nprob * ((a.ny * a.nz + NL - 1) / NL);
+  li.lds = (size_t)(N + N * L) * sizeof(c2<T>);
+  {
+    static bool attr = false;
+    if (!attr && li.lds > 65536) {
+      hipFuncSetAttribute(reinterpret_cast<const void*>(&k_xfwd<T, C, N, NL>),
+                          hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+      (void)hipGetLastError();
+      attr = true;
+    }
+  }
+  if (!dry) {
+    hipLaunchKernelGGL((k_xfwd<T, C, N, NL>), dim3(li.blocks), dim3(li.threads), li.lds, s, a);
+  }
+  return li;
+}
+
+template <typename T, int C, int N, int NL>
+LaunchInfo xinv_c(const Pipe<T>& a, hipStream_t s, bool dry) {
+  constexpr int G = N / Plan<N>::M;
+  constexpr int NP = (C + 1) / 2;
+  constexpr int L = NL * NP;
+  constexpr int H = N / 2 + 1;
+  constexpr int B = (NL * H * C > N * L) ? NL * H * C : N * L;
+  LaunchInfo li;
+  li.threads = G * L;
+  li.blocks = a.nprob * ((a.ny * a.nz + NL - 1) / NL);
+  li.lds = (size_t)(N + B) * sizeof(c2<T>);
+  {
+    static bool attr = false;
+    if (!attr && li.lds > 65536) {
+      hipFuncSetAttribute(reinterpret_cast<const void*>(&k_xinv<T, C, N, NL>),
+                          hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+      (void)hipGetLastError();
+      attr = true;
+    }
+  }
+  if (!dry) {
+    hipLaunchKernelGGL((k_xinv<T, C, N, NL>), dim3(li.blocks), dim3(li.threads), li.lds, s, a);
+  }
+  return li;
+}
+
+template <typename T, int C, int N, int TX>
+LaunchInfo ypass_c(const Pipe<T>& a, int inverse, hipStream_t s, bool dry) {
+  constexpr int G = N / Plan<N>::M;
+  LaunchInfo li;
+  li.threads = G * TX * C;
+  li.blocks = a.nprob * a.nz * ((a.P + TX - 1) / TX);
+  li.lds = (size_t)(N + N * TX * C) * sizeof(c2<T>);
+  {
+    static bool attr = false;
+    if (!attr && li.lds > 65536) {
+      hipFuncSetAttribute(reinterpret_cast<const void*>(&k_ypass<T, C, N, TX>),
+                          hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+      (void)hipGetLastError();
+      attr = true;
+    }
+  }
+  if (!dry) {
+    hipLaunchKernelGGL((k_ypass<T, C, N, TX>), dim3(li.blocks), dim3(li.threads), li.lds, s, a, inverse);
+  }
+  return li;
+}
+
+template <typename T, int C, int N, int TX>
+LaunchInfo zgreen_c(const Pipe<T>& a, hipStream_t s, bool dry) {
+  constexpr int G = N / Plan<N>::M;
+  LaunchInfo li;
+  li.threads = G * TX * C;
+  li.blocks = a.nprob * a.ny * ((a.P + TX - 1) / TX);
+  li.lds = (size_t)(N + N * TX * C) * sizeof(c2<T>);
+  {
+    static bool attr = false;
+    if (!attr && li.lds > 65536) {
+      hipFuncSetAttribute(reinterpret_cast<const void*>(&k_zgreen<T, C, N, TX>),
+                          hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+      (void)hipGetLastError();
+      attr = true;
+    }
+  }
+  if (!dry) {
+    hipLaunchKernelGGL((k_zgreen<T, C, N, TX>), dim3(li.blocks), dim3(li.threads), li.lds, s, a);
+  }
+  return li;
+}
+
+constexpr int nl_of(int n, bool fp64) {
+  return ((fp64 ? 64 : 128) / (n / Plan<HOM_N>::M)) < 1 ? 1 : ((fp64 ? 64 : 128) / (n / Plan<HOM_N>::M));
+}
+
+}  // namespace
+
+template <typename T, int N>
+LaunchInfo xfwd_launch(const Pipe<T>& a, hipStream_t s, bool dry) {
+  constexpr int NL = nl_of(N, sizeof(T) == 8);
+  return a.C == 6 ? xfwd_c<T, 6, N, NL>(a, s, dry) : xfwd_c<T, 3, N, NL>(a, s, dry);
+}
+
+template <typename T, int N>
+LaunchInfo xinv_launch(const Pipe<T>& a, hipStream_t s, bool dry) {
+  constexpr int NL = nl_of(N, sizeof(T) == 8);
+  return a.C == 6 ? xinv_c<T, 6, N, NL>(a, s, dry) : xinv_c<T, 3, N, NL>(a, s, dry);
+}
+
+template <typename T, int N>
+LaunchInfo ypass_launch(const Pipe<T>& a, int tx, int inverse, hipStream_t s, bool dry) {
+  if (a.C == 6) {
+    if (tx == 2) return ypass_c<T, 6, N, 2>(a, inverse, s, dry);
+    if (tx == 8) return ypass_c<T, 6, N, 8>(a, inverse, s, dry);
+    return ypass_c<T, 6, N, 4>(a, inverse, s, dry);
+  }
+  if (tx == 2) return ypass_c<T, 3, N, 2>(a, inverse, s, dry);
+  if (tx == 8) return ypass_c<T, 3, N, 8>(a, inverse, s, dry);
+  return ypass_c<T, 3, N, 4>(a, inverse, s, dry);
+}
+
+template <typename T, int N>
+LaunchInfo zgreen_launch(const Pipe<T>& a, int tx, hipStream_t s, bool dry) {
+  if (a.C == 6) {
+    if (tx == 2) return zgreen_c<T, 6, N, 2>(a, s, dry);
+    if (tx == 8) return zgreen_c<T, 6, N, 8>(a, s, dry);
+    return zgreen_c<T, 6, N, 4>(a, s, dry);
+  }
+  if (tx == 2) return zgreen_c<T, 3, N, 2>(a, s, dry);
+  if (tx == 8) return zgreen_c<T, 3, N, 8>(a, s, dry);
+  return zgreen_c<T, 3, N, 4>(a, s, dry);
+}
+
+#define HOM_INST(T)                                                                         \
+  template LaunchInfo xfwd_launch<T, HOM_N>(const Pipe<T>&, hipStream_t, bool);             \
+  template LaunchInfo xinv_launch<T, HOM_N>(const Pipe<T>&, hipStream_t, bool);             \
+  template LaunchInfo ypass_launch<T, HOM_N>(const Pipe<T>&, int, int, hipStream_t, bool);  \
+  template LaunchInfo zgreen_launch<T, HOM_N>(const Pipe<T>&, int, hipStream_t, bool);
+HOM_INST(float)
+HOM_INST(double)
+
+}  // namespace hom

@@ -1,0 +1,67 @@
+// Host launchers of the FFT pipeline kernels. The kernels are templated on
+// the line length; one object file per supported length instantiates them
+// (pipe_inst.hip compiled with -DHOM_N=<n>), and the dispatchers below pick
+// the instantiation at run time.
+#pragma once
+#include "common.h"
+
+namespace hom {
+
+// Supported transform lengths along every axis.
+constexpr int kSupportedN[] = {16, 24, 32, 48, 64, 96, 128, 256};
+
+inline bool supported_n(int n) {
+  for (int v : kSupportedN)
+    if (v == n) return true;
+  return false;
+}
+
+// Elements per thread of the line FFT of length n (threads per line = n / M).
+inline int plan_m(int n) {
+  switch (n) {
+    case 16: return 4;
+    case 24: return 12;
+    case 32: return 8;
+    case 48: return 12;
+    case 64: return 8;
+    case 96: return 24;
+    case 128: return 16;
+    case 256: return 16;
+  }
+  return 0;
+}
+
+// x-pass lines per work-group
+inline int x_lines(int n, bool fp64) {
+  int g = n / plan_m(n);
+  int nl = (fp64 ? 64 : 128) / g;
+  return nl < 1 ? 1 : nl;
+}
+
+constexpr int kTileChoices[] = {2, 4, 8};
+
+struct LaunchInfo {
+  int blocks;
+  int threads;
+  size_t lds;
+};
+
+template <typename T, int N>
+LaunchInfo xfwd_launch(const Pipe<T>& a, hipStream_t s, bool dry);
+template <typename T, int N>
+LaunchInfo xinv_launch(const Pipe<T>& a, hipStream_t s, bool dry);
+template <typename T, int N>
+LaunchInfo ypass_launch(const Pipe<T>& a, int tx, int inverse, hipStream_t s, bool dry);
+template <typename T, int N>
+LaunchInfo zgreen_launch(const Pipe<T>& a, int tx, hipStream_t s, bool dry);
+
+template <typename T>
+LaunchInfo run_xfwd(const Pipe<T>& a, hipStream_t s, bool dry = false);
+template <typename T>
+LaunchInfo run_xinv(const Pipe<T>& a, hipStream_t s, bool dry = false);
+template <typename T>
+LaunchInfo run_ypass(const Pipe<T>& a, int tx, int inverse, hipStream_t s, bool dry = false);
+template <typename T>
+LaunchInfo run_zgreen(const Pipe<T>& a, int tx, hipStream_t s, bool dry = false);
+
+}  // namespace hom

@@ -1,0 +1,444 @@
+// The five-pass FFT / Green-operator pipeline of one solver iteration.
+//
+//   xfwd   pre-operation per voxel (copy of the stress / flux field, or the
+//          algorithmic tangent applied to the CG direction), then real-to-
+//          complex transforms along x (two real components packed into one
+//          complex line), written as the half spectrum kx = 0..nx/2.
+//   ypass  complex transforms along y on tiles of TX contiguous kx columns.
+//   zgreen forward transform along z, Green operator per frequency on all
+//          components, inverse transform along z.
+//   ypass  inverse along y.
+//   xinv   complex-to-real inverse along x, scaled by 1/(nx ny nz), then the
+//          post-operation per voxel (residual / A p / basic-scheme update)
+//          with FP64 partial sums for the reductions.
+//
+// Every kernel serves all problems of a group in one launch: blockIdx.x runs
+// over (problem, tile), and a block whose problem is not iterating exits at
+// once.
+#pragma once
+#include "common.h"
+
+namespace hom {
+
+// Sum of per-thread doubles over the block, deterministic (fixed tree).
+template <int K>
+__device__ __forceinline__ void block_sum(double (&v)[K], double* red /* >= K * 16 doubles */) {
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+  const int nw = (blockDim.x + 63) >> 6;
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v[k] += __shfl_down(v[k], off, 64);
+  }
+  __syncthreads();
+  if (lane == 0) {
+#pragma unroll
+    for (int k = 0; k < K; ++k) red[k * 16 + wave] = v[k];
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      double s = 0.0;
+      for (int w = 0; w < nw; ++w) s += red[k * 16 + w];
+      v[k] = s;
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Green operators on a Mandel (C = 6) or vector (C = 3) complex array.
+// ---------------------------------------------------------------------------
+template <typename T>
+__device__ __forceinline__ void frequency_direction(int kx, int ky, int kz, int nx, int ny, int nz,
+                                                    const double* len, T& n0, T& n1, T& n2, bool& zero) {
+  // signed frequencies; even-size Nyquist entries are nulled
+  int sx = kx;
+  if ((nx & 1) == 0 && kx == nx / 2) sx = 0;
+  int sy = ky < (ny + 1) / 2 ? ky : ky - ny;
+  if ((ny & 1) == 0 && ky == ny / 2) sy = 0;
+  int sz = kz < (nz + 1) / 2 ? kz : kz - nz;
+  if ((nz & 1) == 0 && kz == nz / 2) sz = 0;
+  T a = T(sx) / T(len[0]);
+  T b = T(sy) / T(len[1]);
+  T c = T(sz) / T(len[2]);
+  T m2 = a * a + b * b + c * c;
+  zero = !(m2 > T(0));
+  T inv = zero ? T(0) : T(1) / sqrt(m2);
+  n0 = a * inv;
+  n1 = b * inv;
+  n2 = c * inv;
+}
+
+template <typename T>
+__device__ __forceinline__ void green_mech(c2<T>* v, T n0, T n1, T n2, T cs, T cn) {
+  // out = cs (n (x) tau n + tau n (x) n) - cn (n . tau n) n (x) n, applied to
+  // real and imaginary parts; projector: cs = 1, cn = 1.
+  const T r2 = T(0.70710678118654752);
+  const T s2 = T(1.4142135623730951);
+  c2<T> t11 = v[0], t22 = v[1], t33 = v[2];
+  c2<T> t23 = cscale(v[3], r2), t13 = cscale(v[4], r2), t12 = cscale(v[5], r2);
+  c2<T> u0 = cscale(t11, n0) + cscale(t12, n1) + cscale(t13, n2);
+  c2<T> u1 = cscale(t12, n0) + cscale(t22, n1) + cscale(t23, n2);
+  c2<T> u2 = cscale(t13, n0) + cscale(t23, n1) + cscale(t33, n2);
+  c2<T> q = cscale(u0, n0) + cscale(u1, n1) + cscale(u2, n2);
+  c2<T> qn = cscale(q, cn);
+  v[0] = cscale(cscale(u0, n0), T(2) * cs) - cscale(qn, n0 * n0);
+  v[1] = cscale(cscale(u1, n1), T(2) * cs) - cscale(qn, n1 * n1);
+  v[2] = cscale(cscale(u2, n2), T(2) * cs) - cscale(qn, n2 * n2);
+  v[3] = cscale(cscale(cscale(u1, n2) + cscale(u2, n1), cs) - cscale(qn, n1 * n2), s2);
+  v[4] = cscale(cscale(cscale(u0, n2) + cscale(u2, n0), cs) - cscale(qn, n0 * n2), s2);
+  v[5] = cscale(cscale(cscale(u0, n1) + cscale(u1, n0), cs) - cscale(qn, n0 * n1), s2);
+}
+
+template <typename T>
+__device__ __forceinline__ void green_grad(c2<T>* v, T n0, T n1, T n2, T s) {
+  c2<T> q = cscale(cscale(v[0], n0) + cscale(v[1], n1) + cscale(v[2], n2), s);
+  v[0] = cscale(q, n0);
+  v[1] = cscale(q, n1);
+  v[2] = cscale(q, n2);
+}
+
+// ---------------------------------------------------------------------------
+// x forward: pre-operation + packed real-to-complex transforms
+// ---------------------------------------------------------------------------
+template <typename T, int C, int N, int NL>
+__global__ void __launch_bounds__((N / Plan<N>::M) * NL * ((C + 1) / 2)) k_xfwd(Pipe<T> a) {
+  constexpr int M = Plan<N>::M;
+  constexpr int G = N / M;
+  constexpr int NP = (C + 1) / 2;
+  constexpr int L = NL * NP;
+  constexpr int H = N / 2 + 1;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  c2<T>* tw = reinterpret_cast<c2<T>*>(smem_raw);
+  c2<T>* buf = tw + N;
+
+  const int nlines = a.ny * a.nz;
+  const int bpp = (nlines + NL - 1) / NL;
+  const int prob = blockIdx.x / bpp;
+  const int line0 = (blockIdx.x % bpp) * NL;
+  const Ctl& ctl = a.ctl[prob];
+  const int mode = ctl.mode;
+  if (!pipeline_mode(mode)) return;
+  const int tid = threadIdx.x;
+  const int nth = blockDim.x;
+  for (int i = tid; i < N; i += nth) tw[i] = a.twx[i];
+
+  const long long nv = a.nvox;
+  const long long fo = (long long)prob * C * nv;
+  const uint8_t* phase = a.phase + (long long)prob * nv;
+  const ProbInc& inc = a.inc[prob];
+  const bool cg = (mode == M_CG);
+  const bool first = (ctl.cg_it == 0);
+  const T beta = T(ctl.beta);
+
+  for (int idx = tid; idx < NL * N; idx += nth) {
+    const int li = idx / N;
+    const int xv = idx - li * N;
+    const int line = line0 + li;
+    T out[2 * NP];
+#pragma unroll
+    for (int c = 0; c < 2 * NP; ++c) out[c] = T(0);
+    if (line < nlines) {
+      const long long v = (long long)line * N + xv;
+      if (!cg) {
+#pragma unroll
+        for (int c = 0; c < C; ++c) out[c] = a.f[fo + c * nv + v];
+      } else {
+        T pv[C];
+#pragma unroll
+        for (int c = 0; c < C; ++c) {
+          T rv = a.r[fo + c * nv + v];
+          pv[c] = first ? rv : rv + beta * a.p[fo + c * nv + v];
+          a.p[fo + c * nv + v] = pv[c];
+        }
+        const int ph = phase[v];
+        if constexpr (C == 6) {
+          const long long to = (long long)prob * 2 * nv;
+          const T K3 = T(inc.ph[ph].K3);
+          const T ca = a.tab[to + v];
+          const T cb = a.tab[to + nv + v];
+          const T tr3 = (pv[0] + pv[1] + pv[2]) * T(1.0 / 3.0);
+          const T sph = K3 * tr3 - ca * tr3;
+#pragma unroll
+          for (int c = 0; c < 6; ++c) out[c] = ca * pv[c];
+          out[0] += sph;
+          out[1] += sph;
+          out[2] += sph;
+          if (cb != T(0)) {
+            const long long no = (long long)prob * 6 * nv;
+            T nd[6];
+            T dot = T(0);
+#pragma unroll
+            for (int c = 0; c < 6; ++c) {
+              nd[c] = a.tn[no + c * nv + v];
+              dot += nd[c] * pv[c];
+            }
+#pragma unroll
+            for (int c = 0; c < 6; ++c) out[c] += cb * dot * nd[c];
+          }
+        } else {
+          const T kap = T(inc.ph[ph].kappa);
+#pragma unroll
+          for (int c = 0; c < C; ++c) out[c] = kap * pv[c];
+        }
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < NP; ++q) buf[xv * L + li * NP + q] = mk(out[2 * q], out[2 * q + 1]);
+  }
+  __syncthreads();
+
+  const int l = tid % L;
+  const int t = tid / L;
+  c2<T> r[M];
+#pragma unroll
+  for (int m = 0; m < M; ++m) r[m] = buf[(t + G * m) * L + l];
+  Plan<N>::run(r, t, tw, buf, L, l, true);
+  __syncthreads();
+#pragma unroll
+  for (int m = 0; m < M; ++m) buf[(t + G * m) * L + l] = r[m];
+  __syncthreads();
+
+  c2<T>* spec = a.spec + (long long)prob * a.nz * a.ny * a.P * C;
+  const int P = a.P;
+  for (int idx = tid; idx < NL * H * C; idx += nth) {
+    const int c = idx % C;
+    const int rest = idx / C;
+    const int k = rest % H;
+    const int li = rest / H;
+    const int line = line0 + li;
+    if (line >= nlines) continue;
+    const int q = c >> 1;
+    const c2<T> zk = buf[k * L + li * NP + q];
+    const c2<T> zm = conjg(buf[((N - k) % N) * L + li * NP + q]);
+    c2<T> val = (c & 1) ? mul_mi(zk - zm) : (zk + zm);
+    spec[((long long)line * P + k) * C + c] = cscale(val, T(0.5));
+  }
+}
+
+// ---------------------------------------------------------------------------
+// y pass (forward or inverse) on tiles of TX kx columns
+// ---------------------------------------------------------------------------
+template <typename T, int C, int N, int TX>
+__global__ void __launch_bounds__((N / Plan<N>::M) * TX * C) k_ypass(Pipe<T> a, int inverse) {
+  constexpr int M = Plan<N>::M;
+  constexpr int G = N / M;
+  constexpr int L = TX * C;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  c2<T>* tw = reinterpret_cast<c2<T>*>(smem_raw);
+  c2<T>* buf = tw + N;
+  const int P = a.P;
+  const int nkb = (P + TX - 1) / TX;
+  const int bpp = a.nz * nkb;
+  const int prob = blockIdx.x / bpp;
+  const int b = blockIdx.x % bpp;
+  if (!pipeline_mode(a.ctl[prob].mode)) return;
+  const int z = b / nkb;
+  const int kb = b % nkb;
+  const int tid = threadIdx.x;
+  for (int i = tid; i < N; i += blockDim.x) tw[i] = a.twy[i];
+  const int l = tid % L;
+  const int t = tid / L;
+  const int kx = kb * TX + l / C;
+  const int c = l % C;
+  const bool active = kx < P;
+  const long long stride = (long long)P * C;
+  c2<T>* base = a.spec + (long long)prob * a.nz * a.ny * P * C + ((long long)z * a.ny * P + kx) * C + c;
+  c2<T> r[M];
+  __syncthreads();
+#pragma unroll
+  for (int m = 0; m < M; ++m) {
+    c2<T> v = active ? base[(t + G * m) * stride] : mk(T(0), T(0));
+    r[m] = inverse ? conjg(v) : v;
+  }
+  Plan<N>::run(r, t, tw, buf, L, l, active);
+  if (active) {
+#pragma unroll
+    for (int m = 0; m < M; ++m) base[(t + G * m) * stride] = inverse ? conjg(r[m]) : r[m];
+  }
+}
+
+// ---------------------------------------------------------------------------
+// z forward + Green operator + z inverse on tiles of TX kx columns
+// ---------------------------------------------------------------------------
+template <typename T, int C, int N, int TX>
+__global__ void __launch_bounds__((N / Plan<N>::M) * TX * C) k_zgreen(Pipe<T> a) {
+  constexpr int M = Plan<N>::M;
+  constexpr int G = N / M;
+  constexpr int L = TX * C;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  c2<T>* tw = reinterpret_cast<c2<T>*>(smem_raw);
+  c2<T>* buf = tw + N;
+  const int P = a.P;
+  const int nkb = (P + TX - 1) / TX;
+  const int bpp = a.ny * nkb;
+  const int prob = blockIdx.x / bpp;
+  const int b = blockIdx.x % bpp;
+  if (!pipeline_mode(a.ctl[prob].mode)) return;
+  const int ky = b / nkb;
+  const int kb = b % nkb;
+  const int tid = threadIdx.x;
+  const int nth = blockDim.x;
+  for (int i = tid; i < N; i += nth) tw[i] = a.twz[i];
+  const int l = tid % L;
+  const int t = tid / L;
+  const int kx = kb * TX + l / C;
+  const int c = l % C;
+  const bool active = kx < P;
+  const long long stride = (long long)a.ny * P * C;
+  c2<T>* base = a.spec + (long long)prob * a.nz * a.ny * P * C + ((long long)ky * P + kx) * C + c;
+  c2<T> r[M];
+  __syncthreads();
+#pragma unroll
+  for (int m = 0; m < M; ++m) r[m] = active ? base[(t + G * m) * stride] : mk(T(0), T(0));
+  Plan<N>::run(r, t, tw, buf, L, l, active);
+  __syncthreads();
+#pragma unroll
+  for (int m = 0; m < M; ++m) buf[(t + G * m) * L + l] = r[m];
+  __syncthreads();
+
+  const ProbInc& inc = a.inc[prob];
+  T cs = T(1), cn = T(1);
+  if (a.green == G_GAMMA0) {
+    cs = T(1.0 / (2.0 * inc.mu0));
+    cn = T((inc.lam0 + inc.mu0) / (inc.mu0 * (inc.lam0 + 2.0 * inc.mu0)));
+  } else if (a.green == G_GAMMA_TH) {
+    cs = T(1.0 / inc.kappa0);
+  }
+  for (int idx = tid; idx < N * TX; idx += nth) {
+    const int kz = idx / TX;
+    const int kxi = idx - kz * TX;
+    const int kxx = kb * TX + kxi;
+    if (kxx >= P) continue;
+    T n0, n1, n2;
+    bool zero;
+    frequency_direction<T>(kxx, ky, kz, a.nx, a.ny, a.nz, a.len, n0, n1, n2, zero);
+    c2<T> v[C];
+#pragma unroll
+    for (int cc = 0; cc < C; ++cc) v[cc] = buf[kz * L + kxi * C + cc];
+    if (zero) {
+#pragma unroll
+      for (int cc = 0; cc < C; ++cc) v[cc] = mk(T(0), T(0));
+    } else {
+      if constexpr (C == 6)
+        green_mech<T>(v, n0, n1, n2, cs, cn);
+      else
+        green_grad<T>(v, n0, n1, n2, cs);
+    }
+#pragma unroll
+    for (int cc = 0; cc < C; ++cc) buf[kz * L + kxi * C + cc] = v[cc];
+  }
+  __syncthreads();
+#pragma unroll
+  for (int m = 0; m < M; ++m) r[m] = conjg(buf[(t + G * m) * L + l]);
+  Plan<N>::run(r, t, tw, buf, L, l, active);
+  if (active) {
+#pragma unroll
+    for (int m = 0; m < M; ++m) base[(t + G * m) * stride] = conjg(r[m]);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// x inverse: packed complex-to-real transforms + post-operation + partial sums
+// ---------------------------------------------------------------------------
+template <typename T, int C, int N, int NL>
+__global__ void __launch_bounds__((N / Plan<N>::M) * NL * ((C + 1) / 2)) k_xinv(Pipe<T> a) {
+  constexpr int M = Plan<N>::M;
+  constexpr int G = N / M;
+  constexpr int NP = (C + 1) / 2;
+  constexpr int L = NL * NP;
+  constexpr int H = N / 2 + 1;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  c2<T>* tw = reinterpret_cast<c2<T>*>(smem_raw);
+  c2<T>* buf = tw + N;  // holds the staged half spectra first, then the line FFTs
+  __shared__ double red[2 * 16];
+
+  const int nlines = a.ny * a.nz;
+  const int bpp = (nlines + NL - 1) / NL;
+  const int prob = blockIdx.x / bpp;
+  const int blk = blockIdx.x % bpp;
+  const int line0 = blk * NL;
+  const int mode = a.ctl[prob].mode;
+  if (!pipeline_mode(mode)) return;
+  const int tid = threadIdx.x;
+  const int nth = blockDim.x;
+  for (int i = tid; i < N; i += nth) tw[i] = a.twx[i];
+  const c2<T>* spec = a.spec + (long long)prob * a.nz * a.ny * a.P * C;
+  const int P = a.P;
+  for (int idx = tid; idx < NL * H * C; idx += nth) {
+    const int rest = idx / C;
+    const int k = rest % H;
+    const int li = rest / H;
+    const int c = idx - rest * C;
+    const int line = line0 + li;
+    buf[idx] = line < nlines ? spec[((long long)line * P + k) * C + c] : mk(T(0), T(0));
+  }
+  __syncthreads();
+  const int l = tid % L;
+  const int t = tid / L;
+  const int li = l / NP;
+  const int q = l - li * NP;
+  c2<T> r[M];
+#pragma unroll
+  for (int m = 0; m < M; ++m) {
+    const int p = t + G * m;
+    const bool lo = p <= N / 2;
+    const int kk = lo ? p : N - p;
+    c2<T> A = buf[(li * H + kk) * C + 2 * q];
+    c2<T> B = (2 * q + 1 < C) ? buf[(li * H + kk) * C + 2 * q + 1] : mk(T(0), T(0));
+    if (!lo) {
+      A = conjg(A);
+      B = conjg(B);
+    }
+    // Z = A + i B, transformed as conj(DFT(conj(Z)))
+    r[m] = mk(A.x - B.y, -(A.y + B.x));
+  }
+  Plan<N>::run(r, t, tw, buf, L, l, true);
+  __syncthreads();
+#pragma unroll
+  for (int m = 0; m < M; ++m) buf[(t + G * m) * L + l] = conjg(r[m]);
+  __syncthreads();
+
+  const long long nv = a.nvox;
+  const long long fo = (long long)prob * C * nv;
+  const T scale = T(1.0 / ((double)a.nx * a.ny * a.nz));
+  double s0 = 0.0, s1 = 0.0;
+  for (int idx = tid; idx < NL * N; idx += nth) {
+    const int lj = idx / N;
+    const int xv = idx - lj * N;
+    const int line = line0 + lj;
+    if (line >= nlines) continue;
+    const long long v = (long long)line * N + xv;
+#pragma unroll
+    for (int c = 0; c < C; ++c) {
+      const c2<T> z = buf[xv * L + lj * NP + (c >> 1)];
+      const T g = ((c & 1) ? z.y : z.x) * scale;
+      const long long o = fo + c * nv + v;
+      if (mode == M_EVAL) {
+        a.r[o] = -g;
+        const double fv = (double)a.f[o];
+        s0 += (double)g * (double)g;
+        s1 += fv * fv;
+      } else if (mode == M_CG) {
+        a.ap[o] = g;
+        s0 += (double)a.p[o] * (double)g;
+      } else {
+        const T xn = a.x[o] - g;
+        a.x[o] = xn;
+        s0 += (double)g * (double)g;
+        s1 += (double)xn * (double)xn;
+      }
+    }
+  }
+  double s[2] = {s0, s1};
+  block_sum<2>(s, red);
+  if (tid == 0) {
+    double* out = a.part + ((long long)prob * a.maxblk + blk) * NPART;
+    out[0] = s[0];
+    out[1] = s[1];
+  }
+}
+
+}  // namespace hom

@@ -1,0 +1,60 @@
+// Per-voxel kernels: constitutive evaluation, CG vector updates, commit of
+// the internal variables, and the per-problem reductions that drive the
+// Newton-CG / basic-scheme state machine on the device.
+#pragma once
+#include "common.h"
+
+namespace hom {
+
+// Arguments of the pointwise kernels of one group.
+template <typename T>
+struct Pt {
+  long long nvox;
+  int nprob;
+  int bpp;                  // blocks per problem
+  const uint8_t* phase;
+  T* x;
+  T* xn;                    // committed strain (mechanics)
+  T* f;
+  T* r;
+  T* p;
+  T* ap;
+  T* dx;
+  T* tab;
+  T* tn;
+  double* state;            // [prob][nstate][nvox] (mechanics with a PA66 phase)
+  int nstate;
+  Ctl* ctl;
+  const ProbInc* inc;
+  double* part;
+  int maxblk;
+  double* pv_diss;          // optional per-voxel dissipation at commit
+  double* pv_coup;          // optional per-voxel coupling term at commit
+};
+
+struct Limits {
+  double tol;
+  int max_newton;   // Newton: residual evaluations; basic: iterations
+  int max_krylov;
+  int linear;       // 1: CG solves to the tolerance at once
+};
+
+}  // namespace hom
+
+// host launchers (pointwise.hip)
+namespace hom {
+template <typename T>
+void launch_init_mech(const Pt<T>& a, int scheme, hipStream_t s);
+template <typename T>
+void launch_init_th(const Pt<T>& a, int scheme, hipStream_t s);
+template <typename T>
+void launch_eval(const Pt<T>& a, int C, hipStream_t s);
+template <typename T>
+void launch_cgupdate(const Pt<T>& a, int C, hipStream_t s);
+void launch_reduce_a(Ctl* ctl, const double* part, int maxblk, int nblk, int nprob, Limits lim, hipStream_t s);
+void launch_reduce_b(Ctl* ctl, const double* part, int maxblk, int nblk, int nprob, Limits lim, hipStream_t s);
+template <typename T>
+void launch_commit(const Pt<T>& a, int C, hipStream_t s);
+void launch_reduce_out(Ctl* ctl, const double* part, int maxblk, int nblk, int nprob, int nk, double scale,
+                       hipStream_t s);
+}  // namespace hom

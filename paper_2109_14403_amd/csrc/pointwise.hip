@@ -1,0 +1,547 @@
+// Per-voxel kernels and per-problem reductions (see pointwise.h).
+#include <math.h>
+
+#include "pipeline.h"
+#include "pointwise.h"
+
+namespace hom {
+
+constexpr int PT_THREADS = 256;
+
+// ---------------------------------------------------------------------------
+// PA66 law (paper Sec. 4) for one voxel, FP64, implicit Euler.
+//
+// With e = eps - eps_vp - alpha (theta - theta0) I, the viscous strains of the
+// Maxwell branches have the closed-form update
+//   sph:  S_i' = (S_i + rK_i tr(e)/3) / (1 + rK_i)
+//   dev:  D_i' = (D_i + rG_i dev e) / (1 + rG_i),
+// rK_i = dt / (a_theta tau_K,i), rG_i = dt / (a_theta tau_G,i). The deviatoric
+// stress is then s = 2 Gbar (dev eps - eps_vp') - sum 2 G_i D_i / (1 + rG_i)
+// with Gbar = G_inf + sum G_i / (1 + rG_i), so the viscoplastic flow along
+// s / |s| reduces to a radial return: s = s_tr (1 - 3 Gbar dp / seq_tr) and the
+// plastic increment dp solves the implicit overstress equation
+//   g(dp) = dp - dt (sY / eta) <(seq_tr - 3 Gbar dp - sY - H(eps_p + dp)) / sY>^m = 0,
+// solved by a bracketed Newton iteration (g is increasing and concave).
+// The algorithmic tangent is 3 Kbar P1 + 2 Gbar [th1 (P2 - N N) + cp N N],
+// stored as (a, b, N) = (2 Gbar th1, 2 Gbar (cp - th1), N).
+// ---------------------------------------------------------------------------
+struct PaOut {
+  double sig[6];
+  double a, b;
+  double nd[6];
+  double dp;
+};
+
+__device__ __forceinline__ double pa66_solve_dp(const ProbInc& in, double seq, double ep, double f, double G3,
+                                                double& dgd) {
+  double lo = 0.0, hi = f / G3;
+  double d = 0.5 * hi;
+  const double c = in.ccoef, sY = in.sY, m = in.mexp, hk = in.hk, nh = in.nh;
+  double gd = 1.0, xp = 0.0;
+  for (int it = 0; it < 80; ++it) {
+    const double e = ep + d;
+    const double x = (seq - G3 * d - sY - hk * pow(e, nh)) / sY;
+    xp = x > 0.0 ? x : 0.0;
+    const double gv = d - c * pow(xp, m);
+    if (gv < 0.0)
+      lo = d;
+    else
+      hi = d;
+    const double hp = e > 0.0 ? hk * nh * pow(e, nh - 1.0) : INFINITY;
+    gd = 1.0 + c * m * pow(xp, m - 1.0) * (G3 + hp) / sY;
+    double dn = d - gv / gd;
+    if (!(dn > lo && dn < hi)) dn = 0.5 * (lo + hi);
+    const bool done = fabs(dn - d) <= 1e-15 * dn || hi - lo <= 1e-16 * hi;
+    d = dn;
+    if (done) break;
+  }
+  // derivative information at the root
+  const double e = ep + d;
+  const double x = (seq - G3 * d - sY - hk * pow(e, nh)) / sY;
+  xp = x > 0.0 ? x : 0.0;
+  const double A = c * m * pow(xp, m - 1.0) / sY;
+  const double hp = e > 0.0 ? hk * nh * pow(e, nh - 1.0) : INFINITY;
+  dgd = A / (1.0 + A * (G3 + hp));  // d dp / d seq_tr
+  return d;
+}
+
+// Trial / final evaluation. If `st_out` is non-null the new internal
+// variables are written there and the dissipation and coupling computed.
+__device__ void pa66_point(const ProbInc& in, const double* eps, const double* st, long long ss, double* st_out,
+                           const double* eps_n, PaOut& o, double* diss, double* coup) {
+  const double tr3 = (eps[0] + eps[1] + eps[2]) * (1.0 / 3.0);
+  const double em = tr3 - in.ph[in.pa_phase].alpha_dth;
+  double d[6];
+#pragma unroll
+  for (int c = 0; c < 6; ++c) d[c] = eps[c];
+  d[0] -= tr3;
+  d[1] -= tr3;
+  d[2] -= tr3;
+  const double ep = st[0];
+  double evp[6];
+#pragma unroll
+  for (int c = 0; c < 6; ++c) evp[c] = st[(1 + c) * ss];
+  double str[6];
+#pragma unroll
+  for (int c = 0; c < 6; ++c) str[c] = in.Gbar2 * (d[c] - evp[c]);
+  double sph = in.Kinf3 * em;
+  for (int i = 0; i < in.nm; ++i) {
+    const double* ev = st + (7 + 6 * i) * ss;
+    const double v0 = ev[0], v1 = ev[ss], v2 = ev[2 * ss];
+    const double sn = (v0 + v1 + v2) * (1.0 / 3.0);
+    const double w = in.G2i[i] * in.fG[i];
+    str[0] -= w * (v0 - sn);
+    str[1] -= w * (v1 - sn);
+    str[2] -= w * (v2 - sn);
+    str[3] -= w * ev[3 * ss];
+    str[4] -= w * ev[4 * ss];
+    str[5] -= w * ev[5 * ss];
+    sph += in.K3i[i] * in.fK[i] * (em - sn);
+  }
+  double sn2 = 0.0;
+#pragma unroll
+  for (int c = 0; c < 6; ++c) sn2 += str[c] * str[c];
+  const double snrm = sqrt(sn2);
+  const double seq = 1.2247448713915890 * snrm;  // sqrt(3/2) |s|
+  const double H = ep > 0.0 ? in.hk * pow(ep, in.nh) : 0.0;
+  const double f = seq - in.sY - H;
+  double dp = 0.0, th1 = 1.0, cp = 1.0;
+  const double G3 = 1.5 * in.Gbar2;
+  if (f > 0.0 && snrm > 0.0) {
+    double dgd;
+    dp = pa66_solve_dp(in, seq, ep, f, G3, dgd);
+    th1 = 1.0 - G3 * dp / seq;
+    cp = 1.0 - G3 * dgd;
+  }
+  const double inv = snrm > 0.0 ? 1.0 / snrm : 0.0;
+#pragma unroll
+  for (int c = 0; c < 6; ++c) {
+    o.nd[c] = str[c] * inv;
+    o.sig[c] = th1 * str[c];
+  }
+  o.sig[0] += sph;
+  o.sig[1] += sph;
+  o.sig[2] += sph;
+  o.a = in.Gbar2 * th1;
+  o.b = in.Gbar2 * (cp - th1);
+  o.dp = dp;
+  if (!st_out) return;
+
+  // ---- commit: new internal variables, dissipation, coupling ------------
+  const double dt = in.dt;
+  const double k15 = 1.2247448713915890 * dp;
+  double evp1[6], dn[6];
+#pragma unroll
+  for (int c = 0; c < 6; ++c) {
+    evp1[c] = evp[c] + k15 * o.nd[c];
+    dn[c] = d[c] - evp1[c];
+    st_out[(1 + c) * ss] = evp1[c];
+  }
+  const double ep1 = ep + dp;
+  st_out[0] = ep1;
+  double dis = in.sY * dp;
+  double trd = 0.0;
+#pragma unroll
+  for (int c = 0; c < 3; ++c) trd += eps[c] - eps_n[c];
+  double trsum = in.Kinf3 * trd;
+  for (int i = 0; i < in.nm; ++i) {
+    const double* ev = st + (7 + 6 * i) * ss;
+    double* evo = st_out + (7 + 6 * i) * ss;
+    double v[6];
+#pragma unroll
+    for (int c = 0; c < 6; ++c) v[c] = ev[c * ss];
+    const double sn = (v[0] + v[1] + v[2]) * (1.0 / 3.0);
+    const double s1 = in.fK[i] * (sn + in.rK[i] * em);
+    double dnew[6], dold[6];
+#pragma unroll
+    for (int c = 0; c < 6; ++c) {
+      dold[c] = v[c] - (c < 3 ? sn : 0.0);
+      dnew[c] = in.fG[i] * (dold[c] + in.rG[i] * dn[c]);
+    }
+    double w = in.K3i[i] * (em - s1) * 3.0 * (s1 - sn);
+#pragma unroll
+    for (int c = 0; c < 6; ++c) w += in.G2i[i] * (dn[c] - dnew[c]) * (dnew[c] - dold[c]);
+    dis += w;
+    trsum += in.K3i[i] * (trd - 3.0 * (s1 - sn));
+#pragma unroll
+    for (int c = 0; c < 6; ++c) evo[c * ss] = dnew[c] + (c < 3 ? s1 : 0.0);
+  }
+  dis /= dt;
+  const double Hn = ep1 > 0.0 ? in.hk * pow(ep1, in.nh) : 0.0;
+  *diss = dis;
+  *coup = -in.theta * (in.alpha0 * trsum / dt + in.beta1 * Hn * dp / dt) + dis;
+}
+
+// ---------------------------------------------------------------------------
+template <typename T, int C>
+__global__ void __launch_bounds__(PT_THREADS) k_init(Pt<T> a, int basic) {
+  const int prob = blockIdx.x / a.bpp;
+  const int blk = blockIdx.x % a.bpp;
+  const ProbInc& in = a.inc[prob];
+  if (blk == 0 && threadIdx.x == 0) {
+    Ctl& c = a.ctl[prob];
+    c.mode = basic ? M_BASIC : M_EVAL;
+    c.newton_it = 0;
+    c.cg_it = 0;
+    c.cg_ready = 0;
+    c.pending = 0;
+    c.status = 0;
+    c.pipelines = 0;
+    c.krylov = 0;
+    c.rr = c.alpha = c.beta = c.res = c.fnorm = c.cg_target = 0.0;
+  }
+  const long long nv = a.nvox;
+  const long long fo = (long long)prob * C * nv;
+  for (long long v = (long long)blk * PT_THREADS + threadIdx.x; v < nv; v += (long long)a.bpp * PT_THREADS) {
+    if constexpr (C == 6) {
+#pragma unroll
+      for (int c = 0; c < 6; ++c) a.x[fo + c * nv + v] = a.xn[fo + c * nv + v] + T(in.dE[c]);
+    } else {
+#pragma unroll
+      for (int c = 0; c < 3; ++c) a.x[fo + c * nv + v] += T(in.dG[c]);
+    }
+  }
+}
+
+template <typename T, int C>
+__global__ void __launch_bounds__(PT_THREADS) k_eval(Pt<T> a) {
+  const int prob = blockIdx.x / a.bpp;
+  const int blk = blockIdx.x % a.bpp;
+  const Ctl& ctl = a.ctl[prob];
+  const int mode = ctl.mode;
+  if (mode != M_EVAL && mode != M_BASIC) return;
+  const bool pending = ctl.pending != 0;
+  const bool want_tan = (mode == M_EVAL);
+  const ProbInc& in = a.inc[prob];
+  const long long nv = a.nvox;
+  const long long fo = (long long)prob * C * nv;
+  const uint8_t* phase = a.phase + (long long)prob * nv;
+  for (long long v = (long long)blk * PT_THREADS + threadIdx.x; v < nv; v += (long long)a.bpp * PT_THREADS) {
+    T e[C];
+#pragma unroll
+    for (int c = 0; c < C; ++c) {
+      T xv = a.x[fo + c * nv + v];
+      if (pending) {
+        xv += a.dx[fo + c * nv + v];
+        a.x[fo + c * nv + v] = xv;
+      }
+      e[c] = xv;
+    }
+    const int ph = phase[v];
+    if constexpr (C == 6) {
+      double sg[6];
+      double ca, cb = 0.0;
+      const long long to = (long long)prob * 2 * nv;
+      if (ph == in.pa_phase) {
+        double ed[6];
+#pragma unroll
+        for (int c = 0; c < 6; ++c) ed[c] = (double)e[c];
+        const double* st = a.state + (long long)prob * a.nstate * nv + v;
+        PaOut o;
+        pa66_point(in, ed, st, nv, nullptr, nullptr, o, nullptr, nullptr);
+#pragma unroll
+        for (int c = 0; c < 6; ++c) sg[c] = o.sig[c];
+        ca = o.a;
+        cb = o.b;
+        if (want_tan && cb != 0.0) {
+          const long long no = (long long)prob * 6 * nv;
+#pragma unroll
+          for (int c = 0; c < 6; ++c) a.tn[no + c * nv + v] = T(o.nd[c]);
+        }
+      } else {
+        const PhaseInc& pi = in.ph[ph];
+        const double tr3 = ((double)e[0] + (double)e[1] + (double)e[2]) * (1.0 / 3.0);
+        const double sph = pi.K3 * (tr3 - pi.alpha_dth) - pi.G2 * tr3;
+#pragma unroll
+        for (int c = 0; c < 6; ++c) sg[c] = pi.G2 * (double)e[c];
+        sg[0] += sph;
+        sg[1] += sph;
+        sg[2] += sph;
+        ca = pi.G2;
+      }
+#pragma unroll
+      for (int c = 0; c < 6; ++c) a.f[fo + c * nv + v] = T(sg[c]);
+      if (want_tan) {
+        a.tab[to + v] = T(ca);
+        a.tab[to + nv + v] = T(cb);
+      }
+    } else {
+      const T kap = T(in.ph[ph].kappa);
+#pragma unroll
+      for (int c = 0; c < C; ++c) a.f[fo + c * nv + v] = kap * e[c];
+    }
+  }
+}
+
+template <typename T, int C>
+__global__ void __launch_bounds__(PT_THREADS) k_cgupdate(Pt<T> a) {
+  __shared__ double red[16];
+  const int prob = blockIdx.x / a.bpp;
+  const int blk = blockIdx.x % a.bpp;
+  const Ctl& ctl = a.ctl[prob];
+  if (ctl.mode != M_CG || !ctl.cg_ready) return;
+  const T alpha = T(ctl.alpha);
+  const bool first = ctl.cg_it == 0;
+  const long long nv = a.nvox;
+  const long long fo = (long long)prob * C * nv;
+  double s = 0.0;
+  for (long long v = (long long)blk * PT_THREADS + threadIdx.x; v < nv; v += (long long)a.bpp * PT_THREADS) {
+#pragma unroll
+    for (int c = 0; c < C; ++c) {
+      const long long o = fo + c * nv + v;
+      const T pv = a.p[o];
+      a.dx[o] = (first ? T(0) : a.dx[o]) + alpha * pv;
+      const T rn = a.r[o] - alpha * a.ap[o];
+      a.r[o] = rn;
+      s += (double)rn * (double)rn;
+    }
+  }
+  double sv[1] = {s};
+  block_sum<1>(sv, red);
+  if (threadIdx.x == 0) a.part[((long long)prob * a.maxblk + blk) * NPART] = sv[0];
+}
+
+template <typename T, int C>
+__global__ void __launch_bounds__(PT_THREADS) k_commit(Pt<T> a) {
+  __shared__ double red[8 * 16];
+  const int prob = blockIdx.x / a.bpp;
+  const int blk = blockIdx.x % a.bpp;
+  const Ctl& ctl = a.ctl[prob];
+  if (ctl.status != 1) return;
+  const ProbInc& in = a.inc[prob];
+  const long long nv = a.nvox;
+  const long long fo = (long long)prob * C * nv;
+  const uint8_t* phase = a.phase + (long long)prob * nv;
+  double acc[8];
+#pragma unroll
+  for (int k = 0; k < 8; ++k) acc[k] = 0.0;
+  for (long long v = (long long)blk * PT_THREADS + threadIdx.x; v < nv; v += (long long)a.bpp * PT_THREADS) {
+    const int ph = phase[v];
+    if constexpr (C == 6) {
+      double e[6], en[6];
+#pragma unroll
+      for (int c = 0; c < 6; ++c) {
+        e[c] = (double)a.x[fo + c * nv + v];
+        en[c] = (double)a.xn[fo + c * nv + v];
+      }
+      double sg[6], dis = 0.0, cpl;
+      if (ph == in.pa_phase) {
+        double* st = a.state + (long long)prob * a.nstate * nv + v;
+        PaOut o;
+        pa66_point(in, e, st, nv, st, en, o, &dis, &cpl);
+#pragma unroll
+        for (int c = 0; c < 6; ++c) sg[c] = o.sig[c];
+      } else {
+        const PhaseInc& pi = in.ph[ph];
+        const double tr3 = (e[0] + e[1] + e[2]) * (1.0 / 3.0);
+        const double sph = pi.K3 * (tr3 - pi.alpha_dth) - pi.G2 * tr3;
+#pragma unroll
+        for (int c = 0; c < 6; ++c) sg[c] = pi.G2 * e[c];
+        sg[0] += sph;
+        sg[1] += sph;
+        sg[2] += sph;
+        const double trd = (e[0] - en[0]) + (e[1] - en[1]) + (e[2] - en[2]);
+        // Gough-Joule: D = -theta eps_dot : C[alpha] (paper Sec. 4, E-glass)
+        cpl = -in.theta * pi.K3 * pi.alpha0 * trd / in.dt;
+      }
+#pragma unroll
+      for (int c = 0; c < 6; ++c) {
+        acc[c] += sg[c];
+        a.xn[fo + c * nv + v] = a.x[fo + c * nv + v];
+        a.f[fo + c * nv + v] = T(sg[c]);
+      }
+      acc[6] += dis;
+      acc[7] += cpl;
+      if (a.pv_diss) {
+        a.pv_diss[(long long)prob * nv + v] = dis;
+        a.pv_coup[(long long)prob * nv + v] = cpl;
+      }
+    } else {
+      const double kap = in.ph[ph].kappa;
+#pragma unroll
+      for (int c = 0; c < 3; ++c) acc[c] -= kap * (double)a.x[fo + c * nv + v];
+    }
+  }
+  block_sum<8>(acc, red);
+  if (threadIdx.x == 0) {
+    double* out = a.part + ((long long)prob * a.maxblk + blk) * NPART;
+#pragma unroll
+    for (int k = 0; k < 8; ++k) out[k] = acc[k];
+  }
+}
+
+// ---------------------------------------------------------------------------
+// per-problem reductions and state transitions (one block per problem)
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ void sum_parts(const double* part, int maxblk, int nblk, int prob, int nk, double* out,
+                                          double* red) {
+  // fixed-order sum over blocks for each of nk entries
+  for (int k = 0; k < nk; ++k) {
+    double s = 0.0;
+    for (int b = threadIdx.x; b < nblk; b += blockDim.x) s += part[((long long)prob * maxblk + b) * NPART + k];
+    double v[1] = {s};
+    block_sum<1>(v, red);
+    if (threadIdx.x == 0) out[k] = v[0];
+    __syncthreads();
+  }
+}
+
+__global__ void __launch_bounds__(PT_THREADS) k_reduce_a(Ctl* ctl, const double* part, int maxblk, int nblk,
+                                                          Limits lim) {
+  __shared__ double red[16];
+  __shared__ double s[2];
+  const int prob = blockIdx.x;
+  Ctl& c = ctl[prob];
+  const int mode = c.mode;
+  if (!(mode == M_EVAL || mode == M_BASIC || (mode == M_CG && !c.cg_ready))) return;
+  sum_parts(part, maxblk, nblk, prob, 2, s, red);
+  if (threadIdx.x != 0) return;
+  c.pipelines += 1;
+  if (mode == M_EVAL) {
+    const double rr = s[0], ff = s[1];
+    const double res = ff > 0.0 ? sqrt(rr / ff) : 0.0;
+    c.res = res;
+    c.fnorm = sqrt(ff);
+    c.newton_it += 1;
+    c.pending = 0;
+    if (!isfinite(res)) {
+      c.mode = M_FAIL;
+      c.status = -4;
+    } else if (res <= lim.tol) {
+      c.mode = M_DONE;
+      c.status = 1;
+    } else if (c.newton_it > lim.max_newton) {
+      c.mode = M_FAIL;
+      c.status = -3;
+    } else {
+      const double eta = lim.linear ? 0.0 : fmin(0.1, res);
+      const double tgt = fmax(eta * sqrt(rr), 0.5 * lim.tol * sqrt(ff));
+      c.cg_target = tgt * tgt;
+      c.rr = rr;
+      c.cg_it = 0;
+      c.cg_ready = 0;
+      c.beta = 0.0;
+      c.mode = M_CG;
+    }
+  } else if (mode == M_CG) {
+    const double pap = s[0];
+    if (!(pap > 0.0) || !isfinite(pap)) {
+      if (c.rr == 0.0) {  // exact solution reached
+        c.mode = M_EVAL;
+        c.pending = 1;
+        c.alpha = 0.0;
+        return;
+      }
+      c.mode = M_FAIL;
+      c.status = -4;
+      return;
+    }
+    c.alpha = c.rr / pap;
+    c.cg_ready = 1;
+  } else {  // basic scheme
+    const double dd = s[0], xx = s[1];
+    const double err = xx > 0.0 ? sqrt(dd / xx) : 0.0;
+    c.res = err;
+    c.newton_it += 1;
+    if (!isfinite(err)) {
+      c.mode = M_FAIL;
+      c.status = -4;
+    } else if (err <= lim.tol) {
+      c.mode = M_DONE;
+      c.status = 1;
+    } else if (c.newton_it >= lim.max_newton) {
+      c.mode = M_FAIL;
+      c.status = -3;
+    }
+  }
+}
+
+__global__ void __launch_bounds__(PT_THREADS) k_reduce_b(Ctl* ctl, const double* part, int maxblk, int nblk,
+                                                          Limits lim) {
+  __shared__ double red[16];
+  __shared__ double s[1];
+  const int prob = blockIdx.x;
+  Ctl& c = ctl[prob];
+  if (c.mode != M_CG || !c.cg_ready) return;
+  sum_parts(part, maxblk, nblk, prob, 1, s, red);
+  if (threadIdx.x != 0) return;
+  const double rn = s[0];
+  c.beta = c.rr > 0.0 ? rn / c.rr : 0.0;
+  c.rr = rn;
+  c.cg_it += 1;
+  c.krylov += 1;
+  c.cg_ready = 0;
+  if (!isfinite(rn)) {
+    c.mode = M_FAIL;
+    c.status = -4;
+  } else if (rn <= c.cg_target || c.cg_it >= lim.max_krylov) {
+    c.mode = M_EVAL;
+    c.pending = 1;
+  }
+}
+
+__global__ void __launch_bounds__(PT_THREADS) k_reduce_out(Ctl* ctl, const double* part, int maxblk, int nblk,
+                                                            int nk, double scale) {
+  __shared__ double red[16];
+  __shared__ double s[NPART];
+  const int prob = blockIdx.x;
+  Ctl& c = ctl[prob];
+  if (c.status != 1) return;
+  sum_parts(part, maxblk, nblk, prob, nk, s, red);
+  if (threadIdx.x == 0)
+    for (int k = 0; k < nk; ++k) c.out[k] = s[k] * scale;
+}
+
+// ---------------------------------------------------------------------------
+// launchers
+// ---------------------------------------------------------------------------
+template <typename T>
+void launch_init_mech(const Pt<T>& a, int scheme, hipStream_t s) {
+  hipLaunchKernelGGL((k_init<T, 6>), dim3(a.nprob * a.bpp), dim3(PT_THREADS), 0, s, a, scheme == 0 ? 1 : 0);
+}
+template <typename T>
+void launch_init_th(const Pt<T>& a, int scheme, hipStream_t s) {
+  hipLaunchKernelGGL((k_init<T, 3>), dim3(a.nprob * a.bpp), dim3(PT_THREADS), 0, s, a, scheme == 0 ? 1 : 0);
+}
+template <typename T>
+void launch_eval(const Pt<T>& a, int C, hipStream_t s) {
+  if (C == 6)
+    hipLaunchKernelGGL((k_eval<T, 6>), dim3(a.nprob * a.bpp), dim3(PT_THREADS), 0, s, a);
+  else
+    hipLaunchKernelGGL((k_eval<T, 3>), dim3(a.nprob * a.bpp), dim3(PT_THREADS), 0, s, a);
+}
+template <typename T>
+void launch_cgupdate(const Pt<T>& a, int C, hipStream_t s) {
+  if (C == 6)
+    hipLaunchKernelGGL((k_cgupdate<T, 6>), dim3(a.nprob * a.bpp), dim3(PT_THREADS), 0, s, a);
+  else
+    hipLaunchKernelGGL((k_cgupdate<T, 3>), dim3(a.nprob * a.bpp), dim3(PT_THREADS), 0, s, a);
+}
+template <typename T>
+void launch_commit(const Pt<T>& a, int C, hipStream_t s) {
+  if (C == 6)
+    hipLaunchKernelGGL((k_commit<T, 6>), dim3(a.nprob * a.bpp), dim3(PT_THREADS), 0, s, a);
+  else
+    hipLaunchKernelGGL((k_commit<T, 3>), dim3(a.nprob * a.bpp), dim3(PT_THREADS), 0, s, a);
+}
+void launch_reduce_a(Ctl* ctl, const double* part, int maxblk, int nblk, int nprob, Limits lim, hipStream_t s) {
+  hipLaunchKernelGGL(k_reduce_a, dim3(nprob), dim3(PT_THREADS), 0, s, ctl, part, maxblk, nblk, lim);
+}
+void launch_reduce_b(Ctl* ctl, const double* part, int maxblk, int nblk, int nprob, Limits lim, hipStream_t s) {
+  hipLaunchKernelGGL(k_reduce_b, dim3(nprob), dim3(PT_THREADS), 0, s, ctl, part, maxblk, nblk, lim);
+}
+void launch_reduce_out(Ctl* ctl, const double* part, int maxblk, int nblk, int nprob, int nk, double scale,
+                       hipStream_t s) {
+  hipLaunchKernelGGL(k_reduce_out, dim3(nprob), dim3(PT_THREADS), 0, s, ctl, part, maxblk, nblk, nk, scale);
+}
+
+#define HOM_INST_PT(T)                                                  \
+  template void launch_init_mech<T>(const Pt<T>&, int, hipStream_t);    \
+  template void launch_init_th<T>(const Pt<T>&, int, hipStream_t);      \
+  template void launch_eval<T>(const Pt<T>&, int, hipStream_t);         \
+  template void launch_cgupdate<T>(const Pt<T>&, int, hipStream_t);     \
+  template void launch_commit<T>(const Pt<T>&, int, hipStream_t);
+HOM_INST_PT(float)
+HOM_INST_PT(double)
+
+}  // namespace hom

@@ -1,0 +1,945 @@
+// Solver runtime (see runtime.h).
+#include "runtime.h"
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <map>
+#include <tuple>
+
+namespace hom {
+
+const char* const kKernelNames[K_COUNT] = {"init",  "eval",     "xfwd",  "yfwd",   "zgreen", "yinv",
+                                           "xinv",  "reduce_a", "cgupd", "reduce_b", "commit", "reduce_out"};
+
+void fail(int code, const std::string& msg) { throw Error{code, msg}; }
+
+void hip_check(hipError_t e, const char* what) {
+  if (e == hipSuccess) return;
+  const int code = (e == hipErrorOutOfMemory || e == hipErrorMemoryAllocation) ? HOM_E_OOM : HOM_E_DEVICE;
+  fail(code, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+// ---------------------------------------------------------------------------
+// profiler
+// ---------------------------------------------------------------------------
+hipEvent_t Profiler::get() {
+  if (!pool.empty()) {
+    hipEvent_t e = pool.back();
+    pool.pop_back();
+    return e;
+  }
+  hipEvent_t e;
+  HIPCHK(hipEventCreate(&e));
+  return e;
+}
+void Profiler::begin(int kind, hipStream_t s) {
+  if (!on) return;
+  cur = kind;
+  ev0 = get();
+  HIPCHK(hipEventRecord(ev0, s));
+}
+void Profiler::end(hipStream_t s) {
+  if (!on) return;
+  hipEvent_t e1 = get();
+  HIPCHK(hipEventRecord(e1, s));
+  pending.push_back({cur, {ev0, e1}});
+}
+void Profiler::collect() {
+  for (auto& p : pending) {
+    float t = 0.f;
+    HIPCHK(hipEventSynchronize(p.second.second));
+    HIPCHK(hipEventElapsedTime(&t, p.second.first, p.second.second));
+    ms[p.first] += t;
+    launches[p.first] += 1;
+    pool.push_back(p.second.first);
+    pool.push_back(p.second.second);
+  }
+  pending.clear();
+}
+Profiler::~Profiler() {
+  for (auto& p : pending) {
+    (void)hipEventDestroy(p.second.first);
+    (void)hipEventDestroy(p.second.second);
+  }
+  for (auto e : pool) (void)hipEventDestroy(e);
+}
+
+// ---------------------------------------------------------------------------
+// laws
+// ---------------------------------------------------------------------------
+void validate_laws(const hom_law* laws, int n) {
+  if (n < 1 || n > HOM_MAX_LAWS) fail(HOM_E_ARG, "n_laws must be in [1, 8]");
+  int npa = 0;
+  for (int i = 0; i < n; ++i) {
+    const hom_law& L = laws[i];
+    auto bad = [&](const char* w) { fail(HOM_E_ARG, "law " + std::to_string(i) + ": " + w); };
+    if (L.kind != HOM_LAW_THERMOELASTIC && L.kind != HOM_LAW_PA66) bad("unknown kind");
+    if (!(L.E > 0.0) || !(L.nu > -1.0 && L.nu < 0.5)) bad("need E > 0 and -1 < nu < 0.5");
+    if (!(L.kappa0 > 0.0) || !(L.c0 >= 0.0) || !(L.theta0 > 0.0)) bad("need kappa0 > 0, c0 >= 0, theta0 > 0");
+    if (!std::isfinite(L.alpha0)) bad("alpha0 must be finite");
+    if (L.kind == HOM_LAW_PA66) {
+      ++npa;
+      if (L.n_maxwell < 0 || L.n_maxwell > HOM_MAX_MAXWELL) bad("n_maxwell out of range");
+      for (int j = 0; j < L.n_maxwell; ++j)
+        if (!(L.E_i[j] >= 0.0) || !std::isfinite(L.log10_tau_i[j])) bad("invalid Maxwell branch");
+      if (!(L.sigma_y0 > 0.0) || !(L.eta0 > 0.0) || !(L.m >= 1.0) || !(L.k_h >= 0.0)) bad("invalid plasticity");
+      if (!(L.n_h > 0.0 && L.n_h <= 1.0)) bad("n_h must be in (0, 1]");
+      if (!std::isfinite(L.C1) || !std::isfinite(L.C2) || !std::isfinite(L.beta1) || !std::isfinite(L.beta2))
+        bad("invalid temperature parameters");
+    }
+  }
+  if (npa > 1) fail(HOM_E_UNSUPPORTED, "at most one PA66 law per setup");
+}
+
+void fill_inc(ProbInc& in, const std::vector<hom_law>& laws, double theta, double dt) {
+  std::memset(&in, 0, sizeof(in));
+  in.theta = theta;
+  in.dt = dt;
+  in.pa_phase = -1;
+  double lmin = 1e300, lmax = -1e300, mmin = 1e300, mmax = -1e300, kmin = 1e300, kmax = -1e300;
+  for (size_t i = 0; i < laws.size(); ++i) {
+    const hom_law& L = laws[i];
+    PhaseInc& ph = in.ph[i];
+    ph.kind = L.kind;
+    ph.alpha0 = L.alpha0;
+    ph.alpha_dth = L.alpha0 * (theta - L.theta0);
+    ph.kappa = L.kappa0;
+    double K, G;
+    if (L.kind == HOM_LAW_THERMOELASTIC) {
+      K = L.E / (3.0 * (1.0 - 2.0 * L.nu));
+      G = L.E / (2.0 * (1.0 + L.nu));
+    } else {
+      in.pa_phase = (int)i;
+      const double d = theta - L.theta_ref;
+      const double a = std::pow(10.0, -L.C1 * d / (L.C2 + d));  // WLF shift
+      const double g1 = std::exp(-L.beta1 * d);                   // softening Gamma(theta, beta1)
+      const double g2 = std::exp(-L.beta2 * d);
+      in.sY = g1 * L.sigma_y0;
+      in.ccoef = dt * in.sY / (g2 * L.eta0);
+      in.hk = g1 * L.k_h;
+      in.nh = L.n_h;
+      in.mexp = L.m;
+      in.beta1 = L.beta1;
+      in.alpha0 = L.alpha0;
+      in.dth = theta - L.theta0;
+      const double Kinf = L.E / (3.0 * (1.0 - 2.0 * L.nu));
+      const double Ginf = L.E / (2.0 * (1.0 + L.nu));
+      K = Kinf;
+      G = Ginf;
+      int nm = 0;
+      for (int j = 0; j < L.n_maxwell; ++j) {
+        const double Ej = L.E_i[j];
+        if (!(Ej > 0.0)) continue;
+        const double tau = std::pow(10.0, L.log10_tau_i[j]);
+        const double Kj = Ej / (3.0 * (1.0 - 2.0 * L.nu));
+        const double Gj = Ej / (2.0 * (1.0 + L.nu));
+        const double tauK = tau * Ej / Kj, tauG = tau * Ej / Gj;
+        const double rK = dt / (a * tauK), rG = dt / (a * tauG);
+        in.K3i[nm] = 3.0 * Kj;
+        in.G2i[nm] = 2.0 * Gj;
+        in.rK[nm] = rK;
+        in.rG[nm] = rG;
+        in.fK[nm] = 1.0 / (1.0 + rK);
+        in.fG[nm] = 1.0 / (1.0 + rG);
+        K += Kj * in.fK[nm];
+        G += Gj * in.fG[nm];
+        ++nm;
+      }
+      in.nm = nm;
+      in.Kinf3 = 3.0 * Kinf;
+      in.Ginf2 = 2.0 * Ginf;
+      in.Kbar3 = 3.0 * K;
+      in.Gbar2 = 2.0 * G;
+    }
+    ph.K3 = 3.0 * K;
+    ph.G2 = 2.0 * G;
+    const double lam = K - 2.0 * G / 3.0;
+    lmin = std::min(lmin, lam);
+    lmax = std::max(lmax, lam);
+    mmin = std::min(mmin, G);
+    mmax = std::max(mmax, G);
+    kmin = std::min(kmin, L.kappa0);
+    kmax = std::max(kmax, L.kappa0);
+  }
+  in.lam0 = 0.5 * (lmin + lmax);
+  in.mu0 = 0.5 * (mmin + mmax);
+  in.kappa0 = 0.5 * (kmin + kmax);
+}
+
+static int pa66_nstate(const std::vector<hom_law>& laws) {
+  for (auto& L : laws)
+    if (L.kind == HOM_LAW_PA66) {
+      int nm = 0;
+      for (int j = 0; j < L.n_maxwell; ++j)
+        if (L.E_i[j] > 0.0) ++nm;
+      return 7 + 6 * nm;
+    }
+  return 0;
+}
+
+// ---------------------------------------------------------------------------
+// twiddles
+// ---------------------------------------------------------------------------
+template <typename T>
+static std::vector<c2<T>> twiddles(int n) {
+  std::vector<c2<T>> w(n);
+  for (int j = 0; j < n; ++j) {
+    // exp(-2 pi i j / n) from an exactly reduced angle
+    const long double ang = -2.0L * 3.14159265358979323846264338327950288L * (long double)j / (long double)n;
+    w[j].x = (T)std::cos(ang);
+    w[j].y = (T)std::sin(ang);
+  }
+  return w;
+}
+
+// ---------------------------------------------------------------------------
+// dispatch of the pipeline launchers by transform length
+// ---------------------------------------------------------------------------
+#define HOM_DISPATCH(n, call)                 \
+  switch (n) {                                \
+    case 16: { constexpr int NN = 16; return call; }  \
+    case 24: { constexpr int NN = 24; return call; }  \
+    case 32: { constexpr int NN = 32; return call; }  \
+    case 48: { constexpr int NN = 48; return call; }  \
+    case 64: { constexpr int NN = 64; return call; }  \
+    case 96: { constexpr int NN = 96; return call; }  \
+    case 128: { constexpr int NN = 128; return call; } \
+    case 256: { constexpr int NN = 256; return call; } \
+  }                                           \
+  fail(HOM_E_UNSUPPORTED, "unsupported transform length " + std::to_string(n));
+
+template <typename T>
+LaunchInfo run_xfwd(const Pipe<T>& a, hipStream_t s, bool dry) {
+  HOM_DISPATCH(a.nx, (xfwd_launch<T, NN>(a, s, dry)))
+}
+template <typename T>
+LaunchInfo run_xinv(const Pipe<T>& a, hipStream_t s, bool dry) {
+  HOM_DISPATCH(a.nx, (xinv_launch<T, NN>(a, s, dry)))
+}
+template <typename T>
+LaunchInfo run_ypass(const Pipe<T>& a, int tx, int inverse, hipStream_t s, bool dry) {
+  HOM_DISPATCH(a.ny, (ypass_launch<T, NN>(a, tx, inverse, s, dry)))
+}
+template <typename T>
+LaunchInfo run_zgreen(const Pipe<T>& a, int tx, hipStream_t s, bool dry) {
+  HOM_DISPATCH(a.nz, (zgreen_launch<T, NN>(a, tx, s, dry)))
+}
+
+static bool launch_ok(const LaunchInfo& li) { return li.threads <= 1024 && li.lds <= 160 * 1024; }
+
+// ---------------------------------------------------------------------------
+// a group of problems sharing one grid
+// ---------------------------------------------------------------------------
+template <typename T>
+struct Group {
+  int nx = 0, ny = 0, nz = 0, P = 0;
+  long long nvox = 0;
+  int nprob = 0;
+  double len[3] = {1, 1, 1};
+  int nstate = 0;
+  std::vector<int> members;
+  std::vector<void*> allocs;
+  size_t bytes = 0;
+
+  uint8_t* phase = nullptr;
+  T *xm = nullptr, *xnm = nullptr, *f = nullptr, *r = nullptr, *p = nullptr, *ap = nullptr, *dx = nullptr;
+  T *tab = nullptr, *tn = nullptr, *xt = nullptr;
+  c2<T>* spec = nullptr;
+  double* state = nullptr;
+  Ctl *ctl_m = nullptr, *ctl_t = nullptr;
+  ProbInc* inc_d = nullptr;
+  ProbInc* inc_h = nullptr;
+  Ctl* ctl_h = nullptr;
+  double* part = nullptr;
+  int maxblk = 0;
+  c2<T>* tw[3] = {nullptr, nullptr, nullptr};
+  int txy[2] = {4, 4}, txz[2] = {4, 4};  // [mech, thermal]
+  int pt_bpp = 1;
+  int xblocks = 1;
+  hipGraphExec_t graph[2] = {nullptr, nullptr};
+  int graph_k[2] = {0, 0};
+  std::vector<std::array<double, 6>> En;
+  std::vector<std::array<double, 3>> Gp;
+  std::vector<double> c0mean;
+
+  template <typename U>
+  U* dalloc(size_t count) {
+    void* ptr = nullptr;
+    HIPCHK(hipMalloc(&ptr, count * sizeof(U) + 256));
+    allocs.push_back(ptr);
+    bytes += count * sizeof(U);
+    HIPCHK(hipMemset(ptr, 0, count * sizeof(U)));
+    return static_cast<U*>(ptr);
+  }
+
+  ~Group() {
+    for (int i = 0; i < 2; ++i)
+      if (graph[i]) (void)hipGraphExecDestroy(graph[i]);
+    for (void* ptr : allocs) (void)hipFree(ptr);
+    if (inc_h) (void)hipHostFree(inc_h);
+    if (ctl_h) (void)hipHostFree(ctl_h);
+  }
+
+  void alloc(bool with_state) {
+    P = nx / 2 + 1;
+    nvox = (long long)nx * ny * nz;
+    const long long nm = (long long)nprob * nvox;
+    phase = dalloc<uint8_t>(nm);
+    xm = dalloc<T>(6 * nm);
+    xnm = dalloc<T>(6 * nm);
+    f = dalloc<T>(6 * nm);
+    r = dalloc<T>(6 * nm);
+    p = dalloc<T>(6 * nm);
+    ap = dalloc<T>(6 * nm);
+    dx = dalloc<T>(6 * nm);
+    tab = dalloc<T>(2 * nm);
+    tn = dalloc<T>(6 * nm);
+    xt = dalloc<T>(3 * nm);
+    spec = dalloc<c2<T>>((size_t)nprob * nz * ny * P * 6);
+    if (with_state && nstate > 0) state = dalloc<double>((size_t)nstate * nm);
+    ctl_m = dalloc<Ctl>(nprob);
+    ctl_t = dalloc<Ctl>(nprob);
+    inc_d = dalloc<ProbInc>(nprob);
+    HIPCHK(hipHostMalloc(reinterpret_cast<void**>(&inc_h), sizeof(ProbInc) * nprob));
+    HIPCHK(hipHostMalloc(reinterpret_cast<void**>(&ctl_h), sizeof(Ctl) * nprob));
+    std::memset(inc_h, 0, sizeof(ProbInc) * nprob);
+    // blocks per problem of the pointwise kernels
+    pt_bpp = (int)std::min<long long>((nvox + 255) / 256, std::max<long long>(1, 8192 / nprob));
+    pt_bpp = std::max(pt_bpp, 1);
+    const int nl = x_lines(nx, sizeof(T) == 8);
+    xblocks = (ny * nz + nl - 1) / nl;
+    maxblk = std::max(pt_bpp, xblocks);
+    part = dalloc<double>((size_t)nprob * maxblk * NPART);
+    for (int d = 0; d < 3; ++d) {
+      const int n = d == 0 ? nx : (d == 1 ? ny : nz);
+      auto w = twiddles<T>(n);
+      tw[d] = dalloc<c2<T>>(n);
+      HIPCHK(hipMemcpy(tw[d], w.data(), n * sizeof(c2<T>), hipMemcpyHostToDevice));
+    }
+    En.assign(nprob, {0, 0, 0, 0, 0, 0});
+    Gp.assign(nprob, {0, 0, 0});
+  }
+
+  Pipe<T> pipe(int phys, int green) const {
+    Pipe<T> a;
+    a.nx = nx;
+    a.ny = ny;
+    a.nz = nz;
+    a.P = P;
+    a.nvox = nvox;
+    a.nprob = nprob;
+    a.C = phys == 0 ? 6 : 3;
+    a.phase = phase;
+    a.x = phys == 0 ? xm : xt;
+    a.f = f;
+    a.r = r;
+    a.p = p;
+    a.ap = ap;
+    a.dx = dx;
+    a.tab = tab;
+    a.tn = tn;
+    a.spec = spec;
+    a.ctl = phys == 0 ? ctl_m : ctl_t;
+    a.inc = inc_d;
+    a.part = part;
+    a.maxblk = maxblk;
+    a.twx = tw[0];
+    a.twy = tw[1];
+    a.twz = tw[2];
+    for (int d = 0; d < 3; ++d) a.len[d] = len[d];
+    a.green = green;
+    return a;
+  }
+
+  Pt<T> pt(int phys) const {
+    Pt<T> a;
+    a.nvox = nvox;
+    a.nprob = nprob;
+    a.bpp = pt_bpp;
+    a.phase = phase;
+    a.x = phys == 0 ? xm : xt;
+    a.xn = xnm;
+    a.f = f;
+    a.r = r;
+    a.p = p;
+    a.ap = ap;
+    a.dx = dx;
+    a.tab = tab;
+    a.tn = tn;
+    a.state = state;
+    a.nstate = nstate;
+    a.ctl = phys == 0 ? ctl_m : ctl_t;
+    a.inc = inc_d;
+    a.part = part;
+    a.maxblk = maxblk;
+    a.pv_diss = nullptr;
+    a.pv_coup = nullptr;
+    return a;
+  }
+};
+
+// ---------------------------------------------------------------------------
+// batch of groups
+// ---------------------------------------------------------------------------
+template <typename T>
+class BatchT : public BatchImpl {
+ public:
+  std::vector<std::unique_ptr<Group<T>>> groups;
+  std::vector<std::pair<int, int>> where;
+  std::vector<hom_law> laws;
+  hom_options opts;
+  hipStream_t stream = nullptr;
+  bool own_stream = false;
+  Profiler prof;
+  bool linear_mech = true;
+
+  ~BatchT() override {
+    groups.clear();
+    if (own_stream && stream) (void)hipStreamDestroy(stream);
+  }
+
+  const Profiler& profiler() const override { return prof; }
+
+  size_t device_bytes() const override {
+    size_t b = 0;
+    for (auto& g : groups) b += g->bytes;
+    return b;
+  }
+
+  void init(int nprob, const hom_grid* grids, const uint8_t* const* phases, const hom_law* lw, int nlaws,
+            const hom_options& o) {
+    opts = o;
+    laws.assign(lw, lw + nlaws);
+    for (auto& L : laws)
+      if (L.kind == HOM_LAW_PA66) linear_mech = false;
+    prof.on = o.profile != 0;
+    if (o.stream) {
+      stream = static_cast<hipStream_t>(o.stream);
+    } else {
+      HIPCHK(hipStreamCreateWithFlags(&stream, hipStreamNonBlocking));
+      own_stream = true;
+    }
+    // group problems by grid
+    std::map<std::tuple<int, int, int, double, double, double>, int> key;
+    where.resize(nprob);
+    for (int i = 0; i < nprob; ++i) {
+      const hom_grid& g = grids[i];
+      for (int d = 0; d < 3; ++d) {
+        if (!supported_n(g.n[d]))
+          fail(HOM_E_UNSUPPORTED, "grid size " + std::to_string(g.n[d]) +
+                                      " not supported (16, 24, 32, 48, 64, 96, 128, 256)");
+        if (!(g.len[d] > 0.0)) fail(HOM_E_ARG, "cell lengths must be positive");
+      }
+      auto k = std::make_tuple(g.n[0], g.n[1], g.n[2], g.len[0], g.len[1], g.len[2]);
+      auto it = key.find(k);
+      int gi;
+      if (it == key.end()) {
+        gi = (int)groups.size();
+        key[k] = gi;
+        groups.emplace_back(new Group<T>());
+        auto& G = *groups.back();
+        G.nx = g.n[0];
+        G.ny = g.n[1];
+        G.nz = g.n[2];
+        for (int d = 0; d < 3; ++d) G.len[d] = g.len[d];
+      } else {
+        gi = it->second;
+      }
+      where[i] = {gi, (int)groups[gi]->members.size()};
+      groups[gi]->members.push_back(i);
+    }
+    const int nst = pa66_nstate(laws);
+    for (auto& gp : groups) {
+      auto& G = *gp;
+      G.nprob = (int)G.members.size();
+      G.nstate = nst;
+      G.alloc(nst > 0);
+      std::vector<uint8_t> buf((size_t)G.nprob * G.nx * G.ny * G.nz);
+      G.c0mean.assign(G.nprob, 0.0);
+      const long long nv = (long long)G.nx * G.ny * G.nz;
+      for (int j = 0; j < G.nprob; ++j) {
+        const uint8_t* src = phases[G.members[j]];
+        if (!src) fail(HOM_E_ARG, "null phase array");
+        std::vector<long long> cnt(256, 0);
+        for (long long v = 0; v < nv; ++v) {
+          if (src[v] >= laws.size()) fail(HOM_E_ARG, "phase id " + std::to_string(src[v]) + " has no law");
+          ++cnt[src[v]];
+        }
+        double c0 = 0.0;
+        for (size_t l = 0; l < laws.size(); ++l) c0 += laws[l].c0 * (double)cnt[l] / (double)nv;
+        G.c0mean[j] = c0;
+        std::memcpy(buf.data() + (size_t)j * nv, src, nv);
+      }
+      HIPCHK(hipMemcpy(G.phase, buf.data(), buf.size(), hipMemcpyHostToDevice));
+      if (opts.autotune) autotune(G);
+    }
+    HIPCHK(hipDeviceSynchronize());
+  }
+
+  // time the y / z tile widths on this group's data and keep the fastest
+  void autotune(Group<T>& G) {
+    hipEvent_t e0, e1;
+    HIPCHK(hipEventCreate(&e0));
+    HIPCHK(hipEventCreate(&e1));
+    std::vector<Ctl> c(G.nprob);
+    for (auto& x : c) {
+      std::memset(&x, 0, sizeof(Ctl));
+      x.mode = M_EVAL;
+    }
+    for (int phys = 0; phys < 2; ++phys) {
+      Ctl* ctl = phys == 0 ? G.ctl_m : G.ctl_t;
+      HIPCHK(hipMemcpy(ctl, c.data(), sizeof(Ctl) * G.nprob, hipMemcpyHostToDevice));
+      Pipe<T> a = G.pipe(phys, phys == 0 ? G_PROJ : G_GRADPROJ);
+      for (int pass = 0; pass < 2; ++pass) {
+        float best = 1e30f;
+        int bt = 4;
+        for (int tx : kTileChoices) {
+          LaunchInfo li = pass == 0 ? run_ypass<T>(a, tx, 0, stream, true) : run_zgreen<T>(a, tx, stream, true);
+          if (!launch_ok(li)) continue;
+          for (int w = 0; w < 2; ++w) pass == 0 ? run_ypass<T>(a, tx, 0, stream) : run_zgreen<T>(a, tx, stream);
+          HIPCHK(hipEventRecord(e0, stream));
+          for (int w = 0; w < 3; ++w) pass == 0 ? run_ypass<T>(a, tx, 0, stream) : run_zgreen<T>(a, tx, stream);
+          HIPCHK(hipEventRecord(e1, stream));
+          HIPCHK(hipEventSynchronize(e1));
+          float t;
+          HIPCHK(hipEventElapsedTime(&t, e0, e1));
+          if (t < best) {
+            best = t;
+            bt = tx;
+          }
+        }
+        (pass == 0 ? G.txy : G.txz)[phys] = bt;
+      }
+      std::memset(c.data(), 0, sizeof(Ctl) * G.nprob);
+      HIPCHK(hipMemcpy(ctl, c.data(), sizeof(Ctl) * G.nprob, hipMemcpyHostToDevice));
+    }
+    HIPCHK(hipMemset(G.spec, 0, sizeof(c2<T>) * (size_t)G.nprob * G.nz * G.ny * G.P * 6));
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+  }
+
+  void check_tiles(Group<T>& G, int phys) {
+    Pipe<T> a = G.pipe(phys, 0);
+    for (int pass = 0; pass < 2; ++pass) {
+      int& tx = (pass == 0 ? G.txy : G.txz)[phys];
+      LaunchInfo li = pass == 0 ? run_ypass<T>(a, tx, 0, stream, true) : run_zgreen<T>(a, tx, stream, true);
+      if (!launch_ok(li)) tx = 2;
+      li = pass == 0 ? run_ypass<T>(a, tx, 0, stream, true) : run_zgreen<T>(a, tx, stream, true);
+      if (!launch_ok(li)) fail(HOM_E_UNSUPPORTED, "no valid tile for this grid");
+    }
+    LaunchInfo lx = run_xfwd<T>(a, stream, true);
+    LaunchInfo li = run_xinv<T>(a, stream, true);
+    if (!launch_ok(lx) || !launch_ok(li)) fail(HOM_E_UNSUPPORTED, "x-pass does not fit the work-group limits");
+  }
+
+  Limits limits(int phys) const {
+    Limits lim;
+    const bool basic = opts.scheme == HOM_SCHEME_BASIC;
+    lim.tol = phys == 0 ? opts.tol : (opts.thermal_tol > 0 ? opts.thermal_tol : opts.tol);
+    lim.max_newton = opts.max_iter > 0 ? opts.max_iter : (basic ? 5000 : 40);
+    lim.max_krylov = opts.max_krylov > 0 ? opts.max_krylov : 500;
+    lim.linear = (phys == 1 || linear_mech) ? 1 : 0;
+    return lim;
+  }
+
+  void iteration(Group<T>& G, int phys, bool basic) {
+    const int green = phys == 0 ? (basic ? G_GAMMA0 : G_PROJ) : (basic ? G_GAMMA_TH : G_GRADPROJ);
+    Pipe<T> a = G.pipe(phys, green);
+    Pt<T> q = G.pt(phys);
+    const int C = phys == 0 ? 6 : 3;
+    const Limits lim = limits(phys);
+    Ctl* ctl = phys == 0 ? G.ctl_m : G.ctl_t;
+    prof.begin(K_EVAL, stream);
+    launch_eval<T>(q, C, stream);
+    prof.end(stream);
+    prof.begin(K_XFWD, stream);
+    run_xfwd<T>(a, stream);
+    prof.end(stream);
+    prof.begin(K_YFWD, stream);
+    run_ypass<T>(a, G.txy[phys], 0, stream);
+    prof.end(stream);
+    prof.begin(K_ZGREEN, stream);
+    run_zgreen<T>(a, G.txz[phys], stream);
+    prof.end(stream);
+    prof.begin(K_YINV, stream);
+    run_ypass<T>(a, G.txy[phys], 1, stream);
+    prof.end(stream);
+    prof.begin(K_XINV, stream);
+    run_xinv<T>(a, stream);
+    prof.end(stream);
+    prof.begin(K_REDA, stream);
+    launch_reduce_a(ctl, G.part, G.maxblk, G.xblocks, G.nprob, lim, stream);
+    prof.end(stream);
+    if (!basic) {
+      prof.begin(K_CGUPD, stream);
+      launch_cgupdate<T>(q, C, stream);
+      prof.end(stream);
+      prof.begin(K_REDB, stream);
+      launch_reduce_b(ctl, G.part, G.maxblk, G.pt_bpp, G.nprob, lim, stream);
+      prof.end(stream);
+    }
+  }
+
+  int chunk_size(const Group<T>& G) const {
+    if (opts.chunk > 0) return opts.chunk;
+    return (G.nvox * G.nprob >= (1LL << 22)) ? 4 : 16;
+  }
+
+  void run_chunk(Group<T>& G, int phys, bool basic, int k) {
+    const bool graph = opts.use_graph && !prof.on;
+    if (!graph) {
+      for (int i = 0; i < k; ++i) iteration(G, phys, basic);
+      return;
+    }
+    if (!G.graph[phys] || G.graph_k[phys] != k) {
+      if (G.graph[phys]) HIPCHK(hipGraphExecDestroy(G.graph[phys]));
+      hipGraph_t gr;
+      HIPCHK(hipStreamBeginCapture(stream, hipStreamCaptureModeThreadLocal));
+      for (int i = 0; i < k; ++i) iteration(G, phys, basic);
+      HIPCHK(hipStreamEndCapture(stream, &gr));
+      HIPCHK(hipGraphInstantiate(&G.graph[phys], gr, nullptr, nullptr, 0));
+      HIPCHK(hipGraphDestroy(gr));
+      G.graph_k[phys] = k;
+    }
+    HIPCHK(hipGraphLaunch(G.graph[phys], stream));
+  }
+
+  void solve_phys(Group<T>& G, int phys) {
+    const bool basic = opts.scheme == HOM_SCHEME_BASIC;
+    Pt<T> q = G.pt(phys);
+    check_tiles(G, phys);
+    prof.begin(K_INIT, stream);
+    if (phys == 0)
+      launch_init_mech<T>(q, opts.scheme, stream);
+    else
+      launch_init_th<T>(q, opts.scheme, stream);
+    prof.end(stream);
+    const Limits lim = limits(phys);
+    const long long cap = basic ? (long long)lim.max_newton + 2
+                                : (long long)(lim.max_newton + 1) * (lim.max_krylov + 2);
+    const int k = chunk_size(G);
+    Ctl* ctl = phys == 0 ? G.ctl_m : G.ctl_t;
+    long long done_its = 0;
+    for (;;) {
+      run_chunk(G, phys, basic, k);
+      done_its += k;
+      HIPCHK(hipMemcpyAsync(G.ctl_h, ctl, sizeof(Ctl) * G.nprob, hipMemcpyDeviceToHost, stream));
+      HIPCHK(hipStreamSynchronize(stream));
+      prof.collect();
+      int active = 0;
+      for (int j = 0; j < G.nprob; ++j) active += pipeline_mode_host(G.ctl_h[j].mode);
+      if (!active || done_its > cap) break;
+    }
+    prof.begin(K_COMMIT, stream);
+    launch_commit<T>(q, phys == 0 ? 6 : 3, stream);
+    prof.end(stream);
+    prof.begin(K_REDOUT, stream);
+    launch_reduce_out(ctl, G.part, G.maxblk, G.pt_bpp, G.nprob, phys == 0 ? 8 : 3, 1.0 / (double)G.nvox, stream);
+    prof.end(stream);
+    HIPCHK(hipMemcpyAsync(G.ctl_h, ctl, sizeof(Ctl) * G.nprob, hipMemcpyDeviceToHost, stream));
+    HIPCHK(hipStreamSynchronize(stream));
+    prof.collect();
+  }
+
+  static int pipeline_mode_host(int m) { return (m == M_EVAL || m == M_CG || m == M_BASIC) ? 1 : 0; }
+
+  void solve(const double* strain, const hom_macro_temp* temp, const double* dt, hom_result* out) override {
+    const int n = (int)where.size();
+    for (int i = 0; i < n; ++i) {
+      if (!(dt[i] > 0.0) || !std::isfinite(dt[i])) fail(HOM_E_ARG, "dt must be positive and finite");
+      if (!(temp[i].theta > 0.0) || !std::isfinite(temp[i].theta)) fail(HOM_E_ARG, "theta must be positive");
+      for (int c = 0; c < 6; ++c)
+        if (!std::isfinite(strain[6 * i + c])) fail(HOM_E_ARG, "macro strain must be finite");
+      for (int c = 0; c < 3; ++c)
+        if (!std::isfinite(temp[i].grad[c])) fail(HOM_E_ARG, "temperature gradient must be finite");
+    }
+    const double sq2 = std::sqrt(2.0);
+    const double w[6] = {1, 1, 1, sq2, sq2, sq2};
+    for (auto& gp : groups) {
+      Group<T>& G = *gp;
+      for (int j = 0; j < G.nprob; ++j) {
+        const int i = G.members[j];
+        ProbInc& in = G.inc_h[j];
+        fill_inc(in, laws, temp[i].theta, dt[i]);
+        for (int c = 0; c < 6; ++c) in.dE[c] = w[c] * strain[6 * i + c] - G.En[j][c];
+        for (int c = 0; c < 3; ++c) in.dG[c] = temp[i].grad[c] - G.Gp[j][c];
+      }
+      HIPCHK(hipMemcpyAsync(G.inc_d, G.inc_h, sizeof(ProbInc) * G.nprob, hipMemcpyHostToDevice, stream));
+      solve_phys(G, 0);
+      std::vector<Ctl> mech(G.ctl_h, G.ctl_h + G.nprob);
+      // the conduction field now holds the new mean gradient
+      for (int j = 0; j < G.nprob; ++j)
+        for (int c = 0; c < 3; ++c) G.Gp[j][c] = temp[G.members[j]].grad[c];
+      solve_phys(G, 1);
+      for (int j = 0; j < G.nprob; ++j) {
+        const int i = G.members[j];
+        const Ctl& cm = mech[j];
+        const Ctl& ct = G.ctl_h[j];
+        hom_result& r = out[i];
+        std::memset(&r, 0, sizeof(r));
+        for (int c = 0; c < 6; ++c) r.stress[c] = cm.out[c] / w[c];
+        for (int c = 0; c < 3; ++c) r.heat_flux[c] = ct.out[c];
+        r.dissipation = cm.out[6];
+        r.coupling = cm.out[7];
+        r.heat_capacity = G.c0mean[j];
+        r.residual = cm.res;
+        r.newton_iters = cm.newton_it;
+        r.krylov_iters = cm.krylov;
+        r.thermal_iters = ct.krylov > 0 ? ct.krylov : ct.newton_it;
+        r.pipelines = cm.pipelines;
+        r.thermal_pipelines = ct.pipelines;
+        int st = HOM_OK;
+        if (cm.status != 1) st = cm.status < 0 ? cm.status : HOM_E_NOT_CONVERGED;
+        if (st == HOM_OK && ct.status != 1) st = ct.status < 0 ? ct.status : HOM_E_NOT_CONVERGED;
+        r.status = st;
+        if (cm.status == 1)
+          for (int c = 0; c < 6; ++c) G.En[j][c] = w[c] * strain[6 * i + c];
+      }
+    }
+  }
+
+  // ---- checkpoint: xn, xt, state, macro history -------------------------
+  size_t state_size() const override {
+    size_t s = 16;
+    for (auto& gp : groups) {
+      const auto& G = *gp;
+      const size_t nm = (size_t)G.nprob * G.nvox;
+      s += nm * 9 * sizeof(T) + (G.state ? nm * G.nstate * sizeof(double) : 0) + G.nprob * 9 * sizeof(double);
+    }
+    return s;
+  }
+  void get_state(void* buf) override {
+    char* p = static_cast<char*>(buf);
+    const uint64_t magic = 0x484f4d5354415445ull, tsz = sizeof(T);
+    std::memcpy(p, &magic, 8);
+    std::memcpy(p + 8, &tsz, 8);
+    p += 16;
+    for (auto& gp : groups) {
+      auto& G = *gp;
+      const size_t nm = (size_t)G.nprob * G.nvox;
+      HIPCHK(hipMemcpy(p, G.xnm, nm * 6 * sizeof(T), hipMemcpyDeviceToHost));
+      p += nm * 6 * sizeof(T);
+      HIPCHK(hipMemcpy(p, G.xt, nm * 3 * sizeof(T), hipMemcpyDeviceToHost));
+      p += nm * 3 * sizeof(T);
+      if (G.state) {
+        HIPCHK(hipMemcpy(p, G.state, nm * G.nstate * sizeof(double), hipMemcpyDeviceToHost));
+        p += nm * G.nstate * sizeof(double);
+      }
+      for (int j = 0; j < G.nprob; ++j) {
+        std::memcpy(p, G.En[j].data(), 6 * sizeof(double));
+        std::memcpy(p + 6 * sizeof(double), G.Gp[j].data(), 3 * sizeof(double));
+        p += 9 * sizeof(double);
+      }
+    }
+  }
+  void set_state(const void* buf) override {
+    const char* p = static_cast<const char*>(buf);
+    uint64_t magic, tsz;
+    std::memcpy(&magic, p, 8);
+    std::memcpy(&tsz, p + 8, 8);
+    if (magic != 0x484f4d5354415445ull || tsz != sizeof(T)) fail(HOM_E_ARG, "state buffer does not match context");
+    p += 16;
+    for (auto& gp : groups) {
+      auto& G = *gp;
+      const size_t nm = (size_t)G.nprob * G.nvox;
+      HIPCHK(hipMemcpy(G.xnm, p, nm * 6 * sizeof(T), hipMemcpyHostToDevice));
+      HIPCHK(hipMemcpy(G.xm, p, nm * 6 * sizeof(T), hipMemcpyHostToDevice));
+      p += nm * 6 * sizeof(T);
+      HIPCHK(hipMemcpy(G.xt, p, nm * 3 * sizeof(T), hipMemcpyHostToDevice));
+      p += nm * 3 * sizeof(T);
+      if (G.state) {
+        HIPCHK(hipMemcpy(G.state, p, nm * G.nstate * sizeof(double), hipMemcpyHostToDevice));
+        p += nm * G.nstate * sizeof(double);
+      }
+      for (int j = 0; j < G.nprob; ++j) {
+        std::memcpy(G.En[j].data(), p, 6 * sizeof(double));
+        std::memcpy(G.Gp[j].data(), p + 6 * sizeof(double), 3 * sizeof(double));
+        p += 9 * sizeof(double);
+      }
+    }
+  }
+
+  void get_field(int which, double* out, size_t count) override {
+    if (groups.size() != 1 || groups[0]->nprob != 1) fail(HOM_E_ARG, "fields are per single-problem context");
+    auto& G = *groups[0];
+    const size_t nv = G.nvox;
+    int nc;
+    const void* src;
+    bool dbl = false;
+    switch (which) {
+      case HOM_FIELD_STRAIN: nc = 6; src = G.xm; break;
+      case HOM_FIELD_STRESS: nc = 6; src = G.f; break;
+      case HOM_FIELD_GRADIENT: nc = 3; src = G.xt; break;
+      case HOM_FIELD_STATE:
+        if (!G.state) fail(HOM_E_ARG, "no internal variables (no PA66 law)");
+        nc = G.nstate;
+        src = G.state;
+        dbl = true;
+        break;
+      default: fail(HOM_E_ARG, "unknown field");
+    }
+    if (count != nv * nc) fail(HOM_E_ARG, "field buffer size mismatch: need " + std::to_string(nv * nc));
+    HIPCHK(hipStreamSynchronize(stream));
+    if (dbl) {
+      HIPCHK(hipMemcpy(out, src, count * sizeof(double), hipMemcpyDeviceToHost));
+    } else {
+      std::vector<T> tmp(count);
+      HIPCHK(hipMemcpy(tmp.data(), src, count * sizeof(T), hipMemcpyDeviceToHost));
+      for (size_t i = 0; i < count; ++i) out[i] = (double)tmp[i];
+    }
+  }
+};
+
+std::unique_ptr<BatchImpl> make_batch(int nprob, const hom_grid* grids, const uint8_t* const* phases,
+                                      const hom_law* laws, int nlaws, const hom_options& opts) {
+  if (nprob < 1) fail(HOM_E_ARG, "need at least one problem");
+  if (!grids || !phases || !laws) fail(HOM_E_ARG, "null argument");
+  validate_laws(laws, nlaws);
+  if (!(opts.tol > 0.0)) fail(HOM_E_ARG, "tol must be positive");
+  if (opts.scheme != HOM_SCHEME_BASIC && opts.scheme != HOM_SCHEME_NEWTON_CG) fail(HOM_E_ARG, "unknown scheme");
+  if (opts.precision == HOM_FP64) {
+    auto b = std::make_unique<BatchT<double>>();
+    b->init(nprob, grids, phases, laws, nlaws, opts);
+    return b;
+  }
+  if (opts.precision == HOM_FP32) {
+    auto b = std::make_unique<BatchT<float>>();
+    b->init(nprob, grids, phases, laws, nlaws, opts);
+    return b;
+  }
+  fail(HOM_E_ARG, "unknown precision");
+}
+
+// ---------------------------------------------------------------------------
+// kernel-level entry points
+// ---------------------------------------------------------------------------
+template <typename T>
+static void apply_operator_t(const hom_grid& g, int ncomp, int op, double p0, double p1, const double* in,
+                             double* out) {
+  Group<T> G;
+  G.nx = g.n[0];
+  G.ny = g.n[1];
+  G.nz = g.n[2];
+  for (int d = 0; d < 3; ++d) G.len[d] = g.len[d];
+  G.nprob = 1;
+  G.alloc(false);
+  const size_t nv = G.nvox;
+  std::vector<T> tmp(nv * ncomp);
+  for (size_t i = 0; i < tmp.size(); ++i) tmp[i] = (T)in[i];
+  HIPCHK(hipMemcpy(G.f, tmp.data(), tmp.size() * sizeof(T), hipMemcpyHostToDevice));
+  Ctl c;
+  std::memset(&c, 0, sizeof(c));
+  c.mode = M_EVAL;
+  HIPCHK(hipMemcpy(G.ctl_m, &c, sizeof(c), hipMemcpyHostToDevice));
+  ProbInc inc;
+  std::memset(&inc, 0, sizeof(inc));
+  inc.lam0 = p0;
+  inc.mu0 = p1;
+  inc.kappa0 = p0;
+  HIPCHK(hipMemcpy(G.inc_d, &inc, sizeof(inc), hipMemcpyHostToDevice));
+  const int green = op;
+  Pipe<T> a = G.pipe(0, green);
+  a.C = ncomp;
+  a.ctl = G.ctl_m;
+  hipStream_t s = nullptr;
+  int tx = 4;
+  if (!launch_ok(run_zgreen<T>(a, tx, s, true))) tx = 2;
+  (void)hipGetLastError();
+  run_xfwd<T>(a, s);
+  hip_check(hipGetLastError(), "xfwd launch");
+  run_ypass<T>(a, tx, 0, s);
+  hip_check(hipGetLastError(), "ypass launch");
+  run_zgreen<T>(a, tx, s);
+  hip_check(hipGetLastError(), "zgreen launch");
+  run_ypass<T>(a, tx, 1, s);
+  run_xinv<T>(a, s);
+  hip_check(hipGetLastError(), "xinv launch");
+  HIPCHK(hipDeviceSynchronize());
+  HIPCHK(hipMemcpy(tmp.data(), G.r, tmp.size() * sizeof(T), hipMemcpyDeviceToHost));
+  for (size_t i = 0; i < tmp.size(); ++i) out[i] = -(double)tmp[i];
+}
+
+void apply_operator(const hom_grid& g, int ncomp, int op, double p0, double p1, int precision, const double* in,
+                    double* out) {
+  for (int d = 0; d < 3; ++d)
+    if (!supported_n(g.n[d])) fail(HOM_E_UNSUPPORTED, "unsupported grid size");
+  if (!((ncomp == 6 && (op == G_PROJ || op == G_GAMMA0)) || (ncomp == 3 && (op == G_GRADPROJ || op == G_GAMMA_TH))))
+    fail(HOM_E_ARG, "operator / component count mismatch");
+  if (op == G_GAMMA0 && !(p1 > 0.0 && p0 + 2.0 * p1 > 0.0)) fail(HOM_E_ARG, "invalid reference medium");
+  if (op == G_GAMMA_TH && !(p0 > 0.0)) fail(HOM_E_ARG, "invalid reference conductivity");
+  if (precision == HOM_FP64)
+    apply_operator_t<double>(g, ncomp, op, p0, p1, in, out);
+  else if (precision == HOM_FP32)
+    apply_operator_t<float>(g, ncomp, op, p0, p1, in, out);
+  else
+    fail(HOM_E_ARG, "unknown precision");
+}
+
+void eval_law(const hom_law& law, int64_t count, const double* eps, const double* eps_n, const double* state,
+              double theta, double dt, int commit, double* sigma, double* ab, double* nd, double* state_out,
+              double* diss, double* coup) {
+  validate_laws(&law, 1);
+  if (count < 1) fail(HOM_E_ARG, "count must be positive");
+  if (!(dt > 0.0) || !(theta > 0.0)) fail(HOM_E_ARG, "need dt > 0 and theta > 0");
+  std::vector<hom_law> laws(1, law);
+  Group<double> G;
+  G.nx = (int)count;
+  G.ny = 1;
+  G.nz = 1;
+  G.nprob = 1;
+  G.nstate = pa66_nstate(laws);
+  // pointwise buffers only
+  G.nvox = count;
+  G.phase = G.dalloc<uint8_t>(count);
+  G.xm = G.dalloc<double>(6 * count);
+  G.xnm = G.dalloc<double>(6 * count);
+  G.f = G.dalloc<double>(6 * count);
+  G.tab = G.dalloc<double>(2 * count);
+  G.tn = G.dalloc<double>(6 * count);
+  if (G.nstate) G.state = G.dalloc<double>(G.nstate * count);
+  G.ctl_m = G.dalloc<Ctl>(1);
+  G.inc_d = G.dalloc<ProbInc>(1);
+  G.pt_bpp = (int)std::min<int64_t>((count + 255) / 256, 4096);
+  G.maxblk = G.pt_bpp;
+  G.part = G.dalloc<double>((size_t)G.maxblk * NPART);
+  double* pvd = G.dalloc<double>(count);
+  double* pvc = G.dalloc<double>(count);
+  HIPCHK(hipMemcpy(G.xm, eps, 6 * count * sizeof(double), hipMemcpyHostToDevice));
+  if (eps_n) HIPCHK(hipMemcpy(G.xnm, eps_n, 6 * count * sizeof(double), hipMemcpyHostToDevice));
+  if (G.nstate) {
+    if (!state) fail(HOM_E_ARG, "PA66 evaluation needs the internal variables");
+    HIPCHK(hipMemcpy(G.state, state, G.nstate * count * sizeof(double), hipMemcpyHostToDevice));
+  }
+  ProbInc inc;
+  fill_inc(inc, laws, theta, dt);
+  HIPCHK(hipMemcpy(G.inc_d, &inc, sizeof(inc), hipMemcpyHostToDevice));
+  Ctl c;
+  std::memset(&c, 0, sizeof(c));
+  c.mode = M_EVAL;
+  HIPCHK(hipMemcpy(G.ctl_m, &c, sizeof(c), hipMemcpyHostToDevice));
+  Pt<double> q = G.pt(0);
+  q.pv_diss = pvd;
+  q.pv_coup = pvc;
+  launch_eval<double>(q, 6, nullptr);
+  HIPCHK(hipGetLastError());
+  HIPCHK(hipDeviceSynchronize());
+  HIPCHK(hipMemcpy(sigma, G.f, 6 * count * sizeof(double), hipMemcpyDeviceToHost));
+  if (ab) HIPCHK(hipMemcpy(ab, G.tab, 2 * count * sizeof(double), hipMemcpyDeviceToHost));
+  if (nd) HIPCHK(hipMemcpy(nd, G.tn, 6 * count * sizeof(double), hipMemcpyDeviceToHost));
+  if (commit) {
+    c.status = 1;
+    c.mode = M_DONE;
+    HIPCHK(hipMemcpy(G.ctl_m, &c, sizeof(c), hipMemcpyHostToDevice));
+    launch_commit<double>(q, 6, nullptr);
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipDeviceSynchronize());
+    if (state_out && G.nstate)
+      HIPCHK(hipMemcpy(state_out, G.state, G.nstate * count * sizeof(double), hipMemcpyDeviceToHost));
+    if (diss) HIPCHK(hipMemcpy(diss, pvd, count * sizeof(double), hipMemcpyDeviceToHost));
+    if (coup) HIPCHK(hipMemcpy(coup, pvc, count * sizeof(double), hipMemcpyDeviceToHost));
+  }
+}
+
+}  // namespace hom

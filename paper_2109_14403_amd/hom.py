@@ -1,0 +1,377 @@
+"""Python binding of libhom.so (ctypes): argument marshalling only.
+
+Every computation runs in the HIP library; this module converts numpy arrays
+and law dictionaries into the C structures of ``include/hom.h`` and back.
+There is no fallback: if the library is missing or cannot be loaded, every
+entry point raises.
+"""
+from __future__ import annotations
+
+import ctypes as ct
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libhom.so")
+
+HOM_OK = 0
+HOM_E_ARG = -1
+HOM_E_OOM = -2
+HOM_E_NOT_CONVERGED = -3
+HOM_E_NAN = -4
+HOM_E_DEVICE = -5
+HOM_E_UNSUPPORTED = -6
+
+SCHEME_BASIC = 0
+SCHEME_NEWTON_CG = 1
+FP64 = 0
+FP32 = 1
+
+FIELD_STRAIN = 0
+FIELD_STRESS = 1
+FIELD_GRADIENT = 2
+FIELD_STATE = 3
+
+OP_PROJECTOR = 0
+OP_GAMMA0 = 1
+OP_GRAD_PROJECTOR = 2
+OP_GAMMA_CONDUCTION = 3
+
+MAX_MAXWELL = 16
+
+
+class HomError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"hom error {code}: {msg}")
+        self.code = code
+
+
+class Grid(ct.Structure):
+    _fields_ = [("n", ct.c_int32 * 3), ("len", ct.c_double * 3)]
+
+
+class Law(ct.Structure):
+    _fields_ = [
+        ("kind", ct.c_int32),
+        ("E", ct.c_double), ("nu", ct.c_double), ("alpha0", ct.c_double), ("kappa0", ct.c_double),
+        ("c0", ct.c_double), ("theta0", ct.c_double),
+        ("n_maxwell", ct.c_int32),
+        ("E_i", ct.c_double * MAX_MAXWELL), ("log10_tau_i", ct.c_double * MAX_MAXWELL),
+        ("C1", ct.c_double), ("C2", ct.c_double), ("theta_ref", ct.c_double), ("sigma_y0", ct.c_double),
+        ("k_h", ct.c_double), ("n_h", ct.c_double), ("eta0", ct.c_double), ("m", ct.c_double),
+        ("beta1", ct.c_double), ("beta2", ct.c_double),
+    ]
+
+
+class Options(ct.Structure):
+    _fields_ = [
+        ("scheme", ct.c_int32), ("precision", ct.c_int32), ("tol", ct.c_double), ("thermal_tol", ct.c_double),
+        ("max_iter", ct.c_int32), ("max_krylov", ct.c_int32), ("chunk", ct.c_int32), ("use_graph", ct.c_int32),
+        ("profile", ct.c_int32), ("autotune", ct.c_int32), ("stream", ct.c_void_p),
+    ]
+
+
+class MacroTemp(ct.Structure):
+    _fields_ = [("theta", ct.c_double), ("grad", ct.c_double * 3)]
+
+
+class Result(ct.Structure):
+    _fields_ = [
+        ("stress", ct.c_double * 6), ("heat_flux", ct.c_double * 3), ("dissipation", ct.c_double),
+        ("coupling", ct.c_double), ("heat_capacity", ct.c_double), ("residual", ct.c_double),
+        ("newton_iters", ct.c_int32), ("krylov_iters", ct.c_int32), ("thermal_iters", ct.c_int32),
+        ("status", ct.c_int32), ("pipelines", ct.c_double), ("thermal_pipelines", ct.c_double),
+    ]
+
+    def as_dict(self):
+        return dict(stress=np.array(self.stress[:]), heat_flux=np.array(self.heat_flux[:]),
+                    dissipation=self.dissipation, coupling=self.coupling, heat_capacity=self.heat_capacity,
+                    residual=self.residual, newton_iters=self.newton_iters, krylov_iters=self.krylov_iters,
+                    thermal_iters=self.thermal_iters, status=self.status, pipelines=self.pipelines,
+                    thermal_pipelines=self.thermal_pipelines)
+
+
+EXPORTS = (
+    "hom_default_options", "hom_setup", "hom_solve_increment", "hom_state_size", "hom_get_state",
+    "hom_set_state", "hom_get_field", "hom_kernel_stats", "hom_device_bytes", "hom_last_error", "hom_destroy",
+    "hom_batch_setup", "hom_batch_solve_increment", "hom_batch_kernel_stats", "hom_batch_last_error",
+    "hom_batch_destroy", "hom_apply_operator", "hom_eval_law",
+)
+
+_lib = None
+
+
+def library(path: str | None = None):
+    """Load libhom.so (once). Raises if it is not built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    p = path or LIB_PATH
+    if not os.path.exists(p):
+        raise HomError(HOM_E_DEVICE, f"{p} is not built; run __graft_entry__.build()")
+    lib = ct.CDLL(p)
+    dp = ct.POINTER(ct.c_double)
+    lib.hom_default_options.argtypes = [ct.POINTER(Options)]
+    lib.hom_setup.argtypes = [ct.POINTER(Grid), ct.c_void_p, ct.POINTER(Law), ct.c_int32, ct.POINTER(Options),
+                              ct.POINTER(ct.c_void_p)]
+    lib.hom_solve_increment.argtypes = [ct.c_void_p, dp, ct.POINTER(MacroTemp), ct.c_double, ct.POINTER(Result)]
+    lib.hom_state_size.argtypes = [ct.c_void_p]
+    lib.hom_state_size.restype = ct.c_size_t
+    lib.hom_get_state.argtypes = [ct.c_void_p, ct.c_void_p, ct.c_size_t]
+    lib.hom_set_state.argtypes = [ct.c_void_p, ct.c_void_p, ct.c_size_t]
+    lib.hom_get_field.argtypes = [ct.c_void_p, ct.c_int32, dp, ct.c_size_t]
+    lib.hom_kernel_stats.argtypes = [ct.c_void_p, ct.POINTER(ct.c_char_p), ct.POINTER(ct.c_int64), dp, ct.c_int32]
+    lib.hom_device_bytes.argtypes = [ct.c_void_p]
+    lib.hom_device_bytes.restype = ct.c_size_t
+    lib.hom_last_error.argtypes = [ct.c_void_p]
+    lib.hom_last_error.restype = ct.c_char_p
+    lib.hom_destroy.argtypes = [ct.c_void_p]
+    lib.hom_destroy.restype = None
+    lib.hom_batch_setup.argtypes = [ct.c_int32, ct.POINTER(Grid), ct.POINTER(ct.c_void_p), ct.POINTER(Law),
+                                    ct.c_int32, ct.POINTER(Options), ct.POINTER(ct.c_void_p)]
+    lib.hom_batch_solve_increment.argtypes = [ct.c_void_p, dp, ct.POINTER(MacroTemp), dp, ct.POINTER(Result)]
+    lib.hom_batch_kernel_stats.argtypes = [ct.c_void_p, ct.POINTER(ct.c_char_p), ct.POINTER(ct.c_int64), dp,
+                                           ct.c_int32]
+    lib.hom_batch_last_error.argtypes = [ct.c_void_p]
+    lib.hom_batch_last_error.restype = ct.c_char_p
+    lib.hom_batch_destroy.argtypes = [ct.c_void_p]
+    lib.hom_batch_destroy.restype = None
+    lib.hom_apply_operator.argtypes = [ct.POINTER(Grid), ct.c_int32, ct.c_int32, ct.c_double, ct.c_double,
+                                       ct.c_int32, dp, dp]
+    lib.hom_eval_law.argtypes = [ct.POINTER(Law), ct.c_int64, dp, dp, dp, ct.c_double, ct.c_double, ct.c_int32,
+                                 dp, dp, dp, dp, dp, dp]
+    _lib = lib
+    return lib
+
+
+def _dptr(a):
+    if a is None:
+        return None
+    return a.ctypes.data_as(ct.POINTER(ct.c_double))
+
+
+def _f64(a):
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+def make_law(p: dict) -> Law:
+    """hom_law from a parameter dictionary (see workloads.py)."""
+    L = Law()
+    kind = p["kind"]
+    L.kind = 1 if kind == "thermoelastic" else 2
+    for k in ("E", "nu", "alpha0", "kappa0", "c0", "theta0"):
+        setattr(L, k, float(p[k]))
+    if L.kind == 2:
+        Ei = list(p["E_i"])
+        ti = list(p["log10_tau_i"])
+        if len(Ei) > MAX_MAXWELL:
+            raise HomError(HOM_E_ARG, "too many Maxwell branches")
+        L.n_maxwell = len(Ei)
+        for i, (e, t) in enumerate(zip(Ei, ti)):
+            L.E_i[i] = e
+            L.log10_tau_i[i] = t
+        for k in ("C1", "C2", "theta_ref", "sigma_y0", "k_h", "n_h", "eta0", "m", "beta1", "beta2"):
+            setattr(L, k, float(p[k]))
+    return L
+
+
+def make_options(scheme=SCHEME_NEWTON_CG, precision=FP32, tol=1e-6, thermal_tol=0.0, max_iter=0, max_krylov=0,
+                 chunk=0, use_graph=1, profile=0, autotune=0, stream=None) -> Options:
+    o = Options()
+    library().hom_default_options(ct.byref(o))
+    o.scheme = scheme
+    o.precision = precision
+    o.tol = tol
+    o.thermal_tol = thermal_tol
+    o.max_iter = max_iter
+    o.max_krylov = max_krylov
+    o.chunk = chunk
+    o.use_graph = use_graph
+    o.profile = profile
+    o.autotune = autotune
+    o.stream = stream
+    return o
+
+
+def make_grid(shape_zyx, lengths=(1.0, 1.0, 1.0)) -> Grid:
+    g = Grid()
+    nz, ny, nx = shape_zyx
+    g.n[0], g.n[1], g.n[2] = nx, ny, nz
+    for i in range(3):
+        g.len[i] = lengths[i]
+    return g
+
+
+def _check(code, msg_fn):
+    if code != HOM_OK:
+        raise HomError(code, msg_fn())
+
+
+class Context:
+    """One microstructure (hom_setup / hom_solve_increment / ...)."""
+
+    def __init__(self, phases, laws, options: Options | None = None, lengths=(1.0, 1.0, 1.0), **opt_kw):
+        lib = library()
+        self._lib = lib
+        ph = np.ascontiguousarray(phases, dtype=np.uint8)
+        self.shape = ph.shape
+        self.grid = make_grid(ph.shape, lengths)
+        n = len(laws)
+        self._laws = (Law * n)(*[make_law(p) for p in laws])
+        self.options = options if options is not None else make_options(**opt_kw)
+        h = ct.c_void_p()
+        rc = lib.hom_setup(ct.byref(self.grid), ph.ctypes.data_as(ct.c_void_p), self._laws, n,
+                           ct.byref(self.options), ct.byref(h))
+        _check(rc, lambda: lib.hom_last_error(None).decode())
+        self._h = h
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self._lib.hom_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def error(self):
+        return self._lib.hom_last_error(self._h).decode()
+
+    def solve_increment(self, strain, theta, grad, dt, check=True):
+        s = _f64(strain)
+        t = MacroTemp()
+        t.theta = theta
+        for i in range(3):
+            t.grad[i] = float(grad[i])
+        r = Result()
+        rc = self._lib.hom_solve_increment(self._h, _dptr(s), ct.byref(t), float(dt), ct.byref(r))
+        if check:
+            _check(rc, self.error)
+        out = r.as_dict()
+        out["rc"] = rc
+        return out
+
+    def field(self, which):
+        nv = int(np.prod(self.shape))
+        nc = {FIELD_STRAIN: 6, FIELD_STRESS: 6, FIELD_GRADIENT: 3}.get(which)
+        if nc is None:
+            nc = self.nstate
+        out = np.empty(nc * nv)
+        rc = self._lib.hom_get_field(self._h, which, _dptr(out), out.size)
+        _check(rc, self.error)
+        return out.reshape((nc,) + tuple(self.shape))
+
+    @property
+    def nstate(self):
+        for L in self._laws:
+            if L.kind == 2:
+                return 7 + 6 * sum(1 for i in range(L.n_maxwell) if L.E_i[i] > 0)
+        return 0
+
+    def get_state(self) -> bytes:
+        n = self._lib.hom_state_size(self._h)
+        buf = ct.create_string_buffer(n)
+        _check(self._lib.hom_get_state(self._h, buf, n), self.error)
+        return buf.raw
+
+    def set_state(self, data: bytes):
+        buf = ct.create_string_buffer(data, len(data))
+        _check(self._lib.hom_set_state(self._h, buf, len(data)), self.error)
+
+    def kernel_stats(self):
+        return _stats(self._lib.hom_kernel_stats, self._h)
+
+    def device_bytes(self):
+        return int(self._lib.hom_device_bytes(self._h))
+
+
+def _stats(fn, h):
+    cap = 32
+    names = (ct.c_char_p * cap)()
+    launches = (ct.c_int64 * cap)()
+    ms = (ct.c_double * cap)()
+    n = fn(h, names, launches, ms, cap)
+    return {names[i].decode(): (int(launches[i]), float(ms[i])) for i in range(n)}
+
+
+class Batch:
+    """Independent microproblems solved together (hom_batch_*)."""
+
+    def __init__(self, phase_list, laws, options: Options | None = None, lengths=(1.0, 1.0, 1.0), **opt_kw):
+        lib = library()
+        self._lib = lib
+        self._phases = [np.ascontiguousarray(p, dtype=np.uint8) for p in phase_list]
+        n = len(self._phases)
+        self.n = n
+        self._grids = (Grid * n)(*[make_grid(p.shape, lengths) for p in self._phases])
+        ptrs = (ct.c_void_p * n)(*[p.ctypes.data_as(ct.c_void_p).value for p in self._phases])
+        nl = len(laws)
+        self._laws = (Law * nl)(*[make_law(p) for p in laws])
+        self.options = options if options is not None else make_options(**opt_kw)
+        h = ct.c_void_p()
+        rc = lib.hom_batch_setup(n, self._grids, ptrs, self._laws, nl, ct.byref(self.options), ct.byref(h))
+        _check(rc, lambda: lib.hom_batch_last_error(None).decode())
+        self._h = h
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self._lib.hom_batch_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def solve_increment(self, strains, thetas, grads, dts):
+        s = _f64(strains).reshape(self.n, 6)
+        temps = (MacroTemp * self.n)()
+        for i in range(self.n):
+            temps[i].theta = float(thetas[i])
+            for c in range(3):
+                temps[i].grad[c] = float(grads[i][c])
+        d = _f64(dts).reshape(self.n)
+        res = (Result * self.n)()
+        rc = self._lib.hom_batch_solve_increment(self._h, _dptr(s), temps, _dptr(d), res)
+        _check(rc, lambda: self._lib.hom_batch_last_error(self._h).decode())
+        return [r.as_dict() for r in res]
+
+    def kernel_stats(self):
+        return _stats(self._lib.hom_batch_kernel_stats, self._h)
+
+
+def apply_operator(field, op, p0=0.0, p1=0.0, precision=FP64, lengths=(1.0, 1.0, 1.0)):
+    """IFFT(Op FFT(field)) on the GPU; field (C, nz, ny, nx) float64."""
+    lib = library()
+    f = _f64(field)
+    C = f.shape[0]
+    g = make_grid(f.shape[1:], lengths)
+    out = np.empty_like(f)
+    rc = lib.hom_apply_operator(ct.byref(g), C, op, p0, p1, precision, _dptr(f), _dptr(out))
+    _check(rc, lambda: lib.hom_last_error(None).decode())
+    return out
+
+
+def eval_law(law: dict, eps, eps_n=None, state=None, theta=293.15, dt=1.0, commit=False):
+    """Evaluate one law on the GPU at points eps (6, M) (Mandel)."""
+    lib = library()
+    L = make_law(law)
+    e = _f64(eps)
+    m = e.shape[1]
+    en = _f64(eps_n) if eps_n is not None else np.zeros_like(e)
+    st = _f64(state) if state is not None else None
+    sig = np.empty((6, m))
+    ab = np.empty((2, m))
+    nd = np.zeros((6, m))
+    nst = 0 if L.kind == 1 else 7 + 6 * sum(1 for i in range(L.n_maxwell) if L.E_i[i] > 0)
+    st_out = np.empty((nst, m)) if (commit and nst) else None
+    diss = np.empty(m) if commit else None
+    coup = np.empty(m) if commit else None
+    rc = lib.hom_eval_law(ct.byref(L), m, _dptr(e), _dptr(en), _dptr(st), float(theta), float(dt), int(commit),
+                          _dptr(sig), _dptr(ab), _dptr(nd), _dptr(st_out), _dptr(diss), _dptr(coup))
+    _check(rc, lambda: lib.hom_last_error(None).decode())
+    return dict(sigma=sig, ab=ab, nd=nd, state=st_out, dissipation=diss, coupling=coup)
