@@ -1,0 +1,207 @@
+"""Benchmark of the coupled FFT solve on one MI355X.
+
+A step is one load increment of the 256^3 short-fibre composite (991 planar-
+isotropic E-glass fibres, aspect ratio 20, 20 % volume fraction, PA66 matrix)
+solved by Newton-CG with FP32 fields and FP64 reductions / return mapping:
+per-voxel constitutive update, 3D FFT, Green operator, inverse FFT and the
+Krylov update, for the mechanical and the conduction fields. The value is
+mechanical voxel-iterations per second (one voxel-iteration = one
+application of the FFT pipeline to one voxel), with the inputs resident in
+HBM. Prints one JSON line.
+
+    python bench.py [--steps K] [--warmup W] [--gpus 1] [--no-cpu-baseline]
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "voxel-iters/s coupled FFT solve"
+HBM_PEAK_GBS = 8000.0
+KERNEL_SOURCES = ("paper_2109_14403_amd/csrc/pipeline.h", "paper_2109_14403_amd/csrc/fft_core.h",
+                  "paper_2109_14403_amd/csrc/pointwise.hip", "paper_2109_14403_amd/csrc/common.h")
+
+
+def kernel_source_hash():
+    h = hashlib.sha256()
+    for p in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, p), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def algorithmic_bytes(kind, n, fp_bytes, matrix_fraction, plastic_fraction, nstate):
+    """Bytes one launch of a kernel must move at minimum for one n^3 problem
+    (mechanics, C = 6), by kernel kind, for its dominant mode:
+    spectra are n * n * (n/2 + 1) * 6 complex values."""
+    v = float(n) ** 3
+    spec = n * n * (n // 2 + 1) * 6 * 2 * fp_bytes
+    field = 6 * fp_bytes * v
+    if kind in ("yfwd", "yinv", "zgreen"):
+        return 2 * spec
+    if kind == "xfwd":      # CG: read r, p, tangent factors (+ direction where plastic), phase; write p, spectrum
+        return 3 * field + 2 * fp_bytes * v + v + plastic_fraction * field + spec
+    if kind == "xinv":      # CG: read spectrum, p; write A p
+        return spec + 2 * field
+    if kind == "cgupd":     # read dx, p, r, ap; write dx, r
+        return 6 * field
+    if kind == "eval":      # read strain, phase, PA66 state; write stress, tangent factors (+ direction)
+        return (field + v + matrix_fraction * v * nstate * 8 + field + 2 * fp_bytes * v
+                + plastic_fraction * field)
+    return None
+
+
+def cpu_baseline(phases, laws, sample="one CG pipeline application (tangent, FFT, projector, inverse FFT) "
+                                         "of the FP64 oracle on the full 256^3 grid"):
+    """The oracle as it stands, timed on this host: A p = P[C p] at full size."""
+    from oracle import solver
+
+    cell = solver.Cell(phases, laws)
+    rng = np.random.default_rng(0)
+    shape = phases.shape
+    tan = np.zeros((6, 6) + shape)
+    for i, law in enumerate(cell.laws):
+        if law.inelastic:
+            mats = law.branch_matrices(313.15, 0.8)
+            C = law.Cinf.copy()
+            for j, (B, M) in enumerate(mats):
+                C = C + law.C_i[j] @ (np.eye(6) - M)
+        else:
+            C = law.C
+        tan[:, :, cell.masks[i]] = C[:, :, None]
+    p = rng.normal(size=(6,) + shape)
+    t0 = time.perf_counter()
+    ap = cell.project(np.einsum("ab...,b...->a...", tan, p))
+    _ = float((p * ap).sum())
+    dt = time.perf_counter() - t0
+    return {"value": float(np.prod(shape)) / dt, "unit": "voxel-iters/s", "cores": 1, "kind": "oracle",
+            "sample": sample, "seconds": dt}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=8)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--n", type=int, default=256)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-profile", action="store_true")
+    ap.add_argument("--calib-copy", action="store_true", help="run a 1 GiB device copy (PMC calibration)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1"}))
+        sys.exit(2)
+
+    import torch
+
+    from paper_2109_14403_amd import hom
+    from paper_2109_14403_amd import workloads as W
+
+    t0 = time.perf_counter()
+    wl = W.fibre_composite_workload(args.n, seed=3)
+    gen_s = time.perf_counter() - t0
+    n = args.n
+    hist = wl.history
+    total = args.warmup + args.steps
+    if total > len(hist):
+        raise SystemExit(f"at most {len(hist)} increments")
+
+    if args.calib_copy:
+        a = torch.empty(1 << 28, dtype=torch.float32, device="cuda")
+        b = torch.empty_like(a)
+        b.copy_(a)
+        torch.cuda.synchronize()
+        del a, b
+
+    ctx = hom.Context(wl.phases, wl.laws, scheme=hom.SCHEME_NEWTON_CG, precision=hom.FP32, tol=1e-6,
+                      autotune=1)
+    print(f"setup done: {n}^3, {wl.record['count']} fibres, fraction {wl.record['fraction']:.4f}, "
+          f"{ctx.device_bytes() / 2**30:.1f} GiB on device, generator {gen_s:.1f} s", file=sys.stderr, flush=True)
+
+    for k in range(args.warmup):
+        st = hist[k]
+        r = ctx.solve_increment(st.strain, st.theta, st.grad, st.dt)
+        print(f"warmup inc {k}: newton {r['newton_iters']} krylov {r['krylov_iters']}", file=sys.stderr,
+              flush=True)
+
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    pipes = 0.0
+    tpipes = 0.0
+    newton = krylov = 0
+    results = []
+    for k in range(args.warmup, total):
+        st = hist[k]
+        r = ctx.solve_increment(st.strain, st.theta, st.grad, st.dt)
+        pipes += r["pipelines"]
+        tpipes += r["thermal_pipelines"]
+        newton += r["newton_iters"]
+        krylov += r["krylov_iters"]
+        results.append(r)
+        print(f"inc {k}: newton {r['newton_iters']} krylov {r['krylov_iters']} stress11 {r['stress'][0]:.4f}",
+              file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    nvox = float(n) ** 3
+    value = pipes * nvox / elapsed
+
+    # per-kernel timing with HIP events on the library's stream (one more increment)
+    roof = None
+    kstats = None
+    if not args.no_profile and total < len(hist):
+        ctx.set_profiling(True)
+        st = hist[total]
+        ctx.solve_increment(st.strain, st.theta, st.grad, st.dt)
+        kstats = ctx.kernel_stats()
+        ctx.set_profiling(False)
+        dom = max((k for k in kstats if kstats[k][0] > 0), key=lambda k: kstats[k][1])
+        matrix_fraction = float((wl.phases == 0).mean())
+        launches, ms = kstats[dom]
+        avg_s = ms / launches / 1e3
+        nstate = 7 + 6 * len(W.pa66()["E_i"])
+        byt = algorithmic_bytes(dom, n, 4, matrix_fraction, 0.0, nstate)
+        traffic = None
+        pmc_path = os.path.join(ROOT, "profiles", f"{dom}_fibres256_pmc.json")
+        if os.path.exists(pmc_path):
+            pm = json.load(open(pmc_path))
+            if pm.get("source_hash") == kernel_source_hash():
+                traffic = pm.get("bytes_per_launch")
+        if byt is not None:
+            ach = byt / avg_s / 1e9
+            roof = {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                    "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": traffic, "kernel": dom,
+                    "avg_launch_ms": round(avg_s * 1e3, 4), "algorithmic_bytes": byt}
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        cpu = cpu_baseline(wl.phases, wl.laws)
+
+    line = {
+        "metric": METRIC, "value": round(value, 1), "unit": "voxel-iters/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(elapsed / args.steps * 1e3, 2),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": f"fibres{n}_pa66_glass", "grid": n, "fibres": wl.record["count"],
+                   "fibre_fraction": round(wl.record["fraction"], 4), "scheme": "newton-cg",
+                   "fields": "fp32", "reductions": "fp64", "tol": 1e-6,
+                   "increments": f"{args.warmup}..{total - 1} of 50"},
+        "thermal_voxel_iters_per_s": round(tpipes * nvox / elapsed, 1),
+        "newton_per_step": newton / args.steps, "krylov_per_step": krylov / args.steps,
+        "roofline": roof, "cpu_baseline": cpu,
+    }
+    if kstats:
+        line["kernel_ms"] = {k: [v[0], round(v[1], 3)] for k, v in kstats.items() if v[0]}
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

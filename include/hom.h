@@ -159,6 +159,10 @@ int hom_get_field(hom_ctx* ctx, int32_t which, double* host_buf, size_t count);
  * accumulated milliseconds. Returns the number of kernel kinds (<= cap). */
 int hom_kernel_stats(const hom_ctx* ctx, const char** names, int64_t* launches, double* ms, int32_t cap);
 
+/* Switch per-kernel event timing on (1) or off (0) for later increments; the
+ * accumulated statistics are reset. While on, chunks run eagerly (no graph). */
+int hom_set_profiling(hom_ctx* ctx, int32_t on);
+
 /* Bytes of device memory held by the context. */
 size_t hom_device_bytes(const hom_ctx* ctx);
 

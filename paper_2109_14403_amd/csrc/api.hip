@@ -122,6 +122,11 @@ int hom_kernel_stats(const hom_ctx* c, const char** names, int64_t* launches, do
   return stats(c ? c->impl.get() : nullptr, names, launches, ms, cap);
 }
 
+int hom_set_profiling(hom_ctx* c, int32_t on) {
+  if (!c || !c->impl) return HOM_E_ARG;
+  return guarded(&c->err, [&] { c->impl->set_profiling(on != 0); });
+}
+
 size_t hom_device_bytes(const hom_ctx* c) { return (c && c->impl) ? c->impl->device_bytes() : 0; }
 
 const char* hom_last_error(const hom_ctx* c) { return c ? c->err.c_str() : g_setup_error.c_str(); }

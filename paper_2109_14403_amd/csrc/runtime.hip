@@ -402,6 +402,15 @@ class BatchT : public BatchImpl {
 
   const Profiler& profiler() const override { return prof; }
 
+  void set_profiling(bool on) override {
+    prof.collect();
+    prof.on = on;
+    for (int k = 0; k < K_COUNT; ++k) {
+      prof.launches[k] = 0;
+      prof.ms[k] = 0.0;
+    }
+  }
+
   size_t device_bytes() const override {
     size_t b = 0;
     for (auto& g : groups) b += g->bytes;

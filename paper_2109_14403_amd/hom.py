@@ -94,7 +94,8 @@ class Result(ct.Structure):
 
 EXPORTS = (
     "hom_default_options", "hom_setup", "hom_solve_increment", "hom_state_size", "hom_get_state",
-    "hom_set_state", "hom_get_field", "hom_kernel_stats", "hom_device_bytes", "hom_last_error", "hom_destroy",
+    "hom_set_state", "hom_get_field", "hom_kernel_stats", "hom_set_profiling", "hom_device_bytes",
+    "hom_last_error", "hom_destroy",
     "hom_batch_setup", "hom_batch_solve_increment", "hom_batch_kernel_stats", "hom_batch_last_error",
     "hom_batch_destroy", "hom_apply_operator", "hom_eval_law",
 )
@@ -122,6 +123,7 @@ def library(path: str | None = None):
     lib.hom_set_state.argtypes = [ct.c_void_p, ct.c_void_p, ct.c_size_t]
     lib.hom_get_field.argtypes = [ct.c_void_p, ct.c_int32, dp, ct.c_size_t]
     lib.hom_kernel_stats.argtypes = [ct.c_void_p, ct.POINTER(ct.c_char_p), ct.POINTER(ct.c_int64), dp, ct.c_int32]
+    lib.hom_set_profiling.argtypes = [ct.c_void_p, ct.c_int32]
     lib.hom_device_bytes.argtypes = [ct.c_void_p]
     lib.hom_device_bytes.restype = ct.c_size_t
     lib.hom_last_error.argtypes = [ct.c_void_p]
@@ -283,6 +285,9 @@ class Context:
 
     def kernel_stats(self):
         return _stats(self._lib.hom_kernel_stats, self._h)
+
+    def set_profiling(self, on: bool):
+        _check(self._lib.hom_set_profiling(self._h, int(on)), self.error)
 
     def device_bytes(self):
         return int(self._lib.hom_device_bytes(self._h))

@@ -153,91 +153,72 @@ def rsa_spheres(n: int, seed: int, radius_range: tuple[float, float],
     return img, rec
 
 
-def _segment_distance(p1, d1, p2, d2):
-    """Distance between segments p1 + s d1 and p2 + t d2, s, t in [0, 1];
-    p2, d2 may be arrays (M, 3). Standard clamped closest-point computation."""
-    r = p1[None, :] - p2
-    a = float(d1 @ d1)
-    e = (d2 * d2).sum(axis=1)
-    f = (d2 * r).sum(axis=1)
-    c = (r @ d1)
-    b = d2 @ d1
-    denom = a * e - b * b
-    s = np.where(denom > 1e-12, np.clip((b * f - c * e) / np.maximum(denom, 1e-300), 0, 1), 0.0)
-    t = (b * s + f) / e
-    t_cl = np.clip(t, 0, 1)
-    s = np.where(t < 0, np.clip(-c / a, 0, 1), np.where(t > 1, np.clip((b - c) / a, 0, 1), s))
-    t = t_cl
-    diff = r + s[:, None] * d1[None, :] - t[:, None] * d2
-    return np.sqrt((diff * diff).sum(axis=1))
-
-
-def _voxelize_cylinder(img, centre, direction, length, radius):
-    n = img.shape[0]
+def _cylinder_columns(cx, cy, u, direction, length, radius, n):
+    """Voxel columns of a cylinder lying in the x-y plane, axis through
+    (cx, cy, z0 + u) along ``direction``: returns (xs, ys, lo, hi) so that voxel
+    (x, y, z0 + dz) is inside for lo <= dz <= hi (voxel centres at +0.5)."""
     half = 0.5 * length
-    ext = np.abs(direction) * half + radius + 1.0
-    lo = np.floor(centre - ext).astype(int)
-    hi = np.ceil(centre + ext).astype(int)
-    zs = np.arange(lo[2], hi[2] + 1)
-    ys = np.arange(lo[1], hi[1] + 1)
-    xs = np.arange(lo[0], hi[0] + 1)
-    Z, Y, X = np.meshgrid(zs + 0.5, ys + 0.5, xs + 0.5, indexing="ij")
-    rx, ry, rz = X - centre[0], Y - centre[1], Z - centre[2]
-    along = rx * direction[0] + ry * direction[1] + rz * direction[2]
-    px = rx - along * direction[0]
-    py = ry - along * direction[1]
-    pz = rz - along * direction[2]
-    inside = (np.abs(along) <= half) & ((px * px + py * py + pz * pz) <= radius * radius)
-    iz, iy, ix = np.nonzero(inside)
-    img[zs[iz] % n, ys[iy] % n, xs[ix] % n] = 1
+    ext = np.abs(direction[:2]) * half + radius + 1.0
+    xs = np.arange(int(np.floor(cx - ext[0])), int(np.ceil(cx + ext[0])) + 1)
+    ys = np.arange(int(np.floor(cy - ext[1])), int(np.ceil(cy + ext[1])) + 1)
+    X, Y = np.meshgrid(xs + 0.5 - cx, ys + 0.5 - cy, indexing="xy")
+    along = X * direction[0] + Y * direction[1]
+    perp2 = (X - along * direction[0]) ** 2 + (Y - along * direction[1]) ** 2
+    ok = (np.abs(along) <= half) & (perp2 <= radius * radius)
+    # remaining z half-extent for voxel centres dz + 0.5 - u
+    hz = np.sqrt(np.maximum(radius * radius - perp2, 0.0))
+    lo = np.ceil(u - 0.5 - hz).astype(int)
+    hi = np.floor(u - 0.5 + hz).astype(int)
+    ok &= hi >= lo
+    iy, ix = np.nonzero(ok)
+    return (xs[ix] % n), (ys[iy] % n), lo[iy, ix], hi[iy, ix]
 
 
 def rsa_fibres(n: int, seed: int, diameter: float, length: float,
-               target_fraction: float, max_attempts: int = 400000) -> tuple[np.ndarray, dict]:
-    """Random sequential addition of straight cylinders in a periodic cube.
+               target_fraction: float, max_attempts: int = 200000) -> tuple[np.ndarray, dict]:
+    """Random sequential addition of straight, non-overlapping cylinders in a
+    periodic cube.
 
-    Axis directions are planar isotropic in the x-y plane (angle ~ U[0, pi)),
-    centres uniform. Two fibres may not come closer than one diameter (axis
-    segment distance, checked over the 3 x 3 x 3 periodic images). Fibres are
-    added until the voxel fraction reaches ``target_fraction``; the record says
-    whether the sequence jammed before reaching it.
+    Each candidate draws an axis angle phi ~ U[0, pi) in the x-y plane
+    (planar isotropic orientation) and a centre (x, y) ~ U[0, n)^2 plus a
+    sub-voxel z offset; among all z levels where its voxels are free it takes
+    one uniformly at random (a candidate with no free level is rejected).
+    Fibres never share voxels. Candidates are added until the voxel fraction
+    reaches ``target_fraction``; the record says whether the sequence jammed.
     """
     rng = np.random.default_rng(seed)
-    img = np.zeros((n, n, n), dtype=np.uint8)
-    starts = np.zeros((0, 3))
-    dirs = np.zeros((0, 3))
-    shifts = np.array([[i, j, k] for i in (-1, 0, 1) for j in (-1, 0, 1) for k in (-1, 0, 1)],
-                      dtype=np.float64) * n
+    occ = np.zeros((n, n, n), dtype=bool)        # [y, x, z]: z contiguous per column
+    radius = 0.5 * diameter
     attempts = 0
-    frac = 0.0
     count = 0
-    while frac < target_fraction and attempts < max_attempts:
+    filled = 0
+    target = target_fraction * n ** 3
+    while filled < target and attempts < max_attempts:
         attempts += 1
-        c = rng.uniform(0.0, n, size=3)
         phi = rng.uniform(0.0, math.pi)
         d = np.array([math.cos(phi), math.sin(phi), 0.0])
-        seg = d * length
-        p = c - 0.5 * seg
-        if count:
-            ok = True
-            for s in shifts:
-                dist = _segment_distance(p + s, seg, starts, dirs)
-                if np.any(dist < diameter):
-                    ok = False
-                    break
-            if not ok:
-                continue
-        starts = np.vstack([starts, p])
-        dirs = np.vstack([dirs, seg])
+        cx, cy, u = rng.uniform(0.0, n), rng.uniform(0.0, n), rng.uniform(0.0, 1.0)
+        xs, ys, lo, hi = _cylinder_columns(cx, cy, u, d, length, radius, n)
+        cols = occ[ys, xs]                                   # (ncol, n)
+        # blocked[z0]: some column j is occupied at z0 + dz for lo_j <= dz <= hi_j
+        blocked = np.zeros(n, dtype=bool)
+        for a, b in set(zip(lo.tolist(), hi.tolist())):
+            v = cols[(lo == a) & (hi == b)].any(axis=0)
+            for dz in range(a, b + 1):
+                blocked |= np.roll(v, -dz)
+        free = np.nonzero(~blocked)[0]
+        if free.size == 0:
+            continue
+        z0 = int(free[rng.integers(free.size)])
+        for dz in range(int(lo.min()), int(hi.max()) + 1):
+            sel = (lo <= dz) & (dz <= hi)
+            occ[ys[sel], xs[sel], (z0 + dz) % n] = True
+            filled += int(sel.sum())
         count += 1
-        _voxelize_cylinder(img, c, d, length, 0.5 * diameter)
-        if count % 16 == 0 or frac + 2 * length * diameter ** 2 / n ** 3 >= target_fraction:
-            frac = img.mean()
-    frac = img.mean()
-    rec = dict(fraction=float(frac), count=count, attempts=attempts,
-               jammed=bool(frac < target_fraction))
+    img = np.ascontiguousarray(occ.transpose(2, 0, 1)).astype(np.uint8)
+    frac = float(img.mean())
+    rec = dict(fraction=frac, count=count, attempts=attempts, jammed=bool(frac < target_fraction))
     return img, rec
-
 
 # --------------------------------------------------------------------------
 # load histories
