@@ -39,24 +39,22 @@ def kernel_source_hash():
     return h.hexdigest()[:16]
 
 
-def algorithmic_bytes(kind, n, fp_bytes, matrix_fraction, plastic_fraction, nstate):
-    """Bytes one launch of a kernel must move at minimum for one n^3 problem
-    (mechanics, C = 6), by kernel kind, for its dominant mode:
-    spectra are n * n * (n/2 + 1) * 6 complex values."""
+def algorithmic_bytes(kind, n, fp_bytes, matrix_fraction):
+    """Minimum bytes one launch of a mechanical kernel moves on one n^3 problem,
+    as (residual-evaluation iteration, CG iteration). Spectra hold
+    n * n * (n/2 + 1) * 6 complex values; the direction field of plastic
+    voxels is not counted (a lower bound)."""
     v = float(n) ** 3
     spec = n * n * (n // 2 + 1) * 6 * 2 * fp_bytes
     field = 6 * fp_bytes * v
     if kind in ("yfwd", "yinv", "zgreen"):
-        return 2 * spec
-    if kind == "xfwd":      # CG: read r, p, tangent factors (+ direction where plastic), phase; write p, spectrum
-        return 3 * field + 2 * fp_bytes * v + v + plastic_fraction * field + spec
-    if kind == "xinv":      # CG: read spectrum, p; write A p
-        return spec + 2 * field
-    if kind == "cgupd":     # read dx, p, r, ap; write dx, r
-        return 6 * field
-    if kind == "eval":      # read strain, phase, PA66 state; write stress, tangent factors (+ direction)
-        return (field + v + matrix_fraction * v * nstate * 8 + field + 2 * fp_bytes * v
-                + plastic_fraction * field)
+        return 2 * spec, 2 * spec
+    if kind == "xfwd":   # eval: read stress; CG: read r, p, tangent factors, phase, write p; both write spectra
+        return field + spec, 3 * field + 2 * fp_bytes * v + v + spec
+    if kind == "xinv":   # eval: read spectra and stress, write r; CG: read spectra, p, r, dx, write r, dx
+        return spec + 2 * field, spec + 5 * field
+    if kind == "eval":   # read strain, phase, PA66 eps_p, eps_vp and history sums; write stress, tangent factors
+        return 2 * field + v + matrix_fraction * v * 14 * 8 + 2 * fp_bytes * v, 0.0
     return None
 
 
@@ -160,15 +158,18 @@ def main():
     if not args.no_profile and total < len(hist):
         ctx.set_profiling(True)
         st = hist[total]
-        ctx.solve_increment(st.strain, st.theta, st.grad, st.dt)
+        pr = ctx.solve_increment(st.strain, st.theta, st.grad, st.dt)
         kstats = ctx.kernel_stats()
         ctx.set_profiling(False)
         dom = max((k for k in kstats if kstats[k][0] > 0), key=lambda k: kstats[k][1])
         matrix_fraction = float((wl.phases == 0).mean())
         launches, ms = kstats[dom]
         avg_s = ms / launches / 1e3
-        nstate = 7 + 6 * len(W.pa66()["E_i"])
-        byt = algorithmic_bytes(dom, n, 4, matrix_fraction, 0.0, nstate)
+        n_eval, n_cg = pr["newton_iters"], pr["krylov_iters"]
+        mix = algorithmic_bytes(dom, n, 4, matrix_fraction)
+        byt = None
+        if mix is not None and launches == n_eval + n_cg:
+            byt = (n_eval * mix[0] + n_cg * mix[1]) / launches
         traffic = None
         pmc_path = os.path.join(ROOT, "profiles", f"{dom}_fibres256_pmc.json")
         if os.path.exists(pmc_path):

@@ -44,7 +44,7 @@ int worst(const hom_result* r, int n) {
 int stats(const hom::BatchImpl* b, const char** names, int64_t* launches, double* ms, int32_t cap) {
   if (!b) return HOM_E_ARG;
   const hom::Profiler& p = b->profiler();
-  const int n = cap < hom::K_COUNT ? cap : hom::K_COUNT;
+  const int n = cap < 2 * hom::K_COUNT ? cap : 2 * hom::K_COUNT;
   for (int i = 0; i < n; ++i) {
     if (names) names[i] = hom::kKernelNames[i];
     if (launches) launches[i] = p.launches[i];

@@ -85,7 +85,6 @@ struct Pipe {
   T* f;                     // field to transform (stress / flux)
   T* r;
   T* p;
-  T* ap;
   T* dx;
   const T* tab;             // tangent factors [prob][2][nvox] (mechanics)
   const T* tn;              // tangent direction [prob][6][nvox] (mechanics)

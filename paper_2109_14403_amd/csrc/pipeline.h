@@ -101,6 +101,43 @@ __device__ __forceinline__ void green_grad(c2<T>* v, T n0, T n1, T n2, T s) {
 }
 
 // ---------------------------------------------------------------------------
+// 16-byte global accesses: four consecutive reals, a run of complex values
+// ---------------------------------------------------------------------------
+template <typename T>
+struct Q4 {
+  T v[4];
+};
+__device__ __forceinline__ Q4<float> ld4(const float* p) {
+  const float4 t = *reinterpret_cast<const float4*>(p);
+  return Q4<float>{{t.x, t.y, t.z, t.w}};
+}
+__device__ __forceinline__ Q4<double> ld4(const double* p) {
+  const double2 a = reinterpret_cast<const double2*>(p)[0];
+  const double2 b = reinterpret_cast<const double2*>(p)[1];
+  return Q4<double>{{a.x, a.y, b.x, b.y}};
+}
+__device__ __forceinline__ void st4(float* p, const float (&v)[4]) {
+  *reinterpret_cast<float4*>(p) = make_float4(v[0], v[1], v[2], v[3]);
+}
+__device__ __forceinline__ void st4(double* p, const double (&v)[4]) {
+  reinterpret_cast<double2*>(p)[0] = make_double2(v[0], v[1]);
+  reinterpret_cast<double2*>(p)[1] = make_double2(v[2], v[3]);
+}
+
+// copy `count` complex values (16-byte aligned at both ends' start)
+template <typename T>
+__device__ __forceinline__ void copy_c2(c2<T>* __restrict__ dst, const c2<T>* __restrict__ src, int count, int tid,
+                                        int nth) {
+  constexpr int V = 16 / sizeof(c2<T>);
+  const int nvec = count / V;
+  const uint4* s = reinterpret_cast<const uint4*>(src);
+  uint4* d = reinterpret_cast<uint4*>(dst);
+#pragma unroll 4
+  for (int i = tid; i < nvec; i += nth) d[i] = s[i];
+  for (int e = nvec * V + tid; e < count; e += nth) dst[e] = src[e];
+}
+
+// ---------------------------------------------------------------------------
 // x forward: pre-operation + packed real-to-complex transforms
 // ---------------------------------------------------------------------------
 template <typename T, int C, int N, int NL>
@@ -114,16 +151,19 @@ __global__ void __launch_bounds__((N / Plan<N>::M) * NL * ((C + 1) / 2)) k_xfwd(
   c2<T>* tw = reinterpret_cast<c2<T>*>(smem_raw);
   c2<T>* buf = tw + N;
 
+  __shared__ double red[16];
   const int nlines = a.ny * a.nz;
   const int bpp = (nlines + NL - 1) / NL;
   const int prob = blockIdx.x / bpp;
-  const int line0 = (blockIdx.x % bpp) * NL;
+  const int blk = blockIdx.x % bpp;
+  const int line0 = blk * NL;
   const Ctl& ctl = a.ctl[prob];
   const int mode = ctl.mode;
   if (!pipeline_mode(mode)) return;
   const int tid = threadIdx.x;
   const int nth = blockDim.x;
   for (int i = tid; i < N; i += nth) tw[i] = a.twx[i];
+  double pcp = 0.0;  // CG: partial sum of p . C p  (= p . A p, p being compatible)
 
   const long long nv = a.nvox;
   const long long fo = (long long)prob * C * nv;
@@ -132,61 +172,104 @@ __global__ void __launch_bounds__((N / Plan<N>::M) * NL * ((C + 1) / 2)) k_xfwd(
   const bool cg = (mode == M_CG);
   const bool first = (ctl.cg_it == 0);
   const T beta = T(ctl.beta);
+  __shared__ T ptab[MAX_PHASES];  // 3K (mechanics) or kappa (conduction) per phase
+  if (tid < MAX_PHASES) ptab[tid] = T(C == 6 ? inc.ph[tid].K3 : inc.ph[tid].kappa);
+  __syncthreads();
 
-  for (int idx = tid; idx < NL * N; idx += nth) {
-    const int li = idx / N;
-    const int xv = idx - li * N;
-    const int line = line0 + li;
-    T out[2 * NP];
+  // four consecutive voxels of one line per work item, 16-byte accesses
+  const int nvl = min(NL, nlines - line0);
+  const long long v0 = (long long)line0 * N;
+  for (int w = tid; w < NL * N / 4; w += nth) {
+    const int e = 4 * w;
+    const int li = e / N;
+    const int xv = e - li * N;
+    T out[4][2 * NP];
 #pragma unroll
-    for (int c = 0; c < 2 * NP; ++c) out[c] = T(0);
-    if (line < nlines) {
-      const long long v = (long long)line * N + xv;
+    for (int j = 0; j < 4; ++j)
+#pragma unroll
+      for (int c = 0; c < 2 * NP; ++c) out[j][c] = T(0);
+    if (li < nvl) {
+      const long long v = v0 + e;
       if (!cg) {
 #pragma unroll
-        for (int c = 0; c < C; ++c) out[c] = a.f[fo + c * nv + v];
+        for (int c = 0; c < C; ++c) {
+          const Q4<T> q = ld4(a.f + fo + c * nv + v);
+#pragma unroll
+          for (int j = 0; j < 4; ++j) out[j][c] = q.v[j];
+        }
       } else {
-        T pv[C];
+        T pv[C][4];
 #pragma unroll
         for (int c = 0; c < C; ++c) {
-          T rv = a.r[fo + c * nv + v];
-          pv[c] = first ? rv : rv + beta * a.p[fo + c * nv + v];
-          a.p[fo + c * nv + v] = pv[c];
+          const Q4<T> rq = ld4(a.r + fo + c * nv + v);
+          if (first) {
+#pragma unroll
+            for (int j = 0; j < 4; ++j) pv[c][j] = rq.v[j];
+          } else {
+            const Q4<T> pq = ld4(a.p + fo + c * nv + v);
+#pragma unroll
+            for (int j = 0; j < 4; ++j) pv[c][j] = rq.v[j] + beta * pq.v[j];
+          }
+          st4(a.p + fo + c * nv + v, pv[c]);
         }
-        const int ph = phase[v];
+        const uchar4 ph = *reinterpret_cast<const uchar4*>(phase + v);
+        const int phs[4] = {ph.x, ph.y, ph.z, ph.w};
         if constexpr (C == 6) {
           const long long to = (long long)prob * 2 * nv;
-          const T K3 = T(inc.ph[ph].K3);
-          const T ca = a.tab[to + v];
-          const T cb = a.tab[to + nv + v];
-          const T tr3 = (pv[0] + pv[1] + pv[2]) * T(1.0 / 3.0);
-          const T sph = K3 * tr3 - ca * tr3;
+          const Q4<T> ca = ld4(a.tab + to + v);
+          const Q4<T> cb = ld4(a.tab + to + nv + v);
 #pragma unroll
-          for (int c = 0; c < 6; ++c) out[c] = ca * pv[c];
-          out[0] += sph;
-          out[1] += sph;
-          out[2] += sph;
-          if (cb != T(0)) {
+          for (int j = 0; j < 4; ++j) {
+            const T tr3 = (pv[0][j] + pv[1][j] + pv[2][j]) * T(1.0 / 3.0);
+            const T sph = (ptab[phs[j]] - ca.v[j]) * tr3;
+#pragma unroll
+            for (int c = 0; c < 6; ++c) out[j][c] = ca.v[j] * pv[c][j];
+            out[j][0] += sph;
+            out[j][1] += sph;
+            out[j][2] += sph;
+          }
+          if (cb.v[0] != T(0) || cb.v[1] != T(0) || cb.v[2] != T(0) || cb.v[3] != T(0)) {
             const long long no = (long long)prob * 6 * nv;
-            T nd[6];
-            T dot = T(0);
+            T nd[6][4];
 #pragma unroll
             for (int c = 0; c < 6; ++c) {
-              nd[c] = a.tn[no + c * nv + v];
-              dot += nd[c] * pv[c];
+              const Q4<T> q = ld4(a.tn + no + c * nv + v);
+#pragma unroll
+              for (int j = 0; j < 4; ++j) nd[c][j] = q.v[j];
             }
 #pragma unroll
-            for (int c = 0; c < 6; ++c) out[c] += cb * dot * nd[c];
+            for (int j = 0; j < 4; ++j) {
+              if (cb.v[j] == T(0)) continue;
+              T dot = T(0);
+#pragma unroll
+              for (int c = 0; c < 6; ++c) dot += nd[c][j] * pv[c][j];
+#pragma unroll
+              for (int c = 0; c < 6; ++c) out[j][c] += cb.v[j] * dot * nd[c][j];
+            }
           }
         } else {
-          const T kap = T(inc.ph[ph].kappa);
 #pragma unroll
-          for (int c = 0; c < C; ++c) out[c] = kap * pv[c];
+          for (int j = 0; j < 4; ++j) {
+            const T kap = ptab[phs[j]];
+#pragma unroll
+            for (int c = 0; c < C; ++c) out[j][c] = kap * pv[c][j];
+          }
         }
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+#pragma unroll
+          for (int c = 0; c < C; ++c) pcp += (double)pv[c][j] * (double)out[j][c];
       }
     }
 #pragma unroll
-    for (int q = 0; q < NP; ++q) buf[xv * L + li * NP + q] = mk(out[2 * q], out[2 * q + 1]);
+    for (int j = 0; j < 4; ++j)
+#pragma unroll
+      for (int q = 0; q < NP; ++q) buf[(xv + j) * L + li * NP + q] = mk(out[j][2 * q], out[j][2 * q + 1]);
+  }
+  if (cg) {  // uniform per block
+    double s[1] = {pcp};
+    block_sum<1>(s, red);
+    if (tid == 0) a.part[((long long)prob * a.maxblk + blk) * NPART] = s[0];
   }
   __syncthreads();
 
@@ -201,21 +284,32 @@ __global__ void __launch_bounds__((N / Plan<N>::M) * NL * ((C + 1) / 2)) k_xfwd(
   for (int m = 0; m < M; ++m) buf[(t + G * m) * L + l] = r[m];
   __syncthreads();
 
-  c2<T>* spec = a.spec + (long long)prob * a.nz * a.ny * a.P * C;
-  const int P = a.P;
-  for (int idx = tid; idx < NL * H * C; idx += nth) {
-    const int c = idx % C;
-    const int rest = idx / C;
+  // unpack the two real transforms of each complex line and write the block's
+  // contiguous run of half spectra [line][kx][comp] with 16-byte stores
+  c2<T>* spec = a.spec + (long long)prob * a.nz * a.ny * a.P * C + (long long)line0 * H * C;
+  constexpr int V = 16 / sizeof(c2<T>);
+  const int total = nvl * H * C;
+  auto value = [&](int e) -> c2<T> {
+    const int c = e % C;
+    const int rest = e / C;
     const int k = rest % H;
     const int li = rest / H;
-    const int line = line0 + li;
-    if (line >= nlines) continue;
     const int q = c >> 1;
     const c2<T> zk = buf[k * L + li * NP + q];
     const c2<T> zm = conjg(buf[((N - k) % N) * L + li * NP + q]);
-    c2<T> val = (c & 1) ? mul_mi(zk - zm) : (zk + zm);
-    spec[((long long)line * P + k) * C + c] = cscale(val, T(0.5));
+    const c2<T> val = (c & 1) ? mul_mi(zk - zm) : (zk + zm);
+    return cscale(val, T(0.5));
+  };
+  const int nvec = total / V;
+  for (int i = tid; i < nvec; i += nth) {
+    if constexpr (V == 2) {
+      const c2<T> u0 = value(2 * i), u1 = value(2 * i + 1);
+      reinterpret_cast<float4*>(spec)[i] = make_float4(u0.x, u0.y, u1.x, u1.y);
+    } else {
+      spec[i] = value(i);
+    }
   }
+  for (int e = nvec * V + tid; e < total; e += nth) spec[e] = value(e);
 }
 
 // ---------------------------------------------------------------------------
@@ -360,21 +454,19 @@ __global__ void __launch_bounds__((N / Plan<N>::M) * NL * ((C + 1) / 2)) k_xinv(
   const int prob = blockIdx.x / bpp;
   const int blk = blockIdx.x % bpp;
   const int line0 = blk * NL;
-  const int mode = a.ctl[prob].mode;
+  const Ctl& ctl = a.ctl[prob];
+  const int mode = ctl.mode;
   if (!pipeline_mode(mode)) return;
+  const T alpha = T(ctl.alpha);
+  const bool cg_first = ctl.cg_it == 0;
   const int tid = threadIdx.x;
   const int nth = blockDim.x;
   for (int i = tid; i < N; i += nth) tw[i] = a.twx[i];
-  const c2<T>* spec = a.spec + (long long)prob * a.nz * a.ny * a.P * C;
-  const int P = a.P;
-  for (int idx = tid; idx < NL * H * C; idx += nth) {
-    const int rest = idx / C;
-    const int k = rest % H;
-    const int li = rest / H;
-    const int c = idx - rest * C;
-    const int line = line0 + li;
-    buf[idx] = line < nlines ? spec[((long long)line * P + k) * C + c] : mk(T(0), T(0));
-  }
+  // stage the block's contiguous run of half spectra [line][kx][comp]
+  const int nvl = min(NL, nlines - line0);
+  const c2<T>* spec = a.spec + (long long)prob * a.nz * a.ny * a.P * C + (long long)line0 * H * C;
+  copy_c2<T>(buf, spec, nvl * H * C, tid, nth);
+  for (int e = nvl * H * C + tid; e < NL * H * C; e += nth) buf[e] = mk(T(0), T(0));
   __syncthreads();
   const int l = tid % L;
   const int t = tid / L;
@@ -405,30 +497,62 @@ __global__ void __launch_bounds__((N / Plan<N>::M) * NL * ((C + 1) / 2)) k_xinv(
   const long long fo = (long long)prob * C * nv;
   const T scale = T(1.0 / ((double)a.nx * a.ny * a.nz));
   double s0 = 0.0, s1 = 0.0;
-  for (int idx = tid; idx < NL * N; idx += nth) {
-    const int lj = idx / N;
-    const int xv = idx - lj * N;
-    const int line = line0 + lj;
-    if (line >= nlines) continue;
-    const long long v = (long long)line * N + xv;
+  const long long v0 = (long long)line0 * N;
+  for (int w = tid; w < nvl * N / 4; w += nth) {
+    const int e = 4 * w;
+    const int lj = e / N;
+    const int xv = e - lj * N;
+    const long long v = v0 + e;
 #pragma unroll
     for (int c = 0; c < C; ++c) {
-      const c2<T> z = buf[xv * L + lj * NP + (c >> 1)];
-      const T g = ((c & 1) ? z.y : z.x) * scale;
+      T g[4];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const c2<T> z = buf[(xv + j) * L + lj * NP + (c >> 1)];
+        g[j] = ((c & 1) ? z.y : z.x) * scale;
+      }
       const long long o = fo + c * nv + v;
       if (mode == M_EVAL) {
-        a.r[o] = -g;
-        const double fv = (double)a.f[o];
-        s0 += (double)g * (double)g;
-        s1 += fv * fv;
+        T ng[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) ng[j] = -g[j];
+        st4(a.r + o, ng);
+        const Q4<T> fq = ld4(a.f + o);
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          s0 += (double)g[j] * (double)g[j];
+          s1 += (double)fq.v[j] * (double)fq.v[j];
+        }
       } else if (mode == M_CG) {
-        a.ap[o] = g;
-        s0 += (double)a.p[o] * (double)g;
+        // CG update with alpha = r.r / p.C p: r -= alpha A p, dx += alpha p
+        const Q4<T> pq = ld4(a.p + o);
+        const Q4<T> rq = ld4(a.r + o);
+        T rn[4], dn[4];
+        if (cg_first) {
+#pragma unroll
+          for (int j = 0; j < 4; ++j) dn[j] = alpha * pq.v[j];
+        } else {
+          const Q4<T> dq = ld4(a.dx + o);
+#pragma unroll
+          for (int j = 0; j < 4; ++j) dn[j] = dq.v[j] + alpha * pq.v[j];
+        }
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          rn[j] = rq.v[j] - alpha * g[j];
+          s0 += (double)rn[j] * (double)rn[j];
+        }
+        st4(a.r + o, rn);
+        st4(a.dx + o, dn);
       } else {
-        const T xn = a.x[o] - g;
-        a.x[o] = xn;
-        s0 += (double)g * (double)g;
-        s1 += (double)xn * (double)xn;
+        const Q4<T> xq = ld4(a.x + o);
+        T xn[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          xn[j] = xq.v[j] - g[j];
+          s0 += (double)g[j] * (double)g[j];
+          s1 += (double)xn[j] * (double)xn[j];
+        }
+        st4(a.x + o, xn);
       }
     }
   }

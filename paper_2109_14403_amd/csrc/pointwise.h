@@ -18,12 +18,12 @@ struct Pt {
   T* f;
   T* r;
   T* p;
-  T* ap;
   T* dx;
   T* tab;
   T* tn;
   double* state;            // [prob][nstate][nvox] (mechanics with a PA66 phase)
   int nstate;
+  double* hist;             // [prob][7][nvox] PA66 branch history sums of the increment
   Ctl* ctl;
   const ProbInc* inc;
   double* part;
@@ -50,9 +50,9 @@ void launch_init_th(const Pt<T>& a, int scheme, hipStream_t s);
 template <typename T>
 void launch_eval(const Pt<T>& a, int C, hipStream_t s);
 template <typename T>
-void launch_cgupdate(const Pt<T>& a, int C, hipStream_t s);
+void launch_history(const Pt<T>& a, hipStream_t s);
 void launch_reduce_a(Ctl* ctl, const double* part, int maxblk, int nblk, int nprob, Limits lim, hipStream_t s);
-void launch_reduce_b(Ctl* ctl, const double* part, int maxblk, int nblk, int nprob, Limits lim, hipStream_t s);
+void launch_reduce_alpha(Ctl* ctl, const double* part, int maxblk, int nblk, int nprob, hipStream_t s);
 template <typename T>
 void launch_commit(const Pt<T>& a, int C, hipStream_t s);
 void launch_reduce_out(Ctl* ctl, const double* part, int maxblk, int nblk, int nprob, int nk, double scale,

@@ -65,10 +65,39 @@ __device__ __forceinline__ double pa66_solve_dp(const ProbInc& in, double seq, d
   return d;
 }
 
-// Trial / final evaluation. If `st_out` is non-null the new internal
-// variables are written there and the dissipation and coupling computed.
+// Branch history sums of one voxel, fixed during an increment (they depend on
+// the viscous strains of step n and on theta, dt only):
+//   hd = sum_i 2 G_i D_i / (1 + rG_i)   (deviatoric, 6 Mandel components)
+//   hs = sum_i 3 K_i S_i / (1 + rK_i)   (S_i = tr(eps_v_i) / 3)
+// so that the trial stress is s_tr = 2 Gbar (dev eps - eps_vp) - hd and the
+// spherical stress 3 Kbar tr(e)/3 - hs.
+__device__ __forceinline__ void pa66_history(const ProbInc& in, const double* st, long long ss, double* hd,
+                                             double& hs) {
+#pragma unroll
+  for (int c = 0; c < 6; ++c) hd[c] = 0.0;
+  hs = 0.0;
+  for (int i = 0; i < in.nm; ++i) {
+    const double* ev = st + (7 + 6 * i) * ss;
+    const double v0 = ev[0], v1 = ev[ss], v2 = ev[2 * ss];
+    const double sn = (v0 + v1 + v2) * (1.0 / 3.0);
+    const double w = in.G2i[i] * in.fG[i];
+    hd[0] += w * (v0 - sn);
+    hd[1] += w * (v1 - sn);
+    hd[2] += w * (v2 - sn);
+    hd[3] += w * ev[3 * ss];
+    hd[4] += w * ev[4 * ss];
+    hd[5] += w * ev[5 * ss];
+    hs += in.K3i[i] * in.fK[i] * sn;
+  }
+}
+
+// Trial / final evaluation. If `hist` is non-null (trial only) the branch
+// history sums are read from it ([7][ss]: hd, hs), else computed from the
+// state. If `st_out` is non-null the new internal variables are written
+// there and the dissipation and coupling computed.
 __device__ void pa66_point(const ProbInc& in, const double* eps, const double* st, long long ss, double* st_out,
-                           const double* eps_n, PaOut& o, double* diss, double* coup) {
+                           const double* eps_n, PaOut& o, double* diss, double* coup,
+                           const double* hist = nullptr) {
   const double tr3 = (eps[0] + eps[1] + eps[2]) * (1.0 / 3.0);
   const double em = tr3 - in.ph[in.pa_phase].alpha_dth;
   double d[6];
@@ -81,23 +110,18 @@ __device__ void pa66_point(const ProbInc& in, const double* eps, const double* s
   double evp[6];
 #pragma unroll
   for (int c = 0; c < 6; ++c) evp[c] = st[(1 + c) * ss];
+  double hd[6], hs;
+  if (hist) {
+#pragma unroll
+    for (int c = 0; c < 6; ++c) hd[c] = hist[c * ss];
+    hs = hist[6 * ss];
+  } else {
+    pa66_history(in, st, ss, hd, hs);
+  }
   double str[6];
 #pragma unroll
-  for (int c = 0; c < 6; ++c) str[c] = in.Gbar2 * (d[c] - evp[c]);
-  double sph = in.Kinf3 * em;
-  for (int i = 0; i < in.nm; ++i) {
-    const double* ev = st + (7 + 6 * i) * ss;
-    const double v0 = ev[0], v1 = ev[ss], v2 = ev[2 * ss];
-    const double sn = (v0 + v1 + v2) * (1.0 / 3.0);
-    const double w = in.G2i[i] * in.fG[i];
-    str[0] -= w * (v0 - sn);
-    str[1] -= w * (v1 - sn);
-    str[2] -= w * (v2 - sn);
-    str[3] -= w * ev[3 * ss];
-    str[4] -= w * ev[4 * ss];
-    str[5] -= w * ev[5 * ss];
-    sph += in.K3i[i] * in.fK[i] * (em - sn);
-  }
+  for (int c = 0; c < 6; ++c) str[c] = in.Gbar2 * (d[c] - evp[c]) - hd[c];
+  const double sph = in.Kbar3 * em - hs;
   double sn2 = 0.0;
 #pragma unroll
   for (int c = 0; c < 6; ++c) sn2 += str[c] * str[c];
@@ -237,8 +261,9 @@ __global__ void __launch_bounds__(PT_THREADS) k_eval(Pt<T> a) {
 #pragma unroll
         for (int c = 0; c < 6; ++c) ed[c] = (double)e[c];
         const double* st = a.state + (long long)prob * a.nstate * nv + v;
+        const double* hs = a.hist ? a.hist + (long long)prob * 7 * nv + v : nullptr;
         PaOut o;
-        pa66_point(in, ed, st, nv, nullptr, nullptr, o, nullptr, nullptr);
+        pa66_point(in, ed, st, nv, nullptr, nullptr, o, nullptr, nullptr, hs);
 #pragma unroll
         for (int c = 0; c < 6; ++c) sg[c] = o.sig[c];
         ca = o.a;
@@ -273,32 +298,23 @@ __global__ void __launch_bounds__(PT_THREADS) k_eval(Pt<T> a) {
   }
 }
 
-template <typename T, int C>
-__global__ void __launch_bounds__(PT_THREADS) k_cgupdate(Pt<T> a) {
-  __shared__ double red[16];
+// Branch history sums of the PA66 voxels for the increment about to be solved.
+template <typename T>
+__global__ void __launch_bounds__(PT_THREADS) k_history(Pt<T> a) {
   const int prob = blockIdx.x / a.bpp;
   const int blk = blockIdx.x % a.bpp;
-  const Ctl& ctl = a.ctl[prob];
-  if (ctl.mode != M_CG || !ctl.cg_ready) return;
-  const T alpha = T(ctl.alpha);
-  const bool first = ctl.cg_it == 0;
+  const ProbInc& in = a.inc[prob];
   const long long nv = a.nvox;
-  const long long fo = (long long)prob * C * nv;
-  double s = 0.0;
+  const uint8_t* phase = a.phase + (long long)prob * nv;
   for (long long v = (long long)blk * PT_THREADS + threadIdx.x; v < nv; v += (long long)a.bpp * PT_THREADS) {
+    if (phase[v] != in.pa_phase) continue;
+    double hd[6], hs;
+    pa66_history(in, a.state + (long long)prob * a.nstate * nv + v, nv, hd, hs);
+    double* h = a.hist + (long long)prob * 7 * nv + v;
 #pragma unroll
-    for (int c = 0; c < C; ++c) {
-      const long long o = fo + c * nv + v;
-      const T pv = a.p[o];
-      a.dx[o] = (first ? T(0) : a.dx[o]) + alpha * pv;
-      const T rn = a.r[o] - alpha * a.ap[o];
-      a.r[o] = rn;
-      s += (double)rn * (double)rn;
-    }
+    for (int c = 0; c < 6; ++c) h[c * nv] = hd[c];
+    h[6 * nv] = hs;
   }
-  double sv[1] = {s};
-  block_sum<1>(sv, red);
-  if (threadIdx.x == 0) a.part[((long long)prob * a.maxblk + blk) * NPART] = sv[0];
 }
 
 template <typename T, int C>
@@ -393,11 +409,26 @@ __global__ void __launch_bounds__(PT_THREADS) k_reduce_a(Ctl* ctl, const double*
   const int prob = blockIdx.x;
   Ctl& c = ctl[prob];
   const int mode = c.mode;
-  if (!(mode == M_EVAL || mode == M_BASIC || (mode == M_CG && !c.cg_ready))) return;
+  if (!(mode == M_EVAL || mode == M_BASIC || (mode == M_CG && c.cg_ready))) return;
   sum_parts(part, maxblk, nblk, prob, 2, s, red);
   if (threadIdx.x != 0) return;
   c.pipelines += 1;
-  if (mode == M_EVAL) {
+  if (mode == M_CG) {
+    // after the CG update of the x-inverse pass: s[0] = r.r of the new residual
+    const double rn = s[0];
+    c.beta = c.rr > 0.0 ? rn / c.rr : 0.0;
+    c.rr = rn;
+    c.cg_it += 1;
+    c.krylov += 1;
+    c.cg_ready = 0;
+    if (!isfinite(rn)) {
+      c.mode = M_FAIL;
+      c.status = -4;
+    } else if (rn <= c.cg_target || c.cg_it >= lim.max_krylov) {
+      c.mode = M_EVAL;
+      c.pending = 1;
+    }
+  } else if (mode == M_EVAL) {
     const double rr = s[0], ff = s[1];
     const double res = ff > 0.0 ? sqrt(rr / ff) : 0.0;
     c.res = res;
@@ -423,21 +454,6 @@ __global__ void __launch_bounds__(PT_THREADS) k_reduce_a(Ctl* ctl, const double*
       c.beta = 0.0;
       c.mode = M_CG;
     }
-  } else if (mode == M_CG) {
-    const double pap = s[0];
-    if (!(pap > 0.0) || !isfinite(pap)) {
-      if (c.rr == 0.0) {  // exact solution reached
-        c.mode = M_EVAL;
-        c.pending = 1;
-        c.alpha = 0.0;
-        return;
-      }
-      c.mode = M_FAIL;
-      c.status = -4;
-      return;
-    }
-    c.alpha = c.rr / pap;
-    c.cg_ready = 1;
   } else {  // basic scheme
     const double dd = s[0], xx = s[1];
     const double err = xx > 0.0 ? sqrt(dd / xx) : 0.0;
@@ -456,28 +472,26 @@ __global__ void __launch_bounds__(PT_THREADS) k_reduce_a(Ctl* ctl, const double*
   }
 }
 
-__global__ void __launch_bounds__(PT_THREADS) k_reduce_b(Ctl* ctl, const double* part, int maxblk, int nblk,
-                                                          Limits lim) {
+// After the x-forward pass of a CG iteration: alpha = r.r / p.C p. For a
+// compatible direction p, p.C p equals p.A p = p.P[C p] because P is an
+// orthogonal projector, so alpha is known before the inverse transforms and
+// the x-inverse pass can apply the CG update itself.
+__global__ void __launch_bounds__(PT_THREADS) k_reduce_alpha(Ctl* ctl, const double* part, int maxblk, int nblk) {
   __shared__ double red[16];
   __shared__ double s[1];
   const int prob = blockIdx.x;
   Ctl& c = ctl[prob];
-  if (c.mode != M_CG || !c.cg_ready) return;
+  if (c.mode != M_CG || c.cg_ready) return;
   sum_parts(part, maxblk, nblk, prob, 1, s, red);
   if (threadIdx.x != 0) return;
-  const double rn = s[0];
-  c.beta = c.rr > 0.0 ? rn / c.rr : 0.0;
-  c.rr = rn;
-  c.cg_it += 1;
-  c.krylov += 1;
-  c.cg_ready = 0;
-  if (!isfinite(rn)) {
+  const double pap = s[0];
+  if (!(pap > 0.0) || !isfinite(pap)) {
     c.mode = M_FAIL;
     c.status = -4;
-  } else if (rn <= c.cg_target || c.cg_it >= lim.max_krylov) {
-    c.mode = M_EVAL;
-    c.pending = 1;
+    return;
   }
+  c.alpha = c.rr / pap;
+  c.cg_ready = 1;
 }
 
 __global__ void __launch_bounds__(PT_THREADS) k_reduce_out(Ctl* ctl, const double* part, int maxblk, int nblk,
@@ -511,11 +525,8 @@ void launch_eval(const Pt<T>& a, int C, hipStream_t s) {
     hipLaunchKernelGGL((k_eval<T, 3>), dim3(a.nprob * a.bpp), dim3(PT_THREADS), 0, s, a);
 }
 template <typename T>
-void launch_cgupdate(const Pt<T>& a, int C, hipStream_t s) {
-  if (C == 6)
-    hipLaunchKernelGGL((k_cgupdate<T, 6>), dim3(a.nprob * a.bpp), dim3(PT_THREADS), 0, s, a);
-  else
-    hipLaunchKernelGGL((k_cgupdate<T, 3>), dim3(a.nprob * a.bpp), dim3(PT_THREADS), 0, s, a);
+void launch_history(const Pt<T>& a, hipStream_t s) {
+  hipLaunchKernelGGL((k_history<T>), dim3(a.nprob * a.bpp), dim3(PT_THREADS), 0, s, a);
 }
 template <typename T>
 void launch_commit(const Pt<T>& a, int C, hipStream_t s) {
@@ -527,8 +538,8 @@ void launch_commit(const Pt<T>& a, int C, hipStream_t s) {
 void launch_reduce_a(Ctl* ctl, const double* part, int maxblk, int nblk, int nprob, Limits lim, hipStream_t s) {
   hipLaunchKernelGGL(k_reduce_a, dim3(nprob), dim3(PT_THREADS), 0, s, ctl, part, maxblk, nblk, lim);
 }
-void launch_reduce_b(Ctl* ctl, const double* part, int maxblk, int nblk, int nprob, Limits lim, hipStream_t s) {
-  hipLaunchKernelGGL(k_reduce_b, dim3(nprob), dim3(PT_THREADS), 0, s, ctl, part, maxblk, nblk, lim);
+void launch_reduce_alpha(Ctl* ctl, const double* part, int maxblk, int nblk, int nprob, hipStream_t s) {
+  hipLaunchKernelGGL(k_reduce_alpha, dim3(nprob), dim3(PT_THREADS), 0, s, ctl, part, maxblk, nblk);
 }
 void launch_reduce_out(Ctl* ctl, const double* part, int maxblk, int nblk, int nprob, int nk, double scale,
                        hipStream_t s) {
@@ -539,7 +550,7 @@ void launch_reduce_out(Ctl* ctl, const double* part, int maxblk, int nblk, int n
   template void launch_init_mech<T>(const Pt<T>&, int, hipStream_t);    \
   template void launch_init_th<T>(const Pt<T>&, int, hipStream_t);      \
   template void launch_eval<T>(const Pt<T>&, int, hipStream_t);         \
-  template void launch_cgupdate<T>(const Pt<T>&, int, hipStream_t);     \
+  template void launch_history<T>(const Pt<T>&, hipStream_t);           \
   template void launch_commit<T>(const Pt<T>&, int, hipStream_t);
 HOM_INST_PT(float)
 HOM_INST_PT(double)

@@ -32,20 +32,21 @@ enum KernelKind {
   K_YINV,
   K_XINV,
   K_REDA,
-  K_CGUPD,
-  K_REDB,
+  K_HIST,
+  K_REDALPHA,
   K_COMMIT,
   K_REDOUT,
   K_COUNT
 };
-extern const char* const kKernelNames[K_COUNT];
+extern const char* const kKernelNames[2 * K_COUNT];
 
 struct Profiler {
   bool on = false;
   std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> pending;
   std::vector<hipEvent_t> pool;
-  int64_t launches[K_COUNT] = {};
-  double ms[K_COUNT] = {};
+  int offset = 0;  // K_COUNT for the conduction solve
+  int64_t launches[2 * K_COUNT] = {};
+  double ms[2 * K_COUNT] = {};
   void begin(int kind, hipStream_t s);
   void end(hipStream_t s);
   void collect();

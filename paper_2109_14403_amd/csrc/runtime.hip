@@ -10,8 +10,10 @@
 
 namespace hom {
 
-const char* const kKernelNames[K_COUNT] = {"init",  "eval",     "xfwd",  "yfwd",   "zgreen", "yinv",
-                                           "xinv",  "reduce_a", "cgupd", "reduce_b", "commit", "reduce_out"};
+const char* const kKernelNames[2 * K_COUNT] = {
+    "init",   "eval",   "xfwd",   "yfwd",     "zgreen",  "yinv",      "xinv",    "reduce_a",
+    "history",  "reduce_alpha", "commit", "reduce_out", "t.init", "t.eval", "t.xfwd", "t.yfwd",
+    "t.zgreen", "t.yinv", "t.xinv", "t.reduce_a", "t.history", "t.reduce_alpha", "t.commit", "t.reduce_out"};
 
 void fail(int code, const std::string& msg) { throw Error{code, msg}; }
 
@@ -36,7 +38,7 @@ hipEvent_t Profiler::get() {
 }
 void Profiler::begin(int kind, hipStream_t s) {
   if (!on) return;
-  cur = kind;
+  cur = kind + offset;
   ev0 = get();
   HIPCHK(hipEventRecord(ev0, s));
 }
@@ -244,7 +246,8 @@ struct Group {
   size_t bytes = 0;
 
   uint8_t* phase = nullptr;
-  T *xm = nullptr, *xnm = nullptr, *f = nullptr, *r = nullptr, *p = nullptr, *ap = nullptr, *dx = nullptr;
+  T *xm = nullptr, *xnm = nullptr, *f = nullptr, *r = nullptr, *p = nullptr, *dx = nullptr;
+  double* hist = nullptr;
   T *tab = nullptr, *tn = nullptr, *xt = nullptr;
   c2<T>* spec = nullptr;
   double* state = nullptr;
@@ -292,13 +295,15 @@ struct Group {
     f = dalloc<T>(6 * nm);
     r = dalloc<T>(6 * nm);
     p = dalloc<T>(6 * nm);
-    ap = dalloc<T>(6 * nm);
     dx = dalloc<T>(6 * nm);
     tab = dalloc<T>(2 * nm);
     tn = dalloc<T>(6 * nm);
     xt = dalloc<T>(3 * nm);
     spec = dalloc<c2<T>>((size_t)nprob * nz * ny * P * 6);
-    if (with_state && nstate > 0) state = dalloc<double>((size_t)nstate * nm);
+    if (with_state && nstate > 0) {
+      state = dalloc<double>((size_t)nstate * nm);
+      hist = dalloc<double>((size_t)7 * nm);
+    }
     ctl_m = dalloc<Ctl>(nprob);
     ctl_t = dalloc<Ctl>(nprob);
     inc_d = dalloc<ProbInc>(nprob);
@@ -336,7 +341,6 @@ struct Group {
     a.f = f;
     a.r = r;
     a.p = p;
-    a.ap = ap;
     a.dx = dx;
     a.tab = tab;
     a.tn = tn;
@@ -364,12 +368,12 @@ struct Group {
     a.f = f;
     a.r = r;
     a.p = p;
-    a.ap = ap;
     a.dx = dx;
     a.tab = tab;
     a.tn = tn;
     a.state = state;
     a.nstate = nstate;
+    a.hist = hist;
     a.ctl = phys == 0 ? ctl_m : ctl_t;
     a.inc = inc_d;
     a.part = part;
@@ -405,7 +409,7 @@ class BatchT : public BatchImpl {
   void set_profiling(bool on) override {
     prof.collect();
     prof.on = on;
-    for (int k = 0; k < K_COUNT; ++k) {
+    for (int k = 0; k < 2 * K_COUNT; ++k) {
       prof.launches[k] = 0;
       prof.ms[k] = 0.0;
     }
@@ -566,6 +570,11 @@ class BatchT : public BatchImpl {
     prof.begin(K_XFWD, stream);
     run_xfwd<T>(a, stream);
     prof.end(stream);
+    if (!basic) {
+      prof.begin(K_REDALPHA, stream);
+      launch_reduce_alpha(ctl, G.part, G.maxblk, G.xblocks, G.nprob, stream);
+      prof.end(stream);
+    }
     prof.begin(K_YFWD, stream);
     run_ypass<T>(a, G.txy[phys], 0, stream);
     prof.end(stream);
@@ -581,19 +590,13 @@ class BatchT : public BatchImpl {
     prof.begin(K_REDA, stream);
     launch_reduce_a(ctl, G.part, G.maxblk, G.xblocks, G.nprob, lim, stream);
     prof.end(stream);
-    if (!basic) {
-      prof.begin(K_CGUPD, stream);
-      launch_cgupdate<T>(q, C, stream);
-      prof.end(stream);
-      prof.begin(K_REDB, stream);
-      launch_reduce_b(ctl, G.part, G.maxblk, G.pt_bpp, G.nprob, lim, stream);
-      prof.end(stream);
-    }
   }
 
   int chunk_size(const Group<T>& G) const {
     if (opts.chunk > 0) return opts.chunk;
-    return (G.nvox * G.nprob >= (1LL << 22)) ? 4 : 16;
+    // large grids: one iteration per host check (a check costs ~1 % of an
+    // iteration and no idle launches follow convergence); small ones: 16
+    return (G.nvox * G.nprob >= (1LL << 22)) ? 1 : 16;
   }
 
   void run_chunk(Group<T>& G, int phys, bool basic, int k) {
@@ -619,12 +622,18 @@ class BatchT : public BatchImpl {
     const bool basic = opts.scheme == HOM_SCHEME_BASIC;
     Pt<T> q = G.pt(phys);
     check_tiles(G, phys);
+    prof.offset = phys * K_COUNT;
     prof.begin(K_INIT, stream);
     if (phys == 0)
       launch_init_mech<T>(q, opts.scheme, stream);
     else
       launch_init_th<T>(q, opts.scheme, stream);
     prof.end(stream);
+    if (phys == 0 && G.state) {
+      prof.begin(K_HIST, stream);
+      launch_history<T>(q, stream);
+      prof.end(stream);
+    }
     const Limits lim = limits(phys);
     const long long cap = basic ? (long long)lim.max_newton + 2
                                 : (long long)(lim.max_newton + 1) * (lim.max_krylov + 2);
@@ -907,7 +916,10 @@ void eval_law(const hom_law& law, int64_t count, const double* eps, const double
   G.f = G.dalloc<double>(6 * count);
   G.tab = G.dalloc<double>(2 * count);
   G.tn = G.dalloc<double>(6 * count);
-  if (G.nstate) G.state = G.dalloc<double>(G.nstate * count);
+  if (G.nstate) {
+    G.state = G.dalloc<double>(G.nstate * count);
+    G.hist = G.dalloc<double>(7 * count);
+  }
   G.ctl_m = G.dalloc<Ctl>(1);
   G.inc_d = G.dalloc<ProbInc>(1);
   G.pt_bpp = (int)std::min<int64_t>((count + 255) / 256, 4096);
@@ -931,6 +943,7 @@ void eval_law(const hom_law& law, int64_t count, const double* eps, const double
   Pt<double> q = G.pt(0);
   q.pv_diss = pvd;
   q.pv_coup = pvc;
+  if (G.nstate) launch_history<double>(q, nullptr);
   launch_eval<double>(q, 6, nullptr);
   HIPCHK(hipGetLastError());
   HIPCHK(hipDeviceSynchronize());
