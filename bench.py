@@ -85,6 +85,41 @@ def cpu_baseline(phases, laws, sample="one CG pipeline application (tangent, FFT
             "sample": sample, "seconds": dt}
 
 
+def batch_bench(nprob=512, steps=5, seed=4):
+    """The batched two-scale workload: nprob microproblems of 24^3 / 32^3 / 48^3
+    (seeded RSA spheres, own macro histories), all increments, FP32 fields,
+    hipGraph chunks. Returns Gauss-point updates/s and voxel-iterations/s."""
+    import torch
+
+    from paper_2109_14403_amd import hom
+    from paper_2109_14403_amd import workloads as W
+
+    wls = [W.batch_problem(i, seed=seed, n_steps=steps) for i in range(nprob)]
+    laws = [W.pa66(), W.e_glass()]
+    b = hom.Batch([w.phases for w in wls], laws, scheme=hom.SCHEME_NEWTON_CG, precision=hom.FP32, tol=1e-6,
+                  autotune=1)
+    nvox = np.array([w.phases.size for w in wls], dtype=np.float64)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    pipes = np.zeros(nprob)
+    failed = 0
+    for k in range(steps):
+        strains = np.array([w.history[k].strain for w in wls])
+        res = b.solve_increment(strains, [w.history[k].theta for w in wls], [w.history[k].grad for w in wls],
+                                [w.history[k].dt for w in wls])
+        pipes += np.array([r["pipelines"] for r in res])
+        failed += sum(1 for r in res if r["status"] != 0)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    b.close()
+    sizes = {}
+    for w in wls:
+        sizes[w.record["n"]] = sizes.get(w.record["n"], 0) + 1
+    return {"problems": nprob, "increments": steps, "sizes": {str(k): v for k, v in sorted(sizes.items())},
+            "seconds": round(el, 3), "gauss_point_updates_per_s": round(nprob * steps / el, 1),
+            "voxel_iters_per_s": round(float((pipes * nvox).sum()) / el, 1), "failed": failed}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -93,6 +128,7 @@ def main():
     ap.add_argument("--n", type=int, default=256)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-profile", action="store_true")
+    ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--calib-copy", action="store_true", help="run a 1 GiB device copy (PMC calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -182,6 +218,12 @@ def main():
                     "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": traffic, "kernel": dom,
                     "avg_launch_ms": round(avg_s * 1e3, 4), "algorithmic_bytes": byt}
 
+    ctx.close()
+    batch = None
+    if not args.no_batch:
+        batch = batch_bench()
+        print(f"batch: {batch}", file=sys.stderr, flush=True)
+
     cpu = None
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(wl.phases, wl.laws)
@@ -197,7 +239,7 @@ def main():
                    "increments": f"{args.warmup}..{total - 1} of 50"},
         "thermal_voxel_iters_per_s": round(tpipes * nvox / elapsed, 1),
         "newton_per_step": newton / args.steps, "krylov_per_step": krylov / args.steps,
-        "roofline": roof, "cpu_baseline": cpu,
+        "roofline": roof, "cpu_baseline": cpu, "batch": batch,
     }
     if kstats:
         line["kernel_ms"] = {k: [v[0], round(v[1], 3)] for k, v in kstats.items() if v[0]}
