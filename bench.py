@@ -120,6 +120,63 @@ def batch_bench(nprob=512, steps=5, seed=4):
             "voxel_iters_per_s": round(float((pipes * nvox).sum()) / el, 1), "failed": failed}
 
 
+def surrogate_bench(n_hist=4000, test_hist=1000, epochs=150, rows=65536):
+    """Surrogate vs FFT Gauss-point updates/s on the fixed 32^3 microstructure:
+    20k FFT samples (4000 histories x 5 increments, batched solver) train two
+    networks; acceptance is calibrated on held-out histories so that 99 % of
+    accepted rows meet the error target; a fresh test set measures acceptance
+    and error; rejected rows are charged at the batched FFT rate."""
+    import torch
+
+    from paper_2109_14403_amd import surrogate as S
+
+    img, _ = S.microstructure()
+    hist = S.histories(n_hist, seed=10)
+    sol = S.solve_histories(img, hist)
+    X, Y, den, hid = S.features(hist, sol)
+    tr = hid < int(0.9 * n_hist)
+    sur = S.Surrogate()
+    t0 = time.perf_counter()
+    sur.fit(X[tr], Y[tr], epochs=epochs)
+    fit_s = time.perf_counter() - t0
+    th = S.histories(test_hist, seed=99)
+    ts = S.solve_histories(img, th)
+    r_fft = ts["updates"] / ts["seconds"]
+    Xt, Yt, dent, _ = S.features(th, ts)
+    big = torch.as_tensor(np.tile(Xt, (rows // len(Xt) + 1, 1))[:rows], device="cuda")
+    xt_dev = torch.as_tensor(Xt, device="cuda")
+    e_skip = S.stress_errors(sur.skip_only(Xt), Yt, dent)
+    out = {"fft_gauss_point_updates_per_s": round(r_fft, 1), "train_rows": int(tr.sum()), "fit_seconds": round(fit_s, 1),
+           "test_rows": len(Xt), "skip_only_median_error": float(np.median(e_skip))}
+    for target in (1e-3, 1e-2):
+        cal = sur.calibrate(X[~tr], Y[~tr], den[~tr], target=target, quantile=0.99)
+        y, _, acc = sur.infer(xt_dev)
+        torch.cuda.synchronize()
+        y, acc = y.cpu().numpy(), acc.cpu().numpy().astype(bool)
+        err = S.stress_errors(y, Yt, dent)
+        for _ in range(3):
+            sur.infer(big)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        reps = 20
+        for _ in range(reps):
+            sur.infer(big)
+        torch.cuda.synchronize()
+        t_inf = (time.perf_counter() - t1) / reps
+        frac = float(acc.mean())
+        rate = rows / (t_inf + (1.0 - frac) * rows / r_fft)
+        out[f"target_{target:g}"] = {
+            "accepted": round(frac, 4), "threshold": cal["threshold"],
+            "accepted_p99_error": float(np.quantile(err[acc], 0.99)) if acc.any() else None,
+            "accepted_max_error": float(err[acc].max()) if acc.any() else None,
+            "all_median_error": float(np.median(err)), "all_p90_error": float(np.quantile(err, 0.9)),
+            "infer_ms_65536": round(t_inf * 1e3, 3), "surrogate_gauss_point_updates_per_s": round(rate, 1),
+            "ratio_vs_fft": round(rate / r_fft, 2)}
+    flops = rows * 2 * 414720
+    out["network_tflops"] = round(flops / (out["target_0.001"]["infer_ms_65536"] * 1e-3) / 1e12, 2)
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -129,6 +186,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-profile", action="store_true")
     ap.add_argument("--no-batch", action="store_true")
+    ap.add_argument("--no-surrogate", action="store_true")
     ap.add_argument("--calib-copy", action="store_true", help="run a 1 GiB device copy (PMC calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -223,6 +281,10 @@ def main():
     if not args.no_batch:
         batch = batch_bench()
         print(f"batch: {batch}", file=sys.stderr, flush=True)
+    surr = None
+    if not args.no_surrogate:
+        surr = surrogate_bench()
+        print(f"surrogate: {surr}", file=sys.stderr, flush=True)
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -239,7 +301,7 @@ def main():
                    "increments": f"{args.warmup}..{total - 1} of 50"},
         "thermal_voxel_iters_per_s": round(tpipes * nvox / elapsed, 1),
         "newton_per_step": newton / args.steps, "krylov_per_step": krylov / args.steps,
-        "roofline": roof, "cpu_baseline": cpu, "batch": batch,
+        "roofline": roof, "cpu_baseline": cpu, "batch": batch, "surrogate": surr,
     }
     if kstats:
         line["kernel_ms"] = {k: [v[0], round(v[1], 3)] for k, v in kstats.items() if v[0]}

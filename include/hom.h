@@ -182,6 +182,58 @@ int hom_batch_kernel_stats(const hom_batch* b, const char** names, int64_t* laun
 const char* hom_batch_last_error(const hom_batch* b);
 void hom_batch_destroy(hom_batch* b);
 
+/* ---- learned surrogate ------------------------------------------------------
+ * A fully connected network n_in (<= 32) -> 4 x 256 (GELU) -> n_out (<= 16)
+ * mapping the macroscopic inputs of an increment (strain, temperature, dt and
+ * a summary of the macroscopic history) to the effective outputs. It plays
+ * the role the paper gives its learned surrogate (Sec. 3: a fixed
+ * microstructure, macroscopic inputs, effective stress and heat outputs),
+ * with the FFT solver as fallback and judge. Weights are bf16 on the matrix
+ * cores with FP32 accumulation; inputs and outputs are FP32.
+ *
+ * Parameters cross the ABI in layer order, each layer its weight matrix
+ * [out][in] row-major followed by its bias. Scaling: inputs are normalized as
+ * (x - x_mean) / x_std, outputs as (y - y_mean) / y_std; the training loss is
+ * the loss_weight-weighted mean squared error of the normalized outputs. */
+typedef struct hom_mlp hom_mlp;
+int hom_mlp_create(int32_t n_in, int32_t n_out, uint64_t seed, hom_mlp** out);
+size_t hom_mlp_param_count(const hom_mlp* net);
+int hom_mlp_set_scaling(hom_mlp* net, const float* x_mean, const float* x_std, const float* y_mean,
+                        const float* y_std, const float* loss_weight);
+/* Fixed gated-polynomial skip added to the outputs (default zero), on the
+ * normalized inputs xhat: y_j += c_j + sum_g s_g sum_k G[j][g][k] xhat_k with
+ * the 10 gate functions s = (1, v0, v0^2, v0^3, v1, .., v2^3), v_i = xhat at
+ * input index gates[i]. G is [n_out][10][n_in] row-major, c [n_out]. The
+ * network learns the remainder. */
+int hom_mlp_set_skip(hom_mlp* net, const int32_t gates[3], const float* G, const float* c);
+/* Fit the skip to host rows (x [n][n_in], y [n][n_out]) by least squares
+ * (FP64 normal equations) and set the input scaling from x and the output
+ * scaling from the residual y - skip(x); loss_weight may be NULL (all 1).
+ * hom_mlp_train then trains the network on that residual. */
+int hom_mlp_fit_skip(hom_mlp* net, const float* x, const float* y, int64_t n, const int32_t gates[3],
+                     const float* loss_weight);
+int hom_mlp_get_params(const hom_mlp* net, float* host, size_t count);
+int hom_mlp_set_params(hom_mlp* net, const float* host, size_t count);
+/* Train on n rows (host arrays x [n][n_in], y [n][n_out]) with Adam, minibatch
+ * `batch`, peak learning rate lr (cosine decay), seeded shuffling; writes the
+ * mean loss of every epoch into epoch_loss (epochs entries) if non-null. */
+int hom_mlp_train(hom_mlp* net, const float* x, const float* y, int64_t n, int32_t epochs, int32_t batch,
+                  double lr, uint64_t seed, float* epoch_loss);
+/* Inference on device arrays x_dev [n][n_in] -> y_dev [n][n_out] on `stream`.
+ * precise = 1 splits the weights into two bf16 parts (FP32-equivalent). */
+int hom_mlp_forward(hom_mlp* net, const float* x_dev, float* y_dev, int64_t n, int32_t precise, void* stream);
+/* Loss and its gradient w.r.t. all parameters for host rows (x, y); grad has
+ * hom_mlp_param_count entries. */
+int hom_mlp_loss_grad(hom_mlp* net, const float* x, const float* y, int64_t n, int32_t precise, double* loss,
+                      float* grad);
+/* Two-network inference with acceptance: y = mean of the two networks,
+ * spread = |stress_a - stress_b| / max(|stress|, floor_scale) over the first
+ * six outputs, accept = spread <= threshold. All arrays on the device. */
+int hom_surrogate_infer(hom_mlp* a, hom_mlp* b, const float* x_dev, float* y_dev, float* spread_dev,
+                        uint8_t* accept_dev, int64_t n, double threshold, double floor_scale, void* stream);
+const char* hom_mlp_last_error(const hom_mlp* net);
+void hom_mlp_destroy(hom_mlp* net);
+
 /* ---- kernel-level entry points (used by the parity tests) ------------------
  * hom_apply_operator: out = IFFT(Op(n) FFT(in)) on one grid, in/out host FP64
  * arrays of ncomp x nvox (component-major). ncomp = 6 (Mandel) with op 0 =

@@ -2,6 +2,7 @@
 #include <cstring>
 #include <new>
 
+#include "mlp.h"
 #include "runtime.h"
 
 struct hom_ctx {
@@ -11,6 +12,15 @@ struct hom_ctx {
 struct hom_batch {
   std::unique_ptr<hom::BatchImpl> impl;
   std::string err;
+};
+struct hom_mlp {
+  std::unique_ptr<hom::Mlp> net;
+  std::string err;
+  float* scratch = nullptr;  // two-network outputs of hom_surrogate_infer
+  long long scratch_rows = 0;
+  ~hom_mlp() {
+    if (scratch) (void)hipFree(scratch);
+  }
 };
 
 namespace {
@@ -166,6 +176,120 @@ int hom_batch_kernel_stats(const hom_batch* b, const char** names, int64_t* laun
 const char* hom_batch_last_error(const hom_batch* b) { return b ? b->err.c_str() : g_setup_error.c_str(); }
 
 void hom_batch_destroy(hom_batch* b) { delete b; }
+
+int hom_mlp_create(int32_t n_in, int32_t n_out, uint64_t seed, hom_mlp** out) {
+  if (!out) return HOM_E_ARG;
+  *out = nullptr;
+  hom_mlp* m = new (std::nothrow) hom_mlp();
+  if (!m) return HOM_E_OOM;
+  int rc = guarded(&g_setup_error, [&] { m->net = std::make_unique<hom::Mlp>(n_in, n_out, seed); });
+  if (rc != HOM_OK) {
+    delete m;
+    return rc;
+  }
+  *out = m;
+  return HOM_OK;
+}
+
+size_t hom_mlp_param_count(const hom_mlp* m) { return (m && m->net) ? m->net->param_count() : 0; }
+
+int hom_mlp_set_scaling(hom_mlp* m, const float* xm, const float* xs, const float* ym, const float* ys,
+                        const float* lw) {
+  if (!m || !m->net || !xm || !xs || !ym || !ys) return HOM_E_ARG;
+  return guarded(&m->err, [&] { m->net->set_scaling(xm, xs, ym, ys, lw); });
+}
+
+int hom_mlp_set_skip(hom_mlp* m, const int32_t gates[3], const float* G, const float* c) {
+  if (!m || !m->net || !gates || !G || !c) return HOM_E_ARG;
+  return guarded(&m->err, [&] {
+    const int g[3] = {gates[0], gates[1], gates[2]};
+    m->net->set_skip(g, G, c);
+  });
+}
+
+int hom_mlp_fit_skip(hom_mlp* m, const float* x, const float* y, int64_t n, const int32_t gates[3],
+                     const float* lw) {
+  if (!m || !m->net || !x || !y || !gates || n < 2) return HOM_E_ARG;
+  return guarded(&m->err, [&] {
+    const int g[3] = {gates[0], gates[1], gates[2]};
+    std::vector<float> w(m->net->n_out, 1.f);
+    if (lw) w.assign(lw, lw + m->net->n_out);
+    m->net->fit_skip(x, y, n, g, w.data());
+  });
+}
+
+int hom_mlp_get_params(const hom_mlp* m, float* host, size_t count) {
+  if (!m || !m->net || !host || count != m->net->param_count()) return HOM_E_ARG;
+  return guarded(nullptr, [&] { m->net->get_params(host); });
+}
+
+int hom_mlp_set_params(hom_mlp* m, const float* host, size_t count) {
+  if (!m || !m->net || !host || count != m->net->param_count()) return HOM_E_ARG;
+  return guarded(&m->err, [&] { m->net->set_params(host); });
+}
+
+int hom_mlp_train(hom_mlp* m, const float* x, const float* y, int64_t n, int32_t epochs, int32_t batch, double lr,
+                  uint64_t seed, float* epoch_loss) {
+  if (!m || !m->net || !x || !y || n < 1 || epochs < 1 || batch < 1 || !(lr > 0.0)) return HOM_E_ARG;
+  return guarded(&m->err, [&] { m->net->train(x, y, n, epochs, batch, lr, seed, epoch_loss); });
+}
+
+int hom_mlp_forward(hom_mlp* m, const float* x_dev, float* y_dev, int64_t n, int32_t precise, void* stream) {
+  if (!m || !m->net || !x_dev || !y_dev || n < 0) return HOM_E_ARG;
+  return guarded(&m->err, [&] {
+    m->net->forward(x_dev, y_dev, n, precise != 0, false, static_cast<hipStream_t>(stream));
+    hom::hip_check(hipGetLastError(), "mlp forward launch");
+  });
+}
+
+int hom_mlp_loss_grad(hom_mlp* m, const float* x, const float* y, int64_t n, int32_t precise, double* loss,
+                      float* grad) {
+  if (!m || !m->net || !x || !y || n < 1) return HOM_E_ARG;
+  return guarded(&m->err, [&] {
+    hom::Mlp& net = *m->net;
+    std::vector<float> tn((size_t)n * hom::MLP_OUT);
+    net.normalized_targets(x, y, n, tn.data());
+    float *dx = nullptr, *dt = nullptr;
+    HIPCHK(hipMalloc((void**)&dx, n * net.n_in * 4));
+    HIPCHK(hipMalloc((void**)&dt, tn.size() * 4));
+    struct G {
+      float *a, *b;
+      ~G() {
+        (void)hipFree(a);
+        (void)hipFree(b);
+      }
+    } g{dx, dt};
+    HIPCHK(hipMemcpy(dx, x, n * net.n_in * 4, hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpy(dt, tn.data(), tn.size() * 4, hipMemcpyHostToDevice));
+    const double L = net.loss_grad(dx, dt, n, precise != 0, nullptr);
+    hom::hip_check(hipDeviceSynchronize(), "mlp gradient");
+    if (loss) *loss = L;
+    if (grad) net.get_grads(grad);
+  });
+}
+
+int hom_surrogate_infer(hom_mlp* a, hom_mlp* b, const float* x_dev, float* y_dev, float* spread_dev,
+                        uint8_t* accept_dev, int64_t n, double threshold, double floor_scale, void* stream) {
+  if (!a || !b || !a->net || !b->net || !x_dev || !y_dev || !spread_dev || !accept_dev || n < 0) return HOM_E_ARG;
+  return guarded(&a->err, [&] {
+    if (a->net->n_in != b->net->n_in || a->net->n_out != b->net->n_out) hom::fail(HOM_E_ARG, "network shapes differ");
+    if (n > a->scratch_rows) {
+      if (a->scratch) HIPCHK(hipFree(a->scratch));
+      a->scratch = nullptr;
+      HIPCHK(hipMalloc((void**)&a->scratch, (size_t)n * 2 * a->net->n_out * 4));
+      a->scratch_rows = n;
+    }
+    float* ya = a->scratch;
+    float* yb = a->scratch + (size_t)n * a->net->n_out;
+    hom::surrogate_accept(*a->net, *b->net, x_dev, y_dev, ya, yb, spread_dev, accept_dev, n, (float)threshold,
+                          (float)floor_scale, static_cast<hipStream_t>(stream));
+    hom::hip_check(hipGetLastError(), "surrogate launch");
+  });
+}
+
+const char* hom_mlp_last_error(const hom_mlp* m) { return m ? m->err.c_str() : g_setup_error.c_str(); }
+
+void hom_mlp_destroy(hom_mlp* m) { delete m; }
 
 int hom_apply_operator(const hom_grid* grid, int32_t ncomp, int32_t op, double p0, double p1, int32_t precision,
                        const double* in, double* out) {

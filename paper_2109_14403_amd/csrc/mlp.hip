@@ -1,0 +1,799 @@
+// Surrogate network: n_in (<= 32) -> 4 x 256 (GELU) -> n_out (<= 16).
+//
+// Forward: one work-group of 4 waves per 64 rows; every layer is a
+// [64 x K] x [K x 256] product on the bf16 matrix cores
+// (v_mfma_f32_16x16x32_bf16, FP32 accumulation). Weights are bf16; the
+// activations are split into bf16 hi + lo parts (two MFMAs per tile), so the
+// product sees the activations to ~16 significant bits. In "precise" mode the
+// weights are split as well (three MFMAs: a_hi w_hi + a_lo w_hi + a_hi w_lo),
+// which reproduces FP32 weights for gradient checks. Bias and GELU are fused
+// into the epilogue; the layer output stays in LDS for the next layer.
+//
+// Training: FP32 backward (tiled GEMMs for dA = dZ W and dW = dZ^T A,
+// column sums for db), weighted MSE on normalized outputs, Adam on FP32
+// master weights with refreshed bf16 copies after each step.
+#include <hip/hip_runtime.h>
+#include <math.h>
+
+#include <algorithm>
+#include <cstring>
+#include <random>
+#include <vector>
+
+#include "mlp.h"
+#include "runtime.h"
+
+namespace hom {
+
+typedef __bf16 bf16x8_t __attribute__((ext_vector_type(8)));
+typedef float floatx4_t __attribute__((ext_vector_type(4)));
+
+constexpr int MROWS = 64;     // rows per forward work-group
+constexpr int ASTRIDE = 264;  // LDS row stride of the activation tile (floats)
+
+__device__ __forceinline__ float gelu_f(float z) { return 0.5f * z * (1.0f + erff(z * 0.70710678118654752f)); }
+__device__ __forceinline__ float gelu_prime_f(float z) {
+  return 0.5f * (1.0f + erff(z * 0.70710678118654752f)) + z * expf(-0.5f * z * z) * 0.39894228040143268f;
+}
+
+struct FwdArgs {
+  const float* x;
+  long long n;
+  int n_in, n_out;
+  const float* xmean;
+  const float* xinv;
+  const float* ymean;
+  const float* ystd;
+  const float* skip;  // G [16][MLP_GATES][32], c [16]
+  int g0, g1, g2;     // gate input indices
+  const __bf16* whi[MLP_LAYERS];
+  const __bf16* wlo[MLP_LAYERS];
+  const float* bias[MLP_LAYERS];
+  float* y;      // [n][n_out] outputs in physical units (optional)
+  float* yhat;   // [n][16] normalized outputs (optional)
+  float* xs;     // [n][32] normalized inputs (optional, training)
+  float* zs[MLP_LAYERS - 1];  // [n][256] pre-activations (optional)
+  float* as[MLP_LAYERS - 1];  // [n][256] activations (optional)
+};
+
+template <int PRECISE>
+__global__ void __launch_bounds__(256) k_mlp_fwd(FwdArgs a) {
+  __shared__ float act[MROWS * ASTRIDE];
+  __shared__ float xin[MROWS * (MLP_IN + 1)];  // normalized inputs, kept for the linear skip
+  const int tid = threadIdx.x;
+  const int wave = tid >> 6;
+  const int lane = tid & 63;
+  const long long row0 = (long long)blockIdx.x * MROWS;
+  for (int i = tid; i < MROWS * MLP_IN; i += 256) {
+    const int r = i / MLP_IN, k = i % MLP_IN;
+    const long long gr = row0 + r;
+    float v = 0.0f;
+    if (gr < a.n && k < a.n_in) v = (a.x[gr * a.n_in + k] - a.xmean[k]) * a.xinv[k];
+    act[r * ASTRIDE + k] = v;
+    xin[r * (MLP_IN + 1) + k] = v;
+    if (a.xs && gr < a.n) a.xs[gr * MLP_IN + k] = v;
+  }
+  __syncthreads();
+  const int lrow = lane & 15;
+  const int kq = (lane >> 4) * 8;
+#pragma unroll 1
+  for (int l = 0; l < MLP_LAYERS - 1; ++l) {
+    const int K = l == 0 ? MLP_IN : MLP_W;
+    const __bf16* whi = a.whi[l];
+    const __bf16* wlo = a.wlo[l];
+    floatx4_t acc[4][4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+      for (int j = 0; j < 4; ++j) acc[i][j] = floatx4_t{0.f, 0.f, 0.f, 0.f};
+    for (int k0 = 0; k0 < K; k0 += 32) {
+      bf16x8_t ahi[4], alo[4];
+#pragma unroll
+      for (int rb = 0; rb < 4; ++rb) {
+        const float* src = act + (rb * 16 + lrow) * ASTRIDE + k0 + kq;
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+          const float v = src[e];
+          const __bf16 h = (__bf16)v;
+          ahi[rb][e] = h;
+          alo[rb][e] = (__bf16)(v - (float)h);
+        }
+      }
+#pragma unroll
+      for (int cb = 0; cb < 4; ++cb) {
+        const int nn = wave * 64 + cb * 16 + lrow;
+        const bf16x8_t bh = *reinterpret_cast<const bf16x8_t*>(whi + (long long)nn * K + k0 + kq);
+        bf16x8_t bl;
+        if (PRECISE) bl = *reinterpret_cast<const bf16x8_t*>(wlo + (long long)nn * K + k0 + kq);
+#pragma unroll
+        for (int rb = 0; rb < 4; ++rb) {
+          acc[rb][cb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ahi[rb], bh, acc[rb][cb], 0, 0, 0);
+          acc[rb][cb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(alo[rb], bh, acc[rb][cb], 0, 0, 0);
+          if (PRECISE) acc[rb][cb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ahi[rb], bl, acc[rb][cb], 0, 0, 0);
+        }
+      }
+    }
+    __syncthreads();  // all waves done reading this layer's input
+    const float* bias = a.bias[l];
+#pragma unroll
+    for (int rb = 0; rb < 4; ++rb)
+#pragma unroll
+      for (int cb = 0; cb < 4; ++cb)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          const int m = rb * 16 + (lane >> 4) * 4 + i;
+          const int nn = wave * 64 + cb * 16 + lrow;
+          const float z = acc[rb][cb][i] + bias[nn];
+          const float g = gelu_f(z);
+          act[m * ASTRIDE + nn] = g;
+          const long long gr = row0 + m;
+          if (a.zs[l] && gr < a.n) {
+            a.zs[l][gr * MLP_W + nn] = z;
+            a.as[l][gr * MLP_W + nn] = g;
+          }
+        }
+    __syncthreads();
+  }
+  // output layer: each wave 16 rows x 16 outputs
+  {
+    const int l = MLP_LAYERS - 1;
+    const __bf16* whi = a.whi[l];
+    const __bf16* wlo = a.wlo[l];
+    floatx4_t acc = floatx4_t{0.f, 0.f, 0.f, 0.f};
+    for (int k0 = 0; k0 < MLP_W; k0 += 32) {
+      bf16x8_t ahi, alo;
+      const float* src = act + (wave * 16 + lrow) * ASTRIDE + k0 + kq;
+#pragma unroll
+      for (int e = 0; e < 8; ++e) {
+        const float v = src[e];
+        const __bf16 h = (__bf16)v;
+        ahi[e] = h;
+        alo[e] = (__bf16)(v - (float)h);
+      }
+      const bf16x8_t bh = *reinterpret_cast<const bf16x8_t*>(whi + (long long)lrow * MLP_W + k0 + kq);
+      acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ahi, bh, acc, 0, 0, 0);
+      acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(alo, bh, acc, 0, 0, 0);
+      if (PRECISE) {
+        const bf16x8_t bl = *reinterpret_cast<const bf16x8_t*>(wlo + (long long)lrow * MLP_W + k0 + kq);
+        acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ahi, bl, acc, 0, 0, 0);
+      }
+    }
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int m = wave * 16 + (lane >> 4) * 4 + i;
+      const long long gr = row0 + m;
+      if (gr >= a.n) continue;
+      const float z = acc[i] + a.bias[l][lrow];
+      if (a.yhat) a.yhat[gr * MLP_OUT + lrow] = z;
+      if (a.y && lrow < a.n_out) {
+        const float* xr = xin + m * (MLP_IN + 1);
+        const float va = xr[a.g0], vb = xr[a.g1], vc = xr[a.g2];
+        const float s[MLP_GATES] = {1.f, va, va * va, va * va * va, vb, vb * vb, vb * vb * vb,
+                                    vc, vc * vc, vc * vc * vc};
+        float sk = a.skip[MLP_OUT * MLP_GATES * MLP_IN + lrow];
+        const float* G = a.skip + (size_t)lrow * MLP_GATES * MLP_IN;
+#pragma unroll
+        for (int gi = 0; gi < MLP_GATES; ++gi) {
+          float t = 0.f;
+          for (int k = 0; k < MLP_IN; ++k) t += G[gi * MLP_IN + k] * xr[k];
+          sk += s[gi] * t;
+        }
+        a.y[gr * a.n_out + lrow] = z * a.ystd[lrow] + a.ymean[lrow] + sk;
+      }
+    }
+  }
+}
+
+// C[M][N] = op(A) op(B) (+ beta C), row-major, FP32. op(A) = A (M x K, lda)
+// or A^T (A stored K x M); op(B) = B (K x N, ldb) or B^T (B stored N x K).
+template <bool TA, bool TB>
+__global__ void __launch_bounds__(256) k_gemm(int M, int N, int K, const float* __restrict__ A, int lda,
+                                              const float* __restrict__ B, int ldb, float* __restrict__ C, int ldc,
+                                              float beta) {
+  __shared__ float As[16][65];
+  __shared__ float Bs[16][65];
+  const int tid = threadIdx.x;
+  const int tm = tid / 16, tn = tid % 16;
+  const int m0 = blockIdx.y * 64, n0 = blockIdx.x * 64;
+  float acc[4][4] = {};
+  for (int k0 = 0; k0 < K; k0 += 16) {
+    for (int i = tid; i < 16 * 64; i += 256) {
+      const int kk = i / 64, mm = i % 64;
+      const int gm = m0 + mm, gk = k0 + kk;
+      float va = 0.f;
+      if (gm < M && gk < K) va = TA ? A[(long long)gk * lda + gm] : A[(long long)gm * lda + gk];
+      As[kk][mm] = va;
+      const int gn = n0 + mm;
+      float vb = 0.f;
+      if (gn < N && gk < K) vb = TB ? B[(long long)gn * ldb + gk] : B[(long long)gk * ldb + gn];
+      Bs[kk][mm] = vb;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int kk = 0; kk < 16; ++kk) {
+      float av[4], bv[4];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        av[i] = As[kk][tm * 4 + i];
+        bv[i] = Bs[kk][tn * 4 + i];
+      }
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) acc[i][j] += av[i] * bv[j];
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int gm = m0 + tm * 4 + i, gn = n0 + tn * 4 + j;
+      if (gm < M && gn < N) {
+        float* c = C + (long long)gm * ldc + gn;
+        *c = beta == 0.f ? acc[i][j] : beta * *c + acc[i][j];
+      }
+    }
+}
+
+// column sums: out[j] = sum_r in[r][j], one thread per column (fixed order)
+__global__ void k_colsum(const float* in, long long rows, int cols, float* out) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= cols) return;
+  double s = 0.0;
+  for (long long r = 0; r < rows; ++r) s += in[r * cols + j];
+  out[j] = (float)s;
+}
+
+// dz = da * gelu'(z)
+__global__ void k_gelu_back(const float* da, const float* z, float* dz, long long count) {
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < count) dz[i] = da[i] * gelu_prime_f(z[i]);
+}
+
+// weighted MSE on normalized outputs: dyhat = 2 w (yhat - t) / B, loss partials
+__global__ void k_loss(const float* yhat, const float* t, const float* w, long long B, int n_out, float* dy,
+                       double* part) {
+  __shared__ double red[256];
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  double l = 0.0;
+  if (i < B * MLP_OUT) {
+    const int j = (int)(i % MLP_OUT);
+    float g = 0.f;
+    if (j < n_out) {
+      const float d = yhat[i] - t[i];
+      g = 2.0f * w[j] * d / (float)B;
+      l = (double)w[j] * (double)d * (double)d / (double)B;
+    }
+    dy[i] = g;
+  }
+  red[threadIdx.x] = l;
+  __syncthreads();
+  for (int s = 128; s > 0; s >>= 1) {
+    if (threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) part[blockIdx.x] = red[0];
+}
+
+__global__ void k_adam(float* w, const float* g, float* m, float* v, long long count, float lr, float b1, float b2,
+                       float c1, float c2, float eps) {
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= count) return;
+  const float gi = g[i];
+  const float mi = b1 * m[i] + (1.f - b1) * gi;
+  const float vi = b2 * v[i] + (1.f - b2) * gi * gi;
+  m[i] = mi;
+  v[i] = vi;
+  w[i] -= lr * (mi / c1) / (sqrtf(vi / c2) + eps);
+}
+
+// master FP32 weights -> bf16 hi / lo copies and the effective FP32 weights
+// the forward pass uses (hi, or hi + lo in precise mode)
+__global__ void k_split(const float* w, __bf16* hi, __bf16* lo, float* eff_bf, float* eff_pr, long long count) {
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= count) return;
+  const float v = w[i];
+  const __bf16 h = (__bf16)v;
+  const __bf16 l = (__bf16)(v - (float)h);
+  hi[i] = h;
+  lo[i] = l;
+  eff_bf[i] = (float)h;
+  eff_pr[i] = (float)h + (float)l;
+}
+
+__global__ void k_gather(const float* src, int cols, const int* idx, long long count, float* dst) {
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= count * cols) return;
+  const long long r = i / cols;
+  const int c = (int)(i % cols);
+  dst[i] = src[(long long)idx[r] * cols + c];
+}
+
+// ensemble mean, spread of the stress outputs, acceptance
+__global__ void k_accept(const float* ya, const float* yb, long long n, int n_out, float* y, float* spread,
+                         uint8_t* accept, float thr, float floor_scale) {
+  const long long r = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= n) return;
+  float d2 = 0.f, m2 = 0.f;
+  for (int j = 0; j < n_out; ++j) {
+    const float p = ya[r * n_out + j], q = yb[r * n_out + j];
+    const float mean = 0.5f * (p + q);
+    y[r * n_out + j] = mean;
+    if (j < 6) {
+      d2 += (p - q) * (p - q);
+      m2 += mean * mean;
+    }
+  }
+  const float s = sqrtf(d2) / fmaxf(sqrtf(m2), floor_scale);
+  spread[r] = s;
+  accept[r] = s <= thr ? 1 : 0;
+}
+
+// ---------------------------------------------------------------------------
+// host side
+// ---------------------------------------------------------------------------
+static int lay_k(int l) { return l == 0 ? MLP_IN : MLP_W; }
+static int lay_n(int l) { return l == MLP_LAYERS - 1 ? MLP_OUT : MLP_W; }
+
+Mlp::Mlp(int n_in_, int n_out_, uint64_t seed) : n_in(n_in_), n_out(n_out_) {
+  if (n_in < 1 || n_in > MLP_IN || n_out < 1 || n_out > MLP_OUT) fail(HOM_E_ARG, "network size out of range");
+  size_t off = 0;
+  for (int l = 0; l < MLP_LAYERS; ++l) {
+    woff[l] = off;
+    off += (size_t)lay_n(l) * lay_k(l);
+    boff[l] = off;
+    off += lay_n(l);
+  }
+  npad = off;
+  auto alloc = [&](void** p, size_t b) {
+    HIPCHK(hipMalloc(p, b));
+    HIPCHK(hipMemset(*p, 0, b));
+    allocs.push_back(*p);
+  };
+  alloc((void**)&w, npad * 4);
+  alloc((void**)&g, npad * 4);
+  alloc((void**)&m, npad * 4);
+  alloc((void**)&v, npad * 4);
+  alloc((void**)&eff_bf, npad * 4);
+  alloc((void**)&eff_pr, npad * 4);
+  alloc((void**)&hi, npad * 2);
+  alloc((void**)&lo, npad * 2);
+  alloc((void**)&scal, 5 * MLP_OUT * 4 + 2 * MLP_IN * 4);
+  alloc((void**)&skip, (MLP_OUT * MLP_GATES * MLP_IN + MLP_OUT) * 4);
+  // He initialization (normal, std sqrt(2 / fan_in)), seeded; biases zero
+  std::vector<float> hw(npad, 0.f);
+  std::mt19937_64 gen(seed);
+  for (int l = 0; l < MLP_LAYERS; ++l) {
+    const int K = lay_k(l), N = lay_n(l);
+    const int kin = l == 0 ? n_in : K;
+    const int nout = l == MLP_LAYERS - 1 ? n_out : N;
+    std::normal_distribution<double> nd(0.0, std::sqrt((l == MLP_LAYERS - 1 ? 1.0 : 2.0) / kin));
+    for (int i = 0; i < nout; ++i)
+      for (int k = 0; k < kin; ++k) hw[woff[l] + (size_t)i * K + k] = (float)nd(gen);
+  }
+  HIPCHK(hipMemcpy(w, hw.data(), npad * 4, hipMemcpyHostToDevice));
+  std::vector<float> s(5 * MLP_OUT + 2 * MLP_IN, 0.f);
+  for (int j = 0; j < MLP_IN; ++j) s[MLP_IN + j] = 1.f;            // xinv
+  for (int j = 0; j < MLP_OUT; ++j) s[2 * MLP_IN + MLP_OUT + j] = 1.f;  // ystd
+  for (int j = 0; j < MLP_OUT; ++j) s[2 * MLP_IN + 2 * MLP_OUT + j] = 1.f;  // loss weights
+  HIPCHK(hipMemcpy(scal, s.data(), s.size() * 4, hipMemcpyHostToDevice));
+  hx_mean.assign(n_in, 0.f);
+  hx_inv.assign(n_in, 1.f);
+  hy_mean.assign(n_out, 0.f);
+  hy_std.assign(n_out, 1.f);
+  refresh(nullptr);
+  HIPCHK(hipDeviceSynchronize());
+}
+
+Mlp::~Mlp() {
+  free_work();
+  for (void* p : allocs) (void)hipFree(p);
+}
+
+void Mlp::free_work() {
+  for (void* p : work) (void)hipFree(p);
+  work.clear();
+  work_rows = 0;
+}
+
+void Mlp::refresh(hipStream_t s) {
+  const long long n = (long long)npad;
+  hipLaunchKernelGGL(k_split, dim3((n + 255) / 256), dim3(256), 0, s, w, hi, lo, eff_bf, eff_pr, n);
+}
+
+void Mlp::set_scaling(const float* xmean, const float* xstd, const float* ymean, const float* ystd,
+                      const float* lw) {
+  std::vector<float> s(5 * MLP_OUT + 2 * MLP_IN, 0.f);
+  for (int j = 0; j < MLP_IN; ++j) {
+    s[j] = j < n_in ? xmean[j] : 0.f;
+    s[MLP_IN + j] = j < n_in ? 1.f / xstd[j] : 1.f;
+    if (j < n_in && !(xstd[j] > 0.f)) fail(HOM_E_ARG, "input scale must be positive");
+  }
+  for (int j = 0; j < MLP_OUT; ++j) {
+    s[2 * MLP_IN + j] = j < n_out ? ymean[j] : 0.f;
+    s[2 * MLP_IN + MLP_OUT + j] = j < n_out ? ystd[j] : 1.f;
+    s[2 * MLP_IN + 2 * MLP_OUT + j] = j < n_out ? (lw ? lw[j] : 1.f) : 0.f;
+    if (j < n_out && !(ystd[j] > 0.f)) fail(HOM_E_ARG, "output scale must be positive");
+  }
+  HIPCHK(hipMemcpy(scal, s.data(), s.size() * 4, hipMemcpyHostToDevice));
+  for (int j = 0; j < n_in; ++j) {
+    hx_mean[j] = xmean[j];
+    hx_inv[j] = 1.f / xstd[j];
+  }
+  for (int j = 0; j < n_out; ++j) {
+    hy_mean[j] = ymean[j];
+    hy_std[j] = ystd[j];
+  }
+}
+
+void Mlp::normalized_targets(const float* X, const float* T, long long n, float* out) const {
+  std::vector<double> xn(n_in);
+  for (long long r = 0; r < n; ++r) {
+    if (!hskip.empty()) normalize_row(X + r * n_in, xn.data());
+    for (int j = 0; j < MLP_OUT; ++j) {
+      float v = 0.f;
+      if (j < n_out) {
+        const double sk = hskip.empty() ? 0.0 : skip_value(xn.data(), j);
+        v = (float)((T[r * n_out + j] - sk - hy_mean[j]) / hy_std[j]);
+      }
+      out[r * MLP_OUT + j] = v;
+    }
+  }
+}
+
+void Mlp::set_skip(const int* gates, const float* G, const float* c) {
+  for (int i = 0; i < 3; ++i) {
+    if (gates[i] < 0 || gates[i] >= n_in) fail(HOM_E_ARG, "gate index out of range");
+    gate[i] = gates[i];
+  }
+  std::vector<float> f(MLP_OUT * MLP_GATES * MLP_IN + MLP_OUT, 0.f);
+  hskip.assign((size_t)n_out * MLP_GATES * n_in + n_out, 0.0);
+  for (int j = 0; j < n_out; ++j) {
+    for (int g = 0; g < MLP_GATES; ++g)
+      for (int k = 0; k < n_in; ++k) {
+        const float v = G[((size_t)j * MLP_GATES + g) * n_in + k];
+        f[((size_t)j * MLP_GATES + g) * MLP_IN + k] = v;
+        hskip[((size_t)j * MLP_GATES + g) * n_in + k] = v;
+      }
+    f[MLP_OUT * MLP_GATES * MLP_IN + j] = c[j];
+    hskip[(size_t)n_out * MLP_GATES * n_in + j] = c[j];
+  }
+  HIPCHK(hipMemcpy(skip, f.data(), f.size() * 4, hipMemcpyHostToDevice));
+}
+
+void Mlp::normalize_row(const float* x, double* xn) const {
+  for (int k = 0; k < n_in; ++k) xn[k] = ((double)x[k] - hx_mean[k]) * hx_inv[k];
+}
+
+double Mlp::skip_value(const double* xn, int j) const {
+  if (hskip.empty()) return 0.0;
+  const double va = xn[gate[0]], vb = xn[gate[1]], vc = xn[gate[2]];
+  const double s[MLP_GATES] = {1, va, va * va, va * va * va, vb, vb * vb, vb * vb * vb, vc, vc * vc, vc * vc * vc};
+  double y = hskip[(size_t)n_out * MLP_GATES * n_in + j];
+  for (int g = 0; g < MLP_GATES; ++g) {
+    double t = 0.0;
+    for (int k = 0; k < n_in; ++k) t += hskip[((size_t)j * MLP_GATES + g) * n_in + k] * xn[k];
+    y += s[g] * t;
+  }
+  return y;
+}
+
+// Host-side least squares in FP64: normal equations of the design
+// [1, xhat * s_g(xhat)] with a tiny ridge, solved by Cholesky.
+void Mlp::fit_skip(const float* X, const float* Y, long long n, const int* gates, const float* lw) {
+  if (n < 2) fail(HOM_E_ARG, "need rows to fit");
+  for (int i = 0; i < 3; ++i)
+    if (gates[i] < 0 || gates[i] >= n_in) fail(HOM_E_ARG, "gate index out of range");
+  // input scaling from the rows
+  std::vector<double> xm(n_in, 0.0), xv(n_in, 0.0);
+  for (long long r = 0; r < n; ++r)
+    for (int k = 0; k < n_in; ++k) xm[k] += X[r * n_in + k];
+  for (int k = 0; k < n_in; ++k) xm[k] /= (double)n;
+  for (long long r = 0; r < n; ++r)
+    for (int k = 0; k < n_in; ++k) {
+      const double d = X[r * n_in + k] - xm[k];
+      xv[k] += d * d;
+    }
+  std::vector<float> xmf(n_in), xsf(n_in);
+  for (int k = 0; k < n_in; ++k) {
+    const double sd = std::sqrt(xv[k] / (double)n);
+    xmf[k] = (float)xm[k];
+    xsf[k] = sd > 1e-12 ? (float)sd : 1.f;
+  }
+  hx_mean.assign(xmf.begin(), xmf.end());
+  hx_inv.resize(n_in);
+  for (int k = 0; k < n_in; ++k) hx_inv[k] = 1.f / xsf[k];
+  const int P = 1 + MLP_GATES * n_in;
+  std::vector<double> AtA((size_t)P * P, 0.0), AtY((size_t)P * n_out, 0.0), phi(P), xn(n_in);
+  for (long long r = 0; r < n; ++r) {
+    normalize_row(X + r * n_in, xn.data());
+    const double va = xn[gates[0]], vb = xn[gates[1]], vc = xn[gates[2]];
+    const double s[MLP_GATES] = {1, va, va * va, va * va * va, vb, vb * vb, vb * vb * vb, vc, vc * vc, vc * vc * vc};
+    phi[0] = 1.0;
+    for (int g = 0; g < MLP_GATES; ++g)
+      for (int k = 0; k < n_in; ++k) phi[1 + g * n_in + k] = s[g] * xn[k];
+    for (int a = 0; a < P; ++a) {
+      const double pa = phi[a];
+      double* row = &AtA[(size_t)a * P];
+      for (int b = 0; b <= a; ++b) row[b] += pa * phi[b];
+      for (int j = 0; j < n_out; ++j) AtY[(size_t)a * n_out + j] += pa * Y[r * n_out + j];
+    }
+  }
+  double tr = 0.0;
+  for (int a = 0; a < P; ++a) tr += AtA[(size_t)a * P + a];
+  for (int a = 0; a < P; ++a) AtA[(size_t)a * P + a] += 1e-12 * tr / P;
+  // Cholesky (lower, in place)
+  for (int j = 0; j < P; ++j) {
+    double d = AtA[(size_t)j * P + j];
+    for (int k = 0; k < j; ++k) d -= AtA[(size_t)j * P + k] * AtA[(size_t)j * P + k];
+    if (!(d > 0.0)) fail(HOM_E_NAN, "skip fit: normal equations not positive definite");
+    d = std::sqrt(d);
+    AtA[(size_t)j * P + j] = d;
+    for (int i = j + 1; i < P; ++i) {
+      double v = AtA[(size_t)i * P + j];
+      for (int k = 0; k < j; ++k) v -= AtA[(size_t)i * P + k] * AtA[(size_t)j * P + k];
+      AtA[(size_t)i * P + j] = v / d;
+    }
+  }
+  std::vector<float> G((size_t)n_out * MLP_GATES * n_in), c(n_out);
+  std::vector<double> z(P);
+  for (int j = 0; j < n_out; ++j) {
+    for (int i = 0; i < P; ++i) {
+      double v = AtY[(size_t)i * n_out + j];
+      for (int k = 0; k < i; ++k) v -= AtA[(size_t)i * P + k] * z[k];
+      z[i] = v / AtA[(size_t)i * P + i];
+    }
+    for (int i = P - 1; i >= 0; --i) {
+      double v = z[i];
+      for (int k = i + 1; k < P; ++k) v -= AtA[(size_t)k * P + i] * z[k];
+      z[i] = v / AtA[(size_t)i * P + i];
+    }
+    c[j] = (float)z[0];
+    for (int g = 0; g < MLP_GATES; ++g)
+      for (int k = 0; k < n_in; ++k) G[((size_t)j * MLP_GATES + g) * n_in + k] = (float)z[1 + g * n_in + k];
+  }
+  set_skip(gates, G.data(), c.data());
+  // residual scaling
+  std::vector<double> rm(n_out, 0.0), rv(n_out, 0.0);
+  std::vector<double> res((size_t)n * n_out);
+  for (long long r = 0; r < n; ++r) {
+    normalize_row(X + r * n_in, xn.data());
+    for (int j = 0; j < n_out; ++j) {
+      const double v = Y[r * n_out + j] - skip_value(xn.data(), j);
+      res[r * n_out + j] = v;
+      rm[j] += v;
+    }
+  }
+  for (int j = 0; j < n_out; ++j) rm[j] /= (double)n;
+  for (long long r = 0; r < n; ++r)
+    for (int j = 0; j < n_out; ++j) rv[j] += (res[r * n_out + j] - rm[j]) * (res[r * n_out + j] - rm[j]);
+  std::vector<float> rmf(n_out), rsf(n_out);
+  for (int j = 0; j < n_out; ++j) {
+    const double sd = std::sqrt(rv[j] / (double)n);
+    rmf[j] = (float)rm[j];
+    rsf[j] = sd > 1e-12 ? (float)sd : 1.f;
+  }
+  set_scaling(xmf.data(), xsf.data(), rmf.data(), rsf.data(), lw);
+}
+
+void Mlp::ensure_work(long long rows) {
+  if (rows <= work_rows) return;
+  free_work();
+  auto alloc = [&](float** p, size_t count) {
+    HIPCHK(hipMalloc((void**)p, count * 4));
+    work.push_back(*p);
+  };
+  alloc(&xs, rows * MLP_IN);
+  for (int l = 0; l < MLP_LAYERS - 1; ++l) {
+    alloc(&zs[l], rows * MLP_W);
+    alloc(&as[l], rows * MLP_W);
+  }
+  alloc(&yhat, rows * MLP_OUT);
+  alloc(&dy, rows * MLP_OUT);
+  alloc(&da, rows * MLP_W);
+  alloc(&dz, rows * MLP_W);
+  alloc(&xb, rows * MLP_IN);
+  alloc(&tb, rows * MLP_OUT);
+  alloc(&lpart, (rows * MLP_OUT + 255) / 256 * 2);
+  work_rows = rows;
+}
+
+void Mlp::forward(const float* x, float* y, long long n, bool precise, bool save, hipStream_t s) {
+  FwdArgs a;
+  std::memset(&a, 0, sizeof(a));
+  a.x = x;
+  a.n = n;
+  a.n_in = n_in;
+  a.n_out = n_out;
+  a.xmean = scal;
+  a.xinv = scal + MLP_IN;
+  a.ymean = scal + 2 * MLP_IN;
+  a.ystd = scal + 2 * MLP_IN + MLP_OUT;
+  a.skip = skip;
+  a.g0 = gate[0];
+  a.g1 = gate[1];
+  a.g2 = gate[2];
+  for (int l = 0; l < MLP_LAYERS; ++l) {
+    a.whi[l] = hi + woff[l];
+    a.wlo[l] = lo + woff[l];
+    a.bias[l] = w + boff[l];
+  }
+  a.y = y;
+  if (save) {
+    a.yhat = yhat;
+    a.xs = xs;
+    for (int l = 0; l < MLP_LAYERS - 1; ++l) {
+      a.zs[l] = zs[l];
+      a.as[l] = as[l];
+    }
+  }
+  const unsigned blocks = (unsigned)((n + MROWS - 1) / MROWS);
+  if (precise)
+    hipLaunchKernelGGL(k_mlp_fwd<1>, dim3(blocks), dim3(256), 0, s, a);
+  else
+    hipLaunchKernelGGL(k_mlp_fwd<0>, dim3(blocks), dim3(256), 0, s, a);
+}
+
+static void gemm(bool ta, bool tb, int M, int N, int K, const float* A, int lda, const float* B, int ldb, float* C,
+                 int ldc, hipStream_t s) {
+  dim3 grid((N + 63) / 64, (M + 63) / 64);
+  if (!ta && !tb) hipLaunchKernelGGL((k_gemm<false, false>), grid, dim3(256), 0, s, M, N, K, A, lda, B, ldb, C, ldc, 0.f);
+  if (ta && !tb) hipLaunchKernelGGL((k_gemm<true, false>), grid, dim3(256), 0, s, M, N, K, A, lda, B, ldb, C, ldc, 0.f);
+  if (!ta && tb) hipLaunchKernelGGL((k_gemm<false, true>), grid, dim3(256), 0, s, M, N, K, A, lda, B, ldb, C, ldc, 0.f);
+  if (ta && tb) hipLaunchKernelGGL((k_gemm<true, true>), grid, dim3(256), 0, s, M, N, K, A, lda, B, ldb, C, ldc, 0.f);
+}
+
+// loss and gradient of the rows (x, t normalized targets already in xb / tb
+// layout: x raw [B][n_in], t normalized [B][16])
+double Mlp::loss_grad(const float* x, const float* tnorm, long long B, bool precise, hipStream_t s) {
+  ensure_work(B);
+  forward(x, nullptr, B, precise, true, s);
+  const long long cnt = B * MLP_OUT;
+  const int lb = (int)((cnt + 255) / 256);
+  hipLaunchKernelGGL(k_loss, dim3(lb), dim3(256), 0, s, yhat, tnorm, scal + 2 * MLP_IN + 2 * MLP_OUT, B, n_out, dy,
+                     reinterpret_cast<double*>(lpart));
+  const float* eff = precise ? eff_pr : eff_bf;
+  const float* dcur = dy;
+  int ncur = MLP_OUT;
+  for (int l = MLP_LAYERS - 1; l >= 0; --l) {
+    const int K = lay_k(l), N = lay_n(l);
+    const float* ain = l == 0 ? xs : as[l - 1];
+    // dW[N][K] = dZ^T (B x N) . A (B x K)
+    gemm(true, false, N, K, (int)B, dcur, ncur, ain, K, g + woff[l], K, s);
+    hipLaunchKernelGGL(k_colsum, dim3((N + 255) / 256), dim3(256), 0, s, dcur, B, N, g + boff[l]);
+    if (l > 0) {
+      // dA (B x K) = dZ (B x N) . W (N x K), then dZ_prev = dA * gelu'(Z_prev)
+      gemm(false, false, (int)B, K, N, dcur, ncur, eff + woff[l], K, da, K, s);
+      const long long c = B * K;
+      hipLaunchKernelGGL(k_gelu_back, dim3((c + 255) / 256), dim3(256), 0, s, da, zs[l - 1], dz, c);
+      // dz is read by the next layer's dW / dA products before its own
+      // gelu' step overwrites it (stream order), so one pair of buffers suffices
+      dcur = dz;
+      ncur = K;
+    }
+  }
+  std::vector<double> lp(lb);
+  HIPCHK(hipMemcpyAsync(lp.data(), lpart, lb * sizeof(double), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  double L = 0.0;
+  for (double v : lp) L += v;
+  return L;
+}
+
+void Mlp::get_params(float* out) const {
+  std::vector<float> hw(npad);
+  HIPCHK(hipMemcpy(hw.data(), w, npad * 4, hipMemcpyDeviceToHost));
+  size_t o = 0;
+  for (int l = 0; l < MLP_LAYERS; ++l) {
+    const int K = lay_k(l);
+    const int kin = l == 0 ? n_in : K;
+    const int nout = l == MLP_LAYERS - 1 ? n_out : lay_n(l);
+    for (int i = 0; i < nout; ++i)
+      for (int k = 0; k < kin; ++k) out[o++] = hw[woff[l] + (size_t)i * K + k];
+    for (int i = 0; i < nout; ++i) out[o++] = hw[boff[l] + i];
+  }
+}
+
+void Mlp::get_grads(float* out) const {
+  std::vector<float> hg(npad);
+  HIPCHK(hipMemcpy(hg.data(), g, npad * 4, hipMemcpyDeviceToHost));
+  size_t o = 0;
+  for (int l = 0; l < MLP_LAYERS; ++l) {
+    const int K = lay_k(l);
+    const int kin = l == 0 ? n_in : K;
+    const int nout = l == MLP_LAYERS - 1 ? n_out : lay_n(l);
+    for (int i = 0; i < nout; ++i)
+      for (int k = 0; k < kin; ++k) out[o++] = hg[woff[l] + (size_t)i * K + k];
+    for (int i = 0; i < nout; ++i) out[o++] = hg[boff[l] + i];
+  }
+}
+
+void Mlp::set_params(const float* in) {
+  std::vector<float> hw(npad, 0.f);
+  size_t o = 0;
+  for (int l = 0; l < MLP_LAYERS; ++l) {
+    const int K = lay_k(l);
+    const int kin = l == 0 ? n_in : K;
+    const int nout = l == MLP_LAYERS - 1 ? n_out : lay_n(l);
+    for (int i = 0; i < nout; ++i)
+      for (int k = 0; k < kin; ++k) hw[woff[l] + (size_t)i * K + k] = in[o++];
+    for (int i = 0; i < nout; ++i) hw[boff[l] + i] = in[o++];
+  }
+  HIPCHK(hipMemcpy(w, hw.data(), npad * 4, hipMemcpyHostToDevice));
+  refresh(nullptr);
+  HIPCHK(hipDeviceSynchronize());
+}
+
+size_t Mlp::param_count() const {
+  size_t c = 0;
+  for (int l = 0; l < MLP_LAYERS; ++l) {
+    const int kin = l == 0 ? n_in : lay_k(l);
+    const int nout = l == MLP_LAYERS - 1 ? n_out : lay_n(l);
+    c += (size_t)nout * kin + nout;
+  }
+  return c;
+}
+
+void Mlp::train(const float* X, const float* T, long long n, int epochs, int batch, double lr0, uint64_t seed,
+                float* loss_out) {
+  if (n < batch || batch < 1) fail(HOM_E_ARG, "need at least one full batch");
+  hipStream_t s = nullptr;
+  float *dX = nullptr, *dT = nullptr;
+  int* didx = nullptr;
+  HIPCHK(hipMalloc((void**)&dX, n * n_in * 4));
+  HIPCHK(hipMalloc((void**)&dT, n * MLP_OUT * 4));
+  HIPCHK(hipMalloc((void**)&didx, n * 4));
+  struct Guard {
+    std::vector<void*> p;
+    ~Guard() {
+      for (void* q : p) (void)hipFree(q);
+    }
+  } guard{{dX, dT, didx}};
+  std::vector<float> tn((size_t)n * MLP_OUT);
+  normalized_targets(X, T, n, tn.data());
+  HIPCHK(hipMemcpy(dX, X, n * n_in * 4, hipMemcpyHostToDevice));
+  HIPCHK(hipMemcpy(dT, tn.data(), tn.size() * 4, hipMemcpyHostToDevice));
+  ensure_work(batch);
+  std::mt19937_64 gen(seed);
+  std::vector<int> perm(n);
+  const long long steps_per_epoch = n / batch;
+  const long long total = steps_per_epoch * epochs;
+  long long step = 0;
+  const float b1 = 0.9f, b2 = 0.999f;
+  for (int e = 0; e < epochs; ++e) {
+    for (long long i = 0; i < n; ++i) perm[i] = (int)i;
+    std::shuffle(perm.begin(), perm.end(), gen);
+    HIPCHK(hipMemcpy(didx, perm.data(), n * 4, hipMemcpyHostToDevice));
+    double el = 0.0;
+    for (long long sidx = 0; sidx < steps_per_epoch; ++sidx) {
+      const int* bi = didx + sidx * batch;
+      const long long cx = (long long)batch * n_in, ct = (long long)batch * MLP_OUT;
+      hipLaunchKernelGGL(k_gather, dim3((cx + 255) / 256), dim3(256), 0, s, dX, n_in, bi, (long long)batch, xb);
+      hipLaunchKernelGGL(k_gather, dim3((ct + 255) / 256), dim3(256), 0, s, dT, MLP_OUT, bi, (long long)batch, tb);
+      el += loss_grad(xb, tb, batch, false, s);
+      ++step;
+      // cosine decay to 1 % with a short warm-up
+      const double prog = (double)step / (double)total;
+      double lr = lr0 * (0.01 + 0.99 * 0.5 * (1.0 + std::cos(3.14159265358979 * prog)));
+      if (step < 200) lr *= (double)step / 200.0;
+      const float c1 = 1.f - std::pow(b1, (float)step), c2 = 1.f - std::pow(b2, (float)step);
+      const long long np = (long long)npad;
+      hipLaunchKernelGGL(k_adam, dim3((np + 255) / 256), dim3(256), 0, s, w, g, m, v, np, (float)lr, b1, b2, c1, c2,
+                         1e-8f);
+      refresh(s);
+    }
+    if (loss_out) loss_out[e] = (float)(el / steps_per_epoch);
+  }
+  HIPCHK(hipDeviceSynchronize());
+}
+
+void surrogate_accept(const Mlp& a, const Mlp& b, const float* x, float* y, float* ya, float* yb, float* spread,
+                      uint8_t* accept, long long n, float thr, float floor_scale, hipStream_t s) {
+  const_cast<Mlp&>(a).forward(x, ya, n, false, false, s);
+  const_cast<Mlp&>(b).forward(x, yb, n, false, false, s);
+  hipLaunchKernelGGL(k_accept, dim3((n + 255) / 256), dim3(256), 0, s, ya, yb, n, a.n_out, y, spread, accept, thr,
+                     floor_scale);
+}
+
+}  // namespace hom

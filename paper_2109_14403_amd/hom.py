@@ -98,6 +98,11 @@ EXPORTS = (
     "hom_last_error", "hom_destroy",
     "hom_batch_setup", "hom_batch_solve_increment", "hom_batch_kernel_stats", "hom_batch_last_error",
     "hom_batch_destroy", "hom_apply_operator", "hom_eval_law",
+    "hom_mlp_create", "hom_mlp_param_count", "hom_mlp_set_scaling", "hom_mlp_set_skip", "hom_mlp_fit_skip",
+    "hom_mlp_get_params",
+    "hom_mlp_set_params",
+    "hom_mlp_train", "hom_mlp_forward", "hom_mlp_loss_grad", "hom_surrogate_infer", "hom_mlp_last_error",
+    "hom_mlp_destroy",
 )
 
 _lib = None
@@ -111,6 +116,12 @@ def library(path: str | None = None):
     p = path or LIB_PATH
     if not os.path.exists(p):
         raise HomError(HOM_E_DEVICE, f"{p} is not built; run __graft_entry__.build()")
+    # PyTorch (used for device buffers and streams) ships its own HIP runtime;
+    # it has to be loaded before this library's, or it finds no GPU later.
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
     lib = ct.CDLL(p)
     dp = ct.POINTER(ct.c_double)
     lib.hom_default_options.argtypes = [ct.POINTER(Options)]
@@ -143,6 +154,25 @@ def library(path: str | None = None):
                                        ct.c_int32, dp, dp]
     lib.hom_eval_law.argtypes = [ct.POINTER(Law), ct.c_int64, dp, dp, dp, ct.c_double, ct.c_double, ct.c_int32,
                                  dp, dp, dp, dp, dp, dp]
+    fp = ct.POINTER(ct.c_float)
+    lib.hom_mlp_create.argtypes = [ct.c_int32, ct.c_int32, ct.c_uint64, ct.POINTER(ct.c_void_p)]
+    lib.hom_mlp_param_count.argtypes = [ct.c_void_p]
+    lib.hom_mlp_param_count.restype = ct.c_size_t
+    lib.hom_mlp_set_scaling.argtypes = [ct.c_void_p, fp, fp, fp, fp, fp]
+    lib.hom_mlp_set_skip.argtypes = [ct.c_void_p, ct.POINTER(ct.c_int32), fp, fp]
+    lib.hom_mlp_fit_skip.argtypes = [ct.c_void_p, fp, fp, ct.c_int64, ct.POINTER(ct.c_int32), fp]
+    lib.hom_mlp_get_params.argtypes = [ct.c_void_p, fp, ct.c_size_t]
+    lib.hom_mlp_set_params.argtypes = [ct.c_void_p, fp, ct.c_size_t]
+    lib.hom_mlp_train.argtypes = [ct.c_void_p, fp, fp, ct.c_int64, ct.c_int32, ct.c_int32, ct.c_double, ct.c_uint64,
+                                  fp]
+    lib.hom_mlp_forward.argtypes = [ct.c_void_p, ct.c_void_p, ct.c_void_p, ct.c_int64, ct.c_int32, ct.c_void_p]
+    lib.hom_mlp_loss_grad.argtypes = [ct.c_void_p, fp, fp, ct.c_int64, ct.c_int32, ct.POINTER(ct.c_double), fp]
+    lib.hom_surrogate_infer.argtypes = [ct.c_void_p, ct.c_void_p, ct.c_void_p, ct.c_void_p, ct.c_void_p,
+                                        ct.c_void_p, ct.c_int64, ct.c_double, ct.c_double, ct.c_void_p]
+    lib.hom_mlp_last_error.argtypes = [ct.c_void_p]
+    lib.hom_mlp_last_error.restype = ct.c_char_p
+    lib.hom_mlp_destroy.argtypes = [ct.c_void_p]
+    lib.hom_mlp_destroy.restype = None
     _lib = lib
     return lib
 
@@ -380,3 +410,127 @@ def eval_law(law: dict, eps, eps_n=None, state=None, theta=293.15, dt=1.0, commi
                           _dptr(sig), _dptr(ab), _dptr(nd), _dptr(st_out), _dptr(diss), _dptr(coup))
     _check(rc, lambda: lib.hom_last_error(None).decode())
     return dict(sigma=sig, ab=ab, nd=nd, state=st_out, dissipation=diss, coupling=coup)
+
+
+def _fptr(a):
+    return a.ctypes.data_as(ct.POINTER(ct.c_float))
+
+
+def _f32(a):
+    return np.ascontiguousarray(a, dtype=np.float32)
+
+
+class MLP:
+    """The surrogate network (hom_mlp_*). Device arrays are torch tensors."""
+
+    def __init__(self, n_in, n_out, seed=0):
+        lib = library()
+        self._lib = lib
+        h = ct.c_void_p()
+        _check(lib.hom_mlp_create(n_in, n_out, seed, ct.byref(h)), lambda: lib.hom_mlp_last_error(None).decode())
+        self._h = h
+        self.n_in, self.n_out = n_in, n_out
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self._lib.hom_mlp_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def error(self):
+        return self._lib.hom_mlp_last_error(self._h).decode()
+
+    @property
+    def param_count(self):
+        return int(self._lib.hom_mlp_param_count(self._h))
+
+    def set_scaling(self, x_mean, x_std, y_mean, y_std, loss_weight=None):
+        lw = _f32(loss_weight) if loss_weight is not None else _f32(np.ones(self.n_out))
+        arrs = [_f32(a) for a in (x_mean, x_std, y_mean, y_std)]
+        _check(self._lib.hom_mlp_set_scaling(self._h, *[_fptr(a) for a in arrs], _fptr(lw)), self.error)
+
+    N_GATES = 10
+
+    def set_skip(self, gates, G, c):
+        """Gated polynomial skip: G [n_out, 10, n_in], c [n_out], gates: 3 input indices."""
+        g = (ct.c_int32 * 3)(*[int(v) for v in gates])
+        G = _f32(G).reshape(self.n_out, self.N_GATES, self.n_in)
+        c = _f32(c).reshape(self.n_out)
+        _check(self._lib.hom_mlp_set_skip(self._h, g, _fptr(G), _fptr(c)), self.error)
+
+    def fit_skip(self, x, y, gates, loss_weight=None):
+        x, y = _f32(x), _f32(y)
+        g = (ct.c_int32 * 3)(*[int(v) for v in gates])
+        lw = _fptr(_f32(loss_weight)) if loss_weight is not None else None
+        _check(self._lib.hom_mlp_fit_skip(self._h, _fptr(x), _fptr(y), x.shape[0], g, lw), self.error)
+
+    def get_params(self):
+        out = np.empty(self.param_count, dtype=np.float32)
+        _check(self._lib.hom_mlp_get_params(self._h, _fptr(out), out.size), self.error)
+        return out
+
+    def set_params(self, p):
+        p = _f32(p)
+        _check(self._lib.hom_mlp_set_params(self._h, _fptr(p), p.size), self.error)
+
+    def layers(self, flat=None):
+        """Split a flat parameter vector into [(W [out, in], b [out])]."""
+        flat = self.get_params() if flat is None else flat
+        sizes = [self.n_in, 256, 256, 256, 256, self.n_out]
+        out, o = [], 0
+        for i, j in zip(sizes[:-1], sizes[1:]):
+            W = flat[o:o + i * j].reshape(j, i)
+            o += i * j
+            b = flat[o:o + j]
+            o += j
+            out.append((W, b))
+        return out
+
+    def train(self, x, y, epochs, batch=256, lr=2e-3, seed=0):
+        x, y = _f32(x), _f32(y)
+        losses = np.empty(epochs, dtype=np.float32)
+        _check(self._lib.hom_mlp_train(self._h, _fptr(x), _fptr(y), x.shape[0], epochs, batch, lr, seed,
+                                       _fptr(losses)), self.error)
+        return losses
+
+    def forward_device(self, x_dev, y_dev, precise=False, stream=None):
+        n = x_dev.shape[0]
+        _check(self._lib.hom_mlp_forward(self._h, ct.c_void_p(x_dev.data_ptr()), ct.c_void_p(y_dev.data_ptr()), n,
+                                         int(precise), stream), self.error)
+
+    def forward(self, x, precise=False):
+        import torch
+        xd = torch.as_tensor(_f32(x), device="cuda")
+        yd = torch.empty((xd.shape[0], self.n_out), dtype=torch.float32, device="cuda")
+        self.forward_device(xd, yd, precise, ct.c_void_p(torch.cuda.current_stream().cuda_stream))
+        torch.cuda.synchronize()
+        return yd.cpu().numpy()
+
+    def loss_grad(self, x, y, precise=True):
+        x, y = _f32(x), _f32(y)
+        g = np.empty(self.param_count, dtype=np.float32)
+        L = ct.c_double()
+        _check(self._lib.hom_mlp_loss_grad(self._h, _fptr(x), _fptr(y), x.shape[0], int(precise), ct.byref(L),
+                                           _fptr(g)), self.error)
+        return L.value, g
+
+
+def surrogate_infer(net_a: MLP, net_b: MLP, x_dev, threshold, floor_scale):
+    """Two-network inference with acceptance on device tensors; returns
+    (y, spread, accept) tensors."""
+    import torch
+    n = x_dev.shape[0]
+    y = torch.empty((n, net_a.n_out), dtype=torch.float32, device=x_dev.device)
+    spread = torch.empty(n, dtype=torch.float32, device=x_dev.device)
+    acc = torch.empty(n, dtype=torch.uint8, device=x_dev.device)
+    lib = library()
+    _check(lib.hom_surrogate_infer(net_a._h, net_b._h, ct.c_void_p(x_dev.data_ptr()), ct.c_void_p(y.data_ptr()),
+                                   ct.c_void_p(spread.data_ptr()), ct.c_void_p(acc.data_ptr()), n, threshold,
+                                   floor_scale, ct.c_void_p(torch.cuda.current_stream().cuda_stream)),
+           net_a.error)
+    return y, spread, acc

@@ -1,0 +1,126 @@
+"""Surrogate network kernels against the FP64 oracle network: forward (bf16
+matrix cores, precise split mode), gradients, and a training smoke test."""
+import numpy as np
+import pytest
+
+from oracle import mlp as omlp
+from paper_2109_14403_amd import hom
+
+pytestmark = pytest.mark.gpu
+
+N_IN, N_OUT = 32, 10
+
+
+def bf16_round(a):
+    """Round FP32 values to the nearest bf16 (ties to even)."""
+    u = np.ascontiguousarray(a, dtype=np.float32).view(np.uint32).astype(np.uint64)
+    u = (u + 0x7FFF + ((u >> 16) & 1)) & 0xFFFF0000
+    return u.astype(np.uint32).view(np.float32)
+
+
+@pytest.fixture(scope="module")
+def net_and_data():
+    rng = np.random.default_rng(3)
+    net = hom.MLP(N_IN, N_OUT, seed=11)
+    layers = net.layers()
+    # perturb the biases so the test sees nonzero bias paths
+    flat = net.get_params().copy()
+    o = 0
+    for (W, b) in layers:
+        o += W.size
+        flat[o:o + b.size] = rng.normal(scale=0.1, size=b.size)
+        o += b.size
+    net.set_params(flat)
+    xm, xs = rng.normal(size=N_IN), rng.uniform(0.5, 2.0, size=N_IN)
+    ym, ys = rng.normal(size=N_OUT), rng.uniform(0.5, 2.0, size=N_OUT)
+    lw = rng.uniform(0.5, 2.0, size=N_OUT)
+    net.set_scaling(xm, xs, ym, ys, lw)
+    x = (xm + xs * rng.normal(size=(333, N_IN))).astype(np.float32)   # 333 rows: a ragged last tile
+    y = (ym + ys * rng.normal(size=(333, N_OUT))).astype(np.float32)
+    return net, x, y, (xm, xs, ym, ys, lw)
+
+
+def oracle_forward(params, x, scal):
+    xm, xs, ym, ys, _ = scal
+    xh = (x.astype(np.float64) - xm) / xs
+    yh, _ = omlp.forward(params, xh)
+    return yh * ys + ym
+
+
+def f64(layers, rounding=None):
+    return [((rounding(W) if rounding else W).astype(np.float64), b.astype(np.float64)) for W, b in layers]
+
+
+def test_forward_precise_matches_oracle(net_and_data):
+    net, x, _, scal = net_and_data
+    ref = oracle_forward(f64(net.layers()), x, scal)
+    out = net.forward(x, precise=True)
+    err = np.abs(out - ref).max() / np.abs(ref).max()
+    print(f"precise forward max rel err {err:.2e}", flush=True)
+    assert err < 2e-5
+
+
+def test_forward_bf16_matches_rounded_weight_oracle(net_and_data):
+    net, x, _, scal = net_and_data
+    ref = oracle_forward(f64(net.layers(), bf16_round), x, scal)
+    out = net.forward(x, precise=False)
+    err = np.abs(out - ref).max() / np.abs(ref).max()
+    print(f"bf16 forward max rel err {err:.2e}", flush=True)
+    assert err < 1e-4
+
+
+def test_gated_skip_matches_numpy(net_and_data):
+    net, x, _, scal = net_and_data
+    xm, xs, ym, ys, _ = scal
+    rng = np.random.default_rng(8)
+    gates = (7, 6, 26)
+    G = rng.normal(scale=0.1, size=(N_OUT, 10, N_IN))
+    c = rng.normal(size=N_OUT)
+    net.set_skip(gates, G, c)
+    try:
+        xh = (x.astype(np.float64) - xm) / xs
+        s = [np.ones(len(xh))]
+        for i in gates:
+            s += [xh[:, i], xh[:, i] ** 2, xh[:, i] ** 3]
+        s = np.stack(s, axis=1)
+        skip = c + np.einsum("rg,jgk,rk->rj", s, G, xh)
+        ref = oracle_forward(f64(net.layers()), x, scal) + skip
+        out = net.forward(x, precise=True)
+        err = np.abs(out - ref).max() / np.abs(ref).max()
+        print(f"forward with skip max rel err {err:.2e}", flush=True)
+        assert err < 2e-5
+    finally:
+        net.set_skip(gates, np.zeros_like(G), np.zeros_like(c))
+
+
+def test_gradients_match_oracle(net_and_data):
+    net, x, y, scal = net_and_data
+    xm, xs, ym, ys, lw = scal
+    L, g = net.loss_grad(x, y, precise=True)
+    xh = (x.astype(np.float64) - xm) / xs
+    th = (y.astype(np.float64) - ym) / ys
+    grads, Lref = omlp.gradients(f64(net.layers()), xh, th, lw)
+    assert L == pytest.approx(Lref, rel=1e-5)
+    gl = net.layers(g)
+    for i, ((gW, gb), (rW, rb)) in enumerate(zip(gl, grads)):
+        eW = np.linalg.norm(gW - rW) / np.linalg.norm(rW)
+        eb = np.linalg.norm(gb - rb) / np.linalg.norm(rb)
+        print(f"layer {i}: dW rel err {eW:.2e}, db rel err {eb:.2e}", flush=True)
+        # precise mode carries activations and weights as two bf16 parts
+        # (about 16 significant bits), FP32 accumulation
+        assert eW < 5e-5 and eb < 5e-5
+
+
+def test_training_reduces_loss():
+    rng = np.random.default_rng(0)
+    x = rng.uniform(-1, 1, size=(8192, 8)).astype(np.float32)
+    y = np.stack([np.sin(2 * x[:, 0]) + x[:, 1] ** 2, x[:, 2] * x[:, 3], np.cos(x[:, 4] + x[:, 5])], axis=1)
+    y = y.astype(np.float32)
+    net = hom.MLP(8, 3, seed=1)
+    net.set_scaling(x.mean(0), x.std(0), y.mean(0), y.std(0))
+    losses = net.train(x, y, epochs=40, batch=256, lr=2e-3, seed=2)
+    print(f"loss {losses[0]:.3e} -> {losses[-1]:.3e}", flush=True)
+    assert losses[-1] < 1e-2 * losses[0]
+    pred = net.forward(x[:512])
+    rel = np.abs(pred - y[:512]).max() / np.abs(y).max()
+    assert rel < 0.1
