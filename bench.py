@@ -25,10 +25,14 @@ import numpy as np
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-METRIC = "voxel-iters/s coupled FFT solve"
+METRIC = "voxel-iters/s coupled FFT solve; surrogate vs FFT Gauss-pts/s at 1e-3 err"
 HBM_PEAK_GBS = 8000.0
 KERNEL_SOURCES = ("paper_2109_14403_amd/csrc/pipeline.h", "paper_2109_14403_amd/csrc/fft_core.h",
                   "paper_2109_14403_amd/csrc/pointwise.hip", "paper_2109_14403_amd/csrc/common.h")
+
+
+CALIB_FLOATS = 1 << 28
+PMC_KINDS = {"xfwd": "k_xfwd", "ypass": "k_ypass", "zgreen": "k_zgreen", "xinv": "k_xinv", "eval": "k_eval"}
 
 
 def kernel_source_hash():
@@ -41,20 +45,23 @@ def kernel_source_hash():
 
 def algorithmic_bytes(kind, n, fp_bytes, matrix_fraction):
     """Minimum bytes one launch of a mechanical kernel moves on one n^3 problem,
-    as (residual-evaluation iteration, CG iteration). Spectra hold
-    n * n * (n/2 + 1) * 6 complex values; the direction field of plastic
-    voxels is not counted (a lower bound)."""
+    as (residual evaluation, first CG iteration of a Newton step, later CG
+    iteration). Spectra hold n * n * (n/2 + 1) * 6 complex values; the
+    direction field of plastic voxels is not counted (a lower bound)."""
     v = float(n) ** 3
     spec = n * n * (n // 2 + 1) * 6 * 2 * fp_bytes
     field = 6 * fp_bytes * v
     if kind in ("yfwd", "yinv", "zgreen"):
-        return 2 * spec, 2 * spec
-    if kind == "xfwd":   # eval: read stress; CG: read r, p, tangent factors, phase, write p; both write spectra
-        return field + spec, 3 * field + 2 * fp_bytes * v + v + spec
-    if kind == "xinv":   # eval: read spectra and stress, write r; CG: read spectra, p, r, dx, write r, dx
-        return spec + 2 * field, spec + 5 * field
+        return 2 * spec, 2 * spec, 2 * spec
+    if kind == "xfwd":
+        # eval: read stress, write spectra. CG: read r (+ p, x), tangent factors
+        # and phase, write p (+ x) and spectra
+        tang = 2 * fp_bytes * v + v
+        return field + spec, 2 * field + tang + spec, 5 * field + tang + spec
+    if kind == "xinv":   # eval: read spectra and stress, write r; CG: read spectra and r, write r
+        return spec + 2 * field, spec + 2 * field, spec + 2 * field
     if kind == "eval":   # read strain, phase, PA66 eps_p, eps_vp and history sums; write stress, tangent factors
-        return 2 * field + v + matrix_fraction * v * 14 * 8 + 2 * fp_bytes * v, 0.0
+        return 2 * field + v + matrix_fraction * v * 14 * 8 + 2 * fp_bytes * v, 0.0, 0.0
     return None
 
 
@@ -177,6 +184,68 @@ def surrogate_bench(n_hist=4000, test_hist=1000, epochs=150, rows=65536):
     return out
 
 
+def _counter_rows(folder):
+    import csv
+    import glob
+    rows = []
+    for path in glob.glob(os.path.join(folder, "**", "*counter_collection.csv"), recursive=True):
+        with open(path, newline="") as f:
+            rows += list(csv.DictReader(f))
+    if not rows:
+        raise SystemExit(f"no counter_collection.csv under {folder}")
+    return rows
+
+
+def _per_kernel(rows, counter):
+    """{kernel name: [values per dispatch]} of one counter (KiB per dispatch)."""
+    out = {}
+    for r in rows:
+        if r["Counter_Name"] == counter:
+            out.setdefault(r["Kernel_Name"], []).append(float(r["Counter_Value"]))
+    return out
+
+
+def pmc_summary(fetch_dir, write_dir, n, command):
+    """Turn two rocprofv3 --pmc runs (FETCH_SIZE, WRITE_SIZE) into HBM bytes per
+    launch of each mechanical pipeline kernel, scaled by what the same counters
+    read for the 1 GiB calibration kernel (torch's elementwise multiply)."""
+    fetch = _per_kernel(_counter_rows(fetch_dir), "FETCH_SIZE")
+    write = _per_kernel(_counter_rows(write_dir), "WRITE_SIZE")
+    calib_bytes = CALIB_FLOATS * 4
+
+    def calib(table):
+        cand = [max(v) for k, v in table.items() if "hom::" not in k and "elementwise" in k.lower()]
+        if not cand:
+            raise SystemExit("calibration kernel missing: run bench.py with --calib-copy")
+        return calib_bytes / (max(cand) * 1024.0)
+
+    fscale, wscale = calib(fetch), calib(write)
+    h = kernel_source_hash()
+    lines = [f"# HBM traffic of the pipeline kernels, {n}^3 fibre composite", "",
+             f"command: {command}", f"kernel source hash: {h}",
+             f"calibration: 1 GiB read + 1 GiB write kernel; FETCH_SIZE scale {fscale:.4f}, "
+             f"WRITE_SIZE scale {wscale:.4f}", "",
+             "| kernel | launches | FETCH MB/launch | WRITE MB/launch | HBM MB/launch (scaled) |",
+             "|---|---|---|---|---|"]
+    for kind, name in PMC_KINDS.items():
+        groups = [k for k in fetch if name in k and "hom::" in k]
+        if not groups:
+            continue
+        main_name = max(groups, key=lambda k: len(fetch[k]))    # the mechanical instance
+        f = float(np.mean(fetch[main_name])) * 1024.0
+        w = float(np.mean(write.get(main_name, [0.0]))) * 1024.0
+        tot = f * fscale + w * wscale
+        rec = {"source_hash": h, "bytes_per_launch": tot, "fetch_bytes_raw": f, "write_bytes_raw": w,
+               "fetch_scale": fscale, "write_scale": wscale, "launches": len(fetch[main_name]),
+               "kernel": main_name, "command": command}
+        with open(os.path.join(ROOT, "profiles", f"{kind}_fibres{n}_pmc.json"), "w") as fo:
+            json.dump(rec, fo, indent=1)
+        lines.append(f"| {kind} | {len(fetch[main_name])} | {f / 1e6:.1f} | {w / 1e6:.1f} | {tot / 1e6:.1f} |")
+    with open(os.path.join(ROOT, "profiles", f"pipeline_fibres{n}_hbm_traffic.md"), "w") as fo:
+        fo.write("\n".join(lines) + "\n")
+    print("\n".join(lines))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -188,7 +257,13 @@ def main():
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--no-surrogate", action="store_true")
     ap.add_argument("--calib-copy", action="store_true", help="run a 1 GiB device copy (PMC calibration)")
+    ap.add_argument("--pmc-summary", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
+                    help="summarize two rocprofv3 --pmc output folders into profiles/ (no GPU needed)")
+    ap.add_argument("--pmc-command", default="", help="command line recorded in the --pmc-summary output")
     args = ap.parse_args()
+    if args.pmc_summary:
+        pmc_summary(args.pmc_summary[0], args.pmc_summary[1], args.n, args.pmc_command)
+        return
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1"}))
         sys.exit(2)
@@ -208,9 +283,10 @@ def main():
         raise SystemExit(f"at most {len(hist)} increments")
 
     if args.calib_copy:
-        a = torch.empty(1 << 28, dtype=torch.float32, device="cuda")
+        # a plain streaming kernel of known size (reads 1 GiB, writes 1 GiB)
+        a = torch.empty(CALIB_FLOATS, dtype=torch.float32, device="cuda")
         b = torch.empty_like(a)
-        b.copy_(a)
+        torch.mul(a, 1.0, out=b)
         torch.cuda.synchronize()
         del a, b
 
@@ -263,9 +339,10 @@ def main():
         mix = algorithmic_bytes(dom, n, 4, matrix_fraction)
         byt = None
         if mix is not None and launches == n_eval + n_cg:
-            byt = (n_eval * mix[0] + n_cg * mix[1]) / launches
+            n_first = max(n_eval - 1, 0)       # every Newton step but the converged one runs CG
+            byt = (n_eval * mix[0] + n_first * mix[1] + (n_cg - n_first) * mix[2]) / launches
         traffic = None
-        pmc_path = os.path.join(ROOT, "profiles", f"{dom}_fibres256_pmc.json")
+        pmc_path = os.path.join(ROOT, "profiles", f"{dom}_fibres{n}_pmc.json")
         if os.path.exists(pmc_path):
             pm = json.load(open(pmc_path))
             if pm.get("source_hash") == kernel_source_hash():

@@ -77,6 +77,8 @@ struct ProbInc {
 template <typename T>
 struct Pipe {
   int nx, ny, nz, P;        // P = nx / 2 + 1
+  int PS;                   // row pitch of the spectra in kx entries: P rounded up so that a
+                            // row of PS * C complex values is a whole number of 128-byte lines
   long long nvox;
   int nprob;
   int C;
@@ -85,10 +87,9 @@ struct Pipe {
   T* f;                     // field to transform (stress / flux)
   T* r;
   T* p;
-  T* dx;
   const T* tab;             // tangent factors [prob][2][nvox] (mechanics)
   const T* tn;              // tangent direction [prob][6][nvox] (mechanics)
-  c2<T>* spec;              // [prob][nz][ny][P][C]
+  c2<T>* spec;              // [prob][nz][ny][PS][C], kx < P used
   Ctl* ctl;
   const ProbInc* inc;
   double* part;             // [prob][maxblk][NPART]

@@ -9,8 +9,12 @@
 //          components, inverse transform along z.
 //   ypass  inverse along y.
 //   xinv   complex-to-real inverse along x, scaled by 1/(nx ny nz), then the
-//          post-operation per voxel (residual / A p / basic-scheme update)
-//          with FP64 partial sums for the reductions.
+//          post-operation per voxel (residual / CG residual update / basic-
+//          scheme update) with FP64 partial sums for the reductions.
+//
+// CG keeps three fields (x, r, p): the step x += alpha p of iteration k is
+// deferred to the x-forward pass of iteration k + 1 (or to the next
+// constitutive evaluation), which reads the old p anyway.
 //
 // Every kernel serves all problems of a group in one launch: blockIdx.x runs
 // over (problem, tile), and a block whose problem is not iterating exits at
@@ -124,19 +128,6 @@ __device__ __forceinline__ void st4(double* p, const double (&v)[4]) {
   reinterpret_cast<double2*>(p)[1] = make_double2(v[2], v[3]);
 }
 
-// copy `count` complex values (16-byte aligned at both ends' start)
-template <typename T>
-__device__ __forceinline__ void copy_c2(c2<T>* __restrict__ dst, const c2<T>* __restrict__ src, int count, int tid,
-                                        int nth) {
-  constexpr int V = 16 / sizeof(c2<T>);
-  const int nvec = count / V;
-  const uint4* s = reinterpret_cast<const uint4*>(src);
-  uint4* d = reinterpret_cast<uint4*>(dst);
-#pragma unroll 4
-  for (int i = tid; i < nvec; i += nth) d[i] = s[i];
-  for (int e = nvec * V + tid; e < count; e += nth) dst[e] = src[e];
-}
-
 // ---------------------------------------------------------------------------
 // x forward: pre-operation + packed real-to-complex transforms
 // ---------------------------------------------------------------------------
@@ -172,6 +163,7 @@ __global__ void __launch_bounds__((N / Plan<N>::M) * NL * ((C + 1) / 2)) k_xfwd(
   const bool cg = (mode == M_CG);
   const bool first = (ctl.cg_it == 0);
   const T beta = T(ctl.beta);
+  const T alpha_prev = T(ctl.alpha);  // step length of the previous CG iteration
   __shared__ T ptab[MAX_PHASES];  // 3K (mechanics) or kappa (conduction) per phase
   if (tid < MAX_PHASES) ptab[tid] = T(C == 6 ? inc.ph[tid].K3 : inc.ph[tid].kappa);
   __syncthreads();
@@ -198,6 +190,8 @@ __global__ void __launch_bounds__((N / Plan<N>::M) * NL * ((C + 1) / 2)) k_xfwd(
           for (int j = 0; j < 4; ++j) out[j][c] = q.v[j];
         }
       } else {
+        // p = r + beta p; the step x += alpha p of the previous iteration is
+        // applied here, where the old direction is read anyway
         T pv[C][4];
 #pragma unroll
         for (int c = 0; c < C; ++c) {
@@ -207,8 +201,14 @@ __global__ void __launch_bounds__((N / Plan<N>::M) * NL * ((C + 1) / 2)) k_xfwd(
             for (int j = 0; j < 4; ++j) pv[c][j] = rq.v[j];
           } else {
             const Q4<T> pq = ld4(a.p + fo + c * nv + v);
+            const Q4<T> xq = ld4(a.x + fo + c * nv + v);
+            T xn[4];
 #pragma unroll
-            for (int j = 0; j < 4; ++j) pv[c][j] = rq.v[j] + beta * pq.v[j];
+            for (int j = 0; j < 4; ++j) {
+              pv[c][j] = rq.v[j] + beta * pq.v[j];
+              xn[j] = xq.v[j] + alpha_prev * pq.v[j];
+            }
+            st4(a.x + fo + c * nv + v, xn);
           }
           st4(a.p + fo + c * nv + v, pv[c]);
         }
@@ -286,7 +286,8 @@ __global__ void __launch_bounds__((N / Plan<N>::M) * NL * ((C + 1) / 2)) k_xfwd(
 
   // unpack the two real transforms of each complex line and write the block's
   // contiguous run of half spectra [line][kx][comp] with 16-byte stores
-  c2<T>* spec = a.spec + (long long)prob * a.nz * a.ny * a.P * C + (long long)line0 * H * C;
+  const int rowp = a.PS * C;
+  c2<T>* spec = a.spec + (long long)prob * a.nz * a.ny * rowp + (long long)line0 * rowp;
   constexpr int V = 16 / sizeof(c2<T>);
   const int total = nvl * H * C;
   auto value = [&](int e) -> c2<T> {
@@ -300,16 +301,22 @@ __global__ void __launch_bounds__((N / Plan<N>::M) * NL * ((C + 1) / 2)) k_xfwd(
     const c2<T> val = (c & 1) ? mul_mi(zk - zm) : (zk + zm);
     return cscale(val, T(0.5));
   };
-  const int nvec = total / V;
-  for (int i = tid; i < nvec; i += nth) {
-    if constexpr (V == 2) {
-      const c2<T> u0 = value(2 * i), u1 = value(2 * i + 1);
-      reinterpret_cast<float4*>(spec)[i] = make_float4(u0.x, u0.y, u1.x, u1.y);
-    } else {
-      spec[i] = value(i);
+  // rows are rowp apart; the (kx, comp) entries of one row are contiguous
+  if constexpr (V == 2 && C % 2 == 0) {
+    // pairs of components of one kx: 16-byte aligned stores (rowp * 8 is a
+    // multiple of 128 and the pair starts at an even entry)
+    for (int i = tid; i < total / 2; i += nth) {
+      const int e = 2 * i;
+      const int li = e / (H * C);
+      const c2<T> u0 = value(e), u1 = value(e + 1);
+      *reinterpret_cast<float4*>(spec + li * rowp + (e - li * H * C)) = make_float4(u0.x, u0.y, u1.x, u1.y);
+    }
+  } else {
+    for (int e = tid; e < total; e += nth) {
+      const int li = e / (H * C);
+      spec[li * rowp + (e - li * H * C)] = value(e);
     }
   }
-  for (int e = nvec * V + tid; e < total; e += nth) spec[e] = value(e);
 }
 
 // ---------------------------------------------------------------------------
@@ -338,8 +345,8 @@ __global__ void __launch_bounds__((N / Plan<N>::M) * TX * C) k_ypass(Pipe<T> a, 
   const int kx = kb * TX + l / C;
   const int c = l % C;
   const bool active = kx < P;
-  const long long stride = (long long)P * C;
-  c2<T>* base = a.spec + (long long)prob * a.nz * a.ny * P * C + ((long long)z * a.ny * P + kx) * C + c;
+  const long long stride = (long long)a.PS * C;
+  c2<T>* base = a.spec + (long long)prob * a.nz * a.ny * a.PS * C + ((long long)z * a.ny * a.PS + kx) * C + c;
   c2<T> r[M];
   __syncthreads();
 #pragma unroll
@@ -381,8 +388,8 @@ __global__ void __launch_bounds__((N / Plan<N>::M) * TX * C) k_zgreen(Pipe<T> a)
   const int kx = kb * TX + l / C;
   const int c = l % C;
   const bool active = kx < P;
-  const long long stride = (long long)a.ny * P * C;
-  c2<T>* base = a.spec + (long long)prob * a.nz * a.ny * P * C + ((long long)ky * P + kx) * C + c;
+  const long long stride = (long long)a.ny * a.PS * C;
+  c2<T>* base = a.spec + (long long)prob * a.nz * a.ny * a.PS * C + ((long long)ky * a.PS + kx) * C + c;
   c2<T> r[M];
   __syncthreads();
 #pragma unroll
@@ -458,14 +465,28 @@ __global__ void __launch_bounds__((N / Plan<N>::M) * NL * ((C + 1) / 2)) k_xinv(
   const int mode = ctl.mode;
   if (!pipeline_mode(mode)) return;
   const T alpha = T(ctl.alpha);
-  const bool cg_first = ctl.cg_it == 0;
   const int tid = threadIdx.x;
   const int nth = blockDim.x;
   for (int i = tid; i < N; i += nth) tw[i] = a.twx[i];
-  // stage the block's contiguous run of half spectra [line][kx][comp]
+  // stage the block's half spectra [line][kx][comp] (rows rowp apart in
+  // memory, packed in LDS)
   const int nvl = min(NL, nlines - line0);
-  const c2<T>* spec = a.spec + (long long)prob * a.nz * a.ny * a.P * C + (long long)line0 * H * C;
-  copy_c2<T>(buf, spec, nvl * H * C, tid, nth);
+  const int rowp = a.PS * C;
+  const c2<T>* spec = a.spec + (long long)prob * a.nz * a.ny * rowp + (long long)line0 * rowp;
+  if constexpr (sizeof(c2<T>) == 8 && C % 2 == 0) {
+    const uint4* s4 = reinterpret_cast<const uint4*>(spec);
+    uint4* d4 = reinterpret_cast<uint4*>(buf);
+    for (int i = tid; i < nvl * H * C / 2; i += nth) {
+      const int e = 2 * i;
+      const int li = e / (H * C);
+      d4[i] = s4[(li * rowp + (e - li * H * C)) / 2];
+    }
+  } else {
+    for (int e = tid; e < nvl * H * C; e += nth) {
+      const int li = e / (H * C);
+      buf[e] = spec[li * rowp + (e - li * H * C)];
+    }
+  }
   for (int e = nvl * H * C + tid; e < NL * H * C; e += nth) buf[e] = mk(T(0), T(0));
   __syncthreads();
   const int l = tid % L;
@@ -524,25 +545,16 @@ __global__ void __launch_bounds__((N / Plan<N>::M) * NL * ((C + 1) / 2)) k_xinv(
           s1 += (double)fq.v[j] * (double)fq.v[j];
         }
       } else if (mode == M_CG) {
-        // CG update with alpha = r.r / p.C p: r -= alpha A p, dx += alpha p
-        const Q4<T> pq = ld4(a.p + o);
+        // residual update with alpha = r.r / p.C p: r -= alpha A p (the step
+        // x += alpha p follows in the next x-forward pass or evaluation)
         const Q4<T> rq = ld4(a.r + o);
-        T rn[4], dn[4];
-        if (cg_first) {
-#pragma unroll
-          for (int j = 0; j < 4; ++j) dn[j] = alpha * pq.v[j];
-        } else {
-          const Q4<T> dq = ld4(a.dx + o);
-#pragma unroll
-          for (int j = 0; j < 4; ++j) dn[j] = dq.v[j] + alpha * pq.v[j];
-        }
+        T rn[4];
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
           rn[j] = rq.v[j] - alpha * g[j];
           s0 += (double)rn[j] * (double)rn[j];
         }
         st4(a.r + o, rn);
-        st4(a.dx + o, dn);
       } else {
         const Q4<T> xq = ld4(a.x + o);
         T xn[4];

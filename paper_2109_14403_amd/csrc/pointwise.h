@@ -18,7 +18,6 @@ struct Pt {
   T* f;
   T* r;
   T* p;
-  T* dx;
   T* tab;
   T* tn;
   double* state;            // [prob][nstate][nvox] (mechanics with a PA66 phase)

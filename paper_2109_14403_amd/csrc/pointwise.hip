@@ -32,36 +32,54 @@ struct PaOut {
   double dp;
 };
 
+// x^p for x > 0 by one log and one exp (a few ulp; FP64 pow is several
+// times dearer and the root is only needed to ~1e-15 relative)
+__device__ __forceinline__ double powpos(double x, double p) { return exp(p * log(x)); }
+
+// <x>^m and <x>^(m-1) for x >= 0 (exact products for m = 2)
+__device__ __forceinline__ void pow_m(double x, double m, double& xm, double& xm1) {
+  if (x > 0.0) {
+    if (m == 2.0) {
+      xm = x * x;
+      xm1 = x;
+    } else {
+      xm = powpos(x, m);
+      xm1 = xm / x;
+    }
+  } else {
+    xm = 0.0;
+    xm1 = m > 1.0 ? 0.0 : (m == 1.0 ? 1.0 : INFINITY);
+  }
+}
+
 __device__ __forceinline__ double pa66_solve_dp(const ProbInc& in, double seq, double ep, double f, double G3,
                                                 double& dgd) {
   double lo = 0.0, hi = f / G3;
   double d = 0.5 * hi;
   const double c = in.ccoef, sY = in.sY, m = in.mexp, hk = in.hk, nh = in.nh;
-  double gd = 1.0, xp = 0.0;
+  double A = 0.0, hp = INFINITY;
   for (int it = 0; it < 80; ++it) {
     const double e = ep + d;
-    const double x = (seq - G3 * d - sY - hk * pow(e, nh)) / sY;
-    xp = x > 0.0 ? x : 0.0;
-    const double gv = d - c * pow(xp, m);
+    const double he = e > 0.0 ? hk * powpos(e, nh) : 0.0;  // H(eps_p + d)
+    const double x = (seq - G3 * d - sY - he) / sY;
+    double xm, xm1;
+    pow_m(x, m, xm, xm1);
+    const double gv = d - c * xm;
     if (gv < 0.0)
       lo = d;
     else
       hi = d;
-    const double hp = e > 0.0 ? hk * nh * pow(e, nh - 1.0) : INFINITY;
-    gd = 1.0 + c * m * pow(xp, m - 1.0) * (G3 + hp) / sY;
+    hp = e > 0.0 ? nh * he / e : INFINITY;  // H'
+    A = c * m * xm1 / sY;
+    const double gd = 1.0 + A * (G3 + hp);
     double dn = d - gv / gd;
     if (!(dn > lo && dn < hi)) dn = 0.5 * (lo + hi);
     const bool done = fabs(dn - d) <= 1e-15 * dn || hi - lo <= 1e-16 * hi;
     d = dn;
     if (done) break;
   }
-  // derivative information at the root
-  const double e = ep + d;
-  const double x = (seq - G3 * d - sY - hk * pow(e, nh)) / sY;
-  xp = x > 0.0 ? x : 0.0;
-  const double A = c * m * pow(xp, m - 1.0) / sY;
-  const double hp = e > 0.0 ? hk * nh * pow(e, nh - 1.0) : INFINITY;
-  dgd = A / (1.0 + A * (G3 + hp));  // d dp / d seq_tr
+  // d dp / d seq_tr at the root (from the last step: d moved by <= 1e-15 relative)
+  dgd = A > 0.0 ? A / (1.0 + A * (G3 + hp)) : 0.0;
   return d;
 }
 
@@ -127,7 +145,7 @@ __device__ void pa66_point(const ProbInc& in, const double* eps, const double* s
   for (int c = 0; c < 6; ++c) sn2 += str[c] * str[c];
   const double snrm = sqrt(sn2);
   const double seq = 1.2247448713915890 * snrm;  // sqrt(3/2) |s|
-  const double H = ep > 0.0 ? in.hk * pow(ep, in.nh) : 0.0;
+  const double H = ep > 0.0 ? in.hk * powpos(ep, in.nh) : 0.0;
   const double f = seq - in.sY - H;
   double dp = 0.0, th1 = 1.0, cp = 1.0;
   const double G3 = 1.5 * in.Gbar2;
@@ -191,7 +209,7 @@ __device__ void pa66_point(const ProbInc& in, const double* eps, const double* s
     for (int c = 0; c < 6; ++c) evo[c * ss] = dnew[c] + (c < 3 ? s1 : 0.0);
   }
   dis /= dt;
-  const double Hn = ep1 > 0.0 ? in.hk * pow(ep1, in.nh) : 0.0;
+  const double Hn = ep1 > 0.0 ? in.hk * powpos(ep1, in.nh) : 0.0;
   *diss = dis;
   *coup = -in.theta * (in.alpha0 * trsum / dt + in.beta1 * Hn * dp / dt) + dis;
 }
@@ -234,7 +252,8 @@ __global__ void __launch_bounds__(PT_THREADS) k_eval(Pt<T> a) {
   const Ctl& ctl = a.ctl[prob];
   const int mode = ctl.mode;
   if (mode != M_EVAL && mode != M_BASIC) return;
-  const bool pending = ctl.pending != 0;
+  const bool pending = ctl.pending != 0;  // last CG step x += alpha p not yet applied
+  const T alpha = T(ctl.alpha);
   const bool want_tan = (mode == M_EVAL);
   const ProbInc& in = a.inc[prob];
   const long long nv = a.nvox;
@@ -246,7 +265,7 @@ __global__ void __launch_bounds__(PT_THREADS) k_eval(Pt<T> a) {
     for (int c = 0; c < C; ++c) {
       T xv = a.x[fo + c * nv + v];
       if (pending) {
-        xv += a.dx[fo + c * nv + v];
+        xv += alpha * a.p[fo + c * nv + v];
         a.x[fo + c * nv + v] = xv;
       }
       e[c] = xv;

@@ -6,6 +6,7 @@
 #include <cmath>
 #include <cstring>
 #include <map>
+#include <numeric>
 #include <tuple>
 
 namespace hom {
@@ -237,6 +238,8 @@ static bool launch_ok(const LaunchInfo& li) { return li.threads <= 1024 && li.ld
 template <typename T>
 struct Group {
   int nx = 0, ny = 0, nz = 0, P = 0;
+  int ps[2] = {0, 0};      // spectral row pitch in kx entries [mech, thermal]
+  size_t spec_count = 0;   // complex values of the spectral buffer
   long long nvox = 0;
   int nprob = 0;
   double len[3] = {1, 1, 1};
@@ -246,7 +249,7 @@ struct Group {
   size_t bytes = 0;
 
   uint8_t* phase = nullptr;
-  T *xm = nullptr, *xnm = nullptr, *f = nullptr, *r = nullptr, *p = nullptr, *dx = nullptr;
+  T *xm = nullptr, *xnm = nullptr, *f = nullptr, *r = nullptr, *p = nullptr;
   double* hist = nullptr;
   T *tab = nullptr, *tn = nullptr, *xt = nullptr;
   c2<T>* spec = nullptr;
@@ -295,11 +298,17 @@ struct Group {
     f = dalloc<T>(6 * nm);
     r = dalloc<T>(6 * nm);
     p = dalloc<T>(6 * nm);
-    dx = dalloc<T>(6 * nm);
     tab = dalloc<T>(2 * nm);
     tn = dalloc<T>(6 * nm);
     xt = dalloc<T>(3 * nm);
-    spec = dalloc<c2<T>>((size_t)nprob * nz * ny * P * 6);
+    for (int phys = 0; phys < 2; ++phys) {
+      // smallest kx multiple that makes a row a whole number of 128-byte lines
+      const int row_bytes = (phys == 0 ? 6 : 3) * (int)sizeof(c2<T>);
+      const int step = 128 / std::gcd(128, row_bytes);
+      ps[phys] = (P + step - 1) / step * step;
+    }
+    spec_count = (size_t)nprob * nz * ny * std::max(ps[0] * 6, ps[1] * 3);
+    spec = dalloc<c2<T>>(spec_count);
     if (with_state && nstate > 0) {
       state = dalloc<double>((size_t)nstate * nm);
       hist = dalloc<double>((size_t)7 * nm);
@@ -333,6 +342,7 @@ struct Group {
     a.ny = ny;
     a.nz = nz;
     a.P = P;
+    a.PS = ps[phys];
     a.nvox = nvox;
     a.nprob = nprob;
     a.C = phys == 0 ? 6 : 3;
@@ -341,7 +351,6 @@ struct Group {
     a.f = f;
     a.r = r;
     a.p = p;
-    a.dx = dx;
     a.tab = tab;
     a.tn = tn;
     a.spec = spec;
@@ -368,7 +377,6 @@ struct Group {
     a.f = f;
     a.r = r;
     a.p = p;
-    a.dx = dx;
     a.tab = tab;
     a.tn = tn;
     a.state = state;
@@ -528,7 +536,7 @@ class BatchT : public BatchImpl {
       std::memset(c.data(), 0, sizeof(Ctl) * G.nprob);
       HIPCHK(hipMemcpy(ctl, c.data(), sizeof(Ctl) * G.nprob, hipMemcpyHostToDevice));
     }
-    HIPCHK(hipMemset(G.spec, 0, sizeof(c2<T>) * (size_t)G.nprob * G.nz * G.ny * G.P * 6));
+    HIPCHK(hipMemset(G.spec, 0, sizeof(c2<T>) * G.spec_count));
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
   }
