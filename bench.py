@@ -32,6 +32,7 @@ KERNEL_SOURCES = ("paper_2109_14403_amd/csrc/pipeline.h", "paper_2109_14403_amd/
 
 
 CALIB_FLOATS = 1 << 28
+NETWORK_PARAMS_MACS = 32 * 256 + 3 * 256 * 256 + 256 * 10   # multiply-adds per row of one network
 PMC_KINDS = {"xfwd": "k_xfwd", "ypass": "k_ypass", "zgreen": "k_zgreen", "xinv": "k_xinv", "eval": "k_eval"}
 
 
@@ -179,7 +180,7 @@ def surrogate_bench(n_hist=4000, test_hist=1000, epochs=150, rows=65536):
             "all_median_error": float(np.median(err)), "all_p90_error": float(np.quantile(err, 0.9)),
             "infer_ms_65536": round(t_inf * 1e3, 3), "surrogate_gauss_point_updates_per_s": round(rate, 1),
             "ratio_vs_fft": round(rate / r_fft, 2)}
-    flops = rows * 2 * 414720
+    flops = rows * 2 * 2 * NETWORK_PARAMS_MACS
     out["network_tflops"] = round(flops / (out["target_0.001"]["infer_ms_65536"] * 1e-3) / 1e12, 2)
     return out
 
@@ -205,28 +206,48 @@ def _per_kernel(rows, counter):
     return out
 
 
-def pmc_summary(fetch_dir, write_dir, n, command):
-    """Turn two rocprofv3 --pmc runs (FETCH_SIZE, WRITE_SIZE) into HBM bytes per
-    launch of each mechanical pipeline kernel, scaled by what the same counters
-    read for the 1 GiB calibration kernel (torch's elementwise multiply)."""
-    fetch = _per_kernel(_counter_rows(fetch_dir), "FETCH_SIZE")
-    write = _per_kernel(_counter_rows(write_dir), "WRITE_SIZE")
+def pmc_summary(dirs, n, command):
+    """Turn rocprofv3 --pmc runs into HBM bytes per launch of each mechanical
+    pipeline kernel. dirs = (FETCH_SIZE run, WRITE_SIZE run[, request-size
+    run]). Each counter is scaled by what it reads for the 1 GiB calibration
+    kernel (torch's elementwise multiply, 1 GiB read + 1 GiB written). The
+    optional request-size run (TCC_EA0_RDREQ_32B/_64B/_128B) gives the read
+    bytes directly: FETCH_SIZE prices a request as 64 bytes unless the
+    TCC_BUBBLE counter flags it as 128 bytes."""
+    fetch = _per_kernel(_counter_rows(dirs[0]), "FETCH_SIZE")
+    write = _per_kernel(_counter_rows(dirs[1]), "WRITE_SIZE")
+    req = None
+    if len(dirs) > 2:
+        rows = _counter_rows(dirs[2])
+        req = {c: _per_kernel(rows, c) for c in ("TCC_EA0_RDREQ_32B", "TCC_EA0_RDREQ_64B", "TCC_EA0_RDREQ_128B")}
     calib_bytes = CALIB_FLOATS * 4
 
-    def calib(table):
-        cand = [max(v) for k, v in table.items() if "hom::" not in k and "elementwise" in k.lower()]
+    def calib_name(table):
+        cand = [k for k in table if "hom::" not in k and "elementwise" in k.lower()]
         if not cand:
             raise SystemExit("calibration kernel missing: run bench.py with --calib-copy")
-        return calib_bytes / (max(cand) * 1024.0)
+        return max(cand, key=lambda k: max(table[k]))
 
-    fscale, wscale = calib(fetch), calib(write)
+    fscale = calib_bytes / (max(fetch[calib_name(fetch)]) * 1024.0)
+    wscale = calib_bytes / (max(write[calib_name(write)]) * 1024.0)
+
+    def req_bytes(name):
+        if req is None or name not in req["TCC_EA0_RDREQ_32B"]:
+            return None
+        return float(32 * np.mean(req["TCC_EA0_RDREQ_32B"][name]) + 64 * np.mean(req["TCC_EA0_RDREQ_64B"][name])
+                     + 128 * np.mean(req["TCC_EA0_RDREQ_128B"][name]))
+
     h = kernel_source_hash()
     lines = [f"# HBM traffic of the pipeline kernels, {n}^3 fibre composite", "",
              f"command: {command}", f"kernel source hash: {h}",
-             f"calibration: 1 GiB read + 1 GiB write kernel; FETCH_SIZE scale {fscale:.4f}, "
-             f"WRITE_SIZE scale {wscale:.4f}", "",
-             "| kernel | launches | FETCH MB/launch | WRITE MB/launch | HBM MB/launch (scaled) |",
-             "|---|---|---|---|---|"]
+             f"calibration kernel: 1 GiB read + 1 GiB write; FETCH_SIZE scale {fscale:.4f}, "
+             f"WRITE_SIZE scale {wscale:.4f}"]
+    if req is not None:
+        cn = calib_name(req["TCC_EA0_RDREQ_128B"])
+        lines.append(f"calibration kernel read bytes by request size: {req_bytes(cn) / calib_bytes:.4f} x 1 GiB")
+    lines += ["", "MB per launch, averaged over the launches of the mechanical instance:", "",
+              "| kernel | launches | FETCH raw | WRITE raw | HBM (scaled FETCH + scaled WRITE) | reads by request size |",
+              "|---|---|---|---|---|---|"]
     for kind, name in PMC_KINDS.items():
         groups = [k for k in fetch if name in k and "hom::" in k]
         if not groups:
@@ -235,13 +256,74 @@ def pmc_summary(fetch_dir, write_dir, n, command):
         f = float(np.mean(fetch[main_name])) * 1024.0
         w = float(np.mean(write.get(main_name, [0.0]))) * 1024.0
         tot = f * fscale + w * wscale
+        rb = req_bytes(main_name)
         rec = {"source_hash": h, "bytes_per_launch": tot, "fetch_bytes_raw": f, "write_bytes_raw": w,
-               "fetch_scale": fscale, "write_scale": wscale, "launches": len(fetch[main_name]),
-               "kernel": main_name, "command": command}
+               "fetch_scale": fscale, "write_scale": wscale, "read_bytes_by_request_size": rb,
+               "launches": len(fetch[main_name]), "kernel": main_name, "command": command}
         with open(os.path.join(ROOT, "profiles", f"{kind}_fibres{n}_pmc.json"), "w") as fo:
             json.dump(rec, fo, indent=1)
-        lines.append(f"| {kind} | {len(fetch[main_name])} | {f / 1e6:.1f} | {w / 1e6:.1f} | {tot / 1e6:.1f} |")
+        rbs = f"{rb / 1e6:.1f}" if rb is not None else "-"
+        lines.append(f"| {kind} | {len(fetch[main_name])} | {f / 1e6:.1f} | {w / 1e6:.1f} | {tot / 1e6:.1f} | {rbs} |")
     with open(os.path.join(ROOT, "profiles", f"pipeline_fibres{n}_hbm_traffic.md"), "w") as fo:
+        fo.write("\n".join(lines) + "\n")
+    print("\n".join(lines))
+
+
+def copy_probe(reps=20):
+    """Streaming rate of a plain 1 GiB read + 1 GiB write kernel (torch's
+    elementwise multiply), GB/s: what a pure streaming kernel reaches here."""
+    import torch
+    a = torch.ones(CALIB_FLOATS, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    for _ in range(3):
+        torch.mul(a, 1.0, out=b)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        torch.mul(a, 1.0, out=b)
+    e1.record()
+    e1.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    del a, b
+    return round(2 * CALIB_FLOATS * 4 / (ms * 1e-3) / 1e9, 1)
+
+
+def network_only(rows=65536, reps=50):
+    """Two-network surrogate inference (random weights: the speed does not
+    depend on their values) on one 65,536-row batch; prints ms and TFLOP/s."""
+    import torch
+
+    from paper_2109_14403_amd import hom
+    nets = [hom.MLP(32, 10, seed=s) for s in (0, 1)]
+    x = torch.randn(rows, 32, device="cuda")
+    for _ in range(5):
+        hom.surrogate_infer(nets[0], nets[1], x, 0.0, 1.0)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        hom.surrogate_infer(nets[0], nets[1], x, 0.0, 1.0)
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) / reps * 1e3
+    flops = 2 * rows * 2 * NETWORK_PARAMS_MACS
+    print(json.dumps({"rows": rows, "infer_ms": round(ms, 4), "network_tflops": round(flops / (ms * 1e-3) / 1e12, 2)}))
+
+
+def mfma_summary(folder, command):
+    """MFMA busy fraction of the network kernels from one rocprofv3 --pmc run
+    with SQ_VALU_MFMA_BUSY_CYCLES and GRBM_GUI_ACTIVE (1024 SIMDs)."""
+    rows = _counter_rows(folder)
+    busy = _per_kernel(rows, "SQ_VALU_MFMA_BUSY_CYCLES")
+    active = _per_kernel(rows, "GRBM_GUI_ACTIVE")
+    lines = ["# MFMA utilisation of the surrogate network kernels (65,536-row two-network inference)", "",
+             f"command: {command}", "",
+             "MfmaUtil = SQ_VALU_MFMA_BUSY_CYCLES / (GRBM_GUI_ACTIVE x 1024 SIMDs)", "",
+             "| kernel | launches | MfmaUtil % |", "|---|---|---|"]
+    for k in sorted(busy):
+        if "mlp" not in k or k not in active:
+            continue
+        u = float(np.mean(busy[k])) / (float(np.mean(active[k])) * 1024) * 100
+        lines.append(f"| {k[:70]} | {len(busy[k])} | {u:.1f} |")
+    with open(os.path.join(ROOT, "profiles", "mlp_infer65536_mfma.md"), "w") as fo:
         fo.write("\n".join(lines) + "\n")
     print("\n".join(lines))
 
@@ -257,12 +339,21 @@ def main():
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--no-surrogate", action="store_true")
     ap.add_argument("--calib-copy", action="store_true", help="run a 1 GiB device copy (PMC calibration)")
-    ap.add_argument("--pmc-summary", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
-                    help="summarize two rocprofv3 --pmc output folders into profiles/ (no GPU needed)")
-    ap.add_argument("--pmc-command", default="", help="command line recorded in the --pmc-summary output")
+    ap.add_argument("--pmc-summary", nargs="+", metavar="DIR",
+                    help="summarize rocprofv3 --pmc output folders (FETCH_SIZE, WRITE_SIZE[, request sizes]) "
+                         "into profiles/ (no GPU needed)")
+    ap.add_argument("--mfma-summary", metavar="DIR", help="summarize an MFMA --pmc run into profiles/")
+    ap.add_argument("--pmc-command", default="", help="command line recorded in the summary")
+    ap.add_argument("--network-only", action="store_true", help="time the surrogate network inference alone")
     args = ap.parse_args()
     if args.pmc_summary:
-        pmc_summary(args.pmc_summary[0], args.pmc_summary[1], args.n, args.pmc_command)
+        pmc_summary(args.pmc_summary, args.n, args.pmc_command)
+        return
+    if args.mfma_summary:
+        mfma_summary(args.mfma_summary, args.pmc_command)
+        return
+    if args.network_only:
+        network_only()
         return
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1"}))
@@ -341,19 +432,23 @@ def main():
         if mix is not None and launches == n_eval + n_cg:
             n_first = max(n_eval - 1, 0)       # every Newton step but the converged one runs CG
             byt = (n_eval * mix[0] + n_first * mix[1] + (n_cg - n_first) * mix[2]) / launches
-        traffic = None
+        traffic = traffic_req = None
         pmc_path = os.path.join(ROOT, "profiles", f"{dom}_fibres{n}_pmc.json")
         if os.path.exists(pmc_path):
             pm = json.load(open(pmc_path))
-            if pm.get("source_hash") == kernel_source_hash():
+            if pm.get("source_hash") == kernel_source_hash():   # counters of the current kernels only
                 traffic = pm.get("bytes_per_launch")
+                if pm.get("read_bytes_by_request_size") is not None:
+                    traffic_req = pm["read_bytes_by_request_size"] + pm["write_bytes_raw"] * pm["write_scale"]
         if byt is not None:
             ach = byt / avg_s / 1e9
             roof = {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                    "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": traffic, "kernel": dom,
+                    "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": traffic,
+                    "traffic_request_sized": traffic_req, "kernel": dom,
                     "avg_launch_ms": round(avg_s * 1e3, 4), "algorithmic_bytes": byt}
 
     ctx.close()
+    copy_gbs = copy_probe()
     batch = None
     if not args.no_batch:
         batch = batch_bench()
@@ -378,7 +473,7 @@ def main():
                    "increments": f"{args.warmup}..{total - 1} of 50"},
         "thermal_voxel_iters_per_s": round(tpipes * nvox / elapsed, 1),
         "newton_per_step": newton / args.steps, "krylov_per_step": krylov / args.steps,
-        "roofline": roof, "cpu_baseline": cpu, "batch": batch, "surrogate": surr,
+        "roofline": roof, "copy_probe_gbs": copy_gbs, "cpu_baseline": cpu, "batch": batch, "surrogate": surr,
     }
     if kstats:
         line["kernel_ms"] = {k: [v[0], round(v[1], 3)] for k, v in kstats.items() if v[0]}

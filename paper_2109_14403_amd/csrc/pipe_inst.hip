@@ -17,7 +17,7 @@ LaunchInfo xfwd_c(const Pipe<T>& a, hipStream_t s, bool dry) {
   LaunchInfo li;
   li.threads = G * L;
   li.blocks = a.nprob * ((a.ny * a.nz + NL - 1) / NL);
-  li.lds = (size_t)(N + N * L) * sizeof(c2<T>);
+  li.lds = (size_t)xfwd_lds_elems<N, NL, C>() * sizeof(c2<T>);
   {
     static bool attr = false;
     if (!attr && li.lds > 65536) {
@@ -38,12 +38,10 @@ LaunchInfo xinv_c(const Pipe<T>& a, hipStream_t s, bool dry) {
   constexpr int G = N / Plan<N>::M;
   constexpr int NP = (C + 1) / 2;
   constexpr int L = NL * NP;
-  constexpr int H = N / 2 + 1;
-  constexpr int B = (NL * H * C > N * L) ? NL * H * C : N * L;
   LaunchInfo li;
   li.threads = G * L;
   li.blocks = a.nprob * ((a.ny * a.nz + NL - 1) / NL);
-  li.lds = (size_t)(N + B) * sizeof(c2<T>);
+  li.lds = (size_t)xinv_lds_elems<N, NL, C>() * sizeof(c2<T>);
   {
     static bool attr = false;
     if (!attr && li.lds > 65536) {
@@ -65,7 +63,7 @@ LaunchInfo ypass_c(const Pipe<T>& a, int inverse, hipStream_t s, bool dry) {
   LaunchInfo li;
   li.threads = G * TX * C;
   li.blocks = a.nprob * a.nz * ((a.P + TX - 1) / TX);
-  li.lds = (size_t)(N + N * TX * C) * sizeof(c2<T>);
+  li.lds = (size_t)tile_lds_elems<N, TX, C>() * sizeof(c2<T>);
   {
     static bool attr = false;
     if (!attr && li.lds > 65536) {
@@ -87,7 +85,7 @@ LaunchInfo zgreen_c(const Pipe<T>& a, hipStream_t s, bool dry) {
   LaunchInfo li;
   li.threads = G * TX * C;
   li.blocks = a.nprob * a.ny * ((a.P + TX - 1) / TX);
-  li.lds = (size_t)(N + N * TX * C) * sizeof(c2<T>);
+  li.lds = (size_t)tile_lds_elems<N, TX, C>() * sizeof(c2<T>);
   {
     static bool attr = false;
     if (!attr && li.lds > 65536) {

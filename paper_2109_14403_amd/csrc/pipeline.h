@@ -128,6 +128,30 @@ __device__ __forceinline__ void st4(double* p, const double (&v)[4]) {
   reinterpret_cast<double2*>(p)[1] = make_double2(v[2], v[3]);
 }
 
+// Staging layout of the x passes between the per-voxel phases and the line
+// transforms: one row of SP complex values per transform lane, x fastest. A
+// thread's four consecutive voxels are 32 contiguous bytes, and the odd pitch
+// puts neighbouring transform lanes on different LDS banks.
+constexpr int xstage_pitch(int n) { return n + 1; }
+
+// Dynamic LDS of the pipeline kernels in complex values: N twiddles, then the
+// work buffer. The launchers size their launches from these, so kernel and
+// launch cannot disagree.
+template <int N, int NL, int C>
+constexpr int xfwd_lds_elems() {
+  return N + NL * ((C + 1) / 2) * xstage_pitch(N);  // staging rows (>= N * L, the exchange)
+}
+template <int N, int NL, int C>
+constexpr int xinv_lds_elems() {
+  // staged half spectra, or the staging rows (>= N * L, the exchange)
+  return N + (NL * (N / 2 + 1) * C > NL * ((C + 1) / 2) * xstage_pitch(N) ? NL * (N / 2 + 1) * C
+                                                                            : NL * ((C + 1) / 2) * xstage_pitch(N));
+}
+template <int N, int TX, int C>
+constexpr int tile_lds_elems() {
+  return N + N * TX * C;  // y and z passes: the transform exchange of TX * C lines
+}
+
 // ---------------------------------------------------------------------------
 // x forward: pre-operation + packed real-to-complex transforms
 // ---------------------------------------------------------------------------
@@ -138,6 +162,8 @@ __global__ void __launch_bounds__((N / Plan<N>::M) * NL * ((C + 1) / 2)) k_xfwd(
   constexpr int NP = (C + 1) / 2;
   constexpr int L = NL * NP;
   constexpr int H = N / 2 + 1;
+  constexpr int SP = xstage_pitch(N);
+  static_assert(xfwd_lds_elems<N, NL, C>() - N >= L * SP && L * SP >= N * L, "x-forward LDS buffer too small");
   extern __shared__ __align__(16) unsigned char smem_raw[];
   c2<T>* tw = reinterpret_cast<c2<T>*>(smem_raw);
   c2<T>* buf = tw + N;
@@ -262,9 +288,9 @@ __global__ void __launch_bounds__((N / Plan<N>::M) * NL * ((C + 1) / 2)) k_xfwd(
       }
     }
 #pragma unroll
-    for (int j = 0; j < 4; ++j)
+    for (int q = 0; q < NP; ++q)
 #pragma unroll
-      for (int q = 0; q < NP; ++q) buf[(xv + j) * L + li * NP + q] = mk(out[j][2 * q], out[j][2 * q + 1]);
+      for (int j = 0; j < 4; ++j) buf[(li * NP + q) * SP + xv + j] = mk(out[j][2 * q], out[j][2 * q + 1]);
   }
   if (cg) {  // uniform per block
     double s[1] = {pcp};
@@ -277,7 +303,7 @@ __global__ void __launch_bounds__((N / Plan<N>::M) * NL * ((C + 1) / 2)) k_xfwd(
   const int t = tid / L;
   c2<T> r[M];
 #pragma unroll
-  for (int m = 0; m < M; ++m) r[m] = buf[(t + G * m) * L + l];
+  for (int m = 0; m < M; ++m) r[m] = buf[l * SP + t + G * m];
   Plan<N>::run(r, t, tw, buf, L, l, true);
   __syncthreads();
 #pragma unroll
@@ -319,6 +345,16 @@ __global__ void __launch_bounds__((N / Plan<N>::M) * NL * ((C + 1) / 2)) k_xfwd(
   }
 }
 
+// Work-groups are dispatched to the 8 XCDs round-robin (work-group i to XCD
+// i mod 8), each XCD with its own L2. This bijection of [0, n) gives every XCD
+// a contiguous range of tiles, so neighbouring kx tiles, which share 128-byte
+// lines when a tile row is not a whole number of lines, meet in one L2.
+__device__ __forceinline__ int xcd_remap(int i, int n) {
+  const int q = n >> 3, rem = n & 7;
+  const int x = i & 7, k = i >> 3;
+  return x * q + min(x, rem) + k;
+}
+
 // ---------------------------------------------------------------------------
 // y pass (forward or inverse) on tiles of TX kx columns
 // ---------------------------------------------------------------------------
@@ -327,14 +363,16 @@ __global__ void __launch_bounds__((N / Plan<N>::M) * TX * C) k_ypass(Pipe<T> a, 
   constexpr int M = Plan<N>::M;
   constexpr int G = N / M;
   constexpr int L = TX * C;
+  static_assert(tile_lds_elems<N, TX, C>() - N >= N * L, "tile LDS buffer too small");
   extern __shared__ __align__(16) unsigned char smem_raw[];
   c2<T>* tw = reinterpret_cast<c2<T>*>(smem_raw);
   c2<T>* buf = tw + N;
   const int P = a.P;
   const int nkb = (P + TX - 1) / TX;
   const int bpp = a.nz * nkb;
-  const int prob = blockIdx.x / bpp;
-  const int b = blockIdx.x % bpp;
+  const int bid = xcd_remap(blockIdx.x, gridDim.x);
+  const int prob = bid / bpp;
+  const int b = bid % bpp;
   if (!pipeline_mode(a.ctl[prob].mode)) return;
   const int z = b / nkb;
   const int kb = b % nkb;
@@ -369,14 +407,16 @@ __global__ void __launch_bounds__((N / Plan<N>::M) * TX * C) k_zgreen(Pipe<T> a)
   constexpr int M = Plan<N>::M;
   constexpr int G = N / M;
   constexpr int L = TX * C;
+  static_assert(tile_lds_elems<N, TX, C>() - N >= N * L, "tile LDS buffer too small");
   extern __shared__ __align__(16) unsigned char smem_raw[];
   c2<T>* tw = reinterpret_cast<c2<T>*>(smem_raw);
   c2<T>* buf = tw + N;
   const int P = a.P;
   const int nkb = (P + TX - 1) / TX;
   const int bpp = a.ny * nkb;
-  const int prob = blockIdx.x / bpp;
-  const int b = blockIdx.x % bpp;
+  const int bid = xcd_remap(blockIdx.x, gridDim.x);
+  const int prob = bid / bpp;
+  const int b = bid % bpp;
   if (!pipeline_mode(a.ctl[prob].mode)) return;
   const int ky = b / nkb;
   const int kb = b % nkb;
@@ -451,6 +491,10 @@ __global__ void __launch_bounds__((N / Plan<N>::M) * NL * ((C + 1) / 2)) k_xinv(
   constexpr int NP = (C + 1) / 2;
   constexpr int L = NL * NP;
   constexpr int H = N / 2 + 1;
+  constexpr int SP = xstage_pitch(N);
+  static_assert(xinv_lds_elems<N, NL, C>() - N >= L * SP && xinv_lds_elems<N, NL, C>() - N >= NL * H * C &&
+                    L * SP >= N * L,
+                "x-inverse LDS buffer too small");
   extern __shared__ __align__(16) unsigned char smem_raw[];
   c2<T>* tw = reinterpret_cast<c2<T>*>(smem_raw);
   c2<T>* buf = tw + N;  // holds the staged half spectra first, then the line FFTs
@@ -511,7 +555,7 @@ __global__ void __launch_bounds__((N / Plan<N>::M) * NL * ((C + 1) / 2)) k_xinv(
   Plan<N>::run(r, t, tw, buf, L, l, true);
   __syncthreads();
 #pragma unroll
-  for (int m = 0; m < M; ++m) buf[(t + G * m) * L + l] = conjg(r[m]);
+  for (int m = 0; m < M; ++m) buf[l * SP + t + G * m] = conjg(r[m]);
   __syncthreads();
 
   const long long nv = a.nvox;
@@ -529,7 +573,7 @@ __global__ void __launch_bounds__((N / Plan<N>::M) * NL * ((C + 1) / 2)) k_xinv(
       T g[4];
 #pragma unroll
       for (int j = 0; j < 4; ++j) {
-        const c2<T> z = buf[(xv + j) * L + lj * NP + (c >> 1)];
+        const c2<T> z = buf[(lj * NP + (c >> 1)) * SP + xv + j];
         g[j] = ((c & 1) ? z.y : z.x) * scale;
       }
       const long long o = fo + c * nv + v;

@@ -6,6 +6,10 @@
 
 namespace hom {
 
+// Per-voxel slots of the PA66 increment data: deviatoric branch history sum
+// (6), spherical history sum, plastic increment of the latest evaluation.
+constexpr int HIST_SLOTS = 8;
+
 // Arguments of the pointwise kernels of one group.
 template <typename T>
 struct Pt {
@@ -22,7 +26,7 @@ struct Pt {
   T* tn;
   double* state;            // [prob][nstate][nvox] (mechanics with a PA66 phase)
   int nstate;
-  double* hist;             // [prob][7][nvox] PA66 branch history sums of the increment
+  double* hist;             // [prob][HIST_SLOTS][nvox] PA66 branch history sums of the increment, last dp
   Ctl* ctl;
   const ProbInc* inc;
   double* part;

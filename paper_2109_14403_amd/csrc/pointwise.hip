@@ -52,12 +52,16 @@ __device__ __forceinline__ void pow_m(double x, double m, double& xm, double& xm
   }
 }
 
+// guess: a previous root for nearby data (warm start), used if inside the bracket
 __device__ __forceinline__ double pa66_solve_dp(const ProbInc& in, double seq, double ep, double f, double G3,
-                                                double& dgd) {
+                                                double guess, double& dgd) {
   double lo = 0.0, hi = f / G3;
-  double d = 0.5 * hi;
+  double d = (guess > lo && guess < hi) ? guess : 0.5 * hi;
   const double c = in.ccoef, sY = in.sY, m = in.mexp, hk = in.hk, nh = in.nh;
   double A = 0.0, hp = INFINITY;
+  // step tolerance: the stress correction 3 Gbar dp moves by < 1e-14 seq_tr
+  // (a relative test on dp alone can sit below the rounding noise of g)
+  const double dtol = 1e-14 * seq / G3;
   for (int it = 0; it < 80; ++it) {
     const double e = ep + d;
     const double he = e > 0.0 ? hk * powpos(e, nh) : 0.0;  // H(eps_p + d)
@@ -72,11 +76,15 @@ __device__ __forceinline__ double pa66_solve_dp(const ProbInc& in, double seq, d
     hp = e > 0.0 ? nh * he / e : INFINITY;  // H'
     A = c * m * xm1 / sY;
     const double gd = 1.0 + A * (G3 + hp);
-    double dn = d - gv / gd;
-    if (!(dn > lo && dn < hi)) dn = 0.5 * (lo + hi);
-    const bool done = fabs(dn - d) <= 1e-15 * dn || hi - lo <= 1e-16 * hi;
-    d = dn;
-    if (done) break;
+    const double dn = d - gv / gd;
+    // converged: accept the Newton point (it may sit on the bracket end the
+    // step came from, so test before the bracket safeguard)
+    if (gv == 0.0 || fabs(dn - d) <= dtol) {
+      d = fmin(fmax(dn, lo), hi);
+      break;
+    }
+    d = (dn > lo && dn < hi) ? dn : 0.5 * (lo + hi);
+    if (hi - lo <= dtol) break;
   }
   // d dp / d seq_tr at the root (from the last step: d moved by <= 1e-15 relative)
   dgd = A > 0.0 ? A / (1.0 + A * (G3 + hp)) : 0.0;
@@ -110,12 +118,15 @@ __device__ __forceinline__ void pa66_history(const ProbInc& in, const double* st
 }
 
 // Trial / final evaluation. If `hist` is non-null (trial only) the branch
-// history sums are read from it ([7][ss]: hd, hs), else computed from the
-// state. If `st_out` is non-null the new internal variables are written
-// there and the dissipation and coupling computed.
+// history sums are read from it ([HIST_SLOTS][ss]: hd, hs, dp), else computed
+// from the state. `dp_slot`, if non-null, holds the plastic increment of the
+// voxel's previous evaluation in this increment (negative: none), the start
+// of the scalar Newton iteration; a trial evaluation stores its result there.
+// If `st_out` is non-null the new internal variables are written there and
+// the dissipation and coupling computed.
 __device__ void pa66_point(const ProbInc& in, const double* eps, const double* st, long long ss, double* st_out,
                            const double* eps_n, PaOut& o, double* diss, double* coup,
-                           const double* hist = nullptr) {
+                           const double* hist = nullptr, double* dp_slot = nullptr) {
   const double tr3 = (eps[0] + eps[1] + eps[2]) * (1.0 / 3.0);
   const double em = tr3 - in.ph[in.pa_phase].alpha_dth;
   double d[6];
@@ -151,7 +162,7 @@ __device__ void pa66_point(const ProbInc& in, const double* eps, const double* s
   const double G3 = 1.5 * in.Gbar2;
   if (f > 0.0 && snrm > 0.0) {
     double dgd;
-    dp = pa66_solve_dp(in, seq, ep, f, G3, dgd);
+    dp = pa66_solve_dp(in, seq, ep, f, G3, dp_slot ? *dp_slot : -1.0, dgd);
     th1 = 1.0 - G3 * dp / seq;
     cp = 1.0 - G3 * dgd;
   }
@@ -167,7 +178,10 @@ __device__ void pa66_point(const ProbInc& in, const double* eps, const double* s
   o.a = in.Gbar2 * th1;
   o.b = in.Gbar2 * (cp - th1);
   o.dp = dp;
-  if (!st_out) return;
+  if (!st_out) {
+    if (dp_slot) *dp_slot = dp;
+    return;
+  }
 
   // ---- commit: new internal variables, dissipation, coupling ------------
   const double dt = in.dt;
@@ -280,9 +294,9 @@ __global__ void __launch_bounds__(PT_THREADS) k_eval(Pt<T> a) {
 #pragma unroll
         for (int c = 0; c < 6; ++c) ed[c] = (double)e[c];
         const double* st = a.state + (long long)prob * a.nstate * nv + v;
-        const double* hs = a.hist ? a.hist + (long long)prob * 7 * nv + v : nullptr;
+        double* hs = a.hist ? a.hist + (long long)prob * HIST_SLOTS * nv + v : nullptr;
         PaOut o;
-        pa66_point(in, ed, st, nv, nullptr, nullptr, o, nullptr, nullptr, hs);
+        pa66_point(in, ed, st, nv, nullptr, nullptr, o, nullptr, nullptr, hs, hs ? hs + 7 * nv : nullptr);
 #pragma unroll
         for (int c = 0; c < 6; ++c) sg[c] = o.sig[c];
         ca = o.a;
@@ -329,10 +343,11 @@ __global__ void __launch_bounds__(PT_THREADS) k_history(Pt<T> a) {
     if (phase[v] != in.pa_phase) continue;
     double hd[6], hs;
     pa66_history(in, a.state + (long long)prob * a.nstate * nv + v, nv, hd, hs);
-    double* h = a.hist + (long long)prob * 7 * nv + v;
+    double* h = a.hist + (long long)prob * HIST_SLOTS * nv + v;
 #pragma unroll
     for (int c = 0; c < 6; ++c) h[c * nv] = hd[c];
     h[6 * nv] = hs;
+    h[7 * nv] = -1.0;  // no plastic increment known yet
   }
 }
 
@@ -362,8 +377,9 @@ __global__ void __launch_bounds__(PT_THREADS) k_commit(Pt<T> a) {
       double sg[6], dis = 0.0, cpl;
       if (ph == in.pa_phase) {
         double* st = a.state + (long long)prob * a.nstate * nv + v;
+        double* dps = a.hist ? a.hist + (long long)prob * HIST_SLOTS * nv + v + 7 * nv : nullptr;
         PaOut o;
-        pa66_point(in, e, st, nv, st, en, o, &dis, &cpl);
+        pa66_point(in, e, st, nv, st, en, o, &dis, &cpl, nullptr, dps);
 #pragma unroll
         for (int c = 0; c < 6; ++c) sg[c] = o.sig[c];
       } else {
@@ -408,28 +424,40 @@ __global__ void __launch_bounds__(PT_THREADS) k_commit(Pt<T> a) {
 // ---------------------------------------------------------------------------
 // per-problem reductions and state transitions (one block per problem)
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ void sum_parts(const double* part, int maxblk, int nblk, int prob, int nk, double* out,
-                                          double* red) {
-  // fixed-order sum over blocks for each of nk entries
-  for (int k = 0; k < nk; ++k) {
-    double s = 0.0;
-    for (int b = threadIdx.x; b < nblk; b += blockDim.x) s += part[((long long)prob * maxblk + b) * NPART + k];
-    double v[1] = {s};
-    block_sum<1>(v, red);
-    if (threadIdx.x == 0) out[k] = v[0];
-    __syncthreads();
+constexpr int RED_THREADS = 1024;
+
+// Fixed-order sums of the first NK entries of every block's partial row, in
+// one pass over the rows (each row's entries are contiguous).
+template <int NK>
+__device__ __forceinline__ void sum_parts(const double* part, int maxblk, int nblk, int prob, double* out,
+                                          double* red /* >= NK * 16 */) {
+  double v[NK];
+#pragma unroll
+  for (int k = 0; k < NK; ++k) v[k] = 0.0;
+  const double* base = part + (long long)prob * maxblk * NPART;
+#pragma unroll 4
+  for (int b = threadIdx.x; b < nblk; b += blockDim.x) {
+    const double* row = base + (long long)b * NPART;
+#pragma unroll
+    for (int k = 0; k < NK; ++k) v[k] += row[k];
   }
+  block_sum<NK>(v, red);
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int k = 0; k < NK; ++k) out[k] = v[k];
+  }
+  __syncthreads();
 }
 
-__global__ void __launch_bounds__(PT_THREADS) k_reduce_a(Ctl* ctl, const double* part, int maxblk, int nblk,
-                                                          Limits lim) {
-  __shared__ double red[16];
+__global__ void __launch_bounds__(RED_THREADS) k_reduce_a(Ctl* ctl, const double* part, int maxblk, int nblk,
+                                                           Limits lim) {
+  __shared__ double red[2 * 16];
   __shared__ double s[2];
   const int prob = blockIdx.x;
   Ctl& c = ctl[prob];
   const int mode = c.mode;
   if (!(mode == M_EVAL || mode == M_BASIC || (mode == M_CG && c.cg_ready))) return;
-  sum_parts(part, maxblk, nblk, prob, 2, s, red);
+  sum_parts<2>(part, maxblk, nblk, prob, s, red);
   if (threadIdx.x != 0) return;
   c.pipelines += 1;
   if (mode == M_CG) {
@@ -495,13 +523,13 @@ __global__ void __launch_bounds__(PT_THREADS) k_reduce_a(Ctl* ctl, const double*
 // compatible direction p, p.C p equals p.A p = p.P[C p] because P is an
 // orthogonal projector, so alpha is known before the inverse transforms and
 // the x-inverse pass can apply the CG update itself.
-__global__ void __launch_bounds__(PT_THREADS) k_reduce_alpha(Ctl* ctl, const double* part, int maxblk, int nblk) {
+__global__ void __launch_bounds__(RED_THREADS) k_reduce_alpha(Ctl* ctl, const double* part, int maxblk, int nblk) {
   __shared__ double red[16];
   __shared__ double s[1];
   const int prob = blockIdx.x;
   Ctl& c = ctl[prob];
   if (c.mode != M_CG || c.cg_ready) return;
-  sum_parts(part, maxblk, nblk, prob, 1, s, red);
+  sum_parts<1>(part, maxblk, nblk, prob, s, red);
   if (threadIdx.x != 0) return;
   const double pap = s[0];
   if (!(pap > 0.0) || !isfinite(pap)) {
@@ -513,14 +541,14 @@ __global__ void __launch_bounds__(PT_THREADS) k_reduce_alpha(Ctl* ctl, const dou
   c.cg_ready = 1;
 }
 
-__global__ void __launch_bounds__(PT_THREADS) k_reduce_out(Ctl* ctl, const double* part, int maxblk, int nblk,
-                                                            int nk, double scale) {
-  __shared__ double red[16];
+__global__ void __launch_bounds__(RED_THREADS) k_reduce_out(Ctl* ctl, const double* part, int maxblk, int nblk,
+                                                             int nk, double scale) {
+  __shared__ double red[NPART * 16];
   __shared__ double s[NPART];
   const int prob = blockIdx.x;
   Ctl& c = ctl[prob];
   if (c.status != 1) return;
-  sum_parts(part, maxblk, nblk, prob, nk, s, red);
+  sum_parts<NPART>(part, maxblk, nblk, prob, s, red);
   if (threadIdx.x == 0)
     for (int k = 0; k < nk; ++k) c.out[k] = s[k] * scale;
 }
@@ -555,14 +583,14 @@ void launch_commit(const Pt<T>& a, int C, hipStream_t s) {
     hipLaunchKernelGGL((k_commit<T, 3>), dim3(a.nprob * a.bpp), dim3(PT_THREADS), 0, s, a);
 }
 void launch_reduce_a(Ctl* ctl, const double* part, int maxblk, int nblk, int nprob, Limits lim, hipStream_t s) {
-  hipLaunchKernelGGL(k_reduce_a, dim3(nprob), dim3(PT_THREADS), 0, s, ctl, part, maxblk, nblk, lim);
+  hipLaunchKernelGGL(k_reduce_a, dim3(nprob), dim3(RED_THREADS), 0, s, ctl, part, maxblk, nblk, lim);
 }
 void launch_reduce_alpha(Ctl* ctl, const double* part, int maxblk, int nblk, int nprob, hipStream_t s) {
-  hipLaunchKernelGGL(k_reduce_alpha, dim3(nprob), dim3(PT_THREADS), 0, s, ctl, part, maxblk, nblk);
+  hipLaunchKernelGGL(k_reduce_alpha, dim3(nprob), dim3(RED_THREADS), 0, s, ctl, part, maxblk, nblk);
 }
 void launch_reduce_out(Ctl* ctl, const double* part, int maxblk, int nblk, int nprob, int nk, double scale,
                        hipStream_t s) {
-  hipLaunchKernelGGL(k_reduce_out, dim3(nprob), dim3(PT_THREADS), 0, s, ctl, part, maxblk, nblk, nk, scale);
+  hipLaunchKernelGGL(k_reduce_out, dim3(nprob), dim3(RED_THREADS), 0, s, ctl, part, maxblk, nblk, nk, scale);
 }
 
 #define HOM_INST_PT(T)                                                  \

@@ -311,7 +311,7 @@ struct Group {
     spec = dalloc<c2<T>>(spec_count);
     if (with_state && nstate > 0) {
       state = dalloc<double>((size_t)nstate * nm);
-      hist = dalloc<double>((size_t)7 * nm);
+      hist = dalloc<double>((size_t)HIST_SLOTS * nm);
     }
     ctl_m = dalloc<Ctl>(nprob);
     ctl_t = dalloc<Ctl>(nprob);
@@ -926,7 +926,7 @@ void eval_law(const hom_law& law, int64_t count, const double* eps, const double
   G.tn = G.dalloc<double>(6 * count);
   if (G.nstate) {
     G.state = G.dalloc<double>(G.nstate * count);
-    G.hist = G.dalloc<double>(7 * count);
+    G.hist = G.dalloc<double>(HIST_SLOTS * count);
   }
   G.ctl_m = G.dalloc<Ctl>(1);
   G.inc_d = G.dalloc<ProbInc>(1);
