@@ -27,8 +27,11 @@ sys.path.insert(0, ROOT)
 
 METRIC = "voxel-iters/s coupled FFT solve; surrogate vs FFT Gauss-pts/s at 1e-3 err"
 HBM_PEAK_GBS = 8000.0
+# sources whose change makes stored counter data stale (kernels and launch shapes)
 KERNEL_SOURCES = ("paper_2109_14403_amd/csrc/pipeline.h", "paper_2109_14403_amd/csrc/fft_core.h",
-                  "paper_2109_14403_amd/csrc/pointwise.hip", "paper_2109_14403_amd/csrc/common.h")
+                  "paper_2109_14403_amd/csrc/pointwise.hip", "paper_2109_14403_amd/csrc/pointwise.h",
+                  "paper_2109_14403_amd/csrc/common.h", "paper_2109_14403_amd/csrc/pipe_inst.hip",
+                  "paper_2109_14403_amd/csrc/pipe_launch.h")
 
 
 CALIB_FLOATS = 1 << 28
@@ -206,7 +209,16 @@ def _per_kernel(rows, counter):
     return out
 
 
-def pmc_summary(dirs, n, command):
+def _timed_launches(log_path):
+    """Launches of each pipeline kernel in the timed increments of a bench run,
+    from the JSON line it printed."""
+    with open(log_path) as f:
+        line = [l for l in f if l.startswith("{") and '"metric"' in l][-1]
+    d = json.loads(line)
+    return int(round((d["newton_per_step"] + d["krylov_per_step"]) * d["steps"]))
+
+
+def pmc_summary(dirs, n, command, log_path=None):
     """Turn rocprofv3 --pmc runs into HBM bytes per launch of each mechanical
     pipeline kernel. dirs = (FETCH_SIZE run, WRITE_SIZE run[, request-size
     run]). Each counter is scaled by what it reads for the 1 GiB calibration
@@ -248,15 +260,27 @@ def pmc_summary(dirs, n, command):
     lines += ["", "MB per launch, averaged over the launches of the mechanical instance:", "",
               "| kernel | launches | FETCH raw | WRITE raw | HBM (scaled FETCH + scaled WRITE) | reads by request size |",
               "|---|---|---|---|---|---|"]
+    last = _timed_launches(log_path) if log_path else None
+    if last:
+        lines.insert(5, f"averages over the last {last} launches of each kernel: the timed increments")
     for kind, name in PMC_KINDS.items():
         groups = [k for k in fetch if name in k and "hom::" in k]
         if not groups:
             continue
         main_name = max(groups, key=lambda k: len(fetch[k]))    # the mechanical instance
-        f = float(np.mean(fetch[main_name])) * 1024.0
-        w = float(np.mean(write.get(main_name, [0.0]))) * 1024.0
+        nl = last * (2 if kind == "ypass" else 1) if last else None   # the y kernel runs forward and inverse
+
+        def avg(table, nm):
+            v = table.get(nm, [0.0])
+            return float(np.mean(v[-nl:] if nl else v))
+
+        f = avg(fetch, main_name) * 1024.0
+        w = avg(write, main_name) * 1024.0
         tot = f * fscale + w * wscale
-        rb = req_bytes(main_name)
+        rb = None
+        if req is not None and main_name in req["TCC_EA0_RDREQ_32B"]:
+            rb = 32 * avg(req["TCC_EA0_RDREQ_32B"], main_name) + 64 * avg(req["TCC_EA0_RDREQ_64B"], main_name) \
+                + 128 * avg(req["TCC_EA0_RDREQ_128B"], main_name)
         rec = {"source_hash": h, "bytes_per_launch": tot, "fetch_bytes_raw": f, "write_bytes_raw": w,
                "fetch_scale": fscale, "write_scale": wscale, "read_bytes_by_request_size": rb,
                "launches": len(fetch[main_name]), "kernel": main_name, "command": command}
@@ -288,6 +312,47 @@ def copy_probe(reps=20):
     return round(2 * CALIB_FLOATS * 4 / (ms * 1e-3) / 1e9, 1)
 
 
+def trace_summary(folder, log_path, n, command):
+    """rocprofv3 --kernel-trace --stats of a bench run: the stats table, and
+    the average duration of the roofline kernel over the launches bench timed
+    with events (the last ones of its replayed increments) beside bench's own."""
+    import csv
+    import glob
+    stats = list(csv.DictReader(open(glob.glob(os.path.join(folder, "**", "*kernel_stats.csv"), recursive=True)[0])))
+    trace = list(csv.DictReader(open(glob.glob(os.path.join(folder, "**", "*kernel_trace.csv"), recursive=True)[0])))
+    with open(log_path) as f:
+        d = json.loads([l for l in f if l.startswith("{") and '"metric"' in l][-1])
+    roof = d["roofline"]
+    kind = roof["kernel"]
+    name_part = {"xfwd": "k_xfwd", "xinv": "k_xinv", "zgreen": "k_zgreen", "eval": "k_eval",
+                 "yfwd": "k_ypass", "yinv": "k_ypass"}[kind]
+    bench_launches = d["kernel_ms"][kind][0]
+    rows = [r for r in trace if name_part in r["Kernel_Name"] and "hom::" in r["Kernel_Name"]]
+    names = {}
+    for r in rows:
+        names.setdefault(r["Kernel_Name"], []).append(int(r["End_Timestamp"]) - int(r["Start_Timestamp"]))
+    main_name = max(names, key=lambda k: len(names[k]))
+    durs = names[main_name]
+    if kind in ("yfwd", "yinv"):
+        durs = durs[::2] if kind == "yfwd" else durs[1::2]
+    tail = durs[-bench_launches:]
+    rp_ms = float(np.mean(tail)) / 1e6
+    lines = [f"# Kernel trace of the {n}^3 fibre-composite bench", "", f"command: {command}", "",
+             f"bench line: value {d['value']:.4g} {d['unit']}, {d['ms_per_step']} ms per increment", "",
+             f"roofline kernel `{kind}` ({main_name}):",
+             f"- bench (HIP events over its {bench_launches} replayed timed launches): {roof['avg_launch_ms']:.4f} ms",
+             f"- rocprofv3 (same {len(tail)} launches): {rp_ms:.4f} ms "
+             f"({(rp_ms / roof['avg_launch_ms'] - 1) * 100:+.1f} %)",
+             f"- rocprofv3 (all {len(durs)} launches of the run): {float(np.mean(durs)) / 1e6:.4f} ms", "",
+             "| kernel | calls | total ms | average us | % |", "|---|---|---|---|---|"]
+    for r in stats[:16]:
+        lines.append(f"| {r['Name'][:80]} | {r['Calls']} | {float(r['TotalDurationNs']) / 1e6:.2f} | "
+                     f"{float(r['AverageNs']) / 1e3:.1f} | {float(r['Percentage']):.2f} |")
+    with open(os.path.join(ROOT, "profiles", f"pipeline_fibres{n}_kernel_trace.md"), "w") as fo:
+        fo.write("\n".join(lines) + "\n")
+    print("\n".join(lines))
+
+
 def network_only(rows=65536, reps=50):
     """Two-network surrogate inference (random weights: the speed does not
     depend on their values) on one 65,536-row batch; prints ms and TFLOP/s."""
@@ -310,19 +375,21 @@ def network_only(rows=65536, reps=50):
 
 def mfma_summary(folder, command):
     """MFMA busy fraction of the network kernels from one rocprofv3 --pmc run
-    with SQ_VALU_MFMA_BUSY_CYCLES and GRBM_GUI_ACTIVE (1024 SIMDs)."""
+    with SQ_VALU_MFMA_BUSY_CYCLES (summed over all 1024 SIMDs) and
+    GRBM_GUI_ACTIVE (the CSV holds the sum over the 8 XCDs; rocprofv3's own
+    MfmaUtil takes the per-XCD value)."""
     rows = _counter_rows(folder)
     busy = _per_kernel(rows, "SQ_VALU_MFMA_BUSY_CYCLES")
     active = _per_kernel(rows, "GRBM_GUI_ACTIVE")
     lines = ["# MFMA utilisation of the surrogate network kernels (65,536-row two-network inference)", "",
              f"command: {command}", "",
-             "MfmaUtil = SQ_VALU_MFMA_BUSY_CYCLES / (GRBM_GUI_ACTIVE x 1024 SIMDs)", "",
-             "| kernel | launches | MfmaUtil % |", "|---|---|---|"]
+             "MfmaUtil = SQ_VALU_MFMA_BUSY_CYCLES / ((GRBM_GUI_ACTIVE / 8 XCDs) x 1024 SIMDs)", "",
+             "| kernel | launches | MFMA busy cycles | GUI active cycles per XCD | MfmaUtil % |", "|---|---|---|---|---|"]
     for k in sorted(busy):
         if "mlp" not in k or k not in active:
             continue
-        u = float(np.mean(busy[k])) / (float(np.mean(active[k])) * 1024) * 100
-        lines.append(f"| {k[:70]} | {len(busy[k])} | {u:.1f} |")
+        b, a = float(np.mean(busy[k])), float(np.mean(active[k])) / 8
+        lines.append(f"| {k[:70]} | {len(busy[k])} | {b:.4g} | {a:.4g} | {b / (a * 1024) * 100:.1f} |")
     with open(os.path.join(ROOT, "profiles", "mlp_infer65536_mfma.md"), "w") as fo:
         fo.write("\n".join(lines) + "\n")
     print("\n".join(lines))
@@ -344,10 +411,16 @@ def main():
                          "into profiles/ (no GPU needed)")
     ap.add_argument("--mfma-summary", metavar="DIR", help="summarize an MFMA --pmc run into profiles/")
     ap.add_argument("--pmc-command", default="", help="command line recorded in the summary")
+    ap.add_argument("--pmc-log", help="stdout of the profiled bench run (restricts averages to its timed launches)")
+    ap.add_argument("--trace-summary", nargs=2, metavar=("TRACE_DIR", "LOG"),
+                    help="summarize a rocprofv3 --kernel-trace --stats run of bench.py into profiles/")
     ap.add_argument("--network-only", action="store_true", help="time the surrogate network inference alone")
     args = ap.parse_args()
     if args.pmc_summary:
-        pmc_summary(args.pmc_summary, args.n, args.pmc_command)
+        pmc_summary(args.pmc_summary, args.n, args.pmc_command, args.pmc_log)
+        return
+    if args.trace_summary:
+        trace_summary(args.trace_summary[0], args.trace_summary[1], args.n, args.pmc_command)
         return
     if args.mfma_summary:
         mfma_summary(args.mfma_summary, args.pmc_command)
@@ -392,6 +465,8 @@ def main():
         print(f"warmup inc {k}: newton {r['newton_iters']} krylov {r['krylov_iters']}", file=sys.stderr,
               flush=True)
 
+    # checkpoint, so that the timed increments can be replayed with per-kernel events
+    state0 = ctx.get_state(as_array=True) if not args.no_profile else None
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     pipes = 0.0
@@ -413,24 +488,33 @@ def main():
     nvox = float(n) ** 3
     value = pipes * nvox / elapsed
 
-    # per-kernel timing with HIP events on the library's stream (one more increment)
+    # per-kernel timing: the timed increments again from the checkpoint, each
+    # kernel bracketed by HIP events on the library's stream (launched one by
+    # one instead of as graphs; same kernels, same work, same iterations)
     roof = None
     kstats = None
-    if not args.no_profile and total < len(hist):
+    if not args.no_profile:
+        ctx.set_state(state0)
+        del state0
         ctx.set_profiling(True)
-        st = hist[total]
-        pr = ctx.solve_increment(st.strain, st.theta, st.grad, st.dt)
+        n_eval = n_cg = n_first = 0
+        for k, r0 in zip(range(args.warmup, total), results):
+            st = hist[k]
+            pr = ctx.solve_increment(st.strain, st.theta, st.grad, st.dt)
+            if (pr["newton_iters"], pr["krylov_iters"]) != (r0["newton_iters"], r0["krylov_iters"]):
+                print(f"warning: replay of increment {k} took different iterations", file=sys.stderr)
+            n_eval += pr["newton_iters"]
+            n_cg += pr["krylov_iters"]
+            n_first += max(pr["newton_iters"] - 1, 0)   # every Newton step but the converged one runs CG
         kstats = ctx.kernel_stats()
         ctx.set_profiling(False)
         dom = max((k for k in kstats if kstats[k][0] > 0), key=lambda k: kstats[k][1])
         matrix_fraction = float((wl.phases == 0).mean())
         launches, ms = kstats[dom]
         avg_s = ms / launches / 1e3
-        n_eval, n_cg = pr["newton_iters"], pr["krylov_iters"]
         mix = algorithmic_bytes(dom, n, 4, matrix_fraction)
         byt = None
         if mix is not None and launches == n_eval + n_cg:
-            n_first = max(n_eval - 1, 0)       # every Newton step but the converged one runs CG
             byt = (n_eval * mix[0] + n_first * mix[1] + (n_cg - n_first) * mix[2]) / launches
         traffic = traffic_req = None
         pmc_path = os.path.join(ROOT, "profiles", f"{dom}_fibres{n}_pmc.json")

@@ -303,15 +303,18 @@ class Context:
                 return 7 + 6 * sum(1 for i in range(L.n_maxwell) if L.E_i[i] > 0)
         return 0
 
-    def get_state(self) -> bytes:
+    def get_state(self, as_array=False):
+        """Checkpoint (committed fields, internal variables, macro state) as
+        bytes, or as a uint8 array without the extra host copy."""
         n = self._lib.hom_state_size(self._h)
-        buf = ct.create_string_buffer(n)
-        _check(self._lib.hom_get_state(self._h, buf, n), self.error)
-        return buf.raw
+        buf = np.empty(n, dtype=np.uint8)
+        _check(self._lib.hom_get_state(self._h, buf.ctypes.data_as(ct.c_void_p), n), self.error)
+        return buf if as_array else buf.tobytes()
 
-    def set_state(self, data: bytes):
-        buf = ct.create_string_buffer(data, len(data))
-        _check(self._lib.hom_set_state(self._h, buf, len(data)), self.error)
+    def set_state(self, data):
+        buf = np.frombuffer(data, dtype=np.uint8) if isinstance(data, (bytes, bytearray)) else data
+        buf = np.ascontiguousarray(buf, dtype=np.uint8)
+        _check(self._lib.hom_set_state(self._h, buf.ctypes.data_as(ct.c_void_p), buf.size), self.error)
 
     def kernel_stats(self):
         return _stats(self._lib.hom_kernel_stats, self._h)
