@@ -252,6 +252,7 @@ struct Group {
   T *xm = nullptr, *xnm = nullptr, *f = nullptr, *r = nullptr, *p = nullptr;
   double* hist = nullptr;
   T *tab = nullptr, *tn = nullptr, *xt = nullptr;
+  T* ft = nullptr;  // heat flux of the conduction solve (the stress field stays in f)
   c2<T>* spec = nullptr;
   double* state = nullptr;
   Ctl *ctl_m = nullptr, *ctl_t = nullptr;
@@ -296,6 +297,7 @@ struct Group {
     xm = dalloc<T>(6 * nm);
     xnm = dalloc<T>(6 * nm);
     f = dalloc<T>(6 * nm);
+    ft = dalloc<T>(3 * nm);
     r = dalloc<T>(6 * nm);
     p = dalloc<T>(6 * nm);
     tab = dalloc<T>(2 * nm);
@@ -348,7 +350,7 @@ struct Group {
     a.C = phys == 0 ? 6 : 3;
     a.phase = phase;
     a.x = phys == 0 ? xm : xt;
-    a.f = f;
+    a.f = phys == 0 ? f : ft;
     a.r = r;
     a.p = p;
     a.tab = tab;
@@ -374,7 +376,7 @@ struct Group {
     a.phase = phase;
     a.x = phys == 0 ? xm : xt;
     a.xn = xnm;
-    a.f = f;
+    a.f = phys == 0 ? f : ft;
     a.r = r;
     a.p = p;
     a.tab = tab;
