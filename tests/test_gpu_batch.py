@@ -58,3 +58,33 @@ def test_batch_matches_oracle():
             print(f"batch problem {i} (n={w.record['n']}) inc {k}: stress err {err:.2e}", flush=True)
             assert err <= 2e-4
             assert np.allclose(rb[i]["heat_flux"], o["heat_flux"], rtol=2e-4)
+
+
+def test_full_batch_in_bench_configuration_matches_oracle():
+    """The 512-problem batch as the benchmark runs it (FP32, autotuned tiles,
+    graph chunks, 5 increments): every problem converges, and one problem of
+    each grid size matches the oracle (48^3 on its first two increments)."""
+    wls = problems(range(512))
+    laws = [W.pa66(), W.e_glass()]
+    b = hom.Batch([w.phases for w in wls], laws, scheme=hom.SCHEME_NEWTON_CG, precision=hom.FP32, tol=1e-6,
+                  autotune=1)
+    picks = {}
+    for i, w in enumerate(wls):
+        picks.setdefault(w.record["n"], i)
+    assert sorted(picks) == [24, 32, 48]
+    refs = {i: solver.Cell(wls[i].phases, laws) for i in picks.values()}
+    for k in range(5):
+        strains = np.array([w.history[k].strain for w in wls])
+        rb = b.solve_increment(strains, [w.history[k].theta for w in wls], [w.history[k].grad for w in wls],
+                               [w.history[k].dt for w in wls])
+        assert all(r["status"] == 0 for r in rb)
+        for n, i in picks.items():
+            if n == 48 and k >= 2:
+                continue
+            st = wls[i].history[k]
+            o = refs[i].solve_increment(st.strain, st.theta, st.grad, st.dt, tol=1e-9)
+            scale = max(np.abs(o["stress"]).max(), 1e-3)
+            err = np.abs(rb[i]["stress"] - o["stress"]).max() / scale
+            print(f"batch of 512, problem {i} (n={n}) inc {k}: stress err {err:.2e}", flush=True)
+            assert err <= 2e-4
+            assert np.allclose(rb[i]["heat_flux"], o["heat_flux"], rtol=2e-4)
