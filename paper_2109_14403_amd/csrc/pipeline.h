@@ -128,6 +128,19 @@ __device__ __forceinline__ void st4(double* p, const double (&v)[4]) {
   reinterpret_cast<double2*>(p)[1] = make_double2(v[2], v[3]);
 }
 
+// Element v of a uniform base, with the byte offset formed in 32-bit unsigned
+// arithmetic so the access takes the scalar-base + 32-bit-offset form (needs
+// v * sizeof(T) < 2^32 inside one component of one problem: true for every
+// supported grid, n <= 256).
+template <typename T>
+__device__ __forceinline__ const T* at(const T* base, unsigned v) {
+  return reinterpret_cast<const T*>(reinterpret_cast<const char*>(base) + v * (unsigned)sizeof(T));
+}
+template <typename T>
+__device__ __forceinline__ T* at(T* base, unsigned v) {
+  return reinterpret_cast<T*>(reinterpret_cast<char*>(base) + v * (unsigned)sizeof(T));
+}
+
 // Staging layout of the x passes between the per-voxel phases and the line
 // transforms: one row of SP complex values per transform lane, x fastest. A
 // thread's four consecutive voxels are 32 contiguous bytes, and the odd pitch
@@ -196,7 +209,15 @@ __global__ void __launch_bounds__((N / Plan<N>::M) * NL * ((C + 1) / 2)) k_xfwd(
 
   // four consecutive voxels of one line per work item, 16-byte accesses
   const int nvl = min(NL, nlines - line0);
-  const long long v0 = (long long)line0 * N;
+  // uniform per-component bases and a 32-bit voxel offset: loads and stores
+  // take the scalar-base + 32-bit-offset form
+  const unsigned v0 = (unsigned)(line0 * N);
+  const T* fb = a.f + fo;
+  const T* rb = a.r + fo;
+  T* pb = a.p + fo;
+  T* xb = a.x + fo;
+  const T* tb = a.tab + (long long)prob * 2 * nv;
+  const T* nb = a.tn + (long long)prob * 6 * nv;
   for (int w = tid; w < NL * N / 4; w += nth) {
     const int e = 4 * w;
     const int li = e / N;
@@ -207,43 +228,57 @@ __global__ void __launch_bounds__((N / Plan<N>::M) * NL * ((C + 1) / 2)) k_xfwd(
 #pragma unroll
       for (int c = 0; c < 2 * NP; ++c) out[j][c] = T(0);
     if (li < nvl) {
-      const long long v = v0 + e;
+      const unsigned v = v0 + (unsigned)e;
       if (!cg) {
 #pragma unroll
         for (int c = 0; c < C; ++c) {
-          const Q4<T> q = ld4(a.f + fo + c * nv + v);
+          const Q4<T> q = ld4(at(fb + c * nv, v));
 #pragma unroll
           for (int j = 0; j < 4; ++j) out[j][c] = q.v[j];
         }
       } else {
         // p = r + beta p; the step x += alpha p of the previous iteration is
-        // applied here, where the old direction is read anyway
+        // applied here, where the old direction is read anyway. Every load of
+        // the work item is issued before the first store (one memory round
+        // trip instead of one per component).
+        Q4<T> rq[C], pq[C], xq[C];
+#pragma unroll
+        for (int c = 0; c < C; ++c) rq[c] = ld4(at(rb + c * nv, v));
+        if (!first) {  // uniform over the block
+#pragma unroll
+          for (int c = 0; c < C; ++c) {
+            pq[c] = ld4(at(pb + c * nv, v));
+            xq[c] = ld4(at(xb + c * nv, v));
+          }
+        }
+        Q4<T> ca, cb;
+        if constexpr (C == 6) {
+          ca = ld4(at(tb, v));
+          cb = ld4(at(tb + nv, v));
+        }
+        const uchar4 ph = *reinterpret_cast<const uchar4*>(at(phase, v));
         T pv[C][4];
+        if (first) {
 #pragma unroll
-        for (int c = 0; c < C; ++c) {
-          const Q4<T> rq = ld4(a.r + fo + c * nv + v);
-          if (first) {
+          for (int c = 0; c < C; ++c)
 #pragma unroll
-            for (int j = 0; j < 4; ++j) pv[c][j] = rq.v[j];
-          } else {
-            const Q4<T> pq = ld4(a.p + fo + c * nv + v);
-            const Q4<T> xq = ld4(a.x + fo + c * nv + v);
+            for (int j = 0; j < 4; ++j) pv[c][j] = rq[c].v[j];
+        } else {
+#pragma unroll
+          for (int c = 0; c < C; ++c) {
             T xn[4];
 #pragma unroll
             for (int j = 0; j < 4; ++j) {
-              pv[c][j] = rq.v[j] + beta * pq.v[j];
-              xn[j] = xq.v[j] + alpha_prev * pq.v[j];
+              pv[c][j] = rq[c].v[j] + beta * pq[c].v[j];
+              xn[j] = xq[c].v[j] + alpha_prev * pq[c].v[j];
             }
-            st4(a.x + fo + c * nv + v, xn);
+            st4(at(xb + c * nv, v), xn);
           }
-          st4(a.p + fo + c * nv + v, pv[c]);
         }
-        const uchar4 ph = *reinterpret_cast<const uchar4*>(phase + v);
+#pragma unroll
+        for (int c = 0; c < C; ++c) st4(at(pb + c * nv, v), pv[c]);
         const int phs[4] = {ph.x, ph.y, ph.z, ph.w};
         if constexpr (C == 6) {
-          const long long to = (long long)prob * 2 * nv;
-          const Q4<T> ca = ld4(a.tab + to + v);
-          const Q4<T> cb = ld4(a.tab + to + nv + v);
 #pragma unroll
           for (int j = 0; j < 4; ++j) {
             const T tr3 = (pv[0][j] + pv[1][j] + pv[2][j]) * T(1.0 / 3.0);
@@ -255,11 +290,10 @@ __global__ void __launch_bounds__((N / Plan<N>::M) * NL * ((C + 1) / 2)) k_xfwd(
             out[j][2] += sph;
           }
           if (cb.v[0] != T(0) || cb.v[1] != T(0) || cb.v[2] != T(0) || cb.v[3] != T(0)) {
-            const long long no = (long long)prob * 6 * nv;
             T nd[6][4];
 #pragma unroll
             for (int c = 0; c < 6; ++c) {
-              const Q4<T> q = ld4(a.tn + no + c * nv + v);
+              const Q4<T> q = ld4(at(nb + c * nv, v));
 #pragma unroll
               for (int j = 0; j < 4; ++j) nd[c][j] = q.v[j];
             }
@@ -517,19 +551,37 @@ __global__ void __launch_bounds__((N / Plan<N>::M) * NL * ((C + 1) / 2)) k_xinv(
   const int nvl = min(NL, nlines - line0);
   const int rowp = a.PS * C;
   const c2<T>* spec = a.spec + (long long)prob * a.nz * a.ny * rowp + (long long)line0 * rowp;
+  // all of a thread's loads are issued before the LDS writes (the launch has
+  // exactly NTH threads)
+  constexpr int NTH = G * L;
   if constexpr (sizeof(c2<T>) == 8 && C % 2 == 0) {
+    constexpr int K = (NL * H * C / 2 + NTH - 1) / NTH;
+    const int tot = nvl * H * C / 2;
     const uint4* s4 = reinterpret_cast<const uint4*>(spec);
     uint4* d4 = reinterpret_cast<uint4*>(buf);
-    for (int i = tid; i < nvl * H * C / 2; i += nth) {
-      const int e = 2 * i;
+    uint4 t4[K];
+#pragma unroll
+    for (int k = 0; k < K; ++k) {  // unconditional loads (index clamped in range), no branch between them
+      const int e = 2 * min(tid + k * NTH, tot - 1);
       const int li = e / (H * C);
-      d4[i] = s4[(li * rowp + (e - li * H * C)) / 2];
+      t4[k] = s4[(li * rowp + (e - li * H * C)) / 2];
     }
+    // unconditional writes too (else the compiler sinks each load into its
+    // write's branch): a clamped thread rewrites the last element's own value
+#pragma unroll
+    for (int k = 0; k < K; ++k) d4[min(tid + k * NTH, tot - 1)] = t4[k];
   } else {
-    for (int e = tid; e < nvl * H * C; e += nth) {
+    constexpr int K = (NL * H * C + NTH - 1) / NTH;
+    const int tot = nvl * H * C;
+    c2<T> t2[K];
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      const int e = min(tid + k * NTH, tot - 1);
       const int li = e / (H * C);
-      buf[e] = spec[li * rowp + (e - li * H * C)];
+      t2[k] = spec[li * rowp + (e - li * H * C)];
     }
+#pragma unroll
+    for (int k = 0; k < K; ++k) buf[min(tid + k * NTH, tot - 1)] = t2[k];
   }
   for (int e = nvl * H * C + tid; e < NL * H * C; e += nth) buf[e] = mk(T(0), T(0));
   __syncthreads();
@@ -562,12 +614,19 @@ __global__ void __launch_bounds__((N / Plan<N>::M) * NL * ((C + 1) / 2)) k_xinv(
   const long long fo = (long long)prob * C * nv;
   const T scale = T(1.0 / ((double)a.nx * a.ny * a.nz));
   double s0 = 0.0, s1 = 0.0;
-  const long long v0 = (long long)line0 * N;
+  const unsigned v0 = (unsigned)(line0 * N);
+  const T* sb = (mode == M_EVAL ? a.f : (mode == M_CG ? a.r : a.x)) + fo;  // uniform bases
+  T* db = (mode == M_BASIC ? a.x : a.r) + fo;
   for (int w = tid; w < nvl * N / 4; w += nth) {
     const int e = 4 * w;
     const int lj = e / N;
     const int xv = e - lj * N;
-    const long long v = v0 + e;
+    const unsigned v = v0 + (unsigned)e;
+    // the work item's global operand for every component first (one memory
+    // round trip), then the transformed values from LDS, then the stores
+    Q4<T> q[C];
+#pragma unroll
+    for (int c = 0; c < C; ++c) q[c] = ld4(at(sb + c * nv, v));
 #pragma unroll
     for (int c = 0; c < C; ++c) {
       T g[4];
@@ -576,39 +635,33 @@ __global__ void __launch_bounds__((N / Plan<N>::M) * NL * ((C + 1) / 2)) k_xinv(
         const c2<T> z = buf[(lj * NP + (c >> 1)) * SP + xv + j];
         g[j] = ((c & 1) ? z.y : z.x) * scale;
       }
-      const long long o = fo + c * nv + v;
-      if (mode == M_EVAL) {
-        T ng[4];
-#pragma unroll
-        for (int j = 0; j < 4; ++j) ng[j] = -g[j];
-        st4(a.r + o, ng);
-        const Q4<T> fq = ld4(a.f + o);
+      T* o = at(db + c * nv, v);
+      T out[4];
+      if (mode == M_EVAL) {  // residual field r = -Gamma sigma; norms of r and sigma
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
+          out[j] = -g[j];
           s0 += (double)g[j] * (double)g[j];
-          s1 += (double)fq.v[j] * (double)fq.v[j];
+          s1 += (double)q[c].v[j] * (double)q[c].v[j];
         }
+        st4(o, out);
       } else if (mode == M_CG) {
         // residual update with alpha = r.r / p.C p: r -= alpha A p (the step
         // x += alpha p follows in the next x-forward pass or evaluation)
-        const Q4<T> rq = ld4(a.r + o);
-        T rn[4];
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
-          rn[j] = rq.v[j] - alpha * g[j];
-          s0 += (double)rn[j] * (double)rn[j];
+          out[j] = q[c].v[j] - alpha * g[j];
+          s0 += (double)out[j] * (double)out[j];
         }
-        st4(a.r + o, rn);
-      } else {
-        const Q4<T> xq = ld4(a.x + o);
-        T xn[4];
+        st4(o, out);
+      } else {  // basic scheme: x -= Gamma0 sigma
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
-          xn[j] = xq.v[j] - g[j];
+          out[j] = q[c].v[j] - g[j];
           s0 += (double)g[j] * (double)g[j];
-          s1 += (double)xn[j] * (double)xn[j];
+          s1 += (double)out[j] * (double)out[j];
         }
-        st4(a.x + o, xn);
+        st4(o, out);
       }
     }
   }
