@@ -207,18 +207,21 @@ int hom_mlp_set_scaling(hom_mlp* net, const float* x_mean, const float* x_std, c
  * network learns the remainder. */
 int hom_mlp_set_skip(hom_mlp* net, const int32_t gates[3], const float* G, const float* c);
 /* Fit the skip to host rows (x [n][n_in], y [n][n_out]) by least squares
- * (FP64 normal equations) and set the input scaling from x and the output
- * scaling from the residual y - skip(x); loss_weight may be NULL (all 1).
- * hom_mlp_train then trains the network on that residual. */
+ * (FP64 normal equations, rows weighted by row_weight [n], NULL: all 1) and
+ * set the input scaling from x and the output scaling from the residual
+ * y - skip(x); loss_weight [n_out] may be NULL (all 1). hom_mlp_train then
+ * trains the network on that residual. */
 int hom_mlp_fit_skip(hom_mlp* net, const float* x, const float* y, int64_t n, const int32_t gates[3],
-                     const float* loss_weight);
+                     const float* loss_weight, const float* row_weight);
 int hom_mlp_get_params(const hom_mlp* net, float* host, size_t count);
 int hom_mlp_set_params(hom_mlp* net, const float* host, size_t count);
 /* Train on n rows (host arrays x [n][n_in], y [n][n_out]) with Adam, minibatch
- * `batch`, peak learning rate lr (cosine decay), seeded shuffling; writes the
- * mean loss of every epoch into epoch_loss (epochs entries) if non-null. */
+ * `batch`, peak learning rate lr (cosine decay), seeded shuffling; each row's
+ * squared error is weighted by row_weight [n] (NULL: all 1, e.g. the inverse
+ * square of the row's error normalization); writes the mean loss of every
+ * epoch into epoch_loss (epochs entries) if non-null. */
 int hom_mlp_train(hom_mlp* net, const float* x, const float* y, int64_t n, int32_t epochs, int32_t batch,
-                  double lr, uint64_t seed, float* epoch_loss);
+                  double lr, uint64_t seed, const float* row_weight, float* epoch_loss);
 /* Inference on device arrays x_dev [n][n_in] -> y_dev [n][n_out] on `stream`.
  * precise = 1 splits the weights into two bf16 parts (FP32-equivalent). */
 int hom_mlp_forward(hom_mlp* net, const float* x_dev, float* y_dev, int64_t n, int32_t precise, void* stream);

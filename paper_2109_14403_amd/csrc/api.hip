@@ -208,13 +208,13 @@ int hom_mlp_set_skip(hom_mlp* m, const int32_t gates[3], const float* G, const f
 }
 
 int hom_mlp_fit_skip(hom_mlp* m, const float* x, const float* y, int64_t n, const int32_t gates[3],
-                     const float* lw) {
+                     const float* lw, const float* rw) {
   if (!m || !m->net || !x || !y || !gates || n < 2) return HOM_E_ARG;
   return guarded(&m->err, [&] {
     const int g[3] = {gates[0], gates[1], gates[2]};
     std::vector<float> w(m->net->n_out, 1.f);
     if (lw) w.assign(lw, lw + m->net->n_out);
-    m->net->fit_skip(x, y, n, g, w.data());
+    m->net->fit_skip(x, y, n, g, w.data(), rw);
   });
 }
 
@@ -229,9 +229,12 @@ int hom_mlp_set_params(hom_mlp* m, const float* host, size_t count) {
 }
 
 int hom_mlp_train(hom_mlp* m, const float* x, const float* y, int64_t n, int32_t epochs, int32_t batch, double lr,
-                  uint64_t seed, float* epoch_loss) {
+                  uint64_t seed, const float* row_weight, float* epoch_loss) {
   if (!m || !m->net || !x || !y || n < 1 || epochs < 1 || batch < 1 || !(lr > 0.0)) return HOM_E_ARG;
-  return guarded(&m->err, [&] { m->net->train(x, y, n, epochs, batch, lr, seed, epoch_loss); });
+  if (row_weight)
+    for (int64_t r = 0; r < n; ++r)
+      if (!(row_weight[r] >= 0.f) || !std::isfinite(row_weight[r])) return HOM_E_ARG;
+  return guarded(&m->err, [&] { m->net->train(x, y, n, epochs, batch, lr, seed, row_weight, epoch_loss); });
 }
 
 int hom_mlp_forward(hom_mlp* m, const float* x_dev, float* y_dev, int64_t n, int32_t precise, void* stream) {

@@ -38,13 +38,13 @@ struct Mlp {
   double skip_value(const double* xn, int j) const;
   // Least-squares fit of the skip on (X, Y), then input / residual scaling
   // from the same rows (lw: loss weights of the outputs)
-  void fit_skip(const float* X, const float* Y, long long n, const int* gates, const float* lw);
+  void fit_skip(const float* X, const float* Y, long long n, const int* gates, const float* lw, const float* rw);
   std::vector<void*> allocs;
   // training work space
   long long work_rows = 0;
   std::vector<void*> work;
   float *xs = nullptr, *zs[MLP_LAYERS - 1] = {}, *as[MLP_LAYERS - 1] = {}, *yhat = nullptr, *dy = nullptr;
-  float *da = nullptr, *dz = nullptr, *xb = nullptr, *tb = nullptr, *lpart = nullptr;
+  float *da = nullptr, *dz = nullptr, *xb = nullptr, *tb = nullptr, *rwb = nullptr, *lpart = nullptr;
 
   Mlp(int n_in, int n_out, uint64_t seed);
   ~Mlp();
@@ -59,10 +59,12 @@ struct Mlp {
   void free_work();
   // x: device [n][n_in]; y: device [n][n_out] (physical units) or null
   void forward(const float* x, float* y, long long n, bool precise, bool save, hipStream_t s);
-  // x: device raw inputs, t: device normalized targets [B][16]; fills g
-  double loss_grad(const float* x, const float* tnorm, long long B, bool precise, hipStream_t s);
+  // x: device raw inputs, t: device normalized targets [B][16], rw: device
+  // row weights [B] or null; fills g
+  double loss_grad(const float* x, const float* tnorm, long long B, bool precise, hipStream_t s,
+                   const float* rw = nullptr);
   void train(const float* X, const float* T, long long n, int epochs, int batch, double lr, uint64_t seed,
-             float* loss_out);
+             const float* row_weight, float* loss_out);
   void get_params(float* out) const;
   void get_grads(float* out) const;
   void set_params(const float* in);

@@ -252,8 +252,9 @@ __global__ void k_gelu_back(const float* da, const float* z, float* dz, long lon
 }
 
 // weighted MSE on normalized outputs: dyhat = 2 w (yhat - t) / B, loss partials
-__global__ void k_loss(const float* yhat, const float* t, const float* w, long long B, int n_out, float* dy,
-                       double* part) {
+// weighted mean squared error: output weights w [16], row weights rw [B] (or null)
+__global__ void k_loss(const float* yhat, const float* t, const float* w, const float* rw, long long B, int n_out,
+                       float* dy, double* part) {
   __shared__ double red[256];
   const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   double l = 0.0;
@@ -262,8 +263,9 @@ __global__ void k_loss(const float* yhat, const float* t, const float* w, long l
     float g = 0.f;
     if (j < n_out) {
       const float d = yhat[i] - t[i];
-      g = 2.0f * w[j] * d / (float)B;
-      l = (double)w[j] * (double)d * (double)d / (double)B;
+      const float wj = w[j] * (rw ? rw[i / MLP_OUT] : 1.0f);
+      g = 2.0f * wj * d / (float)B;
+      l = (double)wj * (double)d * (double)d / (double)B;
     }
     dy[i] = g;
   }
@@ -481,7 +483,8 @@ double Mlp::skip_value(const double* xn, int j) const {
 
 // Host-side least squares in FP64: normal equations of the design
 // [1, xhat * s_g(xhat)] with a tiny ridge, solved by Cholesky.
-void Mlp::fit_skip(const float* X, const float* Y, long long n, const int* gates, const float* lw) {
+void Mlp::fit_skip(const float* X, const float* Y, long long n, const int* gates, const float* lw,
+                   const float* rw) {
   if (n < 2) fail(HOM_E_ARG, "need rows to fit");
   for (int i = 0; i < 3; ++i)
     if (gates[i] < 0 || gates[i] >= n_in) fail(HOM_E_ARG, "gate index out of range");
@@ -513,8 +516,9 @@ void Mlp::fit_skip(const float* X, const float* Y, long long n, const int* gates
     phi[0] = 1.0;
     for (int g = 0; g < MLP_GATES; ++g)
       for (int k = 0; k < n_in; ++k) phi[1 + g * n_in + k] = s[g] * xn[k];
+    const double wr = rw ? (double)rw[r] : 1.0;  // weighted least squares
     for (int a = 0; a < P; ++a) {
-      const double pa = phi[a];
+      const double pa = wr * phi[a];
       double* row = &AtA[(size_t)a * P];
       for (int b = 0; b <= a; ++b) row[b] += pa * phi[b];
       for (int j = 0; j < n_out; ++j) AtY[(size_t)a * n_out + j] += pa * Y[r * n_out + j];
@@ -595,6 +599,7 @@ void Mlp::ensure_work(long long rows) {
   alloc(&dz, rows * MLP_W);
   alloc(&xb, rows * MLP_IN);
   alloc(&tb, rows * MLP_OUT);
+  alloc(&rwb, rows);
   alloc(&lpart, (rows * MLP_OUT + 255) / 256 * 2);
   work_rows = rows;
 }
@@ -646,12 +651,13 @@ static void gemm(bool ta, bool tb, int M, int N, int K, const float* A, int lda,
 
 // loss and gradient of the rows (x, t normalized targets already in xb / tb
 // layout: x raw [B][n_in], t normalized [B][16])
-double Mlp::loss_grad(const float* x, const float* tnorm, long long B, bool precise, hipStream_t s) {
+double Mlp::loss_grad(const float* x, const float* tnorm, long long B, bool precise, hipStream_t s,
+                      const float* rw) {
   ensure_work(B);
   forward(x, nullptr, B, precise, true, s);
   const long long cnt = B * MLP_OUT;
   const int lb = (int)((cnt + 255) / 256);
-  hipLaunchKernelGGL(k_loss, dim3(lb), dim3(256), 0, s, yhat, tnorm, scal + 2 * MLP_IN + 2 * MLP_OUT, B, n_out, dy,
+  hipLaunchKernelGGL(k_loss, dim3(lb), dim3(256), 0, s, yhat, tnorm, scal + 2 * MLP_IN + 2 * MLP_OUT, rw, B, n_out, dy,
                      reinterpret_cast<double*>(lpart));
   const float* eff = precise ? eff_pr : eff_bf;
   const float* dcur = dy;
@@ -736,24 +742,34 @@ size_t Mlp::param_count() const {
 }
 
 void Mlp::train(const float* X, const float* T, long long n, int epochs, int batch, double lr0, uint64_t seed,
-                float* loss_out) {
+                const float* row_weight, float* loss_out) {
   if (n < batch || batch < 1) fail(HOM_E_ARG, "need at least one full batch");
   hipStream_t s = nullptr;
-  float *dX = nullptr, *dT = nullptr;
+  float *dX = nullptr, *dT = nullptr, *dW = nullptr;
   int* didx = nullptr;
   HIPCHK(hipMalloc((void**)&dX, n * n_in * 4));
   HIPCHK(hipMalloc((void**)&dT, n * MLP_OUT * 4));
   HIPCHK(hipMalloc((void**)&didx, n * 4));
+  if (row_weight) HIPCHK(hipMalloc((void**)&dW, n * 4));
   struct Guard {
     std::vector<void*> p;
     ~Guard() {
-      for (void* q : p) (void)hipFree(q);
+      for (void* q : p)
+        if (q) (void)hipFree(q);
     }
-  } guard{{dX, dT, didx}};
+  } guard{{dX, dT, didx, dW}};
   std::vector<float> tn((size_t)n * MLP_OUT);
   normalized_targets(X, T, n, tn.data());
   HIPCHK(hipMemcpy(dX, X, n * n_in * 4, hipMemcpyHostToDevice));
   HIPCHK(hipMemcpy(dT, tn.data(), tn.size() * 4, hipMemcpyHostToDevice));
+  if (row_weight) {  // scaled to mean 1, so the learning rate keeps its meaning
+    double sum = 0.0;
+    for (long long r = 0; r < n; ++r) sum += row_weight[r];
+    if (!(sum > 0.0)) fail(HOM_E_ARG, "row weights sum to zero");
+    std::vector<float> rw(row_weight, row_weight + n);
+    for (float& x : rw) x = (float)(x * (double)n / sum);
+    HIPCHK(hipMemcpy(dW, rw.data(), n * 4, hipMemcpyHostToDevice));
+  }
   ensure_work(batch);
   std::mt19937_64 gen(seed);
   std::vector<int> perm(n);
@@ -771,7 +787,9 @@ void Mlp::train(const float* X, const float* T, long long n, int epochs, int bat
       const long long cx = (long long)batch * n_in, ct = (long long)batch * MLP_OUT;
       hipLaunchKernelGGL(k_gather, dim3((cx + 255) / 256), dim3(256), 0, s, dX, n_in, bi, (long long)batch, xb);
       hipLaunchKernelGGL(k_gather, dim3((ct + 255) / 256), dim3(256), 0, s, dT, MLP_OUT, bi, (long long)batch, tb);
-      el += loss_grad(xb, tb, batch, false, s);
+      if (dW)
+        hipLaunchKernelGGL(k_gather, dim3((batch + 255) / 256), dim3(256), 0, s, dW, 1, bi, (long long)batch, rwb);
+      el += loss_grad(xb, tb, batch, false, s, dW ? rwb : nullptr);
       ++step;
       // cosine decay to 1 % with a short warm-up
       const double prog = (double)step / (double)total;

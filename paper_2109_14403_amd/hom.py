@@ -160,11 +160,11 @@ def library(path: str | None = None):
     lib.hom_mlp_param_count.restype = ct.c_size_t
     lib.hom_mlp_set_scaling.argtypes = [ct.c_void_p, fp, fp, fp, fp, fp]
     lib.hom_mlp_set_skip.argtypes = [ct.c_void_p, ct.POINTER(ct.c_int32), fp, fp]
-    lib.hom_mlp_fit_skip.argtypes = [ct.c_void_p, fp, fp, ct.c_int64, ct.POINTER(ct.c_int32), fp]
+    lib.hom_mlp_fit_skip.argtypes = [ct.c_void_p, fp, fp, ct.c_int64, ct.POINTER(ct.c_int32), fp, fp]
     lib.hom_mlp_get_params.argtypes = [ct.c_void_p, fp, ct.c_size_t]
     lib.hom_mlp_set_params.argtypes = [ct.c_void_p, fp, ct.c_size_t]
     lib.hom_mlp_train.argtypes = [ct.c_void_p, fp, fp, ct.c_int64, ct.c_int32, ct.c_int32, ct.c_double, ct.c_uint64,
-                                  fp]
+                                  fp, fp]
     lib.hom_mlp_forward.argtypes = [ct.c_void_p, ct.c_void_p, ct.c_void_p, ct.c_int64, ct.c_int32, ct.c_void_p]
     lib.hom_mlp_loss_grad.argtypes = [ct.c_void_p, fp, fp, ct.c_int64, ct.c_int32, ct.POINTER(ct.c_double), fp]
     lib.hom_surrogate_infer.argtypes = [ct.c_void_p, ct.c_void_p, ct.c_void_p, ct.c_void_p, ct.c_void_p,
@@ -466,11 +466,14 @@ class MLP:
         c = _f32(c).reshape(self.n_out)
         _check(self._lib.hom_mlp_set_skip(self._h, g, _fptr(G), _fptr(c)), self.error)
 
-    def fit_skip(self, x, y, gates, loss_weight=None):
+    def fit_skip(self, x, y, gates, loss_weight=None, row_weight=None):
         x, y = _f32(x), _f32(y)
         g = (ct.c_int32 * 3)(*[int(v) for v in gates])
-        lw = _fptr(_f32(loss_weight)) if loss_weight is not None else None
-        _check(self._lib.hom_mlp_fit_skip(self._h, _fptr(x), _fptr(y), x.shape[0], g, lw), self.error)
+        lw = _f32(loss_weight) if loss_weight is not None else None
+        rw = _f32(row_weight) if row_weight is not None else None
+        _check(self._lib.hom_mlp_fit_skip(self._h, _fptr(x), _fptr(y), x.shape[0], g,
+                                          _fptr(lw) if lw is not None else None,
+                                          _fptr(rw) if rw is not None else None), self.error)
 
     def get_params(self):
         out = np.empty(self.param_count, dtype=np.float32)
@@ -494,11 +497,12 @@ class MLP:
             out.append((W, b))
         return out
 
-    def train(self, x, y, epochs, batch=256, lr=2e-3, seed=0):
+    def train(self, x, y, epochs, batch=256, lr=2e-3, seed=0, row_weight=None):
         x, y = _f32(x), _f32(y)
+        rw = _f32(row_weight) if row_weight is not None else None
         losses = np.empty(epochs, dtype=np.float32)
         _check(self._lib.hom_mlp_train(self._h, _fptr(x), _fptr(y), x.shape[0], epochs, batch, lr, seed,
-                                       _fptr(losses)), self.error)
+                                       _fptr(rw) if rw is not None else None, _fptr(losses)), self.error)
         return losses
 
     def forward_device(self, x_dev, y_dev, precise=False, stream=None):

@@ -135,20 +135,27 @@ class Surrogate:
     # gate inputs of the polynomial skip: log10 dt, theta^{n+1}, theta^n
     GATES = (7, 6, 26)
 
-    def fit(self, X, Y, epochs=150, batch=256, lr=2e-3, seed=0):
+    def fit(self, X, Y, denom=None, epochs=150, batch=256, lr=2e-3, seed=0):
         """Least-squares gated polynomial skip (fixed, fitted by the library),
-        networks trained on the residual. Returns the per-epoch losses."""
+        networks trained on the residual. With denom (each row's error
+        normalization, max_t |<sigma>| of its history) the rows are weighted by
+        1 / denom^2, so the loss is the squared relative error the acceptance
+        is judged by (denominators below `floor` count as `floor`). Returns
+        the per-epoch losses."""
         lw = np.ones(N_OUT, dtype=np.float32)
         lw[:6] = 4.0          # the stress is the accuracy target
         X = np.ascontiguousarray(X, dtype=np.float32)
         Y = np.ascontiguousarray(Y, dtype=np.float32)
+        rw = None
+        if denom is not None:
+            rw = (1.0 / np.maximum(np.asarray(denom, dtype=np.float64), self.floor) ** 2).astype(np.float32)
         losses = []
         for i, net in enumerate(self.nets):
-            net.fit_skip(X, Y, self.GATES, lw)
-            losses.append(net.train(X, Y, epochs=epochs, batch=batch, lr=lr, seed=seed + 17 * i))
+            net.fit_skip(X, Y, self.GATES, lw, rw)
+            losses.append(net.train(X, Y, epochs=epochs, batch=batch, lr=lr, seed=seed + 17 * i, row_weight=rw))
         # the method without the network: same skip, network output held at zero
         self.skip_net = hom.MLP(N_IN, N_OUT, seed=0)
-        self.skip_net.fit_skip(X, Y, self.GATES, lw)
+        self.skip_net.fit_skip(X, Y, self.GATES, lw, rw)
         self.skip_net.set_params(np.zeros(self.skip_net.param_count, dtype=np.float32))
         return losses
 

@@ -124,3 +124,40 @@ def test_training_reduces_loss():
     pred = net.forward(x[:512])
     rel = np.abs(pred - y[:512]).max() / np.abs(y).max()
     assert rel < 0.1
+
+
+def test_row_weights():
+    """Row weights enter the loss as w_r (y - t)^2 after scaling to mean 1:
+    equal weights reproduce unweighted training bit for bit; weights that
+    switch half of the rows off leave those rows' targets unfitted; and the
+    weighted skip fit is weighted least squares (equal weights change nothing)."""
+    rng = np.random.default_rng(3)
+    x = rng.uniform(-1, 1, size=(4096, 6)).astype(np.float32)
+    y = np.stack([np.sin(2 * x[:, 0]) + x[:, 1], x[:, 2] * x[:, 3]], axis=1).astype(np.float32)
+
+    def trained(rw, flip=False):
+        net = hom.MLP(6, 2, seed=4)
+        t = y.copy()
+        if flip:
+            t[1::2] = -t[1::2]          # contradictory targets on the odd rows
+        net.set_scaling(x.mean(0), x.std(0), y.mean(0), y.std(0))
+        net.train(x, t, epochs=8, batch=256, lr=2e-3, seed=5, row_weight=rw)
+        return net
+
+    a = trained(None).get_params()
+    b = trained(np.full(len(x), 2.0, dtype=np.float32)).get_params()
+    assert np.array_equal(a, b)
+    rw = np.zeros(len(x), dtype=np.float32)
+    rw[0::2] = 1.0
+    net = trained(rw, flip=True)       # only the even rows (true targets) count
+    pred = net.forward(x)
+    even = np.abs(pred[0::2] - y[0::2]).mean()
+    odd_flipped = np.abs(pred[1::2] + y[1::2]).mean()
+    assert even < 0.5 * odd_flipped
+    gates = (0, 1, 2)
+    s1, s2 = hom.MLP(6, 2, seed=0), hom.MLP(6, 2, seed=0)
+    s1.fit_skip(x, y, gates)
+    s2.fit_skip(x, y, gates, row_weight=np.full(len(x), 3.0, dtype=np.float32))
+    for m in (s1, s2):
+        m.set_params(np.zeros(m.param_count, dtype=np.float32))
+    assert np.allclose(s1.forward(x[:256]), s2.forward(x[:256]), rtol=1e-5, atol=1e-6)
