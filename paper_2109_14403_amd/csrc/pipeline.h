@@ -437,7 +437,8 @@ __global__ void __launch_bounds__((N / Plan<N>::M) * TX * C) k_ypass(Pipe<T> a, 
 // z forward + Green operator + z inverse on tiles of TX kx columns
 // ---------------------------------------------------------------------------
 template <typename T, int C, int N, int TX>
-__global__ void __launch_bounds__((N / Plan<N>::M) * TX * C) k_zgreen(Pipe<T> a) {
+__global__ void __launch_bounds__((N / Plan<N>::M) * TX * C)
+    __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 5 : 1))) k_zgreen(Pipe<T> a) {
   constexpr int M = Plan<N>::M;
   constexpr int G = N / M;
   constexpr int L = TX * C;
