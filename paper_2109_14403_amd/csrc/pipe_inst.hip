@@ -101,21 +101,18 @@ LaunchInfo zgreen_c(const Pipe<T>& a, hipStream_t s, bool dry) {
   return li;
 }
 
-constexpr int nl_of(int n, bool fp64) {
-  return ((fp64 ? 64 : 128) / (n / Plan<HOM_N>::M)) < 1 ? 1 : ((fp64 ? 64 : 128) / (n / Plan<HOM_N>::M));
-}
-
 }  // namespace
 
 template <typename T, int N>
 LaunchInfo xfwd_launch(const Pipe<T>& a, hipStream_t s, bool dry) {
-  constexpr int NL = nl_of(N, sizeof(T) == 8);
+  static_assert(plan_m(N) == Plan<N>::M, "launch plan and transform plan disagree");
+  constexpr int NL = x_lines(N, sizeof(T) == 8, true);
   return a.C == 6 ? xfwd_c<T, 6, N, NL>(a, s, dry) : xfwd_c<T, 3, N, NL>(a, s, dry);
 }
 
 template <typename T, int N>
 LaunchInfo xinv_launch(const Pipe<T>& a, hipStream_t s, bool dry) {
-  constexpr int NL = nl_of(N, sizeof(T) == 8);
+  constexpr int NL = x_lines(N, sizeof(T) == 8, false);
   return a.C == 6 ? xinv_c<T, 6, N, NL>(a, s, dry) : xinv_c<T, 3, N, NL>(a, s, dry);
 }
 

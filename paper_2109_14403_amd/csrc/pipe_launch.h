@@ -17,7 +17,7 @@ inline bool supported_n(int n) {
 }
 
 // Elements per thread of the line FFT of length n (threads per line = n / M).
-inline int plan_m(int n) {
+constexpr int plan_m(int n) {
   switch (n) {
     case 16: return 4;
     case 24: return 12;
@@ -31,10 +31,12 @@ inline int plan_m(int n) {
   return 0;
 }
 
-// x-pass lines per work-group
-inline int x_lines(int n, bool fp64) {
-  int g = n / plan_m(n);
-  int nl = (fp64 ? 64 : 128) / g;
+// x-pass lines per work-group. The FP32 forward pass holds the three CG
+// fields of its voxels in registers, which allows fewer of its work-groups per
+// CU: it takes half as many lines, so more, smaller work-groups overlap their
+// load and transform phases.
+constexpr int x_lines(int n, bool fp64, bool fwd) {
+  const int nl = ((fp64 ? 64 : 128) / (n / plan_m(n))) / (fwd && !fp64 ? 2 : 1);
   return nl < 1 ? 1 : nl;
 }
 

@@ -264,7 +264,7 @@ struct Group {
   c2<T>* tw[3] = {nullptr, nullptr, nullptr};
   int txy[2] = {4, 4}, txz[2] = {4, 4};  // [mech, thermal]
   int pt_bpp = 1;
-  int xblocks = 1;
+  int xfblocks = 1, xiblocks = 1;  // x-forward / x-inverse work-groups per problem
   hipGraphExec_t graph[2] = {nullptr, nullptr};
   int graph_k[2] = {0, 0};
   std::vector<std::array<double, 6>> En;
@@ -324,9 +324,10 @@ struct Group {
     // blocks per problem of the pointwise kernels
     pt_bpp = (int)std::min<long long>((nvox + 255) / 256, std::max<long long>(1, 8192 / nprob));
     pt_bpp = std::max(pt_bpp, 1);
-    const int nl = x_lines(nx, sizeof(T) == 8);
-    xblocks = (ny * nz + nl - 1) / nl;
-    maxblk = std::max(pt_bpp, xblocks);
+    const int nlf = x_lines(nx, sizeof(T) == 8, true), nli = x_lines(nx, sizeof(T) == 8, false);
+    xfblocks = (ny * nz + nlf - 1) / nlf;
+    xiblocks = (ny * nz + nli - 1) / nli;
+    maxblk = std::max(pt_bpp, std::max(xfblocks, xiblocks));
     part = dalloc<double>((size_t)nprob * maxblk * NPART);
     for (int d = 0; d < 3; ++d) {
       const int n = d == 0 ? nx : (d == 1 ? ny : nz);
@@ -406,11 +407,18 @@ class BatchT : public BatchImpl {
   hom_options opts;
   hipStream_t stream = nullptr;
   bool own_stream = false;
+  // side branch of an iteration: the alpha reduction overlaps the y / z passes
+  // (default priority, like every stream here)
+  hipStream_t side = nullptr;
+  hipEvent_t ev_fork = nullptr, ev_join = nullptr;
   Profiler prof;
   bool linear_mech = true;
 
   ~BatchT() override {
     groups.clear();
+    if (ev_fork) (void)hipEventDestroy(ev_fork);
+    if (ev_join) (void)hipEventDestroy(ev_join);
+    if (side) (void)hipStreamDestroy(side);
     if (own_stream && stream) (void)hipStreamDestroy(stream);
   }
 
@@ -444,6 +452,9 @@ class BatchT : public BatchImpl {
       HIPCHK(hipStreamCreateWithFlags(&stream, hipStreamNonBlocking));
       own_stream = true;
     }
+    HIPCHK(hipStreamCreateWithFlags(&side, hipStreamNonBlocking));
+    HIPCHK(hipEventCreateWithFlags(&ev_fork, hipEventDisableTiming));
+    HIPCHK(hipEventCreateWithFlags(&ev_join, hipEventDisableTiming));
     // group problems by grid
     std::map<std::tuple<int, int, int, double, double, double>, int> key;
     where.resize(nprob);
@@ -581,9 +592,14 @@ class BatchT : public BatchImpl {
     run_xfwd<T>(a, stream);
     prof.end(stream);
     if (!basic) {
-      prof.begin(K_REDALPHA, stream);
-      launch_reduce_alpha(ctl, G.part, G.maxblk, G.xblocks, G.nprob, stream);
-      prof.end(stream);
+      // alpha = r.r / p.C p is first needed by the x-inverse pass: reduce it on
+      // the side stream while the y / z passes run (they only read the mode)
+      HIPCHK(hipEventRecord(ev_fork, stream));
+      HIPCHK(hipStreamWaitEvent(side, ev_fork, 0));
+      prof.begin(K_REDALPHA, side);
+      launch_reduce_alpha(ctl, G.part, G.maxblk, G.xfblocks, G.nprob, side);
+      prof.end(side);
+      HIPCHK(hipEventRecord(ev_join, side));
     }
     prof.begin(K_YFWD, stream);
     run_ypass<T>(a, G.txy[phys], 0, stream);
@@ -594,11 +610,12 @@ class BatchT : public BatchImpl {
     prof.begin(K_YINV, stream);
     run_ypass<T>(a, G.txy[phys], 1, stream);
     prof.end(stream);
+    if (!basic) HIPCHK(hipStreamWaitEvent(stream, ev_join, 0));
     prof.begin(K_XINV, stream);
     run_xinv<T>(a, stream);
     prof.end(stream);
     prof.begin(K_REDA, stream);
-    launch_reduce_a(ctl, G.part, G.maxblk, G.xblocks, G.nprob, lim, stream);
+    launch_reduce_a(ctl, G.part, G.maxblk, G.xiblocks, G.nprob, lim, stream);
     prof.end(stream);
   }
 
