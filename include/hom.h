@@ -223,7 +223,9 @@ int hom_mlp_set_params(hom_mlp* net, const float* host, size_t count);
 int hom_mlp_train(hom_mlp* net, const float* x, const float* y, int64_t n, int32_t epochs, int32_t batch,
                   double lr, uint64_t seed, const float* row_weight, float* epoch_loss);
 /* Inference on device arrays x_dev [n][n_in] -> y_dev [n][n_out] on `stream`.
- * precise = 1 splits the weights into two bf16 parts (FP32-equivalent). */
+ * precise = 1 splits the weights into two bf16 parts (FP32-equivalent).
+ * Rows are independent (any n, a ragged last tile included); n = 0 returns
+ * HOM_OK without touching the arrays. */
 int hom_mlp_forward(hom_mlp* net, const float* x_dev, float* y_dev, int64_t n, int32_t precise, void* stream);
 /* Loss and its gradient w.r.t. all parameters for host rows (x, y); grad has
  * hom_mlp_param_count entries. */
@@ -231,7 +233,8 @@ int hom_mlp_loss_grad(hom_mlp* net, const float* x, const float* y, int64_t n, i
                       float* grad);
 /* Two-network inference with acceptance: y = mean of the two networks,
  * spread = |stress_a - stress_b| / max(|stress|, floor_scale) over the first
- * six outputs, accept = spread <= threshold. All arrays on the device. */
+ * six outputs, accept = spread <= threshold. All arrays on the device; n = 0
+ * returns HOM_OK without touching them. */
 int hom_surrogate_infer(hom_mlp* a, hom_mlp* b, const float* x_dev, float* y_dev, float* spread_dev,
                         uint8_t* accept_dev, int64_t n, double threshold, double floor_scale, void* stream);
 const char* hom_mlp_last_error(const hom_mlp* net);

@@ -238,7 +238,9 @@ int hom_mlp_train(hom_mlp* m, const float* x, const float* y, int64_t n, int32_t
 }
 
 int hom_mlp_forward(hom_mlp* m, const float* x_dev, float* y_dev, int64_t n, int32_t precise, void* stream) {
-  if (!m || !m->net || !x_dev || !y_dev || n < 0) return HOM_E_ARG;
+  if (!m || !m->net || n < 0) return HOM_E_ARG;
+  if (n == 0) return HOM_OK;  // nothing to do (the arrays may be empty)
+  if (!x_dev || !y_dev) return HOM_E_ARG;
   return guarded(&m->err, [&] {
     m->net->forward(x_dev, y_dev, n, precise != 0, false, static_cast<hipStream_t>(stream));
     hom::hip_check(hipGetLastError(), "mlp forward launch");
@@ -273,7 +275,9 @@ int hom_mlp_loss_grad(hom_mlp* m, const float* x, const float* y, int64_t n, int
 
 int hom_surrogate_infer(hom_mlp* a, hom_mlp* b, const float* x_dev, float* y_dev, float* spread_dev,
                         uint8_t* accept_dev, int64_t n, double threshold, double floor_scale, void* stream) {
-  if (!a || !b || !a->net || !b->net || !x_dev || !y_dev || !spread_dev || !accept_dev || n < 0) return HOM_E_ARG;
+  if (!a || !b || !a->net || !b->net || n < 0) return HOM_E_ARG;
+  if (n == 0) return HOM_OK;  // nothing to do (the arrays may be empty)
+  if (!x_dev || !y_dev || !spread_dev || !accept_dev) return HOM_E_ARG;
   return guarded(&a->err, [&] {
     if (a->net->n_in != b->net->n_in || a->net->n_out != b->net->n_out) hom::fail(HOM_E_ARG, "network shapes differ");
     if (n > a->scratch_rows) {
