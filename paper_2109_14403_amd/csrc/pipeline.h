@@ -111,21 +111,49 @@ template <typename T>
 struct Q4 {
   T v[4];
 };
+// Every field and spectrum element is touched once per pass, and a pass moves
+// far more data than the caches hold: the contiguous streaming accesses of the
+// x passes are non-temporal (on gfx950 a 1 GiB copy runs 5-15 % faster that
+// way). The y / z passes keep cached accesses: their tiles fill 128-byte lines
+// from neighbouring work-groups, which the L2 merges.
+typedef float nt_f2 __attribute__((ext_vector_type(2)));
+typedef float nt_f4 __attribute__((ext_vector_type(4)));
+typedef double nt_d2 __attribute__((ext_vector_type(2)));
+
 __device__ __forceinline__ Q4<float> ld4(const float* p) {
-  const float4 t = *reinterpret_cast<const float4*>(p);
+  const nt_f4 t = __builtin_nontemporal_load(reinterpret_cast<const nt_f4*>(p));
   return Q4<float>{{t.x, t.y, t.z, t.w}};
 }
 __device__ __forceinline__ Q4<double> ld4(const double* p) {
-  const double2 a = reinterpret_cast<const double2*>(p)[0];
-  const double2 b = reinterpret_cast<const double2*>(p)[1];
+  const nt_d2 a = __builtin_nontemporal_load(reinterpret_cast<const nt_d2*>(p));
+  const nt_d2 b = __builtin_nontemporal_load(reinterpret_cast<const nt_d2*>(p) + 1);
   return Q4<double>{{a.x, a.y, b.x, b.y}};
 }
 __device__ __forceinline__ void st4(float* p, const float (&v)[4]) {
-  *reinterpret_cast<float4*>(p) = make_float4(v[0], v[1], v[2], v[3]);
+  const nt_f4 t = {v[0], v[1], v[2], v[3]};
+  __builtin_nontemporal_store(t, reinterpret_cast<nt_f4*>(p));
 }
 __device__ __forceinline__ void st4(double* p, const double (&v)[4]) {
-  reinterpret_cast<double2*>(p)[0] = make_double2(v[0], v[1]);
-  reinterpret_cast<double2*>(p)[1] = make_double2(v[2], v[3]);
+  const nt_d2 a = {v[0], v[1]}, b = {v[2], v[3]};
+  __builtin_nontemporal_store(a, reinterpret_cast<nt_d2*>(p));
+  __builtin_nontemporal_store(b, reinterpret_cast<nt_d2*>(p) + 1);
+}
+// one complex value
+__device__ __forceinline__ c2<float> ldc(const c2<float>* p) {
+  const nt_f2 t = __builtin_nontemporal_load(reinterpret_cast<const nt_f2*>(p));
+  return mk(t.x, t.y);
+}
+__device__ __forceinline__ c2<double> ldc(const c2<double>* p) {
+  const nt_d2 t = __builtin_nontemporal_load(reinterpret_cast<const nt_d2*>(p));
+  return mk(t.x, t.y);
+}
+__device__ __forceinline__ void stc(c2<float>* p, c2<float> v) {
+  const nt_f2 t = {v.x, v.y};
+  __builtin_nontemporal_store(t, reinterpret_cast<nt_f2*>(p));
+}
+__device__ __forceinline__ void stc(c2<double>* p, c2<double> v) {
+  const nt_d2 t = {v.x, v.y};
+  __builtin_nontemporal_store(t, reinterpret_cast<nt_d2*>(p));
 }
 
 // Element v of a uniform base, with the byte offset formed in 32-bit unsigned
@@ -369,12 +397,13 @@ __global__ void __launch_bounds__((N / Plan<N>::M) * NL * ((C + 1) / 2)) k_xfwd(
       const int e = 2 * i;
       const int li = e / (H * C);
       const c2<T> u0 = value(e), u1 = value(e + 1);
-      *reinterpret_cast<float4*>(spec + li * rowp + (e - li * H * C)) = make_float4(u0.x, u0.y, u1.x, u1.y);
+      const nt_f4 t = {u0.x, u0.y, u1.x, u1.y};
+      __builtin_nontemporal_store(t, reinterpret_cast<nt_f4*>(spec + li * rowp + (e - li * H * C)));
     }
   } else {
     for (int e = tid; e < total; e += nth) {
       const int li = e / (H * C);
-      spec[li * rowp + (e - li * H * C)] = value(e);
+      stc(spec + li * rowp + (e - li * H * C), value(e));
     }
   }
 }
@@ -558,14 +587,14 @@ __global__ void __launch_bounds__((N / Plan<N>::M) * NL * ((C + 1) / 2)) k_xinv(
   if constexpr (sizeof(c2<T>) == 8 && C % 2 == 0) {
     constexpr int K = (NL * H * C / 2 + NTH - 1) / NTH;
     const int tot = nvl * H * C / 2;
-    const uint4* s4 = reinterpret_cast<const uint4*>(spec);
-    uint4* d4 = reinterpret_cast<uint4*>(buf);
-    uint4 t4[K];
+    const nt_f4* s4 = reinterpret_cast<const nt_f4*>(spec);
+    nt_f4* d4 = reinterpret_cast<nt_f4*>(buf);
+    nt_f4 t4[K];
 #pragma unroll
     for (int k = 0; k < K; ++k) {  // unconditional loads (index clamped in range), no branch between them
       const int e = 2 * min(tid + k * NTH, tot - 1);
       const int li = e / (H * C);
-      t4[k] = s4[(li * rowp + (e - li * H * C)) / 2];
+      t4[k] = __builtin_nontemporal_load(s4 + (li * rowp + (e - li * H * C)) / 2);
     }
     // unconditional writes too (else the compiler sinks each load into its
     // write's branch): a clamped thread rewrites the last element's own value
@@ -579,7 +608,7 @@ __global__ void __launch_bounds__((N / Plan<N>::M) * NL * ((C + 1) / 2)) k_xinv(
     for (int k = 0; k < K; ++k) {
       const int e = min(tid + k * NTH, tot - 1);
       const int li = e / (H * C);
-      t2[k] = spec[li * rowp + (e - li * H * C)];
+      t2[k] = ldc(spec + li * rowp + (e - li * H * C));
     }
 #pragma unroll
     for (int k = 0; k < K; ++k) buf[min(tid + k * NTH, tot - 1)] = t2[k];
