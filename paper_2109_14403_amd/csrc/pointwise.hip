@@ -8,6 +8,19 @@ namespace hom {
 
 constexpr int PT_THREADS = 256;
 
+// Streaming per-voxel data (fields, internal variables, increment slots) is
+// touched once per kernel: non-temporal accesses in the evaluation and the
+// history sums (the in-place commit of the internal variables measured faster
+// with cached accesses).
+template <typename T>
+__device__ __forceinline__ T ldnt(const T* p) {
+  return __builtin_nontemporal_load(p);
+}
+template <typename T>
+__device__ __forceinline__ void stnt(T* p, T v) {
+  __builtin_nontemporal_store(v, p);
+}
+
 // ---------------------------------------------------------------------------
 // PA66 law (paper Sec. 4) for one voxel, FP64, implicit Euler.
 //
@@ -104,22 +117,21 @@ __device__ __forceinline__ void pa66_history(const ProbInc& in, const double* st
   hs = 0.0;
   for (int i = 0; i < in.nm; ++i) {
     const double* ev = st + (7 + 6 * i) * ss;
-    const double v0 = ev[0], v1 = ev[ss], v2 = ev[2 * ss];
+    const double v0 = ldnt(ev), v1 = ldnt(ev + ss), v2 = ldnt(ev + 2 * ss);
     const double sn = (v0 + v1 + v2) * (1.0 / 3.0);
     const double w = in.G2i[i] * in.fG[i];
     hd[0] += w * (v0 - sn);
     hd[1] += w * (v1 - sn);
     hd[2] += w * (v2 - sn);
-    hd[3] += w * ev[3 * ss];
-    hd[4] += w * ev[4 * ss];
-    hd[5] += w * ev[5 * ss];
+    hd[3] += w * ldnt(ev + 3 * ss);
+    hd[4] += w * ldnt(ev + 4 * ss);
+    hd[5] += w * ldnt(ev + 5 * ss);
     hs += in.K3i[i] * in.fK[i] * sn;
   }
 }
 
-// Trial / final evaluation. If `hist` is non-null (trial only) the branch
-// history sums are read from it ([HIST_SLOTS][ss]: hd, hs, dp), else computed
-// from the state. `dp_slot`, if non-null, holds the plastic increment of the
+// Trial / final evaluation. If `hist` is non-null the branch history sums are
+// read from it ([HIST_SLOTS][ss]: hd, hs, dp), else computed from the state. `dp_slot`, if non-null, holds the plastic increment of the
 // voxel's previous evaluation in this increment (negative: none), the start
 // of the scalar Newton iteration; a trial evaluation stores its result there.
 // If `st_out` is non-null the new internal variables are written there and
@@ -135,15 +147,15 @@ __device__ void pa66_point(const ProbInc& in, const double* eps, const double* s
   d[0] -= tr3;
   d[1] -= tr3;
   d[2] -= tr3;
-  const double ep = st[0];
+  const double ep = ldnt(st);
   double evp[6];
 #pragma unroll
-  for (int c = 0; c < 6; ++c) evp[c] = st[(1 + c) * ss];
+  for (int c = 0; c < 6; ++c) evp[c] = ldnt(st + (1 + c) * ss);
   double hd[6], hs;
   if (hist) {
 #pragma unroll
-    for (int c = 0; c < 6; ++c) hd[c] = hist[c * ss];
-    hs = hist[6 * ss];
+    for (int c = 0; c < 6; ++c) hd[c] = ldnt(hist + c * ss);
+    hs = ldnt(hist + 6 * ss);
   } else {
     pa66_history(in, st, ss, hd, hs);
   }
@@ -277,10 +289,10 @@ __global__ void __launch_bounds__(PT_THREADS) k_eval(Pt<T> a) {
     T e[C];
 #pragma unroll
     for (int c = 0; c < C; ++c) {
-      T xv = a.x[fo + c * nv + v];
+      T xv = ldnt(a.x + fo + c * nv + v);
       if (pending) {
-        xv += alpha * a.p[fo + c * nv + v];
-        a.x[fo + c * nv + v] = xv;
+        xv += alpha * ldnt(a.p + fo + c * nv + v);
+        stnt(a.x + fo + c * nv + v, xv);
       }
       e[c] = xv;
     }
@@ -304,7 +316,7 @@ __global__ void __launch_bounds__(PT_THREADS) k_eval(Pt<T> a) {
         if (want_tan && cb != 0.0) {
           const long long no = (long long)prob * 6 * nv;
 #pragma unroll
-          for (int c = 0; c < 6; ++c) a.tn[no + c * nv + v] = T(o.nd[c]);
+          for (int c = 0; c < 6; ++c) stnt(a.tn + no + c * nv + v, T(o.nd[c]));
         }
       } else {
         const PhaseInc& pi = in.ph[ph];
@@ -318,15 +330,15 @@ __global__ void __launch_bounds__(PT_THREADS) k_eval(Pt<T> a) {
         ca = pi.G2;
       }
 #pragma unroll
-      for (int c = 0; c < 6; ++c) a.f[fo + c * nv + v] = T(sg[c]);
+      for (int c = 0; c < 6; ++c) stnt(a.f + fo + c * nv + v, T(sg[c]));
       if (want_tan) {
-        a.tab[to + v] = T(ca);
-        a.tab[to + nv + v] = T(cb);
+        stnt(a.tab + to + v, T(ca));
+        stnt(a.tab + to + nv + v, T(cb));
       }
     } else {
       const T kap = T(in.ph[ph].kappa);
 #pragma unroll
-      for (int c = 0; c < C; ++c) a.f[fo + c * nv + v] = kap * e[c];
+      for (int c = 0; c < C; ++c) stnt(a.f + fo + c * nv + v, kap * e[c]);
     }
   }
 }
@@ -345,9 +357,9 @@ __global__ void __launch_bounds__(PT_THREADS) k_history(Pt<T> a) {
     pa66_history(in, a.state + (long long)prob * a.nstate * nv + v, nv, hd, hs);
     double* h = a.hist + (long long)prob * HIST_SLOTS * nv + v;
 #pragma unroll
-    for (int c = 0; c < 6; ++c) h[c * nv] = hd[c];
-    h[6 * nv] = hs;
-    h[7 * nv] = -1.0;  // no plastic increment known yet
+    for (int c = 0; c < 6; ++c) stnt(h + c * nv, hd[c]);
+    stnt(h + 6 * nv, hs);
+    stnt(h + 7 * nv, -1.0);  // no plastic increment known yet
   }
 }
 
@@ -377,9 +389,12 @@ __global__ void __launch_bounds__(PT_THREADS) k_commit(Pt<T> a) {
       double sg[6], dis = 0.0, cpl;
       if (ph == in.pa_phase) {
         double* st = a.state + (long long)prob * a.nstate * nv + v;
+        // the branch history sums of this increment are in hist (the state
+        // has not changed since they were formed): one pass over the branches
+        const double* hs = a.hist ? a.hist + (long long)prob * HIST_SLOTS * nv + v : nullptr;
         double* dps = a.hist ? a.hist + (long long)prob * HIST_SLOTS * nv + v + 7 * nv : nullptr;
         PaOut o;
-        pa66_point(in, e, st, nv, st, en, o, &dis, &cpl, nullptr, dps);
+        pa66_point(in, e, st, nv, st, en, o, &dis, &cpl, hs, dps);
 #pragma unroll
         for (int c = 0; c < 6; ++c) sg[c] = o.sig[c];
       } else {
@@ -398,7 +413,7 @@ __global__ void __launch_bounds__(PT_THREADS) k_commit(Pt<T> a) {
 #pragma unroll
       for (int c = 0; c < 6; ++c) {
         acc[c] += sg[c];
-        a.xn[fo + c * nv + v] = a.x[fo + c * nv + v];
+        a.xn[fo + c * nv + v] = T(e[c]);  // the committed strain (exact: e was read from T)
         a.f[fo + c * nv + v] = T(sg[c]);
       }
       acc[6] += dis;
