@@ -69,9 +69,11 @@ def algorithmic_bytes(kind, n, fp_bytes, matrix_fraction):
     return None
 
 
-def cpu_baseline(phases, laws, sample="one CG pipeline application (tangent, FFT, projector, inverse FFT) "
-                                         "of the FP64 oracle on the full 256^3 grid"):
-    """The oracle as it stands, timed on this host: A p = P[C p] at full size."""
+def cpu_baseline(phases, laws, reps=2,
+                 sample="two CG pipeline applications (tangent, FFT, projector, inverse FFT) "
+                        "of the FP64 oracle on the full 256^3 grid"):
+    """The oracle as it stands, timed on this host: A p = P[C p] at full size,
+    applied `reps` times in a row (about 13 s of single-threaded numpy)."""
     from oracle import solver
 
     cell = solver.Cell(phases, laws)
@@ -89,10 +91,12 @@ def cpu_baseline(phases, laws, sample="one CG pipeline application (tangent, FFT
         tan[:, :, cell.masks[i]] = C[:, :, None]
     p = rng.normal(size=(6,) + shape)
     t0 = time.perf_counter()
-    ap = cell.project(np.einsum("ab...,b...->a...", tan, p))
-    _ = float((p * ap).sum())
+    for _ in range(reps):
+        ap = cell.project(np.einsum("ab...,b...->a...", tan, p))
+        _ = float((p * ap).sum())
+        p = ap
     dt = time.perf_counter() - t0
-    return {"value": float(np.prod(shape)) / dt, "unit": "voxel-iters/s", "cores": 1, "kind": "oracle",
+    return {"value": reps * float(np.prod(shape)) / dt, "unit": "voxel-iters/s", "cores": 1, "kind": "oracle",
             "sample": sample, "seconds": dt}
 
 
