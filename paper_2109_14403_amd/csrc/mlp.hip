@@ -3,8 +3,8 @@
 // Forward: one work-group of 4 waves per 64 rows; every layer is a
 // [64 x K] x [K x 256] product on the bf16 matrix cores
 // (v_mfma_f32_16x16x32_bf16, FP32 accumulation). Weights are bf16; the
-// activations are split into bf16 hi + lo parts (two MFMAs per tile), so the
-// product sees the activations to ~16 significant bits. In "precise" mode the
+// activations are kept in LDS split into bf16 hi + lo parts (two MFMAs per
+// tile), so the product sees the activations to ~16 significant bits. In "precise" mode the
 // weights are split as well (three MFMAs: a_hi w_hi + a_lo w_hi + a_hi w_lo),
 // which reproduces FP32 weights for gradient checks. Bias and GELU are fused
 // into the epilogue; the layer output stays in LDS for the next layer.
@@ -28,8 +28,8 @@ namespace hom {
 typedef __bf16 bf16x8_t __attribute__((ext_vector_type(8)));
 typedef float floatx4_t __attribute__((ext_vector_type(4)));
 
-constexpr int MROWS = 64;     // rows per forward work-group
-constexpr int ASTRIDE = 264;  // LDS row stride of the activation tile (floats)
+constexpr int MROWS = 64;  // rows per forward work-group
+constexpr int AST = 264;   // LDS row stride of the bf16 activation tiles (16-byte aligned rows)
 
 __device__ __forceinline__ float gelu_f(float z) { return 0.5f * z * (1.0f + erff(z * 0.70710678118654752f)); }
 __device__ __forceinline__ float gelu_prime_f(float z) {
@@ -57,9 +57,13 @@ struct FwdArgs {
 };
 
 template <int PRECISE>
-__global__ void __launch_bounds__(256) k_mlp_fwd(FwdArgs a) {
-  __shared__ float act[MROWS * ASTRIDE];
-  __shared__ float xin[MROWS * (MLP_IN + 1)];  // normalized inputs, kept for the linear skip
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) k_mlp_fwd(FwdArgs a) {
+  // The tile's activations live in LDS already split into bf16 hi + lo: each
+  // value is split once, by the lane that produced it, and every wave reads
+  // its MFMA fragments directly.
+  __shared__ __attribute__((aligned(16))) __bf16 ahi[MROWS * AST];
+  __shared__ __attribute__((aligned(16))) __bf16 alo[MROWS * AST];
+  __shared__ float xin[MROWS * (MLP_IN + 1)];  // normalized inputs, kept for the skip
   const int tid = threadIdx.x;
   const int wave = tid >> 6;
   const int lane = tid & 63;
@@ -69,7 +73,9 @@ __global__ void __launch_bounds__(256) k_mlp_fwd(FwdArgs a) {
     const long long gr = row0 + r;
     float v = 0.0f;
     if (gr < a.n && k < a.n_in) v = (a.x[gr * a.n_in + k] - a.xmean[k]) * a.xinv[k];
-    act[r * ASTRIDE + k] = v;
+    const __bf16 h = (__bf16)v;
+    ahi[r * AST + k] = h;
+    alo[r * AST + k] = (__bf16)(v - (float)h);
     xin[r * (MLP_IN + 1) + k] = v;
     if (a.xs && gr < a.n) a.xs[gr * MLP_IN + k] = v;
   }
@@ -86,31 +92,53 @@ __global__ void __launch_bounds__(256) k_mlp_fwd(FwdArgs a) {
     for (int i = 0; i < 4; ++i)
 #pragma unroll
       for (int j = 0; j < 4; ++j) acc[i][j] = floatx4_t{0.f, 0.f, 0.f, 0.f};
+    bf16x8_t bh[4], bl[4];
+#pragma unroll
+    for (int cb = 0; cb < 4; ++cb) {
+      const long long nn = wave * 64 + cb * 16 + lrow;
+      bh[cb] = *reinterpret_cast<const bf16x8_t*>(whi + nn * K + kq);
+      if constexpr (PRECISE) bl[cb] = *reinterpret_cast<const bf16x8_t*>(wlo + nn * K + kq);
+    }
     for (int k0 = 0; k0 < K; k0 += 32) {
-      bf16x8_t ahi[4], alo[4];
+      bf16x8_t xh[4], xl[4];
 #pragma unroll
       for (int rb = 0; rb < 4; ++rb) {
-        const float* src = act + (rb * 16 + lrow) * ASTRIDE + k0 + kq;
+        const int o = (rb * 16 + lrow) * AST + k0 + kq;
+        xh[rb] = *reinterpret_cast<const bf16x8_t*>(ahi + o);
+        xl[rb] = *reinterpret_cast<const bf16x8_t*>(alo + o);
+      }
+      // weights of the next k-step in flight during this step's products
+      const int k1 = k0 + 32 < K ? k0 + 32 : k0;
+      bf16x8_t nh[4], nl[4];
 #pragma unroll
-        for (int e = 0; e < 8; ++e) {
-          const float v = src[e];
-          const __bf16 h = (__bf16)v;
-          ahi[rb][e] = h;
-          alo[rb][e] = (__bf16)(v - (float)h);
-        }
+      for (int cb = 0; cb < 4; ++cb) {
+        const long long nn = wave * 64 + cb * 16 + lrow;
+        nh[cb] = *reinterpret_cast<const bf16x8_t*>(whi + nn * K + k1 + kq);
+        if constexpr (PRECISE) nl[cb] = *reinterpret_cast<const bf16x8_t*>(wlo + nn * K + k1 + kq);
+      }
+      // hi and lo passes over all 16 tiles: no product waits on the previous
+      // one into the same accumulator
+#pragma unroll
+      for (int rb = 0; rb < 4; ++rb)
+#pragma unroll
+        for (int cb = 0; cb < 4; ++cb)
+          acc[rb][cb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(xh[rb], bh[cb], acc[rb][cb], 0, 0, 0);
+#pragma unroll
+      for (int rb = 0; rb < 4; ++rb)
+#pragma unroll
+        for (int cb = 0; cb < 4; ++cb)
+          acc[rb][cb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(xl[rb], bh[cb], acc[rb][cb], 0, 0, 0);
+      if constexpr (PRECISE) {
+#pragma unroll
+        for (int rb = 0; rb < 4; ++rb)
+#pragma unroll
+          for (int cb = 0; cb < 4; ++cb)
+            acc[rb][cb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(xh[rb], bl[cb], acc[rb][cb], 0, 0, 0);
       }
 #pragma unroll
       for (int cb = 0; cb < 4; ++cb) {
-        const int nn = wave * 64 + cb * 16 + lrow;
-        const bf16x8_t bh = *reinterpret_cast<const bf16x8_t*>(whi + (long long)nn * K + k0 + kq);
-        bf16x8_t bl;
-        if (PRECISE) bl = *reinterpret_cast<const bf16x8_t*>(wlo + (long long)nn * K + k0 + kq);
-#pragma unroll
-        for (int rb = 0; rb < 4; ++rb) {
-          acc[rb][cb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ahi[rb], bh, acc[rb][cb], 0, 0, 0);
-          acc[rb][cb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(alo[rb], bh, acc[rb][cb], 0, 0, 0);
-          if (PRECISE) acc[rb][cb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ahi[rb], bl, acc[rb][cb], 0, 0, 0);
-        }
+        bh[cb] = nh[cb];
+        if constexpr (PRECISE) bl[cb] = nl[cb];
       }
     }
     __syncthreads();  // all waves done reading this layer's input
@@ -125,7 +153,9 @@ __global__ void __launch_bounds__(256) k_mlp_fwd(FwdArgs a) {
           const int nn = wave * 64 + cb * 16 + lrow;
           const float z = acc[rb][cb][i] + bias[nn];
           const float g = gelu_f(z);
-          act[m * ASTRIDE + nn] = g;
+          const __bf16 h = (__bf16)g;
+          ahi[m * AST + nn] = h;
+          alo[m * AST + nn] = (__bf16)(g - (float)h);
           const long long gr = row0 + m;
           if (a.zs[l] && gr < a.n) {
             a.zs[l][gr * MLP_W + nn] = z;
@@ -141,21 +171,15 @@ __global__ void __launch_bounds__(256) k_mlp_fwd(FwdArgs a) {
     const __bf16* wlo = a.wlo[l];
     floatx4_t acc = floatx4_t{0.f, 0.f, 0.f, 0.f};
     for (int k0 = 0; k0 < MLP_W; k0 += 32) {
-      bf16x8_t ahi, alo;
-      const float* src = act + (wave * 16 + lrow) * ASTRIDE + k0 + kq;
-#pragma unroll
-      for (int e = 0; e < 8; ++e) {
-        const float v = src[e];
-        const __bf16 h = (__bf16)v;
-        ahi[e] = h;
-        alo[e] = (__bf16)(v - (float)h);
-      }
+      const int o = (wave * 16 + lrow) * AST + k0 + kq;
+      const bf16x8_t xh = *reinterpret_cast<const bf16x8_t*>(ahi + o);
+      const bf16x8_t xl = *reinterpret_cast<const bf16x8_t*>(alo + o);
       const bf16x8_t bh = *reinterpret_cast<const bf16x8_t*>(whi + (long long)lrow * MLP_W + k0 + kq);
-      acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ahi, bh, acc, 0, 0, 0);
-      acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(alo, bh, acc, 0, 0, 0);
-      if (PRECISE) {
+      acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(xh, bh, acc, 0, 0, 0);
+      acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(xl, bh, acc, 0, 0, 0);
+      if constexpr (PRECISE) {
         const bf16x8_t bl = *reinterpret_cast<const bf16x8_t*>(wlo + (long long)lrow * MLP_W + k0 + kq);
-        acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ahi, bl, acc, 0, 0, 0);
+        acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(xh, bl, acc, 0, 0, 0);
       }
     }
 #pragma unroll
