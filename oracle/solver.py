@@ -190,9 +190,10 @@ class Cell:
             eps, info = self._basic(eps, theta, dt, tol, maxit)
         else:
             eps, info = self._newton(eps, theta, dt, tol, max_newton, cg_rtol)
-        sig, _, diss, coup, new_state = self.evaluate(eps, theta, dt, with_tangent=False)
+        sig, tan, diss, coup, new_state = self.evaluate(eps, theta, dt, with_tangent=True)
         q, th_its = self._thermal(grad, scheme, tol if thermal_tol is None else thermal_tol, maxit)
-        self.last = dict(eps=eps, sigma=sig, dissipation=diss, coupling=coup)
+        # the algorithmic tangent field at the converged strain (state n, before the commit)
+        self.last = dict(eps=eps, sigma=sig, dissipation=diss, coupling=coup, tangent=tan)
         self.eps_n = eps
         self.E_n = E
         self.state.update(new_state)
@@ -208,23 +209,36 @@ class Cell:
         return out
 
     # ---- linear effective properties -------------------------------------
-    def effective_stiffness(self, tol=1e-12):
-        """6 x 6 Mandel effective stiffness at the reference temperature of the
-        thermoelastic phases (all laws linear), by six unit macro strains."""
+    def homogenized_tangent(self, C, tol=1e-12):
+        """Effective 6 x 6 Mandel matrix of a local linear map C(x) (6, 6, ...):
+        for each unit macro strain E_j, the compatible fluctuation d solves
+        P[C (E_j + d)] = 0 (Sec. 2, cell problem, linearized), and column j is
+        <C (E_j + d)>."""
+        apply_C = lambda v: np.einsum("ab...,b...->a...", C, v)
         Cbar = np.zeros((6, 6))
         for j in range(6):
             E = np.zeros(6)
             E[j] = 1.0
             eps = np.broadcast_to(E[:, None, None, None], (6,) + self.shape).copy()
-            C = np.zeros((6, 6) + self.shape)
-            for i, law in enumerate(self.laws):
-                C[:, :, self.masks[i]] = law.C[:, :, None]
-            apply_C = lambda v: np.einsum("ab...,b...->a...", C, v)
             b = -self.project(apply_C(eps))
             d, _ = conjugate_gradient(lambda v: self.project(apply_C(v)), b, rtol=tol)
-            sig = apply_C(eps + d)
-            Cbar[:, j] = sig.reshape(6, -1).mean(axis=1)
+            Cbar[:, j] = apply_C(eps + d).reshape(6, -1).mean(axis=1)
         return Cbar
+
+    def effective_stiffness(self, tol=1e-12):
+        """6 x 6 Mandel effective stiffness of the thermoelastic phases (all
+        laws linear), by six unit macro strains."""
+        C = np.zeros((6, 6) + self.shape)
+        for i, law in enumerate(self.laws):
+            C[:, :, self.masks[i]] = law.C[:, :, None]
+        return self.homogenized_tangent(C, tol)
+
+    def algorithmic_tangent(self, tol=1e-12):
+        """d<sigma>/dE (6 x 6 Mandel) at the converged state of the last
+        increment: the homogenized algorithmic tangent of the local laws
+        (the effective algorithmic tangent a macroscopic Newton method needs,
+        Sec. 3.3)."""
+        return self.homogenized_tangent(self.last["tangent"], tol)
 
     def effective_conductivity(self, tol=1e-12):
         kb = np.zeros((3, 3))
