@@ -192,8 +192,10 @@ class Cell:
             eps, info = self._newton(eps, theta, dt, tol, max_newton, cg_rtol)
         sig, tan, diss, coup, new_state = self.evaluate(eps, theta, dt, with_tangent=True)
         q, th_its = self._thermal(grad, scheme, tol if thermal_tol is None else thermal_tol, maxit)
-        # the algorithmic tangent field at the converged strain (state n, before the commit)
-        self.last = dict(eps=eps, sigma=sig, dissipation=diss, coupling=coup, tangent=tan)
+        # the algorithmic tangent field at the converged strain and what the
+        # point partials need (state n and eps^n, before the commit)
+        self.last = dict(eps=eps, sigma=sig, dissipation=diss, coupling=coup, tangent=tan,
+                         eps_n=self.eps_n, state_n=dict(self.state), theta=theta, dt=dt)
         self.eps_n = eps
         self.E_n = E
         self.state.update(new_state)
@@ -209,21 +211,91 @@ class Cell:
         return out
 
     # ---- linear effective properties -------------------------------------
+    def linearized_solve(self, C, E, s0=None, tol=1e-12):
+        """Strain field x with mean E (Mandel) and a compatible fluctuation d
+        that solves the linearized cell problem P[C x + s0] = 0 (Sec. 2, cell
+        problem; Sec. 3.3, the linear systems of the strain-jump derivatives,
+        with the voxels in place of the DMN phases). Returns (x, C x + s0)."""
+        apply_C = lambda v: np.einsum("ab...,b...->a...", C, v)
+        eps = np.broadcast_to(np.asarray(E, dtype=np.float64)[:, None, None, None], (6,) + self.shape).copy()
+        rhs = apply_C(eps) if s0 is None else apply_C(eps) + s0
+        d, _ = conjugate_gradient(lambda v: self.project(apply_C(v)), -self.project(rhs), rtol=tol)
+        x = eps + d
+        return x, apply_C(x) if s0 is None else apply_C(x) + s0
+
     def homogenized_tangent(self, C, tol=1e-12):
         """Effective 6 x 6 Mandel matrix of a local linear map C(x) (6, 6, ...):
-        for each unit macro strain E_j, the compatible fluctuation d solves
-        P[C (E_j + d)] = 0 (Sec. 2, cell problem, linearized), and column j is
-        <C (E_j + d)>."""
-        apply_C = lambda v: np.einsum("ab...,b...->a...", C, v)
+        column j is <C x_j> for the solution x_j with mean E_j (unit macro
+        strain j)."""
         Cbar = np.zeros((6, 6))
         for j in range(6):
             E = np.zeros(6)
             E[j] = 1.0
-            eps = np.broadcast_to(E[:, None, None, None], (6,) + self.shape).copy()
-            b = -self.project(apply_C(eps))
-            d, _ = conjugate_gradient(lambda v: self.project(apply_C(v)), b, rtol=tol)
-            Cbar[:, j] = apply_C(eps + d).reshape(6, -1).mean(axis=1)
+            Cbar[:, j] = self.linearized_solve(C, E, tol=tol)[1].reshape(6, -1).mean(axis=1)
         return Cbar
+
+    def point_partials(self, h_eps=1e-6, h_theta=1e-3):
+        """Per-voxel partial derivatives of the local laws at the converged
+        strain of the last increment, from state n: d sigma / d theta (6,
+        Mandel), d D / d eps (6, Mandel) and d D / d theta of the coupling
+        term D. Thermoelastic phases in closed form; the PA66 law by central
+        differences of its implicit Euler update, steps h_eps (Mandel strain)
+        and h_theta [K]."""
+        L = self.last
+        eps, eps_n, theta, dt = L["eps"], L["eps_n"], L["theta"], L["dt"]
+        dsdt = np.zeros((6,) + self.shape)
+        dDde = np.zeros((6,) + self.shape)
+        dDdt = np.zeros(self.shape)
+        for i, law in enumerate(self.laws):
+            msk = self.masks[i]
+            if not msk.any():
+                continue
+            e = eps[:, msk]
+            en = eps_n[:, msk]
+            if law.inelastic:
+                st = L["state_n"][i]
+                up = law.update(e, en, st, theta + h_theta, dt)
+                dn = law.update(e, en, st, theta - h_theta, dt)
+                dsdt[:, msk] = (up["sigma"] - dn["sigma"]) / (2.0 * h_theta)
+                dDdt[msk] = (up["coupling"] - dn["coupling"]) / (2.0 * h_theta)
+                for c in range(6):
+                    ep = e.copy()
+                    em = e.copy()
+                    ep[c] += h_eps
+                    em[c] -= h_eps
+                    Dp = law.update(ep, en, st, theta, dt)["coupling"]
+                    Dm = law.update(em, en, st, theta, dt)["coupling"]
+                    dDde[c, msk] = (Dp - Dm) / (2.0 * h_eps)
+            else:
+                Ca = law.C @ law.alpha                 # C[alpha]
+                dsdt[:, msk] = -Ca[:, None]
+                dDde[:, msk] = (-theta / dt) * Ca[:, None]
+                dDdt[msk] = -(Ca @ (e - en)) / dt
+        return dsdt, dDde, dDdt
+
+    def algorithmic_tangents(self, tol=1e-12, h_eps=1e-6, h_theta=1e-3):
+        """The four effective algorithmic tangents of the last increment
+        (Sec. 3.3, derivatives of the effective stress and coupling term with
+        respect to the macro strain and temperature), Mandel components:
+        dsde (6, 6) = d<sigma>/dE, dsdt (6,) = d<sigma>/dtheta,
+        dDde (6,) = d<D>/dE, dDdt = d<D>/dtheta. The strain-jump derivatives
+        of the paper become the fluctuation fields of the linearized cell
+        problem: x_j (mean E_j) for dE_j and x_t (mean 0, source d sigma /
+        d theta) for dtheta, all with the converged algorithmic tangent."""
+        C = self.last["tangent"]
+        dsdt_v, dDde_v, dDdt_v = self.point_partials(h_eps, h_theta)
+        dsde = np.zeros((6, 6))
+        dDde = np.zeros(6)
+        for j in range(6):
+            E = np.zeros(6)
+            E[j] = 1.0
+            x, s = self.linearized_solve(C, E, tol=tol)
+            dsde[:, j] = s.reshape(6, -1).mean(axis=1)
+            dDde[j] = (dDde_v * x).sum(axis=0).mean()
+        x, s = self.linearized_solve(C, np.zeros(6), s0=dsdt_v, tol=tol)
+        dsdt = s.reshape(6, -1).mean(axis=1)
+        dDdt = float((dDdt_v + (dDde_v * x).sum(axis=0)).mean())
+        return dict(dsde=dsde, dsdt=dsdt, dDde=dDde, dDdt=dDdt)
 
     def effective_stiffness(self, tol=1e-12):
         """6 x 6 Mandel effective stiffness of the thermoelastic phases (all
