@@ -399,6 +399,42 @@ def mfma_summary(folder, command):
     print("\n".join(lines))
 
 
+def tangent_bench(ctx, wl, nvox, warmup, total):
+    """d<sigma>/dE of the last timed increment: six linearized cell solves
+    (hom_algorithmic_tangent, what = 0), timed around the synchronous call."""
+    t0 = time.perf_counter()
+    t = ctx.algorithmic_tangent(what=0)
+    el = time.perf_counter() - t0
+    return {"dsde_ms": round(el * 1e3, 2), "dsde_solves": t["solves"], "dsde_krylov": t["krylov_iters"],
+            "dsde_pipelines": t["pipelines"], "dsde_voxel_iters_per_s": round(t["pipelines"] * nvox / el, 1),
+            "increment": total - 1}
+
+
+def tangent_full_bench(wl, nvox, warmup):
+    """All four tangents on a context set up with the tangent option: the
+    first warmup + 1 increments (the last one timed, with the point-partials
+    pass before its commit), then seven linearized solves."""
+    import torch
+    from paper_2109_14403_amd import hom
+    ctx = hom.Context(wl.phases, wl.laws, scheme=hom.SCHEME_NEWTON_CG, precision=hom.FP32, tol=1e-6,
+                      autotune=1, tangent=1)
+    for st in wl.history[:warmup]:
+        ctx.solve_increment(st.strain, st.theta, st.grad, st.dt)
+    st = wl.history[warmup]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    r = ctx.solve_increment(st.strain, st.theta, st.grad, st.dt)
+    inc_s = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    t = ctx.algorithmic_tangent(what=1)
+    el = time.perf_counter() - t0
+    ctx.close()
+    return {"all_ms": round(el * 1e3, 2), "all_solves": t["solves"], "all_krylov": t["krylov_iters"],
+            "all_pipelines": t["pipelines"], "increment_with_partials_ms": round(inc_s * 1e3, 2),
+            "increment_with_partials_pipelines": r["pipelines"],
+            "dsdt": [round(v, 6) for v in t["dsdt"]], "dDdt": t["dDdt"]}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -409,6 +445,7 @@ def main():
     ap.add_argument("--no-profile", action="store_true")
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--no-surrogate", action="store_true")
+    ap.add_argument("--no-tangent", action="store_true")
     ap.add_argument("--calib-copy", action="store_true", help="run a 1 GiB device copy (PMC calibration)")
     ap.add_argument("--pmc-summary", nargs="+", metavar="DIR",
                     help="summarize rocprofv3 --pmc output folders (FETCH_SIZE, WRITE_SIZE[, request sizes]) "
@@ -535,7 +572,14 @@ def main():
                     "traffic_request_sized": traffic_req, "kernel": dom,
                     "avg_launch_ms": round(avg_s * 1e3, 4), "algorithmic_bytes": byt}
 
+    tangent = None
+    if not args.no_tangent:
+        tangent = tangent_bench(ctx, wl, nvox, args.warmup, total)
+        print(f"tangent: {tangent}", file=sys.stderr, flush=True)
     ctx.close()
+    if tangent is not None:
+        tangent.update(tangent_full_bench(wl, nvox, args.warmup))
+        print(f"tangent (all four): {tangent}", file=sys.stderr, flush=True)
     copy_gbs = copy_probe()
     batch = None
     if not args.no_batch:
@@ -562,6 +606,7 @@ def main():
         "thermal_voxel_iters_per_s": round(tpipes * nvox / elapsed, 1),
         "newton_per_step": newton / args.steps, "krylov_per_step": krylov / args.steps,
         "roofline": roof, "copy_probe_gbs": copy_gbs, "cpu_baseline": cpu, "batch": batch, "surrogate": surr,
+        "tangent": tangent,
     }
     if kstats:
         line["kernel_ms"] = {k: [v[0], round(v[1], 3)] for k, v in kstats.items() if v[0]}

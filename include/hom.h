@@ -99,6 +99,10 @@ typedef struct {
   int32_t profile;     /* 1: time every kernel launch with HIP events */
   int32_t autotune;    /* 1: time the tile choices of the y/z passes at setup */
   void* stream;        /* hipStream_t to run on; NULL => a stream owned by the context */
+  int32_t tangent;     /* 1: keep the per-voxel partials of each converged increment that the
+                          temperature and coupling tangents need (hom_algorithmic_tangent,
+                          what = 1); costs 13 field components of memory and one pass of
+                          14 PA66 point evaluations per increment */
 } hom_options;
 
 /* Macroscopic temperature input: theta [K] and its gradient [K/m]. */
@@ -163,6 +167,38 @@ int hom_kernel_stats(const hom_ctx* ctx, const char** names, int64_t* launches, 
  * accumulated statistics are reset. While on, chunks run eagerly (no graph). */
 int hom_set_profiling(hom_ctx* ctx, int32_t on);
 
+/* Effective algorithmic tangents of the last converged increment: the
+ * derivatives of the effective stress and coupling term with respect to the
+ * macro strain and temperature that a macroscopic Newton method needs
+ * (Sec. 3.3, computed after Newton's method has converged). The derivatives
+ * of the paper's strain jumps become the fluctuation fields of the cell
+ * problem linearized at the converged strain with the algorithmic tangent of
+ * the local laws: one linear CG solve through the FFT pipeline per unit macro
+ * strain, and one with mean zero driven by d sigma / d theta. Point partials
+ * that the paper leaves to the law (d sigma / d theta, dD / d eps,
+ * dD / d theta) are closed-form for thermoelastic phases and FP64 central
+ * differences of the PA66 update (steps 1e-6 in Mandel strain, 1e-3 K).
+ *
+ * Strain derivatives are taken with respect to the 6 strain components that
+ * hom_solve_increment takes (tensorial shear: the component eps_23 moves
+ * eps_23 and eps_32 together), stress components as in hom_result.
+ * what = 0: dsde only (6 solves), the other fields are set to NaN;
+ * what = 1: all four (7 solves); needs a setup with opts.tangent = 1.
+ * Needs the Newton-CG scheme and a converged last increment (for a batch:
+ * every problem's), else HOM_E_UNSUPPORTED / HOM_E_ARG. The strain and stress
+ * fields of the increment are left as they were; the calls may be repeated. */
+typedef struct {
+  double dsde[36];       /* d<sigma>_I / dE_J, row-major [I][J] */
+  double dsdt[6];        /* d<sigma>_I / dtheta [MPa/K] */
+  double dDde[6];        /* d<D> / dE_J [MPa/s] */
+  double dDdt;           /* d<D> / dtheta [MPa/(s K)] */
+  int32_t solves;        /* linearized cell solves */
+  int32_t krylov_iters;  /* CG iterations over the solves */
+  double pipelines;      /* FFT pipeline applications over the solves */
+  int32_t status;        /* HOM_OK */
+} hom_tangent;
+int hom_algorithmic_tangent(hom_ctx* ctx, int32_t what, hom_tangent* out);
+
 /* Bytes of device memory held by the context. */
 size_t hom_device_bytes(const hom_ctx* ctx);
 
@@ -179,6 +215,8 @@ int hom_batch_setup(int32_t n_prob, const hom_grid* grids, const uint8_t* const*
 int hom_batch_solve_increment(hom_batch* b, const double* strain, const hom_macro_temp* temp, const double* dt,
                               hom_result* out);
 int hom_batch_kernel_stats(const hom_batch* b, const char** names, int64_t* launches, double* ms, int32_t cap);
+/* hom_algorithmic_tangent for every problem of a batch; out: n_prob entries. */
+int hom_batch_algorithmic_tangent(hom_batch* b, int32_t what, hom_tangent* out);
 const char* hom_batch_last_error(const hom_batch* b);
 void hom_batch_destroy(hom_batch* b);
 

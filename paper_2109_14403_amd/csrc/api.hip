@@ -137,6 +137,11 @@ int hom_set_profiling(hom_ctx* c, int32_t on) {
   return guarded(&c->err, [&] { c->impl->set_profiling(on != 0); });
 }
 
+int hom_algorithmic_tangent(hom_ctx* c, int32_t what, hom_tangent* out) {
+  if (!c || !c->impl || !out) return HOM_E_ARG;
+  return guarded(&c->err, [&] { c->impl->tangent(what, out); });
+}
+
 size_t hom_device_bytes(const hom_ctx* c) { return (c && c->impl) ? c->impl->device_bytes() : 0; }
 
 const char* hom_last_error(const hom_ctx* c) { return c ? c->err.c_str() : g_setup_error.c_str(); }
@@ -171,6 +176,11 @@ int hom_batch_solve_increment(hom_batch* b, const double* strain, const hom_macr
 
 int hom_batch_kernel_stats(const hom_batch* b, const char** names, int64_t* launches, double* ms, int32_t cap) {
   return stats(b ? b->impl.get() : nullptr, names, launches, ms, cap);
+}
+
+int hom_batch_algorithmic_tangent(hom_batch* b, int32_t what, hom_tangent* out) {
+  if (!b || !b->impl || !out) return HOM_E_ARG;
+  return guarded(&b->err, [&] { b->impl->tangent(what, out); });
 }
 
 const char* hom_batch_last_error(const hom_batch* b) { return b ? b->err.c_str() : g_setup_error.c_str(); }

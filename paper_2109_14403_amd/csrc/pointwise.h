@@ -33,7 +33,19 @@ struct Pt {
   int maxblk;
   double* pv_diss;          // optional per-voxel dissipation at commit
   double* pv_coup;          // optional per-voxel coupling term at commit
+  // effective algorithmic tangents: per-voxel partials at the converged
+  // strain of an increment (state n), written by the partials kernel
+  T* dsdt;                  // d sigma / d theta   [prob][6][nvox] (Mandel), or null
+  T* dDde;                  // d D / d eps         [prob][6][nvox] (Mandel)
+  T* dDdt;                  // d D / d theta       [prob][nvox]
+  const ProbInc* inc_pm;    // [prob][2]: increment data at theta + h_theta, theta - h_theta
+  const T* s0;              // source of a linearized evaluation (sigma = C x + s0), or null
 };
+
+// Central-difference steps of the PA66 point partials: Mandel strain and
+// temperature [K].
+constexpr double FD_H_EPS = 1e-6;
+constexpr double FD_H_THETA = 1e-3;
 
 struct Limits {
   double tol;
@@ -52,6 +64,18 @@ template <typename T>
 void launch_init_th(const Pt<T>& a, int scheme, hipStream_t s);
 template <typename T>
 void launch_eval(const Pt<T>& a, int C, hipStream_t s);
+// sigma = C_algo x (+ s0) with the algorithmic tangent of the last Newton
+// evaluation; the tangent fields are read, not written (mechanics only)
+template <typename T>
+void launch_eval_linear(const Pt<T>& a, hipStream_t s);
+// x = dE (uniform) and a fresh Newton state: the start of a linearized solve
+template <typename T>
+void launch_init_linear(const Pt<T>& a, hipStream_t s);
+template <typename T>
+void launch_partials(const Pt<T>& a, hipStream_t s);
+// per-block sums of the stress (6), dD/deps . x and dD/dtheta of converged problems
+template <typename T>
+void launch_tangent_sum(const Pt<T>& a, hipStream_t s);
 template <typename T>
 void launch_history(const Pt<T>& a, hipStream_t s);
 void launch_reduce_a(Ctl* ctl, const double* part, int maxblk, int nblk, int nprob, Limits lim, hipStream_t s);

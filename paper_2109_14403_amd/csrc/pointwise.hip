@@ -131,11 +131,12 @@ __device__ __forceinline__ void pa66_history(const ProbInc& in, const double* st
 }
 
 // Trial / final evaluation. If `hist` is non-null the branch history sums are
-// read from it ([HIST_SLOTS][ss]: hd, hs, dp), else computed from the state. `dp_slot`, if non-null, holds the plastic increment of the
-// voxel's previous evaluation in this increment (negative: none), the start
-// of the scalar Newton iteration; a trial evaluation stores its result there.
-// If `st_out` is non-null the new internal variables are written there and
-// the dissipation and coupling computed.
+// read from it ([HIST_SLOTS][ss]: hd, hs, dp), else computed from the state.
+// `dp_slot`, if non-null, holds the plastic increment of the voxel's previous
+// evaluation in this increment (negative: none), the start of the scalar
+// Newton iteration; a trial evaluation stores its result there. If `diss` is
+// non-null the dissipation and coupling term are computed, and if `st_out`
+// is non-null too the new internal variables are written there.
 __device__ void pa66_point(const ProbInc& in, const double* eps, const double* st, long long ss, double* st_out,
                            const double* eps_n, PaOut& o, double* diss, double* coup,
                            const double* hist = nullptr, double* dp_slot = nullptr) {
@@ -190,7 +191,7 @@ __device__ void pa66_point(const ProbInc& in, const double* eps, const double* s
   o.a = in.Gbar2 * th1;
   o.b = in.Gbar2 * (cp - th1);
   o.dp = dp;
-  if (!st_out) {
+  if (!diss) {
     if (dp_slot) *dp_slot = dp;
     return;
   }
@@ -203,10 +204,10 @@ __device__ void pa66_point(const ProbInc& in, const double* eps, const double* s
   for (int c = 0; c < 6; ++c) {
     evp1[c] = evp[c] + k15 * o.nd[c];
     dn[c] = d[c] - evp1[c];
-    st_out[(1 + c) * ss] = evp1[c];
+    if (st_out) st_out[(1 + c) * ss] = evp1[c];
   }
   const double ep1 = ep + dp;
-  st_out[0] = ep1;
+  if (st_out) st_out[0] = ep1;
   double dis = in.sY * dp;
   double trd = 0.0;
 #pragma unroll
@@ -214,7 +215,7 @@ __device__ void pa66_point(const ProbInc& in, const double* eps, const double* s
   double trsum = in.Kinf3 * trd;
   for (int i = 0; i < in.nm; ++i) {
     const double* ev = st + (7 + 6 * i) * ss;
-    double* evo = st_out + (7 + 6 * i) * ss;
+    double* evo = st_out ? st_out + (7 + 6 * i) * ss : nullptr;
     double v[6];
 #pragma unroll
     for (int c = 0; c < 6; ++c) v[c] = ev[c * ss];
@@ -231,8 +232,10 @@ __device__ void pa66_point(const ProbInc& in, const double* eps, const double* s
     for (int c = 0; c < 6; ++c) w += in.G2i[i] * (dn[c] - dnew[c]) * (dnew[c] - dold[c]);
     dis += w;
     trsum += in.K3i[i] * (trd - 3.0 * (s1 - sn));
+    if (st_out) {
 #pragma unroll
-    for (int c = 0; c < 6; ++c) evo[c * ss] = dnew[c] + (c < 3 ? s1 : 0.0);
+      for (int c = 0; c < 6; ++c) evo[c * ss] = dnew[c] + (c < 3 ? s1 : 0.0);
+    }
   }
   dis /= dt;
   const double Hn = ep1 > 0.0 ? in.hk * powpos(ep1, in.nh) : 0.0;
@@ -437,6 +440,191 @@ __global__ void __launch_bounds__(PT_THREADS) k_commit(Pt<T> a) {
 }
 
 // ---------------------------------------------------------------------------
+// effective algorithmic tangents (paper Sec. 3.3: derivatives of the effective
+// stress and coupling term with respect to the macro strain and temperature,
+// taken after Newton's method has converged). The strain-jump derivatives of
+// the paper become fluctuation fields of the cell problem linearized at the
+// converged strain: x_j with mean E_j, and x_theta with mean zero and source
+// d sigma / d theta, both equilibrated with the algorithmic tangent.
+// ---------------------------------------------------------------------------
+
+// Start of a linearized solve: x = dE (uniform), Newton state reset.
+template <typename T>
+__global__ void __launch_bounds__(PT_THREADS) k_init_linear(Pt<T> a) {
+  const int prob = blockIdx.x / a.bpp;
+  const int blk = blockIdx.x % a.bpp;
+  const ProbInc& in = a.inc[prob];
+  if (blk == 0 && threadIdx.x == 0) {
+    Ctl& c = a.ctl[prob];
+    c.mode = M_EVAL;
+    c.newton_it = c.cg_it = c.cg_ready = c.pending = c.status = c.pipelines = c.krylov = 0;
+    c.rr = c.alpha = c.beta = c.res = c.fnorm = c.cg_target = 0.0;
+  }
+  const long long nv = a.nvox;
+  const long long fo = (long long)prob * 6 * nv;
+  for (long long v = (long long)blk * PT_THREADS + threadIdx.x; v < nv; v += (long long)a.bpp * PT_THREADS) {
+#pragma unroll
+    for (int c = 0; c < 6; ++c) stnt(a.x + fo + c * nv + v, T(in.dE[c]));
+  }
+}
+
+// sigma = C x (+ s0), C = 3K P1 + a P2 + b N N with (a, b, N) of the last
+// Newton evaluation and 3K of the voxel's phase (the operator of the CG steps).
+template <typename T>
+__global__ void __launch_bounds__(PT_THREADS) k_eval_linear(Pt<T> a) {
+  const int prob = blockIdx.x / a.bpp;
+  const int blk = blockIdx.x % a.bpp;
+  const Ctl& ctl = a.ctl[prob];
+  if (ctl.mode != M_EVAL) return;
+  const bool pending = ctl.pending != 0;
+  const T alpha = T(ctl.alpha);
+  const ProbInc& in = a.inc[prob];
+  const long long nv = a.nvox;
+  const long long fo = (long long)prob * 6 * nv;
+  const long long to = (long long)prob * 2 * nv;
+  const uint8_t* phase = a.phase + (long long)prob * nv;
+  for (long long v = (long long)blk * PT_THREADS + threadIdx.x; v < nv; v += (long long)a.bpp * PT_THREADS) {
+    double e[6];
+#pragma unroll
+    for (int c = 0; c < 6; ++c) {
+      T xv = ldnt(a.x + fo + c * nv + v);
+      if (pending) {
+        xv += alpha * ldnt(a.p + fo + c * nv + v);
+        stnt(a.x + fo + c * nv + v, xv);
+      }
+      e[c] = (double)xv;
+    }
+    const double ca = (double)ldnt(a.tab + to + v);
+    const double cb = (double)ldnt(a.tab + to + nv + v);
+    const double K3 = in.ph[phase[v]].K3;
+    const double tr3 = (e[0] + e[1] + e[2]) * (1.0 / 3.0);
+    const double sph = (K3 - ca) * tr3;
+    double sg[6];
+#pragma unroll
+    for (int c = 0; c < 6; ++c) sg[c] = ca * e[c] + (c < 3 ? sph : 0.0);
+    if (cb != 0.0) {
+      double nd[6], dot = 0.0;
+#pragma unroll
+      for (int c = 0; c < 6; ++c) {
+        nd[c] = (double)ldnt(a.tn + fo + c * nv + v);
+        dot += nd[c] * e[c];
+      }
+#pragma unroll
+      for (int c = 0; c < 6; ++c) sg[c] += cb * dot * nd[c];
+    }
+    if (a.s0) {
+#pragma unroll
+      for (int c = 0; c < 6; ++c) sg[c] += (double)ldnt(a.s0 + fo + c * nv + v);
+    }
+#pragma unroll
+    for (int c = 0; c < 6; ++c) stnt(a.f + fo + c * nv + v, T(sg[c]));
+  }
+}
+
+// Point partials at the converged strain x, from state n (run before the
+// commit of a converged increment): d sigma / d theta, d D / d eps and
+// d D / d theta of the coupling term D. Thermoelastic phases in closed form
+// (sigma = C[eps - alpha (theta - theta0)], D = -theta C[alpha] : eps_dot);
+// the PA66 law by central differences of its implicit Euler update: 2
+// evaluations at theta +- h_theta (with the branch history sums of those
+// temperatures) and 12 at eps +- h_eps along each Mandel direction.
+template <typename T>
+__global__ void __launch_bounds__(PT_THREADS) k_partials(Pt<T> a) {
+  const int prob = blockIdx.x / a.bpp;
+  const int blk = blockIdx.x % a.bpp;
+  if (a.ctl[prob].status != 1) return;
+  const ProbInc& in = a.inc[prob];
+  const long long nv = a.nvox;
+  const long long fo = (long long)prob * 6 * nv;
+  const uint8_t* phase = a.phase + (long long)prob * nv;
+  for (long long v = (long long)blk * PT_THREADS + threadIdx.x; v < nv; v += (long long)a.bpp * PT_THREADS) {
+    const int ph = phase[v];
+    double e[6], en[6];
+#pragma unroll
+    for (int c = 0; c < 6; ++c) {
+      e[c] = (double)a.x[fo + c * nv + v];
+      en[c] = (double)a.xn[fo + c * nv + v];
+    }
+    double st_[6], gd[6], hd;
+    if (ph == in.pa_phase) {
+      const double* st = a.state + (long long)prob * a.nstate * nv + v;
+      const double* hs = a.hist ? a.hist + (long long)prob * HIST_SLOTS * nv + v : nullptr;
+      double sp[6], Dp = 0.0;
+      for (int k = 0; k < 14; ++k) {
+        const bool th = k < 2;
+        const ProbInc& ik = th ? a.inc_pm[2 * prob + k] : in;
+        double ek[6];
+#pragma unroll
+        for (int c = 0; c < 6; ++c) ek[c] = e[c];
+        const int dir = (k - 2) >> 1;
+        if (!th) ek[dir] += (k & 1) ? -FD_H_EPS : FD_H_EPS;
+        PaOut o;
+        double dis, cpl;
+        pa66_point(ik, ek, st, nv, nullptr, en, o, &dis, &cpl, th ? nullptr : hs, nullptr);
+        if (!(k & 1)) {  // + side: keep it for the difference with the - side
+#pragma unroll
+          for (int c = 0; c < 6; ++c) sp[c] = o.sig[c];
+          Dp = cpl;
+        } else if (th) {
+#pragma unroll
+          for (int c = 0; c < 6; ++c) st_[c] = (sp[c] - o.sig[c]) * (0.5 / FD_H_THETA);
+          hd = (Dp - cpl) * (0.5 / FD_H_THETA);
+        } else {
+          gd[dir] = (Dp - cpl) * (0.5 / FD_H_EPS);
+        }
+      }
+    } else {
+      const PhaseInc& pi = in.ph[ph];
+      const double ca = pi.K3 * pi.alpha0;  // C[alpha] = 3K alpha0 on the normal components
+      const double trd = (e[0] - en[0]) + (e[1] - en[1]) + (e[2] - en[2]);
+#pragma unroll
+      for (int c = 0; c < 6; ++c) {
+        st_[c] = c < 3 ? -ca : 0.0;
+        gd[c] = c < 3 ? -in.theta * ca / in.dt : 0.0;
+      }
+      hd = -ca * trd / in.dt;
+    }
+#pragma unroll
+    for (int c = 0; c < 6; ++c) {
+      a.dsdt[fo + c * nv + v] = T(st_[c]);
+      a.dDde[fo + c * nv + v] = T(gd[c]);
+    }
+    a.dDdt[(long long)prob * nv + v] = T(hd);
+  }
+}
+
+// Per-block sums over the voxels of a converged linearized solve: the stress
+// (6) and, if the partials are kept, dD/deps . x and dD/dtheta.
+template <typename T>
+__global__ void __launch_bounds__(PT_THREADS) k_tangent_sum(Pt<T> a) {
+  __shared__ double red[8 * 16];
+  const int prob = blockIdx.x / a.bpp;
+  const int blk = blockIdx.x % a.bpp;
+  if (a.ctl[prob].status != 1) return;
+  const long long nv = a.nvox;
+  const long long fo = (long long)prob * 6 * nv;
+  double acc[8];
+#pragma unroll
+  for (int k = 0; k < 8; ++k) acc[k] = 0.0;
+  for (long long v = (long long)blk * PT_THREADS + threadIdx.x; v < nv; v += (long long)a.bpp * PT_THREADS) {
+#pragma unroll
+    for (int c = 0; c < 6; ++c) acc[c] += (double)ldnt(a.f + fo + c * nv + v);
+    if (a.dDde) {
+#pragma unroll
+      for (int c = 0; c < 6; ++c)
+        acc[6] += (double)ldnt(a.dDde + fo + c * nv + v) * (double)ldnt(a.x + fo + c * nv + v);
+      acc[7] += (double)ldnt(a.dDdt + (long long)prob * nv + v);
+    }
+  }
+  block_sum<8>(acc, red);
+  if (threadIdx.x == 0) {
+    double* out = a.part + ((long long)prob * a.maxblk + blk) * NPART;
+#pragma unroll
+    for (int k = 0; k < 8; ++k) out[k] = acc[k];
+  }
+}
+
+// ---------------------------------------------------------------------------
 // per-problem reductions and state transitions (one block per problem)
 // ---------------------------------------------------------------------------
 constexpr int RED_THREADS = 1024;
@@ -608,7 +796,28 @@ void launch_reduce_out(Ctl* ctl, const double* part, int maxblk, int nblk, int n
   hipLaunchKernelGGL(k_reduce_out, dim3(nprob), dim3(RED_THREADS), 0, s, ctl, part, maxblk, nblk, nk, scale);
 }
 
+template <typename T>
+void launch_eval_linear(const Pt<T>& a, hipStream_t s) {
+  hipLaunchKernelGGL((k_eval_linear<T>), dim3(a.nprob * a.bpp), dim3(PT_THREADS), 0, s, a);
+}
+template <typename T>
+void launch_init_linear(const Pt<T>& a, hipStream_t s) {
+  hipLaunchKernelGGL((k_init_linear<T>), dim3(a.nprob * a.bpp), dim3(PT_THREADS), 0, s, a);
+}
+template <typename T>
+void launch_partials(const Pt<T>& a, hipStream_t s) {
+  hipLaunchKernelGGL((k_partials<T>), dim3(a.nprob * a.bpp), dim3(PT_THREADS), 0, s, a);
+}
+template <typename T>
+void launch_tangent_sum(const Pt<T>& a, hipStream_t s) {
+  hipLaunchKernelGGL((k_tangent_sum<T>), dim3(a.nprob * a.bpp), dim3(PT_THREADS), 0, s, a);
+}
+
 #define HOM_INST_PT(T)                                                  \
+  template void launch_eval_linear<T>(const Pt<T>&, hipStream_t);       \
+  template void launch_init_linear<T>(const Pt<T>&, hipStream_t);       \
+  template void launch_partials<T>(const Pt<T>&, hipStream_t);          \
+  template void launch_tangent_sum<T>(const Pt<T>&, hipStream_t);       \
   template void launch_init_mech<T>(const Pt<T>&, int, hipStream_t);    \
   template void launch_init_th<T>(const Pt<T>&, int, hipStream_t);      \
   template void launch_eval<T>(const Pt<T>&, int, hipStream_t);         \

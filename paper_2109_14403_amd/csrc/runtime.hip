@@ -265,8 +265,18 @@ struct Group {
   int txy[2] = {4, 4}, txz[2] = {4, 4};  // [mech, thermal]
   int pt_bpp = 1;
   int xfblocks = 1, xiblocks = 1;  // x-forward / x-inverse work-groups per problem
-  hipGraphExec_t graph[2] = {nullptr, nullptr};
-  int graph_k[2] = {0, 0};
+  // captured chunks: [0] mechanics, [1] conduction, [2] linearized mechanics
+  // (tangent strain columns), [3] linearized mechanics with a source (tangent
+  // temperature column)
+  hipGraphExec_t graph[4] = {nullptr, nullptr, nullptr, nullptr};
+  int graph_k[4] = {0, 0, 0, 0};
+  // effective algorithmic tangents: per-voxel partials kept at each commit
+  // (set up with the tangent option), the stress field saved across the
+  // linearized solves, and whether the last increment can be linearized
+  T *dsdt = nullptr, *dDde = nullptr, *dDdt = nullptr, *fsave = nullptr;
+  ProbInc* inc_pm_d = nullptr;
+  ProbInc* inc_pm_h = nullptr;
+  bool tan_ok = false;
   std::vector<std::array<double, 6>> En;
   std::vector<std::array<double, 3>> Gp;
   std::vector<double> c0mean;
@@ -282,14 +292,15 @@ struct Group {
   }
 
   ~Group() {
-    for (int i = 0; i < 2; ++i)
+    for (int i = 0; i < 4; ++i)
       if (graph[i]) (void)hipGraphExecDestroy(graph[i]);
     for (void* ptr : allocs) (void)hipFree(ptr);
     if (inc_h) (void)hipHostFree(inc_h);
+    if (inc_pm_h) (void)hipHostFree(inc_pm_h);
     if (ctl_h) (void)hipHostFree(ctl_h);
   }
 
-  void alloc(bool with_state) {
+  void alloc(bool with_state, bool partials = false) {
     P = nx / 2 + 1;
     nvox = (long long)nx * ny * nz;
     const long long nm = (long long)nprob * nvox;
@@ -337,6 +348,14 @@ struct Group {
     }
     En.assign(nprob, {0, 0, 0, 0, 0, 0});
     Gp.assign(nprob, {0, 0, 0});
+    if (partials) {
+      dsdt = dalloc<T>(6 * nm);
+      dDde = dalloc<T>(6 * nm);
+      dDdt = dalloc<T>(nm);
+      inc_pm_d = dalloc<ProbInc>(2 * nprob);
+      HIPCHK(hipHostMalloc(reinterpret_cast<void**>(&inc_pm_h), sizeof(ProbInc) * 2 * nprob));
+      std::memset(inc_pm_h, 0, sizeof(ProbInc) * 2 * nprob);
+    }
   }
 
   Pipe<T> pipe(int phys, int green) const {
@@ -391,6 +410,11 @@ struct Group {
     a.maxblk = maxblk;
     a.pv_diss = nullptr;
     a.pv_coup = nullptr;
+    a.dsdt = dsdt;
+    a.dDde = dDde;
+    a.dDdt = dDdt;
+    a.inc_pm = inc_pm_d;
+    a.s0 = nullptr;
     return a;
   }
 };
@@ -489,7 +513,7 @@ class BatchT : public BatchImpl {
       auto& G = *gp;
       G.nprob = (int)G.members.size();
       G.nstate = nst;
-      G.alloc(nst > 0);
+      G.alloc(nst > 0, opts.tangent != 0);
       std::vector<uint8_t> buf((size_t)G.nprob * G.nx * G.ny * G.nz);
       G.c0mean.assign(G.nprob, 0.0);
       const long long nv = (long long)G.nx * G.ny * G.nz;
@@ -578,15 +602,25 @@ class BatchT : public BatchImpl {
     return lim;
   }
 
-  void iteration(Group<T>& G, int phys, bool basic) {
+  // One solver iteration. variant: 0 mechanics, 1 conduction, 2 linearized
+  // mechanics (sigma = C_algo x), 3 linearized mechanics with the source
+  // d sigma / d theta.
+  void iteration(Group<T>& G, int variant, bool basic) {
+    const int phys = variant == 1 ? 1 : 0;
     const int green = phys == 0 ? (basic ? G_GAMMA0 : G_PROJ) : (basic ? G_GAMMA_TH : G_GRADPROJ);
     Pipe<T> a = G.pipe(phys, green);
     Pt<T> q = G.pt(phys);
     const int C = phys == 0 ? 6 : 3;
-    const Limits lim = limits(phys);
+    Limits lim = limits(phys);
+    if (variant >= 2) lim.linear = 1;
     Ctl* ctl = phys == 0 ? G.ctl_m : G.ctl_t;
     prof.begin(K_EVAL, stream);
-    launch_eval<T>(q, C, stream);
+    if (variant >= 2) {
+      q.s0 = variant == 3 ? G.dsdt : nullptr;
+      launch_eval_linear<T>(q, stream);
+    } else {
+      launch_eval<T>(q, C, stream);
+    }
     prof.end(stream);
     prof.begin(K_XFWD, stream);
     run_xfwd<T>(a, stream);
@@ -619,6 +653,10 @@ class BatchT : public BatchImpl {
     prof.end(stream);
   }
 
+  static long long iteration_cap(const Limits& lim, bool basic) {
+    return basic ? (long long)lim.max_newton + 2 : (long long)(lim.max_newton + 1) * (lim.max_krylov + 2);
+  }
+
   int chunk_size(const Group<T>& G) const {
     if (opts.chunk > 0) return opts.chunk;
     // large grids: one iteration per host check (a check costs ~1 % of an
@@ -626,23 +664,40 @@ class BatchT : public BatchImpl {
     return (G.nvox * G.nprob >= (1LL << 22)) ? 1 : 16;
   }
 
-  void run_chunk(Group<T>& G, int phys, bool basic, int k) {
+  void run_chunk(Group<T>& G, int variant, bool basic, int k) {
     const bool graph = opts.use_graph && !prof.on;
     if (!graph) {
-      for (int i = 0; i < k; ++i) iteration(G, phys, basic);
+      for (int i = 0; i < k; ++i) iteration(G, variant, basic);
       return;
     }
-    if (!G.graph[phys] || G.graph_k[phys] != k) {
-      if (G.graph[phys]) HIPCHK(hipGraphExecDestroy(G.graph[phys]));
+    if (!G.graph[variant] || G.graph_k[variant] != k) {
+      if (G.graph[variant]) HIPCHK(hipGraphExecDestroy(G.graph[variant]));
       hipGraph_t gr;
       HIPCHK(hipStreamBeginCapture(stream, hipStreamCaptureModeThreadLocal));
-      for (int i = 0; i < k; ++i) iteration(G, phys, basic);
+      for (int i = 0; i < k; ++i) iteration(G, variant, basic);
       HIPCHK(hipStreamEndCapture(stream, &gr));
-      HIPCHK(hipGraphInstantiate(&G.graph[phys], gr, nullptr, nullptr, 0));
+      HIPCHK(hipGraphInstantiate(&G.graph[variant], gr, nullptr, nullptr, 0));
       HIPCHK(hipGraphDestroy(gr));
-      G.graph_k[phys] = k;
+      G.graph_k[variant] = k;
     }
-    HIPCHK(hipGraphLaunch(G.graph[phys], stream));
+    HIPCHK(hipGraphLaunch(G.graph[variant], stream));
+  }
+
+  // Iterate until no problem of the group is in a pipeline mode (or the cap).
+  void iterate(Group<T>& G, int variant, bool basic, long long cap) {
+    const int k = chunk_size(G);
+    Ctl* ctl = variant == 1 ? G.ctl_t : G.ctl_m;
+    long long done_its = 0;
+    for (;;) {
+      run_chunk(G, variant, basic, k);
+      done_its += k;
+      HIPCHK(hipMemcpyAsync(G.ctl_h, ctl, sizeof(Ctl) * G.nprob, hipMemcpyDeviceToHost, stream));
+      HIPCHK(hipStreamSynchronize(stream));
+      prof.collect();
+      int active = 0;
+      for (int j = 0; j < G.nprob; ++j) active += pipeline_mode_host(G.ctl_h[j].mode);
+      if (!active || done_its > cap) break;
+    }
   }
 
   void solve_phys(Group<T>& G, int phys) {
@@ -662,21 +717,9 @@ class BatchT : public BatchImpl {
       prof.end(stream);
     }
     const Limits lim = limits(phys);
-    const long long cap = basic ? (long long)lim.max_newton + 2
-                                : (long long)(lim.max_newton + 1) * (lim.max_krylov + 2);
-    const int k = chunk_size(G);
     Ctl* ctl = phys == 0 ? G.ctl_m : G.ctl_t;
-    long long done_its = 0;
-    for (;;) {
-      run_chunk(G, phys, basic, k);
-      done_its += k;
-      HIPCHK(hipMemcpyAsync(G.ctl_h, ctl, sizeof(Ctl) * G.nprob, hipMemcpyDeviceToHost, stream));
-      HIPCHK(hipStreamSynchronize(stream));
-      prof.collect();
-      int active = 0;
-      for (int j = 0; j < G.nprob; ++j) active += pipeline_mode_host(G.ctl_h[j].mode);
-      if (!active || done_its > cap) break;
-    }
+    iterate(G, phys, basic, iteration_cap(lim, basic));
+    if (phys == 0 && G.dsdt) launch_partials<T>(q, stream);  // before the commit: they need state n
     prof.begin(K_COMMIT, stream);
     launch_commit<T>(q, phys == 0 ? 6 : 3, stream);
     prof.end(stream);
@@ -712,6 +755,16 @@ class BatchT : public BatchImpl {
         for (int c = 0; c < 3; ++c) in.dG[c] = temp[i].grad[c] - G.Gp[j][c];
       }
       HIPCHK(hipMemcpyAsync(G.inc_d, G.inc_h, sizeof(ProbInc) * G.nprob, hipMemcpyHostToDevice, stream));
+      if (G.inc_pm_h) {  // the increment data at theta +- h_theta for the point partials
+        for (int j = 0; j < G.nprob; ++j) {
+          const int i = G.members[j];
+          fill_inc(G.inc_pm_h[2 * j], laws, temp[i].theta + FD_H_THETA, dt[i]);
+          fill_inc(G.inc_pm_h[2 * j + 1], laws, temp[i].theta - FD_H_THETA, dt[i]);
+        }
+        HIPCHK(hipMemcpyAsync(G.inc_pm_d, G.inc_pm_h, sizeof(ProbInc) * 2 * G.nprob, hipMemcpyHostToDevice,
+                              stream));
+      }
+      G.tan_ok = false;
       solve_phys(G, 0);
       std::vector<Ctl> mech(G.ctl_h, G.ctl_h + G.nprob);
       // the conduction field now holds the new mean gradient
@@ -742,7 +795,93 @@ class BatchT : public BatchImpl {
         if (cm.status == 1)
           for (int c = 0; c < 6; ++c) G.En[j][c] = w[c] * strain[6 * i + c];
       }
+      bool all = opts.scheme == HOM_SCHEME_NEWTON_CG;
+      for (int j = 0; j < G.nprob; ++j) all = all && mech[j].status == 1;
+      G.tan_ok = all;
     }
+  }
+
+  // ---- effective algorithmic tangents of the last increment ---------------
+  // Linearized solves with the algorithmic tangent of the converged Newton
+  // evaluation: one per unit macro strain (Mandel), and for what = 1 one with
+  // mean zero and the source d sigma / d theta. The strain and stress fields
+  // of the increment are restored afterwards.
+  void tangent(int what, hom_tangent* out) override {
+    if (opts.scheme != HOM_SCHEME_NEWTON_CG)
+      fail(HOM_E_UNSUPPORTED, "algorithmic tangents need the Newton-CG scheme (its evaluations keep the tangent)");
+    if (what != 0 && what != 1) fail(HOM_E_ARG, "what must be 0 (d sigma / dE) or 1 (all four tangents)");
+    for (auto& gp : groups) {
+      if (!gp->tan_ok)
+        fail(HOM_E_ARG, "no converged increment to linearize (every problem's last increment must have converged)");
+      if (what == 1 && !gp->dsdt)
+        fail(HOM_E_ARG, "temperature and coupling tangents need a setup with the tangent option");
+    }
+    const double sq2 = std::sqrt(2.0);
+    const double w[6] = {1, 1, 1, sq2, sq2, sq2};
+    const bool prof_on = prof.on;
+    prof.on = false;
+    for (auto& gp : groups) {
+      Group<T>& G = *gp;
+      const size_t nm = (size_t)G.nprob * G.nvox;
+      if (!G.fsave) G.fsave = G.template dalloc<T>(6 * nm);
+      HIPCHK(hipMemcpyAsync(G.fsave, G.f, 6 * nm * sizeof(T), hipMemcpyDeviceToDevice, stream));
+      auto restore = [&] {
+        (void)hipMemcpyAsync(G.xm, G.xnm, 6 * nm * sizeof(T), hipMemcpyDeviceToDevice, stream);
+        (void)hipMemcpyAsync(G.f, G.fsave, 6 * nm * sizeof(T), hipMemcpyDeviceToDevice, stream);
+        (void)hipStreamSynchronize(stream);
+      };
+      try {
+        const int ncol = what == 1 ? 7 : 6;
+        Limits lim = limits(0);
+        lim.linear = 1;
+        const long long cap = iteration_cap(lim, false);
+        const Pt<T> q = G.pt(0);
+        for (int j = 0; j < G.nprob; ++j) {
+          hom_tangent& t = out[G.members[j]];
+          std::memset(&t, 0, sizeof(t));
+          if (what == 0) {
+            for (int c = 0; c < 6; ++c) t.dsdt[c] = t.dDde[c] = NAN;
+            t.dDdt = NAN;
+          }
+        }
+        for (int col = 0; col < ncol; ++col) {
+          for (int j = 0; j < G.nprob; ++j)
+            for (int c = 0; c < 6; ++c) G.inc_h[j].dE[c] = (c == col) ? 1.0 : 0.0;
+          HIPCHK(hipMemcpyAsync(G.inc_d, G.inc_h, sizeof(ProbInc) * G.nprob, hipMemcpyHostToDevice, stream));
+          launch_init_linear<T>(q, stream);
+          iterate(G, col < 6 ? 2 : 3, false, cap);
+          launch_tangent_sum<T>(q, stream);
+          launch_reduce_out(G.ctl_m, G.part, G.maxblk, G.pt_bpp, G.nprob, 8, 1.0 / (double)G.nvox, stream);
+          HIPCHK(hipMemcpyAsync(G.ctl_h, G.ctl_m, sizeof(Ctl) * G.nprob, hipMemcpyDeviceToHost, stream));
+          HIPCHK(hipStreamSynchronize(stream));
+          for (int j = 0; j < G.nprob; ++j) {
+            const Ctl& c = G.ctl_h[j];
+            if (c.status != 1)
+              fail(c.status < 0 ? c.status : HOM_E_NOT_CONVERGED,
+                   "linearized solve " + std::to_string(col) + " of problem " + std::to_string(G.members[j]) +
+                       " did not converge");
+            hom_tangent& t = out[G.members[j]];
+            if (col < 6) {
+              for (int I = 0; I < 6; ++I) t.dsde[6 * I + col] = c.out[I] * w[col] / w[I];
+              if (what == 1) t.dDde[col] = c.out[6] * w[col];
+            } else {
+              for (int I = 0; I < 6; ++I) t.dsdt[I] = c.out[I] / w[I];
+              t.dDdt = c.out[6] + c.out[7];
+            }
+            t.solves += 1;
+            t.krylov_iters += c.krylov;
+            t.pipelines += c.pipelines;
+          }
+        }
+      } catch (...) {
+        restore();
+        prof.on = prof_on;
+        throw;
+      }
+      restore();
+      HIPCHK(hipGetLastError());
+    }
+    prof.on = prof_on;
   }
 
   // ---- checkpoint: xn, xt, state, macro history -------------------------
@@ -780,6 +919,7 @@ class BatchT : public BatchImpl {
     }
   }
   void set_state(const void* buf) override {
+    for (auto& gp : groups) gp->tan_ok = false;  // the tangent fields belong to the replaced state
     const char* p = static_cast<const char*>(buf);
     uint64_t magic, tsz;
     std::memcpy(&magic, p, 8);

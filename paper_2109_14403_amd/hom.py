@@ -68,7 +68,7 @@ class Options(ct.Structure):
     _fields_ = [
         ("scheme", ct.c_int32), ("precision", ct.c_int32), ("tol", ct.c_double), ("thermal_tol", ct.c_double),
         ("max_iter", ct.c_int32), ("max_krylov", ct.c_int32), ("chunk", ct.c_int32), ("use_graph", ct.c_int32),
-        ("profile", ct.c_int32), ("autotune", ct.c_int32), ("stream", ct.c_void_p),
+        ("profile", ct.c_int32), ("autotune", ct.c_int32), ("stream", ct.c_void_p), ("tangent", ct.c_int32),
     ]
 
 
@@ -92,9 +92,22 @@ class Result(ct.Structure):
                     thermal_pipelines=self.thermal_pipelines)
 
 
+class Tangent(ct.Structure):
+    _fields_ = [
+        ("dsde", ct.c_double * 36), ("dsdt", ct.c_double * 6), ("dDde", ct.c_double * 6), ("dDdt", ct.c_double),
+        ("solves", ct.c_int32), ("krylov_iters", ct.c_int32), ("pipelines", ct.c_double), ("status", ct.c_int32),
+    ]
+
+    def as_dict(self):
+        return dict(dsde=np.array(self.dsde[:]).reshape(6, 6), dsdt=np.array(self.dsdt[:]),
+                    dDde=np.array(self.dDde[:]), dDdt=self.dDdt, solves=self.solves,
+                    krylov_iters=self.krylov_iters, pipelines=self.pipelines, status=self.status)
+
+
 EXPORTS = (
     "hom_default_options", "hom_setup", "hom_solve_increment", "hom_state_size", "hom_get_state",
     "hom_set_state", "hom_get_field", "hom_kernel_stats", "hom_set_profiling", "hom_device_bytes",
+    "hom_algorithmic_tangent", "hom_batch_algorithmic_tangent",
     "hom_last_error", "hom_destroy",
     "hom_batch_setup", "hom_batch_solve_increment", "hom_batch_kernel_stats", "hom_batch_last_error",
     "hom_batch_destroy", "hom_apply_operator", "hom_eval_law",
@@ -135,6 +148,8 @@ def library(path: str | None = None):
     lib.hom_get_field.argtypes = [ct.c_void_p, ct.c_int32, dp, ct.c_size_t]
     lib.hom_kernel_stats.argtypes = [ct.c_void_p, ct.POINTER(ct.c_char_p), ct.POINTER(ct.c_int64), dp, ct.c_int32]
     lib.hom_set_profiling.argtypes = [ct.c_void_p, ct.c_int32]
+    lib.hom_algorithmic_tangent.argtypes = [ct.c_void_p, ct.c_int32, ct.POINTER(Tangent)]
+    lib.hom_batch_algorithmic_tangent.argtypes = [ct.c_void_p, ct.c_int32, ct.POINTER(Tangent)]
     lib.hom_device_bytes.argtypes = [ct.c_void_p]
     lib.hom_device_bytes.restype = ct.c_size_t
     lib.hom_last_error.argtypes = [ct.c_void_p]
@@ -209,7 +224,7 @@ def make_law(p: dict) -> Law:
 
 
 def make_options(scheme=SCHEME_NEWTON_CG, precision=FP32, tol=1e-6, thermal_tol=0.0, max_iter=0, max_krylov=0,
-                 chunk=0, use_graph=1, profile=0, autotune=0, stream=None) -> Options:
+                 chunk=0, use_graph=1, profile=0, autotune=0, stream=None, tangent=0) -> Options:
     o = Options()
     library().hom_default_options(ct.byref(o))
     o.scheme = scheme
@@ -223,6 +238,7 @@ def make_options(scheme=SCHEME_NEWTON_CG, precision=FP32, tol=1e-6, thermal_tol=
     o.profile = profile
     o.autotune = autotune
     o.stream = stream
+    o.tangent = tangent
     return o
 
 
@@ -316,6 +332,13 @@ class Context:
         buf = np.ascontiguousarray(buf, dtype=np.uint8)
         _check(self._lib.hom_set_state(self._h, buf.ctypes.data_as(ct.c_void_p), buf.size), self.error)
 
+    def algorithmic_tangent(self, what=1):
+        """Effective algorithmic tangents of the last converged increment
+        (hom_algorithmic_tangent): dsde (6, 6), dsdt (6,), dDde (6,), dDdt."""
+        t = Tangent()
+        _check(self._lib.hom_algorithmic_tangent(self._h, int(what), ct.byref(t)), self.error)
+        return t.as_dict()
+
     def kernel_stats(self):
         return _stats(self._lib.hom_kernel_stats, self._h)
 
@@ -377,6 +400,12 @@ class Batch:
         rc = self._lib.hom_batch_solve_increment(self._h, _dptr(s), temps, _dptr(d), res)
         _check(rc, lambda: self._lib.hom_batch_last_error(self._h).decode())
         return [r.as_dict() for r in res]
+
+    def algorithmic_tangent(self, what=1):
+        out = (Tangent * self.n)()
+        _check(self._lib.hom_batch_algorithmic_tangent(self._h, int(what), out),
+               lambda: self._lib.hom_batch_last_error(self._h).decode())
+        return [t.as_dict() for t in out]
 
     def kernel_stats(self):
         return _stats(self._lib.hom_batch_kernel_stats, self._h)
