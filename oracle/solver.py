@@ -18,6 +18,8 @@ coupling term <D> and the heat capacity <c0>, all volume averages.
 """
 from __future__ import annotations
 
+import copy
+
 import numpy as np
 
 from . import fourier, green, tensor
@@ -208,6 +210,64 @@ class Cell:
             thermal_iterations=th_its,
         )
         out.update(info)
+        return out
+
+    # ---- mixed boundary conditions, adiabatic heat balance -----------------
+    def solve_load(self, strain, stress, mask, theta_n, grad, dt, adiabatic=False, tol=1e-10, cg_rtol=1e-6,
+                   stress_tol=1e-10, theta_tol=1e-9, max_outer=30, max_stagger=30):
+        """One increment of the paper's single-point virtual experiments:
+        mixed boundary conditions (the components with mask[c] True are
+        stress-controlled with target stress[c], the others strain-controlled;
+        Sec. 5.4 and the appendix use them for stress-free lateral directions)
+        and, if adiabatic, the macroscopic heat equation of Sec. 2 at one point
+        without source or flux divergence, c (theta - theta^n) / dt = <D>,
+        solved by the implicit staggered scheme: mechanics at fixed theta,
+        then theta from the heat equation, until theta is stationary.
+
+        The stress-controlled macro strain components follow from an outer
+        Newton iteration with the effective algorithmic tangent; every outer
+        and staggered iterate re-solves the increment from state n. strain,
+        stress: (6,) tensor components. Returns the outputs of
+        solve_increment plus the macro strain (components), theta and the
+        numbers of staggered and outer iterations; commits like
+        solve_increment."""
+        mask = np.asarray(mask, dtype=bool)
+        free = np.nonzero(mask)[0]
+        Em = tensor.components_to_mandel(np.asarray(strain, dtype=np.float64))
+        Sm = tensor.components_to_mandel(np.asarray(stress, dtype=np.float64))
+        E = Em.copy()
+        E[free] = self.E_n[free]          # start from the last mean strain of those components
+        theta = float(theta_n)
+        base = copy.deepcopy(self)
+        outer_total = 0
+        stagger = 0
+        for stagger in range(1, max_stagger + 1):
+            for _ in range(max_outer):
+                trial = copy.deepcopy(base)
+                out = trial.solve_increment(tensor.mandel_to_components(E), theta, grad, dt, tol=tol,
+                                            cg_rtol=cg_rtol)
+                outer_total += 1
+                if free.size == 0:
+                    break
+                s = tensor.components_to_mandel(out["stress"])
+                res = s[free] - Sm[free]
+                if np.abs(res).max() <= stress_tol * max(np.abs(s).max(), 1.0):
+                    break
+                C = trial.algorithmic_tangent(tol=1e-13)
+                E[free] -= np.linalg.solve(C[np.ix_(free, free)], res)
+            else:
+                raise RuntimeError("mixed boundary conditions: outer Newton did not converge")
+            if not adiabatic:
+                break
+            theta_next = float(theta_n) + dt * out["coupling"] / out["heat_capacity"]
+            if abs(theta_next - theta) <= theta_tol:
+                break
+            theta = theta_next
+        else:
+            raise RuntimeError("adiabatic staggering did not converge")
+        out = self.solve_increment(tensor.mandel_to_components(E), theta, grad, dt, tol=tol, cg_rtol=cg_rtol)
+        out.update(strain=tensor.mandel_to_components(E), theta=theta, stagger_iterations=stagger,
+                   outer_iterations=outer_total)
         return out
 
     # ---- linear effective properties -------------------------------------
