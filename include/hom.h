@@ -124,7 +124,33 @@ typedef struct {
   int32_t status;        /* HOM_OK or the error code of this problem */
   double pipelines;      /* FFT pipeline applications (mechanics) */
   double thermal_pipelines;
+  double strain[6];      /* <eps> of the increment, components (equals the prescribed strain
+                            where it is strain-controlled) */
+  double theta;          /* temperature the increment was solved at (theta^{n+1}) */
+  int32_t stagger_iters; /* mechanical solves of the adiabatic staggering (1 otherwise) */
+  int32_t reserved;
 } hom_result;
+
+/* One load increment of a single-point virtual experiment.
+ * Mixed boundary conditions (the paper's stress-free lateral directions,
+ * Sec. 5.4 and the appendix): bit c of stress_mask set => component c (order
+ * 11,22,33,23,13,12) is stress-controlled with <sigma>_c = stress[c];
+ * otherwise <eps>_c = strain[c]. The stress-controlled strain components are
+ * unknowns of the same Newton-CG iteration: the zero-frequency block of the
+ * projector keeps them instead of removing them. Needs the Newton-CG scheme.
+ * adiabatic = 1: temp.theta is theta^n and theta^{n+1} solves the macroscopic
+ * heat equation of Sec. 2 at one point without source or flux divergence,
+ * <c0> (theta^{n+1} - theta^n) / dt = <D>, by implicit staggering (mechanics
+ * at fixed theta, then theta from the heat equation, until theta is
+ * stationary to tol times its change). */
+typedef struct {
+  double strain[6];
+  double stress[6];
+  uint32_t stress_mask;  /* bits 0..5 */
+  int32_t adiabatic;
+  hom_macro_temp temp;
+  double dt;
+} hom_load;
 
 typedef struct hom_ctx hom_ctx;
 typedef struct hom_batch hom_batch;
@@ -141,6 +167,11 @@ int hom_setup(const hom_grid* grid, const uint8_t* phases, const hom_law* laws, 
  * success, commit the internal variables. macro_strain: 6 components. */
 int hom_solve_increment(hom_ctx* ctx, const double macro_strain[6], const hom_macro_temp* temp, double dt,
                         hom_result* out);
+
+/* hom_solve_increment with mixed boundary conditions and / or the adiabatic
+ * heat balance (hom_load). hom_solve_increment(E, temp, dt) equals a load
+ * with stress_mask 0 and adiabatic 0. */
+int hom_solve_load(hom_ctx* ctx, const hom_load* load, hom_result* out);
 
 /* Checkpoint of the committed state (internal variables, last converged
  * strain and gradient fields, macro history). hom_state_size gives the byte
@@ -214,6 +245,8 @@ int hom_batch_setup(int32_t n_prob, const hom_grid* grids, const uint8_t* const*
                     int32_t n_laws, const hom_options* opts, hom_batch** out);
 int hom_batch_solve_increment(hom_batch* b, const double* strain, const hom_macro_temp* temp, const double* dt,
                               hom_result* out);
+/* hom_solve_load for every problem of a batch; loads, out: n_prob entries. */
+int hom_batch_solve_load(hom_batch* b, const hom_load* loads, hom_result* out);
 int hom_batch_kernel_stats(const hom_batch* b, const char** names, int64_t* launches, double* ms, int32_t cap);
 /* hom_algorithmic_tangent for every problem of a batch; out: n_prob entries. */
 int hom_batch_algorithmic_tangent(hom_batch* b, int32_t what, hom_tangent* out);

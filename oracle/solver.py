@@ -225,8 +225,9 @@ class Cell:
         then theta from the heat equation, until theta is stationary.
 
         The stress-controlled macro strain components follow from an outer
-        Newton iteration with the effective algorithmic tangent; every outer
-        and staggered iterate re-solves the increment from state n. strain,
+        chord iteration with the effective algorithmic tangent of its first
+        iterate; every outer and staggered iterate re-solves the increment
+        from state n. strain,
         stress: (6,) tensor components. Returns the outputs of
         solve_increment plus the macro strain (components), theta and the
         numbers of staggered and outer iterations; commits like
@@ -241,6 +242,7 @@ class Cell:
         base = copy.deepcopy(self)
         outer_total = 0
         stagger = 0
+        C = None
         for stagger in range(1, max_stagger + 1):
             for _ in range(max_outer):
                 trial = copy.deepcopy(base)
@@ -253,7 +255,8 @@ class Cell:
                 res = s[free] - Sm[free]
                 if np.abs(res).max() <= stress_tol * max(np.abs(s).max(), 1.0):
                     break
-                C = trial.algorithmic_tangent(tol=1e-13)
+                if C is None:
+                    C = trial.algorithmic_tangent(tol=1e-13)
                 E[free] -= np.linalg.solve(C[np.ix_(free, free)], res)
             else:
                 raise RuntimeError("mixed boundary conditions: outer Newton did not converge")

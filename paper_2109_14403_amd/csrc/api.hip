@@ -1,6 +1,7 @@
 // extern "C" entry points of libhom.so (declared in include/hom.h).
 #include <cstring>
 #include <new>
+#include <vector>
 
 #include "mlp.h"
 #include "runtime.h"
@@ -98,7 +99,17 @@ int hom_setup(const hom_grid* grid, const uint8_t* phases, const hom_law* laws, 
 int hom_solve_increment(hom_ctx* c, const double macro_strain[6], const hom_macro_temp* temp, double dt,
                         hom_result* out) {
   if (!c || !c->impl || !macro_strain || !temp || !out) return HOM_E_ARG;
-  int rc = guarded(&c->err, [&] { c->impl->solve(macro_strain, temp, &dt, out); });
+  hom_load L;
+  std::memset(&L, 0, sizeof(L));
+  std::memcpy(L.strain, macro_strain, sizeof(L.strain));
+  L.temp = *temp;
+  L.dt = dt;
+  return hom_solve_load(c, &L, out);
+}
+
+int hom_solve_load(hom_ctx* c, const hom_load* load, hom_result* out) {
+  if (!c || !c->impl || !load || !out) return HOM_E_ARG;
+  int rc = guarded(&c->err, [&] { c->impl->solve(load, out); });
   if (rc != HOM_OK) return rc;
   rc = worst(out, 1);
   if (rc != HOM_OK) c->err = "increment did not converge (state not committed)";
@@ -169,9 +180,21 @@ int hom_batch_setup(int32_t n_prob, const hom_grid* grids, const uint8_t* const*
 int hom_batch_solve_increment(hom_batch* b, const double* strain, const hom_macro_temp* temp, const double* dt,
                               hom_result* out) {
   if (!b || !b->impl || !strain || !temp || !dt || !out) return HOM_E_ARG;
-  int rc = guarded(&b->err, [&] { b->impl->solve(strain, temp, dt, out); });
-  if (rc != HOM_OK) return rc;
-  return HOM_OK;  // per-problem status is in out[i].status
+  return guarded(&b->err, [&] {
+    std::vector<hom_load> loads(b->impl->problems());
+    for (size_t i = 0; i < loads.size(); ++i) {
+      std::memset(&loads[i], 0, sizeof(hom_load));
+      std::memcpy(loads[i].strain, strain + 6 * i, sizeof(loads[i].strain));
+      loads[i].temp = temp[i];
+      loads[i].dt = dt[i];
+    }
+    b->impl->solve(loads.data(), out);
+  });  // per-problem status is in out[i].status
+}
+
+int hom_batch_solve_load(hom_batch* b, const hom_load* loads, hom_result* out) {
+  if (!b || !b->impl || !loads || !out) return HOM_E_ARG;
+  return guarded(&b->err, [&] { b->impl->solve(loads, out); });
 }
 
 int hom_batch_kernel_stats(const hom_batch* b, const char** names, int64_t* launches, double* ms, int32_t cap) {

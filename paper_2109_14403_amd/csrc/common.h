@@ -60,6 +60,8 @@ struct ProbInc {
   double dE[6];     // change of the macro strain (Mandel) since the last commit
   double dG[3];     // change of the macro temperature gradient
   double lam0, mu0, kappa0;  // basic-scheme reference media
+  int smask;        // mixed conditions: bit c set => Mandel component c of <sigma> is prescribed
+  double S[6];      // prescribed effective stress (Mandel) of the masked components
   PhaseInc ph[MAX_PHASES];
   // PA66 (at most one inelastic law per setup)
   int pa_phase;     // phase id of the PA66 law, -1 if none

@@ -524,8 +524,20 @@ __global__ void __launch_bounds__((N / Plan<N>::M) * TX * C)
 #pragma unroll
     for (int cc = 0; cc < C; ++cc) v[cc] = buf[kz * L + kxi * C + cc];
     if (zero) {
+      // the mean: removed, except for the stress-controlled components of
+      // mixed conditions, whose mean strain is an unknown of the iteration
+      // (the projector's zero-frequency block is the mask). A residual
+      // evaluation compares the mean stress with the prescribed one (the
+      // spectrum is unnormalized: the mean mode holds nvox <sigma>).
+      const bool mean = (kxx == 0 && ky == 0 && kz == 0);
+      const bool eval = a.ctl[prob].mode == M_EVAL;
 #pragma unroll
-      for (int cc = 0; cc < C; ++cc) v[cc] = mk(T(0), T(0));
+      for (int cc = 0; cc < C; ++cc) {
+        if (C == 6 && mean && ((inc.smask >> cc) & 1))
+          v[cc] = mk(v[cc].x - (eval ? T((double)a.nvox * inc.S[cc]) : T(0)), T(0));
+        else
+          v[cc] = mk(T(0), T(0));
+      }
     } else {
       if constexpr (C == 6)
         green_mech<T>(v, n0, n1, n2, cs, cn);

@@ -40,7 +40,12 @@ struct Pt {
   T* dDdt;                  // d D / d theta       [prob][nvox]
   const ProbInc* inc_pm;    // [prob][2]: increment data at theta + h_theta, theta - h_theta
   const T* s0;              // source of a linearized evaluation (sigma = C x + s0), or null
+  int commit;               // commit kernel: 1 commit, 0 only the effective sums (a trial)
 };
+
+// Effective sums of the commit kernel (mechanics): <sigma> (6), dissipation,
+// coupling term, <eps> (6).
+constexpr int MECH_SUMS = 14;
 
 // Central-difference steps of the PA66 point partials: Mandel strain and
 // temperature [K].
@@ -59,7 +64,7 @@ struct Limits {
 // host launchers (pointwise.hip)
 namespace hom {
 template <typename T>
-void launch_init_mech(const Pt<T>& a, int scheme, hipStream_t s);
+void launch_init_mech(const Pt<T>& a, int scheme, hipStream_t s, int keep_x = 0);
 template <typename T>
 void launch_init_th(const Pt<T>& a, int scheme, hipStream_t s);
 template <typename T>

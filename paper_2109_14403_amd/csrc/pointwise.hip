@@ -244,8 +244,10 @@ __device__ void pa66_point(const ProbInc& in, const double* eps, const double* s
 }
 
 // ---------------------------------------------------------------------------
+// Start of an increment: x = x^n + dE (conduction: x += dG) and a fresh
+// solver state; keep_x restarts the iteration from the current x instead.
 template <typename T, int C>
-__global__ void __launch_bounds__(PT_THREADS) k_init(Pt<T> a, int basic) {
+__global__ void __launch_bounds__(PT_THREADS) k_init(Pt<T> a, int basic, int keep_x) {
   const int prob = blockIdx.x / a.bpp;
   const int blk = blockIdx.x % a.bpp;
   const ProbInc& in = a.inc[prob];
@@ -261,6 +263,7 @@ __global__ void __launch_bounds__(PT_THREADS) k_init(Pt<T> a, int basic) {
     c.krylov = 0;
     c.rr = c.alpha = c.beta = c.res = c.fnorm = c.cg_target = 0.0;
   }
+  if (keep_x) return;
   const long long nv = a.nvox;
   const long long fo = (long long)prob * C * nv;
   for (long long v = (long long)blk * PT_THREADS + threadIdx.x; v < nv; v += (long long)a.bpp * PT_THREADS) {
@@ -366,9 +369,13 @@ __global__ void __launch_bounds__(PT_THREADS) k_history(Pt<T> a) {
   }
 }
 
+// Commit of a converged increment (a.commit = 1): new internal variables, the
+// committed strain, the stress field and the effective sums. With a.commit = 0
+// only the sums are formed (an increment that is not final yet).
 template <typename T, int C>
 __global__ void __launch_bounds__(PT_THREADS) k_commit(Pt<T> a) {
-  __shared__ double red[8 * 16];
+  constexpr int NS = C == 6 ? MECH_SUMS : 8;
+  __shared__ double red[NS * 16];
   const int prob = blockIdx.x / a.bpp;
   const int blk = blockIdx.x % a.bpp;
   const Ctl& ctl = a.ctl[prob];
@@ -377,9 +384,10 @@ __global__ void __launch_bounds__(PT_THREADS) k_commit(Pt<T> a) {
   const long long nv = a.nvox;
   const long long fo = (long long)prob * C * nv;
   const uint8_t* phase = a.phase + (long long)prob * nv;
-  double acc[8];
+  const bool commit = a.commit != 0;
+  double acc[NS];
 #pragma unroll
-  for (int k = 0; k < 8; ++k) acc[k] = 0.0;
+  for (int k = 0; k < NS; ++k) acc[k] = 0.0;
   for (long long v = (long long)blk * PT_THREADS + threadIdx.x; v < nv; v += (long long)a.bpp * PT_THREADS) {
     const int ph = phase[v];
     if constexpr (C == 6) {
@@ -397,7 +405,7 @@ __global__ void __launch_bounds__(PT_THREADS) k_commit(Pt<T> a) {
         const double* hs = a.hist ? a.hist + (long long)prob * HIST_SLOTS * nv + v : nullptr;
         double* dps = a.hist ? a.hist + (long long)prob * HIST_SLOTS * nv + v + 7 * nv : nullptr;
         PaOut o;
-        pa66_point(in, e, st, nv, st, en, o, &dis, &cpl, hs, dps);
+        pa66_point(in, e, st, nv, commit ? st : nullptr, en, o, &dis, &cpl, hs, dps);
 #pragma unroll
         for (int c = 0; c < 6; ++c) sg[c] = o.sig[c];
       } else {
@@ -416,11 +424,16 @@ __global__ void __launch_bounds__(PT_THREADS) k_commit(Pt<T> a) {
 #pragma unroll
       for (int c = 0; c < 6; ++c) {
         acc[c] += sg[c];
-        a.xn[fo + c * nv + v] = T(e[c]);  // the committed strain (exact: e was read from T)
-        a.f[fo + c * nv + v] = T(sg[c]);
+        acc[8 + c] += e[c];
       }
       acc[6] += dis;
       acc[7] += cpl;
+      if (!commit) continue;
+#pragma unroll
+      for (int c = 0; c < 6; ++c) {
+        a.xn[fo + c * nv + v] = T(e[c]);  // the committed strain (exact: e was read from T)
+        a.f[fo + c * nv + v] = T(sg[c]);
+      }
       if (a.pv_diss) {
         a.pv_diss[(long long)prob * nv + v] = dis;
         a.pv_coup[(long long)prob * nv + v] = cpl;
@@ -431,11 +444,11 @@ __global__ void __launch_bounds__(PT_THREADS) k_commit(Pt<T> a) {
       for (int c = 0; c < 3; ++c) acc[c] -= kap * (double)a.x[fo + c * nv + v];
     }
   }
-  block_sum<8>(acc, red);
+  block_sum<NS>(acc, red);
   if (threadIdx.x == 0) {
     double* out = a.part + ((long long)prob * a.maxblk + blk) * NPART;
 #pragma unroll
-    for (int k = 0; k < 8; ++k) out[k] = acc[k];
+    for (int k = 0; k < NS; ++k) out[k] = acc[k];
   }
 }
 
@@ -760,12 +773,12 @@ __global__ void __launch_bounds__(RED_THREADS) k_reduce_out(Ctl* ctl, const doub
 // launchers
 // ---------------------------------------------------------------------------
 template <typename T>
-void launch_init_mech(const Pt<T>& a, int scheme, hipStream_t s) {
-  hipLaunchKernelGGL((k_init<T, 6>), dim3(a.nprob * a.bpp), dim3(PT_THREADS), 0, s, a, scheme == 0 ? 1 : 0);
+void launch_init_mech(const Pt<T>& a, int scheme, hipStream_t s, int keep_x) {
+  hipLaunchKernelGGL((k_init<T, 6>), dim3(a.nprob * a.bpp), dim3(PT_THREADS), 0, s, a, scheme == 0 ? 1 : 0, keep_x);
 }
 template <typename T>
 void launch_init_th(const Pt<T>& a, int scheme, hipStream_t s) {
-  hipLaunchKernelGGL((k_init<T, 3>), dim3(a.nprob * a.bpp), dim3(PT_THREADS), 0, s, a, scheme == 0 ? 1 : 0);
+  hipLaunchKernelGGL((k_init<T, 3>), dim3(a.nprob * a.bpp), dim3(PT_THREADS), 0, s, a, scheme == 0 ? 1 : 0, 0);
 }
 template <typename T>
 void launch_eval(const Pt<T>& a, int C, hipStream_t s) {
@@ -818,7 +831,7 @@ void launch_tangent_sum(const Pt<T>& a, hipStream_t s) {
   template void launch_init_linear<T>(const Pt<T>&, hipStream_t);       \
   template void launch_partials<T>(const Pt<T>&, hipStream_t);          \
   template void launch_tangent_sum<T>(const Pt<T>&, hipStream_t);       \
-  template void launch_init_mech<T>(const Pt<T>&, int, hipStream_t);    \
+  template void launch_init_mech<T>(const Pt<T>&, int, hipStream_t, int); \
   template void launch_init_th<T>(const Pt<T>&, int, hipStream_t);      \
   template void launch_eval<T>(const Pt<T>&, int, hipStream_t);         \
   template void launch_history<T>(const Pt<T>&, hipStream_t);           \

@@ -65,8 +65,9 @@ void validate_laws(const hom_law* laws, int n);
 class BatchImpl {
  public:
   virtual ~BatchImpl() = default;
-  virtual void solve(const double* strain, const hom_macro_temp* temp, const double* dt, hom_result* out) = 0;
+  virtual void solve(const hom_load* loads, hom_result* out) = 0;  // one load per problem
   virtual size_t device_bytes() const = 0;
+  virtual int problems() const = 0;
   virtual size_t state_size() const = 0;
   virtual void get_state(void* buf) = 0;
   virtual void set_state(const void* buf) = 0;

@@ -415,6 +415,7 @@ struct Group {
     a.dDdt = dDdt;
     a.inc_pm = inc_pm_d;
     a.s0 = nullptr;
+    a.commit = 1;
     return a;
   }
 };
@@ -456,6 +457,8 @@ class BatchT : public BatchImpl {
       prof.ms[k] = 0.0;
     }
   }
+
+  int problems() const override { return (int)where.size(); }
 
   size_t device_bytes() const override {
     size_t b = 0;
@@ -700,103 +703,209 @@ class BatchT : public BatchImpl {
     }
   }
 
-  void solve_phys(Group<T>& G, int phys) {
+  // Mechanics of one increment up to convergence; restart keeps the current
+  // strain field (a later staggered solve at a new temperature).
+  void mech_iterate(Group<T>& G, bool restart) {
     const bool basic = opts.scheme == HOM_SCHEME_BASIC;
-    Pt<T> q = G.pt(phys);
-    check_tiles(G, phys);
-    prof.offset = phys * K_COUNT;
+    Pt<T> q = G.pt(0);
+    check_tiles(G, 0);
+    prof.offset = 0;
     prof.begin(K_INIT, stream);
-    if (phys == 0)
-      launch_init_mech<T>(q, opts.scheme, stream);
-    else
-      launch_init_th<T>(q, opts.scheme, stream);
+    launch_init_mech<T>(q, opts.scheme, stream, restart ? 1 : 0);
     prof.end(stream);
-    if (phys == 0 && G.state) {
+    if (G.state) {
       prof.begin(K_HIST, stream);
       launch_history<T>(q, stream);
       prof.end(stream);
     }
-    const Limits lim = limits(phys);
-    Ctl* ctl = phys == 0 ? G.ctl_m : G.ctl_t;
-    iterate(G, phys, basic, iteration_cap(lim, basic));
-    if (phys == 0 && G.dsdt) launch_partials<T>(q, stream);  // before the commit: they need state n
+    iterate(G, 0, basic, iteration_cap(limits(0), basic));
+  }
+
+  // Effective sums of the converged mechanics into ctl.out (copied to ctl_h);
+  // commit: also commit the increment of every converged problem.
+  void mech_finish(Group<T>& G, bool commit) {
+    Pt<T> q = G.pt(0);
+    q.commit = commit ? 1 : 0;
+    if (commit && G.dsdt) launch_partials<T>(q, stream);  // before the commit: they need state n
     prof.begin(K_COMMIT, stream);
-    launch_commit<T>(q, phys == 0 ? 6 : 3, stream);
+    launch_commit<T>(q, 6, stream);
     prof.end(stream);
     prof.begin(K_REDOUT, stream);
-    launch_reduce_out(ctl, G.part, G.maxblk, G.pt_bpp, G.nprob, phys == 0 ? 8 : 3, 1.0 / (double)G.nvox, stream);
+    launch_reduce_out(G.ctl_m, G.part, G.maxblk, G.pt_bpp, G.nprob, MECH_SUMS, 1.0 / (double)G.nvox, stream);
     prof.end(stream);
-    HIPCHK(hipMemcpyAsync(G.ctl_h, ctl, sizeof(Ctl) * G.nprob, hipMemcpyDeviceToHost, stream));
+    HIPCHK(hipMemcpyAsync(G.ctl_h, G.ctl_m, sizeof(Ctl) * G.nprob, hipMemcpyDeviceToHost, stream));
+    HIPCHK(hipStreamSynchronize(stream));
+    prof.collect();
+  }
+
+  void thermal_solve(Group<T>& G) {
+    const bool basic = opts.scheme == HOM_SCHEME_BASIC;
+    Pt<T> q = G.pt(1);
+    check_tiles(G, 1);
+    prof.offset = K_COUNT;
+    prof.begin(K_INIT, stream);
+    launch_init_th<T>(q, opts.scheme, stream);
+    prof.end(stream);
+    iterate(G, 1, basic, iteration_cap(limits(1), basic));
+    prof.begin(K_COMMIT, stream);
+    launch_commit<T>(q, 3, stream);
+    prof.end(stream);
+    prof.begin(K_REDOUT, stream);
+    launch_reduce_out(G.ctl_t, G.part, G.maxblk, G.pt_bpp, G.nprob, 3, 1.0 / (double)G.nvox, stream);
+    prof.end(stream);
+    HIPCHK(hipMemcpyAsync(G.ctl_h, G.ctl_t, sizeof(Ctl) * G.nprob, hipMemcpyDeviceToHost, stream));
     HIPCHK(hipStreamSynchronize(stream));
     prof.collect();
   }
 
   static int pipeline_mode_host(int m) { return (m == M_EVAL || m == M_CG || m == M_BASIC) ? 1 : 0; }
 
-  void solve(const double* strain, const hom_macro_temp* temp, const double* dt, hom_result* out) override {
+  static constexpr int kMaxStagger = 30;
+
+  void solve(const hom_load* loads, hom_result* out) override {
     const int n = (int)where.size();
     for (int i = 0; i < n; ++i) {
-      if (!(dt[i] > 0.0) || !std::isfinite(dt[i])) fail(HOM_E_ARG, "dt must be positive and finite");
-      if (!(temp[i].theta > 0.0) || !std::isfinite(temp[i].theta)) fail(HOM_E_ARG, "theta must be positive");
+      const hom_load& L = loads[i];
+      if (!(L.dt > 0.0) || !std::isfinite(L.dt)) fail(HOM_E_ARG, "dt must be positive and finite");
+      if (!(L.temp.theta > 0.0) || !std::isfinite(L.temp.theta)) fail(HOM_E_ARG, "theta must be positive");
       for (int c = 0; c < 6; ++c)
-        if (!std::isfinite(strain[6 * i + c])) fail(HOM_E_ARG, "macro strain must be finite");
+        if (!std::isfinite(L.strain[c]) || !std::isfinite(L.stress[c]))
+          fail(HOM_E_ARG, "macro strain and stress must be finite");
       for (int c = 0; c < 3; ++c)
-        if (!std::isfinite(temp[i].grad[c])) fail(HOM_E_ARG, "temperature gradient must be finite");
+        if (!std::isfinite(L.temp.grad[c])) fail(HOM_E_ARG, "temperature gradient must be finite");
+      if (L.stress_mask > 63u) fail(HOM_E_ARG, "stress_mask has bits above 5");
+      if (L.adiabatic != 0 && L.adiabatic != 1) fail(HOM_E_ARG, "adiabatic must be 0 or 1");
+      if (L.stress_mask && opts.scheme != HOM_SCHEME_NEWTON_CG)
+        fail(HOM_E_UNSUPPORTED, "mixed boundary conditions need the Newton-CG scheme");
     }
     const double sq2 = std::sqrt(2.0);
     const double w[6] = {1, 1, 1, sq2, sq2, sq2};
     for (auto& gp : groups) {
       Group<T>& G = *gp;
-      for (int j = 0; j < G.nprob; ++j) {
-        const int i = G.members[j];
-        ProbInc& in = G.inc_h[j];
-        fill_inc(in, laws, temp[i].theta, dt[i]);
-        for (int c = 0; c < 6; ++c) in.dE[c] = w[c] * strain[6 * i + c] - G.En[j][c];
-        for (int c = 0; c < 3; ++c) in.dG[c] = temp[i].grad[c] - G.Gp[j][c];
-      }
-      HIPCHK(hipMemcpyAsync(G.inc_d, G.inc_h, sizeof(ProbInc) * G.nprob, hipMemcpyHostToDevice, stream));
-      if (G.inc_pm_h) {  // the increment data at theta +- h_theta for the point partials
-        for (int j = 0; j < G.nprob; ++j) {
-          const int i = G.members[j];
-          fill_inc(G.inc_pm_h[2 * j], laws, temp[i].theta + FD_H_THETA, dt[i]);
-          fill_inc(G.inc_pm_h[2 * j + 1], laws, temp[i].theta - FD_H_THETA, dt[i]);
-        }
-        HIPCHK(hipMemcpyAsync(G.inc_pm_d, G.inc_pm_h, sizeof(ProbInc) * 2 * G.nprob, hipMemcpyHostToDevice,
-                              stream));
+      const int np = G.nprob;
+      std::vector<double> th(np), thn(np), pipes(np, 0.0), thprev(np, 0.0), gprev(np, 0.0);
+      std::vector<int> newton(np, 0), krylov(np, 0), stag(np, 0);
+      bool any_adi = false;
+      for (int j = 0; j < np; ++j) {
+        const hom_load& L = loads[G.members[j]];
+        th[j] = thn[j] = L.temp.theta;
+        any_adi = any_adi || L.adiabatic;
       }
       G.tan_ok = false;
-      solve_phys(G, 0);
-      std::vector<Ctl> mech(G.ctl_h, G.ctl_h + G.nprob);
+      // implicit staggering (adiabatic problems): mechanics at fixed theta,
+      // then theta^{n+1} = theta^n + dt <D> / <c0>, until theta is stationary;
+      // every later mechanical solve restarts from the last strain field
+      for (int s = 0;; ++s) {
+        for (int j = 0; j < np; ++j) {
+          const hom_load& L = loads[G.members[j]];
+          ProbInc& in = G.inc_h[j];
+          fill_inc(in, laws, th[j], L.dt);
+          in.smask = (int)L.stress_mask;
+          for (int c = 0; c < 6; ++c) {
+            const bool sc = (L.stress_mask >> c) & 1u;
+            in.dE[c] = sc ? 0.0 : w[c] * L.strain[c] - G.En[j][c];
+            in.S[c] = sc ? w[c] * L.stress[c] : 0.0;
+          }
+          for (int c = 0; c < 3; ++c) in.dG[c] = L.temp.grad[c] - G.Gp[j][c];
+          if (G.inc_pm_h) {  // the increment data at theta +- h_theta for the point partials
+            fill_inc(G.inc_pm_h[2 * j], laws, th[j] + FD_H_THETA, L.dt);
+            fill_inc(G.inc_pm_h[2 * j + 1], laws, th[j] - FD_H_THETA, L.dt);
+          }
+        }
+        HIPCHK(hipMemcpyAsync(G.inc_d, G.inc_h, sizeof(ProbInc) * np, hipMemcpyHostToDevice, stream));
+        if (G.inc_pm_h)
+          HIPCHK(hipMemcpyAsync(G.inc_pm_d, G.inc_pm_h, sizeof(ProbInc) * 2 * np, hipMemcpyHostToDevice, stream));
+        mech_iterate(G, s > 0);
+        mech_finish(G, !any_adi);
+        for (int j = 0; j < np; ++j) {
+          pipes[j] += G.ctl_h[j].pipelines;
+          newton[j] += G.ctl_h[j].newton_it;
+          krylov[j] += G.ctl_h[j].krylov;
+          stag[j] += 1;
+        }
+        if (!any_adi) break;
+        // the temperature each adiabatic problem moves to. The staggering has
+        // converged where the heat equation's image of theta,
+        // t = theta^n + dt <D>(theta) / <c0>, stays within tol times the
+        // change of theta; otherwise the next theta is the secant root of
+        // g(theta) = t - theta through the last two iterates (the first step
+        // is the plain fixed-point step theta = t).
+        std::vector<double> next(th);
+        bool moved = false;
+        for (int j = 0; j < np; ++j) {
+          const hom_load& L = loads[G.members[j]];
+          const Ctl& c = G.ctl_h[j];
+          if (!L.adiabatic || c.status != 1) continue;
+          const double t = thn[j] + L.dt * c.out[7] / G.c0mean[j];
+          if (!std::isfinite(t) || !(t > 0.0)) {
+            G.ctl_h[j].status = HOM_E_NAN;
+            G.ctl_h[j].mode = M_FAIL;
+            continue;
+          }
+          const double g = t - th[j];
+          if (std::fabs(g) <= 10.0 * opts.tol * std::fabs(t - thn[j]) + 1e-12 * thn[j]) continue;
+          double tn = t;
+          if (s > 0 && g != gprev[j]) {
+            const double sec = th[j] - g * (th[j] - thprev[j]) / (g - gprev[j]);
+            if (std::isfinite(sec) && sec > 0.0) tn = sec;
+          }
+          thprev[j] = th[j];
+          gprev[j] = g;
+          next[j] = tn;
+          moved = true;
+        }
+        if (moved && s + 1 < kMaxStagger) {
+          th = next;
+          continue;
+        }
+        // final: commit at the temperatures of the last solve; a problem whose
+        // temperature still moves after the last staggered solve does not commit
+        for (int j = 0; j < np; ++j)
+          if (next[j] != th[j]) {
+            G.ctl_h[j].status = HOM_E_NOT_CONVERGED;
+            G.ctl_h[j].mode = M_FAIL;
+          }
+        HIPCHK(hipMemcpyAsync(G.ctl_m, G.ctl_h, sizeof(Ctl) * np, hipMemcpyHostToDevice, stream));
+        mech_finish(G, true);
+        break;
+      }
+      std::vector<Ctl> mech(G.ctl_h, G.ctl_h + np);
       // the conduction field now holds the new mean gradient
-      for (int j = 0; j < G.nprob; ++j)
-        for (int c = 0; c < 3; ++c) G.Gp[j][c] = temp[G.members[j]].grad[c];
-      solve_phys(G, 1);
-      for (int j = 0; j < G.nprob; ++j) {
+      for (int j = 0; j < np; ++j)
+        for (int c = 0; c < 3; ++c) G.Gp[j][c] = loads[G.members[j]].temp.grad[c];
+      thermal_solve(G);
+      bool all = opts.scheme == HOM_SCHEME_NEWTON_CG;
+      for (int j = 0; j < np; ++j) {
         const int i = G.members[j];
+        const hom_load& L = loads[i];
         const Ctl& cm = mech[j];
         const Ctl& ct = G.ctl_h[j];
         hom_result& r = out[i];
         std::memset(&r, 0, sizeof(r));
-        for (int c = 0; c < 6; ++c) r.stress[c] = cm.out[c] / w[c];
+        for (int c = 0; c < 6; ++c) {
+          r.stress[c] = cm.out[c] / w[c];
+          r.strain[c] = ((L.stress_mask >> c) & 1u) ? cm.out[8 + c] / w[c] : L.strain[c];
+        }
         for (int c = 0; c < 3; ++c) r.heat_flux[c] = ct.out[c];
         r.dissipation = cm.out[6];
         r.coupling = cm.out[7];
         r.heat_capacity = G.c0mean[j];
         r.residual = cm.res;
-        r.newton_iters = cm.newton_it;
-        r.krylov_iters = cm.krylov;
+        r.newton_iters = newton[j];
+        r.krylov_iters = krylov[j];
         r.thermal_iters = ct.krylov > 0 ? ct.krylov : ct.newton_it;
-        r.pipelines = cm.pipelines;
+        r.pipelines = pipes[j];
         r.thermal_pipelines = ct.pipelines;
+        r.theta = th[j];
+        r.stagger_iters = stag[j];
         int st = HOM_OK;
         if (cm.status != 1) st = cm.status < 0 ? cm.status : HOM_E_NOT_CONVERGED;
         if (st == HOM_OK && ct.status != 1) st = ct.status < 0 ? ct.status : HOM_E_NOT_CONVERGED;
         r.status = st;
         if (cm.status == 1)
-          for (int c = 0; c < 6; ++c) G.En[j][c] = w[c] * strain[6 * i + c];
+          for (int c = 0; c < 6; ++c) G.En[j][c] = ((L.stress_mask >> c) & 1u) ? cm.out[8 + c] : w[c] * L.strain[c];
+        all = all && cm.status == 1;
       }
-      bool all = opts.scheme == HOM_SCHEME_NEWTON_CG;
-      for (int j = 0; j < G.nprob; ++j) all = all && mech[j].status == 1;
       G.tan_ok = all;
     }
   }
@@ -845,8 +954,10 @@ class BatchT : public BatchImpl {
           }
         }
         for (int col = 0; col < ncol; ++col) {
-          for (int j = 0; j < G.nprob; ++j)
+          for (int j = 0; j < G.nprob; ++j) {
+            G.inc_h[j].smask = 0;  // the tangents are derivatives at prescribed strain
             for (int c = 0; c < 6; ++c) G.inc_h[j].dE[c] = (c == col) ? 1.0 : 0.0;
+          }
           HIPCHK(hipMemcpyAsync(G.inc_d, G.inc_h, sizeof(ProbInc) * G.nprob, hipMemcpyHostToDevice, stream));
           launch_init_linear<T>(q, stream);
           iterate(G, col < 6 ? 2 : 3, false, cap);

@@ -82,6 +82,8 @@ class Result(ct.Structure):
         ("coupling", ct.c_double), ("heat_capacity", ct.c_double), ("residual", ct.c_double),
         ("newton_iters", ct.c_int32), ("krylov_iters", ct.c_int32), ("thermal_iters", ct.c_int32),
         ("status", ct.c_int32), ("pipelines", ct.c_double), ("thermal_pipelines", ct.c_double),
+        ("strain", ct.c_double * 6), ("theta", ct.c_double), ("stagger_iters", ct.c_int32),
+        ("reserved", ct.c_int32),
     ]
 
     def as_dict(self):
@@ -89,7 +91,32 @@ class Result(ct.Structure):
                     dissipation=self.dissipation, coupling=self.coupling, heat_capacity=self.heat_capacity,
                     residual=self.residual, newton_iters=self.newton_iters, krylov_iters=self.krylov_iters,
                     thermal_iters=self.thermal_iters, status=self.status, pipelines=self.pipelines,
-                    thermal_pipelines=self.thermal_pipelines)
+                    thermal_pipelines=self.thermal_pipelines, strain=np.array(self.strain[:]), theta=self.theta,
+                    stagger_iters=self.stagger_iters)
+
+
+class Load(ct.Structure):
+    _fields_ = [
+        ("strain", ct.c_double * 6), ("stress", ct.c_double * 6), ("stress_mask", ct.c_uint32),
+        ("adiabatic", ct.c_int32), ("temp", MacroTemp), ("dt", ct.c_double),
+    ]
+
+
+def make_load(strain, theta, grad, dt, stress=None, stress_mask=0, adiabatic=False) -> Load:
+    """hom_load; stress_mask: int bit mask or 6 booleans (True: stress-controlled)."""
+    L = Load()
+    for c in range(6):
+        L.strain[c] = float(strain[c])
+        L.stress[c] = 0.0 if stress is None else float(stress[c])
+    if not isinstance(stress_mask, (int, np.integer)):
+        stress_mask = sum(1 << c for c in range(6) if stress_mask[c])
+    L.stress_mask = int(stress_mask)
+    L.adiabatic = int(bool(adiabatic))
+    L.temp.theta = float(theta)
+    for c in range(3):
+        L.temp.grad[c] = float(grad[c])
+    L.dt = float(dt)
+    return L
 
 
 class Tangent(ct.Structure):
@@ -107,7 +134,7 @@ class Tangent(ct.Structure):
 EXPORTS = (
     "hom_default_options", "hom_setup", "hom_solve_increment", "hom_state_size", "hom_get_state",
     "hom_set_state", "hom_get_field", "hom_kernel_stats", "hom_set_profiling", "hom_device_bytes",
-    "hom_algorithmic_tangent", "hom_batch_algorithmic_tangent",
+    "hom_algorithmic_tangent", "hom_batch_algorithmic_tangent", "hom_solve_load", "hom_batch_solve_load",
     "hom_last_error", "hom_destroy",
     "hom_batch_setup", "hom_batch_solve_increment", "hom_batch_kernel_stats", "hom_batch_last_error",
     "hom_batch_destroy", "hom_apply_operator", "hom_eval_law",
@@ -149,6 +176,8 @@ def library(path: str | None = None):
     lib.hom_kernel_stats.argtypes = [ct.c_void_p, ct.POINTER(ct.c_char_p), ct.POINTER(ct.c_int64), dp, ct.c_int32]
     lib.hom_set_profiling.argtypes = [ct.c_void_p, ct.c_int32]
     lib.hom_algorithmic_tangent.argtypes = [ct.c_void_p, ct.c_int32, ct.POINTER(Tangent)]
+    lib.hom_solve_load.argtypes = [ct.c_void_p, ct.POINTER(Load), ct.POINTER(Result)]
+    lib.hom_batch_solve_load.argtypes = [ct.c_void_p, ct.POINTER(Load), ct.POINTER(Result)]
     lib.hom_batch_algorithmic_tangent.argtypes = [ct.c_void_p, ct.c_int32, ct.POINTER(Tangent)]
     lib.hom_device_bytes.argtypes = [ct.c_void_p]
     lib.hom_device_bytes.restype = ct.c_size_t
@@ -302,6 +331,18 @@ class Context:
         out["rc"] = rc
         return out
 
+    def solve_load(self, strain, theta, grad, dt, stress=None, stress_mask=0, adiabatic=False, check=True):
+        """hom_solve_load: mixed boundary conditions and / or the adiabatic heat
+        balance (theta is theta^n when adiabatic)."""
+        L = make_load(strain, theta, grad, dt, stress, stress_mask, adiabatic)
+        r = Result()
+        rc = self._lib.hom_solve_load(self._h, ct.byref(L), ct.byref(r))
+        if check:
+            _check(rc, self.error)
+        out = r.as_dict()
+        out["rc"] = rc
+        return out
+
     def field(self, which):
         nv = int(np.prod(self.shape))
         nc = {FIELD_STRAIN: 6, FIELD_STRESS: 6, FIELD_GRADIENT: 3}.get(which)
@@ -398,6 +439,14 @@ class Batch:
         d = _f64(dts).reshape(self.n)
         res = (Result * self.n)()
         rc = self._lib.hom_batch_solve_increment(self._h, _dptr(s), temps, _dptr(d), res)
+        _check(rc, lambda: self._lib.hom_batch_last_error(self._h).decode())
+        return [r.as_dict() for r in res]
+
+    def solve_load(self, loads):
+        """loads: one dict per problem with the keyword arguments of make_load."""
+        arr = (Load * self.n)(*[make_load(**d) for d in loads])
+        res = (Result * self.n)()
+        rc = self._lib.hom_batch_solve_load(self._h, arr, res)
         _check(rc, lambda: self._lib.hom_batch_last_error(self._h).decode())
         return [r.as_dict() for r in res]
 

@@ -39,12 +39,35 @@ def test_default_options(lib):
     assert o.tol == 1e-6 and o.use_graph == 1
 
 
-def test_struct_layout():
-    # field offsets follow the C declaration order with natural alignment
-    assert ct.sizeof(hom.Grid) == 40
-    assert hom.Law.E.offset == 8
-    assert ct.sizeof(hom.Law) == 8 + 6 * 8 + 8 + 32 * 8 + 10 * 8
-    assert ct.sizeof(hom.Result) == 6 * 8 + 3 * 8 + 4 * 8 + 4 * 4 + 2 * 8
+STRUCTS = {"hom_grid": hom.Grid, "hom_law": hom.Law, "hom_options": hom.Options, "hom_macro_temp": hom.MacroTemp,
+           "hom_result": hom.Result, "hom_load": hom.Load, "hom_tangent": hom.Tangent}
+
+
+def test_struct_layout(tmp_path):
+    """Every ctypes structure has the size and field offsets that the C
+    compiler gives the header's declaration."""
+    import shutil
+    import subprocess
+    if shutil.which("gcc") is None:
+        pytest.skip("no C compiler")
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "hom.h"', "int main(void) {"]
+    for cname, cls in STRUCTS.items():
+        lines.append(f'  printf("{cname} size %zu\\n", sizeof({cname}));')
+        for fname, _ in cls._fields_:
+            lines.append(f'  printf("{cname} {fname} %zu\\n", offsetof({cname}, {fname}));')
+    lines.append("  return 0;\n}")
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
+    got = {}
+    for ln in subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.splitlines():
+        c, f, v = ln.split()
+        got[(c, f)] = int(v)
+    for cname, cls in STRUCTS.items():
+        assert ct.sizeof(cls) == got[(cname, "size")], cname
+        for fname, _ in cls._fields_:
+            assert getattr(cls, fname).offset == got[(cname, fname)], (cname, fname)
 
 
 def test_missing_library_raises(monkeypatch, tmp_path):
