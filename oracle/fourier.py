@@ -74,3 +74,43 @@ def fft3(f):
 def ifft3(F):
     """Inverse transform over the last three axes, real part (input Hermitian)."""
     return np.fft.ifftn(F, axes=(-3, -2, -1)).real
+
+
+def rotated_wavevectors(shape_zyx, lengths_xyz=(1.0, 1.0, 1.0)):
+    """Modified wave vectors of the rotated finite-difference scheme (Willot's
+    discretization, the paper's "staggered grid" citation in Sec. 5.2):
+    with theta_j = 2 pi k_j / n_j and h_j = L_j / n_j,
+
+        k_j = (exp(i theta_j) - 1) / h_j * prod_{l != j} (1 + exp(i theta_l)) / 2,
+
+    the Fourier symbol of the difference along j of a corner displacement,
+    averaged over the 4 cell edges parallel to j. Complex (3, nz, ny, nx)."""
+    nz, ny, nx = shape_zyx
+    e = []
+    h = []
+    for n, L, axis in ((nx, lengths_xyz[0], 2), (ny, lengths_xyz[1], 1), (nz, lengths_xyz[2], 0)):
+        shape = [1, 1, 1]
+        shape[axis] = n
+        e.append(np.exp(2j * np.pi * np.arange(n) / n).reshape(shape))
+        h.append(L / n)
+    k = []
+    for j in range(3):
+        term = (e[j] - 1.0) / h[j]
+        for l in range(3):
+            if l != j:
+                term = term * (1.0 + e[l]) / 2.0
+        k.append(np.broadcast_to(term, (nz, ny, nx)))
+    return np.stack(k)
+
+
+def rotated_directions(shape_zyx, lengths_xyz=(1.0, 1.0, 1.0)):
+    """Complex unit vectors n = k / |k| of the rotated scheme (|k|^2 = sum_j
+    |k_j|^2); zero where k = 0: the mean, and the modes with k_j = 0 for every
+    j (a Nyquist index on two axes), which the scheme cannot see. "Zero" means
+    |k| below 1e-12 of the largest possible |k|, sqrt(sum_j (2 / h_j)^2)."""
+    nz, ny, nx = shape_zyx
+    k = rotated_wavevectors(shape_zyx, lengths_xyz)
+    mag = np.sqrt((np.abs(k) ** 2).sum(axis=0))
+    kmax = np.sqrt(sum((2.0 * n / L) ** 2 for n, L in zip((nx, ny, nz), lengths_xyz)))
+    safe = np.where(mag > 1e-300, mag, 1.0)
+    return np.where(mag > 1e-12 * kmax, k / safe, 0.0)

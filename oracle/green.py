@@ -51,3 +51,22 @@ def gradient_projector(q, n):
 def gamma_conduction(q, n, kappa0):
     """Green operator of a homogeneous conductor kappa0: n (n . q) / kappa0."""
     return gradient_projector(q, n) / kappa0
+
+
+def projector_hermitian(tau_m, n):
+    """Orthogonal projector (Hermitian inner product) onto sym(n (x) a),
+    a complex, for a complex unit direction n (n-bar . n = 1):
+    P tau = sym(n (x) u), u = 2 tau n-bar - n (n-bar . tau n-bar).
+    It equals projector() for a real n."""
+    t = tensor.mandel_to_matrix(tau_m)
+    nb = np.conj(n)
+    tn = _tau_n(t, nb)
+    q = (nb * tn).sum(axis=0)
+    u = 2.0 * tn - n * q[None]
+    out = 0.5 * (np.einsum("i...,j...->ij...", n, u) + np.einsum("i...,j...->ij...", u, n))
+    return tensor.matrix_to_mandel(out)
+
+
+def gradient_projector_hermitian(q, n):
+    """n (n-bar . q): orthogonal projector onto multiples of a complex unit n."""
+    return n * (np.conj(n) * q).sum(axis=0)[None]

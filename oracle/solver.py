@@ -56,12 +56,22 @@ def conjugate_gradient(apply, b, x0=None, rtol=1e-10, maxit=10000):
 class Cell:
     """A voxel microstructure with one constitutive law per phase id."""
 
-    def __init__(self, phases, laws, lengths=(1.0, 1.0, 1.0)):
+    def __init__(self, phases, laws, lengths=(1.0, 1.0, 1.0), discretization="ms"):
+        """discretization: "ms" (Moulinec-Suquet collocation, directions
+        xi / |xi|) or "rotated" (the modified wave vectors of the rotated
+        finite-difference scheme, fourier.rotated_wavevectors; Newton-CG and
+        CG only)."""
         self.phases = np.asarray(phases, dtype=np.uint8)
         self.shape = self.phases.shape
         self.laws = [make_law(p) for p in laws]
         self.masks = [self.phases == i for i in range(len(self.laws))]
-        self.n = fourier.directions(self.shape, lengths)
+        if discretization not in ("ms", "rotated"):
+            raise ValueError(f"unknown discretization {discretization}")
+        self.discretization = discretization
+        if discretization == "ms":
+            self.n = fourier.directions(self.shape, lengths)
+        else:
+            self.n = fourier.rotated_directions(self.shape, lengths)
         self.nvox = self.phases.size
         self.eps_n = np.zeros((6,) + self.shape)
         self.E_n = np.zeros(6)
@@ -123,9 +133,18 @@ class Cell:
 
     # ---- mechanical solvers -------------------------------------------
     def project(self, field):
+        if self.discretization == "rotated":
+            return fourier.ifft3(green.projector_hermitian(fourier.fft3(field), self.n))
         return fourier.ifft3(green.projector(fourier.fft3(field), self.n))
 
+    def project_gradient(self, field):
+        if self.discretization == "rotated":
+            return fourier.ifft3(green.gradient_projector_hermitian(fourier.fft3(field), self.n))
+        return fourier.ifft3(green.gradient_projector(fourier.fft3(field), self.n))
+
     def _basic(self, eps, theta, dt, tol, maxit):
+        if self.discretization != "ms":
+            raise ValueError("the basic scheme is built for the Moulinec-Suquet discretization only")
         lam0, mu0 = self.reference_medium(theta, dt)
         for it in range(1, maxit + 1):
             sig = self.evaluate(eps, theta, dt, with_tangent=False)[0]
@@ -169,7 +188,7 @@ class Cell:
                 if field_norm(d) <= tol * max(field_norm(g), 1e-300):
                     break
         else:
-            proj = lambda v: fourier.ifft3(green.gradient_projector(fourier.fft3(v), self.n))
+            proj = self.project_gradient
             b = -proj(self.kappa[None] * G[:, None, None, None])
             apply = lambda v: proj(self.kappa[None] * v)
             x0 = self.g
