@@ -446,6 +446,7 @@ def main():
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--no-surrogate", action="store_true")
     ap.add_argument("--no-tangent", action="store_true")
+    ap.add_argument("--rotated", action="store_true", help="rotated finite-difference discretization")
     ap.add_argument("--calib-copy", action="store_true", help="run a 1 GiB device copy (PMC calibration)")
     ap.add_argument("--pmc-summary", nargs="+", metavar="DIR",
                     help="summarize rocprofv3 --pmc output folders (FETCH_SIZE, WRITE_SIZE[, request sizes]) "
@@ -495,8 +496,9 @@ def main():
         torch.cuda.synchronize()
         del a, b
 
+    disc = hom.DISC_ROTATED if args.rotated else hom.DISC_COLLOCATION
     ctx = hom.Context(wl.phases, wl.laws, scheme=hom.SCHEME_NEWTON_CG, precision=hom.FP32, tol=1e-6,
-                      autotune=1)
+                      autotune=1, discretization=disc)
     print(f"setup done: {n}^3, {wl.record['count']} fibres, fraction {wl.record['fraction']:.4f}, "
           f"{ctx.device_bytes() / 2**30:.1f} GiB on device, generator {gen_s:.1f} s", file=sys.stderr, flush=True)
 
@@ -602,6 +604,7 @@ def main():
         "config": {"workload": f"fibres{n}_pa66_glass", "grid": n, "fibres": wl.record["count"],
                    "fibre_fraction": round(wl.record["fraction"], 4), "scheme": "newton-cg",
                    "fields": "fp32", "reductions": "fp64", "tol": 1e-6,
+                   "discretization": "rotated" if args.rotated else "collocation",
                    "increments": f"{args.warmup}..{total - 1} of 50"},
         "thermal_voxel_iters_per_s": round(tpipes * nvox / elapsed, 1),
         "newton_per_step": newton / args.steps, "krylov_per_step": krylov / args.steps,

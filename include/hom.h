@@ -86,6 +86,11 @@ typedef struct {
 #define HOM_SCHEME_NEWTON_CG 1 /* inexact Newton with CG on the projected tangent system */
 #define HOM_FP64 0             /* all fields in FP64 */
 #define HOM_FP32 1             /* FP32 fields; FP64 reductions, CG scalars, return mapping and state */
+#define HOM_DISC_COLLOCATION 0 /* Moulinec-Suquet trigonometric collocation (Sec. 5.4) */
+#define HOM_DISC_ROTATED 1     /* rotated finite differences: the projector with modified wave vectors
+                                  k_j = (e_j - 1) / h_j prod_{l != j} (1 + e_l) / 2, e_j = exp(i 2 pi k_j / n_j),
+                                  the discretization the paper cites for its stiffness samples (Sec. 5.2,
+                                  "staggered grid"); Newton-CG only */
 
 typedef struct {
   int32_t scheme;      /* HOM_SCHEME_* */
@@ -103,6 +108,7 @@ typedef struct {
                           temperature and coupling tangents need (hom_algorithmic_tangent,
                           what = 1); costs 13 field components of memory and one pass of
                           14 PA66 point evaluations per increment */
+  int32_t discretization; /* HOM_DISC_*; default collocation */
 } hom_options;
 
 /* Macroscopic temperature input: theta [K] and its gradient [K/m]. */
@@ -316,7 +322,9 @@ void hom_mlp_destroy(hom_mlp* net);
  * arrays of ncomp x nvox (component-major). ncomp = 6 (Mandel) with op 0 =
  * projector P(n) of the laminate equation (Sec. 3.2) or op 1 = isotropic
  * reference Green operator (p0 = lambda0, p1 = mu0); ncomp = 3 with op 2 =
- * n (n . q) or op 3 = n (n . q) / p0. precision: HOM_FP64 / HOM_FP32. */
+ * n (n . q) or op 3 = n (n . q) / p0; op 4 (ncomp 6) and op 5 (ncomp 3): the
+ * projectors of the rotated discretization (HOM_DISC_ROTATED). precision:
+ * HOM_FP64 / HOM_FP32. */
 int hom_apply_operator(const hom_grid* grid, int32_t ncomp, int32_t op, double p0, double p1,
                        int32_t precision, const double* in, double* out);
 

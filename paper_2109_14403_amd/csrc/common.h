@@ -22,7 +22,10 @@ constexpr int MAX_MAXWELL = 16;
 constexpr int NPART = 16;  // FP64 partial sums per block
 
 enum Mode : int { M_DONE = 0, M_EVAL = 1, M_CG = 2, M_BASIC = 3, M_FAIL = -1 };
-enum Green : int { G_PROJ = 0, G_GAMMA0 = 1, G_GRADPROJ = 2, G_GAMMA_TH = 3 };
+// Green operators: projectors and isotropic reference operators of the
+// collocation scheme; *_ROT: the projectors of the rotated finite-difference
+// scheme (complex modified wave vectors).
+enum Green : int { G_PROJ = 0, G_GAMMA0 = 1, G_GRADPROJ = 2, G_GAMMA_TH = 3, G_PROJ_ROT = 4, G_GRADPROJ_ROT = 5 };
 enum LawKind : int { LAW_TE = 1, LAW_PA66 = 2 };
 
 // Per-problem solver control, owned by the device. The reduce kernels are

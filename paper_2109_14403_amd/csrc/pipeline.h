@@ -96,6 +96,68 @@ __device__ __forceinline__ void green_mech(c2<T>* v, T n0, T n1, T n2, T cs, T c
   v[5] = cscale(cscale(cscale(u0, n1) + cscale(u1, n0), cs) - cscale(qn, n0 * n1), s2);
 }
 
+// Rotated finite-difference scheme: with e_j = exp(i 2 pi k_j / n_j) and
+// h_j = L_j / n_j, k_j = (e_j - 1) / h_j * prod_{l != j} (1 + e_l) / 2 (the
+// difference of a corner displacement along j averaged over the 4 cell edges
+// parallel to j); n = k / |k|, zero where |k| < 1e-12 sqrt(sum_j (2 / h_j)^2).
+// ex, ey, ez are exp(-i 2 pi k_j / n_j) (forward twiddles).
+template <typename T>
+__device__ __forceinline__ void rotated_direction(c2<T> ex, c2<T> ey, c2<T> ez, int nx, int ny, int nz,
+                                                  const double* len, c2<T>* n, bool& zero) {
+  const c2<T> e[3] = {conjg(ex), conjg(ey), conjg(ez)};
+  const T ih[3] = {T(nx / len[0]), T(ny / len[1]), T(nz / len[2])};
+  c2<T> d[3], av[3];
+#pragma unroll
+  for (int j = 0; j < 3; ++j) {
+    d[j] = cscale(e[j] - mk(T(1), T(0)), ih[j]);
+    av[j] = cscale(e[j] + mk(T(1), T(0)), T(0.5));
+  }
+  n[0] = cmul(d[0], cmul(av[1], av[2]));
+  n[1] = cmul(d[1], cmul(av[0], av[2]));
+  n[2] = cmul(d[2], cmul(av[0], av[1]));
+  T m2 = T(0);
+#pragma unroll
+  for (int j = 0; j < 3; ++j) m2 += n[j].x * n[j].x + n[j].y * n[j].y;
+  const T kmax2 = T(4) * (ih[0] * ih[0] + ih[1] * ih[1] + ih[2] * ih[2]);
+  zero = !(m2 > T(1e-24) * kmax2);
+  const T inv = zero ? T(0) : T(1) / sqrt(m2);
+#pragma unroll
+  for (int j = 0; j < 3; ++j) n[j] = cscale(n[j], inv);
+}
+
+// Hermitian orthogonal projector onto sym(n (x) a) for a complex unit n:
+// u = tau conj(n), q = conj(n) . u, out = sym(n (x) (2 u - q n)).
+template <typename T>
+__device__ __forceinline__ void green_mech_herm(c2<T>* v, const c2<T>* n) {
+  const T r2 = T(0.70710678118654752);
+  const c2<T> t[3][3] = {{v[0], cscale(v[5], r2), cscale(v[4], r2)},
+                         {cscale(v[5], r2), v[1], cscale(v[3], r2)},
+                         {cscale(v[4], r2), cscale(v[3], r2), v[2]}};
+  const c2<T> nb[3] = {conjg(n[0]), conjg(n[1]), conjg(n[2])};
+  c2<T> u[3];
+#pragma unroll
+  for (int i = 0; i < 3; ++i) u[i] = cmul(t[i][0], nb[0]) + cmul(t[i][1], nb[1]) + cmul(t[i][2], nb[2]);
+  const c2<T> q = cmul(nb[0], u[0]) + cmul(nb[1], u[1]) + cmul(nb[2], u[2]);
+  c2<T> w[3];
+#pragma unroll
+  for (int i = 0; i < 3; ++i) w[i] = cscale(u[i], T(2)) - cmul(n[i], q);
+  v[0] = cmul(n[0], w[0]);
+  v[1] = cmul(n[1], w[1]);
+  v[2] = cmul(n[2], w[2]);
+  v[3] = cscale(cmul(n[1], w[2]) + cmul(n[2], w[1]), r2);  // sqrt2 * (n1 w2 + n2 w1) / 2
+  v[4] = cscale(cmul(n[0], w[2]) + cmul(n[2], w[0]), r2);
+  v[5] = cscale(cmul(n[0], w[1]) + cmul(n[1], w[0]), r2);
+}
+
+// n (conj(n) . g) for a complex unit n.
+template <typename T>
+__device__ __forceinline__ void green_grad_herm(c2<T>* v, const c2<T>* n) {
+  const c2<T> s = cmul(conjg(n[0]), v[0]) + cmul(conjg(n[1]), v[1]) + cmul(conjg(n[2]), v[2]);
+  v[0] = cmul(n[0], s);
+  v[1] = cmul(n[1], s);
+  v[2] = cmul(n[2], s);
+}
+
 template <typename T>
 __device__ __forceinline__ void green_grad(c2<T>* v, T n0, T n1, T n2, T s) {
   c2<T> q = cscale(cscale(v[0], n0) + cscale(v[1], n1) + cscale(v[2], n2), s);
@@ -512,14 +574,19 @@ __global__ void __launch_bounds__((N / Plan<N>::M) * TX * C)
   } else if (a.green == G_GAMMA_TH) {
     cs = T(1.0 / inc.kappa0);
   }
+  const bool rot = (a.green == G_PROJ_ROT || a.green == G_GRADPROJ_ROT);
   for (int idx = tid; idx < N * TX; idx += nth) {
     const int kz = idx / TX;
     const int kxi = idx - kz * TX;
     const int kxx = kb * TX + kxi;
     if (kxx >= P) continue;
-    T n0, n1, n2;
+    T n0 = T(0), n1 = T(0), n2 = T(0);
+    c2<T> nc[3];
     bool zero;
-    frequency_direction<T>(kxx, ky, kz, a.nx, a.ny, a.nz, a.len, n0, n1, n2, zero);
+    if (rot)
+      rotated_direction<T>(a.twx[kxx], a.twy[ky], tw[kz], a.nx, a.ny, a.nz, a.len, nc, zero);
+    else
+      frequency_direction<T>(kxx, ky, kz, a.nx, a.ny, a.nz, a.len, n0, n1, n2, zero);
     c2<T> v[C];
 #pragma unroll
     for (int cc = 0; cc < C; ++cc) v[cc] = buf[kz * L + kxi * C + cc];
@@ -538,6 +605,11 @@ __global__ void __launch_bounds__((N / Plan<N>::M) * TX * C)
         else
           v[cc] = mk(T(0), T(0));
       }
+    } else if (rot) {
+      if constexpr (C == 6)
+        green_mech_herm<T>(v, nc);
+      else
+        green_grad_herm<T>(v, nc);
     } else {
       if constexpr (C == 6)
         green_mech<T>(v, n0, n1, n2, cs, cn);

@@ -610,7 +610,9 @@ class BatchT : public BatchImpl {
   // d sigma / d theta.
   void iteration(Group<T>& G, int variant, bool basic) {
     const int phys = variant == 1 ? 1 : 0;
-    const int green = phys == 0 ? (basic ? G_GAMMA0 : G_PROJ) : (basic ? G_GAMMA_TH : G_GRADPROJ);
+    const bool rot = opts.discretization == HOM_DISC_ROTATED;
+    const int green = phys == 0 ? (basic ? G_GAMMA0 : (rot ? G_PROJ_ROT : G_PROJ))
+                                : (basic ? G_GAMMA_TH : (rot ? G_GRADPROJ_ROT : G_GRADPROJ));
     Pipe<T> a = G.pipe(phys, green);
     Pt<T> q = G.pt(phys);
     const int C = phys == 0 ? 6 : 3;
@@ -1095,6 +1097,10 @@ std::unique_ptr<BatchImpl> make_batch(int nprob, const hom_grid* grids, const ui
   validate_laws(laws, nlaws);
   if (!(opts.tol > 0.0)) fail(HOM_E_ARG, "tol must be positive");
   if (opts.scheme != HOM_SCHEME_BASIC && opts.scheme != HOM_SCHEME_NEWTON_CG) fail(HOM_E_ARG, "unknown scheme");
+  if (opts.discretization != HOM_DISC_COLLOCATION && opts.discretization != HOM_DISC_ROTATED)
+    fail(HOM_E_ARG, "unknown discretization");
+  if (opts.discretization == HOM_DISC_ROTATED && opts.scheme != HOM_SCHEME_NEWTON_CG)
+    fail(HOM_E_UNSUPPORTED, "the rotated discretization is built for the Newton-CG scheme");
   if (opts.precision == HOM_FP64) {
     auto b = std::make_unique<BatchT<double>>();
     b->init(nprob, grids, phases, laws, nlaws, opts);
@@ -1161,7 +1167,8 @@ void apply_operator(const hom_grid& g, int ncomp, int op, double p0, double p1, 
                     double* out) {
   for (int d = 0; d < 3; ++d)
     if (!supported_n(g.n[d])) fail(HOM_E_UNSUPPORTED, "unsupported grid size");
-  if (!((ncomp == 6 && (op == G_PROJ || op == G_GAMMA0)) || (ncomp == 3 && (op == G_GRADPROJ || op == G_GAMMA_TH))))
+  if (!((ncomp == 6 && (op == G_PROJ || op == G_GAMMA0 || op == G_PROJ_ROT)) ||
+        (ncomp == 3 && (op == G_GRADPROJ || op == G_GAMMA_TH || op == G_GRADPROJ_ROT))))
     fail(HOM_E_ARG, "operator / component count mismatch");
   if (op == G_GAMMA0 && !(p1 > 0.0 && p0 + 2.0 * p1 > 0.0)) fail(HOM_E_ARG, "invalid reference medium");
   if (op == G_GAMMA_TH && !(p0 > 0.0)) fail(HOM_E_ARG, "invalid reference conductivity");

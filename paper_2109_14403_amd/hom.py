@@ -27,6 +27,8 @@ SCHEME_BASIC = 0
 SCHEME_NEWTON_CG = 1
 FP64 = 0
 FP32 = 1
+DISC_COLLOCATION = 0
+DISC_ROTATED = 1
 
 FIELD_STRAIN = 0
 FIELD_STRESS = 1
@@ -37,6 +39,8 @@ OP_PROJECTOR = 0
 OP_GAMMA0 = 1
 OP_GRAD_PROJECTOR = 2
 OP_GAMMA_CONDUCTION = 3
+OP_PROJECTOR_ROTATED = 4
+OP_GRAD_PROJECTOR_ROTATED = 5
 
 MAX_MAXWELL = 16
 
@@ -69,6 +73,7 @@ class Options(ct.Structure):
         ("scheme", ct.c_int32), ("precision", ct.c_int32), ("tol", ct.c_double), ("thermal_tol", ct.c_double),
         ("max_iter", ct.c_int32), ("max_krylov", ct.c_int32), ("chunk", ct.c_int32), ("use_graph", ct.c_int32),
         ("profile", ct.c_int32), ("autotune", ct.c_int32), ("stream", ct.c_void_p), ("tangent", ct.c_int32),
+        ("discretization", ct.c_int32),
     ]
 
 
@@ -253,7 +258,8 @@ def make_law(p: dict) -> Law:
 
 
 def make_options(scheme=SCHEME_NEWTON_CG, precision=FP32, tol=1e-6, thermal_tol=0.0, max_iter=0, max_krylov=0,
-                 chunk=0, use_graph=1, profile=0, autotune=0, stream=None, tangent=0) -> Options:
+                 chunk=0, use_graph=1, profile=0, autotune=0, stream=None, tangent=0,
+                 discretization=0) -> Options:
     o = Options()
     library().hom_default_options(ct.byref(o))
     o.scheme = scheme
@@ -268,6 +274,7 @@ def make_options(scheme=SCHEME_NEWTON_CG, precision=FP32, tol=1e-6, thermal_tol=
     o.autotune = autotune
     o.stream = stream
     o.tangent = tangent
+    o.discretization = discretization
     return o
 
 
