@@ -317,6 +317,68 @@ int hom_surrogate_infer(hom_mlp* a, hom_mlp* b, const float* x_dev, float* y_dev
 const char* hom_mlp_last_error(const hom_mlp* net);
 void hom_mlp_destroy(hom_mlp* net);
 
+/* ---- direct deep material network (Sec. 3) ---------------------------------
+ * A two-phase direct DMN of depth K (1..10): a perfect binary tree of 2^K - 1
+ * laminates with free directions of lamination m (2^K - 1 three-vectors,
+ * normalized inside, ordered level K first and the root last) and 2^K leaf
+ * weights v (w = max(v, 0)); leaves alternate between phase 1 (the 1st, 3rd,
+ * ... leaf) and phase 2. Stiffnesses cross the ABI as 6 x 6 row-major
+ * matrices in normalized Voigt-Mandel notation, host FP64.
+ *
+ * Offline (Sec. 3.2): hom_dmn_homogenize is the linear homogenization
+ * function of n stiffness pairs; hom_dmn_loss_grad the loss
+ * J = (1/n) (sum_s e_s^q)^(1/q) + penalty (sum w - 1)^2, with
+ * e_s = |C_eff,s - DMN_s|_1 / |C_eff,s|_1 over the components, and its
+ * gradients for all n samples as one batch; hom_dmn_train runs epochs of
+ * random mini-batches (incomplete batches dropped) with AMSGrad and the
+ * paper's learning-rate modulation
+ * lr(epoch) = decay^epoch (lr_min + (lr_max - lr_min) (1 + cos(pi epoch / M)) / 2),
+ * writing the mean batch loss of each epoch to epoch_loss (epochs entries,
+ * or NULL). FP64 kernels, one work-group per sample.
+ *
+ * Online (Sec. 3.3, the online algorithm): n_points macroscopic points, each
+ * with its own internal variables and jumps; hom_dmn_online_step solves the
+ * balance of the jumps by Newton's method with the paper's backtracking
+ * (steps 1, 1/2, 1/4, ..., at most 8 cuts) and residual, at tolerance tol and
+ * at most maxit Newton steps, then commits (status HOM_OK) or not
+ * (HOM_E_NOT_CONVERGED). Phase laws: laws[0] for phase 1, laws[1] for phase
+ * 2 (at most one PA66). Depth up to 8 (one work-group of 2^K threads per
+ * point, the whole tree in LDS). */
+typedef struct hom_dmn hom_dmn;
+typedef struct hom_dmn_online hom_dmn_online;
+typedef struct {
+  double lr_max, lr_min; /* paper: 1.5e-2, 1.5e-3 */
+  int32_t half_period;   /* M; paper: 50 */
+  double decay;          /* paper: 0.999 */
+  double q, penalty;     /* paper: 10, 1e3 */
+} hom_dmn_train_opts;
+typedef struct {
+  double stress[6];      /* <sigma> = sum_i w_i sigma_i, components */
+  double coupling;       /* sum_i w_i D_i */
+  double dissipation;    /* sum_i w_i D_diss,i */
+  double dsde[36];       /* d<sigma>_I / dE_J, row-major, as hom_tangent.dsde */
+  double residual;
+  int32_t newton_iters;
+  int32_t status;
+} hom_dmn_result;
+void hom_dmn_default_train_opts(hom_dmn_train_opts* opts);
+int hom_dmn_create(int32_t K, uint64_t seed, hom_dmn** out);
+int hom_dmn_get_params(const hom_dmn* net, double* m, double* v);
+int hom_dmn_set_params(hom_dmn* net, const double* m, const double* v);
+int hom_dmn_homogenize(hom_dmn* net, int64_t n, const double* C1, const double* C2, double* C_out);
+int hom_dmn_loss_grad(hom_dmn* net, int64_t n, const double* C1, const double* C2, const double* C_eff,
+                      const hom_dmn_train_opts* opts, double* loss, double* grad_m, double* grad_v);
+int hom_dmn_train(hom_dmn* net, int64_t n, const double* C1, const double* C2, const double* C_eff, int32_t epochs,
+                  int32_t batch, uint64_t seed, const hom_dmn_train_opts* opts, double* epoch_loss);
+const char* hom_dmn_last_error(const hom_dmn* net);
+void hom_dmn_destroy(hom_dmn* net);
+int hom_dmn_online_create(const hom_dmn* net, const hom_law laws[2], int32_t n_points, double tol, int32_t maxit,
+                          hom_dmn_online** out);
+int hom_dmn_online_step(hom_dmn_online* o, const double* strain, const double* theta, const double* dt,
+                        hom_dmn_result* out);
+const char* hom_dmn_online_last_error(const hom_dmn_online* o);
+void hom_dmn_online_destroy(hom_dmn_online* o);
+
 /* ---- kernel-level entry points (used by the parity tests) ------------------
  * hom_apply_operator: out = IFFT(Op(n) FFT(in)) on one grid, in/out host FP64
  * arrays of ncomp x nvox (component-major). ncomp = 6 (Mandel) with op 0 =

@@ -232,7 +232,9 @@ class OnlineDMN:
             eps = self.leaf_strains(E, a)
             _, tan, *_ = self.evaluate(eps, theta, dt)
             Kmat = self.A.T @ self._blockdiag(tan) @ self.A
-            da = np.linalg.solve(Kmat, -g)
+            # minimal-norm solution: the jump of a laminate with a weightless
+            # side is a null mode and stays where it is
+            da = np.linalg.lstsq(Kmat, -g, rcond=1e-13)[0]
             res_old = res
             a = a + da
             res, g = self.residual(E, a, theta, dt)
@@ -248,7 +250,7 @@ class OnlineDMN:
         WC = self._blockdiag(tan)
         Kmat = self.A.T @ WC @ self.A
         one = np.tile(np.eye(6), (self.nleaf, 1))               # E -> every leaf
-        dadE = -np.linalg.solve(Kmat, self.A.T @ WC @ one)
+        dadE = -np.linalg.lstsq(Kmat, self.A.T @ WC @ one, rcond=1e-13)[0]
         dleaf = one + self.A @ dadE                              # d eps_leaf / dE
         Cbar = (np.tile(self.w.repeat(6)[:, None], (1, 6)) * (self._blockdiag_unweighted(tan) @ dleaf))
         Cbar = Cbar.reshape(self.nleaf, 6, 6).sum(axis=0)

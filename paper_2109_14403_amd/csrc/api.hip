@@ -3,6 +3,7 @@
 #include <new>
 #include <vector>
 
+#include "dmn.h"
 #include "mlp.h"
 #include "runtime.h"
 
@@ -13,6 +14,17 @@ struct hom_ctx {
 struct hom_batch {
   std::unique_ptr<hom::BatchImpl> impl;
   std::string err;
+};
+struct hom_dmn {
+  std::unique_ptr<hom::Dmn> net;
+  std::string err;
+};
+struct hom_dmn_online {
+  hom::DmnOnline* impl = nullptr;
+  std::string err;
+  ~hom_dmn_online() {
+    if (impl) hom::dmn_online_destroy(impl);
+  }
 };
 struct hom_mlp {
   std::unique_ptr<hom::Mlp> net;
@@ -209,6 +221,109 @@ int hom_batch_algorithmic_tangent(hom_batch* b, int32_t what, hom_tangent* out) 
 const char* hom_batch_last_error(const hom_batch* b) { return b ? b->err.c_str() : g_setup_error.c_str(); }
 
 void hom_batch_destroy(hom_batch* b) { delete b; }
+
+namespace {
+hom::DmnSchedule schedule_of(const hom_dmn_train_opts* o) {
+  hom::DmnSchedule s;
+  if (o) {
+    s.lr_max = o->lr_max;
+    s.lr_min = o->lr_min;
+    s.half_period = o->half_period;
+    s.decay = o->decay;
+    s.q = o->q;
+    s.penalty = o->penalty;
+  }
+  if (!(s.lr_max > 0.0) || !(s.lr_min >= 0.0) || s.half_period < 1 || !(s.decay > 0.0) || !(s.q >= 1.0) ||
+      !(s.penalty >= 0.0))
+    hom::fail(HOM_E_ARG, "invalid training options");
+  return s;
+}
+}  // namespace
+
+void hom_dmn_default_train_opts(hom_dmn_train_opts* o) {
+  if (!o) return;
+  const hom::DmnSchedule s;
+  o->lr_max = s.lr_max;
+  o->lr_min = s.lr_min;
+  o->half_period = s.half_period;
+  o->decay = s.decay;
+  o->q = s.q;
+  o->penalty = s.penalty;
+}
+
+int hom_dmn_create(int32_t K, uint64_t seed, hom_dmn** out) {
+  if (!out) return HOM_E_ARG;
+  *out = nullptr;
+  hom_dmn* d = new (std::nothrow) hom_dmn();
+  if (!d) return HOM_E_OOM;
+  int rc = guarded(&g_setup_error, [&] { d->net = std::make_unique<hom::Dmn>(K, seed); });
+  if (rc != HOM_OK) {
+    delete d;
+    return rc;
+  }
+  *out = d;
+  return HOM_OK;
+}
+
+int hom_dmn_get_params(const hom_dmn* d, double* m, double* v) {
+  if (!d || !d->net) return HOM_E_ARG;
+  return guarded(nullptr, [&] { d->net->get(m, v); });
+}
+
+int hom_dmn_set_params(hom_dmn* d, const double* m, const double* v) {
+  if (!d || !d->net) return HOM_E_ARG;
+  return guarded(&d->err, [&] { d->net->set(m, v); });
+}
+
+int hom_dmn_homogenize(hom_dmn* d, int64_t n, const double* C1, const double* C2, double* C_out) {
+  if (!d || !d->net) return HOM_E_ARG;
+  return guarded(&d->err, [&] { d->net->homogenize(n, C1, C2, C_out); });
+}
+
+int hom_dmn_loss_grad(hom_dmn* d, int64_t n, const double* C1, const double* C2, const double* C_eff,
+                      const hom_dmn_train_opts* opts, double* loss, double* gm, double* gv) {
+  if (!d || !d->net) return HOM_E_ARG;
+  return guarded(&d->err, [&] {
+    const double J = d->net->loss_grad(n, C1, C2, C_eff, gm, gv, schedule_of(opts));
+    if (loss) *loss = J;
+  });
+}
+
+int hom_dmn_train(hom_dmn* d, int64_t n, const double* C1, const double* C2, const double* C_eff, int32_t epochs,
+                  int32_t batch, uint64_t seed, const hom_dmn_train_opts* opts, double* epoch_loss) {
+  if (!d || !d->net) return HOM_E_ARG;
+  return guarded(&d->err, [&] { d->net->train(n, C1, C2, C_eff, epochs, batch, seed, epoch_loss, schedule_of(opts)); });
+}
+
+const char* hom_dmn_last_error(const hom_dmn* d) { return d ? d->err.c_str() : g_setup_error.c_str(); }
+
+void hom_dmn_destroy(hom_dmn* d) { delete d; }
+
+int hom_dmn_online_create(const hom_dmn* d, const hom_law laws[2], int32_t n_points, double tol, int32_t maxit,
+                          hom_dmn_online** out) {
+  if (!out) return HOM_E_ARG;
+  *out = nullptr;
+  if (!d || !d->net) return HOM_E_ARG;
+  hom_dmn_online* o = new (std::nothrow) hom_dmn_online();
+  if (!o) return HOM_E_OOM;
+  int rc = guarded(&g_setup_error, [&] { o->impl = hom::dmn_online_create(*d->net, laws, n_points, tol, maxit); });
+  if (rc != HOM_OK) {
+    delete o;
+    return rc;
+  }
+  *out = o;
+  return HOM_OK;
+}
+
+int hom_dmn_online_step(hom_dmn_online* o, const double* strain, const double* theta, const double* dt,
+                        hom_dmn_result* out) {
+  if (!o || !o->impl || !strain || !theta || !dt || !out) return HOM_E_ARG;
+  return guarded(&o->err, [&] { hom::dmn_online_step(o->impl, strain, theta, dt, out); });
+}
+
+const char* hom_dmn_online_last_error(const hom_dmn_online* o) { return o ? o->err.c_str() : g_setup_error.c_str(); }
+
+void hom_dmn_online_destroy(hom_dmn_online* o) { delete o; }
 
 int hom_mlp_create(int32_t n_in, int32_t n_out, uint64_t seed, hom_mlp** out) {
   if (!out) return HOM_E_ARG;

@@ -136,6 +136,24 @@ class Tangent(ct.Structure):
                     krylov_iters=self.krylov_iters, pipelines=self.pipelines, status=self.status)
 
 
+class DmnTrainOpts(ct.Structure):
+    _fields_ = [("lr_max", ct.c_double), ("lr_min", ct.c_double), ("half_period", ct.c_int32),
+                ("decay", ct.c_double), ("q", ct.c_double), ("penalty", ct.c_double)]
+
+
+class DmnResult(ct.Structure):
+    _fields_ = [
+        ("stress", ct.c_double * 6), ("coupling", ct.c_double), ("dissipation", ct.c_double),
+        ("dsde", ct.c_double * 36), ("residual", ct.c_double), ("newton_iters", ct.c_int32),
+        ("status", ct.c_int32),
+    ]
+
+    def as_dict(self):
+        return dict(stress=np.array(self.stress[:]), coupling=self.coupling, dissipation=self.dissipation,
+                    dsde=np.array(self.dsde[:]).reshape(6, 6), residual=self.residual,
+                    newton_iters=self.newton_iters, status=self.status)
+
+
 EXPORTS = (
     "hom_default_options", "hom_setup", "hom_solve_increment", "hom_state_size", "hom_get_state",
     "hom_set_state", "hom_get_field", "hom_kernel_stats", "hom_set_profiling", "hom_device_bytes",
@@ -143,6 +161,9 @@ EXPORTS = (
     "hom_last_error", "hom_destroy",
     "hom_batch_setup", "hom_batch_solve_increment", "hom_batch_kernel_stats", "hom_batch_last_error",
     "hom_batch_destroy", "hom_apply_operator", "hom_eval_law",
+    "hom_dmn_default_train_opts", "hom_dmn_create", "hom_dmn_get_params", "hom_dmn_set_params",
+    "hom_dmn_homogenize", "hom_dmn_loss_grad", "hom_dmn_train", "hom_dmn_last_error", "hom_dmn_destroy",
+    "hom_dmn_online_create", "hom_dmn_online_step", "hom_dmn_online_last_error", "hom_dmn_online_destroy",
     "hom_mlp_create", "hom_mlp_param_count", "hom_mlp_set_scaling", "hom_mlp_set_skip", "hom_mlp_fit_skip",
     "hom_mlp_get_params",
     "hom_mlp_set_params",
@@ -203,6 +224,26 @@ def library(path: str | None = None):
                                        ct.c_int32, dp, dp]
     lib.hom_eval_law.argtypes = [ct.POINTER(Law), ct.c_int64, dp, dp, dp, ct.c_double, ct.c_double, ct.c_int32,
                                  dp, dp, dp, dp, dp, dp]
+    lib.hom_dmn_default_train_opts.argtypes = [ct.POINTER(DmnTrainOpts)]
+    lib.hom_dmn_default_train_opts.restype = None
+    lib.hom_dmn_create.argtypes = [ct.c_int32, ct.c_uint64, ct.POINTER(ct.c_void_p)]
+    lib.hom_dmn_get_params.argtypes = [ct.c_void_p, dp, dp]
+    lib.hom_dmn_set_params.argtypes = [ct.c_void_p, dp, dp]
+    lib.hom_dmn_homogenize.argtypes = [ct.c_void_p, ct.c_int64, dp, dp, dp]
+    lib.hom_dmn_loss_grad.argtypes = [ct.c_void_p, ct.c_int64, dp, dp, dp, ct.POINTER(DmnTrainOpts), dp, dp, dp]
+    lib.hom_dmn_train.argtypes = [ct.c_void_p, ct.c_int64, dp, dp, dp, ct.c_int32, ct.c_int32, ct.c_uint64,
+                                  ct.POINTER(DmnTrainOpts), dp]
+    lib.hom_dmn_last_error.argtypes = [ct.c_void_p]
+    lib.hom_dmn_last_error.restype = ct.c_char_p
+    lib.hom_dmn_destroy.argtypes = [ct.c_void_p]
+    lib.hom_dmn_destroy.restype = None
+    lib.hom_dmn_online_create.argtypes = [ct.c_void_p, ct.POINTER(Law), ct.c_int32, ct.c_double, ct.c_int32,
+                                          ct.POINTER(ct.c_void_p)]
+    lib.hom_dmn_online_step.argtypes = [ct.c_void_p, dp, dp, dp, ct.POINTER(DmnResult)]
+    lib.hom_dmn_online_last_error.argtypes = [ct.c_void_p]
+    lib.hom_dmn_online_last_error.restype = ct.c_char_p
+    lib.hom_dmn_online_destroy.argtypes = [ct.c_void_p]
+    lib.hom_dmn_online_destroy.restype = None
     fp = ct.POINTER(ct.c_float)
     lib.hom_mlp_create.argtypes = [ct.c_int32, ct.c_int32, ct.c_uint64, ct.POINTER(ct.c_void_p)]
     lib.hom_mlp_param_count.argtypes = [ct.c_void_p]
@@ -626,3 +667,120 @@ def surrogate_infer(net_a: MLP, net_b: MLP, x_dev, threshold, floor_scale):
                                    floor_scale, ct.c_void_p(torch.cuda.current_stream().cuda_stream)),
            net_a.error)
     return y, spread, acc
+
+
+# ---------------------------------------------------------------------------
+# direct deep material network
+# ---------------------------------------------------------------------------
+def dmn_train_opts(**kw) -> DmnTrainOpts:
+    o = DmnTrainOpts()
+    library().hom_dmn_default_train_opts(ct.byref(o))
+    for k, v in kw.items():
+        setattr(o, k, v)
+    return o
+
+
+def _mats(a, n=None):
+    a = np.ascontiguousarray(a, dtype=np.float64).reshape(-1, 36)
+    if n is not None and a.shape[0] != n:
+        raise HomError(HOM_E_ARG, "stiffness arrays differ in length")
+    return a
+
+
+class Dmn:
+    """hom_dmn_*: a direct DMN of depth K (parameters m (2^K - 1, 3), v (2^K,))."""
+
+    def __init__(self, K, seed=0):
+        lib = library()
+        self._lib = lib
+        self.K = int(K)
+        h = ct.c_void_p()
+        _check(lib.hom_dmn_create(self.K, seed, ct.byref(h)), lambda: lib.hom_dmn_last_error(None).decode())
+        self._h = h
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self._lib.hom_dmn_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def error(self):
+        return self._lib.hom_dmn_last_error(self._h).decode()
+
+    def params(self):
+        m = np.empty((2 ** self.K - 1, 3))
+        v = np.empty(2 ** self.K)
+        _check(self._lib.hom_dmn_get_params(self._h, _dptr(m), _dptr(v)), self.error)
+        return m, v
+
+    def set_params(self, m, v):
+        _check(self._lib.hom_dmn_set_params(self._h, _dptr(_f64(m)), _dptr(_f64(v))), self.error)
+
+    def homogenize(self, C1, C2):
+        a = _mats(C1)
+        b = _mats(C2, a.shape[0])
+        out = np.empty_like(a)
+        _check(self._lib.hom_dmn_homogenize(self._h, a.shape[0], _dptr(a), _dptr(b), _dptr(out)), self.error)
+        return out.reshape(-1, 6, 6)
+
+    def loss_grad(self, C1, C2, Ceff, **opts):
+        a = _mats(C1)
+        b = _mats(C2, a.shape[0])
+        c = _mats(Ceff, a.shape[0])
+        o = dmn_train_opts(**opts)
+        J = ct.c_double()
+        gm = np.empty((2 ** self.K - 1, 3))
+        gv = np.empty(2 ** self.K)
+        _check(self._lib.hom_dmn_loss_grad(self._h, a.shape[0], _dptr(a), _dptr(b), _dptr(c), ct.byref(o),
+                                           ct.byref(J), _dptr(gm), _dptr(gv)), self.error)
+        return J.value, gm, gv
+
+    def train(self, C1, C2, Ceff, epochs, batch=32, seed=0, **opts):
+        a = _mats(C1)
+        b = _mats(C2, a.shape[0])
+        c = _mats(Ceff, a.shape[0])
+        o = dmn_train_opts(**opts)
+        hist = np.empty(max(int(epochs), 1))
+        _check(self._lib.hom_dmn_train(self._h, a.shape[0], _dptr(a), _dptr(b), _dptr(c), int(epochs), int(batch),
+                                       seed, ct.byref(o), _dptr(hist)), self.error)
+        return hist[:epochs]
+
+
+class DmnOnline:
+    """hom_dmn_online_*: a trained DMN at n_points macroscopic points with the
+    laws of its two phases."""
+
+    def __init__(self, net: Dmn, law1: dict, law2: dict, n_points, tol=1e-10, maxit=50):
+        lib = library()
+        self._lib = lib
+        self.n = int(n_points)
+        self._laws = (Law * 2)(make_law(law1), make_law(law2))
+        h = ct.c_void_p()
+        _check(lib.hom_dmn_online_create(net._h, self._laws, self.n, float(tol), int(maxit), ct.byref(h)),
+               lambda: lib.hom_dmn_online_last_error(None).decode())
+        self._h = h
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self._lib.hom_dmn_online_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def step(self, strains, thetas, dts):
+        e = _f64(strains).reshape(self.n, 6)
+        t = _f64(np.broadcast_to(thetas, (self.n,)))
+        d = _f64(np.broadcast_to(dts, (self.n,)))
+        out = (DmnResult * self.n)()
+        _check(self._lib.hom_dmn_online_step(self._h, _dptr(e), _dptr(t), _dptr(d), out),
+               lambda: self._lib.hom_dmn_online_last_error(self._h).decode())
+        return [r.as_dict() for r in out]

@@ -1,0 +1,173 @@
+"""The direct DMN (Sec. 3) on the GPU against the oracle.
+
+Offline: the linear homogenization function (the GPU uses the exact
+laminate rule with a 3 x 3 solve, the oracle the lambda form of Sec. 3.2),
+the loss and its gradients (hand-written reverse mode against torch
+autograd), and training that fits a DMN to data of another DMN. Online: the
+Newton iteration on the displacement jumps with PA66 and E-glass leaves
+(the GPU eliminates the jumps laminate by laminate, the oracle solves the
+dense system), stress, coupling term, dissipation and d<sigma>/dE over
+several increments.
+"""
+import numpy as np
+import pytest
+
+from oracle import dmn, tensor
+from paper_2109_14403_amd import hom
+from paper_2109_14403_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+SQ2 = np.sqrt(2.0)
+WM = np.array([1, 1, 1, SQ2, SQ2, SQ2])
+
+
+def samples(n, rng, rank_one=True):
+    """Isotropic C1 (fibres) and isotropic-minus-rank-one C2 (matrix), the
+    paper's form of the sampled stiffness pairs."""
+    C1, C2 = [], []
+    for _ in range(n):
+        K1, G1 = np.exp(rng.uniform(np.log(5e3), np.log(8e4), 2))
+        K2, G2 = np.exp(rng.uniform(np.log(5e2), np.log(8e3), 2))
+        C1.append(tensor.isotropic(K1, G1))
+        c2 = tensor.isotropic(K2, G2)
+        if rank_one:
+            N = tensor.deviator(rng.standard_normal(6))
+            N /= np.linalg.norm(N)
+            c2 = c2 - 2 * G2 * rng.uniform(0, 0.95) * np.outer(N, N)
+        C2.append(c2)
+    return np.array(C1), np.array(C2)
+
+
+def random_params(K, rng, negative=0):
+    m = rng.standard_normal((2 ** K - 1, 3))
+    v = rng.uniform(0.05, 1.0, 2 ** K)
+    v /= v.sum()
+    if negative:
+        v[rng.choice(2 ** K, negative, replace=False)] = -0.01
+    return m, v
+
+
+@pytest.mark.parametrize("K,negative", [(1, 0), (4, 0), (8, 0), (8, 9)])
+def test_homogenize_matches_oracle(K, negative):
+    rng = np.random.default_rng(K + 10 * negative)
+    m, v = random_params(K, rng, negative)
+    C1, C2 = samples(64, rng)
+    net = hom.Dmn(K)
+    net.set_params(m, v)
+    got = net.homogenize(C1, C2)
+    ref = dmn.homogenize_np(C1, C2, m, v)
+    err = np.abs(got - ref).max() / np.abs(ref).max()
+    print(f"K={K} negative={negative}: homogenize {err:.2e}", flush=True)
+    assert err <= 1e-10
+    assert np.allclose(got, got.transpose(0, 2, 1), atol=1e-9 * np.abs(got).max())
+
+
+@pytest.mark.parametrize("K,negative", [(3, 0), (6, 5)])
+def test_loss_and_gradients_match_autograd(K, negative):
+    rng = np.random.default_rng(50 + K)
+    m, v = random_params(K, rng, negative)
+    C1, C2 = samples(16, rng)
+    Ceff = dmn.homogenize_np(C1, C2, *random_params(K, rng)) * rng.uniform(0.95, 1.05, (16, 1, 1))
+    J, gm, gv = dmn.loss_and_grad(C1, C2, Ceff, m, v * 1.02)
+    net = hom.Dmn(K)
+    net.set_params(m, v * 1.02)
+    Jg, gmg, gvg = net.loss_grad(C1, C2, Ceff)
+    em = np.abs(gmg - gm).max() / np.abs(gm).max()
+    ev = np.abs(gvg - gv).max() / np.abs(gv).max()
+    print(f"K={K}: loss {abs(Jg - J) / J:.2e} grad m {em:.2e} grad v {ev:.2e}", flush=True)
+    assert abs(Jg - J) <= 1e-10 * J
+    assert em <= 1e-7 and ev <= 1e-7
+    assert np.all(gvg[v < 0] == 0.0)
+
+
+def test_training_fits_a_teacher_network():
+    rng = np.random.default_rng(3)
+    K = 4
+    teacher = random_params(K, rng)
+    C1, C2 = samples(320, rng)
+    Ceff = dmn.homogenize_np(C1, C2, *teacher)
+    net = hom.Dmn(K, seed=11)
+    before = np.mean(np.abs(net.homogenize(C1, C2) - Ceff).sum(axis=(1, 2)) / np.abs(Ceff).sum(axis=(1, 2)))
+    hist = net.train(C1, C2, Ceff, epochs=1000, batch=32, seed=5)
+    after = np.mean(np.abs(net.homogenize(C1, C2) - Ceff).sum(axis=(1, 2)) / np.abs(Ceff).sum(axis=(1, 2)))
+    m, v = net.params()
+    print(f"mean error {before:.3e} -> {after:.3e}, loss {hist[0]:.3e} -> {hist[-1]:.3e}, sum w {np.maximum(v, 0).sum():.4f}",
+          flush=True)
+    assert after < 0.2 * before
+    assert hist[-1] < hist[0]
+    assert abs(np.maximum(v, 0).sum() - 1.0) < 0.02
+
+
+def oracle_online(m, v, law1, law2, npts, tol):
+    return [dmn.OnlineDMN(m, v, law1, law2, tol=tol) for _ in range(npts)]
+
+
+@pytest.mark.parametrize("K", [3, 6])
+def test_online_matches_oracle(K):
+    rng = np.random.default_rng(70 + K)
+    m, v = random_params(K, rng)
+    law1, law2 = W.e_glass(), W.pa66()
+    npts = 3
+    tol = 1e-10
+    gpu = hom.DmnOnline(_net(K, m, v), law1, law2, npts, tol=tol)
+    ref = oracle_online(m, v, law1, law2, npts, tol)
+    dirs = np.array([[1, 0, 0, 0, 0, 0.4], [0.3, -0.2, 1, 0, 0.5, 0], [0, 0, 0, 1, 0, 0]], dtype=float)
+    plastic = False
+    for k in range(1, 5):
+        strains = dirs * 0.008 * k
+        theta = 293.15 + 10 * k
+        out = gpu.step(strains, theta, 2.0)
+        for i in range(npts):
+            o = ref[i].step(strains[i], theta, 2.0)
+            g = out[i]
+            es = np.abs(g["stress"] - o["stress"]).max() / np.abs(o["stress"]).max()
+            dsde_o = o["dsde"] * WM[None, :] / WM[:, None]
+            et = np.abs(g["dsde"] - dsde_o).max() / np.abs(dsde_o).max()
+            ec = abs(g["coupling"] - o["coupling"]) / max(abs(o["coupling"]), 1e-9)
+            ed = abs(g["dissipation"] - o["dissipation"]) / max(abs(o["dissipation"]), 1e-12)
+            print(f"K={K} inc {k} point {i}: stress {es:.2e} dsde {et:.2e} coupling {ec:.2e} dissipation {ed:.2e}"
+                  f" newton {g['newton_iters']}/{o['newton_iters']}", flush=True)
+            assert g["status"] == hom.HOM_OK
+            assert es <= 1e-8 and et <= 1e-7 and ec <= 1e-7 and ed <= 1e-6
+            plastic = plastic or o["dissipation"] > 0.0
+    assert plastic
+
+
+def _net(K, m, v):
+    net = hom.Dmn(K)
+    net.set_params(m, v)
+    return net
+
+
+def test_online_linear_phases_equal_offline():
+    rng = np.random.default_rng(9)
+    K = 8
+    m, v = random_params(K, rng)
+    l1 = dict(kind="thermoelastic", E=70e3, nu=0.22, alpha0=5e-6, kappa0=1.0, c0=2.0, theta0=293.15)
+    l2 = dict(l1, E=3e3, nu=0.35)
+    net = _net(K, m, v)
+    C1 = tensor.isotropic(*tensor.bulk_shear(l1["E"], l1["nu"]))
+    C2 = tensor.isotropic(*tensor.bulk_shear(l2["E"], l2["nu"]))
+    D = net.homogenize(C1[None], C2[None])[0]
+    on = hom.DmnOnline(net, l1, l2, 2, tol=1e-12)
+    strains = np.array([[2e-3, -1e-3, 5e-4, 3e-4, 0, -2e-4], [0, 0, 1e-3, 0, 2e-3, 0]])
+    out = on.step(strains, 293.15, 1.0)
+    for i in range(2):
+        expect = tensor.mandel_to_components(D @ tensor.components_to_mandel(strains[i]))
+        assert np.allclose(out[i]["stress"], expect, rtol=1e-9, atol=1e-9 * np.abs(expect).max())
+        assert np.allclose(out[i]["dsde"], D * WM[None, :] / WM[:, None], rtol=1e-8, atol=1e-8 * np.abs(D).max())
+
+
+def test_dmn_argument_errors():
+    with pytest.raises(hom.HomError):
+        hom.Dmn(11)
+    net = hom.Dmn(9)
+    with pytest.raises(hom.HomError) as e:
+        hom.DmnOnline(net, W.e_glass(), W.pa66(), 4)
+    assert e.value.code == hom.HOM_E_UNSUPPORTED
+    net = hom.Dmn(3)
+    with pytest.raises(hom.HomError):
+        net.set_params(np.zeros((7, 3)), np.ones(8))
+    with pytest.raises(hom.HomError):
+        hom.DmnOnline(net, W.pa66(), W.pa66(), 4)      # at most one PA66 law

@@ -40,7 +40,8 @@ def test_default_options(lib):
 
 
 STRUCTS = {"hom_grid": hom.Grid, "hom_law": hom.Law, "hom_options": hom.Options, "hom_macro_temp": hom.MacroTemp,
-           "hom_result": hom.Result, "hom_load": hom.Load, "hom_tangent": hom.Tangent}
+           "hom_result": hom.Result, "hom_load": hom.Load, "hom_tangent": hom.Tangent,
+           "hom_dmn_train_opts": hom.DmnTrainOpts, "hom_dmn_result": hom.DmnResult}
 
 
 def test_struct_layout(tmp_path):
