@@ -399,6 +399,90 @@ def mfma_summary(folder, command):
     print("\n".join(lines))
 
 
+def dmn_bench(n=128, samples=160, epochs=3000, K=8, points=4096, seed=7):
+    """The direct DMN pipeline of Sec. 3 on one fibre microstructure:
+    stiffness samples -> effective stiffnesses by the FFT solver (FP32,
+    linear elastic, d<sigma>/dE of one increment) -> offline training ->
+    online evaluation of many Gauss points with PA66 / E-glass leaves, and the
+    DMN's effective stress against the FFT solver on a uniaxial history."""
+    import torch
+    from paper_2109_14403_amd import hom
+    from paper_2109_14403_amd import workloads as W
+    rng = np.random.default_rng(seed)
+    wl = W.fibre_composite_workload(n, seed=3)          # phase 0 matrix, phase 1 fibres
+    w = np.array([1, 1, 1, np.sqrt(2), np.sqrt(2), np.sqrt(2)])
+
+    def te(E, nu):
+        return dict(kind="thermoelastic", E=float(E), nu=float(nu), alpha0=0.0, kappa0=1.0, c0=1.0, theta0=293.15)
+
+    def iso(E, nu):
+        K, G = E / (3 * (1 - 2 * nu)), E / (2 * (1 + nu))
+        P1 = np.zeros((6, 6))
+        P1[:3, :3] = 1.0 / 3.0
+        return 3 * K * P1 + 2 * G * (np.eye(6) - P1)
+
+    C1, C2, Ce = [], [], []
+    t0 = time.perf_counter()
+    for _ in range(samples):
+        E1, nu1 = 10 ** rng.uniform(4.0, 5.2), rng.uniform(0.15, 0.35)      # fibres
+        E2, nu2 = 10 ** rng.uniform(1.5, 4.0), rng.uniform(0.30, 0.45)      # matrix
+        ctx = hom.Context(wl.phases, [te(E2, nu2), te(E1, nu1)], scheme=hom.SCHEME_NEWTON_CG, precision=hom.FP32,
+                          tol=1e-6)
+        ctx.solve_increment(np.zeros(6), 293.15, [0, 0, 0], 1.0)
+        t = ctx.algorithmic_tangent(what=0)["dsde"]
+        ctx.close()
+        C1.append(iso(E1, nu1))
+        C2.append(iso(E2, nu2))
+        Ce.append(t * w[:, None] / w[None, :])
+    fft_s = time.perf_counter() - t0
+    C1, C2, Ce = np.array(C1), np.array(C2), np.array(Ce)
+    ntr = int(0.9 * samples)
+    net = hom.Dmn(K, seed=seed)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    hist = net.train(C1[:ntr], C2[:ntr], Ce[:ntr], epochs=epochs, batch=32, seed=seed)
+    train_s = time.perf_counter() - t0
+
+    def err(a, b):
+        return float(np.mean(np.abs(a - b).sum(axis=(1, 2)) / np.abs(b).sum(axis=(1, 2))))
+
+    e_tr = err(net.homogenize(C1[:ntr], C2[:ntr]), Ce[:ntr])
+    e_va = err(net.homogenize(C1[ntr:], C2[ntr:]), Ce[ntr:])
+    # online: many Gauss points, 5 increments of random proportional loadings
+    on = hom.DmnOnline(net, W.e_glass(), W.pa66(), points, tol=1e-8, maxit=30)
+    dirs = rng.standard_normal((points, 6))
+    dirs /= np.linalg.norm(dirs, axis=1, keepdims=True)
+    steps_t = []
+    iters = []
+    failed = 0
+    for k in range(1, 6):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        out = on.step(dirs * 0.004 * k, 293.15 + 5 * k, 2.0)
+        steps_t.append(time.perf_counter() - t0)
+        iters += [r["newton_iters"] for r in out]
+        failed += sum(r["status"] != 0 for r in out)
+    on.close()
+    # the DMN against the FFT solver on the first increments of a uniaxial history
+    ctx = hom.Context(wl.phases, wl.laws, scheme=hom.SCHEME_NEWTON_CG, precision=hom.FP32, tol=1e-6)
+    one = hom.DmnOnline(net, W.e_glass(), W.pa66(), 1, tol=1e-8, maxit=30)
+    errs = []
+    for st in wl.history[:10]:
+        f = ctx.solve_increment(st.strain, st.theta, st.grad, st.dt)
+        d = one.step(np.asarray(st.strain)[None], st.theta, st.dt)[0]
+        errs.append(float(np.abs(d["stress"] - f["stress"]).max() / np.abs(f["stress"]).max()))
+    ctx.close()
+    one.close()
+    net.close()
+    return {"K": K, "grid": n, "samples": samples, "fft_seconds": round(fft_s, 2), "epochs": epochs,
+            "train_seconds": round(train_s, 2), "train_loss_first_last": [float(hist[0]), float(hist[-1])],
+            "train_mean_error": round(e_tr, 5), "validation_mean_error": round(e_va, 5),
+            "online_points": points, "online_ms_per_increment": round(1e3 * float(np.median(steps_t)), 3),
+            "online_gauss_point_updates_per_s": round(points / float(np.median(steps_t)), 1),
+            "online_newton_mean": round(float(np.mean(iters)), 2), "online_failed": int(failed),
+            "vs_fft_stress_error_10_increments": [round(e, 4) for e in errs]}
+
+
 def tangent_bench(ctx, wl, nvox, warmup, total):
     """d<sigma>/dE of the last timed increment: six linearized cell solves
     (hom_algorithmic_tangent, what = 0), timed around the synchronous call."""
@@ -447,6 +531,7 @@ def main():
     ap.add_argument("--no-surrogate", action="store_true")
     ap.add_argument("--no-tangent", action="store_true")
     ap.add_argument("--rotated", action="store_true", help="rotated finite-difference discretization")
+    ap.add_argument("--no-dmn", action="store_true")
     ap.add_argument("--calib-copy", action="store_true", help="run a 1 GiB device copy (PMC calibration)")
     ap.add_argument("--pmc-summary", nargs="+", metavar="DIR",
                     help="summarize rocprofv3 --pmc output folders (FETCH_SIZE, WRITE_SIZE[, request sizes]) "
@@ -592,6 +677,11 @@ def main():
         surr = surrogate_bench()
         print(f"surrogate: {surr}", file=sys.stderr, flush=True)
 
+    dmn_line = None
+    if not args.no_dmn:
+        dmn_line = dmn_bench()
+        print(f"dmn: {dmn_line}", file=sys.stderr, flush=True)
+
     cpu = None
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(wl.phases, wl.laws)
@@ -609,7 +699,7 @@ def main():
         "thermal_voxel_iters_per_s": round(tpipes * nvox / elapsed, 1),
         "newton_per_step": newton / args.steps, "krylov_per_step": krylov / args.steps,
         "roofline": roof, "copy_probe_gbs": copy_gbs, "cpu_baseline": cpu, "batch": batch, "surrogate": surr,
-        "tangent": tangent,
+        "tangent": tangent, "dmn": dmn_line,
     }
     if kstats:
         line["kernel_ms"] = {k: [v[0], round(v[1], 3)] for k, v in kstats.items() if v[0]}
