@@ -29,6 +29,7 @@ METRIC = "voxel-iters/s coupled FFT solve; surrogate vs FFT Gauss-pts/s at 1e-3 
 HBM_PEAK_GBS = 8000.0
 # sources whose change makes stored counter data stale (kernels and launch shapes)
 KERNEL_SOURCES = ("paper_2109_14403_amd/csrc/pipeline.h", "paper_2109_14403_amd/csrc/fft_core.h",
+                  "paper_2109_14403_amd/csrc/pa66.h",
                   "paper_2109_14403_amd/csrc/pointwise.hip", "paper_2109_14403_amd/csrc/pointwise.h",
                   "paper_2109_14403_amd/csrc/common.h", "paper_2109_14403_amd/csrc/pipe_inst.hip",
                   "paper_2109_14403_amd/csrc/pipe_launch.h")
