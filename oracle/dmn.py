@@ -219,11 +219,44 @@ class OnlineDMN:
         sbar = sig @ self.w
         return np.linalg.norm(g) / ((self.nleaf - 1) * max(np.linalg.norm(sbar), 1e-300)), g
 
-    def step(self, strain, theta, dt):
+    def point_partials(self, eps, theta, dt, h_eps=1e-6, h_theta=1e-3):
+        """Per-leaf d sigma / d theta (6), d D / d eps (6) and d D / d theta of
+        the coupling term D at the leaf strains, from state n: closed form for
+        thermoelastic phases, central differences of the PA66 update (steps
+        h_eps in Mandel strain, h_theta in K)."""
+        dsdt = np.zeros((6, self.nleaf))
+        dDde = np.zeros((6, self.nleaf))
+        dDdt = np.zeros(self.nleaf)
+        for p in (0, 1):
+            idx = self.leaves[p]
+            law = self.laws[p]
+            e, en = eps[:, idx], self.eps_n[:, idx]
+            if law.inelastic:
+                st = self.state[p]
+                up = law.update(e, en, st, theta + h_theta, dt)
+                dn = law.update(e, en, st, theta - h_theta, dt)
+                dsdt[:, idx] = (up["sigma"] - dn["sigma"]) / (2.0 * h_theta)
+                dDdt[idx] = (up["coupling"] - dn["coupling"]) / (2.0 * h_theta)
+                for c in range(6):
+                    ep, em = e.copy(), e.copy()
+                    ep[c] += h_eps
+                    em[c] -= h_eps
+                    dDde[c, idx] = (law.update(ep, en, st, theta, dt)["coupling"]
+                                    - law.update(em, en, st, theta, dt)["coupling"]) / (2.0 * h_eps)
+            else:
+                Ca = law.C @ law.alpha
+                dsdt[:, idx] = -Ca[:, None]
+                dDde[:, idx] = (-theta / dt) * Ca[:, None]
+                dDdt[idx] = -(Ca @ (e - en)) / dt
+        return dsdt, dDde, dDdt
+
+    def step(self, strain, theta, dt, all_tangents=False):
         """One increment at the macro strain (6 tensor components), theta, dt.
         Commits the internal variables and the jumps; returns the effective
         stress (components), coupling term, dissipation, d<sigma>/dE (Mandel)
-        and the Newton iterations."""
+        and the Newton iterations; with all_tangents also d<sigma>/dtheta,
+        d<D>/dE (Mandel) and d<D>/dtheta (Sec. 3.3: the strain-jump
+        derivatives solve the Newton system with other right-hand sides)."""
         E = tensor.components_to_mandel(np.asarray(strain, dtype=np.float64))
         a = self.a.copy()                        # the jumps of the last increment
         res, g = self.residual(E, a, theta, dt)
@@ -254,11 +287,21 @@ class OnlineDMN:
         dleaf = one + self.A @ dadE                              # d eps_leaf / dE
         Cbar = (np.tile(self.w.repeat(6)[:, None], (1, 6)) * (self._blockdiag_unweighted(tan) @ dleaf))
         Cbar = Cbar.reshape(self.nleaf, 6, 6).sum(axis=0)
+        extra = {}
+        if all_tangents:
+            dsdt_l, dDde_l, dDdt_l = self.point_partials(eps, theta, dt)
+            dadT = -np.linalg.lstsq(Kmat, self.A.T @ (self.w[:, None] * dsdt_l.T).reshape(-1), rcond=1e-13)[0]
+            deps_dT = (self.A @ dadT).reshape(self.nleaf, 6).T
+            dsdt = sum(self.w[l] * (dsdt_l[:, l] + tan[l] @ deps_dT[:, l]) for l in range(self.nleaf))
+            dl = dleaf.reshape(self.nleaf, 6, 6)
+            dDde = sum(self.w[l] * (dl[l].T @ dDde_l[:, l]) for l in range(self.nleaf))
+            dDdt = sum(self.w[l] * (dDdt_l[l] + dDde_l[:, l] @ deps_dT[:, l]) for l in range(self.nleaf))
+            extra = dict(dsdt=dsdt, dDde=dDde, dDdt=float(dDdt))
         self.state.update(new)
         self.eps_n = eps
         self.a = a
         return dict(stress=tensor.mandel_to_components(sig @ self.w), coupling=float(coup @ self.w),
-                    dissipation=float(diss @ self.w), dsde=Cbar, newton_iters=its, residual=res)
+                    dissipation=float(diss @ self.w), dsde=Cbar, newton_iters=its, residual=res, **extra)
 
     def _blockdiag(self, tan):
         out = np.zeros((6 * self.nleaf, 6 * self.nleaf))

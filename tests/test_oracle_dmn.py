@@ -10,8 +10,10 @@
   jumps instead of the laminate equation;
 * online with the same PA66 law in both phases is the point law, with zero
   jumps;
-* the online d<sigma>/dE against finite differences of re-evaluated
-  increments; dissipation >= 0.
+* the online d<sigma>/dE, d<sigma>/dtheta, d<D>/dE and d<D>/dtheta against
+  finite differences of re-evaluated increments; dissipation >= 0;
+* a DMN of one thermoelastic law: d<sigma>/dtheta = -C[alpha],
+  d<D>/dE = -theta C[alpha] / dt, d<D>/dtheta = -C[alpha] : dE / dt.
 """
 import copy
 
@@ -150,3 +152,52 @@ def test_online_tangent_matches_finite_differences():
             res.append(tensor.components_to_mandel(n2.step(tensor.mandel_to_components(Ej), 300.0, 2.0)["stress"]))
         fd[:, j] = (res[0] - res[1]) / (2 * h)
     assert np.abs(fd - out["dsde"]).max() <= 1e-5 * np.abs(fd).max()
+
+
+def test_online_temperature_and_coupling_tangents_match_finite_differences():
+    K = 3
+    m, v = random_params(K)
+    net = dmn.OnlineDMN(m, v, W.e_glass(), W.pa66(), tol=1e-12)
+    for k in range(1, 4):
+        net.step(np.array([0.008 * k, 0, 0, 0, 0, 0.003 * k]), 300.0 + k, 2.0)
+    before = copy.deepcopy(net)
+    strain = np.array([0.032, 0.001, 0, 0, 0, 0.012])
+    th = 305.0
+    out = net.step(strain, th, 2.0, all_tangents=True)
+    assert out["dissipation"] > 0.0
+    E = tensor.components_to_mandel(strain)
+
+    def again(Em, t):
+        n2 = copy.deepcopy(before)
+        r = n2.step(tensor.mandel_to_components(Em), t, 2.0)
+        return tensor.components_to_mandel(r["stress"]), r["coupling"]
+
+    ht = 1e-3
+    sp, Dp = again(E, th + ht)
+    sm, Dm = again(E, th - ht)
+    assert np.abs((sp - sm) / (2 * ht) - out["dsdt"]).max() <= 1e-5 * np.abs(out["dsdt"]).max()
+    assert abs((Dp - Dm) / (2 * ht) - out["dDdt"]) <= 1e-5 * abs(out["dDdt"])
+    h = 1e-7
+    fd = np.zeros(6)
+    for j in range(6):
+        dE = np.zeros(6)
+        dE[j] = h
+        fd[j] = (again(E + dE, th)[1] - again(E - dE, th)[1]) / (2 * h)
+    assert np.abs(fd - out["dDde"]).max() <= 1e-5 * np.abs(fd).max()
+
+
+def test_online_thermoelastic_closed_forms():
+    K = 3
+    m, v = random_params(K)
+    g = glass()
+    net = dmn.OnlineDMN(m, v, g, g, tol=1e-13)
+    E0 = np.array([1e-3, -2e-4, 3e-4, 1e-4, 0.0, -5e-5])
+    net.step(E0, 320.0, 2.0)
+    E1 = E0 + np.array([2e-4, 1e-4, -1e-4, 0.0, 3e-5, 0.0])
+    out = net.step(E1, 340.0, 0.5, all_tangents=True)
+    K_, G_ = tensor.bulk_shear(g["E"], g["nu"])
+    Ca = 3 * K_ * g["alpha0"] * np.array([1.0, 1, 1, 0, 0, 0])
+    wsum = np.maximum(v, 0).sum()
+    assert np.allclose(out["dsdt"], -Ca * wsum, rtol=1e-10)
+    assert np.allclose(out["dDde"], -340.0 * Ca / 0.5 * wsum, rtol=1e-10)
+    assert np.isclose(out["dDdt"], -(Ca @ tensor.components_to_mandel(E1 - E0)) / 0.5 * wsum, rtol=1e-9)
