@@ -341,7 +341,10 @@ void hom_mlp_destroy(hom_mlp* net);
  * balance of the jumps by Newton's method with the paper's backtracking
  * (steps 1, 1/2, 1/4, ..., at most 8 cuts) and residual, at tolerance tol and
  * at most maxit Newton steps, then commits (status HOM_OK) or not
- * (HOM_E_NOT_CONVERGED). Phase laws: laws[0] for phase 1, laws[1] for phase
+ * (HOM_E_NOT_CONVERGED). what = 0 returns d<sigma>/dE of the four
+ * algorithmic tangents of Sec. 3.3, what = 1 all four (the point partials of
+ * the PA66 leaves by central differences, as for hom_algorithmic_tangent).
+ * Phase laws: laws[0] for phase 1, laws[1] for phase
  * 2 (at most one PA66). Depth up to 8 (one work-group of 2^K threads per
  * point, the whole tree in LDS). */
 typedef struct hom_dmn hom_dmn;
@@ -357,6 +360,9 @@ typedef struct {
   double coupling;       /* sum_i w_i D_i */
   double dissipation;    /* sum_i w_i D_diss,i */
   double dsde[36];       /* d<sigma>_I / dE_J, row-major, as hom_tangent.dsde */
+  double dsdt[6];        /* d<sigma>_I / dtheta (what = 1, else NaN) */
+  double dDde[6];        /* d<D> / dE_J (what = 1, else NaN) */
+  double dDdt;           /* d<D> / dtheta (what = 1, else NaN) */
   double residual;
   int32_t newton_iters;
   int32_t status;
@@ -375,7 +381,7 @@ void hom_dmn_destroy(hom_dmn* net);
 int hom_dmn_online_create(const hom_dmn* net, const hom_law laws[2], int32_t n_points, double tol, int32_t maxit,
                           hom_dmn_online** out);
 int hom_dmn_online_step(hom_dmn_online* o, const double* strain, const double* theta, const double* dt,
-                        hom_dmn_result* out);
+                        int32_t what, hom_dmn_result* out);
 const char* hom_dmn_online_last_error(const hom_dmn_online* o);
 void hom_dmn_online_destroy(hom_dmn_online* o);
 

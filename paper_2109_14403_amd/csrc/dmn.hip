@@ -694,13 +694,18 @@ void Dmn::train(long long n, const double* C1, const double* C2, const double* C
 namespace {
 
 constexpr int ON_MAX_K = 8;
-constexpr int ON_OUT = 48;  // sigma 6, coupling, dissipation, dsde 36, residual, iterations, status, pad
+// per point: sigma 6, coupling, dissipation, dsde 36, dsdt 6, dDde 6, dDdt,
+// residual, iterations, status
+constexpr int ON_OUT = 64;
+constexpr int O_DSDT = 44, O_DDDE = 50, O_DDDT = 56, O_RES = 57, O_IT = 58, O_ST = 59;
 constexpr int ON_SCR = 24;  // per internal node: G (18), da0 (3)
 
 struct OnArgs {
   int K, nleaf;
   const double* p;
   const ProbInc* inc;   // [point]
+  const ProbInc* inc_pm;  // [point][2]: theta + h_theta, theta - h_theta (all four tangents)
+  int what;             // 1: also the temperature and coupling tangents
   int pa_phase;         // phase (0: even leaves, 1: odd leaves) with the PA66 law, -1 if none
   double* state;        // [point][nstate][nleaf / 2]
   int nstate;
@@ -759,6 +764,17 @@ __device__ void leaf_eval(const OnArgs& g, const ProbInc& in, int pt, int l, con
   }
 }
 
+// w C of a leaf into KA: C_IJ = ca d_IJ + (K3 - ca) / 3 [I, J < 3] + cb N_I N_J
+__device__ __forceinline__ void put_leaf_tangent(OnShared& S, int l, double w, double K3, double ca, double cb,
+                                                 const double* nd) {
+  double* Kl = S.KA + 36 * l;
+#pragma unroll
+  for (int i = 0; i < 6; ++i)
+#pragma unroll
+    for (int j = 0; j < 6; ++j)
+      Kl[6 * i + j] = w * ((i == j ? ca : 0.0) + (i < 3 && j < 3 ? (K3 - ca) * (1.0 / 3.0) : 0.0) + cb * nd[i] * nd[j]);
+}
+
 __device__ __forceinline__ double node_c1(const OnShared& S, int h) {
   const double wl = S.wsub[2 * h], wr = S.wsub[2 * h + 1], sw = wl + wr;
   return sw > 0.0 ? wl / sw : 0.5;
@@ -796,13 +812,7 @@ __device__ double residual(const OnArgs& g, OnShared& S, const ProbInc& in, int 
   for (int c = 0; c < 6; ++c) e[c] = S.V[6 * (nleaf + l) + c];
   double K3, ca, cb, nd[6];
   leaf_eval(g, in, pt, l, e, sg, K3, ca, cb, nd);
-  // w C of the leaf: C_IJ = ca d_IJ + (K3 - ca) / 3 [I, J < 3] + cb N_I N_J
-  double* Kl = S.KA + 36 * l;
-#pragma unroll
-  for (int i = 0; i < 6; ++i)
-#pragma unroll
-    for (int j = 0; j < 6; ++j)
-      Kl[6 * i + j] = w * ((i == j ? ca : 0.0) + (i < 3 && j < 3 ? (K3 - ca) * (1.0 / 3.0) : 0.0) + cb * nd[i] * nd[j]);
+  put_leaf_tangent(S, l, w, K3, ca, cb, nd);
   __syncthreads();
 #pragma unroll
   for (int c = 0; c < 6; ++c) S.V[6 * (nleaf + l) + c] = w * sg[c];
@@ -935,7 +945,8 @@ __device__ double* condense(const OnArgs& g, OnShared& S, int pt) {
   return src;
 }
 
-// da from the root down (deps_root = 0), into S.da (heap index)
+// da from the root down (deps_root = 0), into S.da (heap index); the strain
+// changes of every node and leaf into V
 __device__ void expand(const OnArgs& g, OnShared& S, int pt) {
   const int nleaf = g.nleaf;
   const int tid = threadIdx.x;
@@ -958,15 +969,13 @@ __device__ void expand(const OnArgs& g, OnShared& S, int pt) {
         d[k] = x;
         S.da[3 * h + k] = x;
       }
-      if (2 * h < nleaf) {
-        double N[6][3];
-        nmat(S.nv + 3 * h, N);
+      double N[6][3];
+      nmat(S.nv + 3 * h, N);
 #pragma unroll
-        for (int c = 0; c < 6; ++c) {
-          const double j6 = N[c][0] * d[0] + N[c][1] * d[1] + N[c][2] * d[2];
-          S.V[6 * (2 * h) + c] = de[c] + c2 * j6;
-          S.V[6 * (2 * h + 1) + c] = de[c] - c1 * j6;
-        }
+      for (int c = 0; c < 6; ++c) {  // children, the leaves included
+        const double j6 = N[c][0] * d[0] + N[c][1] * d[1] + N[c][2] * d[2];
+        S.V[6 * (2 * h) + c] = de[c] + c2 * j6;
+        S.V[6 * (2 * h + 1) + c] = de[c] - c1 * j6;
       }
     }
     __syncthreads();
@@ -1039,6 +1048,88 @@ __global__ void __launch_bounds__(1 << ON_MAX_K) k_dmn_online(OnArgs g) {
   __syncthreads();
   double* Kroot = condense(g, S, pt);
   for (int i = tid; i < 36; i += blockDim.x) o[8 + i] = Kroot[i];
+  __syncthreads();
+  if (g.what) {
+    // point partials of every leaf at its converged strain, from state n:
+    // d sigma / d theta, d D / d eps, d D / d theta (closed form for the
+    // thermoelastic phase, central differences of the PA66 update)
+    const int l = tid;
+    const int phase = l & 1;
+    const double* enp = g.epsn + ((long long)pt * nleaf + l) * 6;
+    double en[6], st_[6], gd[6], hd;
+#pragma unroll
+    for (int c = 0; c < 6; ++c) en[c] = enp[c];
+    if (phase == g.pa_phase) {
+      const long long ss = nleaf >> 1;
+      const int q = l >> 1;
+      const double* st = g.state + (long long)pt * g.nstate * ss + q;
+      const double* hs = g.hist + (long long)pt * HIST_SLOTS * ss + q;
+      double sp[6], Dp = 0.0;
+      for (int k = 0; k < 14; ++k) {
+        const bool th = k < 2;
+        const ProbInc& ik = th ? g.inc_pm[2 * pt + k] : in;
+        double ek[6];
+#pragma unroll
+        for (int c = 0; c < 6; ++c) ek[c] = e[c];
+        const int dir = (k - 2) >> 1;
+        if (!th) ek[dir] += (k & 1) ? -FD_H_EPS : FD_H_EPS;
+        PaOut po;
+        double dis, cpl;
+        pa66_point(ik, ek, st, ss, nullptr, en, po, &dis, &cpl, th ? nullptr : hs, nullptr);
+        if (!(k & 1)) {
+#pragma unroll
+          for (int c = 0; c < 6; ++c) sp[c] = po.sig[c];
+          Dp = cpl;
+        } else if (th) {
+#pragma unroll
+          for (int c = 0; c < 6; ++c) st_[c] = (sp[c] - po.sig[c]) * (0.5 / FD_H_THETA);
+          hd = (Dp - cpl) * (0.5 / FD_H_THETA);
+        } else {
+          gd[dir] = (Dp - cpl) * (0.5 / FD_H_EPS);
+        }
+      }
+    } else {
+      const PhaseInc& pi = in.ph[phase];
+      const double ca = pi.K3 * pi.alpha0;
+      const double trd = (e[0] - en[0]) + (e[1] - en[1]) + (e[2] - en[2]);
+#pragma unroll
+      for (int c = 0; c < 6; ++c) {
+        st_[c] = c < 3 ? -ca : 0.0;
+        gd[c] = c < 3 ? -in.theta * ca / in.dt : 0.0;
+      }
+      hd = -ca * trd / in.dt;
+    }
+    const double wl = S.wsub[nleaf + l];
+    double K3, ca, cb, nd[6], sgl[6];
+    leaf_eval(g, in, pt, l, e, sgl, K3, ca, cb, nd);
+    // d<sigma>/dtheta: the jumps equilibrate the leaf sources w dsigma/dtheta
+    put_leaf_tangent(S, l, wl, K3, ca, cb, nd);
+#pragma unroll
+    for (int c = 0; c < 6; ++c) S.V[6 * (nleaf + l) + c] = wl * st_[c];
+    __syncthreads();
+    condense(g, S, pt);
+    if (tid == 0)
+      for (int c = 0; c < 6; ++c) o[O_DSDT + c] = S.V[6 + c];
+    __syncthreads();
+    expand(g, S, pt);  // the leaf strains' derivatives d eps / d theta
+    double dT = wl * hd;
+#pragma unroll
+    for (int c = 0; c < 6; ++c) dT += wl * gd[c] * S.V[6 * (nleaf + l) + c];
+    double r1[1] = {dT};
+    block_sum<1>(r1, S.red);
+    if (tid == 0) o[O_DDDT] = r1[0];
+    __syncthreads();
+    // d<D>/dE = sum_l w_l (d eps_l / dE)^T dD/deps_l: the condensed value of
+    // the leaf sources w dD/deps (the localization is symmetric in this sense)
+    put_leaf_tangent(S, l, wl, K3, ca, cb, nd);
+#pragma unroll
+    for (int c = 0; c < 6; ++c) S.V[6 * (nleaf + l) + c] = wl * gd[c];
+    __syncthreads();
+    condense(g, S, pt);
+    if (tid == 0)
+      for (int c = 0; c < 6; ++c) o[O_DDDE + c] = S.V[6 + c];
+    __syncthreads();
+  }
   // coupling term and dissipation of every leaf; commit if converged
   double D = 0.0, Dd = 0.0;
   {
@@ -1072,9 +1163,9 @@ __global__ void __launch_bounds__(1 << ON_MAX_K) k_dmn_online(OnArgs g) {
   if (tid == 0) {
     o[6] = r2[0];
     o[7] = r2[1];
-    o[44] = res;
-    o[45] = it;
-    o[46] = conv ? 1.0 : 0.0;
+    o[O_RES] = res;
+    o[O_IT] = it;
+    o[O_ST] = conv ? 1.0 : 0.0;
   }
 }
 
@@ -1087,9 +1178,9 @@ struct DmnOnline {
   std::vector<hom_law> laws;
   std::vector<void*> allocs;
   double *p = nullptr, *state = nullptr, *hist = nullptr, *epsn = nullptr, *a = nullptr, *scr = nullptr;
-  double *E = nullptr, *out = nullptr, *state_save = nullptr, *a_save = nullptr;
-  ProbInc* inc = nullptr;
-  std::vector<ProbInc> inc_h;
+  double *E = nullptr, *out = nullptr;
+  ProbInc *inc = nullptr, *inc_pm = nullptr;
+  std::vector<ProbInc> inc_h, inc_pm_h;
   ~DmnOnline() {
     for (void* ptr : allocs) (void)hipFree(ptr);
   }
@@ -1128,14 +1219,17 @@ DmnOnline* dmn_online_create(const Dmn& net, const hom_law* laws, int npoints, d
   o->E = dalloc_into<double>(o->allocs, (size_t)npoints * 6);
   o->out = dalloc_into<double>(o->allocs, (size_t)npoints * ON_OUT);
   o->inc = dalloc_into<ProbInc>(o->allocs, npoints);
+  o->inc_pm = dalloc_into<ProbInc>(o->allocs, 2 * (size_t)npoints);
   o->inc_h.resize(npoints);
+  o->inc_pm_h.resize(2 * (size_t)npoints);
   return o.release();
 }
 
 void dmn_online_destroy(DmnOnline* o) { delete o; }
 
-void dmn_online_step(DmnOnline* o, const double* strain, const double* theta, const double* dt,
+void dmn_online_step(DmnOnline* o, const double* strain, const double* theta, const double* dt, int what,
                      hom_dmn_result* res) {
+  if (what != 0 && what != 1) fail(HOM_E_ARG, "what must be 0 (d sigma / dE) or 1 (all four tangents)");
   const int n = o->npoints;
   const double sq2 = std::sqrt(2.0);
   const double w[6] = {1, 1, 1, sq2, sq2, sq2};
@@ -1148,7 +1242,14 @@ void dmn_online_step(DmnOnline* o, const double* strain, const double* theta, co
       E[6 * i + c] = w[c] * strain[6 * i + c];
     }
     fill_inc(o->inc_h[i], o->laws, theta[i], dt[i]);
+    if (what) {
+      fill_inc(o->inc_pm_h[2 * i], o->laws, theta[i] + FD_H_THETA, dt[i]);
+      fill_inc(o->inc_pm_h[2 * i + 1], o->laws, theta[i] - FD_H_THETA, dt[i]);
+    }
   }
+  if (what)
+    hip_check(hipMemcpy(o->inc_pm, o->inc_pm_h.data(), 2 * n * sizeof(ProbInc), hipMemcpyHostToDevice),
+              "hipMemcpy");
   hip_check(hipMemcpy(o->E, E.data(), 6 * n * sizeof(double), hipMemcpyHostToDevice), "hipMemcpy");
   hip_check(hipMemcpy(o->inc, o->inc_h.data(), n * sizeof(ProbInc), hipMemcpyHostToDevice), "hipMemcpy");
   OnArgs g{};
@@ -1156,6 +1257,8 @@ void dmn_online_step(DmnOnline* o, const double* strain, const double* theta, co
   g.nleaf = o->nleaf;
   g.p = o->p;
   g.inc = o->inc;
+  g.inc_pm = o->inc_pm;
+  g.what = what;
   g.pa_phase = o->pa_phase;
   g.state = o->state;
   g.nstate = o->nstate;
@@ -1183,9 +1286,14 @@ void dmn_online_step(DmnOnline* o, const double* strain, const double* theta, co
     t.dissipation = r[7];
     for (int I = 0; I < 6; ++I)
       for (int J = 0; J < 6; ++J) t.dsde[6 * I + J] = r[8 + 6 * I + J] * w[J] / w[I];
-    t.residual = r[44];
-    t.newton_iters = (int)r[45];
-    t.status = r[46] == 1.0 ? HOM_OK : HOM_E_NOT_CONVERGED;
+    for (int c = 0; c < 6; ++c) {
+      t.dsdt[c] = what ? r[O_DSDT + c] / w[c] : NAN;
+      t.dDde[c] = what ? r[O_DDDE + c] * w[c] : NAN;
+    }
+    t.dDdt = what ? r[O_DDDT] : NAN;
+    t.residual = r[O_RES];
+    t.newton_iters = (int)r[O_IT];
+    t.status = r[O_ST] == 1.0 ? HOM_OK : HOM_E_NOT_CONVERGED;
   }
 }
 

@@ -144,13 +144,14 @@ class DmnTrainOpts(ct.Structure):
 class DmnResult(ct.Structure):
     _fields_ = [
         ("stress", ct.c_double * 6), ("coupling", ct.c_double), ("dissipation", ct.c_double),
-        ("dsde", ct.c_double * 36), ("residual", ct.c_double), ("newton_iters", ct.c_int32),
-        ("status", ct.c_int32),
+        ("dsde", ct.c_double * 36), ("dsdt", ct.c_double * 6), ("dDde", ct.c_double * 6), ("dDdt", ct.c_double),
+        ("residual", ct.c_double), ("newton_iters", ct.c_int32), ("status", ct.c_int32),
     ]
 
     def as_dict(self):
         return dict(stress=np.array(self.stress[:]), coupling=self.coupling, dissipation=self.dissipation,
-                    dsde=np.array(self.dsde[:]).reshape(6, 6), residual=self.residual,
+                    dsde=np.array(self.dsde[:]).reshape(6, 6), dsdt=np.array(self.dsdt[:]),
+                    dDde=np.array(self.dDde[:]), dDdt=self.dDdt, residual=self.residual,
                     newton_iters=self.newton_iters, status=self.status)
 
 
@@ -239,7 +240,7 @@ def library(path: str | None = None):
     lib.hom_dmn_destroy.restype = None
     lib.hom_dmn_online_create.argtypes = [ct.c_void_p, ct.POINTER(Law), ct.c_int32, ct.c_double, ct.c_int32,
                                           ct.POINTER(ct.c_void_p)]
-    lib.hom_dmn_online_step.argtypes = [ct.c_void_p, dp, dp, dp, ct.POINTER(DmnResult)]
+    lib.hom_dmn_online_step.argtypes = [ct.c_void_p, dp, dp, dp, ct.c_int32, ct.POINTER(DmnResult)]
     lib.hom_dmn_online_last_error.argtypes = [ct.c_void_p]
     lib.hom_dmn_online_last_error.restype = ct.c_char_p
     lib.hom_dmn_online_destroy.argtypes = [ct.c_void_p]
@@ -776,11 +777,11 @@ class DmnOnline:
         except Exception:
             pass
 
-    def step(self, strains, thetas, dts):
+    def step(self, strains, thetas, dts, what=0):
         e = _f64(strains).reshape(self.n, 6)
         t = _f64(np.broadcast_to(thetas, (self.n,)))
         d = _f64(np.broadcast_to(dts, (self.n,)))
         out = (DmnResult * self.n)()
-        _check(self._lib.hom_dmn_online_step(self._h, _dptr(e), _dptr(t), _dptr(d), out),
+        _check(self._lib.hom_dmn_online_step(self._h, _dptr(e), _dptr(t), _dptr(d), int(what), out),
                lambda: self._lib.hom_dmn_online_last_error(self._h).decode())
         return [r.as_dict() for r in out]

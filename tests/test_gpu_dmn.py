@@ -117,10 +117,19 @@ def test_online_matches_oracle(K):
     for k in range(1, 5):
         strains = dirs * 0.008 * k
         theta = 293.15 + 10 * k
-        out = gpu.step(strains, theta, 2.0)
+        what = k % 2                               # all four tangents on every other increment
+        out = gpu.step(strains, theta, 2.0, what=what)
         for i in range(npts):
-            o = ref[i].step(strains[i], theta, 2.0)
+            o = ref[i].step(strains[i], theta, 2.0, all_tangents=bool(what))
             g = out[i]
+            if what:
+                et2 = max(np.abs(g["dsdt"] - o["dsdt"] / WM).max() / np.abs(o["dsdt"]).max(),
+                          np.abs(g["dDde"] - o["dDde"] * WM).max() / np.abs(o["dDde"]).max(),
+                          abs(g["dDdt"] - o["dDdt"]) / abs(o["dDdt"]))
+                print(f"K={K} inc {k} point {i}: temperature / coupling tangents {et2:.2e}", flush=True)
+                assert et2 <= 1e-6
+            else:
+                assert np.isnan(g["dsdt"]).all() and np.isnan(g["dDdt"])
             es = np.abs(g["stress"] - o["stress"]).max() / np.abs(o["stress"]).max()
             dsde_o = o["dsde"] * WM[None, :] / WM[:, None]
             et = np.abs(g["dsde"] - dsde_o).max() / np.abs(dsde_o).max()
