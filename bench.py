@@ -424,17 +424,21 @@ def dmn_bench(n=128, samples=160, epochs=3000, K=8, points=4096, seed=7):
 
     C1, C2, Ce = [], [], []
     t0 = time.perf_counter()
-    for _ in range(samples):
+    ctx = hom.Context(wl.phases, [te(1e3, 0.3), te(1e4, 0.3)], scheme=hom.SCHEME_NEWTON_CG, precision=hom.FP32,
+                      tol=1e-6)
+    for _ in range(samples):      # one context, new law parameters per sample
         E1, nu1 = 10 ** rng.uniform(4.0, 5.2), rng.uniform(0.15, 0.35)      # fibres
         E2, nu2 = 10 ** rng.uniform(1.5, 4.0), rng.uniform(0.30, 0.45)      # matrix
-        ctx = hom.Context(wl.phases, [te(E2, nu2), te(E1, nu1)], scheme=hom.SCHEME_NEWTON_CG, precision=hom.FP32,
-                          tol=1e-6)
+        ctx.set_laws([te(E2, nu2), te(E1, nu1)])
         ctx.solve_increment(np.zeros(6), 293.15, [0, 0, 0], 1.0)
         t = ctx.algorithmic_tangent(what=0)["dsde"]
-        ctx.close()
         C1.append(iso(E1, nu1))
         C2.append(iso(E2, nu2))
         Ce.append(t * w[:, None] / w[None, :])
+        if len(Ce) % 40 == 0:
+            print(f"dmn samples: {len(Ce)} of {samples}, {time.perf_counter() - t0:.1f} s", file=sys.stderr,
+                  flush=True)
+    ctx.close()
     fft_s = time.perf_counter() - t0
     C1, C2, Ce = np.array(C1), np.array(C2), np.array(Ce)
     ntr = int(0.9 * samples)

@@ -174,6 +174,15 @@ int hom_setup(const hom_grid* grid, const uint8_t* phases, const hom_law* laws, 
 int hom_solve_increment(hom_ctx* ctx, const double macro_strain[6], const hom_macro_temp* temp, double dt,
                         hom_result* out);
 
+/* Replace the parameters of the phase laws for later increments: n_laws must
+ * equal the setup's, every law keeps its kind and a PA66 law its number of
+ * Maxwell branches; the committed fields and internal variables stay, the
+ * algorithmic tangent of the last increment is no longer available. One
+ * context (or batch) then serves many material samples of one
+ * microstructure, as the DMN's training data needs (Sec. 3.2). */
+int hom_set_laws(hom_ctx* ctx, const hom_law* laws, int32_t n_laws);
+int hom_batch_set_laws(hom_batch* b, const hom_law* laws, int32_t n_laws);
+
 /* hom_solve_increment with mixed boundary conditions and / or the adiabatic
  * heat balance (hom_load). hom_solve_increment(E, temp, dt) equals a load
  * with stress_mask 0 and adiabatic 0. */

@@ -160,6 +160,16 @@ int hom_set_profiling(hom_ctx* c, int32_t on) {
   return guarded(&c->err, [&] { c->impl->set_profiling(on != 0); });
 }
 
+int hom_set_laws(hom_ctx* c, const hom_law* laws, int32_t n) {
+  if (!c || !c->impl) return HOM_E_ARG;
+  return guarded(&c->err, [&] { c->impl->set_laws(laws, n); });
+}
+
+int hom_batch_set_laws(hom_batch* b, const hom_law* laws, int32_t n) {
+  if (!b || !b->impl) return HOM_E_ARG;
+  return guarded(&b->err, [&] { b->impl->set_laws(laws, n); });
+}
+
 int hom_algorithmic_tangent(hom_ctx* c, int32_t what, hom_tangent* out) {
   if (!c || !c->impl || !out) return HOM_E_ARG;
   return guarded(&c->err, [&] { c->impl->tangent(what, out); });

@@ -73,6 +73,7 @@ class BatchImpl {
   virtual void set_state(const void* buf) = 0;
   virtual void get_field(int which, double* out, size_t count) = 0;
   virtual void tangent(int what, hom_tangent* out) = 0;  // out: one entry per problem
+  virtual void set_laws(const hom_law* laws, int n) = 0;
   virtual const Profiler& profiler() const = 0;
   virtual void set_profiling(bool on) = 0;
   std::string err;

@@ -280,6 +280,7 @@ struct Group {
   std::vector<std::array<double, 6>> En;
   std::vector<std::array<double, 3>> Gp;
   std::vector<double> c0mean;
+  std::vector<std::vector<long long>> phase_count;  // [problem][law]: voxels of each phase
 
   template <typename U>
   U* dalloc(size_t count) {
@@ -528,6 +529,7 @@ class BatchT : public BatchImpl {
           if (src[v] >= laws.size()) fail(HOM_E_ARG, "phase id " + std::to_string(src[v]) + " has no law");
           ++cnt[src[v]];
         }
+        G.phase_count.emplace_back(cnt.begin(), cnt.begin() + laws.size());
         double c0 = 0.0;
         for (size_t l = 0; l < laws.size(); ++l) c0 += laws[l].c0 * (double)cnt[l] / (double)nv;
         G.c0mean[j] = c0;
@@ -909,6 +911,33 @@ class BatchT : public BatchImpl {
         all = all && cm.status == 1;
       }
       G.tan_ok = all;
+    }
+  }
+
+  // New parameters for the phase laws (same kinds; for the PA66 law the same
+  // number of Maxwell branches, so the internal variables keep their layout).
+  void set_laws(const hom_law* lw, int n) override {
+    if (!lw || n != (int)laws.size()) fail(HOM_E_ARG, "need one law per phase of the setup");
+    validate_laws(lw, n);
+    auto branches = [](const hom_law& L) {
+      int nm = 0;
+      for (int j = 0; j < L.n_maxwell; ++j) nm += L.E_i[j] > 0.0 ? 1 : 0;
+      return nm;
+    };
+    for (int i = 0; i < n; ++i) {
+      if (lw[i].kind != laws[i].kind) fail(HOM_E_ARG, "law " + std::to_string(i) + " changes its kind");
+      if (lw[i].kind == HOM_LAW_PA66 && branches(lw[i]) != branches(laws[i]))
+        fail(HOM_E_ARG, "law " + std::to_string(i) + " changes its number of Maxwell branches");
+    }
+    laws.assign(lw, lw + n);
+    for (auto& gp : groups) {
+      Group<T>& G = *gp;
+      for (int j = 0; j < G.nprob; ++j) {
+        double c0 = 0.0;
+        for (int l = 0; l < n; ++l) c0 += laws[l].c0 * (double)G.phase_count[j][l] / (double)G.nvox;
+        G.c0mean[j] = c0;
+      }
+      G.tan_ok = false;  // the tangent fields belong to the old parameters
     }
   }
 

@@ -159,6 +159,7 @@ EXPORTS = (
     "hom_default_options", "hom_setup", "hom_solve_increment", "hom_state_size", "hom_get_state",
     "hom_set_state", "hom_get_field", "hom_kernel_stats", "hom_set_profiling", "hom_device_bytes",
     "hom_algorithmic_tangent", "hom_batch_algorithmic_tangent", "hom_solve_load", "hom_batch_solve_load",
+    "hom_set_laws", "hom_batch_set_laws",
     "hom_last_error", "hom_destroy",
     "hom_batch_setup", "hom_batch_solve_increment", "hom_batch_kernel_stats", "hom_batch_last_error",
     "hom_batch_destroy", "hom_apply_operator", "hom_eval_law",
@@ -204,6 +205,8 @@ def library(path: str | None = None):
     lib.hom_set_profiling.argtypes = [ct.c_void_p, ct.c_int32]
     lib.hom_algorithmic_tangent.argtypes = [ct.c_void_p, ct.c_int32, ct.POINTER(Tangent)]
     lib.hom_solve_load.argtypes = [ct.c_void_p, ct.POINTER(Load), ct.POINTER(Result)]
+    lib.hom_set_laws.argtypes = [ct.c_void_p, ct.POINTER(Law), ct.c_int32]
+    lib.hom_batch_set_laws.argtypes = [ct.c_void_p, ct.POINTER(Law), ct.c_int32]
     lib.hom_batch_solve_load.argtypes = [ct.c_void_p, ct.POINTER(Load), ct.POINTER(Result)]
     lib.hom_batch_algorithmic_tangent.argtypes = [ct.c_void_p, ct.c_int32, ct.POINTER(Tangent)]
     lib.hom_device_bytes.argtypes = [ct.c_void_p]
@@ -380,6 +383,12 @@ class Context:
         out["rc"] = rc
         return out
 
+    def set_laws(self, laws):
+        """hom_set_laws: new parameters for the phase laws (same kinds)."""
+        arr = (Law * len(laws))(*[make_law(p) for p in laws])
+        _check(self._lib.hom_set_laws(self._h, arr, len(laws)), self.error)
+        self._laws = arr
+
     def solve_load(self, strain, theta, grad, dt, stress=None, stress_mask=0, adiabatic=False, check=True):
         """hom_solve_load: mixed boundary conditions and / or the adiabatic heat
         balance (theta is theta^n when adiabatic)."""
@@ -490,6 +499,12 @@ class Batch:
         rc = self._lib.hom_batch_solve_increment(self._h, _dptr(s), temps, _dptr(d), res)
         _check(rc, lambda: self._lib.hom_batch_last_error(self._h).decode())
         return [r.as_dict() for r in res]
+
+    def set_laws(self, laws):
+        arr = (Law * len(laws))(*[make_law(p) for p in laws])
+        _check(self._lib.hom_batch_set_laws(self._h, arr, len(laws)),
+               lambda: self._lib.hom_batch_last_error(self._h).decode())
+        self._laws = arr
 
     def solve_load(self, loads):
         """loads: one dict per problem with the keyword arguments of make_load."""

@@ -161,3 +161,34 @@ def test_tangent_argument_errors():
         basic.algorithmic_tangent(what=0)
     assert e.value.code == hom.HOM_E_UNSUPPORTED
     basic.close()
+
+
+def test_set_laws_reuses_a_context():
+    """One context, new law parameters: the same tangent and heat capacity as
+    a fresh context with those laws (the DMN's sample sweep)."""
+    from test_oracle_cell import MAT_A, MAT_B
+    img = W.centred_sphere(16, 5.8)
+    first = [MAT_A, MAT_B]
+    second = [dict(MAT_A, E=5e3, c0=3.0), dict(MAT_B, E=40e3, nu=0.3)]
+    ctx = hom.Context(img, first, scheme=hom.SCHEME_NEWTON_CG, precision=hom.FP64, tol=1e-10)
+    ctx.solve_increment(np.zeros(6), MAT_A["theta0"], [0, 0, 0], 1.0)
+    t1 = ctx.algorithmic_tangent(what=0)["dsde"]
+    ctx.set_laws(second)
+    with pytest.raises(hom.HomError):          # the tangent belonged to the old laws
+        ctx.algorithmic_tangent(what=0)
+    r = ctx.solve_increment(np.zeros(6), MAT_A["theta0"], [0, 0, 0], 1.0)
+    t2 = ctx.algorithmic_tangent(what=0)["dsde"]
+    fresh = hom.Context(img, second, scheme=hom.SCHEME_NEWTON_CG, precision=hom.FP64, tol=1e-10)
+    rf = fresh.solve_increment(np.zeros(6), MAT_A["theta0"], [0, 0, 0], 1.0)
+    tf = fresh.algorithmic_tangent(what=0)["dsde"]
+    assert np.allclose(t2, tf, rtol=1e-9, atol=1e-9 * np.abs(tf).max())
+    assert not np.allclose(t1, t2, rtol=1e-3)
+    assert r["heat_capacity"] == pytest.approx(rf["heat_capacity"], rel=1e-14)
+    with pytest.raises(hom.HomError) as e:
+        ctx.set_laws([MAT_A])
+    assert e.value.code == hom.HOM_E_ARG
+    with pytest.raises(hom.HomError) as e:
+        ctx.set_laws([W.pa66(), MAT_B])
+    assert e.value.code == hom.HOM_E_ARG
+    ctx.close()
+    fresh.close()
