@@ -156,6 +156,11 @@ typedef struct {
   int32_t adiabatic;
   hom_macro_temp temp;
   double dt;
+  int32_t trial;         /* 1: solve, return the outputs and keep the tangent, but commit
+                            nothing (internal variables, converged strain field and macro
+                            strain stay at step n), as a macroscopic Newton iteration needs;
+                            the same for every problem of a batch */
+  int32_t reserved;
 } hom_load;
 
 typedef struct hom_ctx hom_ctx;
@@ -350,7 +355,8 @@ void hom_mlp_destroy(hom_mlp* net);
  * balance of the jumps by Newton's method with the paper's backtracking
  * (steps 1, 1/2, 1/4, ..., at most 8 cuts) and residual, at tolerance tol and
  * at most maxit Newton steps, then commits (status HOM_OK) or not
- * (HOM_E_NOT_CONVERGED). what = 0 returns d<sigma>/dE of the four
+ * (HOM_E_NOT_CONVERGED); trial = 1 never commits (a macroscopic Newton
+ * iteration), the jumps are kept as the next start. what = 0 returns d<sigma>/dE of the four
  * algorithmic tangents of Sec. 3.3, what = 1 all four (the point partials of
  * the PA66 leaves by central differences, as for hom_algorithmic_tangent).
  * Phase laws: laws[0] for phase 1, laws[1] for phase
@@ -390,7 +396,7 @@ void hom_dmn_destroy(hom_dmn* net);
 int hom_dmn_online_create(const hom_dmn* net, const hom_law laws[2], int32_t n_points, double tol, int32_t maxit,
                           hom_dmn_online** out);
 int hom_dmn_online_step(hom_dmn_online* o, const double* strain, const double* theta, const double* dt,
-                        int32_t what, hom_dmn_result* out);
+                        int32_t what, int32_t trial, hom_dmn_result* out);
 const char* hom_dmn_online_last_error(const hom_dmn_online* o);
 void hom_dmn_online_destroy(hom_dmn_online* o);
 

@@ -326,9 +326,9 @@ int hom_dmn_online_create(const hom_dmn* d, const hom_law laws[2], int32_t n_poi
 }
 
 int hom_dmn_online_step(hom_dmn_online* o, const double* strain, const double* theta, const double* dt,
-                        int32_t what, hom_dmn_result* out) {
+                        int32_t what, int32_t trial, hom_dmn_result* out) {
   if (!o || !o->impl || !strain || !theta || !dt || !out) return HOM_E_ARG;
-  return guarded(&o->err, [&] { hom::dmn_online_step(o->impl, strain, theta, dt, what, out); });
+  return guarded(&o->err, [&] { hom::dmn_online_step(o->impl, strain, theta, dt, what, trial, out); });
 }
 
 const char* hom_dmn_online_last_error(const hom_dmn_online* o) { return o ? o->err.c_str() : g_setup_error.c_str(); }

@@ -706,6 +706,7 @@ struct OnArgs {
   const ProbInc* inc;   // [point]
   const ProbInc* inc_pm;  // [point][2]: theta + h_theta, theta - h_theta (all four tangents)
   int what;             // 1: also the temperature and coupling tangents
+  int trial;            // 1: never commit
   int pa_phase;         // phase (0: even leaves, 1: odd leaves) with the PA66 law, -1 if none
   double* state;        // [point][nstate][nleaf / 2]
   int nstate;
@@ -1039,6 +1040,7 @@ __global__ void __launch_bounds__(1 << ON_MAX_K) k_dmn_online(OnArgs g) {
     if (res < g.tol) break;
   }
   const bool conv = res < g.tol;
+  const bool commit = conv && !g.trial;
   if (it > g.maxit) it = g.maxit;
   // effective stress (V[1] after the last residual), tangent by a final
   // condensation at the converged state
@@ -1145,7 +1147,7 @@ __global__ void __launch_bounds__(1 << ON_MAX_K) k_dmn_online(OnArgs g) {
 #pragma unroll
       for (int c = 0; c < 6; ++c) enl[c] = en[c];
       PaOut po;
-      pa66_point(in, e, st, ss, conv ? st : nullptr, enl, po, &Dd, &D, hs, nullptr);
+      pa66_point(in, e, st, ss, commit ? st : nullptr, enl, po, &Dd, &D, hs, nullptr);
     } else {
       const PhaseInc& pi = in.ph[phase];
       const double trd = (e[0] - en[0]) + (e[1] - en[1]) + (e[2] - en[2]);
@@ -1155,7 +1157,7 @@ __global__ void __launch_bounds__(1 << ON_MAX_K) k_dmn_online(OnArgs g) {
   const double w = S.wsub[nleaf + tid];
   double r2[2] = {w * D, w * Dd};
   block_sum<2>(r2, S.red);
-  if (conv) {
+  if (commit) {
     double* en = g.epsn + ((long long)pt * nleaf + tid) * 6;
 #pragma unroll
     for (int c = 0; c < 6; ++c) en[c] = e[c];
@@ -1228,8 +1230,9 @@ DmnOnline* dmn_online_create(const Dmn& net, const hom_law* laws, int npoints, d
 void dmn_online_destroy(DmnOnline* o) { delete o; }
 
 void dmn_online_step(DmnOnline* o, const double* strain, const double* theta, const double* dt, int what,
-                     hom_dmn_result* res) {
+                     int trial, hom_dmn_result* res) {
   if (what != 0 && what != 1) fail(HOM_E_ARG, "what must be 0 (d sigma / dE) or 1 (all four tangents)");
+  if (trial != 0 && trial != 1) fail(HOM_E_ARG, "trial must be 0 or 1");
   const int n = o->npoints;
   const double sq2 = std::sqrt(2.0);
   const double w[6] = {1, 1, 1, sq2, sq2, sq2};
@@ -1259,6 +1262,7 @@ void dmn_online_step(DmnOnline* o, const double* strain, const double* theta, co
   g.inc = o->inc;
   g.inc_pm = o->inc_pm;
   g.what = what;
+  g.trial = trial;
   g.pa_phase = o->pa_phase;
   g.state = o->state;
   g.nstate = o->nstate;

@@ -726,11 +726,12 @@ class BatchT : public BatchImpl {
   }
 
   // Effective sums of the converged mechanics into ctl.out (copied to ctl_h);
-  // commit: also commit the increment of every converged problem.
-  void mech_finish(Group<T>& G, bool commit) {
+  // commit: also commit the increment of every converged problem; partials:
+  // the point partials of the tangent option (before a commit: state n).
+  void mech_finish(Group<T>& G, bool commit, bool partials) {
     Pt<T> q = G.pt(0);
     q.commit = commit ? 1 : 0;
-    if (commit && G.dsdt) launch_partials<T>(q, stream);  // before the commit: they need state n
+    if (partials && G.dsdt) launch_partials<T>(q, stream);
     prof.begin(K_COMMIT, stream);
     launch_commit<T>(q, 6, stream);
     prof.end(stream);
@@ -781,7 +782,10 @@ class BatchT : public BatchImpl {
       if (L.adiabatic != 0 && L.adiabatic != 1) fail(HOM_E_ARG, "adiabatic must be 0 or 1");
       if (L.stress_mask && opts.scheme != HOM_SCHEME_NEWTON_CG)
         fail(HOM_E_UNSUPPORTED, "mixed boundary conditions need the Newton-CG scheme");
+      if (L.trial != 0 && L.trial != 1) fail(HOM_E_ARG, "trial must be 0 or 1");
+      if (L.trial != loads[0].trial) fail(HOM_E_ARG, "trial must be the same for every problem of a batch");
     }
+    const bool trial = loads[0].trial != 0;
     const double sq2 = std::sqrt(2.0);
     const double w[6] = {1, 1, 1, sq2, sq2, sq2};
     for (auto& gp : groups) {
@@ -820,7 +824,7 @@ class BatchT : public BatchImpl {
         if (G.inc_pm_h)
           HIPCHK(hipMemcpyAsync(G.inc_pm_d, G.inc_pm_h, sizeof(ProbInc) * 2 * np, hipMemcpyHostToDevice, stream));
         mech_iterate(G, s > 0);
-        mech_finish(G, !any_adi);
+        mech_finish(G, !any_adi && !trial, !any_adi);
         for (int j = 0; j < np; ++j) {
           pipes[j] += G.ctl_h[j].pipelines;
           newton[j] += G.ctl_h[j].newton_it;
@@ -870,7 +874,7 @@ class BatchT : public BatchImpl {
             G.ctl_h[j].mode = M_FAIL;
           }
         HIPCHK(hipMemcpyAsync(G.ctl_m, G.ctl_h, sizeof(Ctl) * np, hipMemcpyHostToDevice, stream));
-        mech_finish(G, true);
+        mech_finish(G, !trial, true);
         break;
       }
       std::vector<Ctl> mech(G.ctl_h, G.ctl_h + np);
@@ -906,7 +910,7 @@ class BatchT : public BatchImpl {
         if (cm.status != 1) st = cm.status < 0 ? cm.status : HOM_E_NOT_CONVERGED;
         if (st == HOM_OK && ct.status != 1) st = ct.status < 0 ? ct.status : HOM_E_NOT_CONVERGED;
         r.status = st;
-        if (cm.status == 1)
+        if (cm.status == 1 && !trial)
           for (int c = 0; c < 6; ++c) G.En[j][c] = ((L.stress_mask >> c) & 1u) ? cm.out[8 + c] : w[c] * L.strain[c];
         all = all && cm.status == 1;
       }

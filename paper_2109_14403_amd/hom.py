@@ -103,11 +103,12 @@ class Result(ct.Structure):
 class Load(ct.Structure):
     _fields_ = [
         ("strain", ct.c_double * 6), ("stress", ct.c_double * 6), ("stress_mask", ct.c_uint32),
-        ("adiabatic", ct.c_int32), ("temp", MacroTemp), ("dt", ct.c_double),
+        ("adiabatic", ct.c_int32), ("temp", MacroTemp), ("dt", ct.c_double), ("trial", ct.c_int32),
+        ("reserved", ct.c_int32),
     ]
 
 
-def make_load(strain, theta, grad, dt, stress=None, stress_mask=0, adiabatic=False) -> Load:
+def make_load(strain, theta, grad, dt, stress=None, stress_mask=0, adiabatic=False, trial=False) -> Load:
     """hom_load; stress_mask: int bit mask or 6 booleans (True: stress-controlled)."""
     L = Load()
     for c in range(6):
@@ -117,6 +118,7 @@ def make_load(strain, theta, grad, dt, stress=None, stress_mask=0, adiabatic=Fal
         stress_mask = sum(1 << c for c in range(6) if stress_mask[c])
     L.stress_mask = int(stress_mask)
     L.adiabatic = int(bool(adiabatic))
+    L.trial = int(bool(trial))
     L.temp.theta = float(theta)
     for c in range(3):
         L.temp.grad[c] = float(grad[c])
@@ -243,7 +245,7 @@ def library(path: str | None = None):
     lib.hom_dmn_destroy.restype = None
     lib.hom_dmn_online_create.argtypes = [ct.c_void_p, ct.POINTER(Law), ct.c_int32, ct.c_double, ct.c_int32,
                                           ct.POINTER(ct.c_void_p)]
-    lib.hom_dmn_online_step.argtypes = [ct.c_void_p, dp, dp, dp, ct.c_int32, ct.POINTER(DmnResult)]
+    lib.hom_dmn_online_step.argtypes = [ct.c_void_p, dp, dp, dp, ct.c_int32, ct.c_int32, ct.POINTER(DmnResult)]
     lib.hom_dmn_online_last_error.argtypes = [ct.c_void_p]
     lib.hom_dmn_online_last_error.restype = ct.c_char_p
     lib.hom_dmn_online_destroy.argtypes = [ct.c_void_p]
@@ -389,10 +391,11 @@ class Context:
         _check(self._lib.hom_set_laws(self._h, arr, len(laws)), self.error)
         self._laws = arr
 
-    def solve_load(self, strain, theta, grad, dt, stress=None, stress_mask=0, adiabatic=False, check=True):
+    def solve_load(self, strain, theta, grad, dt, stress=None, stress_mask=0, adiabatic=False, trial=False,
+                   check=True):
         """hom_solve_load: mixed boundary conditions and / or the adiabatic heat
-        balance (theta is theta^n when adiabatic)."""
-        L = make_load(strain, theta, grad, dt, stress, stress_mask, adiabatic)
+        balance (theta is theta^n when adiabatic); trial: commit nothing."""
+        L = make_load(strain, theta, grad, dt, stress, stress_mask, adiabatic, trial)
         r = Result()
         rc = self._lib.hom_solve_load(self._h, ct.byref(L), ct.byref(r))
         if check:
@@ -792,11 +795,12 @@ class DmnOnline:
         except Exception:
             pass
 
-    def step(self, strains, thetas, dts, what=0):
+    def step(self, strains, thetas, dts, what=0, trial=False):
         e = _f64(strains).reshape(self.n, 6)
         t = _f64(np.broadcast_to(thetas, (self.n,)))
         d = _f64(np.broadcast_to(dts, (self.n,)))
         out = (DmnResult * self.n)()
-        _check(self._lib.hom_dmn_online_step(self._h, _dptr(e), _dptr(t), _dptr(d), int(what), out),
+        _check(self._lib.hom_dmn_online_step(self._h, _dptr(e), _dptr(t), _dptr(d), int(what), int(bool(trial)),
+                                             out),
                lambda: self._lib.hom_dmn_online_last_error(self._h).decode())
         return [r.as_dict() for r in out]

@@ -180,3 +180,30 @@ def test_dmn_argument_errors():
         net.set_params(np.zeros((7, 3)), np.ones(8))
     with pytest.raises(hom.HomError):
         hom.DmnOnline(net, W.pa66(), W.pa66(), 4)      # at most one PA66 law
+
+
+def test_online_trial_steps_commit_nothing():
+    rng = np.random.default_rng(31)
+    K = 5
+    m, v = random_params(K, rng)
+    net = _net(K, m, v)
+    a = hom.DmnOnline(net, W.e_glass(), W.pa66(), 2, tol=1e-12)
+    b = hom.DmnOnline(net, W.e_glass(), W.pa66(), 2, tol=1e-12)
+    d = np.array([[1, 0, 0, 0, 0, 0.4], [0, 0.5, -0.2, 0.3, 0, 0]], dtype=float)
+    for k in (1, 2):
+        a.step(d * 0.01 * k, 300.0, 2.0)
+        b.step(d * 0.01 * k, 300.0, 2.0)
+    a.step(d * 0.045, 300.0, 2.0, trial=True)
+    t = a.step(d * 0.03, 300.0, 2.0, trial=True, what=1)
+    ra = a.step(d * 0.03, 300.0, 2.0)
+    rb = b.step(d * 0.03, 300.0, 2.0, what=1)
+    for i in range(2):
+        for r in (ra[i], t[i]):
+            assert np.allclose(r["stress"], rb[i]["stress"], rtol=1e-10, atol=1e-10 * np.abs(rb[i]["stress"]).max())
+            assert abs(r["dissipation"] - rb[i]["dissipation"]) <= 1e-9 * abs(rb[i]["dissipation"])
+        assert np.allclose(t[i]["dDde"], rb[i]["dDde"], rtol=1e-8, atol=1e-8 * np.abs(rb[i]["dDde"]).max())
+    # the next increment after the commit agrees too
+    ra = a.step(d * 0.04, 300.0, 2.0)
+    rb = b.step(d * 0.04, 300.0, 2.0)
+    for i in range(2):
+        assert np.allclose(ra[i]["stress"], rb[i]["stress"], rtol=1e-10, atol=1e-10 * np.abs(rb[i]["stress"]).max())

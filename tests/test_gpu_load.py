@@ -127,3 +127,34 @@ def test_load_argument_errors():
     r = basic.solve_load([1e-3, 0, 0, 0, 0, 0], 300.0, [0, 0, 0], 1.0, adiabatic=True)
     assert r["status"] == hom.HOM_OK and r["theta"] < 300.0
     basic.close()
+
+
+def test_trial_increments_commit_nothing():
+    """Trial solves (a macroscopic Newton method's iterations) leave step n as
+    it was: trials then a commit equal the commit alone, bitwise; a trial's
+    outputs and tangent are those of the committed solve at the same load."""
+    img, laws = plastic_cell(16, seed=5)
+    hist = W.history_shear_tension()
+    a = hom.Context(img, laws, scheme=hom.SCHEME_NEWTON_CG, precision=hom.FP64, tol=1e-10)
+    b = hom.Context(img, laws, scheme=hom.SCHEME_NEWTON_CG, precision=hom.FP64, tol=1e-10)
+    for st in hist[:4]:
+        a.solve_increment(st.strain, st.theta, st.grad, st.dt)
+        b.solve_increment(st.strain, st.theta, st.grad, st.dt)
+    st = hist[4]
+    kw = dict(stress_mask=[False, True, True, False, False, False], adiabatic=True)
+    state_before = a.get_state()
+    t1 = a.solve_load(np.asarray(st.strain) * 1.3, st.theta, st.grad, st.dt, trial=True, **kw)
+    t2 = a.solve_load(st.strain, st.theta, st.grad, st.dt, trial=True, **kw)
+    tan_trial = a.algorithmic_tangent(what=0)["dsde"]
+    assert a.get_state() == state_before
+    assert not np.allclose(t1["stress"], t2["stress"])
+    ra = a.solve_load(st.strain, st.theta, st.grad, st.dt, **kw)
+    rb = b.solve_load(st.strain, st.theta, st.grad, st.dt, **kw)
+    for k in ("stress", "strain"):
+        assert np.array_equal(ra[k], rb[k])
+    assert ra["theta"] == rb["theta"] and ra["coupling"] == rb["coupling"]
+    assert np.array_equal(t2["stress"], rb["stress"]) and t2["theta"] == rb["theta"]
+    assert np.array_equal(tan_trial, b.algorithmic_tangent(what=0)["dsde"])
+    assert a.get_state() != state_before
+    a.close()
+    b.close()
