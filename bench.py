@@ -136,9 +136,9 @@ def batch_bench(nprob=512, steps=5, seed=4):
             "voxel_iters_per_s": round(float((pipes * nvox).sum()) / el, 1), "failed": failed}
 
 
-def surrogate_bench(n_hist=4000, test_hist=1000, epochs=150, rows=65536):
+def surrogate_bench(n_hist=20000, test_hist=1000, epochs=100, rows=65536):
     """Surrogate vs FFT Gauss-point updates/s on the fixed 32^3 microstructure:
-    20k FFT samples (4000 histories x 5 increments, batched solver) train two
+    100k FFT samples (20000 histories x 5 increments, batched solver) train two
     networks; acceptance is calibrated on held-out histories so that 99 % of
     accepted rows meet the error target; a fresh test set measures acceptance
     and error; rejected rows are charged at the batched FFT rate."""

@@ -550,20 +550,33 @@ void Mlp::fit_skip(const float* X, const float* Y, long long n, const int* gates
   }
   double tr = 0.0;
   for (int a = 0; a < P; ++a) tr += AtA[(size_t)a * P + a];
-  for (int a = 0; a < P; ++a) AtA[(size_t)a * P + a] += 1e-12 * tr / P;
-  // Cholesky (lower, in place)
-  for (int j = 0; j < P; ++j) {
-    double d = AtA[(size_t)j * P + j];
-    for (int k = 0; k < j; ++k) d -= AtA[(size_t)j * P + k] * AtA[(size_t)j * P + k];
-    if (!(d > 0.0)) fail(HOM_E_NAN, "skip fit: normal equations not positive definite");
-    d = std::sqrt(d);
-    AtA[(size_t)j * P + j] = d;
-    for (int i = j + 1; i < P; ++i) {
-      double v = AtA[(size_t)i * P + j];
-      for (int k = 0; k < j; ++k) v -= AtA[(size_t)i * P + k] * AtA[(size_t)j * P + k];
-      AtA[(size_t)i * P + j] = v / d;
+  // Cholesky (lower, in place) with a small ridge; the cubic gate features
+  // make the normal equations ill-conditioned, so the ridge grows until the
+  // factorization succeeds in FP64
+  const std::vector<double> A0(AtA);
+  bool ok = false;
+  for (double ridge : {1e-12, 1e-10, 1e-8, 1e-6}) {
+    AtA = A0;
+    for (int a = 0; a < P; ++a) AtA[(size_t)a * P + a] += ridge * tr / P;
+    ok = true;
+    for (int j = 0; j < P && ok; ++j) {
+      double d = AtA[(size_t)j * P + j];
+      for (int k = 0; k < j; ++k) d -= AtA[(size_t)j * P + k] * AtA[(size_t)j * P + k];
+      if (!(d > 0.0)) {
+        ok = false;
+        break;
+      }
+      d = std::sqrt(d);
+      AtA[(size_t)j * P + j] = d;
+      for (int i = j + 1; i < P; ++i) {
+        double v = AtA[(size_t)i * P + j];
+        for (int k = 0; k < j; ++k) v -= AtA[(size_t)i * P + k] * AtA[(size_t)j * P + k];
+        AtA[(size_t)i * P + j] = v / d;
+      }
     }
+    if (ok) break;
   }
+  if (!ok) fail(HOM_E_NAN, "skip fit: normal equations not positive definite");
   std::vector<float> G((size_t)n_out * MLP_GATES * n_in), c(n_out);
   std::vector<double> z(P);
   for (int j = 0; j < n_out; ++j) {
