@@ -63,6 +63,10 @@ struct Mlp {
   // row weights [B] or null; fills g
   double loss_grad(const float* x, const float* tnorm, long long B, bool precise, hipStream_t s,
                    const float* rw = nullptr);
+  // the gradient of loss_grad without reading the loss back; returns the
+  // number of loss partials left in lpart
+  int grad_only(const float* x, const float* tnorm, long long B, bool precise, hipStream_t s,
+                const float* rw = nullptr);
   void train(const float* X, const float* T, long long n, int epochs, int batch, double lr, uint64_t seed,
              const float* row_weight, float* loss_out);
   void get_params(float* out) const;

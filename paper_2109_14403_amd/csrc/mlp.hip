@@ -210,12 +210,23 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) k
 
 // C[M][N] = op(A) op(B) (+ beta C), row-major, FP32. op(A) = A (M x K, lda)
 // or A^T (A stored K x M); op(B) = B (K x N, ldb) or B^T (B stored N x K).
+// C = op(A) op(B) (+ beta C), 64 x 64 tiles. With gridDim.z > 1 the inner
+// dimension is split in chunks of kc: work-group z takes rows z kc .. of A
+// and B (A, B stored [k][*], the weight-gradient form) and writes its own
+// partial C + z M ldc.
 template <bool TA, bool TB>
 __global__ void __launch_bounds__(256) k_gemm(int M, int N, int K, const float* __restrict__ A, int lda,
                                               const float* __restrict__ B, int ldb, float* __restrict__ C, int ldc,
-                                              float beta) {
+                                              float beta, int kc = 0) {
   __shared__ float As[16][65];
   __shared__ float Bs[16][65];
+  if (gridDim.z > 1) {
+    const int k0 = blockIdx.z * kc;
+    K = min(kc, K - k0);
+    A += (long long)k0 * lda;
+    B += (long long)k0 * ldb;
+    C += (long long)blockIdx.z * M * ldc;
+  }
   const int tid = threadIdx.x;
   const int tm = tid / 16, tn = tid % 16;
   const int m0 = blockIdx.y * 64, n0 = blockIdx.x * 64;
@@ -261,12 +272,31 @@ __global__ void __launch_bounds__(256) k_gemm(int M, int N, int K, const float* 
 }
 
 // column sums: out[j] = sum_r in[r][j], one thread per column (fixed order)
-__global__ void k_colsum(const float* in, long long rows, int cols, float* out) {
-  const int j = blockIdx.x * blockDim.x + threadIdx.x;
-  if (j >= cols) return;
+// Column sums (bias gradients) in two fixed-order stages: blocks of 64
+// columns x 4 row lanes over row chunks into FP64 partials, then the chunks.
+constexpr int COLSUM_CHUNK = 256;
+__global__ void __launch_bounds__(256) k_colsum_part(const float* in, long long rows, int cols, double* part) {
+  __shared__ double red[4][64];
+  const int c = blockIdx.x * 64 + (threadIdx.x & 63);
+  const int lane = threadIdx.x >> 6;
+  const long long r0 = (long long)blockIdx.y * COLSUM_CHUNK;
+  const long long r1 = min(rows, r0 + COLSUM_CHUNK);
   double s = 0.0;
-  for (long long r = 0; r < rows; ++r) s += in[r * cols + j];
-  out[j] = (float)s;
+  if (c < cols)
+    for (long long r = r0 + lane; r < r1; r += 4) s += in[r * cols + c];
+  red[lane][threadIdx.x & 63] = s;
+  __syncthreads();
+  if (lane == 0 && c < cols)
+    part[(long long)blockIdx.y * cols + c] = red[0][threadIdx.x] + red[1][threadIdx.x] + red[2][threadIdx.x] +
+                                             red[3][threadIdx.x];
+}
+
+__global__ void __launch_bounds__(256) k_colsum_final(const double* part, int chunks, int cols, float* out) {
+  const int c = blockIdx.x * 256 + threadIdx.x;
+  if (c >= cols) return;
+  double s = 0.0;
+  for (int k = 0; k < chunks; ++k) s += part[(long long)k * cols + c];
+  out[c] = (float)s;
 }
 
 // dz = da * gelu'(z)
@@ -677,9 +707,56 @@ void Mlp::forward(const float* x, float* y, long long n, bool precise, bool save
     hipLaunchKernelGGL(k_mlp_fwd<0>, dim3(blocks), dim3(256), 0, s, a);
 }
 
+// C = sum_s P[s] over the split-K partials, in a fixed order
+__global__ void __launch_bounds__(256) k_sum_splits(const float* P, int splits, int M, int N, float* C, int ldc) {
+  const long long i = (long long)blockIdx.x * 256 + threadIdx.x;
+  if (i >= (long long)M * N) return;
+  const int m = (int)(i / N), n = (int)(i % N);
+  float v = 0.f;
+  for (int k = 0; k < splits; ++k) v += P[(long long)k * M * N + i];
+  C[(long long)m * ldc + n] = v;
+}
+
+// split-K work space of the weight-gradient products (a few MB)
+static float* g_splitk = nullptr;
+static size_t g_splitk_n = 0;
+static double* g_colsum = nullptr;
+static size_t g_colsum_n = 0;
+
+static void colsum(const float* in, long long rows, int cols, float* out, hipStream_t s) {
+  const int chunks = (int)((rows + COLSUM_CHUNK - 1) / COLSUM_CHUNK);
+  const size_t need = (size_t)chunks * cols;
+  if (need > g_colsum_n) {
+    if (g_colsum) HIPCHK(hipFree(g_colsum));
+    HIPCHK(hipMalloc((void**)&g_colsum, need * sizeof(double)));
+    g_colsum_n = need;
+  }
+  hipLaunchKernelGGL(k_colsum_part, dim3((cols + 63) / 64, chunks), dim3(256), 0, s, in, rows, cols, g_colsum);
+  hipLaunchKernelGGL(k_colsum_final, dim3((cols + 255) / 256), dim3(256), 0, s, g_colsum, chunks, cols, out);
+}
+
 static void gemm(bool ta, bool tb, int M, int N, int K, const float* A, int lda, const float* B, int ldb, float* C,
                  int ldc, hipStream_t s) {
   dim3 grid((N + 63) / 64, (M + 63) / 64);
+  // weight gradients: a small M x N output over a long K (the batch) gets
+  // few work-groups; split K over more of them and sum the partials
+  if (ta && !tb && grid.x * grid.y < 128 && K >= 1024) {
+    const int splits = std::min(64, K / 256);
+    const int kc = (K + splits - 1) / splits;
+    const size_t need = (size_t)splits * M * N;
+    if (need > g_splitk_n) {
+      if (g_splitk) HIPCHK(hipFree(g_splitk));
+      HIPCHK(hipMalloc((void**)&g_splitk, need * sizeof(float)));
+      g_splitk_n = need;
+    }
+    const int nsp = (K + kc - 1) / kc;  // every split has at least one row
+    hipLaunchKernelGGL((k_gemm<true, false>), dim3(grid.x, grid.y, nsp), dim3(256), 0, s, M, N, K, A, lda, B, ldb,
+                       g_splitk, N, 0.f, kc);
+    const long long cnt = (long long)M * N;
+    hipLaunchKernelGGL(k_sum_splits, dim3((unsigned)((cnt + 255) / 256)), dim3(256), 0, s, g_splitk, nsp, M, N, C,
+                       ldc);
+    return;
+  }
   if (!ta && !tb) hipLaunchKernelGGL((k_gemm<false, false>), grid, dim3(256), 0, s, M, N, K, A, lda, B, ldb, C, ldc, 0.f);
   if (ta && !tb) hipLaunchKernelGGL((k_gemm<true, false>), grid, dim3(256), 0, s, M, N, K, A, lda, B, ldb, C, ldc, 0.f);
   if (!ta && tb) hipLaunchKernelGGL((k_gemm<false, true>), grid, dim3(256), 0, s, M, N, K, A, lda, B, ldb, C, ldc, 0.f);
@@ -688,8 +765,33 @@ static void gemm(bool ta, bool tb, int M, int N, int K, const float* A, int lda,
 
 // loss and gradient of the rows (x, t normalized targets already in xb / tb
 // layout: x raw [B][n_in], t normalized [B][16])
+// Fixed-order sum of the loss partials of one step into a device accumulator
+// (training reads the losses back once, at the end, not after every step).
+__global__ void __launch_bounds__(256) k_loss_accumulate(const double* part, int n, double* acc) {
+  __shared__ double red[256];
+  double v = 0.0;
+  for (int i = threadIdx.x; i < n; i += 256) v += part[i];
+  red[threadIdx.x] = v;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) *acc += red[0];
+}
+
 double Mlp::loss_grad(const float* x, const float* tnorm, long long B, bool precise, hipStream_t s,
                       const float* rw) {
+  const int lb = grad_only(x, tnorm, B, precise, s, rw);
+  std::vector<double> lp(lb);
+  HIPCHK(hipMemcpyAsync(lp.data(), lpart, lb * sizeof(double), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  double L = 0.0;
+  for (double v : lp) L += v;
+  return L;
+}
+
+int Mlp::grad_only(const float* x, const float* tnorm, long long B, bool precise, hipStream_t s, const float* rw) {
   ensure_work(B);
   forward(x, nullptr, B, precise, true, s);
   const long long cnt = B * MLP_OUT;
@@ -704,7 +806,7 @@ double Mlp::loss_grad(const float* x, const float* tnorm, long long B, bool prec
     const float* ain = l == 0 ? xs : as[l - 1];
     // dW[N][K] = dZ^T (B x N) . A (B x K)
     gemm(true, false, N, K, (int)B, dcur, ncur, ain, K, g + woff[l], K, s);
-    hipLaunchKernelGGL(k_colsum, dim3((N + 255) / 256), dim3(256), 0, s, dcur, B, N, g + boff[l]);
+    colsum(dcur, B, N, g + boff[l], s);
     if (l > 0) {
       // dA (B x K) = dZ (B x N) . W (N x K), then dZ_prev = dA * gelu'(Z_prev)
       gemm(false, false, (int)B, K, N, dcur, ncur, eff + woff[l], K, da, K, s);
@@ -716,12 +818,7 @@ double Mlp::loss_grad(const float* x, const float* tnorm, long long B, bool prec
       ncur = K;
     }
   }
-  std::vector<double> lp(lb);
-  HIPCHK(hipMemcpyAsync(lp.data(), lpart, lb * sizeof(double), hipMemcpyDeviceToHost, s));
-  HIPCHK(hipStreamSynchronize(s));
-  double L = 0.0;
-  for (double v : lp) L += v;
-  return L;
+  return lb;
 }
 
 void Mlp::get_params(float* out) const {
@@ -811,6 +908,10 @@ void Mlp::train(const float* X, const float* T, long long n, int epochs, int bat
   std::mt19937_64 gen(seed);
   std::vector<int> perm(n);
   const long long steps_per_epoch = n / batch;
+  double* dloss = nullptr;  // per-epoch loss sums on the device
+  HIPCHK(hipMalloc((void**)&dloss, std::max(epochs, 1) * sizeof(double)));
+  guard.p.push_back(dloss);
+  HIPCHK(hipMemset(dloss, 0, std::max(epochs, 1) * sizeof(double)));
   const long long total = steps_per_epoch * epochs;
   long long step = 0;
   const float b1 = 0.9f, b2 = 0.999f;
@@ -818,7 +919,6 @@ void Mlp::train(const float* X, const float* T, long long n, int epochs, int bat
     for (long long i = 0; i < n; ++i) perm[i] = (int)i;
     std::shuffle(perm.begin(), perm.end(), gen);
     HIPCHK(hipMemcpy(didx, perm.data(), n * 4, hipMemcpyHostToDevice));
-    double el = 0.0;
     for (long long sidx = 0; sidx < steps_per_epoch; ++sidx) {
       const int* bi = didx + sidx * batch;
       const long long cx = (long long)batch * n_in, ct = (long long)batch * MLP_OUT;
@@ -826,7 +926,9 @@ void Mlp::train(const float* X, const float* T, long long n, int epochs, int bat
       hipLaunchKernelGGL(k_gather, dim3((ct + 255) / 256), dim3(256), 0, s, dT, MLP_OUT, bi, (long long)batch, tb);
       if (dW)
         hipLaunchKernelGGL(k_gather, dim3((batch + 255) / 256), dim3(256), 0, s, dW, 1, bi, (long long)batch, rwb);
-      el += loss_grad(xb, tb, batch, false, s, dW ? rwb : nullptr);
+      const int lb = grad_only(xb, tb, batch, false, s, dW ? rwb : nullptr);
+      hipLaunchKernelGGL(k_loss_accumulate, dim3(1), dim3(256), 0, s, reinterpret_cast<const double*>(lpart), lb,
+                         dloss + e);
       ++step;
       // cosine decay to 1 % with a short warm-up
       const double prog = (double)step / (double)total;
@@ -838,9 +940,13 @@ void Mlp::train(const float* X, const float* T, long long n, int epochs, int bat
                          1e-8f);
       refresh(s);
     }
-    if (loss_out) loss_out[e] = (float)(el / steps_per_epoch);
   }
   HIPCHK(hipDeviceSynchronize());
+  if (loss_out && epochs > 0) {
+    std::vector<double> hl(epochs);
+    HIPCHK(hipMemcpy(hl.data(), dloss, epochs * sizeof(double), hipMemcpyDeviceToHost));
+    for (int e = 0; e < epochs; ++e) loss_out[e] = (float)(hl[e] / steps_per_epoch);
+  }
 }
 
 void surrogate_accept(const Mlp& a, const Mlp& b, const float* x, float* y, float* ya, float* yb, float* spread,
