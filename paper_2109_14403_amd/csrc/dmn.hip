@@ -18,6 +18,8 @@
 #include <cstring>
 #include <random>
 #include <string>
+#include <unordered_map>
+#include <utility>
 
 #include "dmn.h"
 #include "pa66.h"
@@ -689,47 +691,454 @@ void Dmn::train(long long n, const double* C1, const double* C2, const double* C
 }
 
 // ---------------------------------------------------------------------------
-// online evaluation
+// online evaluation (paper Sec. 3.3): Newton's method on the jumps of the
+// whole tree for many macroscopic points, one wave per point.
+//
+// Lane t of a point owns the subtree of R = K - S levels below the depth-S
+// node 2^S + t (S = min(K, 6)), i.e. 2^R leaves whose data stay in its
+// registers. The S levels above are combined across lanes with shuffles: the
+// depth-d node j (heap 2^d + j) belongs to lane j 2^(S-d), its right child to
+// lane j 2^(S-d) + 2^(S-d-1). Per-node data in global memory (the jumps, the
+// elimination factors G, d0 and the last Newton step) are touched only by the
+// owning lane, so a point needs neither LDS nor a barrier and many points
+// share a CU.
+//
+// One bottom-up sweep forms the residual (weighted stress sums and the
+// traction mismatch N^T (c2 s1 - c1 s2) of every laminate) and, in the same
+// pass, eliminates the jumps: with the children's condensed tangents K1, K2
+// and condensed stresses, X = (c2 K1 - c1 K2) N, M = N^T (c2^2 K1 + c1^2 K2) N,
+// G = -M^-1 X^T, d0 = -M^-1 N^T (c2 s1' - c1 s2'), and the parent gets
+// K = K1 + K2 + X G (the symmetric Schur complement) and s' = s1' + s2' + X d0.
+// The top-down sweep turns a root strain change into the jumps' Newton steps
+// da = d0 + G deps. The converged root tangent is the effective algorithmic
+// tangent d<sigma>/dE.
 // ---------------------------------------------------------------------------
 namespace {
 
 constexpr int ON_MAX_K = 8;
+constexpr int ON_LANES = 64;  // one wave per point
+constexpr int ON_SHUF = 6;    // levels combined across the lanes (2^6 = 64)
 // per point: sigma 6, coupling, dissipation, dsde 36, dsdt 6, dDde 6, dDdt,
 // residual, iterations, status
 constexpr int ON_OUT = 64;
 constexpr int O_DSDT = 44, O_DDDE = 50, O_DDDT = 56, O_RES = 57, O_IT = 58, O_ST = 59;
-constexpr int ON_SCR = 24;  // per internal node: G (18), da0 (3)
+constexpr int ON_SCR = 24;  // per internal node: G (18), d0 (3), last Newton step (3)
+constexpr int ON_NODE = 8;  // per heap node: unit direction (3), c1, subtree weight
+constexpr int ON_LP = 16;   // per leaf: d sigma / d theta (6), d D / d eps (6), d D / d theta
 
 struct OnArgs {
-  int K, nleaf;
-  const double* p;
-  const ProbInc* inc;   // [point]
-  const ProbInc* inc_pm;  // [point][2]: theta + h_theta, theta - h_theta (all four tangents)
-  int what;             // 1: also the temperature and coupling tangents
-  int trial;            // 1: never commit
-  int pa_phase;         // phase (0: even leaves, 1: odd leaves) with the PA66 law, -1 if none
-  double* state;        // [point][nstate][nleaf / 2]
+  int K, nleaf, S;
+  const double* node;     // [2 nleaf][ON_NODE], heap index (leaves: weight in slot 4)
+  const ProbInc* inc;     // [distinct (theta, dt) of the call]
+  const ProbInc* inc_pm;  // [distinct][2]: theta + h_theta, theta - h_theta (all four tangents)
+  const int* inc_ix;      // [point] index into inc
+  int what;               // 1: also the temperature and coupling tangents
+  int trial;              // 1: never commit
+  int pa_phase;           // phase (0: even leaves, 1: odd leaves) with the PA66 law, -1 if none
+  double* state;          // [point][nstate][nleaf / 2]
   int nstate;
-  double* hist;         // [point][HIST_SLOTS][nleaf / 2]
-  double* epsn;         // [point][nleaf][6]
-  double* a;            // [point][nleaf][3] jumps (heap index)
-  double* scr;          // [point][nleaf][ON_SCR]
-  const double* E;      // [point][6] Mandel
-  double* out;          // [point][ON_OUT]
+  double* hist;           // [point][HIST_SLOTS][nleaf / 2]
+  double* epsn;           // [point][nleaf][6]
+  double* a;              // [point][nleaf][3] jumps (heap index)
+  double* scr;            // [point][nleaf][ON_SCR]
+  double* lp;             // [point][nleaf][ON_LP] leaf partials (what = 1)
+  const double* E;        // [point][6] Mandel
+  double* out;            // [point][ON_OUT]
   double tol, gamma;
   int maxit, maxbt;
 };
 
-struct OnShared {
-  double wsub[2 << ON_MAX_K];
-  double nv[(1 << ON_MAX_K) * 3];  // unit directions, heap index
-  double V[(2 << ON_MAX_K) * 6];   // strains (top-down) / weighted stress sums (bottom-up)
-  double KA[(1 << ON_MAX_K) * 36]; // condensed tangents, children level
-  double KB[(1 << (ON_MAX_K - 1)) * 36];
-  double da[(1 << ON_MAX_K) * 3];  // Newton step of the jumps (heap index)
-  double red[16 * 2];
-  double res;
+// node table of a network: unit directions, c1 and subtree weights (heap index)
+__global__ void k_dmn_node_table(const double* p, int nleaf, double* node) {
+  if (blockIdx.x != 0 || threadIdx.x != 0) return;
+  const double* v = p + 3 * (nleaf - 1);
+  for (int l = 0; l < nleaf; ++l) node[ON_NODE * (nleaf + l) + 4] = fmax(v[l], 0.0);
+  for (int h = nleaf - 1; h >= 1; --h) {
+    double* nh = node + ON_NODE * h;
+    const double wl = node[ON_NODE * (2 * h) + 4], wr = node[ON_NODE * (2 * h + 1) + 4], sw = wl + wr;
+    double len;
+    unit(p + 3 * param_of(h, nleaf), nh, len);
+    nh[3] = sw > 0.0 ? wl / sw : 0.5;
+    nh[4] = sw;
+  }
+}
+
+// packed index of the symmetric 6 x 6 entry (i, j)
+__host__ __device__ constexpr int sx(int i, int j) {
+  return i <= j ? i * 6 - (i * (i - 1)) / 2 + (j - i) : j * 6 - (j * (j - 1)) / 2 + (i - j);
+}
+
+// a leaf: weight, compressed tangent 3K P1 + ca P2 + cb N N, weighted stress (or source)
+struct LeafV {
+  double w, K3, ca, cb, nd[6];
+  double s[6];
 };
+// a condensed subtree: tangent (packed symmetric, in the lane's LDS slot:
+// entry e at K[e * ON_LANES]), plain and condensed stress sums
+struct NodeV {
+  double* K;
+  double s[6], sp[6];
+};
+
+__device__ __forceinline__ double kent(const LeafV& a, int i, int q) {
+  return a.w * ((i == q ? a.ca : 0.0) + (i < 3 && q < 3 ? (a.K3 - a.ca) * (1.0 / 3.0) : 0.0) + a.cb * a.nd[i] * a.nd[q]);
+}
+__device__ __forceinline__ double kent(const NodeV& a, int i, int q) { return a.K[sx(i, q) * ON_LANES]; }
+__device__ __forceinline__ const double* plain(const LeafV& a) { return a.s; }
+__device__ __forceinline__ const double* plain(const NodeV& a) { return a.s; }
+__device__ __forceinline__ const double* cond(const LeafV& a) { return a.s; }
+__device__ __forceinline__ const double* cond(const NodeV& a) { return a.sp; }
+
+__device__ __forceinline__ void to_node(const LeafV& L, NodeV& v) {
+#pragma unroll
+  for (int i = 0; i < 6; ++i)
+#pragma unroll
+    for (int q = i; q < 6; ++q) v.K[sx(i, q) * ON_LANES] = kent(L, i, q);
+#pragma unroll
+  for (int c = 0; c < 6; ++c) v.s[c] = v.sp[c] = L.s[c];
+}
+
+// N a = sym(a (x) n) (Mandel) for the unit direction n
+__device__ __forceinline__ void n_apply(const double* n, const double* a, double* v) {
+  v[0] = n[0] * a[0];
+  v[1] = n[1] * a[1];
+  v[2] = n[2] * a[2];
+  v[3] = SQ2H * (n[2] * a[1] + n[1] * a[2]);
+  v[4] = SQ2H * (n[2] * a[0] + n[0] * a[2]);
+  v[5] = SQ2H * (n[1] * a[0] + n[0] * a[1]);
+}
+// N^T v
+__device__ __forceinline__ void nt_apply(const double* n, const double* v, double* r) {
+  r[0] = n[0] * v[0] + SQ2H * (n[2] * v[4] + n[1] * v[5]);
+  r[1] = n[1] * v[1] + SQ2H * (n[2] * v[3] + n[0] * v[5]);
+  r[2] = n[2] * v[2] + SQ2H * (n[1] * v[3] + n[0] * v[4]);
+}
+__device__ __forceinline__ double* node_scr(const OnArgs& g, int pt, int h) {
+  return g.scr + ((long long)pt * g.nleaf + h) * ON_SCR;
+}
+__device__ __forceinline__ double* node_jump(const OnArgs& g, int pt, int h) {
+  return g.a + ((long long)pt * g.nleaf + h) * 3;
+}
+
+// Laminate h from its children A (phase 1 side) and B: residual contribution
+// (PLAIN: from the plain sums), elimination factors into the node's scratch,
+// condensed tangent and stresses into P. P may be A itself: every entry of P
+// is written after the last read of the same entry of A.
+template <bool PLAIN, class CA, class CB>
+__device__ __forceinline__ void combine(const OnArgs& g, int pt, int h, const CA& A, const CB& B, NodeV& P,
+                                        double& gg) {
+  const double* nt = g.node + ON_NODE * h;
+  const double n[3] = {nt[0], nt[1], nt[2]};
+  const double c1 = nt[3], c2 = 1.0 - c1, wsub = nt[4];
+  const double s0 = SQ2H * n[0], s1 = SQ2H * n[1], s2 = SQ2H * n[2];
+  // X = (c2 K1 - c1 K2) N and M = N^T (c2^2 K1 + c1^2 K2) N, column by column
+  double X[6][3], M[3][3];
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    double hc[6];
+#pragma unroll
+    for (int i = 0; i < 6; ++i) {
+      double a1, a2;
+      if (k == 0) {
+        a1 = kent(A, i, 0) * n[0] + kent(A, i, 4) * s2 + kent(A, i, 5) * s1;
+        a2 = kent(B, i, 0) * n[0] + kent(B, i, 4) * s2 + kent(B, i, 5) * s1;
+      } else if (k == 1) {
+        a1 = kent(A, i, 1) * n[1] + kent(A, i, 3) * s2 + kent(A, i, 5) * s0;
+        a2 = kent(B, i, 1) * n[1] + kent(B, i, 3) * s2 + kent(B, i, 5) * s0;
+      } else {
+        a1 = kent(A, i, 2) * n[2] + kent(A, i, 3) * s1 + kent(A, i, 4) * s0;
+        a2 = kent(B, i, 2) * n[2] + kent(B, i, 3) * s1 + kent(B, i, 4) * s0;
+      }
+      X[i][k] = c2 * a1 - c1 * a2;
+      hc[i] = c2 * c2 * a1 + c1 * c1 * a2;
+    }
+    double mc[3];
+    nt_apply(n, hc, mc);
+#pragma unroll
+    for (int q = 0; q < 3; ++q) M[q][k] = mc[q];
+  }
+  const double* p1 = cond(A);
+  const double* p2 = cond(B);
+  double dv[6], r[3];
+#pragma unroll
+  for (int c = 0; c < 6; ++c) dv[c] = c2 * p1[c] - c1 * p2[c];
+  nt_apply(n, dv, r);
+  if constexpr (PLAIN) {
+    const double* q1 = plain(A);
+    const double* q2 = plain(B);
+    double pv[6], rp[3];
+#pragma unroll
+    for (int c = 0; c < 6; ++c) {
+      pv[c] = c2 * q1[c] - c1 * q2[c];
+      P.s[c] = q1[c] + q2[c];
+    }
+    nt_apply(n, pv, rp);
+    gg += rp[0] * rp[0] + rp[1] * rp[1] + rp[2] * rp[2];
+  }
+  // a subtree without weight on one side has no say in its jump: it stays
+  double Mi[3][3];
+  const bool ok = (c1 * c2 * wsub > 0.0) && inv3(M, Mi);
+  double* sc = node_scr(g, pt, h);
+  double d0[3];
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    d0[k] = ok ? -(Mi[k][0] * r[0] + Mi[k][1] * r[1] + Mi[k][2] * r[2]) : 0.0;
+    sc[18 + k] = d0[k];
+  }
+#pragma unroll
+  for (int i = 0; i < 6; ++i) P.sp[i] = p1[i] + p2[i] + X[i][0] * d0[0] + X[i][1] * d0[1] + X[i][2] * d0[2];
+  // G = -M^-1 X^T one column at a time; K = K1 + K2 + X G
+#pragma unroll
+  for (int q = 0; q < 6; ++q) {
+    double gq[3];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      gq[k] = ok ? -(Mi[k][0] * X[q][0] + Mi[k][1] * X[q][1] + Mi[k][2] * X[q][2]) : 0.0;
+      sc[6 * k + q] = gq[k];
+    }
+#pragma unroll
+    for (int i = 0; i <= q; ++i)
+      P.K[sx(i, q) * ON_LANES] =
+          kent(A, i, q) + kent(B, i, q) + X[i][0] * gq[0] + X[i][1] * gq[1] + X[i][2] * gq[2];
+  }
+}
+
+// children strains of laminate h: eps1 = eps + c2 N a, eps2 = eps - c1 N a
+__device__ __forceinline__ void split(const OnArgs& g, int h, const double* jump, const double* e, double* el,
+                                      double* er) {
+  const double* nt = g.node + ON_NODE * h;
+  const double c1 = nt[3], c2 = 1.0 - c1;
+  double jn[6];
+  n_apply(nt, jump, jn);
+#pragma unroll
+  for (int c = 0; c < 6; ++c) {
+    el[c] = e[c] + c2 * jn[c];
+    er[c] = e[c] - c1 * jn[c];
+  }
+}
+
+// Newton step of node h from the strain change of the node: da = d0 + G deps
+// (kept in the scratch; added to the jump if `update`), and the children's
+// strain changes
+__device__ __forceinline__ void node_step(const OnArgs& g, int pt, int h, const double* de, bool update, double* dl,
+                                          double* dr) {
+  double* sc = node_scr(g, pt, h);
+  double da[3];
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    double x = sc[18 + k];
+#pragma unroll
+    for (int i = 0; i < 6; ++i) x += sc[6 * k + i] * de[i];
+    da[k] = x;
+    sc[21 + k] = x;
+  }
+  if (update) {
+    double* ah = node_jump(g, pt, h);
+#pragma unroll
+    for (int k = 0; k < 3; ++k) ah[k] += da[k];
+  }
+  split(g, h, da, de, dl, dr);
+}
+
+// the register levels of a lane: the subtree of LV levels below node h
+template <int LV>
+struct RegTree {
+  // strains from the jumps, leaves by leaf(l, eps, LeafV&), combination upwards
+  template <bool PLAIN, class LeafFn>
+  static __device__ __forceinline__ void up(const OnArgs& g, int pt, int h, const double* e, NodeV& out, double& gg,
+                                            LeafFn& leaf) {
+    double el[6], er[6];
+    split(g, h, node_jump(g, pt, h), e, el, er);
+    if constexpr (LV == 1) {
+      LeafV A, B;
+      leaf(2 * h - g.nleaf, el, A);
+      leaf(2 * h + 1 - g.nleaf, er, B);
+      combine<PLAIN>(g, pt, h, A, B, out, gg);
+    } else {
+      NodeV B;
+      B.K = out.K + 21 * ON_LANES;  // the next slot
+      RegTree<LV - 1>::template up<PLAIN>(g, pt, 2 * h, el, out, gg, leaf);
+      RegTree<LV - 1>::template up<PLAIN>(g, pt, 2 * h + 1, er, B, gg, leaf);
+      combine<PLAIN>(g, pt, h, out, B, out, gg);
+    }
+  }
+  // leaf strains from the jumps: fn(l, eps)
+  template <class Fn>
+  static __device__ __forceinline__ void down(const OnArgs& g, int pt, int h, const double* e, Fn& fn) {
+    double el[6], er[6];
+    split(g, h, node_jump(g, pt, h), e, el, er);
+    if constexpr (LV == 1) {
+      fn(2 * h - g.nleaf, el);
+      fn(2 * h + 1 - g.nleaf, er);
+    } else {
+      RegTree<LV - 1>::down(g, pt, 2 * h, el, fn);
+      RegTree<LV - 1>::down(g, pt, 2 * h + 1, er, fn);
+    }
+  }
+  // Newton steps from the node's strain change; leaf strain changes: fn(l, deps)
+  template <class Fn>
+  static __device__ __forceinline__ void expand(const OnArgs& g, int pt, int h, const double* de, bool update,
+                                                Fn& fn) {
+    double dl[6], dr[6];
+    node_step(g, pt, h, de, update, dl, dr);
+    if constexpr (LV == 1) {
+      fn(2 * h - g.nleaf, dl);
+      fn(2 * h + 1 - g.nleaf, dr);
+    } else {
+      RegTree<LV - 1>::expand(g, pt, 2 * h, dl, update, fn);
+      RegTree<LV - 1>::expand(g, pt, 2 * h + 1, dr, update, fn);
+    }
+  }
+};
+
+__device__ __forceinline__ double shdown(double v, int d) { return __shfl_down(v, d, ON_LANES); }
+__device__ __forceinline__ double shup(double v, int d) { return __shfl_up(v, d, ON_LANES); }
+
+// sum over the wave, the same value on every lane
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int off = ON_LANES / 2; off >= 1; off >>= 1) v += __shfl_xor(v, off, ON_LANES);
+  return __shfl(v, 0, ON_LANES);
+}
+
+// root strain (E, or 0 for a change) to the lane's depth-S node: shuffle levels,
+// each owner splits its node with `jump(h, jn)`
+template <class JumpFn>
+__device__ __forceinline__ void shuffle_down(const OnArgs& g, int lane, double* e, JumpFn& jump) {
+  const bool act = lane < (1 << g.S);
+  for (int d = 0; d < g.S; ++d) {
+    const int sh = g.S - d, half = 1 << (sh - 1);
+    const int pos = lane & ((1 << sh) - 1);
+    double er[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    if (act && pos == 0) jump((1 << d) + (lane >> sh), e, er);
+#pragma unroll
+    for (int c = 0; c < 6; ++c) {
+      const double t = shup(er[c], half);
+      if (act && pos == half) e[c] = t;
+    }
+  }
+}
+
+// the lane's depth-S node value up to the root (lane 0), combining at every
+// shuffle level: stress sums by shuffles, tangents read from the right
+// child's LDS slot
+template <bool PLAIN>
+__device__ __forceinline__ void shuffle_up(const OnArgs& g, int pt, int lane, NodeV& cur, double& gg) {
+  const bool act = lane < (1 << g.S);
+  for (int d = g.S - 1; d >= 0; --d) {
+    const int sh = g.S - d, half = 1 << (sh - 1);
+    __syncthreads();  // the children's tangents are in their lanes' slots
+    NodeV rb;
+    rb.K = cur.K + half;
+#pragma unroll
+    for (int c = 0; c < 6; ++c) {
+      rb.s[c] = PLAIN ? shdown(cur.s[c], half) : 0.0;
+      rb.sp[c] = shdown(cur.sp[c], half);
+    }
+    if (act && (lane & ((1 << sh) - 1)) == 0) combine<PLAIN>(g, pt, (1 << d) + (lane >> sh), cur, rb, cur, gg);
+  }
+}
+
+// Strains of every leaf at the current jumps (leaves by `leaf`), residual
+// and elimination of the whole tree; root values on lane 0. root.K names the
+// lane's first LDS slot.
+template <int R, bool PLAIN, class LeafFn>
+__device__ __forceinline__ void eval_pass(const OnArgs& g, int pt, int lane, LeafFn& leaf, NodeV& root,
+                                          double& gg) {
+  __syncthreads();  // the slots of the previous sweep have been read
+  double e[6];
+#pragma unroll
+  for (int c = 0; c < 6; ++c) e[c] = lane == 0 ? g.E[6 * pt + c] : 0.0;
+  auto jump = [&](int h, double* ev, double* er) {
+    double el[6];
+    split(g, h, node_jump(g, pt, h), ev, el, er);
+#pragma unroll
+    for (int c = 0; c < 6; ++c) ev[c] = el[c];
+  };
+  shuffle_down(g, lane, e, jump);
+  if constexpr (R == 0) {
+    LeafV L{};
+    if (lane < g.nleaf) leaf(lane, e, L);
+    to_node(L, root);
+  } else {
+    RegTree<R>::template up<PLAIN>(g, pt, (1 << g.S) + lane, e, root, gg, leaf);
+  }
+  shuffle_up<PLAIN>(g, pt, lane, root, gg);
+}
+
+// leaf strains at the current jumps: fn(l, eps)
+template <int R, class Fn>
+__device__ __forceinline__ void strains_pass(const OnArgs& g, int pt, int lane, Fn& fn) {
+  double e[6];
+#pragma unroll
+  for (int c = 0; c < 6; ++c) e[c] = lane == 0 ? g.E[6 * pt + c] : 0.0;
+  auto jump = [&](int h, double* ev, double* er) {
+    double el[6];
+    split(g, h, node_jump(g, pt, h), ev, el, er);
+#pragma unroll
+    for (int c = 0; c < 6; ++c) ev[c] = el[c];
+  };
+  shuffle_down(g, lane, e, jump);
+  if constexpr (R == 0) {
+    if (lane < g.nleaf) fn(lane, e);
+  } else {
+    RegTree<R>::down(g, pt, (1 << g.S) + lane, e, fn);
+  }
+}
+
+// Newton steps of all jumps for a zero root strain change (after eval_pass);
+// the leaf strain changes: fn(l, deps)
+template <int R, class Fn>
+__device__ __forceinline__ void expand_pass(const OnArgs& g, int pt, int lane, bool update, Fn& fn) {
+  double de[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+  auto step = [&](int h, double* dv, double* dr) {
+    double dl[6];
+    node_step(g, pt, h, dv, update, dl, dr);
+#pragma unroll
+    for (int c = 0; c < 6; ++c) dv[c] = dl[c];
+  };
+  shuffle_down(g, lane, de, step);
+  if constexpr (R == 0) {
+    if (lane < g.nleaf) fn(lane, de);
+  } else {
+    RegTree<R>::expand(g, pt, (1 << g.S) + lane, de, update, fn);
+  }
+}
+
+// every internal node the lane owns: fn(h)
+template <int R, class Fn>
+__device__ __forceinline__ void for_owned(const OnArgs& g, int lane, Fn& fn) {
+  if (lane >= (1 << g.S)) return;
+  for (int d = 0; d < g.S; ++d) {
+    const int sh = g.S - d;
+    if ((lane & ((1 << sh) - 1)) == 0) fn((1 << d) + (lane >> sh));
+  }
+  const int h0 = (1 << g.S) + lane;
+#pragma unroll
+  for (int r = 0; r < R; ++r)
+#pragma unroll
+    for (int k = 0; k < (1 << r); ++k) fn((h0 << r) + k);
+}
+
+// effective stress and the full 6 x 6 tangent of the root
+__device__ __forceinline__ void put_root(double* o, const NodeV& root) {
+#pragma unroll
+  for (int c = 0; c < 6; ++c) o[c] = root.s[c];
+#pragma unroll
+  for (int i = 0; i < 6; ++i)
+#pragma unroll
+    for (int j = 0; j < 6; ++j) o[8 + 6 * i + j] = root.K[sx(i, j) * ON_LANES];
+}
+
+// |A^T W sigma| / ((2^K - 1) |sigma_bar|) from the lanes' sums and the root on lane 0
+__device__ __forceinline__ double residual_norm(const OnArgs& g, int lane, const NodeV& root, double gg) {
+  gg = wave_sum(gg);
+  double sb = 0.0;
+#pragma unroll
+  for (int c = 0; c < 6; ++c) sb += root.s[c] * root.s[c];
+  const double r = sqrt(gg) / ((double)(g.nleaf - 1) * fmax(sqrt(sb), 1e-300));
+  return __shfl(r, 0, ON_LANES);
+}
 
 // leaf law: stress and compressed tangent 3K P1 + ca P2 + cb N N
 __device__ void leaf_eval(const OnArgs& g, const ProbInc& in, int pt, int l, const double* e, double* sg,
@@ -765,379 +1174,191 @@ __device__ void leaf_eval(const OnArgs& g, const ProbInc& in, int pt, int l, con
   }
 }
 
-// w C of a leaf into KA: C_IJ = ca d_IJ + (K3 - ca) / 3 [I, J < 3] + cb N_I N_J
-__device__ __forceinline__ void put_leaf_tangent(OnShared& S, int l, double w, double K3, double ca, double cb,
-                                                 const double* nd) {
-  double* Kl = S.KA + 36 * l;
+// point partials of leaf l at its converged strain e, from state n:
+// d sigma / d theta, d D / d eps, d D / d theta (closed form for the
+// thermoelastic phase, central differences of the PA66 update)
+__device__ void leaf_partials(const OnArgs& g, const ProbInc& in, int pt, int l, const double* e, double* st_,
+                              double* gd, double& hd) {
+  const int phase = l & 1;
+  const double* enp = g.epsn + ((long long)g.nleaf * pt + l) * 6;
+  double en[6];
 #pragma unroll
-  for (int i = 0; i < 6; ++i)
+  for (int c = 0; c < 6; ++c) en[c] = enp[c];
+  if (phase == g.pa_phase) {
+    const long long ss = g.nleaf >> 1;
+    const int q = l >> 1;
+    const double* st = g.state + (long long)pt * g.nstate * ss + q;
+    const double* hs = g.hist + (long long)pt * HIST_SLOTS * ss + q;
+    double sp[6], Dp = 0.0;
+    for (int k = 0; k < 14; ++k) {
+      const bool th = k < 2;
+      const ProbInc& ik = th ? g.inc_pm[2 * g.inc_ix[pt] + k] : in;
+      double ek[6];
 #pragma unroll
-    for (int j = 0; j < 6; ++j)
-      Kl[6 * i + j] = w * ((i == j ? ca : 0.0) + (i < 3 && j < 3 ? (K3 - ca) * (1.0 / 3.0) : 0.0) + cb * nd[i] * nd[j]);
-}
-
-__device__ __forceinline__ double node_c1(const OnShared& S, int h) {
-  const double wl = S.wsub[2 * h], wr = S.wsub[2 * h + 1], sw = wl + wr;
-  return sw > 0.0 ? wl / sw : 0.5;
-}
-
-// Residual at the jumps a (block-wide): leaf strains top-down, leaf laws,
-// weighted stress sums bottom-up, |A^T W sigma| / ((2^K - 1) |sigma_bar|).
-// Leaves keep their strain, stress and w C (in KA) for the Newton step.
-__device__ double residual(const OnArgs& g, OnShared& S, const ProbInc& in, int pt, const double* a, double* e,
-                           double* sg) {
-  const int nleaf = g.nleaf;
-  const int tid = threadIdx.x;
-  if (tid == 0)
-    for (int c = 0; c < 6; ++c) S.V[6 + c] = g.E[6 * pt + c];
-  __syncthreads();
-  for (int cnt = 1; cnt < nleaf; cnt <<= 1) {
-    for (int j = tid; j < cnt; j += blockDim.x) {
-      const int h = cnt + j;
-      const double c1 = node_c1(S, h), c2 = 1.0 - c1;
-      double N[6][3];
-      nmat(S.nv + 3 * h, N);
-      const double* ah = a + 3 * h;
+      for (int c = 0; c < 6; ++c) ek[c] = e[c];
+      const int dir = (k - 2) >> 1;
+      if (!th) ek[dir] += (k & 1) ? -FD_H_EPS : FD_H_EPS;
+      PaOut po;
+      double dis, cpl;
+      pa66_point(ik, ek, st, ss, nullptr, en, po, &dis, &cpl, th ? nullptr : hs, nullptr);
+      if (!(k & 1)) {
 #pragma unroll
-      for (int c = 0; c < 6; ++c) {
-        const double j6 = N[c][0] * ah[0] + N[c][1] * ah[1] + N[c][2] * ah[2];
-        S.V[6 * (2 * h) + c] = S.V[6 * h + c] + c2 * j6;
-        S.V[6 * (2 * h + 1) + c] = S.V[6 * h + c] - c1 * j6;
+        for (int c = 0; c < 6; ++c) sp[c] = po.sig[c];
+        Dp = cpl;
+      } else if (th) {
+#pragma unroll
+        for (int c = 0; c < 6; ++c) st_[c] = (sp[c] - po.sig[c]) * (0.5 / FD_H_THETA);
+        hd = (Dp - cpl) * (0.5 / FD_H_THETA);
+      } else {
+        gd[dir] = (Dp - cpl) * (0.5 / FD_H_EPS);
       }
     }
-    __syncthreads();
-  }
-  const int l = tid;
-  const double w = S.wsub[nleaf + l];
+  } else {
+    const PhaseInc& pi = in.ph[phase];
+    const double ca = pi.K3 * pi.alpha0;
+    const double trd = (e[0] - en[0]) + (e[1] - en[1]) + (e[2] - en[2]);
 #pragma unroll
-  for (int c = 0; c < 6; ++c) e[c] = S.V[6 * (nleaf + l) + c];
-  double K3, ca, cb, nd[6];
-  leaf_eval(g, in, pt, l, e, sg, K3, ca, cb, nd);
-  put_leaf_tangent(S, l, w, K3, ca, cb, nd);
-  __syncthreads();
-#pragma unroll
-  for (int c = 0; c < 6; ++c) S.V[6 * (nleaf + l) + c] = w * sg[c];
-  __syncthreads();
-  double gg = 0.0;
-  for (int cnt = nleaf >> 1; cnt >= 1; cnt >>= 1) {
-    for (int j = tid; j < cnt; j += blockDim.x) {
-      const int h = cnt + j;
-      const double c1 = node_c1(S, h), c2 = 1.0 - c1;
-      double N[6][3];
-      nmat(S.nv + 3 * h, N);
-      const double* s1 = S.V + 6 * (2 * h);
-      const double* s2 = S.V + 6 * (2 * h + 1);
-#pragma unroll
-      for (int k = 0; k < 3; ++k) {
-        double r = 0.0;
-#pragma unroll
-        for (int c = 0; c < 6; ++c) r += N[c][k] * (c2 * s1[c] - c1 * s2[c]);
-        gg += r * r;
-      }
-#pragma unroll
-      for (int c = 0; c < 6; ++c) S.V[6 * h + c] = s1[c] + s2[c];
+    for (int c = 0; c < 6; ++c) {
+      st_[c] = c < 3 ? -ca : 0.0;
+      gd[c] = c < 3 ? -in.theta * ca / in.dt : 0.0;
     }
-    __syncthreads();
-  }
-  double r2[1] = {gg};
-  block_sum<1>(r2, S.red);
-  if (tid == 0) {
-    double sb = 0.0;
-    for (int c = 0; c < 6; ++c) sb += S.V[6 + c] * S.V[6 + c];
-    S.res = sqrt(r2[0]) / ((double)(nleaf - 1) * fmax(sqrt(sb), 1e-300));
-  }
-  __syncthreads();
-  return S.res;
-}
-
-// Condensation from the leaves to the root with the leaf tangents in KA and
-// the weighted leaf stresses in V: per node G and da0 (scratch) with
-// da = da0 + G deps; returns with the root's condensed tangent in the buffer
-// it names (KA or KB).
-__device__ double* condense(const OnArgs& g, OnShared& S, int pt) {
-  const int nleaf = g.nleaf;
-  const int tid = threadIdx.x;
-  double* src = S.KA;
-  double* dst = S.KB;
-  double* scr = g.scr + (long long)pt * nleaf * ON_SCR;
-  for (int cnt = nleaf >> 1; cnt >= 1; cnt >>= 1) {
-    for (int j = tid; j < cnt; j += blockDim.x) {
-      const int h = cnt + j;
-      const double c1 = node_c1(S, h), c2 = 1.0 - c1;
-      double N[6][3];
-      nmat(S.nv + 3 * h, N);
-      const double* K1 = src + 36 * (2 * j);
-      const double* K2 = src + 36 * (2 * j + 1);
-      const double* s1 = S.V + 6 * (2 * h);
-      const double* s2 = S.V + 6 * (2 * h + 1);
-      // X = (c2 K1 - c1 K2) N (6 x 3), M = N^T (c2^2 K1 + c1^2 K2) N, r = N^T (c2 s1 - c1 s2)
-      double X[6][3], HN[6][3];
-#pragma unroll
-      for (int i = 0; i < 6; ++i)
-#pragma unroll
-        for (int k = 0; k < 3; ++k) {
-          double x = 0.0, hh = 0.0;
-#pragma unroll
-          for (int q = 0; q < 6; ++q) {
-            const double k1 = K1[6 * i + q], k2 = K2[6 * i + q];
-            x += (c2 * k1 - c1 * k2) * N[q][k];
-            hh += (c2 * c2 * k1 + c1 * c1 * k2) * N[q][k];
-          }
-          X[i][k] = x;
-          HN[i][k] = hh;
-        }
-      double M[3][3], Mi[3][3], r[3];
-#pragma unroll
-      for (int k = 0; k < 3; ++k) {
-        double rr = 0.0;
-#pragma unroll
-        for (int c = 0; c < 6; ++c) rr += N[c][k] * (c2 * s1[c] - c1 * s2[c]);
-        r[k] = rr;
-#pragma unroll
-        for (int q = 0; q < 3; ++q) {
-          double m = 0.0;
-#pragma unroll
-          for (int i = 0; i < 6; ++i) m += N[i][k] * HN[i][q];
-          M[k][q] = m;
-        }
-      }
-      // a subtree without weight on one side has no say in its jump: it stays
-      const bool ok = (c1 * c2 * S.wsub[h] > 0.0) && inv3(M, Mi);
-      double Gm[3][6], d0[3];
-#pragma unroll
-      for (int k = 0; k < 3; ++k) {
-        d0[k] = 0.0;
-#pragma unroll
-        for (int i = 0; i < 6; ++i) Gm[k][i] = 0.0;
-      }
-      if (ok) {
-#pragma unroll
-        for (int k = 0; k < 3; ++k) {
-          d0[k] = -(Mi[k][0] * r[0] + Mi[k][1] * r[1] + Mi[k][2] * r[2]);
-#pragma unroll
-          for (int i = 0; i < 6; ++i) Gm[k][i] = -(Mi[k][0] * X[i][0] + Mi[k][1] * X[i][1] + Mi[k][2] * X[i][2]);
-        }
-      }
-      double* sc = scr + (long long)h * ON_SCR;
-#pragma unroll
-      for (int k = 0; k < 3; ++k) {
-        sc[18 + k] = d0[k];
-#pragma unroll
-        for (int i = 0; i < 6; ++i) sc[6 * k + i] = Gm[k][i];
-      }
-      // parent: s = s1 + s2 + X d0, K = K1 + K2 + X G
-      double sp[6];
-#pragma unroll
-      for (int i = 0; i < 6; ++i) sp[i] = s1[i] + s2[i] + X[i][0] * d0[0] + X[i][1] * d0[1] + X[i][2] * d0[2];
-      double* Kp = dst + 36 * j;
-#pragma unroll
-      for (int i = 0; i < 6; ++i)
-#pragma unroll
-        for (int q = 0; q < 6; ++q)
-          Kp[6 * i + q] = K1[6 * i + q] + K2[6 * i + q] + X[i][0] * Gm[0][q] + X[i][1] * Gm[1][q] + X[i][2] * Gm[2][q];
-#pragma unroll
-      for (int i = 0; i < 6; ++i) S.V[6 * h + i] = sp[i];
-    }
-    __syncthreads();
-    double* t = src;
-    src = dst;
-    dst = t;
-  }
-  return src;
-}
-
-// da from the root down (deps_root = 0), into S.da (heap index); the strain
-// changes of every node and leaf into V
-__device__ void expand(const OnArgs& g, OnShared& S, int pt) {
-  const int nleaf = g.nleaf;
-  const int tid = threadIdx.x;
-  const double* scr = g.scr + (long long)pt * nleaf * ON_SCR;
-  if (tid == 0)
-    for (int c = 0; c < 6; ++c) S.V[6 + c] = 0.0;
-  __syncthreads();
-  for (int cnt = 1; cnt < nleaf; cnt <<= 1) {
-    for (int j = tid; j < cnt; j += blockDim.x) {
-      const int h = cnt + j;
-      const double c1 = node_c1(S, h), c2 = 1.0 - c1;
-      const double* sc = scr + (long long)h * ON_SCR;
-      const double* de = S.V + 6 * h;
-      double d[3];
-#pragma unroll
-      for (int k = 0; k < 3; ++k) {
-        double x = sc[18 + k];
-#pragma unroll
-        for (int i = 0; i < 6; ++i) x += sc[6 * k + i] * de[i];
-        d[k] = x;
-        S.da[3 * h + k] = x;
-      }
-      double N[6][3];
-      nmat(S.nv + 3 * h, N);
-#pragma unroll
-      for (int c = 0; c < 6; ++c) {  // children, the leaves included
-        const double j6 = N[c][0] * d[0] + N[c][1] * d[1] + N[c][2] * d[2];
-        S.V[6 * (2 * h) + c] = de[c] + c2 * j6;
-        S.V[6 * (2 * h + 1) + c] = de[c] - c1 * j6;
-      }
-    }
-    __syncthreads();
+    hd = -ca * trd / in.dt;
   }
 }
 
-__global__ void __launch_bounds__(1 << ON_MAX_K) k_dmn_online(OnArgs g) {
-  __shared__ OnShared S;
+template <int R>
+__global__ void __launch_bounds__(ON_LANES) k_dmn_online(OnArgs g) {
+  // condensed tangents: one slot per register level (at least one), lane-interleaved
+  __shared__ double kslot[(R > 0 ? R : 1) * 21 * ON_LANES];
   const int pt = blockIdx.x;
+  const int lane = threadIdx.x;
   const int nleaf = g.nleaf;
-  const int tid = threadIdx.x;
-  const ProbInc& in = g.inc[pt];
-  // weights and directions
-  const double* v = g.p + 3 * (nleaf - 1);
-  S.wsub[nleaf + tid] = fmax(v[tid], 0.0);
-  __syncthreads();
-  for (int cnt = nleaf >> 1; cnt >= 1; cnt >>= 1) {
-    for (int j = tid; j < cnt; j += blockDim.x) {
-      const int h = cnt + j;
-      S.wsub[h] = S.wsub[2 * h] + S.wsub[2 * h + 1];
-      double len;
-      unit(g.p + 3 * param_of(h, nleaf), S.nv + 3 * h, len);
-    }
-    __syncthreads();
-  }
-  // branch history sums of the PA66 leaves for this increment
-  if ((tid & 1) == g.pa_phase) {
+  constexpr int LPT = 1 << R;  // leaves per lane
+  const int ix = g.inc_ix[pt];
+  const ProbInc& in = g.inc[ix];
+  const bool leaves = lane * LPT < nleaf;
+  // branch history sums of this lane's PA66 leaves for this increment
+  if (leaves && g.pa_phase >= 0) {
     const long long ss = nleaf >> 1;
-    const int q = tid >> 1;
-    double hd[6], hs;
-    pa66_history(in, g.state + (long long)pt * g.nstate * ss + q, ss, hd, hs);
-    double* h = g.hist + (long long)pt * HIST_SLOTS * ss + q;
 #pragma unroll
-    for (int c = 0; c < 6; ++c) h[c * ss] = hd[c];
-    h[6 * ss] = hs;
-    h[7 * ss] = -1.0;
+    for (int i = 0; i < LPT; ++i) {
+      const int l = lane * LPT + i;
+      if ((l & 1) != g.pa_phase) continue;
+      const int q = l >> 1;
+      double hd[6], hs;
+      pa66_history(in, g.state + (long long)pt * g.nstate * ss + q, ss, hd, hs);
+      double* h = g.hist + (long long)pt * HIST_SLOTS * ss + q;
+#pragma unroll
+      for (int c = 0; c < 6; ++c) h[c * ss] = hd[c];
+      h[6 * ss] = hs;
+      h[7 * ss] = -1.0;
+    }
   }
-  __syncthreads();
-  double* a = g.a + (long long)pt * nleaf * 3;  // heap index, jumps of the last increment
-  double e[6], sg[6];
-  double res = residual(g, S, in, pt, a, e, sg);
+  auto wleaf = [&](int l) { return g.node[ON_NODE * (nleaf + l) + 4]; };
+  auto law = [&](int l, const double* e, LeafV& L) {
+    double sg[6];
+    leaf_eval(g, in, pt, l, e, sg, L.K3, L.ca, L.cb, L.nd);
+    L.w = wleaf(l);
+#pragma unroll
+    for (int c = 0; c < 6; ++c) L.s[c] = L.w * sg[c];
+  };
+  NodeV root;
+  root.K = kslot + lane;
+  double gg = 0.0;
+  eval_pass<R, true>(g, pt, lane, law, root, gg);
+  double res = residual_norm(g, lane, root, gg);
+  auto nothing = [](int, const double*) {};
   int it = 0;
   for (it = 1; it <= g.maxit; ++it) {
-    condense(g, S, pt);
-    expand(g, S, pt);
+    expand_pass<R>(g, pt, lane, true, nothing);
     const double res_old = res;
-    for (int h = tid + 1; h < nleaf; h += blockDim.x)
-#pragma unroll
-      for (int k = 0; k < 3; ++k) a[3 * h + k] += S.da[3 * h + k];
-    __syncthreads();
-    res = residual(g, S, in, pt, a, e, sg);
+    gg = 0.0;
+    eval_pass<R, true>(g, pt, lane, law, root, gg);
+    res = residual_norm(g, lane, root, gg);
     for (int i = 0; i < g.maxbt; ++i) {  // backtracking: steps 1, gamma, gamma^2, ...
       if (res < res_old) break;
       const double cut = pow(g.gamma, (double)i) * (1.0 - g.gamma);
-      for (int h = tid + 1; h < nleaf; h += blockDim.x)
+      auto back = [&](int h) {
+        double* ah = node_jump(g, pt, h);
+        const double* sc = node_scr(g, pt, h);
 #pragma unroll
-        for (int k = 0; k < 3; ++k) a[3 * h + k] -= cut * S.da[3 * h + k];
-      __syncthreads();
-      res = residual(g, S, in, pt, a, e, sg);
+        for (int k = 0; k < 3; ++k) ah[k] -= cut * sc[21 + k];
+      };
+      for_owned<R>(g, lane, back);
+      gg = 0.0;
+      eval_pass<R, true>(g, pt, lane, law, root, gg);
+      res = residual_norm(g, lane, root, gg);
     }
     if (res < g.tol) break;
   }
   const bool conv = res < g.tol;
   const bool commit = conv && !g.trial;
   if (it > g.maxit) it = g.maxit;
-  // effective stress (V[1] after the last residual), tangent by a final
-  // condensation at the converged state
+  // effective stress and tangent: the root of the last sweep
   double* o = g.out + (long long)pt * ON_OUT;
-  if (tid == 0)
-    for (int c = 0; c < 6; ++c) o[c] = S.V[6 + c];
-  __syncthreads();
-  double* Kroot = condense(g, S, pt);
-  for (int i = tid; i < 36; i += blockDim.x) o[8 + i] = Kroot[i];
-  __syncthreads();
+  if (lane == 0) put_root(o, root);
   if (g.what) {
-    // point partials of every leaf at its converged strain, from state n:
-    // d sigma / d theta, d D / d eps, d D / d theta (closed form for the
-    // thermoelastic phase, central differences of the PA66 update)
-    const int l = tid;
-    const int phase = l & 1;
-    const double* enp = g.epsn + ((long long)pt * nleaf + l) * 6;
-    double en[6], st_[6], gd[6], hd;
-#pragma unroll
-    for (int c = 0; c < 6; ++c) en[c] = enp[c];
-    if (phase == g.pa_phase) {
-      const long long ss = nleaf >> 1;
-      const int q = l >> 1;
-      const double* st = g.state + (long long)pt * g.nstate * ss + q;
-      const double* hs = g.hist + (long long)pt * HIST_SLOTS * ss + q;
-      double sp[6], Dp = 0.0;
-      for (int k = 0; k < 14; ++k) {
-        const bool th = k < 2;
-        const ProbInc& ik = th ? g.inc_pm[2 * pt + k] : in;
-        double ek[6];
-#pragma unroll
-        for (int c = 0; c < 6; ++c) ek[c] = e[c];
-        const int dir = (k - 2) >> 1;
-        if (!th) ek[dir] += (k & 1) ? -FD_H_EPS : FD_H_EPS;
-        PaOut po;
-        double dis, cpl;
-        pa66_point(ik, ek, st, ss, nullptr, en, po, &dis, &cpl, th ? nullptr : hs, nullptr);
-        if (!(k & 1)) {
-#pragma unroll
-          for (int c = 0; c < 6; ++c) sp[c] = po.sig[c];
-          Dp = cpl;
-        } else if (th) {
-#pragma unroll
-          for (int c = 0; c < 6; ++c) st_[c] = (sp[c] - po.sig[c]) * (0.5 / FD_H_THETA);
-          hd = (Dp - cpl) * (0.5 / FD_H_THETA);
-        } else {
-          gd[dir] = (Dp - cpl) * (0.5 / FD_H_EPS);
-        }
-      }
-    } else {
-      const PhaseInc& pi = in.ph[phase];
-      const double ca = pi.K3 * pi.alpha0;
-      const double trd = (e[0] - en[0]) + (e[1] - en[1]) + (e[2] - en[2]);
+    auto partials = [&](int l, const double* e) {
+      double st_[6], gd[6], hd;
+      leaf_partials(g, in, pt, l, e, st_, gd, hd);
+      double* lp = g.lp + ((long long)pt * nleaf + l) * ON_LP;
 #pragma unroll
       for (int c = 0; c < 6; ++c) {
-        st_[c] = c < 3 ? -ca : 0.0;
-        gd[c] = c < 3 ? -in.theta * ca / in.dt : 0.0;
+        lp[c] = st_[c];
+        lp[6 + c] = gd[c];
       }
-      hd = -ca * trd / in.dt;
-    }
-    const double wl = S.wsub[nleaf + l];
-    double K3, ca, cb, nd[6], sgl[6];
-    leaf_eval(g, in, pt, l, e, sgl, K3, ca, cb, nd);
+      lp[12] = hd;
+    };
+    strains_pass<R>(g, pt, lane, partials);
     // d<sigma>/dtheta: the jumps equilibrate the leaf sources w dsigma/dtheta
-    put_leaf_tangent(S, l, wl, K3, ca, cb, nd);
+    auto src_theta = [&](int l, const double* e, LeafV& L) {
+      const double* lp = g.lp + ((long long)pt * nleaf + l) * ON_LP;
+      double sg[6];
+      leaf_eval(g, in, pt, l, e, sg, L.K3, L.ca, L.cb, L.nd);
+      L.w = wleaf(l);
 #pragma unroll
-    for (int c = 0; c < 6; ++c) S.V[6 * (nleaf + l) + c] = wl * st_[c];
-    __syncthreads();
-    condense(g, S, pt);
-    if (tid == 0)
-      for (int c = 0; c < 6; ++c) o[O_DSDT + c] = S.V[6 + c];
-    __syncthreads();
-    expand(g, S, pt);  // the leaf strains' derivatives d eps / d theta
-    double dT = wl * hd;
+      for (int c = 0; c < 6; ++c) L.s[c] = L.w * lp[c];
+    };
+    NodeV rt;
+    rt.K = kslot + lane;
+    double unused = 0.0;
+    eval_pass<R, false>(g, pt, lane, src_theta, rt, unused);
+    if (lane == 0)
 #pragma unroll
-    for (int c = 0; c < 6; ++c) dT += wl * gd[c] * S.V[6 * (nleaf + l) + c];
-    double r1[1] = {dT};
-    block_sum<1>(r1, S.red);
-    if (tid == 0) o[O_DDDT] = r1[0];
-    __syncthreads();
+      for (int c = 0; c < 6; ++c) o[O_DSDT + c] = rt.sp[c];
+    // d<D>/dtheta = sum_l w_l (dD/dtheta_l + dD/deps_l . d eps_l / d theta)
+    double dT = 0.0;
+    auto heat = [&](int l, const double* de) {
+      const double* lp = g.lp + ((long long)pt * nleaf + l) * ON_LP;
+      double x = lp[12];
+#pragma unroll
+      for (int c = 0; c < 6; ++c) x += lp[6 + c] * de[c];
+      dT += wleaf(l) * x;
+    };
+    expand_pass<R>(g, pt, lane, false, heat);
+    dT = wave_sum(dT);
+    if (lane == 0) o[O_DDDT] = dT;
     // d<D>/dE = sum_l w_l (d eps_l / dE)^T dD/deps_l: the condensed value of
     // the leaf sources w dD/deps (the localization is symmetric in this sense)
-    put_leaf_tangent(S, l, wl, K3, ca, cb, nd);
+    auto src_coup = [&](int l, const double* e, LeafV& L) {
+      const double* lp = g.lp + ((long long)pt * nleaf + l) * ON_LP;
+      double sg[6];
+      leaf_eval(g, in, pt, l, e, sg, L.K3, L.ca, L.cb, L.nd);
+      L.w = wleaf(l);
 #pragma unroll
-    for (int c = 0; c < 6; ++c) S.V[6 * (nleaf + l) + c] = wl * gd[c];
-    __syncthreads();
-    condense(g, S, pt);
-    if (tid == 0)
-      for (int c = 0; c < 6; ++c) o[O_DDDE + c] = S.V[6 + c];
-    __syncthreads();
+      for (int c = 0; c < 6; ++c) L.s[c] = L.w * lp[6 + c];
+    };
+    eval_pass<R, false>(g, pt, lane, src_coup, rt, unused);
+    if (lane == 0)
+#pragma unroll
+      for (int c = 0; c < 6; ++c) o[O_DDDE + c] = rt.sp[c];
   }
   // coupling term and dissipation of every leaf; commit if converged
   double D = 0.0, Dd = 0.0;
-  {
-    const int l = tid;
+  auto fin = [&](int l, const double* e) {
     const int phase = l & 1;
-    const double* en = g.epsn + ((long long)pt * nleaf + l) * 6;
+    double* en = g.epsn + ((long long)pt * nleaf + l) * 6;
+    double Dl = 0.0, Ddl = 0.0;
     if (phase == g.pa_phase) {
       const long long ss = nleaf >> 1;
       const int q = l >> 1;
@@ -1147,24 +1368,25 @@ __global__ void __launch_bounds__(1 << ON_MAX_K) k_dmn_online(OnArgs g) {
 #pragma unroll
       for (int c = 0; c < 6; ++c) enl[c] = en[c];
       PaOut po;
-      pa66_point(in, e, st, ss, commit ? st : nullptr, enl, po, &Dd, &D, hs, nullptr);
+      pa66_point(in, e, st, ss, commit ? st : nullptr, enl, po, &Ddl, &Dl, hs, nullptr);
     } else {
       const PhaseInc& pi = in.ph[phase];
       const double trd = (e[0] - en[0]) + (e[1] - en[1]) + (e[2] - en[2]);
-      D = -in.theta * pi.K3 * pi.alpha0 * trd / in.dt;
+      Dl = -in.theta * pi.K3 * pi.alpha0 * trd / in.dt;
     }
-  }
-  const double w = S.wsub[nleaf + tid];
-  double r2[2] = {w * D, w * Dd};
-  block_sum<2>(r2, S.red);
-  if (commit) {
-    double* en = g.epsn + ((long long)pt * nleaf + tid) * 6;
+    const double w = wleaf(l);
+    D += w * Dl;
+    Dd += w * Ddl;
+    if (commit)
 #pragma unroll
-    for (int c = 0; c < 6; ++c) en[c] = e[c];
-  }
-  if (tid == 0) {
-    o[6] = r2[0];
-    o[7] = r2[1];
+      for (int c = 0; c < 6; ++c) en[c] = e[c];
+  };
+  strains_pass<R>(g, pt, lane, fin);
+  D = wave_sum(D);
+  Dd = wave_sum(Dd);
+  if (lane == 0) {
+    o[6] = D;
+    o[7] = Dd;
     o[O_RES] = res;
     o[O_IT] = it;
     o[O_ST] = conv ? 1.0 : 0.0;
@@ -1173,18 +1395,30 @@ __global__ void __launch_bounds__(1 << ON_MAX_K) k_dmn_online(OnArgs g) {
 
 }  // namespace
 
+struct PairHash {
+  size_t operator()(const std::pair<uint64_t, uint64_t>& k) const {
+    return std::hash<uint64_t>()(k.first * 0x9E3779B97F4A7C15ull ^ k.second);
+  }
+};
+
 struct DmnOnline {
   int K, nleaf, npoints, nstate = 0, pa_phase = -1;
   double tol;
   int maxit;
   std::vector<hom_law> laws;
   std::vector<void*> allocs;
-  double *p = nullptr, *state = nullptr, *hist = nullptr, *epsn = nullptr, *a = nullptr, *scr = nullptr;
-  double *E = nullptr, *out = nullptr;
+  double *p = nullptr, *node = nullptr, *state = nullptr, *hist = nullptr, *epsn = nullptr, *a = nullptr;
+  double *scr = nullptr, *lp = nullptr, *E = nullptr, *out = nullptr;
   ProbInc *inc = nullptr, *inc_pm = nullptr;
+  int* inc_ix = nullptr;
   std::vector<ProbInc> inc_h, inc_pm_h;
+  // pinned staging of the per-point inputs and outputs
+  double *E_h = nullptr, *out_h = nullptr;
+  int* ix_h = nullptr;
   ~DmnOnline() {
     for (void* ptr : allocs) (void)hipFree(ptr);
+    for (void* ptr : {(void*)E_h, (void*)out_h, (void*)ix_h})
+      if (ptr) (void)hipHostFree(ptr);
   }
 };
 
@@ -1211,6 +1445,9 @@ DmnOnline* dmn_online_create(const Dmn& net, const hom_law* laws, int npoints, d
   const size_t half = (size_t)o->nleaf / 2;
   o->p = dalloc_into<double>(o->allocs, net.nparam);
   hip_check(hipMemcpy(o->p, net.p, net.nparam * sizeof(double), hipMemcpyDeviceToDevice), "hipMemcpy");
+  o->node = dalloc_into<double>(o->allocs, (size_t)2 * o->nleaf * ON_NODE);
+  hipLaunchKernelGGL(k_dmn_node_table, dim3(1), dim3(1), 0, nullptr, o->p, o->nleaf, o->node);
+  hip_check(hipGetLastError(), "k_dmn_node_table");
   if (o->nstate) {
     o->state = dalloc_into<double>(o->allocs, (size_t)npoints * o->nstate * half);
     o->hist = dalloc_into<double>(o->allocs, (size_t)npoints * HIST_SLOTS * half);
@@ -1218,12 +1455,17 @@ DmnOnline* dmn_online_create(const Dmn& net, const hom_law* laws, int npoints, d
   o->epsn = dalloc_into<double>(o->allocs, (size_t)npoints * o->nleaf * 6);
   o->a = dalloc_into<double>(o->allocs, (size_t)npoints * o->nleaf * 3);
   o->scr = dalloc_into<double>(o->allocs, (size_t)npoints * o->nleaf * ON_SCR);
+  o->lp = dalloc_into<double>(o->allocs, (size_t)npoints * o->nleaf * ON_LP);
   o->E = dalloc_into<double>(o->allocs, (size_t)npoints * 6);
   o->out = dalloc_into<double>(o->allocs, (size_t)npoints * ON_OUT);
   o->inc = dalloc_into<ProbInc>(o->allocs, npoints);
   o->inc_pm = dalloc_into<ProbInc>(o->allocs, 2 * (size_t)npoints);
-  o->inc_h.resize(npoints);
-  o->inc_pm_h.resize(2 * (size_t)npoints);
+  o->inc_ix = dalloc_into<int>(o->allocs, npoints);
+  o->inc_h.reserve(npoints);
+  o->inc_pm_h.reserve(2 * (size_t)npoints);
+  hip_check(hipHostMalloc((void**)&o->E_h, (size_t)npoints * 6 * sizeof(double)), "hipHostMalloc");
+  hip_check(hipHostMalloc((void**)&o->out_h, (size_t)npoints * ON_OUT * sizeof(double)), "hipHostMalloc");
+  hip_check(hipHostMalloc((void**)&o->ix_h, (size_t)npoints * sizeof(int)), "hipHostMalloc");
   return o.release();
 }
 
@@ -1236,31 +1478,59 @@ void dmn_online_step(DmnOnline* o, const double* strain, const double* theta, co
   const int n = o->npoints;
   const double sq2 = std::sqrt(2.0);
   const double w[6] = {1, 1, 1, sq2, sq2, sq2};
-  std::vector<double> E(6 * n);
+  // one increment record per distinct (theta, dt): points of one macroscopic
+  // step usually share both
+  o->inc_h.clear();
+  o->inc_pm_h.clear();
+  std::unordered_map<std::pair<uint64_t, uint64_t>, int, PairHash> seen;
+  double last_t = NAN, last_d = NAN;
+  int last_ix = -1;
   for (int i = 0; i < n; ++i) {
     if (!(dt[i] > 0.0) || !std::isfinite(dt[i])) fail(HOM_E_ARG, "dt must be positive and finite");
     if (!(theta[i] > 0.0) || !std::isfinite(theta[i])) fail(HOM_E_ARG, "theta must be positive");
     for (int c = 0; c < 6; ++c) {
       if (!std::isfinite(strain[6 * i + c])) fail(HOM_E_ARG, "macro strain must be finite");
-      E[6 * i + c] = w[c] * strain[6 * i + c];
+      o->E_h[6 * i + c] = w[c] * strain[6 * i + c];
     }
-    fill_inc(o->inc_h[i], o->laws, theta[i], dt[i]);
-    if (what) {
-      fill_inc(o->inc_pm_h[2 * i], o->laws, theta[i] + FD_H_THETA, dt[i]);
-      fill_inc(o->inc_pm_h[2 * i + 1], o->laws, theta[i] - FD_H_THETA, dt[i]);
+    if (theta[i] != last_t || dt[i] != last_d) {
+      uint64_t kt, kd;
+      std::memcpy(&kt, &theta[i], 8);
+      std::memcpy(&kd, &dt[i], 8);
+      auto it = seen.find({kt, kd});
+      if (it != seen.end()) {
+        last_ix = it->second;
+      } else {
+        last_ix = (int)o->inc_h.size();
+        seen.emplace(std::make_pair(kt, kd), last_ix);
+        o->inc_h.emplace_back();
+        fill_inc(o->inc_h.back(), o->laws, theta[i], dt[i]);
+        if (what) {
+          o->inc_pm_h.emplace_back();
+          fill_inc(o->inc_pm_h.back(), o->laws, theta[i] + FD_H_THETA, dt[i]);
+          o->inc_pm_h.emplace_back();
+          fill_inc(o->inc_pm_h.back(), o->laws, theta[i] - FD_H_THETA, dt[i]);
+        }
+      }
+      last_t = theta[i];
+      last_d = dt[i];
     }
+    o->ix_h[i] = last_ix;
   }
+  const size_t nu = o->inc_h.size();
   if (what)
-    hip_check(hipMemcpy(o->inc_pm, o->inc_pm_h.data(), 2 * n * sizeof(ProbInc), hipMemcpyHostToDevice),
+    hip_check(hipMemcpy(o->inc_pm, o->inc_pm_h.data(), 2 * nu * sizeof(ProbInc), hipMemcpyHostToDevice),
               "hipMemcpy");
-  hip_check(hipMemcpy(o->E, E.data(), 6 * n * sizeof(double), hipMemcpyHostToDevice), "hipMemcpy");
-  hip_check(hipMemcpy(o->inc, o->inc_h.data(), n * sizeof(ProbInc), hipMemcpyHostToDevice), "hipMemcpy");
+  hip_check(hipMemcpy(o->inc, o->inc_h.data(), nu * sizeof(ProbInc), hipMemcpyHostToDevice), "hipMemcpy");
+  hip_check(hipMemcpy(o->inc_ix, o->ix_h, n * sizeof(int), hipMemcpyHostToDevice), "hipMemcpy");
+  hip_check(hipMemcpy(o->E, o->E_h, 6 * n * sizeof(double), hipMemcpyHostToDevice), "hipMemcpy");
   OnArgs g{};
   g.K = o->K;
   g.nleaf = o->nleaf;
-  g.p = o->p;
+  g.S = std::min(o->K, ON_SHUF);
+  g.node = o->node;
   g.inc = o->inc;
   g.inc_pm = o->inc_pm;
+  g.inc_ix = o->inc_ix;
   g.what = what;
   g.trial = trial;
   g.pa_phase = o->pa_phase;
@@ -1270,19 +1540,29 @@ void dmn_online_step(DmnOnline* o, const double* strain, const double* theta, co
   g.epsn = o->epsn;
   g.a = o->a;
   g.scr = o->scr;
+  g.lp = o->lp;
   g.E = o->E;
   g.out = o->out;
   g.tol = o->tol;
   g.gamma = 0.5;
   g.maxit = o->maxit;
   g.maxbt = 8;
-  static_assert(sizeof(OnShared) <= 160 * 1024, "online DMN work-group does not fit the LDS");
-  hipLaunchKernelGGL(k_dmn_online, dim3(n), dim3(o->nleaf), 0, nullptr, g);
+  static_assert(ON_MAX_K - ON_SHUF <= 2, "at most two register levels per lane");
+  switch (o->K - g.S) {  // register levels below the shuffle levels
+    case 0:
+      hipLaunchKernelGGL(k_dmn_online<0>, dim3(n), dim3(ON_LANES), 0, nullptr, g);
+      break;
+    case 1:
+      hipLaunchKernelGGL(k_dmn_online<1>, dim3(n), dim3(ON_LANES), 0, nullptr, g);
+      break;
+    default:
+      hipLaunchKernelGGL(k_dmn_online<2>, dim3(n), dim3(ON_LANES), 0, nullptr, g);
+      break;
+  }
   hip_check(hipGetLastError(), "k_dmn_online");
-  std::vector<double> out((size_t)ON_OUT * n);
-  hip_check(hipMemcpy(out.data(), o->out, out.size() * sizeof(double), hipMemcpyDeviceToHost), "hipMemcpy");
+  hip_check(hipMemcpy(o->out_h, o->out, (size_t)ON_OUT * n * sizeof(double), hipMemcpyDeviceToHost), "hipMemcpy");
   for (int i = 0; i < n; ++i) {
-    const double* r = out.data() + (size_t)ON_OUT * i;
+    const double* r = o->out_h + (size_t)ON_OUT * i;
     hom_dmn_result& t = res[i];
     std::memset(&t, 0, sizeof(t));
     for (int c = 0; c < 6; ++c) t.stress[c] = r[c] / w[c];

@@ -157,6 +157,16 @@ class DmnResult(ct.Structure):
                     newton_iters=self.newton_iters, status=self.status)
 
 
+# hom_dmn_result as a numpy record (same layout): DmnOnline.step fills an array
+# of these in place, so results[i]["stress"], results["dsde"] etc. need no copy
+DMN_RESULT_DTYPE = np.dtype([
+    ("stress", "<f8", (6,)), ("coupling", "<f8"), ("dissipation", "<f8"), ("dsde", "<f8", (6, 6)),
+    ("dsdt", "<f8", (6,)), ("dDde", "<f8", (6,)), ("dDdt", "<f8"), ("residual", "<f8"),
+    ("newton_iters", "<i4"), ("status", "<i4"),
+])
+assert DMN_RESULT_DTYPE.itemsize == ct.sizeof(DmnResult)
+
+
 EXPORTS = (
     "hom_default_options", "hom_setup", "hom_solve_increment", "hom_state_size", "hom_get_state",
     "hom_set_state", "hom_get_field", "hom_kernel_stats", "hom_set_profiling", "hom_device_bytes",
@@ -796,11 +806,13 @@ class DmnOnline:
             pass
 
     def step(self, strains, thetas, dts, what=0, trial=False):
+        """One increment at every point (theta, dt scalar or per point). Returns a
+        record array of DMN_RESULT_DTYPE, one record per point."""
         e = _f64(strains).reshape(self.n, 6)
         t = _f64(np.broadcast_to(thetas, (self.n,)))
         d = _f64(np.broadcast_to(dts, (self.n,)))
-        out = (DmnResult * self.n)()
+        out = np.empty(self.n, dtype=DMN_RESULT_DTYPE)
         _check(self._lib.hom_dmn_online_step(self._h, _dptr(e), _dptr(t), _dptr(d), int(what), int(bool(trial)),
-                                             out),
+                                             out.ctypes.data_as(ct.POINTER(DmnResult))),
                lambda: self._lib.hom_dmn_online_last_error(self._h).decode())
-        return [r.as_dict() for r in out]
+        return out

@@ -71,6 +71,14 @@ def test_struct_layout(tmp_path):
             assert getattr(cls, fname).offset == got[(cname, fname)], (cname, fname)
 
 
+def test_dmn_result_record_matches_the_struct():
+    """DmnOnline.step hands the library a numpy record array of this dtype."""
+    dt = hom.DMN_RESULT_DTYPE
+    assert dt.itemsize == ct.sizeof(hom.DmnResult)
+    for name, _ in hom.DmnResult._fields_:
+        assert dt.fields[name][1] == getattr(hom.DmnResult, name).offset, name
+
+
 def test_missing_library_raises(monkeypatch, tmp_path):
     monkeypatch.setattr(hom, "_lib", None)
     with pytest.raises(hom.HomError):
