@@ -191,41 +191,57 @@ __device__ void lam_bwd(const double* C1, const double* C2, double c1, const dou
   for (int i = 0; i < 6; ++i)
 #pragma unroll
     for (int k = 0; k < 3; ++k) GM[i][k] = G[i][0] * Mi[0][k] + G[i][1] * Mi[1][k] + G[i][2] * Mi[2][k];
-  // C = c1 C1 + c2 C2 - cc X, X = G Mi G^T
+  // C = c1 C1 + c2 C2 - cc X, X = G Mi G^T = GM G^T. With T = Cb G:
+  //   <Cb, X> = <GM, T>, dJ/dMi = -cc G^T T, dJ/dG = -cc (Cb + Cb^T) GM,
+  // one row of Cb at a time
   double dx = 0.0, dd = 0.0;  // <Cb, X>, <Cb, C1 - C2>
-  double Gb[6][3];            // dJ/dG = -cc (Cb + Cb^T) G Mi
+  double Gb[6][3], T[6][3];
 #pragma unroll
   for (int i = 0; i < 6; ++i)
 #pragma unroll
     for (int k = 0; k < 3; ++k) Gb[i][k] = 0.0;
-  double Mib[3][3];           // dJ/dMi = -cc G^T Cb G
+#pragma unroll
+  for (int i = 0; i < 6; ++i) {
+    double cr[6];
+#pragma unroll
+    for (int j = 0; j < 6; ++j) {
+      cr[j] = Cb[6 * i + j];
+      dd += cr[j] * (C1[6 * i + j] - C2[6 * i + j]);
+    }
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      double t = 0.0, u = 0.0;
+#pragma unroll
+      for (int j = 0; j < 6; ++j) {
+        t += cr[j] * G[j][k];
+        u += cr[j] * GM[j][k];
+        Gb[j][k] -= cc * cr[j] * GM[i][k];  // (Cb^T GM)[j][k]
+      }
+      T[i][k] = t;
+      Gb[i][k] -= cc * u;  // (Cb GM)[i][k]
+      dx += GM[i][k] * t;
+    }
+  }
+  double Mib[3][3];
 #pragma unroll
   for (int k = 0; k < 3; ++k)
 #pragma unroll
-    for (int l = 0; l < 3; ++l) Mib[k][l] = 0.0;
-  for (int i = 0; i < 6; ++i)
-    for (int j = 0; j < 6; ++j) {
-      const double cb = Cb[6 * i + j];
-      const double cbs = cb + Cb[6 * j + i];
-      dx += cb * (GM[i][0] * G[j][0] + GM[i][1] * G[j][1] + GM[i][2] * G[j][2]);
-      dd += cb * (C1[6 * i + j] - C2[6 * i + j]);
+    for (int l = 0; l < 3; ++l) {
+      double m = 0.0;
 #pragma unroll
-      for (int k = 0; k < 3; ++k) Gb[i][k] -= cc * cbs * GM[j][k];
-#pragma unroll
-      for (int k = 0; k < 3; ++k)
-#pragma unroll
-        for (int l = 0; l < 3; ++l) Mib[k][l] -= cc * G[i][k] * cb * G[j][l];
+      for (int i = 0; i < 6; ++i) m += G[i][k] * T[i][l];
+      Mib[k][l] = -cc * m;
     }
   // Mi = M^-1: Mb = -Mi Mib Mi (Mi symmetric)
-  double T[3][3], Mb[3][3];
+  double W[3][3], Mb[3][3];
 #pragma unroll
   for (int k = 0; k < 3; ++k)
 #pragma unroll
-    for (int l = 0; l < 3; ++l) T[k][l] = Mib[k][0] * Mi[0][l] + Mib[k][1] * Mi[1][l] + Mib[k][2] * Mi[2][l];
+    for (int l = 0; l < 3; ++l) W[k][l] = Mib[k][0] * Mi[0][l] + Mib[k][1] * Mi[1][l] + Mib[k][2] * Mi[2][l];
 #pragma unroll
   for (int k = 0; k < 3; ++k)
 #pragma unroll
-    for (int l = 0; l < 3; ++l) Mb[k][l] = -(Mi[k][0] * T[0][l] + Mi[k][1] * T[1][l] + Mi[k][2] * T[2][l]);
+    for (int l = 0; l < 3; ++l) Mb[k][l] = -(Mi[k][0] * W[0][l] + Mi[k][1] * W[1][l] + Mi[k][2] * W[2][l]);
   // M = N^T H N, H = c2 C1 + c1 C2: Hb = N Mb N^T, Nb = HN (Mb + Mb^T)
   double Nb[6][3];
 #pragma unroll
@@ -238,22 +254,31 @@ __device__ void lam_bwd(const double* C1, const double* C2, double c1, const dou
       Nb[i][k] = s;
     }
   // G = (C1 - C2) N: Nb += (C1 - C2)^T Gb, (C1 - C2)b = Gb N^T
+#pragma unroll
   for (int j = 0; j < 6; ++j)
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
       double s = 0.0;
+#pragma unroll
       for (int i = 0; i < 6; ++i) s += (C1[6 * i + j] - C2[6 * i + j]) * Gb[i][k];
       Nb[j][k] += s;
     }
-  double dh = 0.0;  // <Hb, C2 - C1>
+  // Hb = N Mb N^T = NM N^T
+  double NM[6][3];
+#pragma unroll
   for (int i = 0; i < 6; ++i)
+#pragma unroll
+    for (int l = 0; l < 3; ++l) NM[i][l] = N[i][0] * Mb[0][l] + N[i][1] * Mb[1][l] + N[i][2] * Mb[2][l];
+  double dh = 0.0;  // <Hb, C2 - C1>
+#pragma unroll
+  for (int i = 0; i < 6; ++i)
+#pragma unroll
     for (int j = 0; j < 6; ++j) {
       double hb = 0.0, db = 0.0;
 #pragma unroll
       for (int k = 0; k < 3; ++k) {
         db += Gb[i][k] * N[j][k];
-#pragma unroll
-        for (int l = 0; l < 3; ++l) hb += N[i][k] * Mb[k][l] * N[j][l];
+        hb += NM[i][k] * N[j][k];
       }
       dh += hb * (C2[6 * i + j] - C1[6 * i + j]);
       const double cb = Cb[6 * i + j];
@@ -263,6 +288,11 @@ __device__ void lam_bwd(const double* C1, const double* C2, double c1, const dou
   c1b = dd - (1.0 - 2.0 * c1) * dx + dh;
   nmat_adj(Nb, nb);
 }
+
+// threads of an offline work-group (one sample): the bottom level of a depth-8
+// tree has 128 laminates; deeper trees loop. Small groups leave the reverse
+// mode of a laminate its full register budget.
+constexpr int OFF_THREADS = 128;
 
 struct OffArgs {
   int K, nleaf;
@@ -300,7 +330,7 @@ __device__ __forceinline__ const double* child_C(const OffArgs& a, int s, int sa
   return a.Cnode + ((long long)s * a.nleaf + h) * 36;
 }
 
-__global__ void __launch_bounds__(512) k_dmn_fwd(OffArgs a) {
+__global__ void __launch_bounds__(OFF_THREADS) k_dmn_fwd(OffArgs a) {
   __shared__ double wsub[2 * (1 << DMN_MAX_K)];
   const int s = blockIdx.x;
   const int sample = a.idx ? a.idx[s] : s;
@@ -334,7 +364,7 @@ __global__ void __launch_bounds__(512) k_dmn_fwd(OffArgs a) {
 }
 
 // per-sample gradient of J1 = (1/B) (sum_s e_s^q)^(1/q) with respect to all parameters
-__global__ void __launch_bounds__(512) k_dmn_bwd(OffArgs a) {
+__global__ void __launch_bounds__(OFF_THREADS) k_dmn_bwd(OffArgs a) {
   __shared__ double wsub[2 * (1 << DMN_MAX_K)];
   __shared__ double wbar[2 * (1 << DMN_MAX_K)];
   const int s = blockIdx.x;
@@ -457,7 +487,7 @@ U* dalloc_into(std::vector<void*>& allocs, size_t count) {
   return static_cast<U*>(ptr);
 }
 
-int threads_for(int nleaf) { return std::min(512, std::max(64, nleaf / 2)); }
+int threads_for(int nleaf) { return std::min(OFF_THREADS, std::max(64, nleaf / 2)); }
 
 }  // namespace
 
