@@ -138,7 +138,7 @@ def batch_bench(nprob=512, steps=5, seed=4):
 
 def surrogate_bench(n_hist=60000, test_hist=1000, epochs=100, rows=65536, batch=4096, lr=8e-3, quantile=0.995):
     """Surrogate vs FFT Gauss-point updates/s on the fixed 32^3 microstructure:
-    300k FFT samples (60000 histories x 5 increments, batched solver) train two
+    300k FFT samples (60000 histories x 5 increments, batched solver) train four
     networks; acceptance is calibrated on held-out histories so that 99.5 % of
     accepted rows meet the error target; a fresh test set measures acceptance
     and error; rejected rows are charged at the batched FFT rate."""
@@ -190,7 +190,7 @@ def surrogate_bench(n_hist=60000, test_hist=1000, epochs=100, rows=65536, batch=
             "all_median_error": float(np.median(err)), "all_p90_error": float(np.quantile(err, 0.9)),
             "infer_ms_65536": round(t_inf * 1e3, 3), "surrogate_gauss_point_updates_per_s": round(rate, 1),
             "ratio_vs_fft": round(rate / r_fft, 2)}
-    flops = rows * 2 * 2 * NETWORK_PARAMS_MACS
+    flops = rows * 2 * len(sur.nets) * NETWORK_PARAMS_MACS
     out["network_tflops"] = round(flops / (out["target_0.001"]["infer_ms_65536"] * 1e-3) / 1e12, 2)
     return out
 

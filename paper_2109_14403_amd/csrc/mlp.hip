@@ -386,6 +386,33 @@ __global__ void k_accept(const float* ya, const float* yb, long long n, int n_ou
   accept[r] = s <= thr ? 1 : 0;
 }
 
+// M networks: y = mean, spread = RMS pairwise distance of the stress outputs
+// (sqrt(2 / (M - 1) sum_m |s_m - s_mean|^2), |s_a - s_b| for two networks)
+// over max(|s_mean|, floor_scale)
+__global__ void k_accept_n(const float* ys /* [M][n][n_out] */, int M, long long n, int n_out, float* y,
+                           float* spread, uint8_t* accept, float thr, float floor_scale) {
+  const long long r = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= n) return;
+  const float inv = 1.f / (float)M;
+  float d2 = 0.f, m2 = 0.f;
+  for (int j = 0; j < n_out; ++j) {
+    float mean = 0.f;
+    for (int m = 0; m < M; ++m) mean += ys[((long long)m * n + r) * n_out + j];
+    mean *= inv;
+    y[r * n_out + j] = mean;
+    if (j < 6) {
+      for (int m = 0; m < M; ++m) {
+        const float d = ys[((long long)m * n + r) * n_out + j] - mean;
+        d2 += d * d;
+      }
+      m2 += mean * mean;
+    }
+  }
+  const float s = sqrtf(2.f * d2 / (float)(M - 1)) / fmaxf(sqrtf(m2), floor_scale);
+  spread[r] = s;
+  accept[r] = s <= thr ? 1 : 0;
+}
+
 // ---------------------------------------------------------------------------
 // host side
 // ---------------------------------------------------------------------------
@@ -947,6 +974,15 @@ void Mlp::train(const float* X, const float* T, long long n, int epochs, int bat
     HIPCHK(hipMemcpy(hl.data(), dloss, epochs * sizeof(double), hipMemcpyDeviceToHost));
     for (int e = 0; e < epochs; ++e) loss_out[e] = (float)(hl[e] / steps_per_epoch);
   }
+}
+
+void surrogate_accept_n(const Mlp* const* nets, int M, const float* x, float* y, float* ys, float* spread,
+                        uint8_t* accept, long long n, float thr, float floor_scale, hipStream_t s) {
+  const int n_out = nets[0]->n_out;
+  for (int m = 0; m < M; ++m)
+    const_cast<Mlp*>(nets[m])->forward(x, ys + (size_t)m * n * n_out, n, false, false, s);
+  hipLaunchKernelGGL(k_accept_n, dim3((n + 255) / 256), dim3(256), 0, s, ys, M, n, n_out, y, spread, accept, thr,
+                     floor_scale);
 }
 
 void surrogate_accept(const Mlp& a, const Mlp& b, const float* x, float* y, float* ya, float* yb, float* spread,

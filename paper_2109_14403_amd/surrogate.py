@@ -125,9 +125,10 @@ def stress_errors(y_pred, y_true, denom):
 
 
 class Surrogate:
-    """Two seeded networks with a calibrated acceptance threshold."""
+    """Independently seeded networks (four by default) with a calibrated
+    acceptance threshold on their spread."""
 
-    def __init__(self, seeds=(0, 1)):
+    def __init__(self, seeds=(0, 1, 2, 3)):
         self.nets = [hom.MLP(N_IN, N_OUT, seed=s) for s in seeds]
         self.threshold = None
         self.floor = 1.0  # MPa: stress scale below which the spread is taken absolute
@@ -166,7 +167,7 @@ class Surrogate:
     def infer(self, X_dev):
         """Device tensor [n, 32] -> (y, spread, accept) device tensors."""
         thr = self.threshold if self.threshold is not None else 0.0
-        return hom.surrogate_infer(self.nets[0], self.nets[1], X_dev, thr, self.floor)
+        return hom.surrogate_infer_n(self.nets, X_dev, thr, self.floor)
 
     def calibrate(self, X, Y, denom, target=1e-3, quantile=1.0):
         """Largest spread threshold under which the accepted validation rows all

@@ -207,3 +207,33 @@ def test_online_trial_steps_commit_nothing():
     rb = b.step(d * 0.04, 300.0, 2.0)
     for i in range(2):
         assert np.allclose(ra[i]["stress"], rb[i]["stress"], rtol=1e-10, atol=1e-10 * np.abs(rb[i]["stress"]).max())
+
+
+def test_online_points_with_their_own_temperature_and_step():
+    """Per-point theta and dt (some repeated, some not) give each point the
+    result of a one-point evaluation with its own history."""
+    rng = np.random.default_rng(44)
+    K = 7
+    m, v = random_params(K, rng)
+    net = _net(K, m, v)
+    thetas = np.array([300.0, 310.0, 300.0, 325.0, 310.0])
+    dts = np.array([2.0, 2.0, 0.5, 2.0, 2.0])
+    d = rng.standard_normal((5, 6))
+    d /= np.linalg.norm(d, axis=1, keepdims=True)
+    many = hom.DmnOnline(net, W.e_glass(), W.pa66(), 5, tol=1e-11)
+    ones = [hom.DmnOnline(net, W.e_glass(), W.pa66(), 1, tol=1e-11) for _ in range(5)]
+    for k in (1, 2, 3):
+        th = thetas + 2.0 * k
+        out = many.step(d * 0.006 * k, th, dts, what=k % 2)
+        for i in range(5):
+            r = ones[i].step(d[i:i + 1] * 0.006 * k, th[i], dts[i], what=k % 2)[0]
+            assert out[i]["status"] == hom.HOM_OK and r["status"] == hom.HOM_OK
+            assert out[i]["newton_iters"] == r["newton_iters"]
+            for key in ("stress", "dsde", "coupling", "dissipation") + (("dsdt", "dDde", "dDdt") if k % 2 else ()):
+                a, b = np.asarray(out[i][key]), np.asarray(r[key])
+                assert np.allclose(a, b, rtol=1e-12, atol=1e-12 * max(np.abs(b).max(), 1e-30)), (k, i, key)
+    assert out["dissipation"].max() > 0.0
+    many.close()
+    for o in ones:
+        o.close()
+    net.close()
