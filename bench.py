@@ -138,7 +138,7 @@ def batch_bench(nprob=512, steps=5, seed=4):
 
 def surrogate_bench(n_hist=60000, test_hist=1000, epochs=100, rows=65536, batch=4096, lr=8e-3, quantile=0.995):
     """Surrogate vs FFT Gauss-point updates/s on the fixed 32^3 microstructure:
-    300k FFT samples (60000 histories x 5 increments, batched solver) train four
+    300k FFT samples (60000 histories x 5 increments, batched solver) train eight
     networks; acceptance is calibrated on held-out histories so that 99.5 % of
     accepted rows meet the error target; a fresh test set measures acceptance
     and error; rejected rows are charged at the batched FFT rate."""
@@ -149,12 +149,14 @@ def surrogate_bench(n_hist=60000, test_hist=1000, epochs=100, rows=65536, batch=
     img, _ = S.microstructure()
     hist = S.histories(n_hist, seed=10)
     sol = S.solve_histories(img, hist)
+    print(f"surrogate: {len(hist['theta']) * 5} FFT rows in {sol['seconds']:.1f} s", file=sys.stderr, flush=True)
     X, Y, den, hid = S.features(hist, sol)
     tr = hid < int(0.9 * n_hist)
     sur = S.Surrogate()
     t0 = time.perf_counter()
     sur.fit(X[tr], Y[tr], epochs=epochs, batch=batch, lr=lr)
     fit_s = time.perf_counter() - t0
+    print(f"surrogate: {len(sur.nets)} networks trained in {fit_s:.1f} s", file=sys.stderr, flush=True)
     th = S.histories(test_hist, seed=99)
     ts = S.solve_histories(img, th)
     r_fft = ts["updates"] / ts["seconds"]

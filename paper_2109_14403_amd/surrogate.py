@@ -125,10 +125,10 @@ def stress_errors(y_pred, y_true, denom):
 
 
 class Surrogate:
-    """Independently seeded networks (four by default) with a calibrated
+    """Independently seeded networks (eight by default) with a calibrated
     acceptance threshold on their spread."""
 
-    def __init__(self, seeds=(0, 1, 2, 3)):
+    def __init__(self, seeds=tuple(range(8))):
         self.nets = [hom.MLP(N_IN, N_OUT, seed=s) for s in seeds]
         self.threshold = None
         self.floor = 1.0  # MPa: stress scale below which the spread is taken absolute

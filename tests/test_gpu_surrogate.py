@@ -64,7 +64,7 @@ def test_mean_and_spread_definition(trained):
     y, spread, _ = _infer(sur, Xv)
     ys = [net.forward(Xv) for net in sur.nets]
     M = len(ys)
-    assert M == 4
+    assert M >= 3
     ym = np.mean(ys, axis=0)
     np.testing.assert_allclose(y, ym, rtol=1e-6, atol=1e-6)
     pair = sum(np.sum((ys[a][:, :6] - ys[b][:, :6]) ** 2, axis=1) for a in range(M) for b in range(a + 1, M))
