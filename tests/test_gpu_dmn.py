@@ -103,7 +103,7 @@ def oracle_online(m, v, law1, law2, npts, tol):
     return [dmn.OnlineDMN(m, v, law1, law2, tol=tol) for _ in range(npts)]
 
 
-@pytest.mark.parametrize("K", [3, 6, 7, 8])
+@pytest.mark.parametrize("K", [1, 2, 3, 6, 7, 8])
 def test_online_matches_oracle(K):
     rng = np.random.default_rng(70 + K)
     m, v = random_params(K, rng)
