@@ -334,7 +334,8 @@ int hom_surrogate_infer(hom_mlp* a, hom_mlp* b, const float* x_dev, float* y_dev
  * with s their mean, over max(|s|, floor_scale); accept = spread <= threshold.
  * For two networks this is hom_surrogate_infer's spread. All arrays on the
  * device; n = 0 returns HOM_OK without touching them. The first network keeps
- * a device scratch of n * count * n_out floats between calls. */
+ * a device scratch of n * count * n_out floats between calls, so calls that
+ * share a first network must not overlap. */
 #define HOM_SURROGATE_MAX_NETS 16
 int hom_surrogate_infer_n(hom_mlp* const* nets, int32_t count, const float* x_dev, float* y_dev, float* spread_dev,
                           uint8_t* accept_dev, int64_t n, double threshold, double floor_scale, void* stream);
@@ -370,8 +371,10 @@ void hom_mlp_destroy(hom_mlp* net);
  * algorithmic tangents of Sec. 3.3, what = 1 all four (the point partials of
  * the PA66 leaves by central differences, as for hom_algorithmic_tangent).
  * Phase laws: laws[0] for phase 1, laws[1] for phase
- * 2 (at most one PA66). Depth up to 8 (one work-group of 2^K threads per
- * point, the whole tree in LDS). */
+ * 2 (at most one PA66). strain [n_points][6] (components), theta and dt
+ * [n_points] each, host arrays; points may differ in theta and dt. Depth up
+ * to 8 (one wave per point: each lane holds up to four leaves, the levels
+ * above are combined across the lanes). */
 typedef struct hom_dmn hom_dmn;
 typedef struct hom_dmn_online hom_dmn_online;
 typedef struct {

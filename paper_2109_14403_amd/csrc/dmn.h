@@ -3,7 +3,7 @@
 // and its gradients in hand-written FP64 kernels (one work-group per stiffness
 // sample), AMSGrad with the paper's learning-rate modulation. Online: the
 // Newton iteration on the displacement jumps of many macroscopic points at
-// once (one work-group per point).
+// once (one wave per point).
 //
 // Tree indexing on the device (heap order): node h = 1 is the root, the
 // children of h are 2h and 2h + 1, the leaves are h = 2^K .. 2^(K+1) - 1
