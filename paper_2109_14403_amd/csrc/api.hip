@@ -77,6 +77,36 @@ int stats(const hom::BatchImpl* b, const char** names, int64_t* launches, double
 }
 }  // namespace
 
+namespace {
+hom::DmnSchedule schedule_of(const hom_dmn_train_opts* o) {
+  hom::DmnSchedule s;
+  if (o) {
+    s.lr_max = o->lr_max;
+    s.lr_min = o->lr_min;
+    s.half_period = o->half_period;
+    s.decay = o->decay;
+    s.q = o->q;
+    s.penalty = o->penalty;
+  }
+  if (!(s.lr_max > 0.0) || !(s.lr_min >= 0.0) || s.half_period < 1 || !(s.decay > 0.0) || !(s.q >= 1.0) ||
+      !(s.penalty >= 0.0))
+    hom::fail(HOM_E_ARG, "invalid training options");
+  return s;
+}
+}  // namespace
+
+namespace {
+// the first network's scratch holds the per-network outputs of an inference
+void grow_scratch(hom_mlp* a, size_t floats) {
+  if (floats <= a->scratch_floats) return;
+  if (a->scratch) HIPCHK(hipFree(a->scratch));
+  a->scratch = nullptr;
+  a->scratch_floats = 0;
+  HIPCHK(hipMalloc((void**)&a->scratch, floats * 4));
+  a->scratch_floats = floats;
+}
+}  // namespace
+
 extern "C" {
 
 void hom_default_options(hom_options* o) {
@@ -232,23 +262,6 @@ const char* hom_batch_last_error(const hom_batch* b) { return b ? b->err.c_str()
 
 void hom_batch_destroy(hom_batch* b) { delete b; }
 
-namespace {
-hom::DmnSchedule schedule_of(const hom_dmn_train_opts* o) {
-  hom::DmnSchedule s;
-  if (o) {
-    s.lr_max = o->lr_max;
-    s.lr_min = o->lr_min;
-    s.half_period = o->half_period;
-    s.decay = o->decay;
-    s.q = o->q;
-    s.penalty = o->penalty;
-  }
-  if (!(s.lr_max > 0.0) || !(s.lr_min >= 0.0) || s.half_period < 1 || !(s.decay > 0.0) || !(s.q >= 1.0) ||
-      !(s.penalty >= 0.0))
-    hom::fail(HOM_E_ARG, "invalid training options");
-  return s;
-}
-}  // namespace
 
 void hom_dmn_default_train_opts(hom_dmn_train_opts* o) {
   if (!o) return;
@@ -431,17 +444,6 @@ int hom_mlp_loss_grad(hom_mlp* m, const float* x, const float* y, int64_t n, int
   });
 }
 
-namespace {
-// the first network's scratch holds the per-network outputs of an inference
-void grow_scratch(hom_mlp* a, size_t floats) {
-  if (floats <= a->scratch_floats) return;
-  if (a->scratch) HIPCHK(hipFree(a->scratch));
-  a->scratch = nullptr;
-  a->scratch_floats = 0;
-  HIPCHK(hipMalloc((void**)&a->scratch, floats * 4));
-  a->scratch_floats = floats;
-}
-}  // namespace
 
 int hom_surrogate_infer(hom_mlp* a, hom_mlp* b, const float* x_dev, float* y_dev, float* spread_dev,
                         uint8_t* accept_dev, int64_t n, double threshold, double floor_scale, void* stream) {
