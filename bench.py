@@ -471,6 +471,12 @@ def dmn_bench(n=128, samples=160, epochs=3000, K=8, points=4096, seed=7):
         steps_t.append(time.perf_counter() - t0)
         iters += [r["newton_iters"] for r in out]
         failed += sum(r["status"] != 0 for r in out)
+    # all four algorithmic tangents at every point: a trial increment (commits nothing)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    out4 = on.step(dirs * 0.024, 293.15 + 30, 2.0, what=1, trial=True)
+    t_what1 = time.perf_counter() - t0
+    failed4 = int((out4["status"] != 0).sum())
     on.close()
     # the DMN against the FFT solver on the first increments of a uniaxial history
     ctx = hom.Context(wl.phases, wl.laws, scheme=hom.SCHEME_NEWTON_CG, precision=hom.FP32, tol=1e-6)
@@ -480,6 +486,9 @@ def dmn_bench(n=128, samples=160, epochs=3000, K=8, points=4096, seed=7):
         f = ctx.solve_increment(st.strain, st.theta, st.grad, st.dt)
         d = one.step(np.asarray(st.strain)[None], st.theta, st.dt)[0]
         errs.append(float(np.abs(d["stress"] - f["stress"]).max() / np.abs(f["stress"]).max()))
+    # the effective tangents after the 10th increment: DMN against the FFT solver
+    tf = ctx.algorithmic_tangent(what=0)["dsde"]
+    tan_err = float(np.abs(d["dsde"] - tf).max() / np.abs(tf).max())
     ctx.close()
     one.close()
     net.close()
@@ -489,6 +498,8 @@ def dmn_bench(n=128, samples=160, epochs=3000, K=8, points=4096, seed=7):
             "online_points": points, "online_ms_per_increment": round(1e3 * float(np.median(steps_t)), 3),
             "online_gauss_point_updates_per_s": round(points / float(np.median(steps_t)), 1),
             "online_newton_mean": round(float(np.mean(iters)), 2), "online_failed": int(failed),
+            "online_all_tangents_ms": round(1e3 * t_what1, 3), "online_all_tangents_failed": failed4,
+            "vs_fft_tangent_error_increment_10": round(tan_err, 4),
             "vs_fft_stress_error_10_increments": [round(e, 4) for e in errs]}
 
 
