@@ -503,6 +503,31 @@ def dmn_bench(n=128, samples=160, epochs=3000, K=8, points=4096, seed=7):
             "vs_fft_stress_error_10_increments": [round(e, 4) for e in errs]}
 
 
+def predictor_bench(wl, warmup, total, results, disc):
+    """The timed increments again with the predictor option (start from the
+    last committed strain-fluctuation change): time per increment, iterations,
+    and the largest stress difference from the uniform-start run."""
+    from paper_2109_14403_amd import hom
+    ctx = hom.Context(wl.phases, wl.laws, scheme=hom.SCHEME_NEWTON_CG, precision=hom.FP32, tol=1e-6,
+                      autotune=1, discretization=disc, predictor=1)
+    for st in wl.history[:warmup]:
+        ctx.solve_increment(st.strain, st.theta, st.grad, st.dt)
+    import torch
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    out = [ctx.solve_increment(st.strain, st.theta, st.grad, st.dt) for st in wl.history[warmup:total]]
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    ctx.close()
+    steps = total - warmup
+    diff = max(float(np.abs(a["stress"] - b["stress"]).max() / np.abs(b["stress"]).max())
+               for a, b in zip(out, results))
+    return {"ms_per_step": round(el / steps * 1e3, 2),
+            "newton_per_step": sum(r["newton_iters"] for r in out) / steps,
+            "krylov_per_step": sum(r["krylov_iters"] for r in out) / steps,
+            "max_stress_diff_rel": diff}
+
+
 def tangent_bench(ctx, wl, nvox, warmup, total):
     """d<sigma>/dE of the last timed increment: six linearized cell solves
     (hom_algorithmic_tangent, what = 0), timed around the synchronous call."""
@@ -552,6 +577,7 @@ def main():
     ap.add_argument("--no-tangent", action="store_true")
     ap.add_argument("--rotated", action="store_true", help="rotated finite-difference discretization")
     ap.add_argument("--no-dmn", action="store_true")
+    ap.add_argument("--no-predictor", action="store_true")
     ap.add_argument("--calib-copy", action="store_true", help="run a 1 GiB device copy (PMC calibration)")
     ap.add_argument("--pmc-summary", nargs="+", metavar="DIR",
                     help="summarize rocprofv3 --pmc output folders (FETCH_SIZE, WRITE_SIZE[, request sizes]) "
@@ -687,6 +713,10 @@ def main():
     if tangent is not None:
         tangent.update(tangent_full_bench(wl, nvox, args.warmup))
         print(f"tangent (all four): {tangent}", file=sys.stderr, flush=True)
+    pred = None
+    if not args.no_predictor:
+        pred = predictor_bench(wl, args.warmup, total, results, disc)
+        print(f"predictor: {pred}", file=sys.stderr, flush=True)
     copy_gbs = copy_probe()
     batch = None
     if not args.no_batch:
@@ -719,7 +749,7 @@ def main():
         "thermal_voxel_iters_per_s": round(tpipes * nvox / elapsed, 1),
         "newton_per_step": newton / args.steps, "krylov_per_step": krylov / args.steps,
         "roofline": roof, "copy_probe_gbs": copy_gbs, "cpu_baseline": cpu, "batch": batch, "surrogate": surr,
-        "tangent": tangent, "dmn": dmn_line,
+        "tangent": tangent, "dmn": dmn_line, "predictor": pred,
     }
     if kstats:
         line["kernel_ms"] = {k: [v[0], round(v[1], 3)] for k, v in kstats.items() if v[0]}

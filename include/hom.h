@@ -109,6 +109,12 @@ typedef struct {
                           what = 1); costs 13 field components of memory and one pass of
                           14 PA66 point evaluations per increment */
   int32_t discretization; /* HOM_DISC_*; default collocation */
+  int32_t predictor;   /* 1: start the mechanical solve of an increment from the committed strain
+                          plus the macro increment plus s times the strain fluctuation that the
+                          last committed increment added, s = dE . dE_last / |dE_last|^2 clamped
+                          to [0, 2] (Mandel components; s = 0 after hom_set_state or
+                          hom_set_laws); costs 6 field components of memory and one more write
+                          stream in the commit. 0: the uniform start eps^n + dE (default) */
 } hom_options;
 
 /* Macroscopic temperature input: theta [K] and its gradient [K/m]. */

@@ -65,6 +65,8 @@ struct ProbInc {
   double lam0, mu0, kappa0;  // basic-scheme reference media
   int smask;        // mixed conditions: bit c set => Mandel component c of <sigma> is prescribed
   double S[6];      // prescribed effective stress (Mandel) of the masked components
+  double pred_s;    // predictor: weight of the last committed strain fluctuation change (0: none)
+  double dEp[6];    // mean strain change of the last committed increment (Mandel)
   PhaseInc ph[MAX_PHASES];
   // PA66 (at most one inelastic law per setup)
   int pa_phase;     // phase id of the PA66 law, -1 if none

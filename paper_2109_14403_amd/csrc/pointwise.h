@@ -41,6 +41,7 @@ struct Pt {
   const ProbInc* inc_pm;    // [prob][2]: increment data at theta + h_theta, theta - h_theta
   const T* s0;              // source of a linearized evaluation (sigma = C x + s0), or null
   int commit;               // commit kernel: 1 commit, 0 only the effective sums (a trial)
+  T* dx;                    // strain change of the last committed increment [prob][6][nvox], or null
 };
 
 // Effective sums of the commit kernel (mechanics): <sigma> (6), dissipation,

@@ -32,10 +32,20 @@ __global__ void __launch_bounds__(PT_THREADS) k_init(Pt<T> a, int basic, int kee
   if (keep_x) return;
   const long long nv = a.nvox;
   const long long fo = (long long)prob * C * nv;
+  // predictor: add s times the fluctuation that the last committed increment added
+  const bool pred = C == 6 && a.dx && in.pred_s != 0.0;
+  const T ps = T(in.pred_s);
   for (long long v = (long long)blk * PT_THREADS + threadIdx.x; v < nv; v += (long long)a.bpp * PT_THREADS) {
     if constexpr (C == 6) {
+      if (pred) {
 #pragma unroll
-      for (int c = 0; c < 6; ++c) a.x[fo + c * nv + v] = a.xn[fo + c * nv + v] + T(in.dE[c]);
+        for (int c = 0; c < 6; ++c)
+          a.x[fo + c * nv + v] =
+              a.xn[fo + c * nv + v] + T(in.dE[c]) + ps * (a.dx[fo + c * nv + v] - T(in.dEp[c]));
+      } else {
+#pragma unroll
+        for (int c = 0; c < 6; ++c) a.x[fo + c * nv + v] = a.xn[fo + c * nv + v] + T(in.dE[c]);
+      }
     } else {
 #pragma unroll
       for (int c = 0; c < 3; ++c) a.x[fo + c * nv + v] += T(in.dG[c]);
@@ -200,6 +210,9 @@ __global__ void __launch_bounds__(PT_THREADS) k_commit(Pt<T> a) {
         a.xn[fo + c * nv + v] = T(e[c]);  // the committed strain (exact: e was read from T)
         a.f[fo + c * nv + v] = T(sg[c]);
       }
+      if (a.dx)
+#pragma unroll
+        for (int c = 0; c < 6; ++c) a.dx[fo + c * nv + v] = T(e[c] - en[c]);
       if (a.pv_diss) {
         a.pv_diss[(long long)prob * nv + v] = dis;
         a.pv_coup[(long long)prob * nv + v] = cpl;

@@ -274,6 +274,11 @@ struct Group {
   // (set up with the tangent option), the stress field saved across the
   // linearized solves, and whether the last increment can be linearized
   T *dsdt = nullptr, *dDde = nullptr, *dDdt = nullptr, *fsave = nullptr;
+  // predictor option: the strain change of each problem's last committed
+  // increment (field and mean), and whether it belongs to the current state
+  T* dx = nullptr;
+  std::vector<std::array<double, 6>> dEp;
+  std::vector<char> pred_ok;
   ProbInc* inc_pm_d = nullptr;
   ProbInc* inc_pm_h = nullptr;
   bool tan_ok = false;
@@ -301,7 +306,7 @@ struct Group {
     if (ctl_h) (void)hipHostFree(ctl_h);
   }
 
-  void alloc(bool with_state, bool partials = false) {
+  void alloc(bool with_state, bool partials = false, bool predictor = false) {
     P = nx / 2 + 1;
     nvox = (long long)nx * ny * nz;
     const long long nm = (long long)nprob * nvox;
@@ -349,6 +354,9 @@ struct Group {
     }
     En.assign(nprob, {0, 0, 0, 0, 0, 0});
     Gp.assign(nprob, {0, 0, 0});
+    dEp.assign(nprob, {0, 0, 0, 0, 0, 0});
+    pred_ok.assign(nprob, 0);
+    if (predictor) dx = dalloc<T>(6 * nm);
     if (partials) {
       dsdt = dalloc<T>(6 * nm);
       dDde = dalloc<T>(6 * nm);
@@ -417,6 +425,7 @@ struct Group {
     a.inc_pm = inc_pm_d;
     a.s0 = nullptr;
     a.commit = 1;
+    a.dx = dx;
     return a;
   }
 };
@@ -517,7 +526,7 @@ class BatchT : public BatchImpl {
       auto& G = *gp;
       G.nprob = (int)G.members.size();
       G.nstate = nst;
-      G.alloc(nst > 0, opts.tangent != 0);
+      G.alloc(nst > 0, opts.tangent != 0, opts.predictor != 0);
       std::vector<uint8_t> buf((size_t)G.nprob * G.nx * G.ny * G.nz);
       G.c0mean.assign(G.nprob, 0.0);
       const long long nv = (long long)G.nx * G.ny * G.nz;
@@ -815,6 +824,17 @@ class BatchT : public BatchImpl {
             in.S[c] = sc ? w[c] * L.stress[c] : 0.0;
           }
           for (int c = 0; c < 3; ++c) in.dG[c] = L.temp.grad[c] - G.Gp[j][c];
+          // predictor weight: projection of this macro increment on the last one
+          in.pred_s = 0.0;
+          if (G.dx && G.pred_ok[j]) {
+            double ee = 0.0, ep = 0.0;
+            for (int c = 0; c < 6; ++c) {
+              ee += in.dE[c] * G.dEp[j][c];
+              ep += G.dEp[j][c] * G.dEp[j][c];
+            }
+            if (ep > 0.0 && std::isfinite(ee)) in.pred_s = std::min(2.0, std::max(0.0, ee / ep));
+          }
+          for (int c = 0; c < 6; ++c) in.dEp[c] = G.dEp[j][c];
           if (G.inc_pm_h) {  // the increment data at theta +- h_theta for the point partials
             fill_inc(G.inc_pm_h[2 * j], laws, th[j] + FD_H_THETA, L.dt);
             fill_inc(G.inc_pm_h[2 * j + 1], laws, th[j] - FD_H_THETA, L.dt);
@@ -910,8 +930,14 @@ class BatchT : public BatchImpl {
         if (cm.status != 1) st = cm.status < 0 ? cm.status : HOM_E_NOT_CONVERGED;
         if (st == HOM_OK && ct.status != 1) st = ct.status < 0 ? ct.status : HOM_E_NOT_CONVERGED;
         r.status = st;
-        if (cm.status == 1 && !trial)
-          for (int c = 0; c < 6; ++c) G.En[j][c] = ((L.stress_mask >> c) & 1u) ? cm.out[8 + c] : w[c] * L.strain[c];
+        if (cm.status == 1 && !trial) {
+          for (int c = 0; c < 6; ++c) {
+            const double e = ((L.stress_mask >> c) & 1u) ? cm.out[8 + c] : w[c] * L.strain[c];
+            G.dEp[j][c] = e - G.En[j][c];
+            G.En[j][c] = e;
+          }
+          G.pred_ok[j] = 1;  // the commit wrote the field of this change
+        }
         all = all && cm.status == 1;
       }
       G.tan_ok = all;
@@ -942,6 +968,7 @@ class BatchT : public BatchImpl {
         G.c0mean[j] = c0;
       }
       G.tan_ok = false;  // the tangent fields belong to the old parameters
+      std::fill(G.pred_ok.begin(), G.pred_ok.end(), 0);
     }
   }
 
@@ -1065,7 +1092,10 @@ class BatchT : public BatchImpl {
     }
   }
   void set_state(const void* buf) override {
-    for (auto& gp : groups) gp->tan_ok = false;  // the tangent fields belong to the replaced state
+    for (auto& gp : groups) {
+      gp->tan_ok = false;  // the tangent fields belong to the replaced state
+      std::fill(gp->pred_ok.begin(), gp->pred_ok.end(), 0);  // so does the predictor's last change
+    }
     const char* p = static_cast<const char*>(buf);
     uint64_t magic, tsz;
     std::memcpy(&magic, p, 8);
@@ -1134,6 +1164,7 @@ std::unique_ptr<BatchImpl> make_batch(int nprob, const hom_grid* grids, const ui
     fail(HOM_E_ARG, "unknown discretization");
   if (opts.discretization == HOM_DISC_ROTATED && opts.scheme != HOM_SCHEME_NEWTON_CG)
     fail(HOM_E_UNSUPPORTED, "the rotated discretization is built for the Newton-CG scheme");
+  if (opts.predictor != 0 && opts.predictor != 1) fail(HOM_E_ARG, "predictor must be 0 or 1");
   if (opts.precision == HOM_FP64) {
     auto b = std::make_unique<BatchT<double>>();
     b->init(nprob, grids, phases, laws, nlaws, opts);

@@ -73,7 +73,7 @@ class Options(ct.Structure):
         ("scheme", ct.c_int32), ("precision", ct.c_int32), ("tol", ct.c_double), ("thermal_tol", ct.c_double),
         ("max_iter", ct.c_int32), ("max_krylov", ct.c_int32), ("chunk", ct.c_int32), ("use_graph", ct.c_int32),
         ("profile", ct.c_int32), ("autotune", ct.c_int32), ("stream", ct.c_void_p), ("tangent", ct.c_int32),
-        ("discretization", ct.c_int32),
+        ("discretization", ct.c_int32), ("predictor", ct.c_int32),
     ]
 
 
@@ -320,7 +320,7 @@ def make_law(p: dict) -> Law:
 
 def make_options(scheme=SCHEME_NEWTON_CG, precision=FP32, tol=1e-6, thermal_tol=0.0, max_iter=0, max_krylov=0,
                  chunk=0, use_graph=1, profile=0, autotune=0, stream=None, tangent=0,
-                 discretization=0) -> Options:
+                 discretization=0, predictor=0) -> Options:
     o = Options()
     library().hom_default_options(ct.byref(o))
     o.scheme = scheme
@@ -336,6 +336,7 @@ def make_options(scheme=SCHEME_NEWTON_CG, precision=FP32, tol=1e-6, thermal_tol=
     o.stream = stream
     o.tangent = tangent
     o.discretization = discretization
+    o.predictor = predictor
     return o
 
 

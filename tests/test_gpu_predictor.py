@@ -1,0 +1,93 @@
+"""The predictor option (start each increment from the committed strain plus
+the macro increment plus the last committed strain-fluctuation change, scaled
+by the projection of the new macro increment on the last one).
+
+A start value changes the iterations, not the solution: the converged
+increments equal those of the uniform start within the solver tolerance,
+both for the PA66 / E-glass sphere composite under the shear-tension history
+and for the batch path. After a checkpoint restore the predictor has no last
+change, so that increment starts as without it (bitwise). Parity of the
+uniform start with the oracle is covered by test_gpu_solver.py.
+"""
+import numpy as np
+import pytest
+
+from paper_2109_14403_amd import hom
+from paper_2109_14403_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+def run(wl, predictor, steps, precision=hom.FP64, tol=1e-10):
+    ctx = hom.Context(wl.phases, wl.laws, scheme=hom.SCHEME_NEWTON_CG, precision=precision, tol=tol,
+                      predictor=predictor)
+    out = [ctx.solve_increment(st.strain, st.theta, st.grad, st.dt) for st in wl.history[:steps]]
+    return ctx, out
+
+
+@pytest.mark.parametrize("precision,tol,bound", [(hom.FP64, 1e-10, 1e-7), (hom.FP32, 1e-6, 2e-4)])
+def test_same_increments_fewer_iterations(precision, tol, bound):
+    wl = W.sphere_composite_workload(32, seed=2)
+    c0, a = run(wl, 0, 8, precision, tol)
+    c1, b = run(wl, 1, 8, precision, tol)
+    for k, (x, y) in enumerate(zip(a, b)):
+        scale = np.abs(x["stress"]).max()
+        assert np.abs(x["stress"] - y["stress"]).max() <= bound * scale, k
+        assert abs(x["dissipation"] - y["dissipation"]) <= bound * max(abs(x["dissipation"]), 1e-12), k
+    na = sum(r["newton_iters"] for r in a[1:])
+    nb = sum(r["newton_iters"] for r in b[1:])
+    ka = sum(r["krylov_iters"] for r in a[1:])
+    kb = sum(r["krylov_iters"] for r in b[1:])
+    print(f"precision {precision}: increments 2..8 Newton {na} -> {nb}, CG {ka} -> {kb}", flush=True)
+    assert a[0]["newton_iters"] == b[0]["newton_iters"]      # nothing to extrapolate from yet
+    assert nb + kb < na + ka
+    c0.close()
+    c1.close()
+
+
+def test_no_predictor_after_a_checkpoint_restore():
+    wl = W.sphere_composite_workload(32, seed=2)
+    ctx, _ = run(wl, 1, 4)
+    state = ctx.get_state()
+    ref = hom.Context(wl.phases, wl.laws, scheme=hom.SCHEME_NEWTON_CG, precision=hom.FP64, tol=1e-10)
+    ref.set_state(state)
+    ctx.set_state(state)
+    st = wl.history[4]
+    x = ctx.solve_increment(st.strain, st.theta, st.grad, st.dt)
+    y = ref.solve_increment(st.strain, st.theta, st.grad, st.dt)
+    assert np.array_equal(x["stress"], y["stress"])
+    assert x["newton_iters"] == y["newton_iters"] and x["krylov_iters"] == y["krylov_iters"]
+    # the next increment extrapolates again
+    st = wl.history[5]
+    x = ctx.solve_increment(st.strain, st.theta, st.grad, st.dt)
+    y = ref.solve_increment(st.strain, st.theta, st.grad, st.dt)
+    assert np.abs(x["stress"] - y["stress"]).max() <= 1e-7 * np.abs(y["stress"]).max()
+    assert x["newton_iters"] + x["krylov_iters"] < y["newton_iters"] + y["krylov_iters"]
+    ctx.close()
+    ref.close()
+
+
+def test_batch_with_predictor_equals_single_problems():
+    probs = [W.batch_problem(i) for i in (0, 1, 2)]
+    img = [p.phases for p in probs]
+    hist = [p.history for p in probs]
+    laws = probs[0].laws
+    b = hom.Batch(img, laws, scheme=hom.SCHEME_NEWTON_CG, precision=hom.FP64, tol=1e-10, predictor=1)
+    outs = []
+    for k in range(len(hist[0])):
+        outs.append(b.solve_increment([h[k].strain for h in hist], [h[k].theta for h in hist],
+                                      [h[k].grad for h in hist], [h[k].dt for h in hist]))
+    b.close()
+    for j in range(3):
+        ctx = hom.Context(img[j], laws, scheme=hom.SCHEME_NEWTON_CG, precision=hom.FP64, tol=1e-10, predictor=1)
+        for k, st in enumerate(hist[j]):
+            r = ctx.solve_increment(st.strain, st.theta, st.grad, st.dt)
+            assert np.array_equal(r["stress"], outs[k][j]["stress"]), (j, k)
+        ctx.close()
+
+
+def test_predictor_option_must_be_zero_or_one():
+    wl = W.small_sphere_workload()
+    with pytest.raises(hom.HomError) as e:
+        hom.Context(wl.phases, wl.laws, predictor=2)
+    assert e.value.code == hom.HOM_E_ARG
