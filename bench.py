@@ -101,10 +101,11 @@ def cpu_baseline(phases, laws, reps=2,
             "sample": sample, "seconds": dt}
 
 
-def batch_bench(nprob=512, steps=5, seed=4):
+def batch_bench(nprob=512, steps=5, seed=4, predictor=0):
     """The batched two-scale workload: nprob microproblems of 24^3 / 32^3 / 48^3
     (seeded RSA spheres, own macro histories), all increments, FP32 fields,
-    hipGraph chunks. Returns Gauss-point updates/s and voxel-iterations/s."""
+    hipGraph chunks, with the uniform or the predictor start. Returns
+    Gauss-point updates/s and voxel-iterations/s."""
     import torch
 
     from paper_2109_14403_amd import hom
@@ -113,7 +114,7 @@ def batch_bench(nprob=512, steps=5, seed=4):
     wls = [W.batch_problem(i, seed=seed, n_steps=steps) for i in range(nprob)]
     laws = [W.pa66(), W.e_glass()]
     b = hom.Batch([w.phases for w in wls], laws, scheme=hom.SCHEME_NEWTON_CG, precision=hom.FP32, tol=1e-6,
-                  autotune=1)
+                  autotune=1, predictor=predictor)
     nvox = np.array([w.phases.size for w in wls], dtype=np.float64)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -141,7 +142,8 @@ def surrogate_bench(n_hist=60000, test_hist=1000, epochs=100, rows=65536, batch=
     300k FFT samples (60000 histories x 5 increments, batched solver) train eight
     networks; acceptance is calibrated on held-out histories so that 99.5 % of
     accepted rows meet the error target; a fresh test set measures acceptance
-    and error; rejected rows are charged at the batched FFT rate."""
+    and error; rejected rows are charged at the batched FFT rate (predictor
+    start; the uniform-start rate of the same histories is reported too)."""
     import torch
 
     from paper_2109_14403_amd import surrogate as S
@@ -160,11 +162,14 @@ def surrogate_bench(n_hist=60000, test_hist=1000, epochs=100, rows=65536, batch=
     th = S.histories(test_hist, seed=99)
     ts = S.solve_histories(img, th)
     r_fft = ts["updates"] / ts["seconds"]
+    tu = S.solve_histories(img, th, predictor=0)
     Xt, Yt, dent, _ = S.features(th, ts)
     big = torch.as_tensor(np.tile(Xt, (rows // len(Xt) + 1, 1))[:rows], device="cuda")
     xt_dev = torch.as_tensor(Xt, device="cuda")
     e_skip = S.stress_errors(sur.skip_only(Xt), Yt, dent)
-    out = {"fft_gauss_point_updates_per_s": round(r_fft, 1), "train_rows": int(tr.sum()), "fit_seconds": round(fit_s, 1),
+    out = {"fft_gauss_point_updates_per_s": round(r_fft, 1),
+           "fft_gauss_point_updates_per_s_uniform_start": round(tu["updates"] / tu["seconds"], 1),
+           "train_rows": int(tr.sum()), "fit_seconds": round(fit_s, 1),
            "fft_data_seconds": round(sol["seconds"], 1), "epochs": epochs, "batch": batch,
            "calibration_quantile": quantile,
            "test_rows": len(Xt), "skip_only_median_error": float(np.median(e_skip))}
@@ -721,6 +726,9 @@ def main():
     batch = None
     if not args.no_batch:
         batch = batch_bench()
+        bp = batch_bench(predictor=1)
+        batch["predictor"] = {k: bp[k] for k in ("seconds", "gauss_point_updates_per_s", "voxel_iters_per_s",
+                                                 "failed")}
         print(f"batch: {batch}", file=sys.stderr, flush=True)
     surr = None
     if not args.no_surrogate:

@@ -58,10 +58,11 @@ def histories(count, seed, steps=5):
     return dict(strain=strain, theta=theta, dt=dt, grad=grad)
 
 
-def solve_histories(img, hist, chunk=1000, precision=hom.FP32, tol=1e-6):
-    """Run every history through the batched FFT solver. Returns stress
-    [count, steps, 6] (Mandel), flux [count, steps, 3], dissipation
-    [count, steps], elapsed seconds and the number of point updates."""
+def solve_histories(img, hist, chunk=1000, precision=hom.FP32, tol=1e-6, predictor=1):
+    """Run every history through the batched FFT solver (with the predictor
+    start unless predictor = 0). Returns stress [count, steps, 6] (Mandel),
+    flux [count, steps, 3], dissipation [count, steps], elapsed seconds and
+    the number of point updates."""
     count, steps = hist["theta"].shape
     laws = [W.pa66(), W.e_glass()]
     stress = np.zeros((count, steps, 6))
@@ -71,7 +72,8 @@ def solve_histories(img, hist, chunk=1000, precision=hom.FP32, tol=1e-6):
     elapsed = 0.0
     for c0 in range(0, count, chunk):
         c1 = min(count, c0 + chunk)
-        b = hom.Batch([img] * (c1 - c0), laws, scheme=hom.SCHEME_NEWTON_CG, precision=precision, tol=tol)
+        b = hom.Batch([img] * (c1 - c0), laws, scheme=hom.SCHEME_NEWTON_CG, precision=precision, tol=tol,
+                      predictor=predictor)
         for k in range(steps):
             t0 = time.perf_counter()
             res = b.solve_increment(hist["strain"][c0:c1, k], hist["theta"][c0:c1, k], hist["grad"][c0:c1],
