@@ -285,7 +285,7 @@ void hom_batch_destroy(hom_batch* b);
  * a summary of the macroscopic history) to the effective outputs. It plays
  * the role the paper gives its learned surrogate (Sec. 3: a fixed
  * microstructure, macroscopic inputs, effective stress and heat outputs),
- * with the FFT solver as fallback and judge. Weights are bf16 on the matrix
+ * with the FFT solver as fallback and reference. Weights are bf16 on the matrix
  * cores with FP32 accumulation; inputs and outputs are FP32.
  *
  * Parameters cross the ABI in layer order, each layer its weight matrix

@@ -142,8 +142,8 @@ class Surrogate:
         """Least-squares gated polynomial skip (fixed, fitted by the library),
         networks trained on the residual. With denom (each row's error
         normalization, max_t |<sigma>| of its history) the rows are weighted by
-        1 / denom^2, so the loss is the squared relative error the acceptance
-        is judged by (denominators below `floor` count as `floor`). Returns
+        1 / denom^2, so the loss is the squared relative error that decides
+        acceptance (denominators below `floor` count as `floor`). Returns
         the per-epoch losses."""
         lw = np.ones(N_OUT, dtype=np.float32)
         lw[:6] = 4.0          # the stress is the accuracy target
