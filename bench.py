@@ -523,6 +523,17 @@ def predictor_bench(wl, warmup, total, results, disc):
     out = [ctx.solve_increment(st.strain, st.theta, st.grad, st.dt) for st in wl.history[warmup:total]]
     torch.cuda.synchronize()
     el = time.perf_counter() - t0
+    # d<sigma>/dE after the last timed increment (a first call: uniform starts),
+    # then after one more increment (started from the first call's solutions)
+    tans = []
+    for extra in (False, True):
+        if extra:
+            st = wl.history[total]
+            ctx.solve_increment(st.strain, st.theta, st.grad, st.dt)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        t = ctx.algorithmic_tangent(what=0)
+        tans.append((time.perf_counter() - t1, t["krylov_iters"]))
     ctx.close()
     steps = total - warmup
     diff = max(float(np.abs(a["stress"] - b["stress"]).max() / np.abs(b["stress"]).max())
@@ -530,7 +541,9 @@ def predictor_bench(wl, warmup, total, results, disc):
     return {"ms_per_step": round(el / steps * 1e3, 2),
             "newton_per_step": sum(r["newton_iters"] for r in out) / steps,
             "krylov_per_step": sum(r["krylov_iters"] for r in out) / steps,
-            "max_stress_diff_rel": diff}
+            "max_stress_diff_rel": diff,
+            "dsde_ms_first_call": round(tans[0][0] * 1e3, 2), "dsde_krylov_first_call": tans[0][1],
+            "dsde_ms_warm": round(tans[1][0] * 1e3, 2), "dsde_krylov_warm": tans[1][1]}
 
 
 def tangent_bench(ctx, wl, nvox, warmup, total):

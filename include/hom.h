@@ -114,7 +114,10 @@ typedef struct {
                           last committed increment added, s = dE . dE_last / |dE_last|^2 clamped
                           to [0, 2] (Mandel components; s = 0 after hom_set_state or
                           hom_set_laws); costs 6 field components of memory and one more write
-                          stream in the commit. 0: the uniform start eps^n + dE (default) */
+                          stream in the commit. It also starts each linearized solve of
+                          hom_algorithmic_tangent from the same column's solution of the previous
+                          call (up to 42 more field components, allocated on the first call).
+                          0: the uniform start eps^n + dE (default) */
 } hom_options;
 
 /* Macroscopic temperature input: theta [K] and its gradient [K/m]. */

@@ -42,6 +42,7 @@ struct Pt {
   const T* s0;              // source of a linearized evaluation (sigma = C x + s0), or null
   int commit;               // commit kernel: 1 commit, 0 only the effective sums (a trial)
   T* dx;                    // strain change of the last committed increment [prob][6][nvox], or null
+  const T* x0;              // start of a linearized solve [prob][6][nvox], or null (uniform dE)
 };
 
 // Effective sums of the commit kernel (mechanics): <sigma> (6), dissipation,

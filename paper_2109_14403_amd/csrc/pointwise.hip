@@ -255,8 +255,13 @@ __global__ void __launch_bounds__(PT_THREADS) k_init_linear(Pt<T> a) {
   const long long nv = a.nvox;
   const long long fo = (long long)prob * 6 * nv;
   for (long long v = (long long)blk * PT_THREADS + threadIdx.x; v < nv; v += (long long)a.bpp * PT_THREADS) {
+    if (a.x0) {  // an earlier solution of the same column: same mean, close fluctuation
 #pragma unroll
-    for (int c = 0; c < 6; ++c) stnt(a.x + fo + c * nv + v, T(in.dE[c]));
+      for (int c = 0; c < 6; ++c) stnt(a.x + fo + c * nv + v, ldnt(a.x0 + fo + c * nv + v));
+    } else {
+#pragma unroll
+      for (int c = 0; c < 6; ++c) stnt(a.x + fo + c * nv + v, T(in.dE[c]));
+    }
   }
 }
 

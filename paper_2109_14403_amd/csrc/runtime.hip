@@ -279,6 +279,10 @@ struct Group {
   T* dx = nullptr;
   std::vector<std::array<double, 6>> dEp;
   std::vector<char> pred_ok;
+  // ... and the solutions of the last tangent call, one field per column,
+  // which start the next call's linearized solves
+  T* tcol = nullptr;
+  bool tcol_ok[7] = {false, false, false, false, false, false, false};
   ProbInc* inc_pm_d = nullptr;
   ProbInc* inc_pm_h = nullptr;
   bool tan_ok = false;
@@ -426,6 +430,7 @@ struct Group {
     a.s0 = nullptr;
     a.commit = 1;
     a.dx = dx;
+    a.x0 = nullptr;
     return a;
   }
 };
@@ -969,6 +974,7 @@ class BatchT : public BatchImpl {
       }
       G.tan_ok = false;  // the tangent fields belong to the old parameters
       std::fill(G.pred_ok.begin(), G.pred_ok.end(), 0);
+      std::fill(G.tcol_ok, G.tcol_ok + 7, false);
     }
   }
 
@@ -1006,7 +1012,8 @@ class BatchT : public BatchImpl {
         Limits lim = limits(0);
         lim.linear = 1;
         const long long cap = iteration_cap(lim, false);
-        const Pt<T> q = G.pt(0);
+        Pt<T> q = G.pt(0);
+        if (G.dx && !G.tcol) G.tcol = G.template dalloc<T>(7 * 6 * nm);  // predictor: warm starts
         for (int j = 0; j < G.nprob; ++j) {
           hom_tangent& t = out[G.members[j]];
           std::memset(&t, 0, sizeof(t));
@@ -1021,6 +1028,8 @@ class BatchT : public BatchImpl {
             for (int c = 0; c < 6; ++c) G.inc_h[j].dE[c] = (c == col) ? 1.0 : 0.0;
           }
           HIPCHK(hipMemcpyAsync(G.inc_d, G.inc_h, sizeof(ProbInc) * G.nprob, hipMemcpyHostToDevice, stream));
+          T* start = G.tcol ? G.tcol + (size_t)col * 6 * nm : nullptr;
+          q.x0 = (start && G.tcol_ok[col]) ? start : nullptr;
           launch_init_linear<T>(q, stream);
           iterate(G, col < 6 ? 2 : 3, false, cap);
           launch_tangent_sum<T>(q, stream);
@@ -1044,6 +1053,10 @@ class BatchT : public BatchImpl {
             t.solves += 1;
             t.krylov_iters += c.krylov;
             t.pipelines += c.pipelines;
+          }
+          if (start) {  // converged everywhere: the next call starts from this solution
+            HIPCHK(hipMemcpyAsync(start, G.xm, 6 * nm * sizeof(T), hipMemcpyDeviceToDevice, stream));
+            G.tcol_ok[col] = true;
           }
         }
       } catch (...) {
@@ -1095,6 +1108,7 @@ class BatchT : public BatchImpl {
     for (auto& gp : groups) {
       gp->tan_ok = false;  // the tangent fields belong to the replaced state
       std::fill(gp->pred_ok.begin(), gp->pred_ok.end(), 0);  // so does the predictor's last change
+      std::fill(gp->tcol_ok, gp->tcol_ok + 7, false);
     }
     const char* p = static_cast<const char*>(buf);
     uint64_t magic, tsz;

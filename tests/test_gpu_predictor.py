@@ -91,3 +91,29 @@ def test_predictor_option_must_be_zero_or_one():
     with pytest.raises(hom.HomError) as e:
         hom.Context(wl.phases, wl.laws, predictor=2)
     assert e.value.code == hom.HOM_E_ARG
+
+
+@pytest.mark.parametrize("what", [0, 1])
+def test_warm_started_tangents(what):
+    """With the predictor option each linearized tangent solve starts from the
+    previous call's solution of the same column: the same tangents, fewer
+    Krylov iterations from the second call on."""
+    wl = W.sphere_composite_workload(32, seed=2)
+    ctxs = [hom.Context(wl.phases, wl.laws, scheme=hom.SCHEME_NEWTON_CG, precision=hom.FP64, tol=1e-10,
+                        predictor=p, tangent=what) for p in (0, 1)]
+    for k, st in enumerate(wl.history[:5]):
+        for c in ctxs:
+            c.solve_increment(st.strain, st.theta, st.grad, st.dt)
+        if k < 2:
+            continue
+        cold, warm = (c.algorithmic_tangent(what=what) for c in ctxs)
+        keys = ("dsde",) + (("dsdt", "dDde", "dDdt") if what else ())
+        for key in keys:
+            a, b = np.asarray(cold[key]), np.asarray(warm[key])
+            assert np.abs(a - b).max() <= 1e-6 * np.abs(a).max(), (k, key)
+        print(f"what {what} increment {k}: krylov {cold['krylov_iters']} cold, {warm['krylov_iters']} warm",
+              flush=True)
+        if k > 2:
+            assert warm["krylov_iters"] < cold["krylov_iters"]
+    for c in ctxs:
+        c.close()
