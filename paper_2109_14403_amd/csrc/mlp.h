@@ -45,6 +45,13 @@ struct Mlp {
   std::vector<void*> work;
   float *xs = nullptr, *zs[MLP_LAYERS - 1] = {}, *as[MLP_LAYERS - 1] = {}, *yhat = nullptr, *dy = nullptr;
   float *da = nullptr, *dz = nullptr, *xb = nullptr, *tb = nullptr, *rwb = nullptr, *lpart = nullptr;
+  // split-K partials of the weight-gradient products and FP64 column-sum
+  // partials of the bias gradients (grown on demand, one set per network so
+  // that networks can train concurrently)
+  float* splitk = nullptr;
+  size_t splitk_n = 0;
+  double* csum = nullptr;
+  size_t csum_n = 0;
 
   Mlp(int n_in, int n_out, uint64_t seed);
   ~Mlp();

@@ -472,6 +472,8 @@ Mlp::Mlp(int n_in_, int n_out_, uint64_t seed) : n_in(n_in_), n_out(n_out_) {
 Mlp::~Mlp() {
   free_work();
   for (void* p : allocs) (void)hipFree(p);
+  if (splitk) (void)hipFree(splitk);
+  if (csum) (void)hipFree(csum);
 }
 
 void Mlp::free_work() {
@@ -744,26 +746,21 @@ __global__ void __launch_bounds__(256) k_sum_splits(const float* P, int splits, 
   C[(long long)m * ldc + n] = v;
 }
 
-// split-K work space of the weight-gradient products (a few MB)
-static float* g_splitk = nullptr;
-static size_t g_splitk_n = 0;
-static double* g_colsum = nullptr;
-static size_t g_colsum_n = 0;
-
-static void colsum(const float* in, long long rows, int cols, float* out, hipStream_t s) {
+static void colsum(Mlp& net, const float* in, long long rows, int cols, float* out, hipStream_t s) {
   const int chunks = (int)((rows + COLSUM_CHUNK - 1) / COLSUM_CHUNK);
   const size_t need = (size_t)chunks * cols;
-  if (need > g_colsum_n) {
-    if (g_colsum) HIPCHK(hipFree(g_colsum));
-    HIPCHK(hipMalloc((void**)&g_colsum, need * sizeof(double)));
-    g_colsum_n = need;
+  if (need > net.csum_n) {
+    if (net.csum) HIPCHK(hipFree(net.csum));
+    net.csum = nullptr;
+    HIPCHK(hipMalloc((void**)&net.csum, need * sizeof(double)));
+    net.csum_n = need;
   }
-  hipLaunchKernelGGL(k_colsum_part, dim3((cols + 63) / 64, chunks), dim3(256), 0, s, in, rows, cols, g_colsum);
-  hipLaunchKernelGGL(k_colsum_final, dim3((cols + 255) / 256), dim3(256), 0, s, g_colsum, chunks, cols, out);
+  hipLaunchKernelGGL(k_colsum_part, dim3((cols + 63) / 64, chunks), dim3(256), 0, s, in, rows, cols, net.csum);
+  hipLaunchKernelGGL(k_colsum_final, dim3((cols + 255) / 256), dim3(256), 0, s, net.csum, chunks, cols, out);
 }
 
-static void gemm(bool ta, bool tb, int M, int N, int K, const float* A, int lda, const float* B, int ldb, float* C,
-                 int ldc, hipStream_t s) {
+static void gemm(Mlp& net, bool ta, bool tb, int M, int N, int K, const float* A, int lda, const float* B, int ldb,
+                 float* C, int ldc, hipStream_t s) {
   dim3 grid((N + 63) / 64, (M + 63) / 64);
   // weight gradients: a small M x N output over a long K (the batch) gets
   // few work-groups; split K over more of them and sum the partials
@@ -771,17 +768,18 @@ static void gemm(bool ta, bool tb, int M, int N, int K, const float* A, int lda,
     const int splits = std::min(64, K / 256);
     const int kc = (K + splits - 1) / splits;
     const size_t need = (size_t)splits * M * N;
-    if (need > g_splitk_n) {
-      if (g_splitk) HIPCHK(hipFree(g_splitk));
-      HIPCHK(hipMalloc((void**)&g_splitk, need * sizeof(float)));
-      g_splitk_n = need;
+    if (need > net.splitk_n) {
+      if (net.splitk) HIPCHK(hipFree(net.splitk));
+      net.splitk = nullptr;
+      HIPCHK(hipMalloc((void**)&net.splitk, need * sizeof(float)));
+      net.splitk_n = need;
     }
     const int nsp = (K + kc - 1) / kc;  // every split has at least one row
     hipLaunchKernelGGL((k_gemm<true, false>), dim3(grid.x, grid.y, nsp), dim3(256), 0, s, M, N, K, A, lda, B, ldb,
-                       g_splitk, N, 0.f, kc);
+                       net.splitk, N, 0.f, kc);
     const long long cnt = (long long)M * N;
-    hipLaunchKernelGGL(k_sum_splits, dim3((unsigned)((cnt + 255) / 256)), dim3(256), 0, s, g_splitk, nsp, M, N, C,
-                       ldc);
+    hipLaunchKernelGGL(k_sum_splits, dim3((unsigned)((cnt + 255) / 256)), dim3(256), 0, s, net.splitk, nsp, M, N,
+                       C, ldc);
     return;
   }
   if (!ta && !tb) hipLaunchKernelGGL((k_gemm<false, false>), grid, dim3(256), 0, s, M, N, K, A, lda, B, ldb, C, ldc, 0.f);
@@ -832,11 +830,11 @@ int Mlp::grad_only(const float* x, const float* tnorm, long long B, bool precise
     const int K = lay_k(l), N = lay_n(l);
     const float* ain = l == 0 ? xs : as[l - 1];
     // dW[N][K] = dZ^T (B x N) . A (B x K)
-    gemm(true, false, N, K, (int)B, dcur, ncur, ain, K, g + woff[l], K, s);
-    colsum(dcur, B, N, g + boff[l], s);
+    gemm(*this, true, false, N, K, (int)B, dcur, ncur, ain, K, g + woff[l], K, s);
+    colsum(*this, dcur, B, N, g + boff[l], s);
     if (l > 0) {
       // dA (B x K) = dZ (B x N) . W (N x K), then dZ_prev = dA * gelu'(Z_prev)
-      gemm(false, false, (int)B, K, N, dcur, ncur, eff + woff[l], K, da, K, s);
+      gemm(*this, false, false, (int)B, K, N, dcur, ncur, eff + woff[l], K, da, K, s);
       const long long c = B * K;
       hipLaunchKernelGGL(k_gelu_back, dim3((c + 255) / 256), dim3(256), 0, s, da, zs[l - 1], dz, c);
       // dz is read by the next layer's dW / dA products before its own
@@ -905,20 +903,29 @@ size_t Mlp::param_count() const {
 void Mlp::train(const float* X, const float* T, long long n, int epochs, int batch, double lr0, uint64_t seed,
                 const float* row_weight, float* loss_out) {
   if (n < batch || batch < 1) fail(HOM_E_ARG, "need at least one full batch");
+  // a stream of this call (default priority): networks trained from several
+  // host threads overlap on the device
   hipStream_t s = nullptr;
+  HIPCHK(hipStreamCreateWithFlags(&s, hipStreamNonBlocking));
+  struct StreamGuard {
+    hipStream_t s;
+    ~StreamGuard() { (void)hipStreamDestroy(s); }
+  } sguard{s};
   float *dX = nullptr, *dT = nullptr, *dW = nullptr;
   int* didx = nullptr;
   HIPCHK(hipMalloc((void**)&dX, n * n_in * 4));
   HIPCHK(hipMalloc((void**)&dT, n * MLP_OUT * 4));
   HIPCHK(hipMalloc((void**)&didx, n * 4));
   if (row_weight) HIPCHK(hipMalloc((void**)&dW, n * 4));
-  struct Guard {
+  struct Guard {  // destroyed before sguard: waits for the stream, then frees
+    hipStream_t s;
     std::vector<void*> p;
     ~Guard() {
+      (void)hipStreamSynchronize(s);
       for (void* q : p)
         if (q) (void)hipFree(q);
     }
-  } guard{{dX, dT, didx, dW}};
+  } guard{s, {dX, dT, didx, dW}};
   std::vector<float> tn((size_t)n * MLP_OUT);
   normalized_targets(X, T, n, tn.data());
   HIPCHK(hipMemcpy(dX, X, n * n_in * 4, hipMemcpyHostToDevice));
@@ -938,13 +945,17 @@ void Mlp::train(const float* X, const float* T, long long n, int epochs, int bat
   double* dloss = nullptr;  // per-epoch loss sums on the device
   HIPCHK(hipMalloc((void**)&dloss, std::max(epochs, 1) * sizeof(double)));
   guard.p.push_back(dloss);
-  HIPCHK(hipMemset(dloss, 0, std::max(epochs, 1) * sizeof(double)));
+  HIPCHK(hipMemsetAsync(dloss, 0, std::max(epochs, 1) * sizeof(double), s));
+  // the clears of freshly allocated work buffers ran on the null stream, which
+  // this non-blocking stream does not wait for
+  HIPCHK(hipStreamSynchronize(nullptr));
   const long long total = steps_per_epoch * epochs;
   long long step = 0;
   const float b1 = 0.9f, b2 = 0.999f;
   for (int e = 0; e < epochs; ++e) {
     for (long long i = 0; i < n; ++i) perm[i] = (int)i;
     std::shuffle(perm.begin(), perm.end(), gen);
+    HIPCHK(hipStreamSynchronize(s));  // the last epoch's gathers have read didx
     HIPCHK(hipMemcpy(didx, perm.data(), n * 4, hipMemcpyHostToDevice));
     for (long long sidx = 0; sidx < steps_per_epoch; ++sidx) {
       const int* bi = didx + sidx * batch;
@@ -968,7 +979,7 @@ void Mlp::train(const float* X, const float* T, long long n, int epochs, int bat
       refresh(s);
     }
   }
-  HIPCHK(hipDeviceSynchronize());
+  HIPCHK(hipStreamSynchronize(s));
   if (loss_out && epochs > 0) {
     std::vector<double> hl(epochs);
     HIPCHK(hipMemcpy(hl.data(), dloss, epochs * sizeof(double), hipMemcpyDeviceToHost));

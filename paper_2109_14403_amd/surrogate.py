@@ -152,10 +152,17 @@ class Surrogate:
         rw = None
         if denom is not None:
             rw = (1.0 / np.maximum(np.asarray(denom, dtype=np.float64), self.floor) ** 2).astype(np.float32)
-        losses = []
-        for i, net in enumerate(self.nets):
+        # the networks are independent: one host thread each (the library
+        # releases the interpreter and trains each network on its own stream)
+        from concurrent.futures import ThreadPoolExecutor
+
+        def one(i):
+            net = self.nets[i]
             net.fit_skip(X, Y, self.GATES, lw, rw)
-            losses.append(net.train(X, Y, epochs=epochs, batch=batch, lr=lr, seed=seed + 17 * i, row_weight=rw))
+            return net.train(X, Y, epochs=epochs, batch=batch, lr=lr, seed=seed + 17 * i, row_weight=rw)
+
+        with ThreadPoolExecutor(max_workers=len(self.nets)) as pool:
+            losses = list(pool.map(one, range(len(self.nets))))
         # the method without the network: same skip, network output held at zero
         self.skip_net = hom.MLP(N_IN, N_OUT, seed=0)
         self.skip_net.fit_skip(X, Y, self.GATES, lw, rw)
