@@ -112,7 +112,7 @@ typedef struct {
   int32_t predictor;   /* 1: start the mechanical solve of an increment from the committed strain
                           plus the macro increment plus s times the strain fluctuation that the
                           last committed increment added, s = dE . dE_last / |dE_last|^2 clamped
-                          to [0, 2] (Mandel components; s = 0 after hom_set_state or
+                          to [0, 2] (Mandel, strain-controlled components; s = 0 after hom_set_state or
                           hom_set_laws); costs 6 field components of memory and one more write
                           stream in the commit. It also starts each linearized solve of
                           hom_algorithmic_tangent from the same column's solution of the previous

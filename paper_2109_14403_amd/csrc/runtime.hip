@@ -829,11 +829,13 @@ class BatchT : public BatchImpl {
             in.S[c] = sc ? w[c] * L.stress[c] : 0.0;
           }
           for (int c = 0; c < 3; ++c) in.dG[c] = L.temp.grad[c] - G.Gp[j][c];
-          // predictor weight: projection of this macro increment on the last one
+          // predictor weight: projection of this macro increment on the last
+          // one over the strain-controlled components
           in.pred_s = 0.0;
           if (G.dx && G.pred_ok[j]) {
             double ee = 0.0, ep = 0.0;
             for (int c = 0; c < 6; ++c) {
+              if ((L.stress_mask >> c) & 1u) continue;
               ee += in.dE[c] * G.dEp[j][c];
               ep += G.dEp[j][c] * G.dEp[j][c];
             }

@@ -117,3 +117,30 @@ def test_warm_started_tangents(what):
             assert warm["krylov_iters"] < cold["krylov_iters"]
     for c in ctxs:
         c.close()
+
+
+def test_predictor_under_mixed_conditions_and_adiabatic_balance():
+    """Uniaxial stress (the lateral components of <sigma> held at zero) with
+    the adiabatic heat balance: the same loads with fewer iterations."""
+    rng = np.random.default_rng(4)
+    img = (rng.random((16, 16, 16)) < 0.3).astype(np.uint8)
+    laws = [W.pa66(), W.e_glass()]
+    mask = 0b111110
+    runs = []
+    for p in (0, 1):
+        ctx = hom.Context(img, laws, scheme=hom.SCHEME_NEWTON_CG, precision=hom.FP64, tol=1e-10, predictor=p)
+        out, theta = [], 300.0
+        for k in range(1, 6):
+            r = ctx.solve_load([0.004 * k, 0, 0, 0, 0, 0], theta, [0, 0, 0], 2.0, stress=np.zeros(6),
+                               stress_mask=mask, adiabatic=True)
+            theta = r["theta"]
+            out.append(r)
+        runs.append(out)
+        ctx.close()
+    for k, (a, b) in enumerate(zip(*runs)):
+        assert np.abs(a["stress"] - b["stress"]).max() <= 1e-7 * np.abs(a["stress"]).max(), k
+        assert np.abs(a["strain"] - b["strain"]).max() <= 1e-7 * np.abs(a["strain"]).max(), k
+        assert abs(a["theta"] - b["theta"]) <= 1e-6 * max(abs(a["theta"] - 300.0), 1e-3), k
+    it = [sum(r["newton_iters"] + r["krylov_iters"] for r in out[1:]) for out in runs]
+    print(f"mixed adiabatic increments 2..5: iterations {it[0]} -> {it[1]}", flush=True)
+    assert it[1] < it[0]
