@@ -362,6 +362,19 @@ def trace_summary(folder, log_path, n, command):
     for r in stats[:16]:
         lines.append(f"| {r['Name'][:80]} | {r['Calls']} | {float(r['TotalDurationNs']) / 1e6:.2f} | "
                      f"{float(r['AverageNs']) / 1e3:.1f} | {float(r['Percentage']):.2f} |")
+    # copies inside the timed increments: between the first and the last
+    # launch of the roofline kernel, on the queue that runs it
+    ev = sorted((int(r["Start_Timestamp"]), int(r["End_Timestamp"]), r["Kernel_Name"], r["Queue_Id"])
+                for r in trace)
+    first = next(e for e in ev if e[2] == main_name)
+    last = [e for e in ev if e[2] == main_name][-1]
+    cps = [e for e in ev if "copyBuffer" in e[2] and first[0] <= e[0] <= last[1]]
+    same_q = [e for e in cps if e[3] == first[3]]
+    lines += ["", f"`__amd_rocclr_copyBuffer` inside the window of the {len(durs)} `{kind}` launches: "
+              f"{len(cps)} copies, {sum(e[1] - e[0] for e in cps) / 1e6:.1f} ms; on the queue of the pipeline "
+              f"kernels {len(same_q)} ({sum(e[1] - e[0] for e in same_q) / 1e6:.1f} ms: the per-chunk readback "
+              "of the control words). The rest are the checkpoint download before the per-kernel replay "
+              "and its restore, outside the timed increments."]
     with open(os.path.join(ROOT, "profiles", f"pipeline_fibres{n}_kernel_trace.md"), "w") as fo:
         fo.write("\n".join(lines) + "\n")
     print("\n".join(lines))
