@@ -489,6 +489,16 @@ def dmn_bench(n=128, samples=160, epochs=3000, K=8, points=4096, seed=7):
         steps_t.append(time.perf_counter() - t0)
         iters += [r["newton_iters"] for r in out]
         failed += sum(r["status"] != 0 for r in out)
+    # the same increments with the predictor start of the jumps
+    onp = hom.DmnOnline(net, W.e_glass(), W.pa66(), points, tol=1e-8, maxit=30, predictor=True)
+    steps_p, iters_p = [], []
+    for k in range(1, 6):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        outp = onp.step(dirs * 0.004 * k, 293.15 + 5 * k, 2.0)
+        steps_p.append(time.perf_counter() - t0)
+        iters_p += [r["newton_iters"] for r in outp]
+    onp.close()
     # all four algorithmic tangents at every point: a trial increment (commits nothing)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -517,6 +527,8 @@ def dmn_bench(n=128, samples=160, epochs=3000, K=8, points=4096, seed=7):
             "online_gauss_point_updates_per_s": round(points / float(np.median(steps_t)), 1),
             "online_newton_mean": round(float(np.mean(iters)), 2), "online_failed": int(failed),
             "online_all_tangents_ms": round(1e3 * t_what1, 3), "online_all_tangents_failed": failed4,
+            "online_predictor_ms_per_increment": round(1e3 * float(np.median(steps_p)), 3),
+            "online_predictor_newton_mean": round(float(np.mean(iters_p)), 2),
             "vs_fft_tangent_error_increment_10": round(tan_err, 4),
             "vs_fft_stress_error_10_increments": [round(e, 4) for e in errs]}
 

@@ -419,6 +419,15 @@ int hom_dmn_online_create(const hom_dmn* net, const hom_law laws[2], int32_t n_p
                           hom_dmn_online** out);
 int hom_dmn_online_step(hom_dmn_online* o, const double* strain, const double* theta, const double* dt,
                         int32_t what, int32_t trial, hom_dmn_result* out);
+/* on = 1: start each point's Newton iteration from its committed jumps plus
+ * s times their change over the point's last committed increment, s = the
+ * projection dE . dE_last / |dE_last|^2 of the macro increments (Mandel),
+ * clamped to [0, 2]; no shift after a trial or unconverged call (the jumps
+ * then start where that call left them). Takes effect from the second
+ * committed call after it is switched on. on = 0 (default): start from the
+ * current jumps. Same solutions within the tolerance, fewer Newton steps on
+ * smooth histories. HOM_E_ARG for other values. */
+int hom_dmn_online_set_predictor(hom_dmn_online* o, int32_t on);
 const char* hom_dmn_online_last_error(const hom_dmn_online* o);
 void hom_dmn_online_destroy(hom_dmn_online* o);
 

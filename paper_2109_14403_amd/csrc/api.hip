@@ -344,6 +344,11 @@ int hom_dmn_online_step(hom_dmn_online* o, const double* strain, const double* t
   return guarded(&o->err, [&] { hom::dmn_online_step(o->impl, strain, theta, dt, what, trial, out); });
 }
 
+int hom_dmn_online_set_predictor(hom_dmn_online* o, int32_t on) {
+  if (!o || !o->impl) return HOM_E_ARG;
+  return guarded(&o->err, [&] { hom::dmn_online_set_predictor(o->impl, on); });
+}
+
 const char* hom_dmn_online_last_error(const hom_dmn_online* o) { return o ? o->err.c_str() : g_setup_error.c_str(); }
 
 void hom_dmn_online_destroy(hom_dmn_online* o) { delete o; }

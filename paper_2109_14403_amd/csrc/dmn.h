@@ -58,6 +58,7 @@ struct Dmn {
 struct DmnOnline;
 DmnOnline* dmn_online_create(const Dmn& net, const hom_law* laws, int npoints, double tol, int maxit);
 void dmn_online_destroy(DmnOnline* o);
+void dmn_online_set_predictor(DmnOnline* o, int on);
 void dmn_online_step(DmnOnline* o, const double* strain, const double* theta, const double* dt, int what,
                      int trial, hom_dmn_result* out);
 

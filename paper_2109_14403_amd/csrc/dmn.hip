@@ -772,6 +772,14 @@ struct OnArgs {
   double* a;              // [point][nleaf][3] jumps (heap index)
   double* scr;            // [point][nleaf][ON_SCR]
   double* lp;             // [point][nleaf][ON_LP] leaf partials (what = 1)
+  // predictor (pred = 1): jump change of the last committed increment, the
+  // jumps at the start of this call, last committed macro strain and its
+  // change, and whether the point's last call committed
+  int pred;
+  double* dah;            // [point][nleaf][3]
+  double* a0;             // [point][nleaf][3]
+  double* Ep;             // [point][12]: E of the last commit (6), its change (6)
+  int* committed;         // [point]
   const double* E;        // [point][6] Mandel
   double* out;            // [point][ON_OUT]
   double tol, gamma;
@@ -1284,6 +1292,30 @@ __global__ void __launch_bounds__(ON_LANES) k_dmn_online(OnArgs g) {
       h[7 * ss] = -1.0;
     }
   }
+  // predictor: start from the committed jumps plus s times their last change,
+  // s = projection of this macro increment on the last committed one
+  double pred_s = 0.0;
+  if (g.pred) {
+    const double* ep = g.Ep + 12 * pt;
+    double ee = 0.0, pp = 0.0;
+#pragma unroll
+    for (int c = 0; c < 6; ++c) {
+      ee += (g.E[6 * pt + c] - ep[c]) * ep[6 + c];
+      pp += ep[6 + c] * ep[6 + c];
+    }
+    if (g.committed[pt] && pp > 0.0 && isfinite(ee)) pred_s = fmin(2.0, fmax(0.0, ee / pp));
+    auto start = [&](int h) {
+      double* ah = node_jump(g, pt, h);
+      double* a0 = g.a0 + ((long long)pt * nleaf + h) * 3;
+      const double* dh = g.dah + ((long long)pt * nleaf + h) * 3;
+#pragma unroll
+      for (int k = 0; k < 3; ++k) {
+        a0[k] = ah[k];
+        ah[k] += pred_s * dh[k];
+      }
+    };
+    for_owned<R>(g, lane, start);
+  }
   auto wleaf = [&](int l) { return g.node[ON_NODE * (nleaf + l) + 4]; };
   auto law = [&](int l, const double* e, LeafV& L) {
     double sg[6];
@@ -1412,6 +1444,27 @@ __global__ void __launch_bounds__(ON_LANES) k_dmn_online(OnArgs g) {
       for (int c = 0; c < 6; ++c) en[c] = e[c];
   };
   strains_pass<R>(g, pt, lane, fin);
+  if (g.pred) {
+    if (commit) {
+      auto change = [&](int h) {
+        const double* ah = node_jump(g, pt, h);
+        const double* a0 = g.a0 + ((long long)pt * nleaf + h) * 3;
+        double* dh = g.dah + ((long long)pt * nleaf + h) * 3;
+#pragma unroll
+        for (int k = 0; k < 3; ++k) dh[k] = ah[k] - a0[k];
+      };
+      for_owned<R>(g, lane, change);
+    }
+    if (lane == 0) {
+      double* ep = g.Ep + 12 * pt;
+      if (commit)
+        for (int c = 0; c < 6; ++c) {
+          ep[6 + c] = g.E[6 * pt + c] - ep[c];
+          ep[c] = g.E[6 * pt + c];
+        }
+      g.committed[pt] = commit ? 1 : 0;
+    }
+  }
   D = wave_sum(D);
   Dd = wave_sum(Dd);
   if (lane == 0) {
@@ -1439,6 +1492,9 @@ struct DmnOnline {
   std::vector<void*> allocs;
   double *p = nullptr, *node = nullptr, *state = nullptr, *hist = nullptr, *epsn = nullptr, *a = nullptr;
   double *scr = nullptr, *lp = nullptr, *E = nullptr, *out = nullptr;
+  double *dah = nullptr, *a0 = nullptr, *Ep = nullptr;
+  int* committed = nullptr;
+  int pred = 0;
   ProbInc *inc = nullptr, *inc_pm = nullptr;
   int* inc_ix = nullptr;
   std::vector<ProbInc> inc_h, inc_pm_h;
@@ -1486,6 +1542,10 @@ DmnOnline* dmn_online_create(const Dmn& net, const hom_law* laws, int npoints, d
   o->a = dalloc_into<double>(o->allocs, (size_t)npoints * o->nleaf * 3);
   o->scr = dalloc_into<double>(o->allocs, (size_t)npoints * o->nleaf * ON_SCR);
   o->lp = dalloc_into<double>(o->allocs, (size_t)npoints * o->nleaf * ON_LP);
+  o->dah = dalloc_into<double>(o->allocs, (size_t)npoints * o->nleaf * 3);
+  o->a0 = dalloc_into<double>(o->allocs, (size_t)npoints * o->nleaf * 3);
+  o->Ep = dalloc_into<double>(o->allocs, (size_t)npoints * 12);
+  o->committed = dalloc_into<int>(o->allocs, npoints);
   o->E = dalloc_into<double>(o->allocs, (size_t)npoints * 6);
   o->out = dalloc_into<double>(o->allocs, (size_t)npoints * ON_OUT);
   o->inc = dalloc_into<ProbInc>(o->allocs, npoints);
@@ -1500,6 +1560,11 @@ DmnOnline* dmn_online_create(const Dmn& net, const hom_law* laws, int npoints, d
 }
 
 void dmn_online_destroy(DmnOnline* o) { delete o; }
+
+void dmn_online_set_predictor(DmnOnline* o, int on) {
+  if (on != 0 && on != 1) fail(HOM_E_ARG, "predictor must be 0 or 1");
+  o->pred = on;
+}
 
 void dmn_online_step(DmnOnline* o, const double* strain, const double* theta, const double* dt, int what,
                      int trial, hom_dmn_result* res) {
@@ -1571,6 +1636,11 @@ void dmn_online_step(DmnOnline* o, const double* strain, const double* theta, co
   g.a = o->a;
   g.scr = o->scr;
   g.lp = o->lp;
+  g.pred = o->pred;
+  g.dah = o->dah;
+  g.a0 = o->a0;
+  g.Ep = o->Ep;
+  g.committed = o->committed;
   g.E = o->E;
   g.out = o->out;
   g.tol = o->tol;

@@ -177,7 +177,8 @@ EXPORTS = (
     "hom_batch_destroy", "hom_apply_operator", "hom_eval_law",
     "hom_dmn_default_train_opts", "hom_dmn_create", "hom_dmn_get_params", "hom_dmn_set_params",
     "hom_dmn_homogenize", "hom_dmn_loss_grad", "hom_dmn_train", "hom_dmn_last_error", "hom_dmn_destroy",
-    "hom_dmn_online_create", "hom_dmn_online_step", "hom_dmn_online_last_error", "hom_dmn_online_destroy",
+    "hom_dmn_online_create", "hom_dmn_online_step", "hom_dmn_online_set_predictor", "hom_dmn_online_last_error",
+    "hom_dmn_online_destroy",
     "hom_mlp_create", "hom_mlp_param_count", "hom_mlp_set_scaling", "hom_mlp_set_skip", "hom_mlp_fit_skip",
     "hom_mlp_get_params",
     "hom_mlp_set_params",
@@ -257,6 +258,7 @@ def library(path: str | None = None):
     lib.hom_dmn_online_create.argtypes = [ct.c_void_p, ct.POINTER(Law), ct.c_int32, ct.c_double, ct.c_int32,
                                           ct.POINTER(ct.c_void_p)]
     lib.hom_dmn_online_step.argtypes = [ct.c_void_p, dp, dp, dp, ct.c_int32, ct.c_int32, ct.POINTER(DmnResult)]
+    lib.hom_dmn_online_set_predictor.argtypes = [ct.c_void_p, ct.c_int32]
     lib.hom_dmn_online_last_error.argtypes = [ct.c_void_p]
     lib.hom_dmn_online_last_error.restype = ct.c_char_p
     lib.hom_dmn_online_destroy.argtypes = [ct.c_void_p]
@@ -807,7 +809,7 @@ class DmnOnline:
     """hom_dmn_online_*: a trained DMN at n_points macroscopic points with the
     laws of its two phases."""
 
-    def __init__(self, net: Dmn, law1: dict, law2: dict, n_points, tol=1e-10, maxit=50):
+    def __init__(self, net: Dmn, law1: dict, law2: dict, n_points, tol=1e-10, maxit=50, predictor=False):
         lib = library()
         self._lib = lib
         self.n = int(n_points)
@@ -816,6 +818,13 @@ class DmnOnline:
         _check(lib.hom_dmn_online_create(net._h, self._laws, self.n, float(tol), int(maxit), ct.byref(h)),
                lambda: lib.hom_dmn_online_last_error(None).decode())
         self._h = h
+        if predictor:
+            self.set_predictor(True)
+
+    def set_predictor(self, on: bool):
+        """hom_dmn_online_set_predictor: extrapolated Newton starts."""
+        _check(self._lib.hom_dmn_online_set_predictor(self._h, int(bool(on))),
+               lambda: self._lib.hom_dmn_online_last_error(self._h).decode())
 
     def close(self):
         if getattr(self, "_h", None):

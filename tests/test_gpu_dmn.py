@@ -237,3 +237,57 @@ def test_online_points_with_their_own_temperature_and_step():
     for o in ones:
         o.close()
     net.close()
+
+
+@pytest.mark.parametrize("K", [6, 8])
+def test_online_predictor_same_solutions_fewer_newton_steps(K):
+    rng = np.random.default_rng(80 + K)
+    m, v = random_params(K, rng)
+    net = _net(K, m, v)
+    npts = 4
+    d = rng.standard_normal((npts, 6))
+    d /= np.linalg.norm(d, axis=1, keepdims=True)
+    runs = []
+    for pred in (False, True):
+        # both runs converged far below the comparison bound (the stop test
+        # bounds the traction residual, not the stress)
+        on = hom.DmnOnline(net, W.e_glass(), W.pa66(), npts, tol=1e-12, predictor=pred)
+        runs.append([on.step(d * 0.006 * k, 293.15 + 5 * k, 2.0) for k in range(1, 7)])
+        on.close()
+    for k, (a, b) in enumerate(zip(*runs)):
+        assert (a["status"] == hom.HOM_OK).all() and (b["status"] == hom.HOM_OK).all()
+        for key, bound in (("stress", 1e-8), ("dsde", 1e-6), ("dissipation", 1e-6)):
+            x, y = np.asarray(a[key]), np.asarray(b[key])
+            assert np.abs(x - y).max() <= bound * np.abs(x).max(), (k, key)
+    na = sum(int(r["newton_iters"].sum()) for r in runs[0][2:])
+    nb = sum(int(r["newton_iters"].sum()) for r in runs[1][2:])
+    print(f"K={K}: Newton steps of increments 3..6: {na} -> {nb}", flush=True)
+    assert nb < na
+    net.close()
+
+
+def test_online_predictor_with_trial_steps():
+    """Trials in between: no shift after a trial, the commit equals the plain run."""
+    rng = np.random.default_rng(33)
+    K = 5
+    m, v = random_params(K, rng)
+    net = _net(K, m, v)
+    d = np.array([[1, 0, 0, 0, 0, 0.4], [0, 0.5, -0.2, 0.3, 0, 0]], dtype=float)
+    a = hom.DmnOnline(net, W.e_glass(), W.pa66(), 2, tol=1e-12, predictor=True)
+    b = hom.DmnOnline(net, W.e_glass(), W.pa66(), 2, tol=1e-12)
+    for k in (1, 2, 3):
+        a.step(d * 0.008 * k, 300.0, 2.0)
+        b.step(d * 0.008 * k, 300.0, 2.0)
+    a.step(d * 0.036, 300.0, 2.0, trial=True)
+    ra = a.step(d * 0.032, 300.0, 2.0)
+    rb = b.step(d * 0.032, 300.0, 2.0)
+    ra2 = a.step(d * 0.040, 300.0, 2.0)
+    rb2 = b.step(d * 0.040, 300.0, 2.0)
+    for x, y in ((ra, rb), (ra2, rb2)):
+        assert np.allclose(x["stress"], y["stress"], rtol=1e-9, atol=1e-9 * np.abs(y["stress"]).max())
+        assert np.allclose(x["dissipation"], y["dissipation"], rtol=1e-8)
+    assert a._lib.hom_dmn_online_set_predictor(a._h, 2) == hom.HOM_E_ARG
+    assert a._lib.hom_dmn_online_set_predictor(None, 1) == hom.HOM_E_ARG
+    a.close()
+    b.close()
+    net.close()
