@@ -1,0 +1,51 @@
+"""Host logic of bench.py: the algorithmic byte model behind the roofline
+figure, recounted array by array, and the one-GPU guard."""
+import os
+import subprocess
+import sys
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+sys.path.insert(0, ROOT)
+
+import bench  # noqa: E402
+
+
+def recount(kind, n, fp):
+    """Bytes per launch from the arrays each pass reads and writes (xfwd:
+    residual evaluation, first and later CG iterations)."""
+    v = n ** 3
+    comp = fp * v                        # one real field component
+    spectrum = 6 * n * n * (n // 2 + 1) * 2 * fp
+    tangent = 2 * comp + v               # factors (a, b) and the phase byte
+    if kind == "xfwd":
+        return (6 * comp + spectrum,                 # read sigma, write the spectrum
+                12 * comp + tangent + spectrum,      # read r and the tangent, write p and the spectrum
+                30 * comp + tangent + spectrum)      # read r, p, x and the tangent, write p, x, spectrum
+    if kind == "xinv":
+        return spectrum + 12 * comp                  # read the spectrum and r (or sigma), write r
+    return 2 * spectrum                              # y and z passes: the spectrum in and out
+
+
+@pytest.mark.parametrize("n,fp", [(256, 4), (64, 8), (48, 4)])
+def test_byte_model_matches_a_per_array_count(n, fp):
+    assert bench.algorithmic_bytes("xfwd", n, fp, 0.8) == pytest.approx(recount("xfwd", n, fp), rel=1e-15)
+    for kind in ("xinv", "zgreen"):
+        model = bench.algorithmic_bytes(kind, n, fp, 0.8)
+        assert all(m == pytest.approx(recount(kind, n, fp), rel=1e-15) for m in model)
+    assert bench.algorithmic_bytes("yfwd", n, fp, 0.8) == bench.algorithmic_bytes("zgreen", n, fp, 0.8)
+
+
+def test_byte_model_at_the_bench_size():
+    """The figures the roofline rests on at 256^3 FP32 (GB per launch)."""
+    ev, first, later = bench.algorithmic_bytes("xfwd", 256, 4, 0.8)
+    assert round(ev / 1e9, 3) == 0.808 and round(first / 1e9, 2) == 1.36 and round(later / 1e9, 2) == 2.57
+    assert round(bench.algorithmic_bytes("zgreen", 256, 4, 0.8)[0] / 1e9, 3) == 0.812
+
+
+def test_more_than_one_gpu_is_refused():
+    p = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"], capture_output=True,
+                       text=True, timeout=120, cwd=ROOT)
+    assert p.returncode == 2
+    assert "one GPU" in p.stdout
