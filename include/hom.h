@@ -424,7 +424,8 @@ int hom_dmn_online_step(hom_dmn_online* o, const double* strain, const double* t
  * projection dE . dE_last / |dE_last|^2 of the macro increments (Mandel),
  * clamped to [0, 2]; no shift after a trial or unconverged call (the jumps
  * then start where that call left them). Takes effect from the second
- * committed call after it is switched on. on = 0 (default): start from the
+ * committed call after it is switched on; switching it on again forgets
+ * what an earlier on-period recorded. on = 0 (default): start from the
  * current jumps. Same solutions within the tolerance, fewer Newton steps on
  * smooth histories. HOM_E_ARG for other values. */
 int hom_dmn_online_set_predictor(hom_dmn_online* o, int32_t on);

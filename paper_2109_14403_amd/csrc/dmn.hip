@@ -773,8 +773,9 @@ struct OnArgs {
   double* scr;            // [point][nleaf][ON_SCR]
   double* lp;             // [point][nleaf][ON_LP] leaf partials (what = 1)
   // predictor (pred = 1): jump change of the last committed increment, the
-  // jumps at the start of this call, last committed macro strain and its
-  // change, and whether the point's last call committed
+  // jumps at the start of this call and whether the point's last call
+  // committed; the last committed macro strain and its change (kept with the
+  // predictor off too)
   int pred;
   double* dah;            // [point][nleaf][3]
   double* a0;             // [point][nleaf][3]
@@ -1455,14 +1456,16 @@ __global__ void __launch_bounds__(ON_LANES) k_dmn_online(OnArgs g) {
       };
       for_owned<R>(g, lane, change);
     }
-    if (lane == 0) {
-      double* ep = g.Ep + 12 * pt;
-      if (commit)
-        for (int c = 0; c < 6; ++c) {
-          ep[6 + c] = g.E[6 * pt + c] - ep[c];
-          ep[c] = g.E[6 * pt + c];
-        }
-      g.committed[pt] = commit ? 1 : 0;
+    if (lane == 0) g.committed[pt] = commit ? 1 : 0;
+  }
+  // the committed macro strain and its last change are kept with the
+  // predictor off too, so that switching it on measures the next increment
+  // from the right base
+  if (lane == 0 && commit) {
+    double* ep = g.Ep + 12 * pt;
+    for (int c = 0; c < 6; ++c) {
+      ep[6 + c] = g.E[6 * pt + c] - ep[c];
+      ep[c] = g.E[6 * pt + c];
     }
   }
   D = wave_sum(D);
@@ -1563,6 +1566,11 @@ void dmn_online_destroy(DmnOnline* o) { delete o; }
 
 void dmn_online_set_predictor(DmnOnline* o, int on) {
   if (on != 0 && on != 1) fail(HOM_E_ARG, "predictor must be 0 or 1");
+  // jump changes are recorded only while the predictor is on: switching it
+  // on forgets what an earlier on-period left, so the first call starts from
+  // the current jumps
+  if (on && !o->pred)
+    hip_check(hipMemset(o->committed, 0, (size_t)o->npoints * sizeof(int)), "hipMemset");
   o->pred = on;
 }
 

@@ -291,3 +291,37 @@ def test_online_predictor_with_trial_steps():
     a.close()
     b.close()
     net.close()
+
+
+def test_online_predictor_switched_off_and_on_again_starts_over():
+    """An increment solved with the predictor off records no jump change: the
+    first call after switching it on again starts from the current jumps
+    (bitwise the run that stays off), the next one extrapolates again."""
+    rng = np.random.default_rng(34)
+    K = 5
+    m, v = random_params(K, rng)
+    net = _net(K, m, v)
+    d = rng.standard_normal((4, 6))
+    d /= np.linalg.norm(d, axis=1, keepdims=True)
+    a = hom.DmnOnline(net, W.e_glass(), W.pa66(), 4, tol=1e-12, predictor=True)
+    b = hom.DmnOnline(net, W.e_glass(), W.pa66(), 4, tol=1e-12, predictor=True)
+    for k in (1, 2, 3):
+        a.step(d * 0.006 * k, 300.0, 2.0)
+        b.step(d * 0.006 * k, 300.0, 2.0)
+    a.set_predictor(False)
+    b.set_predictor(False)
+    a.step(d * 0.024, 300.0, 2.0)
+    b.step(d * 0.024, 300.0, 2.0)
+    a.set_predictor(True)
+    ra = a.step(d * 0.030, 300.0, 2.0)
+    rb = b.step(d * 0.030, 300.0, 2.0)
+    assert (ra["status"] == hom.HOM_OK).all() and (rb["status"] == hom.HOM_OK).all()
+    assert np.array_equal(ra["stress"], rb["stress"])
+    assert np.array_equal(ra["newton_iters"], rb["newton_iters"])
+    ra = a.step(d * 0.036, 300.0, 2.0)
+    rb = b.step(d * 0.036, 300.0, 2.0)
+    assert np.abs(ra["stress"] - rb["stress"]).max() <= 1e-8 * np.abs(rb["stress"]).max()
+    assert int(ra["newton_iters"].sum()) <= int(rb["newton_iters"].sum())
+    a.close()
+    b.close()
+    net.close()
