@@ -356,7 +356,19 @@ def _check(code, msg_fn):
         raise HomError(code, msg_fn())
 
 
-class Context:
+class _Handle:
+    """Scope use of an owning handle: `with Context(...) as ctx:` closes it on
+    exit, also when the block raises."""
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+        return False
+
+
+class Context(_Handle):
     """One microstructure (hom_setup / hom_solve_increment / ...)."""
 
     def __init__(self, phases, laws, options: Options | None = None, lengths=(1.0, 1.0, 1.0), **opt_kw):
@@ -477,7 +489,7 @@ def _stats(fn, h):
     return {names[i].decode(): (int(launches[i]), float(ms[i])) for i in range(n)}
 
 
-class Batch:
+class Batch(_Handle):
     """Independent microproblems solved together (hom_batch_*)."""
 
     def __init__(self, phase_list, laws, options: Options | None = None, lengths=(1.0, 1.0, 1.0), **opt_kw):
@@ -585,7 +597,7 @@ def _f32(a):
     return np.ascontiguousarray(a, dtype=np.float32)
 
 
-class MLP:
+class MLP(_Handle):
     """The surrogate network (hom_mlp_*). Device arrays are torch tensors."""
 
     def __init__(self, n_in, n_out, seed=0):
@@ -741,7 +753,7 @@ def _mats(a, n=None):
     return a
 
 
-class Dmn:
+class Dmn(_Handle):
     """hom_dmn_*: a direct DMN of depth K (parameters m (2^K - 1, 3), v (2^K,))."""
 
     def __init__(self, K, seed=0):
@@ -805,7 +817,7 @@ class Dmn:
         return hist[:epochs]
 
 
-class DmnOnline:
+class DmnOnline(_Handle):
     """hom_dmn_online_*: a trained DMN at n_points macroscopic points with the
     laws of its two phases."""
 

@@ -7,7 +7,8 @@
   strain field must match the oracle's element by element;
 * a non-cubic grid (32 x 24 x 16) with unequal cell lengths;
 * a hold increment (macro strain unchanged): viscoelastic relaxation;
-* network inference on ragged and empty row counts.
+* network inference on ragged and empty row counts;
+* handles used as context managers are released at the end of the block.
 """
 import math
 
@@ -121,3 +122,19 @@ def test_network_ragged_and_empty_rows():
     with pytest.raises(hom.HomError) as e:       # an ensemble needs two networks at least
         hom.surrogate_infer_n([net], torch.as_tensor(x[:4], device="cuda"), 0.1, 1.0)
     assert e.value.code == hom.HOM_E_ARG
+
+
+def test_handles_close_at_the_end_of_a_with_block():
+    """Context and Dmn used as context managers release their handles on a
+    normal exit and when the block raises; close() twice is harmless."""
+    wl = W.small_sphere_workload()
+    with hom.Context(wl.phases, wl.laws) as ctx:
+        st = wl.history[0]
+        r = ctx.solve_increment(st.strain, st.theta, st.grad, st.dt)
+        assert r["status"] == hom.HOM_OK
+    assert ctx._h is None
+    ctx.close()
+    with pytest.raises(ValueError):
+        with hom.Dmn(K=2, seed=0) as net:
+            raise ValueError("leave the block")
+    assert net._h is None
