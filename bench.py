@@ -422,6 +422,46 @@ def mfma_summary(folder, command):
     print("\n".join(lines))
 
 
+PASS_COUNTERS = ("SQ_LDS_BANK_CONFLICT", "SQ_LDS_IDX_ACTIVE", "SQ_INSTS_LDS", "SQ_WAIT_INST_LDS",
+                 "SQ_ACTIVE_INST_VALU", "SQ_WAVE_CYCLES", "SQ_BUSY_CYCLES", "GRBM_GUI_ACTIVE")
+
+
+def pass_counter_summary(folder, command, out_name="pipeline_fibres256_lds_valu.md"):
+    """LDS and VALU counters of the four FFT pass kernels from one rocprofv3
+    --pmc run with PASS_COUNTERS. Derived figures follow rocprofv3's own
+    metric definitions, with GRBM_GUI_ACTIVE taken per XCD (the CSV holds the
+    sum over the 8 XCDs) and 256 compute units:
+    LdsBankConflict = bank-conflict cycles / (LDS active cycles - bank-conflict cycles),
+    LdsUtil = LDS active cycles / (GUI active x 256), VALUBusy = VALU active
+    cycles / (GUI active x 256), and the share of wave cycles spent waiting to
+    issue an LDS instruction."""
+    rows = _counter_rows(folder)
+    per = {c: _per_kernel(rows, c) for c in PASS_COUNTERS}
+    lines = ["# LDS and VALU counters of the FFT pass kernels (256^3 fibre composite, FP32 fields)", "",
+             f"command: {command}", "",
+             "Per launch, averaged over the run's launches of each kernel. LdsBankConflict = SQ_LDS_BANK_CONFLICT / "
+             "(SQ_LDS_IDX_ACTIVE - SQ_LDS_BANK_CONFLICT); LdsUtil = SQ_LDS_IDX_ACTIVE / (GUI x 256 CUs); "
+             "VALUBusy = SQ_ACTIVE_INST_VALU / (GUI x 256 CUs); GUI = GRBM_GUI_ACTIVE / 8 XCDs; "
+             "LDS wait = SQ_WAIT_INST_LDS / SQ_WAVE_CYCLES.", "",
+             "| kernel | launches | LDS instructions | LdsBankConflict | LdsUtil % | VALUBusy % | LDS wait % | "
+             "GUI cycles per XCD |", "|---|---|---|---|---|---|---|---|"]
+    names = [k for k in per["GRBM_GUI_ACTIVE"]
+             if any(p in k for p in ("k_xfwd<float, 6", "k_ypass<float, 6", "k_zgreen<float, 6", "k_xinv<float, 6"))]
+    for k in sorted(names):
+        if any(k not in per[c] for c in PASS_COUNTERS):
+            continue
+        m = {c: float(np.mean(per[c][k])) for c in PASS_COUNTERS}
+        gui = m["GRBM_GUI_ACTIVE"] / 8
+        conf = m["SQ_LDS_BANK_CONFLICT"] / max(m["SQ_LDS_IDX_ACTIVE"] - m["SQ_LDS_BANK_CONFLICT"], 1.0)
+        lines.append(f"| {k.split('(')[0].replace('void ', '')} | {len(per['GRBM_GUI_ACTIVE'][k])} | "
+                     f"{m['SQ_INSTS_LDS']:.4g} | {conf:.3f} | {100 * m['SQ_LDS_IDX_ACTIVE'] / (gui * 256):.1f} | "
+                     f"{100 * m['SQ_ACTIVE_INST_VALU'] / (gui * 256):.1f} | "
+                     f"{100 * m['SQ_WAIT_INST_LDS'] / max(m['SQ_WAVE_CYCLES'], 1.0):.1f} | {gui:.4g} |")
+    with open(os.path.join(ROOT, "profiles", out_name), "w") as fo:
+        fo.write("\n".join(lines) + "\n")
+    print("\n".join(lines))
+
+
 def dmn_bench(n=128, samples=160, epochs=3000, K=8, points=4096, seed=7):
     """The direct DMN pipeline of Sec. 3 on one fibre microstructure:
     stiffness samples -> effective stiffnesses by the FFT solver (FP32,
@@ -626,6 +666,8 @@ def main():
                     help="summarize rocprofv3 --pmc output folders (FETCH_SIZE, WRITE_SIZE[, request sizes]) "
                          "into profiles/ (no GPU needed)")
     ap.add_argument("--mfma-summary", metavar="DIR", help="summarize an MFMA --pmc run into profiles/")
+    ap.add_argument("--pass-counter-summary", metavar="DIR",
+                    help="summarize a --pmc run with the LDS/VALU counters of the FFT passes into profiles/")
     ap.add_argument("--pmc-command", default="", help="command line recorded in the summary")
     ap.add_argument("--pmc-log", help="stdout of the profiled bench run (restricts averages to its timed launches)")
     ap.add_argument("--trace-summary", nargs=2, metavar=("TRACE_DIR", "LOG"),
@@ -640,6 +682,9 @@ def main():
         return
     if args.mfma_summary:
         mfma_summary(args.mfma_summary, args.pmc_command)
+        return
+    if args.pass_counter_summary:
+        pass_counter_summary(args.pass_counter_summary, args.pmc_command)
         return
     if args.network_only:
         network_only()
