@@ -426,7 +426,7 @@ PASS_COUNTERS = ("SQ_LDS_BANK_CONFLICT", "SQ_LDS_IDX_ACTIVE", "SQ_INSTS_LDS", "S
                  "SQ_ACTIVE_INST_VALU", "SQ_WAVE_CYCLES", "SQ_BUSY_CYCLES", "GRBM_GUI_ACTIVE")
 
 
-def pass_counter_summary(folder, command, out_name="pipeline_fibres256_lds_valu.md"):
+def pass_counter_summary(folder, command, out_path=None):
     """LDS and VALU counters of the four FFT pass kernels from one rocprofv3
     --pmc run with PASS_COUNTERS. Derived figures follow rocprofv3's own
     metric definitions, with GRBM_GUI_ACTIVE taken per XCD (the CSV holds the
@@ -457,9 +457,11 @@ def pass_counter_summary(folder, command, out_name="pipeline_fibres256_lds_valu.
                      f"{m['SQ_INSTS_LDS']:.4g} | {conf:.3f} | {100 * m['SQ_LDS_IDX_ACTIVE'] / (gui * 256):.1f} | "
                      f"{100 * m['SQ_ACTIVE_INST_VALU'] / (gui * 256):.1f} | "
                      f"{100 * m['SQ_WAIT_INST_LDS'] / max(m['SQ_WAVE_CYCLES'], 1.0):.1f} | {gui:.4g} |")
-    with open(os.path.join(ROOT, "profiles", out_name), "w") as fo:
+    out_path = out_path or os.path.join(ROOT, "profiles", "pipeline_fibres256_lds_valu.md")
+    with open(out_path, "w") as fo:
         fo.write("\n".join(lines) + "\n")
     print("\n".join(lines))
+    return lines
 
 
 def dmn_bench(n=128, samples=160, epochs=3000, K=8, points=4096, seed=7):

@@ -49,3 +49,26 @@ def test_more_than_one_gpu_is_refused():
                        text=True, timeout=120, cwd=ROOT)
     assert p.returncode == 2
     assert "one GPU" in p.stdout
+
+
+def test_pass_counter_summary_derives_rocprof_metrics(tmp_path):
+    """LdsBankConflict, LdsUtil, VALUBusy and the LDS-wait share from
+    per-dispatch counters, with GRBM_GUI_ACTIVE summed over 8 XCDs."""
+    import csv
+    src = tmp_path / "pmc"
+    src.mkdir()
+    vals = {"SQ_LDS_BANK_CONFLICT": 100, "SQ_LDS_IDX_ACTIVE": 1100, "SQ_INSTS_LDS": 5000, "SQ_WAIT_INST_LDS": 50,
+            "SQ_ACTIVE_INST_VALU": 12800, "SQ_WAVE_CYCLES": 1000, "SQ_BUSY_CYCLES": 10, "GRBM_GUI_ACTIVE": 800}
+    with open(src / "run_counter_collection.csv", "w", newline="") as f:
+        w = csv.DictWriter(f, fieldnames=["Dispatch_Id", "Kernel_Name", "Counter_Name", "Counter_Value"])
+        w.writeheader()
+        for d, name in enumerate(["void hom::k_zgreen<float, 6, 256, 2>(hom::Pipe<float>)",
+                                  "void hom::k_mlp_fwd<0>(hom::FwdArgs)"]):
+            for c, v in vals.items():
+                w.writerow(dict(Dispatch_Id=d, Kernel_Name=name, Counter_Name=c, Counter_Value=v))
+    lines = bench.pass_counter_summary(str(src), "cmd", out_path=str(tmp_path / "out.md"))
+    rows = [l for l in lines if l.startswith("| hom::")]
+    assert len(rows) == 1 and "k_zgreen" in rows[0]            # pass kernels only
+    cells = [c.strip() for c in rows[0].strip("|").split("|")]
+    # 100 / (1100 - 100); 100 * 1100 / (100 * 256); 100 * 12800 / (100 * 256); 100 * 50 / 1000
+    assert cells[1:] == ["1", "5000", "0.100", "4.3", "50.0", "5.0", "100"]
