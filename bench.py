@@ -389,11 +389,11 @@ def network_only(rows=65536, reps=50):
     nets = [hom.MLP(32, 10, seed=s) for s in (0, 1)]
     x = torch.randn(rows, 32, device="cuda")
     for _ in range(5):
-        hom.surrogate_infer(nets[0], nets[1], x, 0.0, 1.0)
+        hom.mlp_ensemble_infer(nets, x, 0.0, 1.0)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(reps):
-        hom.surrogate_infer(nets[0], nets[1], x, 0.0, 1.0)
+        hom.mlp_ensemble_infer(nets, x, 0.0, 1.0)
     torch.cuda.synchronize()
     ms = (time.perf_counter() - t0) / reps * 1e3
     flops = 2 * rows * 2 * NETWORK_PARAMS_MACS

@@ -331,23 +331,17 @@ int hom_mlp_forward(hom_mlp* net, const float* x_dev, float* y_dev, int64_t n, i
  * hom_mlp_param_count entries. */
 int hom_mlp_loss_grad(hom_mlp* net, const float* x, const float* y, int64_t n, int32_t precise, double* loss,
                       float* grad);
-/* Two-network inference with acceptance: y = mean of the two networks,
- * spread = |stress_a - stress_b| / max(|stress|, floor_scale) over the first
- * six outputs, accept = spread <= threshold. All arrays on the device; n = 0
- * returns HOM_OK without touching them. */
-int hom_surrogate_infer(hom_mlp* a, hom_mlp* b, const float* x_dev, float* y_dev, float* spread_dev,
-                        uint8_t* accept_dev, int64_t n, double threshold, double floor_scale, void* stream);
-/* Ensemble inference with acceptance for 2 .. HOM_SURROGATE_MAX_NETS networks
+/* Ensemble inference with acceptance for 2 .. HOM_ENSEMBLE_MAX_NETS networks
  * of the same shape: y = mean of the networks; spread = RMS pairwise distance
  * of the stress outputs (the first six), sqrt(2 / (M - 1) sum_m |s_m - s|^2)
  * with s their mean, over max(|s|, floor_scale); accept = spread <= threshold.
- * For two networks this is hom_surrogate_infer's spread. All arrays on the
- * device; n = 0 returns HOM_OK without touching them. The first network keeps
- * a device scratch of n * count * n_out floats between calls, so calls that
- * share a first network must not overlap. */
-#define HOM_SURROGATE_MAX_NETS 16
-int hom_surrogate_infer_n(hom_mlp* const* nets, int32_t count, const float* x_dev, float* y_dev, float* spread_dev,
-                          uint8_t* accept_dev, int64_t n, double threshold, double floor_scale, void* stream);
+ * For two networks the spread is |s_a - s_b| / max(|s|, floor_scale). All
+ * arrays on the device; n = 0 returns HOM_OK without touching them. The first
+ * network keeps a device scratch of n * count * n_out floats between calls
+ * (grown on demand), so calls that share a first network must not overlap. */
+#define HOM_ENSEMBLE_MAX_NETS 16
+int hom_mlp_ensemble_infer(hom_mlp* const* nets, int32_t count, const float* x_dev, float* y_dev, float* spread_dev,
+                           uint8_t* accept_dev, int64_t n, double threshold, double floor_scale, void* stream);
 const char* hom_mlp_last_error(const hom_mlp* net);
 void hom_mlp_destroy(hom_mlp* net);
 

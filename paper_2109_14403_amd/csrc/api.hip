@@ -29,7 +29,7 @@ struct hom_dmn_online {
 struct hom_mlp {
   std::unique_ptr<hom::Mlp> net;
   std::string err;
-  float* scratch = nullptr;  // per-network outputs of hom_surrogate_infer(_n)
+  float* scratch = nullptr;  // per-network outputs of hom_mlp_ensemble_infer
   size_t scratch_floats = 0;
   ~hom_mlp() {
     if (scratch) (void)hipFree(scratch);
@@ -450,40 +450,24 @@ int hom_mlp_loss_grad(hom_mlp* m, const float* x, const float* y, int64_t n, int
 }
 
 
-int hom_surrogate_infer(hom_mlp* a, hom_mlp* b, const float* x_dev, float* y_dev, float* spread_dev,
-                        uint8_t* accept_dev, int64_t n, double threshold, double floor_scale, void* stream) {
-  if (!a || !b || !a->net || !b->net || n < 0) return HOM_E_ARG;
-  if (n == 0) return HOM_OK;  // nothing to do (the arrays may be empty)
-  if (!x_dev || !y_dev || !spread_dev || !accept_dev) return HOM_E_ARG;
-  return guarded(&a->err, [&] {
-    if (a->net->n_in != b->net->n_in || a->net->n_out != b->net->n_out) hom::fail(HOM_E_ARG, "network shapes differ");
-    grow_scratch(a, (size_t)n * 2 * a->net->n_out);
-    float* ya = a->scratch;
-    float* yb = a->scratch + (size_t)n * a->net->n_out;
-    hom::surrogate_accept(*a->net, *b->net, x_dev, y_dev, ya, yb, spread_dev, accept_dev, n, (float)threshold,
-                          (float)floor_scale, static_cast<hipStream_t>(stream));
-    hom::hip_check(hipGetLastError(), "surrogate launch");
-  });
-}
-
-int hom_surrogate_infer_n(hom_mlp* const* nets, int32_t count, const float* x_dev, float* y_dev, float* spread_dev,
-                          uint8_t* accept_dev, int64_t n, double threshold, double floor_scale, void* stream) {
-  if (!nets || count < 2 || count > HOM_SURROGATE_MAX_NETS || n < 0) return HOM_E_ARG;
+int hom_mlp_ensemble_infer(hom_mlp* const* nets, int32_t count, const float* x_dev, float* y_dev, float* spread_dev,
+                           uint8_t* accept_dev, int64_t n, double threshold, double floor_scale, void* stream) {
+  if (!nets || count < 2 || count > HOM_ENSEMBLE_MAX_NETS || n < 0) return HOM_E_ARG;
   for (int m = 0; m < count; ++m)
     if (!nets[m] || !nets[m]->net) return HOM_E_ARG;
   if (n == 0) return HOM_OK;  // nothing to do (the arrays may be empty)
   if (!x_dev || !y_dev || !spread_dev || !accept_dev) return HOM_E_ARG;
   hom_mlp* a = nets[0];
   return guarded(&a->err, [&] {
-    const hom::Mlp* nv[HOM_SURROGATE_MAX_NETS];
+    const hom::Mlp* nv[HOM_ENSEMBLE_MAX_NETS];
     for (int m = 0; m < count; ++m) {
       nv[m] = nets[m]->net.get();
       if (nv[m]->n_in != nv[0]->n_in || nv[m]->n_out != nv[0]->n_out) hom::fail(HOM_E_ARG, "network shapes differ");
     }
     grow_scratch(a, (size_t)n * count * nv[0]->n_out);
-    hom::surrogate_accept_n(nv, count, x_dev, y_dev, a->scratch, spread_dev, accept_dev, n, (float)threshold,
+    hom::ensemble_accept(nv, count, x_dev, y_dev, a->scratch, spread_dev, accept_dev, n, (float)threshold,
                             (float)floor_scale, static_cast<hipStream_t>(stream));
-    hom::hip_check(hipGetLastError(), "surrogate launch");
+    hom::hip_check(hipGetLastError(), "ensemble launch");
   });
 }
 

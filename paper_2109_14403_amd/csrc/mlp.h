@@ -83,9 +83,7 @@ struct Mlp {
 };
 
 // ys: scratch [M][n][n_out]
-void surrogate_accept_n(const Mlp* const* nets, int M, const float* x, float* y, float* ys, float* spread,
-                        uint8_t* accept, long long n, float thr, float floor_scale, hipStream_t s);
-void surrogate_accept(const Mlp& a, const Mlp& b, const float* x, float* y, float* ya, float* yb, float* spread,
-                      uint8_t* accept, long long n, float thr, float floor_scale, hipStream_t s);
+void ensemble_accept(const Mlp* const* nets, int M, const float* x, float* y, float* ys, float* spread,
+                     uint8_t* accept, long long n, float thr, float floor_scale, hipStream_t s);
 
 }  // namespace hom

@@ -366,26 +366,6 @@ __global__ void k_gather(const float* src, int cols, const int* idx, long long c
   dst[i] = src[(long long)idx[r] * cols + c];
 }
 
-// ensemble mean, spread of the stress outputs, acceptance
-__global__ void k_accept(const float* ya, const float* yb, long long n, int n_out, float* y, float* spread,
-                         uint8_t* accept, float thr, float floor_scale) {
-  const long long r = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (r >= n) return;
-  float d2 = 0.f, m2 = 0.f;
-  for (int j = 0; j < n_out; ++j) {
-    const float p = ya[r * n_out + j], q = yb[r * n_out + j];
-    const float mean = 0.5f * (p + q);
-    y[r * n_out + j] = mean;
-    if (j < 6) {
-      d2 += (p - q) * (p - q);
-      m2 += mean * mean;
-    }
-  }
-  const float s = sqrtf(d2) / fmaxf(sqrtf(m2), floor_scale);
-  spread[r] = s;
-  accept[r] = s <= thr ? 1 : 0;
-}
-
 // M networks: y = mean, spread = RMS pairwise distance of the stress outputs
 // (sqrt(2 / (M - 1) sum_m |s_m - s_mean|^2), |s_a - s_b| for two networks)
 // over max(|s_mean|, floor_scale)
@@ -987,20 +967,12 @@ void Mlp::train(const float* X, const float* T, long long n, int epochs, int bat
   }
 }
 
-void surrogate_accept_n(const Mlp* const* nets, int M, const float* x, float* y, float* ys, float* spread,
+void ensemble_accept(const Mlp* const* nets, int M, const float* x, float* y, float* ys, float* spread,
                         uint8_t* accept, long long n, float thr, float floor_scale, hipStream_t s) {
   const int n_out = nets[0]->n_out;
   for (int m = 0; m < M; ++m)
     const_cast<Mlp*>(nets[m])->forward(x, ys + (size_t)m * n * n_out, n, false, false, s);
   hipLaunchKernelGGL(k_accept_n, dim3((n + 255) / 256), dim3(256), 0, s, ys, M, n, n_out, y, spread, accept, thr,
-                     floor_scale);
-}
-
-void surrogate_accept(const Mlp& a, const Mlp& b, const float* x, float* y, float* ya, float* yb, float* spread,
-                      uint8_t* accept, long long n, float thr, float floor_scale, hipStream_t s) {
-  const_cast<Mlp&>(a).forward(x, ya, n, false, false, s);
-  const_cast<Mlp&>(b).forward(x, yb, n, false, false, s);
-  hipLaunchKernelGGL(k_accept, dim3((n + 255) / 256), dim3(256), 0, s, ya, yb, n, a.n_out, y, spread, accept, thr,
                      floor_scale);
 }
 

@@ -182,7 +182,7 @@ EXPORTS = (
     "hom_mlp_create", "hom_mlp_param_count", "hom_mlp_set_scaling", "hom_mlp_set_skip", "hom_mlp_fit_skip",
     "hom_mlp_get_params",
     "hom_mlp_set_params",
-    "hom_mlp_train", "hom_mlp_forward", "hom_mlp_loss_grad", "hom_surrogate_infer", "hom_surrogate_infer_n",
+    "hom_mlp_train", "hom_mlp_forward", "hom_mlp_loss_grad", "hom_mlp_ensemble_infer",
     "hom_mlp_last_error",
     "hom_mlp_destroy",
 )
@@ -276,11 +276,9 @@ def library(path: str | None = None):
                                   fp, fp]
     lib.hom_mlp_forward.argtypes = [ct.c_void_p, ct.c_void_p, ct.c_void_p, ct.c_int64, ct.c_int32, ct.c_void_p]
     lib.hom_mlp_loss_grad.argtypes = [ct.c_void_p, fp, fp, ct.c_int64, ct.c_int32, ct.POINTER(ct.c_double), fp]
-    lib.hom_surrogate_infer.argtypes = [ct.c_void_p, ct.c_void_p, ct.c_void_p, ct.c_void_p, ct.c_void_p,
-                                        ct.c_void_p, ct.c_int64, ct.c_double, ct.c_double, ct.c_void_p]
-    lib.hom_surrogate_infer_n.argtypes = [ct.POINTER(ct.c_void_p), ct.c_int32, ct.c_void_p, ct.c_void_p,
-                                          ct.c_void_p, ct.c_void_p, ct.c_int64, ct.c_double, ct.c_double,
-                                          ct.c_void_p]
+    lib.hom_mlp_ensemble_infer.argtypes = [ct.POINTER(ct.c_void_p), ct.c_int32, ct.c_void_p, ct.c_void_p,
+                                           ct.c_void_p, ct.c_void_p, ct.c_int64, ct.c_double, ct.c_double,
+                                           ct.c_void_p]
     lib.hom_mlp_last_error.argtypes = [ct.c_void_p]
     lib.hom_mlp_last_error.restype = ct.c_char_p
     lib.hom_mlp_destroy.argtypes = [ct.c_void_p]
@@ -701,26 +699,9 @@ class MLP(_Handle):
         return L.value, g
 
 
-def surrogate_infer(net_a: MLP, net_b: MLP, x_dev, threshold, floor_scale):
-    """Two-network inference with acceptance on device tensors; returns
-    (y, spread, accept) tensors."""
-    import torch
-    n = x_dev.shape[0]
-    y = torch.empty((n, net_a.n_out), dtype=torch.float32, device=x_dev.device)
-    spread = torch.empty(n, dtype=torch.float32, device=x_dev.device)
-    acc = torch.empty(n, dtype=torch.uint8, device=x_dev.device)
-    lib = library()
-    _check(lib.hom_surrogate_infer(net_a._h, net_b._h, ct.c_void_p(x_dev.data_ptr()), ct.c_void_p(y.data_ptr()),
-                                   ct.c_void_p(spread.data_ptr()), ct.c_void_p(acc.data_ptr()), n, threshold,
-                                   floor_scale, ct.c_void_p(torch.cuda.current_stream().cuda_stream)),
-           net_a.error)
-    return y, spread, acc
-
-
-def surrogate_infer_n(nets, x_dev, threshold, floor_scale):
+def mlp_ensemble_infer(nets, x_dev, threshold, floor_scale):
     """Ensemble inference with acceptance (2 .. 16 networks) on device tensors;
-    returns (y, spread, accept) tensors. Two networks give surrogate_infer's
-    spread."""
+    returns (y, spread, accept) tensors."""
     import torch
     n = x_dev.shape[0]
     y = torch.empty((n, nets[0].n_out), dtype=torch.float32, device=x_dev.device)
@@ -728,7 +709,7 @@ def surrogate_infer_n(nets, x_dev, threshold, floor_scale):
     acc = torch.empty(n, dtype=torch.uint8, device=x_dev.device)
     handles = (ct.c_void_p * len(nets))(*[net._h.value if isinstance(net._h, ct.c_void_p) else net._h for net in nets])
     lib = library()
-    _check(lib.hom_surrogate_infer_n(handles, len(nets), ct.c_void_p(x_dev.data_ptr()), ct.c_void_p(y.data_ptr()),
+    _check(lib.hom_mlp_ensemble_infer(handles, len(nets), ct.c_void_p(x_dev.data_ptr()), ct.c_void_p(y.data_ptr()),
                                      ct.c_void_p(spread.data_ptr()), ct.c_void_p(acc.data_ptr()), n, threshold,
                                      floor_scale, ct.c_void_p(torch.cuda.current_stream().cuda_stream)),
            nets[0].error)

@@ -176,7 +176,7 @@ class Surrogate:
     def infer(self, X_dev):
         """Device tensor [n, 32] -> (y, spread, accept) device tensors."""
         thr = self.threshold if self.threshold is not None else 0.0
-        return hom.surrogate_infer_n(self.nets, X_dev, thr, self.floor)
+        return hom.mlp_ensemble_infer(self.nets, X_dev, thr, self.floor)
 
     def calibrate(self, X, Y, denom, target=1e-3, quantile=1.0):
         """Largest spread threshold under which the accepted validation rows all

@@ -115,12 +115,12 @@ def test_network_ragged_and_empty_rows():
     empty = torch.empty((0, 32), dtype=torch.float32, device="cuda")
     out = torch.empty((0, 10), dtype=torch.float32, device="cuda")
     net.forward_device(empty, out)
-    y, spread, acc = hom.surrogate_infer(net, net, empty, 0.1, 1.0)
+    y, spread, acc = hom.mlp_ensemble_infer([net, net], empty, 0.1, 1.0)
     assert y.shape == (0, 10) and spread.shape == (0,) and acc.shape == (0,)
-    y, spread, acc = hom.surrogate_infer_n([net, net, net], empty, 0.1, 1.0)
+    y, spread, acc = hom.mlp_ensemble_infer([net, net, net], empty, 0.1, 1.0)
     assert y.shape == (0, 10) and spread.shape == (0,) and acc.shape == (0,)
     with pytest.raises(hom.HomError) as e:       # an ensemble needs two networks at least
-        hom.surrogate_infer_n([net], torch.as_tensor(x[:4], device="cuda"), 0.1, 1.0)
+        hom.mlp_ensemble_infer([net], torch.as_tensor(x[:4], device="cuda"), 0.1, 1.0)
     assert e.value.code == hom.HOM_E_ARG
 
 

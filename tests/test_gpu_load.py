@@ -7,7 +7,8 @@ the library takes secant steps).
 
 Bounds: FP64 fields 1e-6 relative (stress to its largest component, strain
 to its largest component, theta to its change over the increment); FP32
-fields 2e-4 like the increment parity.
+fields 2e-6 like the increment parity, except theta: 1e-5 of its change
+(measured 1.3e-6: the staggering stops at 10 tol of that change).
 """
 import numpy as np
 import pytest
@@ -51,8 +52,8 @@ def plastic_cell(n, seed=4):
     return (rng.random((n, n, n)) < 0.3).astype(np.uint8), [W.pa66(), W.e_glass()]
 
 
-@pytest.mark.parametrize("precision,steps,bound", [(hom.FP64, 5, 1e-6), (hom.FP32, 3, 2e-4)])
-def test_plastic_mixed_adiabatic_matches_oracle(precision, steps, bound):
+@pytest.mark.parametrize("precision,steps,bound,theta_bound", [(hom.FP64, 5, 1e-6, 1e-6), (hom.FP32, 3, 2e-6, 1e-5)])
+def test_plastic_mixed_adiabatic_matches_oracle(precision, steps, bound, theta_bound):
     n = 16
     img, laws = plastic_cell(n)
     tol = 1e-10 if precision == hom.FP64 else 1e-6
@@ -67,7 +68,7 @@ def test_plastic_mixed_adiabatic_matches_oracle(precision, steps, bound):
         print(f"n={n} inc {k}: stress {es:.2e} strain {ee:.2e} theta {et:.2e} coupling {ec:.2e} "
               f"theta {g['theta']:.6f} stagger {g['stagger_iters']} newton {g['newton_iters']} "
               f"krylov {g['krylov_iters']}", flush=True)
-        assert es <= bound and ee <= bound and et <= bound and ec <= bound
+        assert es <= bound and ee <= bound and et <= theta_bound and ec <= bound
         assert g["stagger_iters"] >= 2
         theta_g, theta_o = g["theta"], o["theta"]
     assert o["dissipation"] > 0.0 and g["dissipation"] > 0.0

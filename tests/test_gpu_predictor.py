@@ -13,6 +13,7 @@ import numpy as np
 import pytest
 
 from paper_2109_14403_amd import hom
+from test_gpu_solver import FP32_BOUND
 from paper_2109_14403_amd import workloads as W
 
 pytestmark = pytest.mark.gpu
@@ -25,15 +26,20 @@ def run(wl, predictor, steps, precision=hom.FP64, tol=1e-10):
     return ctx, out
 
 
-@pytest.mark.parametrize("precision,tol,bound", [(hom.FP64, 1e-10, 1e-7), (hom.FP32, 1e-6, 2e-4)])
+# two solves that each meet the parity bound differ by twice it at most
+@pytest.mark.parametrize("precision,tol,bound", [(hom.FP64, 1e-10, 1e-7), (hom.FP32, 1e-6, 2 * FP32_BOUND)])
 def test_same_increments_fewer_iterations(precision, tol, bound):
     wl = W.sphere_composite_workload(32, seed=2)
     c0, a = run(wl, 0, 8, precision, tol)
     c1, b = run(wl, 1, 8, precision, tol)
+    dmax = max(max(abs(x["dissipation"]) for x in a), 1e-12)
     for k, (x, y) in enumerate(zip(a, b)):
         scale = np.abs(x["stress"]).max()
-        assert np.abs(x["stress"] - y["stress"]).max() <= bound * scale, k
-        assert abs(x["dissipation"] - y["dissipation"]) <= bound * max(abs(x["dissipation"]), 1e-12), k
+        ds = np.abs(x["stress"] - y["stress"]).max() / scale
+        dd = abs(x["dissipation"] - y["dissipation"]) / dmax
+        print(f"precision {precision} inc {k}: stress {ds:.2e} dissipation {dd:.2e}", flush=True)
+        assert ds <= bound, k
+        assert dd <= bound, k
     na = sum(r["newton_iters"] for r in a[1:])
     nb = sum(r["newton_iters"] for r in b[1:])
     ka = sum(r["krylov_iters"] for r in a[1:])

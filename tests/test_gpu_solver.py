@@ -3,7 +3,11 @@
 FP64 runs must match the oracle within 1e-5 relative on the effective
 quantities; FP32 runs (FP32 fields, FP64 reductions and return mapping)
 within the bound FP32_BOUND below (relative to the largest stress component
-of the history)."""
+of the history). The bound is stated from measurement: at Newton tolerance
+1e-6 the FP32 effective stress, heat flux and coupling term sit within
+1.3e-7 of the FP64 oracle and the dissipation within 6.8e-7 (the whole
+20-increment cyclic history of the 32^3 sphere composite, the batch, the
+64^3 composite); 2e-6 leaves a factor of three over the worst of them."""
 import numpy as np
 import pytest
 
@@ -13,7 +17,7 @@ from paper_2109_14403_amd import workloads as W
 
 pytestmark = pytest.mark.gpu
 
-FP32_BOUND = 2e-4
+FP32_BOUND = 2e-6
 
 
 def compare(g, o, scale, rtol, label):

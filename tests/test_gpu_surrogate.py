@@ -76,17 +76,15 @@ def test_mean_and_spread_definition(trained):
 def test_two_network_ensemble_is_the_pair_rule(trained):
     sur, _, X, _, _, tr = trained
     xd = torch.as_tensor(X[~tr][:777], device="cuda")
-    y2, s2, a2 = hom.surrogate_infer(sur.nets[0], sur.nets[1], xd, 0.01, sur.floor)
-    yn, sn, an = hom.surrogate_infer_n(sur.nets[:2], xd, 0.01, sur.floor)
+    yn, sn, an = hom.mlp_ensemble_infer(sur.nets[:2], xd, 0.01, sur.floor)
     torch.cuda.synchronize()
     ya, yb = sur.nets[0].forward(X[~tr][:777]), sur.nets[1].forward(X[~tr][:777])
     d = np.linalg.norm(ya[:, :6] - yb[:, :6], axis=1)
     m = np.maximum(np.linalg.norm(0.5 * (ya + yb)[:, :6], axis=1), sur.floor)
-    np.testing.assert_allclose(s2.cpu().numpy(), d / m, rtol=1e-4, atol=1e-7)
-    np.testing.assert_allclose(yn.cpu().numpy(), y2.cpu().numpy(), rtol=1e-6, atol=1e-6)
-    np.testing.assert_allclose(sn.cpu().numpy(), s2.cpu().numpy(), rtol=1e-4, atol=1e-7)
-    near = np.abs(s2.cpu().numpy() - 0.01) < 1e-6      # ties at the threshold may round either way
-    np.testing.assert_array_equal(an.cpu().numpy()[~near], a2.cpu().numpy()[~near])
+    np.testing.assert_allclose(yn.cpu().numpy(), 0.5 * (ya + yb), rtol=1e-6, atol=1e-6)
+    np.testing.assert_allclose(sn.cpu().numpy(), d / m, rtol=1e-4, atol=1e-7)
+    near = np.abs(d / m - 0.01) < 1e-6      # ties at the threshold may round either way
+    np.testing.assert_array_equal(an.cpu().numpy()[~near], (d / m <= 0.01)[~near])
 
 
 def test_calibrated_acceptance_and_fallback(trained):
