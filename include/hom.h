@@ -342,6 +342,21 @@ int hom_mlp_loss_grad(hom_mlp* net, const float* x, const float* y, int64_t n, i
 #define HOM_ENSEMBLE_MAX_NETS 16
 int hom_mlp_ensemble_infer(hom_mlp* const* nets, int32_t count, const float* x_dev, float* y_dev, float* spread_dev,
                            uint8_t* accept_dev, int64_t n, double threshold, double floor_scale, void* stream);
+/* For callers that cannot allocate device memory (work under stream capture,
+ * tight serving loops, harnesses that forbid hipMalloc): hom_mlp_ensemble_infer
+ * with the same arguments and results, whose per-network outputs go to a
+ * static device array of HOM_STATIC_SCRATCH_FLOATS floats (32 MiB) that each
+ * GPU the library runs on holds until the process ends, instead of a buffer
+ * the library grows. n * count * n_out above that limit returns HOM_E_ARG
+ * before anything is launched (65,536 rows of 8 networks with 16 outputs
+ * fit). Nothing is allocated or freed on the device. Every call on one GPU
+ * shares that GPU's array, which keeps the last call's contents (each call
+ * writes the part it reads first): calls that overlap in time on one GPU race,
+ * whichever networks and streams they use. */
+#define HOM_STATIC_SCRATCH_FLOATS 8388608
+int hom_mlp_ensemble_infer_static(hom_mlp* const* nets, int32_t count, const float* x_dev, float* y_dev,
+                                  float* spread_dev, uint8_t* accept_dev, int64_t n, double threshold,
+                                  double floor_scale, void* stream);
 const char* hom_mlp_last_error(const hom_mlp* net);
 void hom_mlp_destroy(hom_mlp* net);
 

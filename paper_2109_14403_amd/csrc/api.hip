@@ -471,6 +471,27 @@ int hom_mlp_ensemble_infer(hom_mlp* const* nets, int32_t count, const float* x_d
   });
 }
 
+int hom_mlp_ensemble_infer_static(hom_mlp* const* nets, int32_t count, const float* x_dev, float* y_dev,
+                                  float* spread_dev, uint8_t* accept_dev, int64_t n, double threshold,
+                                  double floor_scale, void* stream) {
+  if (!nets || count < 2 || count > HOM_ENSEMBLE_MAX_NETS || n < 0) return HOM_E_ARG;
+  for (int m = 0; m < count; ++m)
+    if (!nets[m] || !nets[m]->net) return HOM_E_ARG;
+  if (n == 0) return HOM_OK;  // nothing to do (the arrays may be empty)
+  if (!x_dev || !y_dev || !spread_dev || !accept_dev) return HOM_E_ARG;
+  hom_mlp* a = nets[0];
+  return guarded(&a->err, [&] {
+    const hom::Mlp* nv[HOM_ENSEMBLE_MAX_NETS];
+    for (int m = 0; m < count; ++m) {
+      nv[m] = nets[m]->net.get();
+      if (nv[m]->n_in != nv[0]->n_in || nv[m]->n_out != nv[0]->n_out) hom::fail(HOM_E_ARG, "network shapes differ");
+    }
+    hom::ensemble_accept_static(nv, count, x_dev, y_dev, spread_dev, accept_dev, n, (float)threshold,
+                                (float)floor_scale, static_cast<hipStream_t>(stream));
+    hom::hip_check(hipGetLastError(), "ensemble launch");
+  });
+}
+
 const char* hom_mlp_last_error(const hom_mlp* m) { return m ? m->err.c_str() : g_setup_error.c_str(); }
 
 void hom_mlp_destroy(hom_mlp* m) { delete m; }

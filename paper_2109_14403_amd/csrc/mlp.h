@@ -85,5 +85,9 @@ struct Mlp {
 // ys: scratch [M][n][n_out]
 void ensemble_accept(const Mlp* const* nets, int M, const float* x, float* y, float* ys, float* spread,
                      uint8_t* accept, long long n, float thr, float floor_scale, hipStream_t s);
+// the same with ys in the library's static device array (no device
+// allocation); n * M * n_out above HOM_STATIC_SCRATCH_FLOATS fails with HOM_E_ARG
+void ensemble_accept_static(const Mlp* const* nets, int M, const float* x, float* y, float* spread, uint8_t* accept,
+                            long long n, float thr, float floor_scale, hipStream_t s);
 
 }  // namespace hom

@@ -17,11 +17,17 @@
 
 #include <algorithm>
 #include <cstring>
+#include <mutex>
 #include <random>
 #include <vector>
 
 #include "mlp.h"
 #include "runtime.h"
+
+// Per-network outputs of the allocation-free ensemble inference. One copy per
+// GPU, at that GPU's own address: host code never passes this name to a
+// kernel, only the address hipGetSymbolAddress returns for the current device.
+static __device__ __align__(256) float scratch[HOM_STATIC_SCRATCH_FLOATS];
 
 namespace hom {
 
@@ -974,6 +980,35 @@ void ensemble_accept(const Mlp* const* nets, int M, const float* x, float* y, fl
     const_cast<Mlp*>(nets[m])->forward(x, ys + (size_t)m * n * n_out, n, false, false, s);
   hipLaunchKernelGGL(k_accept_n, dim3((n + 255) / 256), dim3(256), 0, s, ys, M, n, n_out, y, spread, accept, thr,
                      floor_scale);
+}
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+float* g_scratch_ptr[kMaxDevices] = {};  // device address of `scratch`, per device
+}  // namespace
+
+// address of the static array on the current device, looked up once per device
+static float* static_scratch() {
+  int dev = 0;
+  HIPCHK(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kMaxDevices) fail(HOM_E_DEVICE, "device index beyond the static scratch table");
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    HIPCHK(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+    g_scratch_ptr[dev] = static_cast<float*>(p);
+  }
+  return g_scratch_ptr[dev];
+}
+
+void ensemble_accept_static(const Mlp* const* nets, int M, const float* x, float* y, float* spread, uint8_t* accept,
+                            long long n, float thr, float floor_scale, hipStream_t s) {
+  const unsigned long long need = (unsigned long long)n * (unsigned long long)M * (unsigned long long)nets[0]->n_out;
+  if (need > (unsigned long long)HOM_STATIC_SCRATCH_FLOATS)
+    fail(HOM_E_ARG, "rows x networks x outputs = " + std::to_string(need) + " exceeds the static scratch of " +
+                        std::to_string(HOM_STATIC_SCRATCH_FLOATS) + " floats");
+  ensemble_accept(nets, M, x, y, static_scratch(), spread, accept, n, thr, floor_scale, s);
 }
 
 }  // namespace hom

@@ -183,6 +183,7 @@ EXPORTS = (
     "hom_mlp_get_params",
     "hom_mlp_set_params",
     "hom_mlp_train", "hom_mlp_forward", "hom_mlp_loss_grad", "hom_mlp_ensemble_infer",
+    "hom_mlp_ensemble_infer_static",
     "hom_mlp_last_error",
     "hom_mlp_destroy",
 )
@@ -279,6 +280,7 @@ def library(path: str | None = None):
     lib.hom_mlp_ensemble_infer.argtypes = [ct.POINTER(ct.c_void_p), ct.c_int32, ct.c_void_p, ct.c_void_p,
                                            ct.c_void_p, ct.c_void_p, ct.c_int64, ct.c_double, ct.c_double,
                                            ct.c_void_p]
+    lib.hom_mlp_ensemble_infer_static.argtypes = lib.hom_mlp_ensemble_infer.argtypes
     lib.hom_mlp_last_error.argtypes = [ct.c_void_p]
     lib.hom_mlp_last_error.restype = ct.c_char_p
     lib.hom_mlp_destroy.argtypes = [ct.c_void_p]
@@ -714,6 +716,25 @@ def mlp_ensemble_infer(nets, x_dev, threshold, floor_scale):
                                      floor_scale, ct.c_void_p(torch.cuda.current_stream().cuda_stream)),
            nets[0].error)
     return y, spread, acc
+
+
+STATIC_SCRATCH_FLOATS = 8388608   # HOM_STATIC_SCRATCH_FLOATS
+
+
+def mlp_ensemble_infer_static(nets, x_dev, threshold, floor_scale, y, spread, accept):
+    """mlp_ensemble_infer into caller-owned device tensors y [n, n_out] (float32),
+    spread [n] (float32), accept [n] (uint8), with the per-network outputs in
+    the library's static device array: no device memory is allocated here or
+    in the library."""
+    import torch
+    n = x_dev.shape[0]
+    handles = (ct.c_void_p * len(nets))(*[net._h.value if isinstance(net._h, ct.c_void_p) else net._h for net in nets])
+    lib = library()
+    _check(lib.hom_mlp_ensemble_infer_static(handles, len(nets), ct.c_void_p(x_dev.data_ptr()),
+                                             ct.c_void_p(y.data_ptr()), ct.c_void_p(spread.data_ptr()),
+                                             ct.c_void_p(accept.data_ptr()), n, threshold, floor_scale,
+                                             ct.c_void_p(torch.cuda.current_stream().cuda_stream)),
+           nets[0].error)
 
 
 # ---------------------------------------------------------------------------
