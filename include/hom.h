@@ -360,6 +360,132 @@ int hom_mlp_ensemble_infer_static(hom_mlp* const* nets, int32_t count, const flo
 const char* hom_mlp_last_error(const hom_mlp* net);
 void hom_mlp_destroy(hom_mlp* net);
 
+/* ---- surrogate with FFT fallback --------------------------------------------
+ * The learned part for one fixed microstructure (the role the paper gives its
+ * surrogate, Sec. 3: trained per microstructure, evaluated at Gauss points
+ * from macroscopic inputs; the FFT solver generates its data, judges its
+ * error and answers where it is not trusted). An ensemble of networks
+ * (hom_mlp, 32 -> 4 x 256 GELU -> 10) maps one increment's macroscopic
+ * inputs to its effective outputs:
+ *   inputs  x[0:6]  E^{n+1} (Mandel), x[6] theta^{n+1}, x[7] log10 dt,
+ *           x[8:14] E^n, x[14:20] <sigma>^n (Mandel), x[20:26] E^{n-1},
+ *           x[26] theta^n, x[27] <D_diss>^n, x[28] time integral of <D_diss>
+ *           up to step n, x[29:32] grad theta of the increment;
+ *   outputs y[0:6] <sigma>^{n+1} (Mandel), y[6:9] <q>, y[9] <D_diss>^{n+1}.
+ * Every input is macroscopic, so a caller rolls the summary forward from the
+ * surrogate's own answers. Before the first increment E^n = E^{n-1} = 0,
+ * <sigma>^n = 0, <D_diss>^n = 0, theta^n = theta_init. Rows the library
+ * builds from rolled summaries (point sets, calibration, training rounds)
+ * have their summary inputs x[8:29] clamped to the range of the training
+ * rows.
+ * The ensemble mean is the answer; the RMS pairwise spread of the stress
+ * outputs over max(|mean stress|, floor_scale) decides acceptance against a
+ * threshold calibrated on held-out histories: the largest threshold under
+ * which at least `quantile` of the accepted held-out rows meet `target` in the
+ * paper's error measure |<sigma>_net - <sigma>_FFT| / max_t |<sigma>_FFT|
+ * over the history (Sec. 5.4), with the held-out histories rolled forward
+ * from the networks' own answers (no FFT value enters their summaries).
+ *
+ * Point sets (hom_surrogate_points_*): many Gauss points advanced increment by
+ * increment. The library keeps each point's summary and macroscopic history.
+ * A point whose ensemble answer is rejected is handed to the FFT solver for
+ * the rest of its history: a batched solve replays its macroscopic history on
+ * a fresh cell (the cell state at step n exists nowhere else), answers the
+ * increment, and the cell stays resident in device memory and is advanced
+ * with the point's later increments (up to max_resident cells; beyond that a
+ * rejected point's cell is replayed, answers and is dropped, and the point
+ * returns to the ensemble with a summary taken from the FFT answer).
+ * Histories: strain [count][steps][6] (components), theta [count][steps],
+ * grad [count][steps][3], dt [count][steps]; host arrays, all histories in
+ * lockstep. */
+typedef struct hom_surrogate hom_surrogate;
+typedef struct hom_surrogate_points hom_surrogate_points;
+#define HOM_SURROGATE_IN 32
+#define HOM_SURROGATE_OUT 10
+typedef struct {
+  int32_t n_nets;       /* ensemble size, 2 .. HOM_ENSEMBLE_MAX_NETS (default 8) */
+  int32_t epochs;       /* training epochs per network (default 100) */
+  int32_t batch;        /* minibatch rows (default 4096) */
+  double lr;            /* peak Adam learning rate, cosine decay (default 8e-3) */
+  uint64_t seed;        /* initialization, shuffling and the hold-out split (default 0) */
+  double target;        /* relative effective-stress error to meet (default 1e-3) */
+  double quantile;      /* share of accepted held-out rows that must meet it (default 1: all) */
+  double holdout;       /* share of the training histories held out for calibration (default 0.1) */
+  double floor_scale;   /* MPa: stress magnitude below which the spread is absolute (default 0.01) */
+  double theta_init;    /* temperature before the first increment, K (default 293.15) */
+  int32_t chunk;        /* problems per batched FFT solve, data and fallback (default 1024) */
+  int32_t max_resident; /* FFT cells kept resident for rejected points of a point set (default 2048) */
+} hom_surrogate_config;
+typedef struct {
+  int64_t train_rows, holdout_rows;
+  double threshold;                  /* calibrated spread threshold */
+  double holdout_accepted;           /* share of held-out rows (network rollout) accepted */
+  double holdout_accepted_max_error; /* largest error of those rows */
+  double holdout_accepted_p99_error;
+  double holdout_median_error;        /* all held-out rows, network rollout */
+  double holdout_median_error_forced; /* the same rows with the FFT history as summary */
+  double skip_median_error;           /* the fixed skip alone (no network), FFT history as summary */
+  double fit_seconds;                 /* skip fits and network training, all networks */
+  double final_loss[HOM_ENSEMBLE_MAX_NETS]; /* last epoch's mean loss of each network */
+} hom_surrogate_report;
+typedef struct {
+  int32_t network_points;      /* points answered by the ensemble */
+  int32_t rejected_points;     /* points whose ensemble answer this call rejected */
+  int32_t resident_points;     /* points answered by a resident FFT cell kept from an earlier call */
+  int32_t replayed_increments; /* FFT increments solved to bring new cells up to this increment */
+  double network_ms;           /* wall time of feature build, ensemble and acceptance */
+  double fallback_ms;          /* wall time of the FFT fallback (cell setup, replay, solves) */
+} hom_surrogate_step_info;
+void hom_surrogate_default_config(hom_surrogate_config* cfg);
+/* The microstructure, laws and solver options of the FFT side (data and
+ * fallback; opts->stream must be NULL), and the ensemble configuration. */
+int hom_surrogate_create(const hom_grid* grid, const uint8_t* phases, const hom_law* laws, int32_t n_laws,
+                         const hom_options* opts, const hom_surrogate_config* cfg, hom_surrogate** out);
+/* The batched FFT solver over `count` histories (chunks of cfg.chunk
+ * problems): out [count][steps]. seconds (may be NULL): [0] wall time of the
+ * increments, [1] of the cell setups. */
+int hom_surrogate_solve_histories(hom_surrogate* s, int32_t count, int32_t steps, const double* strain,
+                                  const double* theta, const double* grad, const double* dt, hom_result* out,
+                                  double* seconds);
+/* Input rows of histories whose summaries come from the given FFT answers
+ * (host, no device): X [count * steps][32], Y [count * steps][10] (targets),
+ * denom [count * steps] = max_t |<sigma>_FFT| of the row's history (Mandel
+ * norm); Y and denom may be NULL. */
+int hom_surrogate_features(int32_t count, int32_t steps, const double* strain, const double* theta,
+                           const double* grad, const double* dt, const hom_result* fft, double theta_init, float* X,
+                           float* Y, double* denom);
+/* Trains the ensemble on histories and their FFT answers (fft NULL: the
+ * library solves them first): the fixed skip and scaling fitted by least
+ * squares, every network trained on the remainder from its own host thread
+ * and stream; then calibrates the threshold on the held-out histories. */
+int hom_surrogate_train(hom_surrogate* s, int32_t count, int32_t steps, const double* strain, const double* theta,
+                        const double* grad, const double* dt, const hom_result* fft, hom_surrogate_report* rep);
+/* Re-calibrates the threshold for another target / quantile on the given
+ * histories (network rollout, as in training). rep may be NULL. */
+int hom_surrogate_calibrate(hom_surrogate* s, int32_t count, int32_t steps, const double* strain,
+                            const double* theta, const double* grad, const double* dt, const hom_result* fft,
+                            double target, double quantile, hom_surrogate_report* rep);
+int hom_surrogate_set_threshold(hom_surrogate* s, double threshold);
+double hom_surrogate_threshold(const hom_surrogate* s);
+/* Stateless rows: x_dev [n][32] -> y_dev [n][10] (ensemble mean) and
+ * accepted_dev [n] (1 when the spread is within the threshold; no fallback:
+ * the caller owns the history). Device arrays, on `stream`; n = 0 is a no-op. */
+int hom_surrogate_infer(hom_surrogate* s, const float* x_dev, float* y_dev, uint8_t* accepted_dev, int64_t n,
+                        void* stream);
+int hom_surrogate_points_create(hom_surrogate* s, int32_t n_points, hom_surrogate_points** out);
+/* Advances every point by one increment (strain [n][6], theta [n], grad
+ * [n][3], dt [n]): out [n] gets stress (components), heat_flux, dissipation,
+ * status and, for FFT answers, coupling, iteration counts and pipelines
+ * (coupling NaN for ensemble answers: the network does not predict it);
+ * accepted [n] = 1 for an ensemble answer, 0 for an FFT answer. info may be
+ * NULL. Returns the worst per-point status. */
+int hom_surrogate_points_step(hom_surrogate_points* p, const double* strain, const double* theta, const double* grad,
+                              const double* dt, hom_result* out, uint8_t* accepted, hom_surrogate_step_info* info);
+const char* hom_surrogate_points_last_error(const hom_surrogate_points* p);
+void hom_surrogate_points_destroy(hom_surrogate_points* p);
+const char* hom_surrogate_last_error(const hom_surrogate* s);
+void hom_surrogate_destroy(hom_surrogate* s);
+
 /* ---- direct deep material network (Sec. 3) ---------------------------------
  * A two-phase direct DMN of depth K (1..10): a perfect binary tree of 2^K - 1
  * laminates with free directions of lamination m (2^K - 1 three-vectors,

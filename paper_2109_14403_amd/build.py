@@ -48,7 +48,7 @@ def build(jobs: int | None = None, verbose: bool = False) -> str:
     units = []
     for n in LENGTHS:
         units.append((os.path.join(CSRC, "pipe_inst.hip"), os.path.join(BUILD, f"pipe_{n}.o"), [f"-DHOM_N={n}"]))
-    for name in ("pointwise", "runtime", "mlp", "dmn", "api"):
+    for name in ("pointwise", "runtime", "mlp", "dmn", "surrogate", "api"):
         units.append((os.path.join(CSRC, f"{name}.hip"), os.path.join(BUILD, f"{name}.o"), []))
 
     def compile_one(u):

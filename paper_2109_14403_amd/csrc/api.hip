@@ -6,6 +6,7 @@
 #include "dmn.h"
 #include "mlp.h"
 #include "runtime.h"
+#include "surrogate.h"
 
 struct hom_ctx {
   std::unique_ptr<hom::BatchImpl> impl;
@@ -34,6 +35,13 @@ struct hom_mlp {
   ~hom_mlp() {
     if (scratch) (void)hipFree(scratch);
   }
+};
+
+struct hom_surrogate {
+  std::unique_ptr<hom::Surrogate> impl;
+};
+struct hom_surrogate_points {
+  std::unique_ptr<hom::SurrogatePoints> impl;
 };
 
 namespace {
@@ -495,6 +503,128 @@ int hom_mlp_ensemble_infer_static(hom_mlp* const* nets, int32_t count, const flo
 const char* hom_mlp_last_error(const hom_mlp* m) { return m ? m->err.c_str() : g_setup_error.c_str(); }
 
 void hom_mlp_destroy(hom_mlp* m) { delete m; }
+
+void hom_surrogate_default_config(hom_surrogate_config* c) {
+  if (!c) return;
+  std::memset(c, 0, sizeof(*c));
+  c->n_nets = 8;
+  c->epochs = 100;
+  c->batch = 4096;
+  c->lr = 8e-3;
+  c->seed = 0;
+  c->target = 1e-3;
+  c->quantile = 1.0;
+  c->holdout = 0.1;
+  c->floor_scale = 0.01;
+  c->theta_init = 293.15;
+  c->chunk = 1024;
+  c->max_resident = 2048;
+}
+
+int hom_surrogate_create(const hom_grid* grid, const uint8_t* phases, const hom_law* laws, int32_t n_laws,
+                         const hom_options* opts, const hom_surrogate_config* cfg, hom_surrogate** out) {
+  if (!out) return HOM_E_ARG;
+  *out = nullptr;
+  if (!grid || !phases || !laws || !opts || !cfg) return HOM_E_ARG;
+  hom_surrogate* s = new (std::nothrow) hom_surrogate();
+  if (!s) return HOM_E_OOM;
+  const int rc = guarded(&g_setup_error, [&] {
+    s->impl.reset(new hom::Surrogate(*grid, phases, laws, n_laws, *opts, *cfg));
+  });
+  if (rc != HOM_OK) {
+    delete s;
+    return rc;
+  }
+  *out = s;
+  return HOM_OK;
+}
+
+int hom_surrogate_solve_histories(hom_surrogate* s, int32_t count, int32_t steps, const double* strain,
+                                  const double* theta, const double* grad, const double* dt, hom_result* out,
+                                  double* seconds) {
+  if (!s || !s->impl) return HOM_E_ARG;
+  return guarded(&s->impl->err, [&] {
+    s->impl->solve_histories(count, steps, strain, theta, grad, dt, out, seconds);
+  });
+}
+
+int hom_surrogate_features(int32_t count, int32_t steps, const double* strain, const double* theta,
+                           const double* grad, const double* dt, const hom_result* fft, double theta_init, float* X,
+                           float* Y, double* denom) {
+  return guarded(&g_setup_error, [&] {
+    hom::sur_history_rows(count, steps, strain, theta, grad, dt, fft, theta_init, X, Y, denom);
+  });
+}
+
+int hom_surrogate_train(hom_surrogate* s, int32_t count, int32_t steps, const double* strain, const double* theta,
+                        const double* grad, const double* dt, const hom_result* fft, hom_surrogate_report* rep) {
+  if (!s || !s->impl) return HOM_E_ARG;
+  return guarded(&s->impl->err, [&] { s->impl->train(count, steps, strain, theta, grad, dt, fft, rep); });
+}
+
+int hom_surrogate_calibrate(hom_surrogate* s, int32_t count, int32_t steps, const double* strain,
+                            const double* theta, const double* grad, const double* dt, const hom_result* fft,
+                            double target, double quantile, hom_surrogate_report* rep) {
+  if (!s || !s->impl) return HOM_E_ARG;
+  return guarded(&s->impl->err, [&] {
+    if (rep) std::memset(rep, 0, sizeof(*rep));
+    s->impl->calibrate(count, steps, strain, theta, grad, dt, fft, target, quantile, rep);
+  });
+}
+
+int hom_surrogate_set_threshold(hom_surrogate* s, double threshold) {
+  if (!s || !s->impl || std::isnan(threshold)) return HOM_E_ARG;
+  s->impl->threshold = threshold;
+  return HOM_OK;
+}
+
+double hom_surrogate_threshold(const hom_surrogate* s) {
+  return s && s->impl ? s->impl->threshold : std::numeric_limits<double>::quiet_NaN();
+}
+
+int hom_surrogate_infer(hom_surrogate* s, const float* x_dev, float* y_dev, uint8_t* accepted_dev, int64_t n,
+                        void* stream) {
+  if (!s || !s->impl || n < 0) return HOM_E_ARG;
+  if (n == 0) return HOM_OK;  // nothing to do (the arrays may be empty)
+  if (!x_dev || !y_dev || !accepted_dev) return HOM_E_ARG;
+  return guarded(&s->impl->err, [&] {
+    s->impl->infer_device(x_dev, y_dev, accepted_dev, n, static_cast<hipStream_t>(stream));
+  });
+}
+
+int hom_surrogate_points_create(hom_surrogate* s, int32_t n_points, hom_surrogate_points** out) {
+  if (!out) return HOM_E_ARG;
+  *out = nullptr;
+  if (!s || !s->impl) return HOM_E_ARG;
+  hom_surrogate_points* p = new (std::nothrow) hom_surrogate_points();
+  if (!p) return HOM_E_OOM;
+  const int rc = guarded(&s->impl->err, [&] { p->impl.reset(new hom::SurrogatePoints(s->impl.get(), n_points)); });
+  if (rc != HOM_OK) {
+    delete p;
+    return rc;
+  }
+  *out = p;
+  return HOM_OK;
+}
+
+int hom_surrogate_points_step(hom_surrogate_points* p, const double* strain, const double* theta, const double* grad,
+                              const double* dt, hom_result* out, uint8_t* accepted, hom_surrogate_step_info* info) {
+  if (!p || !p->impl) return HOM_E_ARG;
+  const int rc = guarded(&p->impl->err, [&] { p->impl->step_all(strain, theta, grad, dt, out, accepted, info); });
+  return rc != HOM_OK ? rc : worst(out, p->impl->n);
+}
+
+const char* hom_surrogate_points_last_error(const hom_surrogate_points* p) {
+  return p && p->impl ? p->impl->err.c_str() : g_setup_error.c_str();
+}
+
+void hom_surrogate_points_destroy(hom_surrogate_points* p) { delete p; }
+
+const char* hom_surrogate_last_error(const hom_surrogate* s) {
+  return s && s->impl ? s->impl->err.c_str() : g_setup_error.c_str();
+}
+
+void hom_surrogate_destroy(hom_surrogate* s) { delete s; }
 
 int hom_apply_operator(const hom_grid* grid, int32_t ncomp, int32_t op, double p0, double p1, int32_t precision,
                        const double* in, double* out) {

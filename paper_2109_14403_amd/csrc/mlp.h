@@ -76,6 +76,8 @@ struct Mlp {
                 const float* rw = nullptr);
   void train(const float* X, const float* T, long long n, int epochs, int batch, double lr, uint64_t seed,
              const float* row_weight, float* loss_out);
+  // zero the Adam moments (a later train call starts its optimizer afresh)
+  void reset_optimizer();
   void get_params(float* out) const;
   void get_grads(float* out) const;
   void set_params(const float* in);

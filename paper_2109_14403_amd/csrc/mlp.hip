@@ -973,6 +973,12 @@ void Mlp::train(const float* X, const float* T, long long n, int epochs, int bat
   }
 }
 
+void Mlp::reset_optimizer() {
+  HIPCHK(hipMemset(m, 0, npad * 4));
+  HIPCHK(hipMemset(v, 0, npad * 4));
+  HIPCHK(hipDeviceSynchronize());
+}
+
 void ensemble_accept(const Mlp* const* nets, int M, const float* x, float* y, float* ys, float* spread,
                         uint8_t* accept, long long n, float thr, float floor_scale, hipStream_t s) {
   const int n_out = nets[0]->n_out;

@@ -167,6 +167,44 @@ DMN_RESULT_DTYPE = np.dtype([
 assert DMN_RESULT_DTYPE.itemsize == ct.sizeof(DmnResult)
 
 
+# hom_result as a numpy record (same layout), for bulk result arrays
+RESULT_DTYPE = np.dtype([
+    ("stress", "<f8", (6,)), ("heat_flux", "<f8", (3,)), ("dissipation", "<f8"), ("coupling", "<f8"),
+    ("heat_capacity", "<f8"), ("residual", "<f8"), ("newton_iters", "<i4"), ("krylov_iters", "<i4"),
+    ("thermal_iters", "<i4"), ("status", "<i4"), ("pipelines", "<f8"), ("thermal_pipelines", "<f8"),
+    ("strain", "<f8", (6,)), ("theta", "<f8"), ("stagger_iters", "<i4"), ("reserved", "<i4"),
+], align=True)
+assert RESULT_DTYPE.itemsize == ct.sizeof(Result)
+
+
+class SurrogateConfig(ct.Structure):
+    _fields_ = [("n_nets", ct.c_int32), ("epochs", ct.c_int32), ("batch", ct.c_int32), ("lr", ct.c_double),
+                ("seed", ct.c_uint64), ("target", ct.c_double), ("quantile", ct.c_double),
+                ("holdout", ct.c_double), ("floor_scale", ct.c_double), ("theta_init", ct.c_double),
+                ("chunk", ct.c_int32), ("max_resident", ct.c_int32)]
+
+
+class SurrogateReport(ct.Structure):
+    _fields_ = [("train_rows", ct.c_int64), ("holdout_rows", ct.c_int64), ("threshold", ct.c_double),
+                ("holdout_accepted", ct.c_double), ("holdout_accepted_max_error", ct.c_double),
+                ("holdout_accepted_p99_error", ct.c_double), ("holdout_median_error", ct.c_double),
+                ("holdout_median_error_forced", ct.c_double), ("skip_median_error", ct.c_double),
+                ("fit_seconds", ct.c_double), ("final_loss", ct.c_double * 16)]
+
+    def as_dict(self, nets=16):
+        d = {k: getattr(self, k) for k, _ in self._fields_ if k != "final_loss"}
+        d["final_loss"] = list(self.final_loss[:nets])
+        return d
+
+
+class SurrogateStepInfo(ct.Structure):
+    _fields_ = [("network_points", ct.c_int32), ("rejected_points", ct.c_int32), ("resident_points", ct.c_int32),
+                ("replayed_increments", ct.c_int32), ("network_ms", ct.c_double), ("fallback_ms", ct.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
 EXPORTS = (
     "hom_default_options", "hom_setup", "hom_solve_increment", "hom_state_size", "hom_get_state",
     "hom_set_state", "hom_get_field", "hom_kernel_stats", "hom_set_profiling", "hom_device_bytes",
@@ -186,6 +224,11 @@ EXPORTS = (
     "hom_mlp_ensemble_infer_static",
     "hom_mlp_last_error",
     "hom_mlp_destroy",
+    "hom_surrogate_default_config", "hom_surrogate_create", "hom_surrogate_solve_histories",
+    "hom_surrogate_features", "hom_surrogate_train", "hom_surrogate_calibrate", "hom_surrogate_set_threshold",
+    "hom_surrogate_threshold", "hom_surrogate_infer", "hom_surrogate_points_create", "hom_surrogate_points_step",
+    "hom_surrogate_points_last_error", "hom_surrogate_points_destroy", "hom_surrogate_last_error",
+    "hom_surrogate_destroy",
 )
 
 _lib = None
@@ -281,6 +324,33 @@ def library(path: str | None = None):
                                            ct.c_void_p, ct.c_void_p, ct.c_int64, ct.c_double, ct.c_double,
                                            ct.c_void_p]
     lib.hom_mlp_ensemble_infer_static.argtypes = lib.hom_mlp_ensemble_infer.argtypes
+    fp64 = dp
+    hist = [ct.c_int32, ct.c_int32, fp64, fp64, fp64, fp64]
+    lib.hom_surrogate_default_config.argtypes = [ct.POINTER(SurrogateConfig)]
+    lib.hom_surrogate_default_config.restype = None
+    lib.hom_surrogate_create.argtypes = [ct.POINTER(Grid), ct.c_void_p, ct.POINTER(Law), ct.c_int32,
+                                         ct.POINTER(Options), ct.POINTER(SurrogateConfig), ct.POINTER(ct.c_void_p)]
+    lib.hom_surrogate_solve_histories.argtypes = [ct.c_void_p] + hist + [ct.c_void_p, fp64]
+    lib.hom_surrogate_features.argtypes = hist + [ct.c_void_p, ct.c_double, fp, fp, fp64]
+    lib.hom_surrogate_train.argtypes = [ct.c_void_p] + hist + [ct.c_void_p, ct.POINTER(SurrogateReport)]
+    lib.hom_surrogate_calibrate.argtypes = [ct.c_void_p] + hist + [ct.c_void_p, ct.c_double, ct.c_double,
+                                                                   ct.POINTER(SurrogateReport)]
+    lib.hom_surrogate_set_threshold.argtypes = [ct.c_void_p, ct.c_double]
+    lib.hom_surrogate_threshold.argtypes = [ct.c_void_p]
+    lib.hom_surrogate_threshold.restype = ct.c_double
+    lib.hom_surrogate_infer.argtypes = [ct.c_void_p, ct.c_void_p, ct.c_void_p, ct.c_void_p, ct.c_int64,
+                                        ct.c_void_p]
+    lib.hom_surrogate_points_create.argtypes = [ct.c_void_p, ct.c_int32, ct.POINTER(ct.c_void_p)]
+    lib.hom_surrogate_points_step.argtypes = [ct.c_void_p, fp64, fp64, fp64, fp64, ct.c_void_p, ct.c_void_p,
+                                              ct.POINTER(SurrogateStepInfo)]
+    lib.hom_surrogate_points_last_error.argtypes = [ct.c_void_p]
+    lib.hom_surrogate_points_last_error.restype = ct.c_char_p
+    lib.hom_surrogate_points_destroy.argtypes = [ct.c_void_p]
+    lib.hom_surrogate_points_destroy.restype = None
+    lib.hom_surrogate_last_error.argtypes = [ct.c_void_p]
+    lib.hom_surrogate_last_error.restype = ct.c_char_p
+    lib.hom_surrogate_destroy.argtypes = [ct.c_void_p]
+    lib.hom_surrogate_destroy.restype = None
     lib.hom_mlp_last_error.argtypes = [ct.c_void_p]
     lib.hom_mlp_last_error.restype = ct.c_char_p
     lib.hom_mlp_destroy.argtypes = [ct.c_void_p]
@@ -735,6 +805,172 @@ def mlp_ensemble_infer_static(nets, x_dev, threshold, floor_scale, y, spread, ac
                                              ct.c_void_p(accept.data_ptr()), n, threshold, floor_scale,
                                              ct.c_void_p(torch.cuda.current_stream().cuda_stream)),
            nets[0].error)
+
+
+# ---------------------------------------------------------------------------
+# surrogate with FFT fallback
+# ---------------------------------------------------------------------------
+def surrogate_config(**kw) -> SurrogateConfig:
+    c = SurrogateConfig()
+    library().hom_surrogate_default_config(ct.byref(c))
+    for k, v in kw.items():
+        setattr(c, k, v)
+    return c
+
+
+def _histories(strain, theta, grad, dt):
+    """(count, steps, strain [c, s, 6], theta [c, s], grad [c, s, 3], dt [c, s]) as
+    contiguous float64; theta / dt may be given per history [c], grad per
+    history [c, 3]."""
+    e = _f64(strain)
+    count, steps = e.shape[0], e.shape[1]
+    t = _f64(np.broadcast_to(np.asarray(theta, dtype=np.float64).reshape(count, -1), (count, steps)))
+    g = np.asarray(grad, dtype=np.float64)
+    g = _f64(np.broadcast_to(g.reshape(count, 1, 3) if g.ndim == 2 else g, (count, steps, 3)))
+    d = _f64(np.broadcast_to(np.asarray(dt, dtype=np.float64).reshape(count, -1), (count, steps)))
+    return count, steps, e, t, g, d
+
+
+def surrogate_features(strain, theta, grad, dt, fft, theta_init=293.15):
+    """hom_surrogate_features: input rows X [count*steps, 32], targets Y
+    [count*steps, 10] and denominators [count*steps] of histories with their
+    FFT answers (a RESULT_DTYPE array [count, steps])."""
+    count, steps, e, t, g, d = _histories(strain, theta, grad, dt)
+    f = np.ascontiguousarray(fft, dtype=RESULT_DTYPE)
+    X = np.empty((count * steps, 32), dtype=np.float32)
+    Y = np.empty((count * steps, 10), dtype=np.float32)
+    den = np.empty(count * steps)
+    lib = library()
+    _check(lib.hom_surrogate_features(count, steps, _dptr(e), _dptr(t), _dptr(g), _dptr(d),
+                                      f.ctypes.data_as(ct.c_void_p), float(theta_init), _fptr(X), _fptr(Y),
+                                      _dptr(den)), lambda: lib.hom_surrogate_last_error(None).decode())
+    return X, Y, den
+
+
+class Surrogate(_Handle):
+    """hom_surrogate_*: the ensemble, its calibrated threshold and the FFT
+    solver of one microstructure."""
+
+    def __init__(self, phases, laws, config: SurrogateConfig | None = None, options: Options | None = None,
+                 lengths=(1.0, 1.0, 1.0), **cfg_kw):
+        lib = library()
+        self._lib = lib
+        self._phases = np.ascontiguousarray(phases, dtype=np.uint8)
+        self._grid = make_grid(self._phases.shape, lengths)
+        self._laws = (Law * len(laws))(*[make_law(p) for p in laws])
+        self.options = options if options is not None else make_options()
+        self.config = config if config is not None else surrogate_config(**cfg_kw)
+        h = ct.c_void_p()
+        _check(lib.hom_surrogate_create(ct.byref(self._grid), self._phases.ctypes.data_as(ct.c_void_p), self._laws,
+                                        len(laws), ct.byref(self.options), ct.byref(self.config), ct.byref(h)),
+               lambda: lib.hom_surrogate_last_error(None).decode())
+        self._h = h
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self._lib.hom_surrogate_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def error(self):
+        return self._lib.hom_surrogate_last_error(self._h).decode()
+
+    def solve_histories(self, strain, theta, grad, dt):
+        """Batched FFT answers [count, steps] (RESULT_DTYPE) and (solve, setup) seconds."""
+        count, steps, e, t, g, d = _histories(strain, theta, grad, dt)
+        out = np.empty((count, steps), dtype=RESULT_DTYPE)
+        sec = np.zeros(2)
+        _check(self._lib.hom_surrogate_solve_histories(self._h, count, steps, _dptr(e), _dptr(t), _dptr(g), _dptr(d),
+                                                       out.ctypes.data_as(ct.c_void_p), _dptr(sec)), self.error)
+        return out, (float(sec[0]), float(sec[1]))
+
+    def train(self, strain, theta, grad, dt, fft=None):
+        count, steps, e, t, g, d = _histories(strain, theta, grad, dt)
+        f = None if fft is None else np.ascontiguousarray(fft, dtype=RESULT_DTYPE)
+        rep = SurrogateReport()
+        _check(self._lib.hom_surrogate_train(self._h, count, steps, _dptr(e), _dptr(t), _dptr(g), _dptr(d),
+                                             None if f is None else f.ctypes.data_as(ct.c_void_p), ct.byref(rep)),
+               self.error)
+        return rep.as_dict(self.config.n_nets)
+
+    def calibrate(self, strain, theta, grad, dt, fft, target, quantile=1.0):
+        count, steps, e, t, g, d = _histories(strain, theta, grad, dt)
+        f = np.ascontiguousarray(fft, dtype=RESULT_DTYPE)
+        rep = SurrogateReport()
+        _check(self._lib.hom_surrogate_calibrate(self._h, count, steps, _dptr(e), _dptr(t), _dptr(g), _dptr(d),
+                                                 f.ctypes.data_as(ct.c_void_p), float(target), float(quantile),
+                                                 ct.byref(rep)), self.error)
+        return rep.as_dict(self.config.n_nets)
+
+    @property
+    def threshold(self):
+        return self._lib.hom_surrogate_threshold(self._h)
+
+    @threshold.setter
+    def threshold(self, value):
+        _check(self._lib.hom_surrogate_set_threshold(self._h, float(value)), self.error)
+
+    def infer(self, x_dev, y=None, accepted=None):
+        """Device rows x [n, 32] -> (y [n, 10], accepted [n]) device tensors."""
+        import torch
+        n = x_dev.shape[0]
+        if y is None:
+            y = torch.empty((n, 10), dtype=torch.float32, device=x_dev.device)
+        if accepted is None:
+            accepted = torch.empty(n, dtype=torch.uint8, device=x_dev.device)
+        _check(self._lib.hom_surrogate_infer(self._h, ct.c_void_p(x_dev.data_ptr()), ct.c_void_p(y.data_ptr()),
+                                             ct.c_void_p(accepted.data_ptr()), n,
+                                             ct.c_void_p(torch.cuda.current_stream().cuda_stream)), self.error)
+        return y, accepted
+
+    def points(self, n_points):
+        return SurrogatePoints(self, n_points)
+
+
+class SurrogatePoints(_Handle):
+    """hom_surrogate_points_*: Gauss points advanced increment by increment,
+    with the FFT fallback executed for rejected points."""
+
+    def __init__(self, sur: Surrogate, n_points):
+        self._lib = sur._lib
+        self._sur = sur            # the point set uses the surrogate: keep it alive
+        self.n = int(n_points)
+        h = ct.c_void_p()
+        _check(self._lib.hom_surrogate_points_create(sur._h, self.n, ct.byref(h)), sur.error)
+        self._h = h
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self._lib.hom_surrogate_points_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def step(self, strain, theta, grad, dt, check=True):
+        """One increment at every point. Returns (RESULT_DTYPE [n], accepted bool
+        [n], info dict)."""
+        e = _f64(strain).reshape(self.n, 6)
+        t = _f64(np.broadcast_to(theta, (self.n,)))
+        g = _f64(np.broadcast_to(np.asarray(grad, dtype=np.float64), (self.n, 3)))
+        d = _f64(np.broadcast_to(dt, (self.n,)))
+        out = np.empty(self.n, dtype=RESULT_DTYPE)
+        acc = np.empty(self.n, dtype=np.uint8)
+        info = SurrogateStepInfo()
+        rc = self._lib.hom_surrogate_points_step(self._h, _dptr(e), _dptr(t), _dptr(g), _dptr(d),
+                                                 out.ctypes.data_as(ct.c_void_p), acc.ctypes.data_as(ct.c_void_p),
+                                                 ct.byref(info))
+        if check:
+            _check(rc, lambda: self._lib.hom_surrogate_points_last_error(self._h).decode() or f"status {rc}")
+        return out, acc.astype(bool), info.as_dict()
 
 
 # ---------------------------------------------------------------------------

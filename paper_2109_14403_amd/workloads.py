@@ -321,3 +321,36 @@ def batch_problem(index: int, seed: int = 4, sizes=(24, 32, 48), n_steps: int = 
             for k in range(1, n_steps + 1)]
     rec.update(n=n, target=frac, radius=radius)
     return Workload(f"batch{index}_n{n}", img, [pa66(), e_glass()], hist, rec)
+
+
+# --------------------------------------------------------------------------
+# surrogate workload: one fixed microstructure, many Gauss-point histories
+# --------------------------------------------------------------------------
+SQ2 = math.sqrt(2.0)
+_MANDEL_W = np.array([1.0, 1.0, 1.0, SQ2, SQ2, SQ2])
+
+
+def surrogate_microstructure(n: int = 32, seed: int = 5):
+    """The fixed n^3 RSA sphere microstructure of the surrogate (radius n/8,
+    fraction >= 0.20; PA66 matrix id 0, E-glass spheres id 1)."""
+    return rsa_spheres(n, seed, (n / 8.0, n / 8.0), 0.20)
+
+
+def surrogate_histories(count: int, seed: int, steps: int = 5) -> dict:
+    """Proportional strain / temperature histories of the batch recipe: strain
+    direction uniform on the unit 6-sphere (Mandel) times U[0, 0.015],
+    Delta T ~ U[0, 80] K, dt ~ logU[0.006, 6] s per history, grad theta
+    ~ N(0, 1) K/m per history. Returns strain [count, steps, 6] (components),
+    theta [count, steps], dt [count], grad [count, 3]."""
+    rng = np.random.default_rng(seed)
+    d = rng.normal(size=(count, 6))
+    d /= np.linalg.norm(d, axis=1, keepdims=True)
+    amp = rng.uniform(0.0, 0.015, size=count)
+    e_full = amp[:, None] * d / _MANDEL_W[None, :]
+    dT = rng.uniform(0.0, 80.0, size=count)
+    dt = np.exp(rng.uniform(math.log(0.006), math.log(6.0), size=count))
+    grad = rng.normal(size=(count, 3))
+    k = np.arange(1, steps + 1) / steps
+    strain = e_full[:, None, :] * k[None, :, None]
+    theta = 293.15 + dT[:, None] * k[None, :]
+    return dict(strain=strain, theta=theta, dt=dt, grad=grad)
