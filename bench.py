@@ -70,13 +70,68 @@ def algorithmic_bytes(kind, n, fp_bytes, matrix_fraction):
     return None
 
 
-def cpu_baseline(phases, laws, reps=2,
-                 sample="two CG pipeline applications (tangent, FFT, projector, inverse FFT) "
-                        "of the FP64 oracle on the full 256^3 grid"):
-    """The oracle as it stands, timed on this host: A p = P[C p] at full size,
-    applied `reps` times in a row (about 13 s of single-threaded numpy)."""
-    from oracle import solver
+def solve_bytes(n, fp_bytes, matrix_fraction, n_state, n_eval, n_cg, n_first, increments, thermal):
+    """Algorithmic bytes of every kernel of `increments` timed increments, per
+    kernel (GB): the mechanical pipeline launches (n_eval residual
+    evaluations, n_first first and n_cg - n_first later CG iterations), the
+    per-increment kernels (init, branch history sums, commit) and the
+    conduction solve (`thermal`: its launches of each pass kernel, counted at
+    the residual-evaluation size, a lower bound). Evaluation launches of CG
+    iterations return at once and move nothing; reductions are left out
+    (kilobytes)."""
+    v = float(n) ** 3
+    mv = matrix_fraction * v
+    field = 6 * fp_bytes * v
+    launches = n_eval + n_cg
+    xf = algorithmic_bytes("xfwd", n, fp_bytes, matrix_fraction)
+    ev = algorithmic_bytes("eval", n, fp_bytes, matrix_fraction)[0]
+    out = {
+        "xfwd": n_eval * xf[0] + n_first * xf[1] + (n_cg - n_first) * xf[2],
+        "ypass": 2 * launches * algorithmic_bytes("yfwd", n, fp_bytes, matrix_fraction)[0],
+        "zgreen": launches * algorithmic_bytes("zgreen", n, fp_bytes, matrix_fraction)[0],
+        "xinv": launches * algorithmic_bytes("xinv", n, fp_bytes, matrix_fraction)[0],
+        "eval": n_eval * ev,
+        # x = x^n + dE: read x^n, write x
+        "init": increments * 2 * field,
+        # read the viscous strains of the branches, write 8 FP64 slots
+        "history": increments * (mv * ((n_state - 7) * 8 + 8 * 8) + v),
+        # read x, x^n, phase, the state and the history sums; write the state, x^n, the stress
+        "commit": increments * (4 * field + v + mv * (2 * n_state * 8 + 8 * 8)),
+    }
+    spec3 = n * n * (n // 2 + 1) * 3 * 2 * fp_bytes
+    f3 = 3 * fp_bytes * v
+    th = (thermal.get("xfwd", 0) * (f3 + spec3) + thermal.get("yfwd", 0) * 2 * spec3
+          + thermal.get("yinv", 0) * 2 * spec3 + thermal.get("zgreen", 0) * 2 * spec3
+          + thermal.get("xinv", 0) * (spec3 + 2 * f3) + thermal.get("init", 0) * 2 * f3
+          + thermal.get("commit", 0) * (f3 + v))
+    out["conduction"] = th
+    return {k: val / 1e9 for k, val in out.items()}
 
+
+def _host_info():
+    model = None
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return {"nproc": len(os.sched_getaffinity(0)), "cpu_model": model}
+
+
+def cpu_baseline(phases, laws, reps=2):
+    """The oracle as it stands, timed on this host's cores (its library FFT on
+    every core, and on one thread): CG operator applications A p = P[C p] on
+    the full 256^3 grid (the bench workload); the whole 10-increment history of
+    the 16^3 sphere (basic scheme, FP64, tol 1e-8); and the first Newton-CG
+    increment of the 64^3 sphere composite with its PA66 return map (tol 1e-6)."""
+    from oracle import fourier, solver
+    from paper_2109_14403_amd import workloads as W
+
+    host = _host_info()
+    cores = host["nproc"]
     cell = solver.Cell(phases, laws)
     rng = np.random.default_rng(0)
     shape = phases.shape
@@ -90,15 +145,47 @@ def cpu_baseline(phases, laws, reps=2,
         else:
             C = law.C
         tan[:, :, cell.masks[i]] = C[:, :, None]
-    p = rng.normal(size=(6,) + shape)
-    t0 = time.perf_counter()
-    for _ in range(reps):
-        ap = cell.project(np.einsum("ab...,b...->a...", tan, p))
-        _ = float((p * ap).sum())
-        p = ap
-    dt = time.perf_counter() - t0
-    return {"value": reps * float(np.prod(shape)) / dt, "unit": "voxel-iters/s", "cores": 1, "kind": "oracle",
-            "sample": sample, "seconds": dt}
+
+    def operator_rate(workers):
+        fourier.WORKERS = workers
+        p = rng.normal(size=(6,) + shape)
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            ap = cell.project(np.einsum("ab...,b...->a...", tan, p))
+            _ = float((p * ap).sum())
+            p = ap
+        return reps * float(np.prod(shape)) / (time.perf_counter() - t0)
+
+    try:
+        rate_all = operator_rate(cores)
+        rate_one = operator_rate(1)
+        fourier.WORKERS = cores
+        wl = W.small_sphere_workload()
+        ref = solver.Cell(wl.phases, wl.laws)
+        t0 = time.perf_counter()
+        its = 0
+        for st in wl.history:
+            o = ref.solve_increment(st.strain, st.theta, st.grad, st.dt, scheme="basic", tol=1e-8)
+            its += o["iterations"]
+        t1 = time.perf_counter() - t0
+        wl2 = W.sphere_composite_workload(64, seed=2)
+        ref2 = solver.Cell(wl2.phases, wl2.laws)
+        st = wl2.history[0]
+        t0 = time.perf_counter()
+        o2 = ref2.solve_increment(st.strain, st.theta, st.grad, st.dt, tol=1e-6)
+        t2 = time.perf_counter() - t0
+    finally:
+        fourier.WORKERS = 1
+    pipes2 = o2["iterations"] + o2["krylov"]
+    return {"value": rate_all, "unit": "voxel-iters/s", "cores": cores, "kind": "oracle",
+            "sample": f"{reps} CG operator applications (tangent, FFT, projector, inverse FFT) of the FP64 "
+                      "oracle on the full 256^3 grid",
+            "single_thread_value": rate_one, "host": host,
+            "config1_history": {"workload": "sphere16 thermoelastic, basic scheme, 10 increments", "seconds": t1,
+                                "iterations": its, "voxel_iters_per_s": its * 16 ** 3 / t1},
+            "config2_increment": {"workload": "spheres64 PA66/E-glass, increment 1, Newton-CG", "seconds": t2,
+                                  "newton": o2["iterations"], "krylov": o2["krylov"],
+                                  "voxel_iters_per_s": pipes2 * 64 ** 3 / t2}}
 
 
 def batch_bench(nprob=512, steps=5, seed=4, predictor=0):
@@ -704,6 +791,7 @@ def main():
     ap.add_argument("--rotated", action="store_true", help="rotated finite-difference discretization")
     ap.add_argument("--no-dmn", action="store_true")
     ap.add_argument("--no-predictor", action="store_true")
+    ap.add_argument("--chunk", type=int, default=0, help="solver iterations between host checks (0: library default)")
     ap.add_argument("--calib-copy", action="store_true", help="run a 1 GiB device copy (PMC calibration)")
     ap.add_argument("--pmc-summary", nargs="+", metavar="DIR",
                     help="summarize rocprofv3 --pmc output folders (FETCH_SIZE, WRITE_SIZE[, request sizes]) "
@@ -760,7 +848,7 @@ def main():
 
     disc = hom.DISC_ROTATED if args.rotated else hom.DISC_COLLOCATION
     ctx = hom.Context(wl.phases, wl.laws, scheme=hom.SCHEME_NEWTON_CG, precision=hom.FP32, tol=1e-6,
-                      autotune=1, discretization=disc)
+                      autotune=1, discretization=disc, chunk=args.chunk)
     print(f"setup done: {n}^3, {wl.record['count']} fibres, fraction {wl.record['fraction']:.4f}, "
           f"{ctx.device_bytes() / 2**30:.1f} GiB on device, generator {gen_s:.1f} s", file=sys.stderr, flush=True)
 
@@ -835,6 +923,16 @@ def main():
                     "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": traffic,
                     "traffic_request_sized": traffic_req, "kernel": dom,
                     "avg_launch_ms": round(avg_s * 1e3, 4), "algorithmic_bytes": byt}
+            # the whole coupled solve: algorithmic bytes of every kernel of the
+            # timed increments over their wall time (graph replay, not the
+            # per-kernel replay)
+            thermal = {k[2:]: kstats[k][0] for k in kstats if k.startswith("t.")}
+            sb = solve_bytes(n, 4, matrix_fraction, 79, n_eval, n_cg, n_first, args.steps, thermal)
+            tot = sum(sb.values())
+            roof["solve_frac"] = round(tot / elapsed / HBM_PEAK_GBS, 4)
+            roof["solve_gbs"] = round(tot / elapsed, 1)
+            roof["solve_gb_per_step"] = round(tot / args.steps, 2)
+            roof["solve_gb_by_kernel"] = {k: round(val / args.steps, 2) for k, val in sb.items()}
 
     tangent = None
     if not args.no_tangent:

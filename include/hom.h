@@ -99,7 +99,8 @@ typedef struct {
   double thermal_tol;  /* relative tolerance of the conduction problem; 0 => tol */
   int32_t max_iter;    /* basic: iterations; Newton: residual evaluations; 0 => default */
   int32_t max_krylov;  /* CG iterations per Newton step; 0 => default */
-  int32_t chunk;       /* solver iterations launched between host checks; 0 => default */
+  int32_t chunk;       /* solver iterations launched between host checks; 0 => default (4 from 2^22
+                          voxels in a group, else 16) */
   int32_t use_graph;   /* 1: replay chunks as captured hipGraphs */
   int32_t profile;     /* 1: time every kernel launch with HIP events */
   int32_t autotune;    /* 1: time the tile choices of the y/z passes at setup */

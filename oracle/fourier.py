@@ -14,6 +14,11 @@ gets xi_j := 0. Operators built from the direction n = xi / |xi| then stay
 orthogonal projectors and map real fields to real fields.
 """
 import numpy as np
+import scipy.fft
+
+# threads of the library FFT (scipy's pocketfft, the same transform as
+# numpy.fft); the CPU baseline sets it to the host's core count
+WORKERS = 1
 
 
 def integer_frequencies(n):
@@ -68,12 +73,12 @@ def dft_direct(f):
 
 def fft3(f):
     """Forward transform over the last three axes (library FFT)."""
-    return np.fft.fftn(f, axes=(-3, -2, -1))
+    return scipy.fft.fftn(f, axes=(-3, -2, -1), workers=WORKERS)
 
 
 def ifft3(F):
     """Inverse transform over the last three axes, real part (input Hermitian)."""
-    return np.fft.ifftn(F, axes=(-3, -2, -1)).real
+    return scipy.fft.ifftn(F, axes=(-3, -2, -1), workers=WORKERS).real
 
 
 def rotated_wavevectors(shape_zyx, lengths_xyz=(1.0, 1.0, 1.0)):

@@ -21,6 +21,13 @@ constexpr int MAX_PHASES = 8;
 constexpr int MAX_MAXWELL = 16;
 constexpr int NPART = 16;  // FP64 partial sums per block
 
+// Block partial sums are stored quantity-major per problem,
+// [prob][NPART][maxblk], so that a reduction reads each quantity as one
+// contiguous run of doubles.
+__host__ __device__ inline long long part_index(int prob, int q, int blk, int maxblk) {
+  return ((long long)prob * NPART + q) * maxblk + blk;
+}
+
 enum Mode : int { M_DONE = 0, M_EVAL = 1, M_CG = 2, M_BASIC = 3, M_FAIL = -1 };
 // Green operators: projectors and isotropic reference operators of the
 // collocation scheme; *_ROT: the projectors of the rotated finite-difference
@@ -99,7 +106,7 @@ struct Pipe {
   c2<T>* spec;              // [prob][nz][ny][PS][C], kx < P used
   Ctl* ctl;
   const ProbInc* inc;
-  double* part;             // [prob][maxblk][NPART]
+  double* part;             // [prob][NPART][maxblk]
   int maxblk;
   const c2<T>* twx;         // W_nx^j, j < nx
   const c2<T>* twy;

@@ -37,9 +37,25 @@ typedef float floatx4_t __attribute__((ext_vector_type(4)));
 constexpr int MROWS = 64;  // rows per forward work-group
 constexpr int AST = 264;   // LDS row stride of the bf16 activation tiles (16-byte aligned rows)
 
-__device__ __forceinline__ float gelu_f(float z) { return 0.5f * z * (1.0f + erff(z * 0.70710678118654752f)); }
+// erf by Abramowitz and Stegun's rational approximation 7.1.26 (Handbook of
+// Mathematical Functions, 1964): erf(x) = 1 - t (a1 + t (a2 + ... + t a5))
+// exp(-x^2), t = 1 / (1 + p x) for x >= 0, odd extension; absolute error
+// below 1.5e-7 (2e-7 with the hardware reciprocal), about a third of the
+// instructions of the library erf. The network's forward and backward passes
+// both use it, so training sees one consistent activation function.
+__device__ __forceinline__ float erf_as(float x) {
+  const float ax = fabsf(x);
+  const float t = __builtin_amdgcn_rcpf(fmaf(0.3275911f, ax, 1.0f));  // v_rcp_f32, 1 ulp
+  float p = fmaf(1.061405429f, t, -1.453152027f);
+  p = fmaf(p, t, 1.421413741f);
+  p = fmaf(p, t, -0.284496736f);
+  p = fmaf(p, t, 0.254829592f);
+  const float e = __expf(-ax * ax);
+  return copysignf(fmaf(-p * t, e, 1.0f), x);
+}
+__device__ __forceinline__ float gelu_f(float z) { return 0.5f * z * (1.0f + erf_as(z * 0.70710678118654752f)); }
 __device__ __forceinline__ float gelu_prime_f(float z) {
-  return 0.5f * (1.0f + erff(z * 0.70710678118654752f)) + z * expf(-0.5f * z * z) * 0.39894228040143268f;
+  return 0.5f * (1.0f + erf_as(z * 0.70710678118654752f)) + z * __expf(-0.5f * z * z) * 0.39894228040143268f;
 }
 
 struct FwdArgs {
@@ -62,7 +78,9 @@ struct FwdArgs {
   float* as[MLP_LAYERS - 1];  // [n][256] activations (optional)
 };
 
-template <int PRECISE>
+// SAVE: keep the normalized inputs, pre-activations, activations and
+// normalized outputs for the backward pass (training); inference writes y only
+template <int PRECISE, bool SAVE>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) k_mlp_fwd(FwdArgs a) {
   // The tile's activations live in LDS already split into bf16 hi + lo: each
   // value is split once, by the lane that produced it, and every wave reads
@@ -83,7 +101,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) k
     ahi[r * AST + k] = h;
     alo[r * AST + k] = (__bf16)(v - (float)h);
     xin[r * (MLP_IN + 1) + k] = v;
-    if (a.xs && gr < a.n) a.xs[gr * MLP_IN + k] = v;
+    if (SAVE && gr < a.n) a.xs[gr * MLP_IN + k] = v;
   }
   __syncthreads();
   const int lrow = lane & 15;
@@ -148,7 +166,9 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) k
       }
     }
     __syncthreads();  // all waves done reading this layer's input
-    const float* bias = a.bias[l];
+    float bv[4];
+#pragma unroll
+    for (int cb = 0; cb < 4; ++cb) bv[cb] = a.bias[l][wave * 64 + cb * 16 + lrow];
 #pragma unroll
     for (int rb = 0; rb < 4; ++rb)
 #pragma unroll
@@ -157,15 +177,17 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) k
         for (int i = 0; i < 4; ++i) {
           const int m = rb * 16 + (lane >> 4) * 4 + i;
           const int nn = wave * 64 + cb * 16 + lrow;
-          const float z = acc[rb][cb][i] + bias[nn];
+          const float z = acc[rb][cb][i] + bv[cb];
           const float g = gelu_f(z);
           const __bf16 h = (__bf16)g;
           ahi[m * AST + nn] = h;
           alo[m * AST + nn] = (__bf16)(g - (float)h);
-          const long long gr = row0 + m;
-          if (a.zs[l] && gr < a.n) {
-            a.zs[l][gr * MLP_W + nn] = z;
-            a.as[l][gr * MLP_W + nn] = g;
+          if constexpr (SAVE) {
+            const long long gr = row0 + m;
+            if (gr < a.n) {
+              a.zs[l][gr * MLP_W + nn] = z;
+              a.as[l][gr * MLP_W + nn] = g;
+            }
           }
         }
     __syncthreads();
@@ -194,7 +216,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) k
       const long long gr = row0 + m;
       if (gr >= a.n) continue;
       const float z = acc[i] + a.bias[l][lrow];
-      if (a.yhat) a.yhat[gr * MLP_OUT + lrow] = z;
+      if (SAVE) a.yhat[gr * MLP_OUT + lrow] = z;
       if (a.y && lrow < a.n_out) {
         const float* xr = xin + m * (MLP_IN + 1);
         const float va = xr[a.g0], vb = xr[a.g1], vc = xr[a.g2];
@@ -716,10 +738,17 @@ void Mlp::forward(const float* x, float* y, long long n, bool precise, bool save
     }
   }
   const unsigned blocks = (unsigned)((n + MROWS - 1) / MROWS);
-  if (precise)
-    hipLaunchKernelGGL(k_mlp_fwd<1>, dim3(blocks), dim3(256), 0, s, a);
-  else
-    hipLaunchKernelGGL(k_mlp_fwd<0>, dim3(blocks), dim3(256), 0, s, a);
+  if (save) {
+    if (precise)
+      hipLaunchKernelGGL((k_mlp_fwd<1, true>), dim3(blocks), dim3(256), 0, s, a);
+    else
+      hipLaunchKernelGGL((k_mlp_fwd<0, true>), dim3(blocks), dim3(256), 0, s, a);
+  } else {
+    if (precise)
+      hipLaunchKernelGGL((k_mlp_fwd<1, false>), dim3(blocks), dim3(256), 0, s, a);
+    else
+      hipLaunchKernelGGL((k_mlp_fwd<0, false>), dim3(blocks), dim3(256), 0, s, a);
+  }
 }
 
 // C = sum_s P[s] over the split-K partials, in a fixed order

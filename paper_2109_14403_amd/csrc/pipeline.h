@@ -419,7 +419,7 @@ __global__ void __launch_bounds__((N / Plan<N>::M) * NL * ((C + 1) / 2)) k_xfwd(
   if (cg) {  // uniform per block
     double s[1] = {pcp};
     block_sum<1>(s, red);
-    if (tid == 0) a.part[((long long)prob * a.maxblk + blk) * NPART] = s[0];
+    if (tid == 0) a.part[part_index(prob, 0, blk, a.maxblk)] = s[0];
   }
   __syncthreads();
 
@@ -782,9 +782,8 @@ __global__ void __launch_bounds__((N / Plan<N>::M) * NL * ((C + 1) / 2)) k_xinv(
   double s[2] = {s0, s1};
   block_sum<2>(s, red);
   if (tid == 0) {
-    double* out = a.part + ((long long)prob * a.maxblk + blk) * NPART;
-    out[0] = s[0];
-    out[1] = s[1];
+    a.part[part_index(prob, 0, blk, a.maxblk)] = s[0];
+    a.part[part_index(prob, 1, blk, a.maxblk)] = s[1];
   }
 }
 

@@ -225,9 +225,8 @@ __global__ void __launch_bounds__(PT_THREADS) k_commit(Pt<T> a) {
   }
   block_sum<NS>(acc, red);
   if (threadIdx.x == 0) {
-    double* out = a.part + ((long long)prob * a.maxblk + blk) * NPART;
 #pragma unroll
-    for (int k = 0; k < NS; ++k) out[k] = acc[k];
+    for (int k = 0; k < NS; ++k) a.part[part_index(prob, k, blk, a.maxblk)] = acc[k];
   }
 }
 
@@ -415,9 +414,8 @@ __global__ void __launch_bounds__(PT_THREADS) k_tangent_sum(Pt<T> a) {
   }
   block_sum<8>(acc, red);
   if (threadIdx.x == 0) {
-    double* out = a.part + ((long long)prob * a.maxblk + blk) * NPART;
 #pragma unroll
-    for (int k = 0; k < 8; ++k) out[k] = acc[k];
+    for (int k = 0; k < 8; ++k) a.part[part_index(prob, k, blk, a.maxblk)] = acc[k];
   }
 }
 
@@ -426,20 +424,20 @@ __global__ void __launch_bounds__(PT_THREADS) k_tangent_sum(Pt<T> a) {
 // ---------------------------------------------------------------------------
 constexpr int RED_THREADS = 1024;
 
-// Fixed-order sums of the first NK entries of every block's partial row, in
-// one pass over the rows (each row's entries are contiguous).
+// Fixed-order sums of the first NK quantities over the blocks' partials: each
+// thread takes blocks tid, tid + blockDim, ... of every quantity (contiguous
+// runs), then a fixed tree over the threads.
 template <int NK>
 __device__ __forceinline__ void sum_parts(const double* part, int maxblk, int nblk, int prob, double* out,
                                           double* red /* >= NK * 16 */) {
   double v[NK];
 #pragma unroll
   for (int k = 0; k < NK; ++k) v[k] = 0.0;
-  const double* base = part + (long long)prob * maxblk * NPART;
+  const double* base = part + part_index(prob, 0, 0, maxblk);
 #pragma unroll 4
   for (int b = threadIdx.x; b < nblk; b += blockDim.x) {
-    const double* row = base + (long long)b * NPART;
 #pragma unroll
-    for (int k = 0; k < NK; ++k) v[k] += row[k];
+    for (int k = 0; k < NK; ++k) v[k] += base[(long long)k * maxblk + b];
   }
   block_sum<NK>(v, red);
   if (threadIdx.x == 0) {

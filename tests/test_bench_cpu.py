@@ -72,3 +72,30 @@ def test_pass_counter_summary_derives_rocprof_metrics(tmp_path):
     cells = [c.strip() for c in rows[0].strip("|").split("|")]
     # 100 / (1100 - 100); 100 * 1100 / (100 * 256); 100 * 12800 / (100 * 256); 100 * 50 / 1000
     assert cells[1:] == ["1", "5000", "0.100", "4.3", "50.0", "5.0", "100"]
+
+
+def test_whole_solve_byte_model_recount():
+    """solve_bytes: every kernel of the timed increments, array by array."""
+    n, fp, mf, ns = 64, 4, 0.75, 79
+    v = n ** 3
+    comp = fp * v
+    spec6 = 6 * n * n * (n // 2 + 1) * 2 * fp
+    spec3 = spec6 // 2
+    n_eval, n_cg, n_first, inc = 9, 40, 6, 2
+    th = {"xfwd": 5, "yfwd": 5, "zgreen": 5, "yinv": 5, "xinv": 5, "init": 2, "commit": 2}
+    got = bench.solve_bytes(n, fp, mf, ns, n_eval, n_cg, n_first, inc, th)
+    ev, first, later = recount("xfwd", n, fp)
+    assert got["xfwd"] * 1e9 == pytest.approx(n_eval * ev + n_first * first + (n_cg - n_first) * later)
+    assert got["ypass"] * 1e9 == pytest.approx(2 * (n_eval + n_cg) * 2 * spec6)
+    assert got["zgreen"] * 1e9 == pytest.approx((n_eval + n_cg) * 2 * spec6)
+    assert got["xinv"] * 1e9 == pytest.approx((n_eval + n_cg) * (spec6 + 12 * comp))
+    # evaluation: read the strain and phase, 14 FP64 of every PA66 voxel, write stress and two tangent factors
+    assert got["eval"] * 1e9 == pytest.approx(n_eval * (6 * comp + v + mf * v * 14 * 8 + 6 * comp + 2 * comp))
+    assert got["init"] * 1e9 == pytest.approx(inc * 12 * comp)
+    # history: 72 branch values in, 8 slots out, per PA66 voxel, and the phase byte
+    assert got["history"] * 1e9 == pytest.approx(inc * (mf * v * (72 + 8) * 8 + v))
+    # commit: x, x^n, phase in; 79 state values in and out and 8 slots in per PA66 voxel; x^n and stress out
+    assert got["commit"] * 1e9 == pytest.approx(inc * (24 * comp + v + mf * v * (2 * 79 + 8) * 8))
+    # conduction (3 components): x forward at the evaluation size, y, z and y^-1 passes, x inverse, init, commit
+    cond = 5 * (3 * comp + spec3) + 3 * 5 * 2 * spec3 + 5 * (spec3 + 6 * comp) + 2 * 6 * comp + 2 * (3 * comp + v)
+    assert got["conduction"] * 1e9 == pytest.approx(cond)
