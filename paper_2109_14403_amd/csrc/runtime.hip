@@ -6,6 +6,7 @@
 #include <cmath>
 #include <cstring>
 #include <map>
+#include <thread>
 #include <numeric>
 #include <tuple>
 
@@ -302,6 +303,11 @@ struct Group {
     return static_cast<U*>(ptr);
   }
 
+  // streams of this group's work (the batch's own, or a lane of its own that
+  // lets groups of different grids run at the same time)
+  hipStream_t stream = nullptr, side = nullptr;
+  hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+
   ~Group() {
     for (int i = 0; i < 4; ++i)
       if (graph[i]) (void)hipGraphExecDestroy(graph[i]);
@@ -458,9 +464,15 @@ class BatchT : public BatchImpl {
   hipEvent_t ev_fork = nullptr, ev_join = nullptr;
   Profiler prof;
   bool linear_mech = true;
+  int device = 0;
+  // lanes created for groups after the first (library-owned streams only)
+  std::vector<hipStream_t> lane_streams;
+  std::vector<hipEvent_t> lane_events;
 
   ~BatchT() override {
     groups.clear();
+    for (hipEvent_t e : lane_events) (void)hipEventDestroy(e);
+    for (hipStream_t q : lane_streams) (void)hipStreamDestroy(q);
     if (ev_fork) (void)hipEventDestroy(ev_fork);
     if (ev_join) (void)hipEventDestroy(ev_join);
     if (side) (void)hipStreamDestroy(side);
@@ -531,6 +543,27 @@ class BatchT : public BatchImpl {
       where[i] = {gi, (int)groups[gi]->members.size()};
       groups[gi]->members.push_back(i);
     }
+    HIPCHK(hipGetDevice(&device));
+    // group 0 runs on the batch's streams; with library-owned streams every
+    // further group gets a lane of its own (default priority, like all others)
+    for (size_t gi = 0; gi < groups.size(); ++gi) {
+      Group<T>& G = *groups[gi];
+      if (gi == 0 || !own_stream) {
+        G.stream = stream;
+        G.side = side;
+        G.ev_fork = ev_fork;
+        G.ev_join = ev_join;
+        continue;
+      }
+      HIPCHK(hipStreamCreateWithFlags(&G.stream, hipStreamNonBlocking));
+      lane_streams.push_back(G.stream);
+      HIPCHK(hipStreamCreateWithFlags(&G.side, hipStreamNonBlocking));
+      lane_streams.push_back(G.side);
+      HIPCHK(hipEventCreateWithFlags(&G.ev_fork, hipEventDisableTiming));
+      lane_events.push_back(G.ev_fork);
+      HIPCHK(hipEventCreateWithFlags(&G.ev_join, hipEventDisableTiming));
+      lane_events.push_back(G.ev_join);
+    }
     const int nst = pa66_nstate(laws);
     for (auto& gp : groups) {
       auto& G = *gp;
@@ -562,6 +595,7 @@ class BatchT : public BatchImpl {
 
   // time the y / z tile widths on this group's data and keep the fastest
   void autotune(Group<T>& G) {
+    hipStream_t stream = G.stream;  // this group's lane
     hipEvent_t e0, e1;
     HIPCHK(hipEventCreate(&e0));
     HIPCHK(hipEventCreate(&e1));
@@ -616,6 +650,7 @@ class BatchT : public BatchImpl {
   }
 
   void check_tiles(Group<T>& G, int phys) {
+    hipStream_t stream = G.stream;  // this group's lane
     Pipe<T> a = G.pipe(phys, 0);
     for (int pass = 0; pass < 2; ++pass) {
       int& tx = (pass == 0 ? G.txy : G.txz)[phys];
@@ -643,6 +678,8 @@ class BatchT : public BatchImpl {
   // mechanics (sigma = C_algo x), 3 linearized mechanics with the source
   // d sigma / d theta.
   void iteration(Group<T>& G, int variant, bool basic) {
+    hipStream_t stream = G.stream, side = G.side;  // this group's lane
+    hipEvent_t ev_fork = G.ev_fork, ev_join = G.ev_join;
     const int phys = variant == 1 ? 1 : 0;
     const bool rot = opts.discretization == HOM_DISC_ROTATED;
     const int green = phys == 0 ? (basic ? G_GAMMA0 : (rot ? G_PROJ_ROT : G_PROJ))
@@ -705,6 +742,7 @@ class BatchT : public BatchImpl {
   }
 
   void run_chunk(Group<T>& G, int variant, bool basic, int k) {
+    hipStream_t stream = G.stream;  // this group's lane
     const bool graph = opts.use_graph && !prof.on;
     if (!graph) {
       for (int i = 0; i < k; ++i) iteration(G, variant, basic);
@@ -725,6 +763,7 @@ class BatchT : public BatchImpl {
 
   // Iterate until no problem of the group is in a pipeline mode (or the cap).
   void iterate(Group<T>& G, int variant, bool basic, long long cap) {
+    hipStream_t stream = G.stream;  // this group's lane
     // timed per kernel (profiling): one iteration per check, so that no launch
     // follows convergence and every timed launch did work
     const int k = prof.on ? 1 : chunk_size(G);
@@ -745,6 +784,7 @@ class BatchT : public BatchImpl {
   // Mechanics of one increment up to convergence; restart keeps the current
   // strain field (a later staggered solve at a new temperature).
   void mech_iterate(Group<T>& G, bool restart) {
+    hipStream_t stream = G.stream;  // this group's lane
     const bool basic = opts.scheme == HOM_SCHEME_BASIC;
     Pt<T> q = G.pt(0);
     check_tiles(G, 0);
@@ -766,6 +806,7 @@ class BatchT : public BatchImpl {
   // commit: also commit the increment of every converged problem; partials:
   // the point partials of the tangent option (before a commit: state n).
   void mech_finish(Group<T>& G, bool commit, bool partials) {
+    hipStream_t stream = G.stream;  // this group's lane
     Pt<T> q = G.pt(0);
     q.commit = commit ? 1 : 0;
     if (partials && G.dsdt) launch_partials<T>(q, stream);
@@ -782,6 +823,7 @@ class BatchT : public BatchImpl {
   }
 
   void thermal_solve(Group<T>& G) {
+    hipStream_t stream = G.stream;  // this group's lane
     const bool basic = opts.scheme == HOM_SCHEME_BASIC;
     Pt<T> q = G.pt(1);
     check_tiles(G, 1);
@@ -827,8 +869,8 @@ class BatchT : public BatchImpl {
     const bool trial = loads[0].trial != 0;
     const double sq2 = std::sqrt(2.0);
     const double w[6] = {1, 1, 1, sq2, sq2, sq2};
-    for (auto& gp : groups) {
-      Group<T>& G = *gp;
+    auto solve_group = [&](Group<T>& G) {
+      hipStream_t stream = G.stream;  // this group's lane
       const int np = G.nprob;
       std::vector<double> th(np), thn(np), pipes(np, 0.0), thprev(np, 0.0), gprev(np, 0.0);
       std::vector<int> newton(np, 0), krylov(np, 0), stag(np, 0);
@@ -973,6 +1015,32 @@ class BatchT : public BatchImpl {
         all = all && cm.status == 1;
       }
       G.tan_ok = all;
+    };
+    // groups of different grids are independent: with library-owned lanes
+    // they run at the same time, one host thread each (the per-kernel
+    // profiler times launches one by one, so it keeps them in turn)
+    if (groups.size() > 1 && own_stream && !prof.on) {
+      std::vector<std::thread> pool;
+      std::vector<int> codes(groups.size(), HOM_OK);
+      std::vector<std::string> msgs(groups.size());
+      for (size_t gi = 0; gi < groups.size(); ++gi)
+        pool.emplace_back([&, gi] {
+          try {
+            HIPCHK(hipSetDevice(device));
+            solve_group(*groups[gi]);
+          } catch (const Error& e) {
+            codes[gi] = e.code;
+            msgs[gi] = e.msg;
+          } catch (const std::exception& e) {
+            codes[gi] = HOM_E_DEVICE;
+            msgs[gi] = e.what();
+          }
+        });
+      for (auto& t : pool) t.join();
+      for (size_t gi = 0; gi < groups.size(); ++gi)
+        if (codes[gi] != HOM_OK) fail(codes[gi], msgs[gi]);
+    } else {
+      for (auto& gp : groups) solve_group(*gp);
     }
   }
 
@@ -1026,6 +1094,7 @@ class BatchT : public BatchImpl {
     prof.on = false;
     for (auto& gp : groups) {
       Group<T>& G = *gp;
+      hipStream_t stream = G.stream;  // this group's lane
       const size_t nm = (size_t)G.nprob * G.nvox;
       if (!G.fsave) G.fsave = G.template dalloc<T>(6 * nm);
       HIPCHK(hipMemcpyAsync(G.fsave, G.f, 6 * nm * sizeof(T), hipMemcpyDeviceToDevice, stream));
