@@ -71,14 +71,17 @@ __device__ __forceinline__ double pa66_solve_dp(const ProbInc& in, double seq, d
   double lo = 0.0, hi = f / G3;
   double d = (guess > lo && guess < hi) ? guess : 0.5 * hi;
   const double c = in.ccoef, sY = in.sY, m = in.mexp, hk = in.hk, nh = in.nh;
+  const double isY = 1.0 / sY;
   double A = 0.0, hp = INFINITY;
   // step tolerance: the stress correction 3 Gbar dp moves by < 1e-14 seq_tr
   // (a relative test on dp alone can sit below the rounding noise of g)
   const double dtol = 1e-14 * seq / G3;
   for (int it = 0; it < 80; ++it) {
     const double e = ep + d;
-    const double he = e > 0.0 ? hk * powpos(e, nh) : 0.0;  // H(eps_p + d)
-    const double x = (seq - G3 * d - sY - he) / sY;
+    // H(eps_p + d) = hk e^nh and H' = nh hk e^(nh - 1) from one power
+    const double hq = e > 0.0 ? hk * powpos(e, nh - 1.0) : 0.0;
+    const double he = hq * e;
+    const double x = (seq - G3 * d - sY - he) * isY;
     double xm, xm1;
     pow_m(x, m, xm, xm1);
     const double gv = d - c * xm;
@@ -86,8 +89,8 @@ __device__ __forceinline__ double pa66_solve_dp(const ProbInc& in, double seq, d
       lo = d;
     else
       hi = d;
-    hp = e > 0.0 ? nh * he / e : INFINITY;  // H'
-    A = c * m * xm1 / sY;
+    hp = e > 0.0 ? nh * hq : INFINITY;  // H'
+    A = c * m * xm1 * isY;
     const double gd = 1.0 + A * (G3 + hp);
     const double dn = d - gv / gd;
     // converged: accept the Newton point (it may sit on the bracket end the

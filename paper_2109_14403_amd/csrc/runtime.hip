@@ -265,7 +265,7 @@ struct Group {
   c2<T>* tw[3] = {nullptr, nullptr, nullptr};
   int txy[2] = {4, 4}, txz[2] = {4, 4};  // [mech, thermal]
   int pt_bpp = 1;
-  int cm_bpp = 1;  // blocks per problem of the once-per-increment history and commit kernels
+  int cm_bpp = 1;  // blocks per problem of the once-per-increment history sums
   int xfblocks = 1, xiblocks = 1;  // x-forward / x-inverse work-groups per problem
   // captured chunks: [0] mechanics, [1] conduction, [2] linearized mechanics
   // (tangent strain columns), [3] linearized mechanics with a source (tangent
@@ -352,14 +352,16 @@ struct Group {
     // blocks per problem of the pointwise kernels
     pt_bpp = (int)std::min<long long>((nvox + 255) / 256, std::max<long long>(1, 8192 / nprob));
     pt_bpp = std::max(pt_bpp, 1);
-    // history and commit stream the internal variables once per increment:
-    // one voxel per thread (many short work-groups) up to 65536 groups
+    // the history sums stream the branch strains once per increment and write
+    // no partial sums: one voxel per thread (many short work-groups) up to
+    // 65536 groups. The commit keeps pt_bpp: its partial sums are reduced by
+    // one work-group per problem, which grows with the number of groups.
     cm_bpp = (int)std::min<long long>((nvox + 255) / 256, std::max<long long>(1, 65536 / nprob));
     cm_bpp = std::max(cm_bpp, pt_bpp);
     const int nlf = x_lines(nx, sizeof(T) == 8, true), nli = x_lines(nx, sizeof(T) == 8, false);
     xfblocks = (ny * nz + nlf - 1) / nlf;
     xiblocks = (ny * nz + nli - 1) / nli;
-    maxblk = std::max(cm_bpp, std::max(xfblocks, xiblocks));
+    maxblk = std::max(pt_bpp, std::max(xfblocks, xiblocks));
     part = dalloc<double>((size_t)nprob * maxblk * NPART);
     for (int d = 0; d < 3; ++d) {
       const int n = d == 0 ? nx : (d == 1 ? ny : nz);
@@ -810,12 +812,11 @@ class BatchT : public BatchImpl {
     Pt<T> q = G.pt(0);
     q.commit = commit ? 1 : 0;
     if (partials && G.dsdt) launch_partials<T>(q, stream);
-    q.bpp = G.cm_bpp;
     prof.begin(K_COMMIT, stream);
     launch_commit<T>(q, 6, stream);
     prof.end(stream);
     prof.begin(K_REDOUT, stream);
-    launch_reduce_out(G.ctl_m, G.part, G.maxblk, G.cm_bpp, G.nprob, MECH_SUMS, 1.0 / (double)G.nvox, stream);
+    launch_reduce_out(G.ctl_m, G.part, G.maxblk, G.pt_bpp, G.nprob, MECH_SUMS, 1.0 / (double)G.nvox, stream);
     prof.end(stream);
     HIPCHK(hipMemcpyAsync(G.ctl_h, G.ctl_m, sizeof(Ctl) * G.nprob, hipMemcpyDeviceToHost, stream));
     HIPCHK(hipStreamSynchronize(stream));
@@ -832,12 +833,11 @@ class BatchT : public BatchImpl {
     launch_init_th<T>(q, opts.scheme, stream);
     prof.end(stream);
     iterate(G, 1, basic, iteration_cap(limits(1), basic));
-    q.bpp = G.cm_bpp;
     prof.begin(K_COMMIT, stream);
     launch_commit<T>(q, 3, stream);
     prof.end(stream);
     prof.begin(K_REDOUT, stream);
-    launch_reduce_out(G.ctl_t, G.part, G.maxblk, G.cm_bpp, G.nprob, 3, 1.0 / (double)G.nvox, stream);
+    launch_reduce_out(G.ctl_t, G.part, G.maxblk, G.pt_bpp, G.nprob, 3, 1.0 / (double)G.nvox, stream);
     prof.end(stream);
     HIPCHK(hipMemcpyAsync(G.ctl_h, G.ctl_t, sizeof(Ctl) * G.nprob, hipMemcpyDeviceToHost, stream));
     HIPCHK(hipStreamSynchronize(stream));
