@@ -37,7 +37,8 @@ KERNEL_SOURCES = ("paper_2109_14403_amd/csrc/pipeline.h", "paper_2109_14403_amd/
 
 CALIB_FLOATS = 1 << 28
 NETWORK_PARAMS_MACS = 32 * 256 + 3 * 256 * 256 + 256 * 10   # multiply-adds per row of one network
-PMC_KINDS = {"xfwd": "k_xfwd", "ypass": "k_ypass", "zgreen": "k_zgreen", "xinv": "k_xinv", "eval": "k_eval"}
+PMC_KINDS = {"xfwd": "k_xfwd", "ypass": "k_ypass", "zgreen": "k_zgreen", "xinv": "k_xinv", "eval": "k_eval",
+             "commit": "k_commit_vox", "history": "k_history", "init": "k_init"}
 
 
 def kernel_source_hash():
@@ -119,6 +120,27 @@ def _host_info():
     except OSError:
         pass
     return {"nproc": len(os.sched_getaffinity(0)), "cpu_model": model}
+
+
+def counter_solve_bytes(n, kstats):
+    """HBM GB that the counters measured over the replayed timed increments:
+    bytes per launch of each per-voxel kernel (profiles/<kind>_fibres<n>_pmc.json,
+    current kernel sources only) times its launches. None if one is missing."""
+    launches = {"xfwd": kstats.get("xfwd", [0])[0], "ypass": kstats.get("yfwd", [0])[0] + kstats.get("yinv", [0])[0],
+                "zgreen": kstats.get("zgreen", [0])[0], "xinv": kstats.get("xinv", [0])[0],
+                "eval": kstats.get("eval", [0])[0], "commit": kstats.get("commit", [0])[0],
+                "history": kstats.get("history", [0])[0], "init": kstats.get("init", [0])[0]}
+    h = kernel_source_hash()
+    tot = 0.0
+    for kind, nl in launches.items():
+        path = os.path.join(ROOT, "profiles", f"{kind}_fibres{n}_pmc.json")
+        if not os.path.exists(path):
+            return None
+        pm = json.load(open(path))
+        if pm.get("source_hash") != h:
+            return None
+        tot += pm["bytes_per_launch"] * nl
+    return tot / 1e9
 
 
 def cpu_baseline(phases, laws, reps=2):
@@ -409,7 +431,9 @@ def pmc_summary(dirs, n, command, log_path=None):
         groups = [k for k in fetch if name in k and "hom::" in k]
         if not groups:
             continue
-        main_name = max(groups, key=lambda k: len(fetch[k]))    # the mechanical instance
+        # the mechanical instance: the most launches, and the 6-component one
+        # where the conduction instance has as many (init, commit)
+        main_name = max(groups, key=lambda k: (len(fetch[k]), ", 6>" in k))
         nl = last * (2 if kind == "ypass" else 1) if last else None   # the y kernel runs forward and inverse
 
         def avg(table, nm):
@@ -933,6 +957,15 @@ def main():
             roof["solve_gbs"] = round(tot / elapsed, 1)
             roof["solve_gb_per_step"] = round(tot / args.steps, 2)
             roof["solve_gb_by_kernel"] = {k: round(val / args.steps, 2) for k, val in sb.items()}
+            # the same with the HBM bytes the counters measured per launch
+            # (profiles/*_pmc.json of the current kernel sources), where every
+            # per-voxel kernel of the increment has them; the conduction solve
+            # keeps its algorithmic bytes
+            cb = counter_solve_bytes(n, kstats)
+            if cb is not None:
+                per_step = (cb + sb["conduction"]) / args.steps
+                roof["solve_frac_counters"] = round(per_step * args.steps / elapsed / HBM_PEAK_GBS, 4)
+                roof["solve_gb_per_step_counters"] = round(per_step, 2)
 
     tangent = None
     if not args.no_tangent:

@@ -112,6 +112,7 @@ struct Pipe {
   const c2<T>* twy;
   const c2<T>* twz;
   double len[3];
+  double ilen[3];           // 1 / len
   int green;                // Green enum
 };
 

@@ -74,6 +74,26 @@ __device__ __forceinline__ c2<T> wconst(int j) {
   return mk(T(cos48(j * (48 / R))), T(-sin48(j * (48 / R))));
 }
 
+// a * exp(-2 pi i j / R); the quarter-turn factors 1, -i, -1, i exactly, as
+// sign changes and swaps
+template <typename T, int R>
+__device__ __forceinline__ c2<T> mul_wconst(c2<T> a, int j) {
+  const int q = ((j * (48 / R)) % 48 + 48) % 48;
+  if (q % 12 == 0) {
+    switch (q / 12) {
+      case 0:
+        return a;
+      case 1:
+        return mul_mi(a);
+      case 2:
+        return mk(-a.x, -a.y);
+      default:
+        return mk(-a.y, a.x);
+    }
+  }
+  return cmul(a, wconst<T, R>(j));
+}
+
 template <int R, typename T>
 struct DFT;
 
@@ -132,7 +152,7 @@ __device__ __forceinline__ void dft_ct(c2<T>* v) {
     for (int n1 = 0; n1 < R1; ++n1) t[n1] = v[R2 * n1 + n2];
     DFT<R1, T>::run(t);
 #pragma unroll
-    for (int k1 = 0; k1 < R1; ++k1) u[n2 * R1 + k1] = (n2 * k1 == 0) ? t[k1] : cmul(t[k1], wconst<T, R>(n2 * k1));
+    for (int k1 = 0; k1 < R1; ++k1) u[n2 * R1 + k1] = mul_wconst<T, R>(t[k1], n2 * k1);
   }
 #pragma unroll
   for (int k1 = 0; k1 < R1; ++k1) {

@@ -21,6 +21,20 @@ __device__ __forceinline__ void stnt(T* p, T v) {
   __builtin_nontemporal_store(v, p);
 }
 
+// p + off elements with a 32-bit offset (off * sizeof(T) < 2^32). The per-voxel
+// functions below take uniform array bases and the voxel as `off`, so that
+// every access has the scalar-base + 32-bit-offset form (no 64-bit address
+// arithmetic per access and per component); off = 0 takes p as the voxel's
+// own pointer.
+template <typename T>
+__device__ __forceinline__ T* pa_at(T* p, unsigned off) {
+  return reinterpret_cast<T*>(reinterpret_cast<char*>(p) + off * (unsigned)sizeof(T));
+}
+template <typename T>
+__device__ __forceinline__ const T* pa_at(const T* p, unsigned off) {
+  return reinterpret_cast<const T*>(reinterpret_cast<const char*>(p) + off * (unsigned)sizeof(T));
+}
+
 // ---------------------------------------------------------------------------
 // PA66 law (paper Sec. 4) for one voxel, FP64, implicit Euler.
 //
@@ -107,6 +121,9 @@ __device__ __forceinline__ double pa66_solve_dp(const ProbInc& in, double seq, d
   return d;
 }
 
+// Maxwell branches streamed together by the per-voxel branch loops
+constexpr int PA66_GROUP = 2;
+
 // Branch history sums of one voxel, fixed during an increment (they depend on
 // the viscous strains of step n and on theta, dt only):
 //   hd = sum_i 2 G_i D_i / (1 + rG_i)   (deviatoric, 6 Mandel components)
@@ -114,74 +131,85 @@ __device__ __forceinline__ double pa66_solve_dp(const ProbInc& in, double seq, d
 // so that the trial stress is s_tr = 2 Gbar (dev eps - eps_vp) - hd and the
 // spherical stress 3 Kbar tr(e)/3 - hs.
 __device__ __forceinline__ void pa66_history(const ProbInc& in, const double* st, long long ss, double* hd,
-                                             double& hs) {
+                                             double& hs, unsigned off = 0) {
 #pragma unroll
   for (int c = 0; c < 6; ++c) hd[c] = 0.0;
   hs = 0.0;
-  for (int i = 0; i < in.nm; ++i) {
-    const double* ev = st + (7 + 6 * i) * ss;
-    const double v0 = ldnt(ev), v1 = ldnt(ev + ss), v2 = ldnt(ev + 2 * ss);
-    const double sn = (v0 + v1 + v2) * (1.0 / 3.0);
-    const double w = in.G2i[i] * in.fG[i];
-    hd[0] += w * (v0 - sn);
-    hd[1] += w * (v1 - sn);
-    hd[2] += w * (v2 - sn);
-    hd[3] += w * ldnt(ev + 3 * ss);
-    hd[4] += w * ldnt(ev + 4 * ss);
-    hd[5] += w * ldnt(ev + 5 * ss);
-    hs += in.K3i[i] * in.fK[i] * sn;
+  const int nm = in.nm;
+  // PA66_GROUP branches a step: all their loads are issued before the first
+  // is used (a load index past the last branch repeats the last one, in
+  // bounds, and is not summed)
+  for (int i0 = 0; i0 < nm; i0 += PA66_GROUP) {
+    double v[PA66_GROUP][6];
+#pragma unroll
+    for (int j = 0; j < PA66_GROUP; ++j) {
+      const int i = min(i0 + j, nm - 1);
+#pragma unroll
+      for (int c = 0; c < 6; ++c) v[j][c] = ldnt(pa_at(st + (7 + 6 * i + c) * ss, off));
+    }
+#pragma unroll
+    for (int j = 0; j < PA66_GROUP; ++j) {
+      const int i = i0 + j;
+      if (i >= nm) break;
+      const double sn = (v[j][0] + v[j][1] + v[j][2]) * (1.0 / 3.0);
+      const double w = in.G2i[i] * in.fG[i];
+      hd[0] += w * (v[j][0] - sn);
+      hd[1] += w * (v[j][1] - sn);
+      hd[2] += w * (v[j][2] - sn);
+      hd[3] += w * v[j][3];
+      hd[4] += w * v[j][4];
+      hd[5] += w * v[j][5];
+      hs += in.K3i[i] * in.fK[i] * sn;
+    }
   }
 }
 
-// Trial / final evaluation. If `hist` is non-null the branch history sums are
-// read from it ([HIST_SLOTS][ss]: hd, hs, dp), else computed from the state.
-// `dp_slot`, if non-null, holds the plastic increment of the voxel's previous
-// evaluation in this increment (negative: none), the start of the scalar
-// Newton iteration; a trial evaluation stores its result there. If `diss` is
-// non-null the dissipation and coupling term are computed, and if `st_out`
-// is non-null too the new internal variables are written there.
-static __device__ void pa66_point(const ProbInc& in, const double* eps, const double* st, long long ss, double* st_out,
-                           const double* eps_n, PaOut& o, double* diss, double* coup,
-                           const double* hist = nullptr, double* dp_slot = nullptr) {
+// What the commit of a voxel needs from its evaluation besides PaOut: the
+// deviatoric strain, the internal variables of step n (eps_vp, eps_p) and
+// tr(eps)/3 - alpha (theta - theta0).
+struct PaPre {
+  double d[6], evp[6];
+  double ep, em;
+};
+
+// Trial state of one voxel at strain eps: the strain split and the internal
+// variables of step n (p), the deviatoric trial stress str, the spherical
+// stress sph and |str|. If `hist` is non-null the branch history sums are
+// read from it ([HIST_SLOTS][ss]: hd, hs), else computed from the state.
+__device__ __forceinline__ void pa66_trial(const ProbInc& in, const double* eps, const double* st, long long ss,
+                                           const double* hist, PaPre& p, double* str, double& sph, double& snrm,
+                                           unsigned off = 0) {
   const double tr3 = (eps[0] + eps[1] + eps[2]) * (1.0 / 3.0);
-  const double em = tr3 - in.ph[in.pa_phase].alpha_dth;
-  double d[6];
+  p.em = tr3 - in.ph[in.pa_phase].alpha_dth;
 #pragma unroll
-  for (int c = 0; c < 6; ++c) d[c] = eps[c];
-  d[0] -= tr3;
-  d[1] -= tr3;
-  d[2] -= tr3;
-  const double ep = ldnt(st);
-  double evp[6];
+  for (int c = 0; c < 6; ++c) p.d[c] = eps[c];
+  p.d[0] -= tr3;
+  p.d[1] -= tr3;
+  p.d[2] -= tr3;
+  p.ep = ldnt(pa_at(st, off));
 #pragma unroll
-  for (int c = 0; c < 6; ++c) evp[c] = ldnt(st + (1 + c) * ss);
+  for (int c = 0; c < 6; ++c) p.evp[c] = ldnt(pa_at(st + (1 + c) * ss, off));
   double hd[6], hs;
   if (hist) {
 #pragma unroll
-    for (int c = 0; c < 6; ++c) hd[c] = ldnt(hist + c * ss);
-    hs = ldnt(hist + 6 * ss);
+    for (int c = 0; c < 6; ++c) hd[c] = ldnt(pa_at(hist + c * ss, off));
+    hs = ldnt(pa_at(hist + 6 * ss, off));
   } else {
-    pa66_history(in, st, ss, hd, hs);
+    pa66_history(in, st, ss, hd, hs, off);
   }
-  double str[6];
 #pragma unroll
-  for (int c = 0; c < 6; ++c) str[c] = in.Gbar2 * (d[c] - evp[c]) - hd[c];
-  const double sph = in.Kbar3 * em - hs;
+  for (int c = 0; c < 6; ++c) str[c] = in.Gbar2 * (p.d[c] - p.evp[c]) - hd[c];
+  sph = in.Kbar3 * p.em - hs;
   double sn2 = 0.0;
 #pragma unroll
   for (int c = 0; c < 6; ++c) sn2 += str[c] * str[c];
-  const double snrm = sqrt(sn2);
-  const double seq = 1.2247448713915890 * snrm;  // sqrt(3/2) |s|
-  const double H = ep > 0.0 ? in.hk * powpos(ep, in.nh) : 0.0;
-  const double f = seq - in.sY - H;
-  double dp = 0.0, th1 = 1.0, cp = 1.0;
-  const double G3 = 1.5 * in.Gbar2;
-  if (f > 0.0 && snrm > 0.0) {
-    double dgd;
-    dp = pa66_solve_dp(in, seq, ep, f, G3, dp_slot ? *dp_slot : -1.0, dgd);
-    th1 = 1.0 - G3 * dp / seq;
-    cp = 1.0 - G3 * dgd;
-  }
+  snrm = sqrt(sn2);
+}
+
+// Stress, flow direction and tangent factors of the return with plastic
+// increment dp (th1 = 1 - 3 Gbar dp / seq_tr, cp = 1 - 3 Gbar d dp / d seq_tr)
+__device__ __forceinline__ void pa66_out(const ProbInc& in, const double* str, double sph, double snrm, double dp,
+                                         double th1, double cp, PaOut& o) {
   const double inv = snrm > 0.0 ? 1.0 / snrm : 0.0;
 #pragma unroll
   for (int c = 0; c < 6; ++c) {
@@ -194,8 +222,118 @@ static __device__ void pa66_point(const ProbInc& in, const double* eps, const do
   o.a = in.Gbar2 * th1;
   o.b = in.Gbar2 * (cp - th1);
   o.dp = dp;
+}
+
+// Radial return of one voxel at strain eps (history sums as in pa66_trial).
+// `guess` is the plastic increment of the voxel's previous evaluation in this
+// increment (negative: none), the start of the scalar Newton iteration.
+__device__ __forceinline__ void pa66_return(const ProbInc& in, const double* eps, const double* st, long long ss,
+                                            const double* hist, double guess, PaOut& o, PaPre& p,
+                                            unsigned off = 0) {
+  double str[6], sph, snrm;
+  pa66_trial(in, eps, st, ss, hist, p, str, sph, snrm, off);
+  const double seq = 1.2247448713915890 * snrm;  // sqrt(3/2) |s|
+  const double H = p.ep > 0.0 ? in.hk * powpos(p.ep, in.nh) : 0.0;
+  const double f = seq - in.sY - H;
+  double dp = 0.0, th1 = 1.0, cp = 1.0;
+  const double G3 = 1.5 * in.Gbar2;
+  if (f > 0.0 && snrm > 0.0) {
+    double dgd;
+    dp = pa66_solve_dp(in, seq, p.ep, f, G3, guess, dgd);
+    th1 = 1.0 - G3 * dp / seq;
+    cp = 1.0 - G3 * dgd;
+  }
+  pa66_out(in, str, sph, snrm, dp, th1, cp, o);
+}
+
+// The same return with its plastic increment dp known (an evaluation at this
+// strain has solved for it): stress and flow direction without the scalar
+// Newton iteration (the tangent factor b is left at zero).
+__device__ __forceinline__ void pa66_return_at(const ProbInc& in, const double* eps, const double* st, long long ss,
+                                               const double* hist, double dp, PaOut& o, PaPre& p,
+                                               unsigned off = 0) {
+  double str[6], sph, snrm;
+  pa66_trial(in, eps, st, ss, hist, p, str, sph, snrm, off);
+  const double seq = 1.2247448713915890 * snrm;
+  const bool flow = dp > 0.0 && snrm > 0.0;
+  const double th1 = flow ? 1.0 - 1.5 * in.Gbar2 * dp / seq : 1.0;
+  pa66_out(in, str, sph, snrm, flow ? dp : 0.0, th1, th1, o);
+}
+
+// 3 K_inf + sum_i 3 K_i: the trace share of the coupling term that does not
+// depend on the branches' viscous strains
+__device__ __forceinline__ double pa66_k3_total(const ProbInc& in) {
+  double k = in.Kinf3;
+  for (int i = 0; i < in.nm; ++i) k += in.K3i[i];
+  return k;
+}
+
+// Commit of the Maxwell branches of one voxel, given dn = dev eps - eps_vp'
+// and em = tr(eps)/3 - alpha (theta - theta0) of the converged strain: the
+// closed-form viscous strain update (written to st_out if non-null; st_out
+// may be st), the branches' share of the dissipation times dt
+//   wsum = sum_i [3 K_i (em - S_i') 3 (S_i' - S_i) + 2 G_i (dn - D_i') : (D_i' - D_i)]
+// and ksum = sum_i 3 K_i (S_i' - S_i), the branches' share of the coupling
+// term's trace sum (which is (3 K_inf + sum_i 3 K_i) tr(deps) - 3 ksum).
+// PA66_GROUP branches a step: their loads are all issued before the first
+// store (a load index past the last branch repeats the last one, in bounds;
+// it is neither updated nor summed).
+__device__ __forceinline__ void pa66_branches(const ProbInc& in, const double* st, long long ss, double* st_out,
+                                              const double* dn, double em, double& wsum, double& ksum,
+                                              unsigned off = 0) {
+  wsum = 0.0;
+  ksum = 0.0;
+  const int nm = in.nm;
+  for (int i0 = 0; i0 < nm; i0 += PA66_GROUP) {
+    double v[PA66_GROUP][6];
+#pragma unroll
+    for (int j = 0; j < PA66_GROUP; ++j) {
+      const int i = min(i0 + j, nm - 1);
+#pragma unroll
+      for (int c = 0; c < 6; ++c) v[j][c] = *pa_at(st + (7 + 6 * i + c) * ss, off);
+    }
+#pragma unroll
+    for (int j = 0; j < PA66_GROUP; ++j) {
+      const int i = i0 + j;
+      if (i >= nm) break;
+      const double sn = (v[j][0] + v[j][1] + v[j][2]) * (1.0 / 3.0);
+      const double s1 = in.fK[i] * (sn + in.rK[i] * em);
+      double dnew[6], dold[6];
+#pragma unroll
+      for (int c = 0; c < 6; ++c) {
+        dold[c] = v[j][c] - (c < 3 ? sn : 0.0);
+        dnew[c] = in.fG[i] * (dold[c] + in.rG[i] * dn[c]);
+      }
+      double w = in.K3i[i] * (em - s1) * 3.0 * (s1 - sn);
+#pragma unroll
+      for (int c = 0; c < 6; ++c) w += in.G2i[i] * (dn[c] - dnew[c]) * (dnew[c] - dold[c]);
+      wsum += w;
+      ksum += in.K3i[i] * (s1 - sn);
+      if (st_out) {
+        double* evo = st_out + (7 + 6 * i) * ss;
+#pragma unroll
+        for (int c = 0; c < 6; ++c) *pa_at(evo + c * ss, off) = dnew[c] + (c < 3 ? s1 : 0.0);
+      }
+    }
+  }
+}
+
+// Trial / final evaluation. `hist` and the start of the scalar Newton
+// iteration as in pa66_return; `dp_slot`, if non-null, holds the start and a
+// trial evaluation stores its result there. If `diss` is non-null the
+// dissipation and coupling term are computed, and if `st_out` is non-null too
+// the new internal variables are written there.
+static __device__ void pa66_point(const ProbInc& in, const double* eps, const double* st, long long ss, double* st_out,
+                           const double* eps_n, PaOut& o, double* diss, double* coup,
+                           const double* hist = nullptr, double* dp_slot = nullptr, unsigned off = 0) {
+  PaPre p;
+  pa66_return(in, eps, st, ss, hist, dp_slot ? *pa_at(dp_slot, off) : -1.0, o, p, off);
+  const double dp = o.dp;
+  const double em = p.em, ep = p.ep;
+  const double* d = p.d;
+  const double* evp = p.evp;
   if (!diss) {
-    if (dp_slot) *dp_slot = dp;
+    if (dp_slot) *pa_at(dp_slot, off) = dp;
     return;
   }
 
@@ -207,40 +345,17 @@ static __device__ void pa66_point(const ProbInc& in, const double* eps, const do
   for (int c = 0; c < 6; ++c) {
     evp1[c] = evp[c] + k15 * o.nd[c];
     dn[c] = d[c] - evp1[c];
-    if (st_out) st_out[(1 + c) * ss] = evp1[c];
+    if (st_out) *pa_at(st_out + (1 + c) * ss, off) = evp1[c];
   }
   const double ep1 = ep + dp;
-  if (st_out) st_out[0] = ep1;
-  double dis = in.sY * dp;
+  if (st_out) *pa_at(st_out, off) = ep1;
   double trd = 0.0;
 #pragma unroll
   for (int c = 0; c < 3; ++c) trd += eps[c] - eps_n[c];
-  double trsum = in.Kinf3 * trd;
-  for (int i = 0; i < in.nm; ++i) {
-    const double* ev = st + (7 + 6 * i) * ss;
-    double* evo = st_out ? st_out + (7 + 6 * i) * ss : nullptr;
-    double v[6];
-#pragma unroll
-    for (int c = 0; c < 6; ++c) v[c] = ev[c * ss];
-    const double sn = (v[0] + v[1] + v[2]) * (1.0 / 3.0);
-    const double s1 = in.fK[i] * (sn + in.rK[i] * em);
-    double dnew[6], dold[6];
-#pragma unroll
-    for (int c = 0; c < 6; ++c) {
-      dold[c] = v[c] - (c < 3 ? sn : 0.0);
-      dnew[c] = in.fG[i] * (dold[c] + in.rG[i] * dn[c]);
-    }
-    double w = in.K3i[i] * (em - s1) * 3.0 * (s1 - sn);
-#pragma unroll
-    for (int c = 0; c < 6; ++c) w += in.G2i[i] * (dn[c] - dnew[c]) * (dnew[c] - dold[c]);
-    dis += w;
-    trsum += in.K3i[i] * (trd - 3.0 * (s1 - sn));
-    if (st_out) {
-#pragma unroll
-      for (int c = 0; c < 6; ++c) evo[c * ss] = dnew[c] + (c < 3 ? s1 : 0.0);
-    }
-  }
-  dis /= dt;
+  double wsum, ksum;
+  pa66_branches(in, st, ss, st_out, dn, em, wsum, ksum, off);
+  const double dis = (in.sY * dp + wsum) / dt;
+  const double trsum = pa66_k3_total(in) * trd - 3.0 * ksum;
   const double Hn = ep1 > 0.0 ? in.hk * powpos(ep1, in.nh) : 0.0;
   *diss = dis;
   *coup = -in.theta * (in.alpha0 * trsum / dt + in.beta1 * Hn * dp / dt) + dis;

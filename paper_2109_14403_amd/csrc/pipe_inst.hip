@@ -12,10 +12,8 @@ namespace {
 
 template <typename T, int C, int N, int NL>
 LaunchInfo xfwd_c(const Pipe<T>& a, hipStream_t s, bool dry) {
-  constexpr int G = N / Plan<N>::M;
-  constexpr int L = NL * ((C + 1) / 2);
   LaunchInfo li;
-  li.threads = G * L;
+  li.threads = xfwd_threads<N, NL, C>();
   li.blocks = a.nprob * ((a.ny * a.nz + NL - 1) / NL);
   li.lds = (size_t)xfwd_lds_elems<N, NL, C>() * sizeof(c2<T>);
   {

@@ -54,46 +54,44 @@ __device__ __forceinline__ void block_sum(double (&v)[K], double* red /* >= K * 
 // ---------------------------------------------------------------------------
 // Green operators on a Mandel (C = 6) or vector (C = 3) complex array.
 // ---------------------------------------------------------------------------
+// Signed frequency of index k on an n-point axis over a length with
+// reciprocal il; the Nyquist entry of an even axis is nulled.
 template <typename T>
-__device__ __forceinline__ void frequency_direction(int kx, int ky, int kz, int nx, int ny, int nz,
-                                                    const double* len, T& n0, T& n1, T& n2, bool& zero) {
-  // signed frequencies; even-size Nyquist entries are nulled
-  int sx = kx;
-  if ((nx & 1) == 0 && kx == nx / 2) sx = 0;
-  int sy = ky < (ny + 1) / 2 ? ky : ky - ny;
-  if ((ny & 1) == 0 && ky == ny / 2) sy = 0;
-  int sz = kz < (nz + 1) / 2 ? kz : kz - nz;
-  if ((nz & 1) == 0 && kz == nz / 2) sz = 0;
-  T a = T(sx) / T(len[0]);
-  T b = T(sy) / T(len[1]);
-  T c = T(sz) / T(len[2]);
-  T m2 = a * a + b * b + c * c;
-  zero = !(m2 > T(0));
-  T inv = zero ? T(0) : T(1) / sqrt(m2);
-  n0 = a * inv;
-  n1 = b * inv;
-  n2 = c * inv;
+__device__ __forceinline__ T frequency_component(int k, int n, T il) {
+  int sk = k < (n + 1) / 2 ? k : k - n;
+  if ((n & 1) == 0 && k == n / 2) sk = 0;
+  return T(sk) * il;
 }
 
+// 1 / sqrt(m2) for m2 > 0: the hardware reciprocal square root (1 ulp) in
+// FP32, the correctly rounded quotient in FP64
+__device__ __forceinline__ float inv_norm(float m2) { return __builtin_amdgcn_rsqf(m2); }
+__device__ __forceinline__ double inv_norm(double m2) { return 1.0 / sqrt(m2); }
+
 template <typename T>
-__device__ __forceinline__ void green_mech(c2<T>* v, T n0, T n1, T n2, T cs, T cn) {
-  // out = cs (n (x) tau n + tau n (x) n) - cn (n . tau n) n (x) n, applied to
-  // real and imaginary parts; projector: cs = 1, cn = 1.
+__device__ __forceinline__ void green_mech(c2<T>* v, T n0, T n1, T n2, T cs, T hcn) {
+  // out = cs (n (x) u + u (x) n) - cn (n . u) n (x) n with u = tau n, applied
+  // to real and imaginary parts (projector: cs = 1, cn = 1), as
+  //   w = cs u - (cn / 2) (n . u) n,  out_ii = 2 n_i w_i,
+  //   out_jk = sqrt2 (n_j w_k + n_k w_j)  (Mandel);  hcn = cn / 2.
+  // Mandel off-diagonal entries carry sqrt2: tau_jk = v / sqrt2.
   const T r2 = T(0.70710678118654752);
   const T s2 = T(1.4142135623730951);
-  c2<T> t11 = v[0], t22 = v[1], t33 = v[2];
-  c2<T> t23 = cscale(v[3], r2), t13 = cscale(v[4], r2), t12 = cscale(v[5], r2);
-  c2<T> u0 = cscale(t11, n0) + cscale(t12, n1) + cscale(t13, n2);
-  c2<T> u1 = cscale(t12, n0) + cscale(t22, n1) + cscale(t23, n2);
-  c2<T> u2 = cscale(t13, n0) + cscale(t23, n1) + cscale(t33, n2);
-  c2<T> q = cscale(u0, n0) + cscale(u1, n1) + cscale(u2, n2);
-  c2<T> qn = cscale(q, cn);
-  v[0] = cscale(cscale(u0, n0), T(2) * cs) - cscale(qn, n0 * n0);
-  v[1] = cscale(cscale(u1, n1), T(2) * cs) - cscale(qn, n1 * n1);
-  v[2] = cscale(cscale(u2, n2), T(2) * cs) - cscale(qn, n2 * n2);
-  v[3] = cscale(cscale(cscale(u1, n2) + cscale(u2, n1), cs) - cscale(qn, n1 * n2), s2);
-  v[4] = cscale(cscale(cscale(u0, n2) + cscale(u2, n0), cs) - cscale(qn, n0 * n2), s2);
-  v[5] = cscale(cscale(cscale(u0, n1) + cscale(u1, n0), cs) - cscale(qn, n0 * n1), s2);
+  const T m0 = n0 * r2, m1 = n1 * r2, m2 = n2 * r2;
+  const c2<T> u0 = cscale(v[0], n0) + cscale(v[5], m1) + cscale(v[4], m2);
+  const c2<T> u1 = cscale(v[5], m0) + cscale(v[1], n1) + cscale(v[3], m2);
+  const c2<T> u2 = cscale(v[4], m0) + cscale(v[3], m1) + cscale(v[2], n2);
+  const c2<T> hq = cscale(cscale(u0, n0) + cscale(u1, n1) + cscale(u2, n2), hcn);
+  const c2<T> w0 = cscale(u0, cs) - cscale(hq, n0);
+  const c2<T> w1 = cscale(u1, cs) - cscale(hq, n1);
+  const c2<T> w2 = cscale(u2, cs) - cscale(hq, n2);
+  v[0] = cscale(w0, n0 + n0);
+  v[1] = cscale(w1, n1 + n1);
+  v[2] = cscale(w2, n2 + n2);
+  const T q0 = n0 * s2, q1 = n1 * s2, q2 = n2 * s2;
+  v[3] = cscale(w2, q1) + cscale(w1, q2);
+  v[4] = cscale(w2, q0) + cscale(w0, q2);
+  v[5] = cscale(w1, q0) + cscale(w0, q1);
 }
 
 // Rotated finite-difference scheme: with e_j = exp(i 2 pi k_j / n_j) and
@@ -258,8 +256,19 @@ constexpr int tile_lds_elems() {
 // ---------------------------------------------------------------------------
 // x forward: pre-operation + packed real-to-complex transforms
 // ---------------------------------------------------------------------------
+// Threads of an x-forward work-group: the G * L of the line transforms, or
+// one per four-voxel work item of the per-voxel phase if that is more (the
+// extra threads idle through the transforms), so that the per-voxel phase,
+// whose loads dominate, takes one memory round trip
+template <int N, int NL, int C>
+constexpr int xfwd_threads() {
+  constexpr int ft = (N / Plan<N>::M) * NL * ((C + 1) / 2);
+  constexpr int items = NL * N / 4;
+  return items > ft ? items : ft;
+}
+
 template <typename T, int C, int N, int NL>
-__global__ void __launch_bounds__((N / Plan<N>::M) * NL * ((C + 1) / 2)) k_xfwd(Pipe<T> a) {
+__global__ void __launch_bounds__((xfwd_threads<N, NL, C>())) k_xfwd(Pipe<T> a) {
   constexpr int M = Plan<N>::M;
   constexpr int G = N / M;
   constexpr int NP = (C + 1) / 2;
@@ -423,15 +432,18 @@ __global__ void __launch_bounds__((N / Plan<N>::M) * NL * ((C + 1) / 2)) k_xfwd(
   }
   __syncthreads();
 
+  const bool fw = tid < G * L;  // a thread of the line transforms
   const int l = tid % L;
-  const int t = tid / L;
+  const int t = fw ? tid / L : 0;
   c2<T> r[M];
 #pragma unroll
-  for (int m = 0; m < M; ++m) r[m] = buf[l * SP + t + G * m];
-  Plan<N>::run(r, t, tw, buf, L, l, true);
+  for (int m = 0; m < M; ++m) r[m] = fw ? buf[l * SP + t + G * m] : mk(T(0), T(0));
+  Plan<N>::run(r, t, tw, buf, L, l, fw);
   __syncthreads();
+  if (fw) {
 #pragma unroll
-  for (int m = 0; m < M; ++m) buf[(t + G * m) * L + l] = r[m];
+    for (int m = 0; m < M; ++m) buf[(t + G * m) * L + l] = r[m];
+  }
   __syncthreads();
 
   // unpack the two real transforms of each complex line and write the block's
@@ -567,26 +579,40 @@ __global__ void __launch_bounds__((N / Plan<N>::M) * TX * C)
   __syncthreads();
 
   const ProbInc& inc = a.inc[prob];
-  T cs = T(1), cn = T(1);
+  T cs = T(1), hcn = T(0.5);
   if (a.green == G_GAMMA0) {
     cs = T(1.0 / (2.0 * inc.mu0));
-    cn = T((inc.lam0 + inc.mu0) / (inc.mu0 * (inc.lam0 + 2.0 * inc.mu0)));
+    hcn = T(0.5 * (inc.lam0 + inc.mu0) / (inc.mu0 * (inc.lam0 + 2.0 * inc.mu0)));
   } else if (a.green == G_GAMMA_TH) {
     cs = T(1.0 / inc.kappa0);
   }
   const bool rot = (a.green == G_PROJ_ROT || a.green == G_GRADPROJ_ROT);
+  // every index of this thread has the same kx (nth is a multiple of TX):
+  // the x and y parts of the frequency are fixed, the z part varies
+  const int kxx = kb * TX + tid % TX;
+  const T fa = frequency_component<T>(kxx, a.nx, T(a.ilen[0]));
+  const T fb = frequency_component<T>(ky, a.ny, T(a.ilen[1]));
+  const T fab2 = fa * fa + fb * fb;
+  const T il2 = T(a.ilen[2]);
+  static_assert(((N / Plan<N>::M) * TX * C) % TX == 0, "thread count must be a multiple of TX");
   for (int idx = tid; idx < N * TX; idx += nth) {
     const int kz = idx / TX;
     const int kxi = idx - kz * TX;
-    const int kxx = kb * TX + kxi;
-    if (kxx >= P) continue;
+    if (kxx >= P) break;
     T n0 = T(0), n1 = T(0), n2 = T(0);
     c2<T> nc[3];
     bool zero;
-    if (rot)
+    if (rot) {
       rotated_direction<T>(a.twx[kxx], a.twy[ky], tw[kz], a.nx, a.ny, a.nz, a.len, nc, zero);
-    else
-      frequency_direction<T>(kxx, ky, kz, a.nx, a.ny, a.nz, a.len, n0, n1, n2, zero);
+    } else {
+      const T fc = frequency_component<T>(kz, a.nz, il2);
+      const T m2 = fc * fc + fab2;
+      zero = !(m2 > T(0));
+      const T inv = zero ? T(0) : inv_norm(m2);
+      n0 = fa * inv;
+      n1 = fb * inv;
+      n2 = fc * inv;
+    }
     c2<T> v[C];
 #pragma unroll
     for (int cc = 0; cc < C; ++cc) v[cc] = buf[kz * L + kxi * C + cc];
@@ -612,7 +638,7 @@ __global__ void __launch_bounds__((N / Plan<N>::M) * TX * C)
         green_grad_herm<T>(v, nc);
     } else {
       if constexpr (C == 6)
-        green_mech<T>(v, n0, n1, n2, cs, cn);
+        green_mech<T>(v, n0, n1, n2, cs, hcn);
       else
         green_grad<T>(v, n0, n1, n2, cs);
     }

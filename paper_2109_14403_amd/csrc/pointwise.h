@@ -41,6 +41,8 @@ struct Pt {
   const ProbInc* inc_pm;    // [prob][2]: increment data at theta + h_theta, theta - h_theta
   const T* s0;              // source of a linearized evaluation (sigma = C x + s0), or null
   int commit;               // commit kernel: 1 commit, 0 only the effective sums (a trial)
+  int dp_known;             // commit: the last evaluation was at the converged strain (its
+                            // plastic increments are in the increment slots)
   T* dx;                    // strain change of the last committed increment [prob][6][nvox], or null
   const T* x0;              // start of a linearized solve [prob][6][nvox], or null (uniform dE)
 };
@@ -87,8 +89,24 @@ template <typename T>
 void launch_history(const Pt<T>& a, hipStream_t s);
 void launch_reduce_a(Ctl* ctl, const double* part, int maxblk, int nblk, int nprob, Limits lim, hipStream_t s);
 void launch_reduce_alpha(Ctl* ctl, const double* part, int maxblk, int nblk, int nprob, hipStream_t s);
+// Whether a commit with these arguments takes the one-voxel-per-thread path
+// (internal variables, plastic increments of the last evaluation known), and
+// the blocks per problem (partial sums) it then writes.
 template <typename T>
-void launch_commit(const Pt<T>& a, int C, hipStream_t s);
+inline bool commit_per_voxel(const Pt<T>& a, int C) {
+  return C == 6 && a.dp_known && a.state && a.hist;
+}
+inline int commit_voxel_blocks(long long nvox) { return (int)((nvox + 255) / 256); }
+// Returns the blocks per problem whose partial sums it wrote (a.bpp, or
+// commit_voxel_blocks(a.nvox) on the one-voxel-per-thread path; a.maxblk must
+// hold them).
+template <typename T>
+int launch_commit(const Pt<T>& a, int C, hipStream_t s);
 void launch_reduce_out(Ctl* ctl, const double* part, int maxblk, int nblk, int nprob, int nk, double scale,
                        hipStream_t s);
+// First stage of a reduction over many blocks: block (prob, j) sums the
+// partials [j * RED_CHUNK, (j + 1) * RED_CHUNK) of every quantity in a fixed
+// order into out[prob][NPART][nout], nout = ceil(nblk / RED_CHUNK).
+constexpr int RED_CHUNK = 512;
+void launch_reduce_stage(const double* part, int maxblk, int nblk, double* out, int nout, int nprob, hipStream_t s);
 }  // namespace hom

@@ -133,21 +133,26 @@ __global__ void __launch_bounds__(PT_THREADS) k_history(Pt<T> a) {
   const ProbInc& in = a.inc[prob];
   const long long nv = a.nvox;
   const uint8_t* phase = a.phase + (long long)prob * nv;
-  for (long long v = (long long)blk * PT_THREADS + threadIdx.x; v < nv; v += (long long)a.bpp * PT_THREADS) {
-    if (phase[v] != in.pa_phase) continue;
+  const double* st = a.state + (long long)prob * a.nstate * nv;
+  double* h = a.hist + (long long)prob * HIST_SLOTS * nv;
+  for (long long vl = (long long)blk * PT_THREADS + threadIdx.x; vl < nv; vl += (long long)a.bpp * PT_THREADS) {
+    const unsigned v = (unsigned)vl;
+    if (*pa_at(phase, v) != in.pa_phase) continue;
     double hd[6], hs;
-    pa66_history(in, a.state + (long long)prob * a.nstate * nv + v, nv, hd, hs);
-    double* h = a.hist + (long long)prob * HIST_SLOTS * nv + v;
+    pa66_history(in, st, nv, hd, hs, v);
 #pragma unroll
-    for (int c = 0; c < 6; ++c) stnt(h + c * nv, hd[c]);
-    stnt(h + 6 * nv, hs);
-    stnt(h + 7 * nv, -1.0);  // no plastic increment known yet
+    for (int c = 0; c < 6; ++c) stnt(pa_at(h + c * nv, v), hd[c]);
+    stnt(pa_at(h + 6 * nv, v), hs);
+    stnt(pa_at(h + 7 * nv, v), -1.0);  // no plastic increment known yet
   }
 }
 
-// Commit of a converged increment (a.commit = 1): new internal variables, the
-// committed strain, the stress field and the effective sums. With a.commit = 0
-// only the sums are formed (an increment that is not final yet).
+// One-kernel commit: the effective sums of a converged increment and, with
+// a.commit = 1, the new internal variables, the committed strain and the
+// stress field (a.commit = 0: the sums of an increment that is not final
+// yet). It serves conduction, mechanics without internal variables, and the
+// basic scheme, whose last evaluation precedes its last strain update;
+// otherwise k_commit_vox below takes the mechanics.
 template <typename T, int C>
 __global__ void __launch_bounds__(PT_THREADS) k_commit(Pt<T> a) {
   constexpr int NS = C == 6 ? MECH_SUMS : 8;
@@ -227,6 +232,116 @@ __global__ void __launch_bounds__(PT_THREADS) k_commit(Pt<T> a) {
   if (threadIdx.x == 0) {
 #pragma unroll
     for (int k = 0; k < NS; ++k) a.part[part_index(prob, k, blk, a.maxblk)] = acc[k];
+  }
+}
+
+// Effective sums (and, with a.commit = 1, the commit) of a converged
+// increment for mechanics with internal variables whose last evaluation was
+// at the converged strain (a.dp_known = 1: its plastic increments are in the
+// increment slots): the radial return at that plastic increment without the
+// scalar Newton iteration, the new eps_p and eps_vp, the Maxwell branches
+// streamed PA66_GROUP at a time, the committed strain and stress fields, and
+// the effective sums. One voxel per thread (a.bpp = ceil(nvox / PT_THREADS)):
+// without a voxel loop the loop-invariant constants of the FP64 exp/log do
+// not hold registers for the whole kernel, and more waves keep loads in
+// flight. A trial (a.commit = 0) runs the same arithmetic without the writes,
+// so that its sums equal those of the commit bit for bit.
+template <typename T>
+__global__ void __launch_bounds__(PT_THREADS) k_commit_vox(Pt<T> a) {
+  __shared__ double red[MECH_SUMS * 16];
+  const int prob = blockIdx.x / a.bpp;
+  const int blk = blockIdx.x % a.bpp;
+  const Ctl& ctl = a.ctl[prob];
+  if (ctl.status != 1) return;
+  const ProbInc& in = a.inc[prob];
+  const long long nv = a.nvox;
+  const long long fo = (long long)prob * 6 * nv;
+  const uint8_t* phase = a.phase + (long long)prob * nv;
+  const double k3 = pa66_k3_total(in);
+  const bool commit = a.commit != 0;
+  // uniform bases; the voxel is a 32-bit offset
+  const T* xb = a.x + fo;
+  T* xnb = a.xn + fo;
+  T* fb = a.f + fo;
+  T* dxb = a.dx ? a.dx + fo : nullptr;
+  double* st = a.state + (long long)prob * a.nstate * nv;
+  const double* hs = a.hist + (long long)prob * HIST_SLOTS * nv;
+  double* pvd = commit && a.pv_diss ? a.pv_diss + (long long)prob * nv : nullptr;
+  double* pvc = commit && a.pv_coup ? a.pv_coup + (long long)prob * nv : nullptr;
+  double acc[MECH_SUMS];
+#pragma unroll
+  for (int k = 0; k < MECH_SUMS; ++k) acc[k] = 0.0;
+  const long long vl = (long long)blk * PT_THREADS + threadIdx.x;
+  if (vl < nv) {
+    const unsigned v = (unsigned)vl;
+    const int ph = *pa_at(phase, v);
+    double e[6], en[6];
+#pragma unroll
+    for (int c = 0; c < 6; ++c) {
+      e[c] = (double)*pa_at(xb + c * nv, v);
+      en[c] = (double)*pa_at(xnb + c * nv, v);
+    }
+    double sg[6], dis = 0.0, cpl;
+    const double trd = (e[0] - en[0]) + (e[1] - en[1]) + (e[2] - en[2]);
+    if (ph == in.pa_phase) {
+      PaOut o;
+      PaPre p;
+      pa66_return_at(in, e, st, nv, hs, ldnt(pa_at(hs + 7 * nv, v)), o, p, v);
+      const double k15 = 1.2247448713915890 * o.dp;
+      double dn[6];
+#pragma unroll
+      for (int c = 0; c < 6; ++c) {
+        const double evp1 = p.evp[c] + k15 * o.nd[c];
+        dn[c] = p.d[c] - evp1;
+        if (commit) *pa_at(st + (1 + c) * nv, v) = evp1;
+      }
+      const double ep1 = p.ep + o.dp;
+      if (commit) *pa_at(st, v) = ep1;
+      double wsum, ksum;
+      pa66_branches(in, st, nv, commit ? st : nullptr, dn, p.em, wsum, ksum, v);
+      const double Hn = ep1 > 0.0 ? in.hk * powpos(ep1, in.nh) : 0.0;
+      dis = (in.sY * o.dp + wsum) / in.dt;
+      cpl = -in.theta * (in.alpha0 * (k3 * trd - 3.0 * ksum) + in.beta1 * Hn * o.dp) / in.dt + dis;
+#pragma unroll
+      for (int c = 0; c < 6; ++c) sg[c] = o.sig[c];
+    } else {
+      const PhaseInc& pi = in.ph[ph];
+      const double tr3 = (e[0] + e[1] + e[2]) * (1.0 / 3.0);
+      const double sph = pi.K3 * (tr3 - pi.alpha_dth) - pi.G2 * tr3;
+#pragma unroll
+      for (int c = 0; c < 6; ++c) sg[c] = pi.G2 * e[c];
+      sg[0] += sph;
+      sg[1] += sph;
+      sg[2] += sph;
+      // Gough-Joule: D = -theta eps_dot : C[alpha] (paper Sec. 4, E-glass)
+      cpl = -in.theta * pi.K3 * pi.alpha0 * trd / in.dt;
+    }
+#pragma unroll
+    for (int c = 0; c < 6; ++c) {
+      acc[c] = sg[c];
+      acc[8 + c] = e[c];
+    }
+    acc[6] = dis;
+    acc[7] = cpl;
+    if (commit) {
+#pragma unroll
+      for (int c = 0; c < 6; ++c) {
+        *pa_at(xnb + c * nv, v) = T(e[c]);  // the committed strain (exact: e was read from T)
+        *pa_at(fb + c * nv, v) = T(sg[c]);
+      }
+      if (dxb)
+#pragma unroll
+        for (int c = 0; c < 6; ++c) *pa_at(dxb + c * nv, v) = T(e[c] - en[c]);
+      if (pvd) {
+        *pa_at(pvd, v) = dis;
+        *pa_at(pvc, v) = cpl;
+      }
+    }
+  }
+  block_sum<MECH_SUMS>(acc, red);
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int k = 0; k < MECH_SUMS; ++k) a.part[part_index(prob, k, blk, a.maxblk)] = acc[k];
   }
 }
 
@@ -539,6 +654,29 @@ __global__ void __launch_bounds__(RED_THREADS) k_reduce_alpha(Ctl* ctl, const do
   c.cg_ready = 1;
 }
 
+constexpr int RED_STAGE_THREADS = 256;
+__global__ void __launch_bounds__(RED_STAGE_THREADS) k_reduce_stage(const double* part, int maxblk, int nblk,
+                                                                    double* out, int nout) {
+  __shared__ double red[NPART * 16];
+  const int prob = blockIdx.x / nout;
+  const int j = blockIdx.x % nout;
+  const int b0 = j * RED_CHUNK;
+  const int nb = min(RED_CHUNK, nblk - b0);
+  double v[NPART];
+#pragma unroll
+  for (int k = 0; k < NPART; ++k) v[k] = 0.0;
+  const double* base = part + part_index(prob, 0, b0, maxblk);
+  for (int b = threadIdx.x; b < nb; b += blockDim.x) {
+#pragma unroll
+    for (int k = 0; k < NPART; ++k) v[k] += base[(long long)k * maxblk + b];
+  }
+  block_sum<NPART>(v, red);
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int k = 0; k < NPART; ++k) out[part_index(prob, k, j, nout)] = v[k];
+  }
+}
+
 __global__ void __launch_bounds__(RED_THREADS) k_reduce_out(Ctl* ctl, const double* part, int maxblk, int nblk,
                                                              int nk, double scale) {
   __shared__ double red[NPART * 16];
@@ -574,17 +712,29 @@ void launch_history(const Pt<T>& a, hipStream_t s) {
   hipLaunchKernelGGL((k_history<T>), dim3(a.nprob * a.bpp), dim3(PT_THREADS), 0, s, a);
 }
 template <typename T>
-void launch_commit(const Pt<T>& a, int C, hipStream_t s) {
+int launch_commit(const Pt<T>& a, int C, hipStream_t s) {
+  static_assert(PT_THREADS == 256, "commit_voxel_blocks takes 256 voxels a block");
+  if (commit_per_voxel(a, C)) {
+    Pt<T> b = a;
+    b.bpp = commit_voxel_blocks(a.nvox);
+    hipLaunchKernelGGL((k_commit_vox<T>), dim3((long long)b.nprob * b.bpp), dim3(PT_THREADS), 0, s, b);
+    return b.bpp;
+  }
   if (C == 6)
     hipLaunchKernelGGL((k_commit<T, 6>), dim3(a.nprob * a.bpp), dim3(PT_THREADS), 0, s, a);
   else
     hipLaunchKernelGGL((k_commit<T, 3>), dim3(a.nprob * a.bpp), dim3(PT_THREADS), 0, s, a);
+  return a.bpp;
 }
 void launch_reduce_a(Ctl* ctl, const double* part, int maxblk, int nblk, int nprob, Limits lim, hipStream_t s) {
   hipLaunchKernelGGL(k_reduce_a, dim3(nprob), dim3(RED_THREADS), 0, s, ctl, part, maxblk, nblk, lim);
 }
 void launch_reduce_alpha(Ctl* ctl, const double* part, int maxblk, int nblk, int nprob, hipStream_t s) {
   hipLaunchKernelGGL(k_reduce_alpha, dim3(nprob), dim3(RED_THREADS), 0, s, ctl, part, maxblk, nblk);
+}
+void launch_reduce_stage(const double* part, int maxblk, int nblk, double* out, int nout, int nprob, hipStream_t s) {
+  hipLaunchKernelGGL(k_reduce_stage, dim3((long long)nprob * nout), dim3(RED_STAGE_THREADS), 0, s, part, maxblk, nblk,
+                     out, nout);
 }
 void launch_reduce_out(Ctl* ctl, const double* part, int maxblk, int nblk, int nprob, int nk, double scale,
                        hipStream_t s) {
@@ -617,7 +767,7 @@ void launch_tangent_sum(const Pt<T>& a, hipStream_t s) {
   template void launch_init_th<T>(const Pt<T>&, int, hipStream_t);      \
   template void launch_eval<T>(const Pt<T>&, int, hipStream_t);         \
   template void launch_history<T>(const Pt<T>&, hipStream_t);           \
-  template void launch_commit<T>(const Pt<T>&, int, hipStream_t);
+  template int launch_commit<T>(const Pt<T>&, int, hipStream_t);
 HOM_INST_PT(float)
 HOM_INST_PT(double)
 

@@ -262,6 +262,7 @@ struct Group {
   Ctl* ctl_h = nullptr;
   double* part = nullptr;
   int maxblk = 0;
+  double* part2 = nullptr;  // first-stage sums of a reduction over many blocks [prob][NPART][nout]
   c2<T>* tw[3] = {nullptr, nullptr, nullptr};
   int txy[2] = {4, 4}, txz[2] = {4, 4};  // [mech, thermal]
   int pt_bpp = 1;
@@ -362,7 +363,10 @@ struct Group {
     xfblocks = (ny * nz + nlf - 1) / nlf;
     xiblocks = (ny * nz + nli - 1) / nli;
     maxblk = std::max(pt_bpp, std::max(xfblocks, xiblocks));
+    // the commit of the internal variables: one partial a block of 256 voxels
+    if (with_state && nstate > 0) maxblk = std::max(maxblk, commit_voxel_blocks(nvox));
     part = dalloc<double>((size_t)nprob * maxblk * NPART);
+    part2 = dalloc<double>((size_t)nprob * ((maxblk + RED_CHUNK - 1) / RED_CHUNK) * NPART);
     for (int d = 0; d < 3; ++d) {
       const int n = d == 0 ? nx : (d == 1 ? ny : nz);
       auto w = twiddles<T>(n);
@@ -409,7 +413,10 @@ struct Group {
     a.twx = tw[0];
     a.twy = tw[1];
     a.twz = tw[2];
-    for (int d = 0; d < 3; ++d) a.len[d] = len[d];
+    for (int d = 0; d < 3; ++d) {
+      a.len[d] = len[d];
+      a.ilen[d] = 1.0 / len[d];
+    }
     a.green = green;
     return a;
   }
@@ -442,6 +449,7 @@ struct Group {
     a.inc_pm = inc_pm_d;
     a.s0 = nullptr;
     a.commit = 1;
+    a.dp_known = 0;
     a.dx = dx;
     a.x0 = nullptr;
     return a;
@@ -804,6 +812,18 @@ class BatchT : public BatchImpl {
     iterate(G, 0, basic, iteration_cap(limits(0), basic));
   }
 
+  // Per-problem means of the first nk partial-sum quantities over nb blocks into
+  // ctl.out; many blocks (one voxel per thread) are summed in two stages.
+  static void reduce_out(Group<T>& G, Ctl* ctl, int nb, int nk, hipStream_t stream) {
+    if (nb > 2 * RED_CHUNK) {
+      const int nout = (nb + RED_CHUNK - 1) / RED_CHUNK;
+      launch_reduce_stage(G.part, G.maxblk, nb, G.part2, nout, G.nprob, stream);
+      launch_reduce_out(ctl, G.part2, nout, nout, G.nprob, nk, 1.0 / (double)G.nvox, stream);
+    } else {
+      launch_reduce_out(ctl, G.part, G.maxblk, nb, G.nprob, nk, 1.0 / (double)G.nvox, stream);
+    }
+  }
+
   // Effective sums of the converged mechanics into ctl.out (copied to ctl_h);
   // commit: also commit the increment of every converged problem; partials:
   // the point partials of the tangent option (before a commit: state n).
@@ -811,12 +831,14 @@ class BatchT : public BatchImpl {
     hipStream_t stream = G.stream;  // this group's lane
     Pt<T> q = G.pt(0);
     q.commit = commit ? 1 : 0;
+    // Newton-CG converges on a residual evaluation at the final strain
+    q.dp_known = opts.scheme == HOM_SCHEME_NEWTON_CG ? 1 : 0;
     if (partials && G.dsdt) launch_partials<T>(q, stream);
     prof.begin(K_COMMIT, stream);
-    launch_commit<T>(q, 6, stream);
+    const int nb = launch_commit<T>(q, 6, stream);
     prof.end(stream);
     prof.begin(K_REDOUT, stream);
-    launch_reduce_out(G.ctl_m, G.part, G.maxblk, G.pt_bpp, G.nprob, MECH_SUMS, 1.0 / (double)G.nvox, stream);
+    reduce_out(G, G.ctl_m, nb, MECH_SUMS, stream);
     prof.end(stream);
     HIPCHK(hipMemcpyAsync(G.ctl_h, G.ctl_m, sizeof(Ctl) * G.nprob, hipMemcpyDeviceToHost, stream));
     HIPCHK(hipStreamSynchronize(stream));
@@ -834,10 +856,10 @@ class BatchT : public BatchImpl {
     prof.end(stream);
     iterate(G, 1, basic, iteration_cap(limits(1), basic));
     prof.begin(K_COMMIT, stream);
-    launch_commit<T>(q, 3, stream);
+    const int nb = launch_commit<T>(q, 3, stream);
     prof.end(stream);
     prof.begin(K_REDOUT, stream);
-    launch_reduce_out(G.ctl_t, G.part, G.maxblk, G.pt_bpp, G.nprob, 3, 1.0 / (double)G.nvox, stream);
+    reduce_out(G, G.ctl_t, nb, 3, stream);
     prof.end(stream);
     HIPCHK(hipMemcpyAsync(G.ctl_h, G.ctl_t, sizeof(Ctl) * G.nprob, hipMemcpyDeviceToHost, stream));
     HIPCHK(hipStreamSynchronize(stream));
@@ -1382,7 +1404,7 @@ void eval_law(const hom_law& law, int64_t count, const double* eps, const double
   G.ctl_m = G.dalloc<Ctl>(1);
   G.inc_d = G.dalloc<ProbInc>(1);
   G.pt_bpp = (int)std::min<int64_t>((count + 255) / 256, 4096);
-  G.maxblk = G.pt_bpp;
+  G.maxblk = std::max(G.pt_bpp, commit_voxel_blocks(count));  // the commit below: a partial a block of 256
   G.part = G.dalloc<double>((size_t)G.maxblk * NPART);
   double* pvd = G.dalloc<double>(count);
   double* pvc = G.dalloc<double>(count);
@@ -1413,6 +1435,7 @@ void eval_law(const hom_law& law, int64_t count, const double* eps, const double
     c.status = 1;
     c.mode = M_DONE;
     HIPCHK(hipMemcpy(G.ctl_m, &c, sizeof(c), hipMemcpyHostToDevice));
+    q.dp_known = 1;  // the evaluation above was at this strain
     launch_commit<double>(q, 6, nullptr);
     HIPCHK(hipGetLastError());
     HIPCHK(hipDeviceSynchronize());
