@@ -114,6 +114,8 @@ struct Pipe {
   double len[3];
   double ilen[3];           // 1 / len
   int green;                // Green enum
+  int alpha_blocks;         // > 0: the z pass forms the CG step length from the first
+                            // alpha_blocks partial sums of the x-forward pass
 };
 
 __device__ __forceinline__ bool pipeline_mode(int m) { return m == M_EVAL || m == M_CG || m == M_BASIC; }

@@ -560,6 +560,30 @@ __global__ void __launch_bounds__((N / Plan<N>::M) * TX * C)
   const int kb = b % nkb;
   const int tid = threadIdx.x;
   const int nth = blockDim.x;
+  if (a.alpha_blocks > 0 && b == 0) {
+    // CG step length alpha = r.r / p.C p from the x-forward pass's partials of
+    // p.C p (= p.A p: p is compatible and the projector orthogonal). Formed
+    // by the first work-group of the problem while the others transform; the
+    // x-inverse pass applies it.
+    Ctl& cw = a.ctl[prob];
+    if (cw.mode == M_CG && !cw.cg_ready) {  // uniform over the work-group
+      __shared__ double red[16];
+      double s[1] = {0.0};
+      const double* pp = a.part + part_index(prob, 0, 0, a.maxblk);
+      for (int i = tid; i < a.alpha_blocks; i += nth) s[0] += pp[i];
+      block_sum<1>(s, red);
+      if (tid == 0) {
+        const double pap = s[0];
+        if (!(pap > 0.0) || !isfinite(pap)) {
+          cw.mode = M_FAIL;
+          cw.status = -4;
+        } else {
+          cw.alpha = cw.rr / pap;
+          cw.cg_ready = 1;
+        }
+      }
+    }
+  }
   for (int i = tid; i < N; i += nth) tw[i] = a.twz[i];
   const int l = tid % L;
   const int t = tid / L;

@@ -88,7 +88,6 @@ void launch_tangent_sum(const Pt<T>& a, hipStream_t s);
 template <typename T>
 void launch_history(const Pt<T>& a, hipStream_t s);
 void launch_reduce_a(Ctl* ctl, const double* part, int maxblk, int nblk, int nprob, Limits lim, hipStream_t s);
-void launch_reduce_alpha(Ctl* ctl, const double* part, int maxblk, int nblk, int nprob, hipStream_t s);
 // Whether a commit with these arguments takes the one-voxel-per-thread path
 // (internal variables, plastic increments of the last evaluation known), and
 // the blocks per problem (partial sums) it then writes.

@@ -632,28 +632,6 @@ __global__ void __launch_bounds__(RED_THREADS) k_reduce_a(Ctl* ctl, const double
   }
 }
 
-// After the x-forward pass of a CG iteration: alpha = r.r / p.C p. For a
-// compatible direction p, p.C p equals p.A p = p.P[C p] because P is an
-// orthogonal projector, so alpha is known before the inverse transforms and
-// the x-inverse pass can apply the CG update itself.
-__global__ void __launch_bounds__(RED_THREADS) k_reduce_alpha(Ctl* ctl, const double* part, int maxblk, int nblk) {
-  __shared__ double red[16];
-  __shared__ double s[1];
-  const int prob = blockIdx.x;
-  Ctl& c = ctl[prob];
-  if (c.mode != M_CG || c.cg_ready) return;
-  sum_parts<1>(part, maxblk, nblk, prob, s, red);
-  if (threadIdx.x != 0) return;
-  const double pap = s[0];
-  if (!(pap > 0.0) || !isfinite(pap)) {
-    c.mode = M_FAIL;
-    c.status = -4;
-    return;
-  }
-  c.alpha = c.rr / pap;
-  c.cg_ready = 1;
-}
-
 constexpr int RED_STAGE_THREADS = 256;
 __global__ void __launch_bounds__(RED_STAGE_THREADS) k_reduce_stage(const double* part, int maxblk, int nblk,
                                                                     double* out, int nout) {
@@ -728,9 +706,6 @@ int launch_commit(const Pt<T>& a, int C, hipStream_t s) {
 }
 void launch_reduce_a(Ctl* ctl, const double* part, int maxblk, int nblk, int nprob, Limits lim, hipStream_t s) {
   hipLaunchKernelGGL(k_reduce_a, dim3(nprob), dim3(RED_THREADS), 0, s, ctl, part, maxblk, nblk, lim);
-}
-void launch_reduce_alpha(Ctl* ctl, const double* part, int maxblk, int nblk, int nprob, hipStream_t s) {
-  hipLaunchKernelGGL(k_reduce_alpha, dim3(nprob), dim3(RED_THREADS), 0, s, ctl, part, maxblk, nblk);
 }
 void launch_reduce_stage(const double* part, int maxblk, int nblk, double* out, int nout, int nprob, hipStream_t s) {
   hipLaunchKernelGGL(k_reduce_stage, dim3((long long)nprob * nout), dim3(RED_STAGE_THREADS), 0, s, part, maxblk, nblk,

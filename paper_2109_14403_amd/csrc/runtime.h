@@ -33,7 +33,6 @@ enum KernelKind {
   K_XINV,
   K_REDA,
   K_HIST,
-  K_REDALPHA,
   K_COMMIT,
   K_REDOUT,
   K_COUNT

@@ -13,9 +13,9 @@
 namespace hom {
 
 const char* const kKernelNames[2 * K_COUNT] = {
-    "init",   "eval",   "xfwd",   "yfwd",     "zgreen",  "yinv",      "xinv",    "reduce_a",
-    "history",  "reduce_alpha", "commit", "reduce_out", "t.init", "t.eval", "t.xfwd", "t.yfwd",
-    "t.zgreen", "t.yinv", "t.xinv", "t.reduce_a", "t.history", "t.reduce_alpha", "t.commit", "t.reduce_out"};
+    "init",     "eval",   "xfwd",   "yfwd",       "zgreen",   "yinv",    "xinv",   "reduce_a", "history",
+    "commit",   "reduce_out", "t.init", "t.eval",  "t.xfwd",   "t.yfwd",  "t.zgreen", "t.yinv", "t.xinv",
+    "t.reduce_a", "t.history", "t.commit", "t.reduce_out"};
 
 void fail(int code, const std::string& msg) { throw Error{code, msg}; }
 
@@ -306,8 +306,7 @@ struct Group {
 
   // streams of this group's work (the batch's own, or a lane of its own that
   // lets groups of different grids run at the same time)
-  hipStream_t stream = nullptr, side = nullptr;
-  hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+  hipStream_t stream = nullptr;
 
   ~Group() {
     for (int i = 0; i < 4; ++i)
@@ -418,6 +417,7 @@ struct Group {
       a.ilen[d] = 1.0 / len[d];
     }
     a.green = green;
+    a.alpha_blocks = 0;
     return a;
   }
 
@@ -468,24 +468,15 @@ class BatchT : public BatchImpl {
   hom_options opts;
   hipStream_t stream = nullptr;
   bool own_stream = false;
-  // side branch of an iteration: the alpha reduction overlaps the y / z passes
-  // (default priority, like every stream here)
-  hipStream_t side = nullptr;
-  hipEvent_t ev_fork = nullptr, ev_join = nullptr;
   Profiler prof;
   bool linear_mech = true;
   int device = 0;
   // lanes created for groups after the first (library-owned streams only)
   std::vector<hipStream_t> lane_streams;
-  std::vector<hipEvent_t> lane_events;
 
   ~BatchT() override {
     groups.clear();
-    for (hipEvent_t e : lane_events) (void)hipEventDestroy(e);
     for (hipStream_t q : lane_streams) (void)hipStreamDestroy(q);
-    if (ev_fork) (void)hipEventDestroy(ev_fork);
-    if (ev_join) (void)hipEventDestroy(ev_join);
-    if (side) (void)hipStreamDestroy(side);
     if (own_stream && stream) (void)hipStreamDestroy(stream);
   }
 
@@ -521,9 +512,6 @@ class BatchT : public BatchImpl {
       HIPCHK(hipStreamCreateWithFlags(&stream, hipStreamNonBlocking));
       own_stream = true;
     }
-    HIPCHK(hipStreamCreateWithFlags(&side, hipStreamNonBlocking));
-    HIPCHK(hipEventCreateWithFlags(&ev_fork, hipEventDisableTiming));
-    HIPCHK(hipEventCreateWithFlags(&ev_join, hipEventDisableTiming));
     // group problems by grid
     std::map<std::tuple<int, int, int, double, double, double>, int> key;
     where.resize(nprob);
@@ -560,19 +548,10 @@ class BatchT : public BatchImpl {
       Group<T>& G = *groups[gi];
       if (gi == 0 || !own_stream) {
         G.stream = stream;
-        G.side = side;
-        G.ev_fork = ev_fork;
-        G.ev_join = ev_join;
         continue;
       }
       HIPCHK(hipStreamCreateWithFlags(&G.stream, hipStreamNonBlocking));
       lane_streams.push_back(G.stream);
-      HIPCHK(hipStreamCreateWithFlags(&G.side, hipStreamNonBlocking));
-      lane_streams.push_back(G.side);
-      HIPCHK(hipEventCreateWithFlags(&G.ev_fork, hipEventDisableTiming));
-      lane_events.push_back(G.ev_fork);
-      HIPCHK(hipEventCreateWithFlags(&G.ev_join, hipEventDisableTiming));
-      lane_events.push_back(G.ev_join);
     }
     const int nst = pa66_nstate(laws);
     for (auto& gp : groups) {
@@ -688,13 +667,13 @@ class BatchT : public BatchImpl {
   // mechanics (sigma = C_algo x), 3 linearized mechanics with the source
   // d sigma / d theta.
   void iteration(Group<T>& G, int variant, bool basic) {
-    hipStream_t stream = G.stream, side = G.side;  // this group's lane
-    hipEvent_t ev_fork = G.ev_fork, ev_join = G.ev_join;
+    hipStream_t stream = G.stream;  // this group's lane
     const int phys = variant == 1 ? 1 : 0;
     const bool rot = opts.discretization == HOM_DISC_ROTATED;
     const int green = phys == 0 ? (basic ? G_GAMMA0 : (rot ? G_PROJ_ROT : G_PROJ))
                                 : (basic ? G_GAMMA_TH : (rot ? G_GRADPROJ_ROT : G_GRADPROJ));
     Pipe<T> a = G.pipe(phys, green);
+    if (!basic) a.alpha_blocks = G.xfblocks;  // the z pass forms the CG step length
     Pt<T> q = G.pt(phys);
     const int C = phys == 0 ? 6 : 3;
     Limits lim = limits(phys);
@@ -711,16 +690,6 @@ class BatchT : public BatchImpl {
     prof.begin(K_XFWD, stream);
     run_xfwd<T>(a, stream);
     prof.end(stream);
-    if (!basic) {
-      // alpha = r.r / p.C p is first needed by the x-inverse pass: reduce it on
-      // the side stream while the y / z passes run (they only read the mode)
-      HIPCHK(hipEventRecord(ev_fork, stream));
-      HIPCHK(hipStreamWaitEvent(side, ev_fork, 0));
-      prof.begin(K_REDALPHA, side);
-      launch_reduce_alpha(ctl, G.part, G.maxblk, G.xfblocks, G.nprob, side);
-      prof.end(side);
-      HIPCHK(hipEventRecord(ev_join, side));
-    }
     prof.begin(K_YFWD, stream);
     run_ypass<T>(a, G.txy[phys], 0, stream);
     prof.end(stream);
@@ -730,7 +699,6 @@ class BatchT : public BatchImpl {
     prof.begin(K_YINV, stream);
     run_ypass<T>(a, G.txy[phys], 1, stream);
     prof.end(stream);
-    if (!basic) HIPCHK(hipStreamWaitEvent(stream, ev_join, 0));
     prof.begin(K_XINV, stream);
     run_xinv<T>(a, stream);
     prof.end(stream);
