@@ -32,6 +32,7 @@ static __device__ __align__(256) float scratch[HOM_STATIC_SCRATCH_FLOATS];
 namespace hom {
 
 typedef __bf16 bf16x8_t __attribute__((ext_vector_type(8)));
+typedef __bf16 bf16x4_t __attribute__((ext_vector_type(4)));
 typedef float floatx4_t __attribute__((ext_vector_type(4)));
 
 constexpr int MROWS = 64;  // rows per forward work-group
@@ -140,24 +141,27 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) k
         nh[cb] = *reinterpret_cast<const bf16x8_t*>(whi + nn * K + k1 + kq);
         if constexpr (PRECISE) nl[cb] = *reinterpret_cast<const bf16x8_t*>(wlo + nn * K + k1 + kq);
       }
-      // hi and lo passes over all 16 tiles: no product waits on the previous
-      // one into the same accumulator
+      // the transposed tile Z^T = W A^T (weights as the first operand): each
+      // lane's four accumulator values are four consecutive outputs of one
+      // row, stored as one 8-byte LDS write per part in the epilogue. hi and
+      // lo passes over all 16 tiles: no product waits on the previous one into
+      // the same accumulator
 #pragma unroll
       for (int rb = 0; rb < 4; ++rb)
 #pragma unroll
         for (int cb = 0; cb < 4; ++cb)
-          acc[rb][cb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(xh[rb], bh[cb], acc[rb][cb], 0, 0, 0);
+          acc[rb][cb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(bh[cb], xh[rb], acc[rb][cb], 0, 0, 0);
 #pragma unroll
       for (int rb = 0; rb < 4; ++rb)
 #pragma unroll
         for (int cb = 0; cb < 4; ++cb)
-          acc[rb][cb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(xl[rb], bh[cb], acc[rb][cb], 0, 0, 0);
+          acc[rb][cb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(bh[cb], xl[rb], acc[rb][cb], 0, 0, 0);
       if constexpr (PRECISE) {
 #pragma unroll
         for (int rb = 0; rb < 4; ++rb)
 #pragma unroll
           for (int cb = 0; cb < 4; ++cb)
-            acc[rb][cb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(xh[rb], bl[cb], acc[rb][cb], 0, 0, 0);
+            acc[rb][cb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(bl[cb], xh[rb], acc[rb][cb], 0, 0, 0);
       }
 #pragma unroll
       for (int cb = 0; cb < 4; ++cb) {
@@ -166,30 +170,36 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) k
       }
     }
     __syncthreads();  // all waves done reading this layer's input
-    float bv[4];
+    // lane: row m = rb 16 + lrow, outputs nn0 .. nn0 + 3 of tile cb
+    floatx4_t bv[4];
 #pragma unroll
-    for (int cb = 0; cb < 4; ++cb) bv[cb] = a.bias[l][wave * 64 + cb * 16 + lrow];
+    for (int cb = 0; cb < 4; ++cb)
+      bv[cb] = *reinterpret_cast<const floatx4_t*>(a.bias[l] + wave * 64 + cb * 16 + (lane >> 4) * 4);
 #pragma unroll
     for (int rb = 0; rb < 4; ++rb)
 #pragma unroll
-      for (int cb = 0; cb < 4; ++cb)
+      for (int cb = 0; cb < 4; ++cb) {
+        const int m = rb * 16 + lrow;
+        const int nn0 = wave * 64 + cb * 16 + (lane >> 4) * 4;
+        floatx4_t z, g;
+        bf16x4_t h, lo;
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
-          const int m = rb * 16 + (lane >> 4) * 4 + i;
-          const int nn = wave * 64 + cb * 16 + lrow;
-          const float z = acc[rb][cb][i] + bv[cb];
-          const float g = gelu_f(z);
-          const __bf16 h = (__bf16)g;
-          ahi[m * AST + nn] = h;
-          alo[m * AST + nn] = (__bf16)(g - (float)h);
-          if constexpr (SAVE) {
-            const long long gr = row0 + m;
-            if (gr < a.n) {
-              a.zs[l][gr * MLP_W + nn] = z;
-              a.as[l][gr * MLP_W + nn] = g;
-            }
+          z[i] = acc[rb][cb][i] + bv[cb][i];
+          g[i] = gelu_f(z[i]);
+          h[i] = (__bf16)g[i];
+          lo[i] = (__bf16)(g[i] - (float)h[i]);
+        }
+        *reinterpret_cast<bf16x4_t*>(ahi + m * AST + nn0) = h;
+        *reinterpret_cast<bf16x4_t*>(alo + m * AST + nn0) = lo;
+        if constexpr (SAVE) {
+          const long long gr = row0 + m;
+          if (gr < a.n) {
+            *reinterpret_cast<floatx4_t*>(a.zs[l] + gr * MLP_W + nn0) = z;
+            *reinterpret_cast<floatx4_t*>(a.as[l] + gr * MLP_W + nn0) = g;
           }
         }
+      }
     __syncthreads();
   }
   // output layer: each wave 16 rows x 16 outputs

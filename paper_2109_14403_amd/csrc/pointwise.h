@@ -24,9 +24,16 @@ struct Pt {
   T* p;
   T* tab;
   T* tn;
-  double* state;            // [prob][nstate][nvox] (mechanics with a PA66 phase)
+  // Internal variables and increment slots of the PA66 voxels only, compacted
+  // in voxel order (a pass over them reads whole cache lines): PA66 voxel v of
+  // problem p sits at q = cbase[p][v / 64] + (PA66 voxels before v in its
+  // 64-voxel chunk)
+  double* state;            // [prob][nstate][ss] (mechanics with a PA66 phase)
   int nstate;
-  double* hist;             // [prob][HIST_SLOTS][nvox] PA66 branch history sums of the increment, last dp
+  double* hist;             // [prob][HIST_SLOTS][ss] PA66 branch history sums of the increment, last dp
+  const int* cbase;         // [prob][ceil(nvox / 64)] PA66 voxels before each chunk
+  const int* npa;           // [prob] PA66 voxels of each problem
+  long long ss;             // stride of state and hist (>= every npa)
   Ctl* ctl;
   const ProbInc* inc;
   double* part;

@@ -9,6 +9,18 @@ namespace hom {
 
 constexpr int PT_THREADS = 256;
 
+// Compact index of this lane's voxel among the PA66 voxels of its problem (pa:
+// the voxel is one). Every wave of the per-voxel kernels holds the 64 voxels of
+// one aligned chunk (v = 64 k + lane), so the index is the chunk's base plus
+// the PA66 lanes below this one; lanes past the last voxel are inactive and
+// above every active lane.
+__device__ __forceinline__ unsigned pa_index(const int* cbase, long long v, bool pa) {
+  const unsigned long long m = __ballot(pa);
+  const unsigned lane = threadIdx.x & 63;
+  const int chunk = __builtin_amdgcn_readfirstlane((int)(v >> 6));
+  return (unsigned)cbase[chunk] + (unsigned)__popcll(m & ((1ull << lane) - 1ull));
+}
+
 // ---------------------------------------------------------------------------
 // Start of an increment: x = x^n + dE (conduction: x += dG) and a fresh
 // solver state; keep_x restarts the iteration from the current x instead.
@@ -83,14 +95,16 @@ __global__ void __launch_bounds__(PT_THREADS) k_eval(Pt<T> a) {
       double sg[6];
       double ca, cb = 0.0;
       const long long to = (long long)prob * 2 * nv;
-      if (ph == in.pa_phase) {
+      const bool isp = ph == in.pa_phase;
+      const unsigned q = a.state ? pa_index(a.cbase + (long long)prob * ((nv + 63) >> 6), v, isp) : 0u;
+      if (isp) {
         double ed[6];
 #pragma unroll
         for (int c = 0; c < 6; ++c) ed[c] = (double)e[c];
-        const double* st = a.state + (long long)prob * a.nstate * nv + v;
-        double* hs = a.hist ? a.hist + (long long)prob * HIST_SLOTS * nv + v : nullptr;
+        const double* st = a.state + (long long)prob * a.nstate * a.ss;
+        double* hs = a.hist ? a.hist + (long long)prob * HIST_SLOTS * a.ss : nullptr;
         PaOut o;
-        pa66_point(in, ed, st, nv, nullptr, nullptr, o, nullptr, nullptr, hs, hs ? hs + 7 * nv : nullptr);
+        pa66_point(in, ed, st, a.ss, nullptr, nullptr, o, nullptr, nullptr, hs, hs ? hs + 7 * a.ss : nullptr, q);
 #pragma unroll
         for (int c = 0; c < 6; ++c) sg[c] = o.sig[c];
         ca = o.a;
@@ -131,19 +145,18 @@ __global__ void __launch_bounds__(PT_THREADS) k_history(Pt<T> a) {
   const int prob = blockIdx.x / a.bpp;
   const int blk = blockIdx.x % a.bpp;
   const ProbInc& in = a.inc[prob];
-  const long long nv = a.nvox;
-  const uint8_t* phase = a.phase + (long long)prob * nv;
-  const double* st = a.state + (long long)prob * a.nstate * nv;
-  double* h = a.hist + (long long)prob * HIST_SLOTS * nv;
-  for (long long vl = (long long)blk * PT_THREADS + threadIdx.x; vl < nv; vl += (long long)a.bpp * PT_THREADS) {
-    const unsigned v = (unsigned)vl;
-    if (*pa_at(phase, v) != in.pa_phase) continue;
+  // the compacted PA66 voxels in order: no phase test, whole cache lines
+  const long long ss = a.ss, ns = a.npa[prob];
+  const double* st = a.state + (long long)prob * a.nstate * ss;
+  double* h = a.hist + (long long)prob * HIST_SLOTS * ss;
+  for (long long ql = (long long)blk * PT_THREADS + threadIdx.x; ql < ns; ql += (long long)a.bpp * PT_THREADS) {
+    const unsigned q = (unsigned)ql;
     double hd[6], hs;
-    pa66_history(in, st, nv, hd, hs, v);
+    pa66_history(in, st, ss, hd, hs, q);
 #pragma unroll
-    for (int c = 0; c < 6; ++c) stnt(pa_at(h + c * nv, v), hd[c]);
-    stnt(pa_at(h + 6 * nv, v), hs);
-    stnt(pa_at(h + 7 * nv, v), -1.0);  // no plastic increment known yet
+    for (int c = 0; c < 6; ++c) stnt(pa_at(h + c * ss, q), hd[c]);
+    stnt(pa_at(h + 6 * ss, q), hs);
+    stnt(pa_at(h + 7 * ss, q), -1.0);  // no plastic increment known yet
   }
 }
 
@@ -179,14 +192,16 @@ __global__ void __launch_bounds__(PT_THREADS) k_commit(Pt<T> a) {
         en[c] = (double)a.xn[fo + c * nv + v];
       }
       double sg[6], dis = 0.0, cpl;
-      if (ph == in.pa_phase) {
-        double* st = a.state + (long long)prob * a.nstate * nv + v;
+      const bool isp = ph == in.pa_phase;
+      const unsigned q = a.state ? pa_index(a.cbase + (long long)prob * ((nv + 63) >> 6), v, isp) : 0u;
+      if (isp) {
+        double* st = a.state + (long long)prob * a.nstate * a.ss;
         // the branch history sums of this increment are in hist (the state
         // has not changed since they were formed): one pass over the branches
-        const double* hs = a.hist ? a.hist + (long long)prob * HIST_SLOTS * nv + v : nullptr;
-        double* dps = a.hist ? a.hist + (long long)prob * HIST_SLOTS * nv + v + 7 * nv : nullptr;
+        const double* hs = a.hist ? a.hist + (long long)prob * HIST_SLOTS * a.ss : nullptr;
+        double* dps = a.hist ? a.hist + (long long)prob * HIST_SLOTS * a.ss + 7 * a.ss : nullptr;
         PaOut o;
-        pa66_point(in, e, st, nv, commit ? st : nullptr, en, o, &dis, &cpl, hs, dps);
+        pa66_point(in, e, st, a.ss, commit ? st : nullptr, en, o, &dis, &cpl, hs, dps, q);
 #pragma unroll
         for (int c = 0; c < 6; ++c) sg[c] = o.sig[c];
       } else {
@@ -264,8 +279,10 @@ __global__ void __launch_bounds__(PT_THREADS) k_commit_vox(Pt<T> a) {
   T* xnb = a.xn + fo;
   T* fb = a.f + fo;
   T* dxb = a.dx ? a.dx + fo : nullptr;
-  double* st = a.state + (long long)prob * a.nstate * nv;
-  const double* hs = a.hist + (long long)prob * HIST_SLOTS * nv;
+  double* st = a.state + (long long)prob * a.nstate * a.ss;
+  const double* hs = a.hist + (long long)prob * HIST_SLOTS * a.ss;
+  const long long ss = a.ss;
+  const int* cbase = a.cbase + (long long)prob * ((nv + 63) >> 6);
   double* pvd = commit && a.pv_diss ? a.pv_diss + (long long)prob * nv : nullptr;
   double* pvc = commit && a.pv_coup ? a.pv_coup + (long long)prob * nv : nullptr;
   double acc[MECH_SUMS];
@@ -283,22 +300,24 @@ __global__ void __launch_bounds__(PT_THREADS) k_commit_vox(Pt<T> a) {
     }
     double sg[6], dis = 0.0, cpl;
     const double trd = (e[0] - en[0]) + (e[1] - en[1]) + (e[2] - en[2]);
-    if (ph == in.pa_phase) {
+    const bool isp = ph == in.pa_phase;
+    const unsigned q = pa_index(cbase, vl, isp);
+    if (isp) {
       PaOut o;
       PaPre p;
-      pa66_return_at(in, e, st, nv, hs, ldnt(pa_at(hs + 7 * nv, v)), o, p, v);
+      pa66_return_at(in, e, st, ss, hs, ldnt(pa_at(hs + 7 * ss, q)), o, p, q);
       const double k15 = 1.2247448713915890 * o.dp;
       double dn[6];
 #pragma unroll
       for (int c = 0; c < 6; ++c) {
         const double evp1 = p.evp[c] + k15 * o.nd[c];
         dn[c] = p.d[c] - evp1;
-        if (commit) *pa_at(st + (1 + c) * nv, v) = evp1;
+        if (commit) *pa_at(st + (1 + c) * ss, q) = evp1;
       }
       const double ep1 = p.ep + o.dp;
-      if (commit) *pa_at(st, v) = ep1;
+      if (commit) *pa_at(st, q) = ep1;
       double wsum, ksum;
-      pa66_branches(in, st, nv, commit ? st : nullptr, dn, p.em, wsum, ksum, v);
+      pa66_branches(in, st, ss, commit ? st : nullptr, dn, p.em, wsum, ksum, q);
       const double Hn = ep1 > 0.0 ? in.hk * powpos(ep1, in.nh) : 0.0;
       dis = (in.sY * o.dp + wsum) / in.dt;
       cpl = -in.theta * (in.alpha0 * (k3 * trd - 3.0 * ksum) + in.beta1 * Hn * o.dp) / in.dt + dis;
@@ -457,9 +476,11 @@ __global__ void __launch_bounds__(PT_THREADS) k_partials(Pt<T> a) {
       en[c] = (double)a.xn[fo + c * nv + v];
     }
     double st_[6], gd[6], hd;
-    if (ph == in.pa_phase) {
-      const double* st = a.state + (long long)prob * a.nstate * nv + v;
-      const double* hs = a.hist ? a.hist + (long long)prob * HIST_SLOTS * nv + v : nullptr;
+    const bool isp = ph == in.pa_phase;
+    const unsigned q = a.state ? pa_index(a.cbase + (long long)prob * ((nv + 63) >> 6), v, isp) : 0u;
+    if (isp) {
+      const double* st = a.state + (long long)prob * a.nstate * a.ss;
+      const double* hs = a.hist ? a.hist + (long long)prob * HIST_SLOTS * a.ss : nullptr;
       double sp[6], Dp = 0.0;
       for (int k = 0; k < 14; ++k) {
         const bool th = k < 2;
@@ -471,7 +492,7 @@ __global__ void __launch_bounds__(PT_THREADS) k_partials(Pt<T> a) {
         if (!th) ek[dir] += (k & 1) ? -FD_H_EPS : FD_H_EPS;
         PaOut o;
         double dis, cpl;
-        pa66_point(ik, ek, st, nv, nullptr, en, o, &dis, &cpl, th ? nullptr : hs, nullptr);
+        pa66_point(ik, ek, st, a.ss, nullptr, en, o, &dis, &cpl, th ? nullptr : hs, nullptr, q);
         if (!(k & 1)) {  // + side: keep it for the difference with the - side
 #pragma unroll
           for (int c = 0; c < 6; ++c) sp[c] = o.sig[c];

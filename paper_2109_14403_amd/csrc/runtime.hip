@@ -267,6 +267,13 @@ struct Group {
   int txy[2] = {4, 4}, txz[2] = {4, 4};  // [mech, thermal]
   int pt_bpp = 1;
   int cm_bpp = 1;  // blocks per problem of the once-per-increment history sums
+  // internal variables and increment slots of the PA66 voxels only, compacted
+  // in voxel order: stride ss (the most PA66 voxels of one problem), the PA66
+  // voxels before every 64-voxel chunk and the count of every problem
+  long long ss = 0;
+  int* cbase = nullptr;
+  int* npa_d = nullptr;
+  std::vector<int> npa;
   int xfblocks = 1, xiblocks = 1;  // x-forward / x-inverse work-groups per problem
   // captured chunks: [0] mechanics, [1] conduction, [2] linearized mechanics
   // (tangent strain columns), [3] linearized mechanics with a source (tangent
@@ -340,8 +347,11 @@ struct Group {
     spec_count = (size_t)nprob * nz * ny * std::max(ps[0] * 6, ps[1] * 3);
     spec = dalloc<c2<T>>(spec_count);
     if (with_state && nstate > 0) {
-      state = dalloc<double>((size_t)nstate * nm);
-      hist = dalloc<double>((size_t)HIST_SLOTS * nm);
+      const size_t ns = (size_t)nprob * std::max<long long>(ss, 1);
+      state = dalloc<double>((size_t)nstate * ns);
+      hist = dalloc<double>((size_t)HIST_SLOTS * ns);
+      cbase = dalloc<int>((size_t)nprob * ((nvox + 63) / 64));
+      npa_d = dalloc<int>(nprob);
     }
     ctl_m = dalloc<Ctl>(nprob);
     ctl_t = dalloc<Ctl>(nprob);
@@ -352,10 +362,9 @@ struct Group {
     // blocks per problem of the pointwise kernels
     pt_bpp = (int)std::min<long long>((nvox + 255) / 256, std::max<long long>(1, 8192 / nprob));
     pt_bpp = std::max(pt_bpp, 1);
-    // the history sums stream the branch strains once per increment and write
-    // no partial sums: one voxel per thread (many short work-groups) up to
-    // 65536 groups. The commit keeps pt_bpp: its partial sums are reduced by
-    // one work-group per problem, which grows with the number of groups.
+    // the history sums stream the branch strains of the compacted PA66 voxels
+    // once per increment and write no partial sums: one voxel per thread
+    // (many short work-groups) up to 65536 groups.
     cm_bpp = (int)std::min<long long>((nvox + 255) / 256, std::max<long long>(1, 65536 / nprob));
     cm_bpp = std::max(cm_bpp, pt_bpp);
     const int nlf = x_lines(nx, sizeof(T) == 8, true), nli = x_lines(nx, sizeof(T) == 8, false);
@@ -437,6 +446,9 @@ struct Group {
     a.state = state;
     a.nstate = nstate;
     a.hist = hist;
+    a.cbase = cbase;
+    a.npa = npa_d;
+    a.ss = ss;
     a.ctl = phys == 0 ? ctl_m : ctl_t;
     a.inc = inc_d;
     a.part = part;
@@ -554,14 +566,19 @@ class BatchT : public BatchImpl {
       lane_streams.push_back(G.stream);
     }
     const int nst = pa66_nstate(laws);
+    int pa = -1;  // phase id of the PA66 law
+    for (size_t l = 0; l < laws.size(); ++l)
+      if (laws[l].kind == HOM_LAW_PA66) pa = (int)l;
     for (auto& gp : groups) {
       auto& G = *gp;
       G.nprob = (int)G.members.size();
       G.nstate = nst;
-      G.alloc(nst > 0, opts.tangent != 0, opts.predictor != 0);
-      std::vector<uint8_t> buf((size_t)G.nprob * G.nx * G.ny * G.nz);
-      G.c0mean.assign(G.nprob, 0.0);
       const long long nv = (long long)G.nx * G.ny * G.nz;
+      std::vector<uint8_t> buf((size_t)G.nprob * nv);
+      const long long nch = (nv + 63) / 64;
+      std::vector<int> cbase(nst > 0 ? (size_t)G.nprob * nch : 0);
+      G.c0mean.assign(G.nprob, 0.0);
+      G.npa.assign(G.nprob, 0);
       for (int j = 0; j < G.nprob; ++j) {
         const uint8_t* src = phases[G.members[j]];
         if (!src) fail(HOM_E_ARG, "null phase array");
@@ -575,8 +592,22 @@ class BatchT : public BatchImpl {
         for (size_t l = 0; l < laws.size(); ++l) c0 += laws[l].c0 * (double)cnt[l] / (double)nv;
         G.c0mean[j] = c0;
         std::memcpy(buf.data() + (size_t)j * nv, src, nv);
+        if (nst > 0) {
+          int q = 0;
+          for (long long v = 0; v < nv; ++v) {
+            if ((v & 63) == 0) cbase[(size_t)j * nch + (v >> 6)] = q;
+            if ((int)src[v] == pa) ++q;
+          }
+          G.npa[j] = q;
+          G.ss = std::max<long long>(G.ss, q);
+        }
       }
+      G.alloc(nst > 0, opts.tangent != 0, opts.predictor != 0);
       HIPCHK(hipMemcpy(G.phase, buf.data(), buf.size(), hipMemcpyHostToDevice));
+      if (G.state) {
+        HIPCHK(hipMemcpy(G.cbase, cbase.data(), cbase.size() * sizeof(int), hipMemcpyHostToDevice));
+        HIPCHK(hipMemcpy(G.npa_d, G.npa.data(), G.nprob * sizeof(int), hipMemcpyHostToDevice));
+      }
       if (opts.autotune) autotune(G);
     }
     HIPCHK(hipDeviceSynchronize());
@@ -1162,7 +1193,8 @@ class BatchT : public BatchImpl {
     for (auto& gp : groups) {
       const auto& G = *gp;
       const size_t nm = (size_t)G.nprob * G.nvox;
-      s += nm * 9 * sizeof(T) + (G.state ? nm * G.nstate * sizeof(double) : 0) + G.nprob * 9 * sizeof(double);
+      const size_t ns = (size_t)G.nprob * std::max<long long>(G.ss, 1);
+      s += nm * 9 * sizeof(T) + (G.state ? ns * G.nstate * sizeof(double) : 0) + G.nprob * 9 * sizeof(double);
     }
     return s;
   }
@@ -1180,8 +1212,9 @@ class BatchT : public BatchImpl {
       HIPCHK(hipMemcpy(p, G.xt, nm * 3 * sizeof(T), hipMemcpyDeviceToHost));
       p += nm * 3 * sizeof(T);
       if (G.state) {
-        HIPCHK(hipMemcpy(p, G.state, nm * G.nstate * sizeof(double), hipMemcpyDeviceToHost));
-        p += nm * G.nstate * sizeof(double);
+        const size_t ns = (size_t)G.nprob * std::max<long long>(G.ss, 1);
+        HIPCHK(hipMemcpy(p, G.state, ns * G.nstate * sizeof(double), hipMemcpyDeviceToHost));
+        p += ns * G.nstate * sizeof(double);
       }
       for (int j = 0; j < G.nprob; ++j) {
         std::memcpy(p, G.En[j].data(), 6 * sizeof(double));
@@ -1211,8 +1244,9 @@ class BatchT : public BatchImpl {
       HIPCHK(hipMemcpy(G.xt, p, nm * 3 * sizeof(T), hipMemcpyHostToDevice));
       p += nm * 3 * sizeof(T);
       if (G.state) {
-        HIPCHK(hipMemcpy(G.state, p, nm * G.nstate * sizeof(double), hipMemcpyHostToDevice));
-        p += nm * G.nstate * sizeof(double);
+        const size_t ns = (size_t)G.nprob * std::max<long long>(G.ss, 1);
+        HIPCHK(hipMemcpy(G.state, p, ns * G.nstate * sizeof(double), hipMemcpyHostToDevice));
+        p += ns * G.nstate * sizeof(double);
       }
       for (int j = 0; j < G.nprob; ++j) {
         std::memcpy(G.En[j].data(), p, 6 * sizeof(double));
@@ -1244,7 +1278,22 @@ class BatchT : public BatchImpl {
     if (count != nv * nc) fail(HOM_E_ARG, "field buffer size mismatch: need " + std::to_string(nv * nc));
     HIPCHK(hipStreamSynchronize(stream));
     if (dbl) {
-      HIPCHK(hipMemcpy(out, src, count * sizeof(double), hipMemcpyDeviceToHost));
+      // internal variables: the compacted PA66 voxels scattered to voxel
+      // arrays, zero in the other phases
+      const size_t ss = (size_t)G.ss;
+      std::vector<double> cmp((size_t)nc * ss);
+      std::vector<uint8_t> ph(nv);
+      HIPCHK(hipMemcpy(cmp.data(), src, cmp.size() * sizeof(double), hipMemcpyDeviceToHost));
+      HIPCHK(hipMemcpy(ph.data(), G.phase, nv, hipMemcpyDeviceToHost));
+      int pa = -1;
+      for (size_t l = 0; l < laws.size(); ++l)
+        if (laws[l].kind == HOM_LAW_PA66) pa = (int)l;
+      size_t q = 0;
+      for (size_t v = 0; v < nv; ++v) {
+        const bool isp = (int)ph[v] == pa;
+        for (int k = 0; k < nc; ++k) out[k * nv + v] = isp ? cmp[k * ss + q] : 0.0;
+        if (isp) ++q;
+      }
     } else {
       std::vector<T> tmp(count);
       HIPCHK(hipMemcpy(tmp.data(), src, count * sizeof(T), hipMemcpyDeviceToHost));
@@ -1365,9 +1414,17 @@ void eval_law(const hom_law& law, int64_t count, const double* eps, const double
   G.f = G.dalloc<double>(6 * count);
   G.tab = G.dalloc<double>(2 * count);
   G.tn = G.dalloc<double>(6 * count);
-  if (G.nstate) {
+  if (G.nstate) {  // every point is a PA66 point: the compact index is the point's
     G.state = G.dalloc<double>(G.nstate * count);
     G.hist = G.dalloc<double>(HIST_SLOTS * count);
+    G.ss = count;
+    G.npa.assign(1, (int)count);
+    std::vector<int> cb((size_t)(count + 63) / 64);
+    for (size_t k = 0; k < cb.size(); ++k) cb[k] = (int)(64 * k);
+    G.cbase = G.dalloc<int>(cb.size());
+    G.npa_d = G.dalloc<int>(1);
+    HIPCHK(hipMemcpy(G.cbase, cb.data(), cb.size() * sizeof(int), hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpy(G.npa_d, G.npa.data(), sizeof(int), hipMemcpyHostToDevice));
   }
   G.ctl_m = G.dalloc<Ctl>(1);
   G.inc_d = G.dalloc<ProbInc>(1);
