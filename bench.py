@@ -237,13 +237,15 @@ def batch_bench(nprob=512, steps=5, seed=4, predictor=0):
         failed += sum(1 for r in res if r["status"] != 0)
     torch.cuda.synchronize()
     el = time.perf_counter() - t0
+    sched = b.schedules()
     b.close()
     sizes = {}
     for w in wls:
         sizes[w.record["n"]] = sizes.get(w.record["n"], 0) + 1
     return {"problems": nprob, "increments": steps, "sizes": {str(k): v for k, v in sorted(sizes.items())},
             "seconds": round(el, 3), "gauss_point_updates_per_s": round(nprob * steps / el, 1),
-            "voxel_iters_per_s": round(float((pipes * nvox).sum()) / el, 1), "failed": failed}
+            "voxel_iters_per_s": round(float((pipes * nvox).sum()) / el, 1), "failed": failed,
+            "schedules": sched}
 
 
 def _hist_args(h, sl=slice(None)):
@@ -971,6 +973,7 @@ def main():
     if not args.no_tangent:
         tangent = tangent_bench(ctx, wl, nvox, args.warmup, total)
         print(f"tangent: {tangent}", file=sys.stderr, flush=True)
+    schedules = ctx.schedules()
     ctx.close()
     if tangent is not None:
         tangent.update(tangent_full_bench(wl, nvox, args.warmup))
@@ -1014,7 +1017,7 @@ def main():
         "thermal_voxel_iters_per_s": round(tpipes * nvox / elapsed, 1),
         "newton_per_step": newton / args.steps, "krylov_per_step": krylov / args.steps,
         "roofline": roof, "copy_probe_gbs": copy_gbs, "cpu_baseline": cpu, "batch": batch, "surrogate": surr,
-        "tangent": tangent, "dmn": dmn_line, "predictor": pred,
+        "tangent": tangent, "dmn": dmn_line, "predictor": pred, "schedules": schedules,
     }
     if kstats:
         line["kernel_ms"] = {k: [v[0], round(v[1], 3)] for k, v in kstats.items() if v[0]}

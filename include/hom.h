@@ -278,6 +278,15 @@ int hom_batch_solve_increment(hom_batch* b, const double* strain, const hom_macr
 /* hom_solve_load for every problem of a batch; loads, out: n_prob entries. */
 int hom_batch_solve_load(hom_batch* b, const hom_load* loads, hom_result* out);
 int hom_batch_kernel_stats(const hom_batch* b, const char** names, int64_t* launches, double* ms, int32_t cap);
+/* Schedules the autotuner chose (project-written, autotune = 1): per group of
+ * problems with one grid, 7 values: nx, ny, nz, then the schedule of the y
+ * pass and of the z pass of the mechanics, then of the conduction, each a
+ * tile width (kx columns per work-group: 2, 4 or 8) + 16 x FFT plan variant
+ * (0 or 1). Writes at most cap groups into out (7 cap values); returns the
+ * number of groups, or a negative error code. hom_schedules: the same for a
+ * single-problem context. */
+int hom_batch_schedules(const hom_batch* b, int32_t* out, int32_t cap);
+int hom_schedules(const hom_ctx* ctx, int32_t* out, int32_t cap);
 /* hom_algorithmic_tangent for every problem of a batch; out: n_prob entries. */
 int hom_batch_algorithmic_tangent(hom_batch* b, int32_t what, hom_tangent* out);
 const char* hom_batch_last_error(const hom_batch* b);
@@ -578,6 +587,13 @@ void hom_dmn_online_destroy(hom_dmn_online* o);
  * HOM_FP64 / HOM_FP32. */
 int hom_apply_operator(const hom_grid* grid, int32_t ncomp, int32_t op, double p0, double p1,
                        int32_t precision, const double* in, double* out);
+/* The same with a given schedule of the y and z passes: tile width (kx
+ * columns per work-group, 2, 4 or 8) + 16 x FFT plan variant (0 or 1; the
+ * solver's autotuner picks among these). hom_apply_operator uses width 4,
+ * plan 0. HOM_E_ARG for other values; HOM_E_UNSUPPORTED if the schedule does
+ * not fit the work-group limits on this grid. */
+int hom_apply_operator_schedule(const hom_grid* grid, int32_t ncomp, int32_t op, double p0, double p1,
+                                int32_t precision, int32_t schedule, const double* in, double* out);
 
 /* hom_eval_law: evaluate the law of phase 0 of `law` on count points with
  * strains eps (6 x count Mandel, host FP64), previous strains eps_n, and (PA66)

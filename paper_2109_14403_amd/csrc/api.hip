@@ -261,6 +261,16 @@ int hom_batch_kernel_stats(const hom_batch* b, const char** names, int64_t* laun
   return stats(b ? b->impl.get() : nullptr, names, launches, ms, cap);
 }
 
+int hom_batch_schedules(const hom_batch* b, int32_t* out, int32_t cap) {
+  if (!b || !b->impl || !out || cap < 0) return HOM_E_ARG;
+  return b->impl->schedules(out, cap);
+}
+
+int hom_schedules(const hom_ctx* c, int32_t* out, int32_t cap) {
+  if (!c || !c->impl || !out || cap < 0) return HOM_E_ARG;
+  return c->impl->schedules(out, cap);
+}
+
 int hom_batch_algorithmic_tangent(hom_batch* b, int32_t what, hom_tangent* out) {
   if (!b || !b->impl || !out) return HOM_E_ARG;
   return guarded(&b->err, [&] { b->impl->tangent(what, out); });
@@ -630,6 +640,13 @@ int hom_apply_operator(const hom_grid* grid, int32_t ncomp, int32_t op, double p
                        const double* in, double* out) {
   if (!grid || !in || !out) return HOM_E_ARG;
   return guarded(&g_setup_error, [&] { hom::apply_operator(*grid, ncomp, op, p0, p1, precision, in, out); });
+}
+
+int hom_apply_operator_schedule(const hom_grid* grid, int32_t ncomp, int32_t op, double p0, double p1,
+                                int32_t precision, int32_t schedule, const double* in, double* out) {
+  if (!grid || !in || !out) return HOM_E_ARG;
+  return guarded(&g_setup_error,
+                 [&] { hom::apply_operator(*grid, ncomp, op, p0, p1, precision, in, out, schedule); });
 }
 
 int hom_eval_law(const hom_law* law, int64_t count, const double* eps, const double* eps_n, const double* state,

@@ -226,13 +226,17 @@ __device__ __forceinline__ void stockham_pass(c2<T>* a, int t, const c2<T>* __re
 
 // Plans: per-thread element count M (threads per line G = N / M) and the
 // sequence of radix passes.
-template <int N>
+// Plan<N, V>: elements per thread M and the radix passes of a length-N line
+// transform. V = 0 is the plan of every pass; the y and z passes also have
+// plan V = 1 (another register / pass trade-off), and the autotuner times
+// both on the problem's own data.
+template <int N, int V = 0>
 struct Plan;
 
 #define HOM_PASS(Nv, Mv, R, NS, LAST) stockham_pass<Nv, Mv, R, NS, LAST, T>(a, t, tw, buf, L, l, active)
 
 template <>
-struct Plan<16> {
+struct Plan<16, 0> {
   static constexpr int M = 4;
   template <typename T>
   static __device__ __forceinline__ void run(c2<T>* a, int t, const c2<T>* tw, c2<T>* buf, int L, int l,
@@ -242,7 +246,7 @@ struct Plan<16> {
   }
 };
 template <>
-struct Plan<24> {
+struct Plan<24, 0> {
   static constexpr int M = 12;
   template <typename T>
   static __device__ __forceinline__ void run(c2<T>* a, int t, const c2<T>* tw, c2<T>* buf, int L, int l,
@@ -252,7 +256,7 @@ struct Plan<24> {
   }
 };
 template <>
-struct Plan<32> {
+struct Plan<32, 0> {
   static constexpr int M = 8;
   template <typename T>
   static __device__ __forceinline__ void run(c2<T>* a, int t, const c2<T>* tw, c2<T>* buf, int L, int l,
@@ -262,7 +266,7 @@ struct Plan<32> {
   }
 };
 template <>
-struct Plan<48> {
+struct Plan<48, 0> {
   static constexpr int M = 12;
   template <typename T>
   static __device__ __forceinline__ void run(c2<T>* a, int t, const c2<T>* tw, c2<T>* buf, int L, int l,
@@ -272,7 +276,7 @@ struct Plan<48> {
   }
 };
 template <>
-struct Plan<64> {
+struct Plan<64, 0> {
   static constexpr int M = 8;
   template <typename T>
   static __device__ __forceinline__ void run(c2<T>* a, int t, const c2<T>* tw, c2<T>* buf, int L, int l,
@@ -282,7 +286,7 @@ struct Plan<64> {
   }
 };
 template <>
-struct Plan<96> {
+struct Plan<96, 0> {
   static constexpr int M = 24;
   template <typename T>
   static __device__ __forceinline__ void run(c2<T>* a, int t, const c2<T>* tw, c2<T>* buf, int L, int l,
@@ -292,7 +296,7 @@ struct Plan<96> {
   }
 };
 template <>
-struct Plan<128> {
+struct Plan<128, 0> {
   static constexpr int M = 16;
   template <typename T>
   static __device__ __forceinline__ void run(c2<T>* a, int t, const c2<T>* tw, c2<T>* buf, int L, int l,
@@ -302,13 +306,97 @@ struct Plan<128> {
   }
 };
 template <>
-struct Plan<256> {
+struct Plan<256, 0> {
   static constexpr int M = 16;
   template <typename T>
   static __device__ __forceinline__ void run(c2<T>* a, int t, const c2<T>* tw, c2<T>* buf, int L, int l,
                                              bool active) {
     HOM_PASS(256, 16, 16, 1, false);
     HOM_PASS(256, 16, 16, 16, true);
+  }
+};
+// the alternative plans (V = 1)
+template <>
+struct Plan<16, 1> {
+  static constexpr int M = 8;
+  template <typename T>
+  static __device__ __forceinline__ void run(c2<T>* a, int t, const c2<T>* tw, c2<T>* buf, int L, int l,
+                                             bool active) {
+    HOM_PASS(16, 8, 8, 1, false);
+    HOM_PASS(16, 8, 2, 8, true);
+  }
+};
+template <>
+struct Plan<24, 1> {
+  static constexpr int M = 12;
+  template <typename T>
+  static __device__ __forceinline__ void run(c2<T>* a, int t, const c2<T>* tw, c2<T>* buf, int L, int l,
+                                             bool active) {
+    HOM_PASS(24, 12, 4, 1, false);
+    HOM_PASS(24, 12, 6, 4, true);
+  }
+};
+template <>
+struct Plan<32, 1> {
+  static constexpr int M = 16;
+  template <typename T>
+  static __device__ __forceinline__ void run(c2<T>* a, int t, const c2<T>* tw, c2<T>* buf, int L, int l,
+                                             bool active) {
+    HOM_PASS(32, 16, 16, 1, false);
+    HOM_PASS(32, 16, 2, 16, true);
+  }
+};
+template <>
+struct Plan<48, 1> {
+  static constexpr int M = 12;
+  template <typename T>
+  static __device__ __forceinline__ void run(c2<T>* a, int t, const c2<T>* tw, c2<T>* buf, int L, int l,
+                                             bool active) {
+    HOM_PASS(48, 12, 4, 1, false);
+    HOM_PASS(48, 12, 12, 4, true);
+  }
+};
+template <>
+struct Plan<64, 1> {
+  static constexpr int M = 16;
+  template <typename T>
+  static __device__ __forceinline__ void run(c2<T>* a, int t, const c2<T>* tw, c2<T>* buf, int L, int l,
+                                             bool active) {
+    HOM_PASS(64, 16, 16, 1, false);
+    HOM_PASS(64, 16, 4, 16, true);
+  }
+};
+template <>
+struct Plan<96, 1> {
+  static constexpr int M = 12;
+  template <typename T>
+  static __device__ __forceinline__ void run(c2<T>* a, int t, const c2<T>* tw, c2<T>* buf, int L, int l,
+                                             bool active) {
+    HOM_PASS(96, 12, 12, 1, false);
+    HOM_PASS(96, 12, 4, 12, false);
+    HOM_PASS(96, 12, 2, 48, true);
+  }
+};
+template <>
+struct Plan<128, 1> {
+  static constexpr int M = 8;
+  template <typename T>
+  static __device__ __forceinline__ void run(c2<T>* a, int t, const c2<T>* tw, c2<T>* buf, int L, int l,
+                                             bool active) {
+    HOM_PASS(128, 8, 8, 1, false);
+    HOM_PASS(128, 8, 8, 8, false);
+    HOM_PASS(128, 8, 2, 64, true);
+  }
+};
+template <>
+struct Plan<256, 1> {
+  static constexpr int M = 8;
+  template <typename T>
+  static __device__ __forceinline__ void run(c2<T>* a, int t, const c2<T>* tw, c2<T>* buf, int L, int l,
+                                             bool active) {
+    HOM_PASS(256, 8, 8, 1, false);
+    HOM_PASS(256, 8, 8, 8, false);
+    HOM_PASS(256, 8, 4, 64, true);
   }
 };
 #undef HOM_PASS

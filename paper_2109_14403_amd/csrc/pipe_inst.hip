@@ -55,9 +55,9 @@ LaunchInfo xinv_c(const Pipe<T>& a, hipStream_t s, bool dry) {
   return li;
 }
 
-template <typename T, int C, int N, int TX>
+template <typename T, int C, int N, int TX, int V>
 LaunchInfo ypass_c(const Pipe<T>& a, int inverse, hipStream_t s, bool dry) {
-  constexpr int G = N / Plan<N>::M;
+  constexpr int G = N / Plan<N, V>::M;
   LaunchInfo li;
   li.threads = G * TX * C;
   li.blocks = a.nprob * a.nz * ((a.P + TX - 1) / TX);
@@ -65,21 +65,21 @@ LaunchInfo ypass_c(const Pipe<T>& a, int inverse, hipStream_t s, bool dry) {
   {
     static bool attr = false;
     if (!attr && li.lds > 65536) {
-      hipFuncSetAttribute(reinterpret_cast<const void*>(&k_ypass<T, C, N, TX>),
+      hipFuncSetAttribute(reinterpret_cast<const void*>(&k_ypass<T, C, N, TX, V>),
                           hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
       (void)hipGetLastError();
       attr = true;
     }
   }
   if (!dry) {
-    hipLaunchKernelGGL((k_ypass<T, C, N, TX>), dim3(li.blocks), dim3(li.threads), li.lds, s, a, inverse);
+    hipLaunchKernelGGL((k_ypass<T, C, N, TX, V>), dim3(li.blocks), dim3(li.threads), li.lds, s, a, inverse);
   }
   return li;
 }
 
-template <typename T, int C, int N, int TX>
+template <typename T, int C, int N, int TX, int V>
 LaunchInfo zgreen_c(const Pipe<T>& a, hipStream_t s, bool dry) {
-  constexpr int G = N / Plan<N>::M;
+  constexpr int G = N / Plan<N, V>::M;
   LaunchInfo li;
   li.threads = G * TX * C;
   li.blocks = a.nprob * a.ny * ((a.P + TX - 1) / TX);
@@ -87,16 +87,30 @@ LaunchInfo zgreen_c(const Pipe<T>& a, hipStream_t s, bool dry) {
   {
     static bool attr = false;
     if (!attr && li.lds > 65536) {
-      hipFuncSetAttribute(reinterpret_cast<const void*>(&k_zgreen<T, C, N, TX>),
+      hipFuncSetAttribute(reinterpret_cast<const void*>(&k_zgreen<T, C, N, TX, V>),
                           hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
       (void)hipGetLastError();
       attr = true;
     }
   }
   if (!dry) {
-    hipLaunchKernelGGL((k_zgreen<T, C, N, TX>), dim3(li.blocks), dim3(li.threads), li.lds, s, a);
+    hipLaunchKernelGGL((k_zgreen<T, C, N, TX, V>), dim3(li.blocks), dim3(li.threads), li.lds, s, a);
   }
   return li;
+}
+
+// schedule code -> tile width and plan variant
+template <typename T, int C, int N, int V>
+LaunchInfo ypass_v(const Pipe<T>& a, int tx, int inverse, hipStream_t s, bool dry) {
+  if (tx == 2) return ypass_c<T, C, N, 2, V>(a, inverse, s, dry);
+  if (tx == 8) return ypass_c<T, C, N, 8, V>(a, inverse, s, dry);
+  return ypass_c<T, C, N, 4, V>(a, inverse, s, dry);
+}
+template <typename T, int C, int N, int V>
+LaunchInfo zgreen_v(const Pipe<T>& a, int tx, hipStream_t s, bool dry) {
+  if (tx == 2) return zgreen_c<T, C, N, 2, V>(a, s, dry);
+  if (tx == 8) return zgreen_c<T, C, N, 8, V>(a, s, dry);
+  return zgreen_c<T, C, N, 4, V>(a, s, dry);
 }
 
 }  // namespace
@@ -115,27 +129,19 @@ LaunchInfo xinv_launch(const Pipe<T>& a, hipStream_t s, bool dry) {
 }
 
 template <typename T, int N>
-LaunchInfo ypass_launch(const Pipe<T>& a, int tx, int inverse, hipStream_t s, bool dry) {
-  if (a.C == 6) {
-    if (tx == 2) return ypass_c<T, 6, N, 2>(a, inverse, s, dry);
-    if (tx == 8) return ypass_c<T, 6, N, 8>(a, inverse, s, dry);
-    return ypass_c<T, 6, N, 4>(a, inverse, s, dry);
-  }
-  if (tx == 2) return ypass_c<T, 3, N, 2>(a, inverse, s, dry);
-  if (tx == 8) return ypass_c<T, 3, N, 8>(a, inverse, s, dry);
-  return ypass_c<T, 3, N, 4>(a, inverse, s, dry);
+LaunchInfo ypass_launch(const Pipe<T>& a, int sched, int inverse, hipStream_t s, bool dry) {
+  const int tx = schedule_tile(sched);
+  if (schedule_plan(sched) == 1)
+    return a.C == 6 ? ypass_v<T, 6, N, 1>(a, tx, inverse, s, dry) : ypass_v<T, 3, N, 1>(a, tx, inverse, s, dry);
+  return a.C == 6 ? ypass_v<T, 6, N, 0>(a, tx, inverse, s, dry) : ypass_v<T, 3, N, 0>(a, tx, inverse, s, dry);
 }
 
 template <typename T, int N>
-LaunchInfo zgreen_launch(const Pipe<T>& a, int tx, hipStream_t s, bool dry) {
-  if (a.C == 6) {
-    if (tx == 2) return zgreen_c<T, 6, N, 2>(a, s, dry);
-    if (tx == 8) return zgreen_c<T, 6, N, 8>(a, s, dry);
-    return zgreen_c<T, 6, N, 4>(a, s, dry);
-  }
-  if (tx == 2) return zgreen_c<T, 3, N, 2>(a, s, dry);
-  if (tx == 8) return zgreen_c<T, 3, N, 8>(a, s, dry);
-  return zgreen_c<T, 3, N, 4>(a, s, dry);
+LaunchInfo zgreen_launch(const Pipe<T>& a, int sched, hipStream_t s, bool dry) {
+  const int tx = schedule_tile(sched);
+  if (schedule_plan(sched) == 1)
+    return a.C == 6 ? zgreen_v<T, 6, N, 1>(a, tx, s, dry) : zgreen_v<T, 3, N, 1>(a, tx, s, dry);
+  return a.C == 6 ? zgreen_v<T, 6, N, 0>(a, tx, s, dry) : zgreen_v<T, 3, N, 0>(a, tx, s, dry);
 }
 
 #define HOM_INST(T)                                                                         \

@@ -40,7 +40,14 @@ constexpr int x_lines(int n, bool fp64, bool fwd) {
   return nl < 1 ? 1 : nl;
 }
 
-constexpr int kTileChoices[] = {2, 4, 8};
+// Schedules of the y and z passes: tile width (kx columns per work-group: 2,
+// 4 or 8) and FFT plan variant (0 or 1, Plan<N, V>), packed as width + 16 V.
+// The autotuner times every one on the problem's own data.
+constexpr int schedule(int tile, int plan) { return tile + 16 * plan; }
+constexpr int schedule_tile(int s) { return s & 15; }
+constexpr int schedule_plan(int s) { return s >> 4; }
+constexpr int kScheduleChoices[] = {schedule(2, 0), schedule(4, 0), schedule(8, 0),
+                                    schedule(2, 1), schedule(4, 1), schedule(8, 1)};
 
 struct LaunchInfo {
   int blocks;
@@ -53,17 +60,17 @@ LaunchInfo xfwd_launch(const Pipe<T>& a, hipStream_t s, bool dry);
 template <typename T, int N>
 LaunchInfo xinv_launch(const Pipe<T>& a, hipStream_t s, bool dry);
 template <typename T, int N>
-LaunchInfo ypass_launch(const Pipe<T>& a, int tx, int inverse, hipStream_t s, bool dry);
+LaunchInfo ypass_launch(const Pipe<T>& a, int sched, int inverse, hipStream_t s, bool dry);
 template <typename T, int N>
-LaunchInfo zgreen_launch(const Pipe<T>& a, int tx, hipStream_t s, bool dry);
+LaunchInfo zgreen_launch(const Pipe<T>& a, int sched, hipStream_t s, bool dry);
 
 template <typename T>
 LaunchInfo run_xfwd(const Pipe<T>& a, hipStream_t s, bool dry = false);
 template <typename T>
 LaunchInfo run_xinv(const Pipe<T>& a, hipStream_t s, bool dry = false);
 template <typename T>
-LaunchInfo run_ypass(const Pipe<T>& a, int tx, int inverse, hipStream_t s, bool dry = false);
+LaunchInfo run_ypass(const Pipe<T>& a, int sched, int inverse, hipStream_t s, bool dry = false);
 template <typename T>
-LaunchInfo run_zgreen(const Pipe<T>& a, int tx, hipStream_t s, bool dry = false);
+LaunchInfo run_zgreen(const Pipe<T>& a, int sched, hipStream_t s, bool dry = false);
 
 }  // namespace hom

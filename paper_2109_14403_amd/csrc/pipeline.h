@@ -495,9 +495,9 @@ __device__ __forceinline__ int xcd_remap(int i, int n) {
 // ---------------------------------------------------------------------------
 // y pass (forward or inverse) on tiles of TX kx columns
 // ---------------------------------------------------------------------------
-template <typename T, int C, int N, int TX>
-__global__ void __launch_bounds__((N / Plan<N>::M) * TX * C) k_ypass(Pipe<T> a, int inverse) {
-  constexpr int M = Plan<N>::M;
+template <typename T, int C, int N, int TX, int V>
+__global__ void __launch_bounds__((N / Plan<N, V>::M) * TX * C) k_ypass(Pipe<T> a, int inverse) {
+  constexpr int M = Plan<N, V>::M;
   constexpr int G = N / M;
   constexpr int L = TX * C;
   static_assert(tile_lds_elems<N, TX, C>() - N >= N * L, "tile LDS buffer too small");
@@ -529,7 +529,7 @@ __global__ void __launch_bounds__((N / Plan<N>::M) * TX * C) k_ypass(Pipe<T> a, 
     c2<T> v = active ? base[(t + G * m) * stride] : mk(T(0), T(0));
     r[m] = inverse ? conjg(v) : v;
   }
-  Plan<N>::run(r, t, tw, buf, L, l, active);
+  Plan<N, V>::run(r, t, tw, buf, L, l, active);
   if (active) {
 #pragma unroll
     for (int m = 0; m < M; ++m) base[(t + G * m) * stride] = inverse ? conjg(r[m]) : r[m];
@@ -539,10 +539,10 @@ __global__ void __launch_bounds__((N / Plan<N>::M) * TX * C) k_ypass(Pipe<T> a, 
 // ---------------------------------------------------------------------------
 // z forward + Green operator + z inverse on tiles of TX kx columns
 // ---------------------------------------------------------------------------
-template <typename T, int C, int N, int TX>
-__global__ void __launch_bounds__((N / Plan<N>::M) * TX * C)
+template <typename T, int C, int N, int TX, int V>
+__global__ void __launch_bounds__((N / Plan<N, V>::M) * TX * C)
     __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 5 : 1))) k_zgreen(Pipe<T> a) {
-  constexpr int M = Plan<N>::M;
+  constexpr int M = Plan<N, V>::M;
   constexpr int G = N / M;
   constexpr int L = TX * C;
   static_assert(tile_lds_elems<N, TX, C>() - N >= N * L, "tile LDS buffer too small");
@@ -596,7 +596,7 @@ __global__ void __launch_bounds__((N / Plan<N>::M) * TX * C)
   __syncthreads();
 #pragma unroll
   for (int m = 0; m < M; ++m) r[m] = active ? base[(t + G * m) * stride] : mk(T(0), T(0));
-  Plan<N>::run(r, t, tw, buf, L, l, active);
+  Plan<N, V>::run(r, t, tw, buf, L, l, active);
   __syncthreads();
 #pragma unroll
   for (int m = 0; m < M; ++m) buf[(t + G * m) * L + l] = r[m];
@@ -618,7 +618,7 @@ __global__ void __launch_bounds__((N / Plan<N>::M) * TX * C)
   const T fb = frequency_component<T>(ky, a.ny, T(a.ilen[1]));
   const T fab2 = fa * fa + fb * fb;
   const T il2 = T(a.ilen[2]);
-  static_assert(((N / Plan<N>::M) * TX * C) % TX == 0, "thread count must be a multiple of TX");
+  static_assert(((N / Plan<N, V>::M) * TX * C) % TX == 0, "thread count must be a multiple of TX");
   for (int idx = tid; idx < N * TX; idx += nth) {
     const int kz = idx / TX;
     const int kxi = idx - kz * TX;
@@ -672,7 +672,7 @@ __global__ void __launch_bounds__((N / Plan<N>::M) * TX * C)
   __syncthreads();
 #pragma unroll
   for (int m = 0; m < M; ++m) r[m] = conjg(buf[(t + G * m) * L + l]);
-  Plan<N>::run(r, t, tw, buf, L, l, active);
+  Plan<N, V>::run(r, t, tw, buf, L, l, active);
   if (active) {
 #pragma unroll
     for (int m = 0; m < M; ++m) base[(t + G * m) * stride] = conjg(r[m]);

@@ -75,14 +75,18 @@ class BatchImpl {
   virtual void set_laws(const hom_law* laws, int n) = 0;
   virtual const Profiler& profiler() const = 0;
   virtual void set_profiling(bool on) = 0;
+  // per grid group: nx, ny, nz and the schedules of the y and z passes of the
+  // mechanics and the conduction; returns the number of groups
+  virtual int schedules(int32_t* out, int cap) const = 0;
   std::string err;
 };
 
 std::unique_ptr<BatchImpl> make_batch(int nprob, const hom_grid* grids, const uint8_t* const* phases,
                                       const hom_law* laws, int nlaws, const hom_options& opts);
 
+// sched < 0: the default schedule (tile width 4, plan 0, else width 2)
 void apply_operator(const hom_grid& g, int ncomp, int op, double p0, double p1, int precision, const double* in,
-                    double* out);
+                    double* out, int sched = -1);
 void eval_law(const hom_law& law, int64_t count, const double* eps, const double* eps_n, const double* state,
               double theta, double dt, int commit, double* sigma, double* ab, double* nd, double* state_out,
               double* diss, double* coup);

@@ -223,12 +223,12 @@ LaunchInfo run_xinv(const Pipe<T>& a, hipStream_t s, bool dry) {
   HOM_DISPATCH(a.nx, (xinv_launch<T, NN>(a, s, dry)))
 }
 template <typename T>
-LaunchInfo run_ypass(const Pipe<T>& a, int tx, int inverse, hipStream_t s, bool dry) {
-  HOM_DISPATCH(a.ny, (ypass_launch<T, NN>(a, tx, inverse, s, dry)))
+LaunchInfo run_ypass(const Pipe<T>& a, int sched, int inverse, hipStream_t s, bool dry) {
+  HOM_DISPATCH(a.ny, (ypass_launch<T, NN>(a, sched, inverse, s, dry)))
 }
 template <typename T>
-LaunchInfo run_zgreen(const Pipe<T>& a, int tx, hipStream_t s, bool dry) {
-  HOM_DISPATCH(a.nz, (zgreen_launch<T, NN>(a, tx, s, dry)))
+LaunchInfo run_zgreen(const Pipe<T>& a, int sched, hipStream_t s, bool dry) {
+  HOM_DISPATCH(a.nz, (zgreen_launch<T, NN>(a, sched, s, dry)))
 }
 
 static bool launch_ok(const LaunchInfo& li) { return li.threads <= 1024 && li.lds <= 160 * 1024; }
@@ -264,7 +264,9 @@ struct Group {
   int maxblk = 0;
   double* part2 = nullptr;  // first-stage sums of a reduction over many blocks [prob][NPART][nout]
   c2<T>* tw[3] = {nullptr, nullptr, nullptr};
-  int txy[2] = {4, 4}, txz[2] = {4, 4};  // [mech, thermal]
+  // schedules of the y and z passes, [mech, thermal]: tile width + 16 x plan
+  // variant (pipe_launch.h)
+  int txy[2] = {schedule(4, 0), schedule(4, 0)}, txz[2] = {schedule(4, 0), schedule(4, 0)};
   int pt_bpp = 1;
   int cm_bpp = 1;  // blocks per problem of the once-per-increment history sums
   // internal variables and increment slots of the PA66 voxels only, compacted
@@ -505,6 +507,18 @@ class BatchT : public BatchImpl {
 
   int problems() const override { return (int)where.size(); }
 
+  int schedules(int32_t* out, int cap) const override {
+    int n = 0;
+    for (auto& gp : groups) {
+      if (n >= cap) break;
+      const auto& G = *gp;
+      const int32_t row[7] = {G.nx, G.ny, G.nz, G.txy[0], G.txz[0], G.txy[1], G.txz[1]};
+      std::memcpy(out + 7 * n, row, sizeof(row));
+      ++n;
+    }
+    return (int)groups.size();
+  }
+
   size_t device_bytes() const override {
     size_t b = 0;
     for (auto& g : groups) b += g->bytes;
@@ -613,7 +627,8 @@ class BatchT : public BatchImpl {
     HIPCHK(hipDeviceSynchronize());
   }
 
-  // time the y / z tile widths on this group's data and keep the fastest
+  // time the y / z schedules (tile width and FFT plan) on this group's data
+  // and keep the fastest
   void autotune(Group<T>& G) {
     hipStream_t stream = G.stream;  // this group's lane
     hipEvent_t e0, e1;
@@ -629,17 +644,17 @@ class BatchT : public BatchImpl {
       HIPCHK(hipMemcpy(ctl, c.data(), sizeof(Ctl) * G.nprob, hipMemcpyHostToDevice));
       Pipe<T> a = G.pipe(phys, phys == 0 ? G_PROJ : G_GRADPROJ);
       for (int pass = 0; pass < 2; ++pass) {
-        auto run = [&](int tx) { pass == 0 ? run_ypass<T>(a, tx, 0, stream) : run_zgreen<T>(a, tx, stream); };
+        auto run = [&](int sc) { pass == 0 ? run_ypass<T>(a, sc, 0, stream) : run_zgreen<T>(a, sc, stream); };
         std::vector<int> cand;
-        for (int tx : kTileChoices) {
-          LaunchInfo li = pass == 0 ? run_ypass<T>(a, tx, 0, stream, true) : run_zgreen<T>(a, tx, stream, true);
+        for (int sc : kScheduleChoices) {
+          LaunchInfo li = pass == 0 ? run_ypass<T>(a, sc, 0, stream, true) : run_zgreen<T>(a, sc, stream, true);
           if (!launch_ok(li)) continue;
-          cand.push_back(tx);
-          for (int w = 0; w < 2; ++w) run(tx);
+          cand.push_back(sc);
+          for (int w = 0; w < 2; ++w) run(sc);
         }
         // the candidates take turns over several rounds (in alternating
         // order, so clock ramps and neighbours favour none), each keeping its
-        // fastest round: one noisy timing does not decide the tile
+        // fastest round: one noisy timing does not decide the schedule
         std::vector<float> best(cand.size(), 1e30f);
         for (int round = 0; round < 5; ++round)
           for (size_t j = 0; j < cand.size(); ++j) {
@@ -652,7 +667,7 @@ class BatchT : public BatchImpl {
             HIPCHK(hipEventElapsedTime(&t, e0, e1));
             best[i] = std::min(best[i], t);
           }
-        int bt = 4;
+        int bt = schedule(4, 0);
         float bmin = 1e30f;
         for (size_t i = 0; i < cand.size(); ++i)
           if (best[i] < bmin) {
@@ -673,10 +688,10 @@ class BatchT : public BatchImpl {
     hipStream_t stream = G.stream;  // this group's lane
     Pipe<T> a = G.pipe(phys, 0);
     for (int pass = 0; pass < 2; ++pass) {
-      int& tx = (pass == 0 ? G.txy : G.txz)[phys];
-      LaunchInfo li = pass == 0 ? run_ypass<T>(a, tx, 0, stream, true) : run_zgreen<T>(a, tx, stream, true);
-      if (!launch_ok(li)) tx = 2;
-      li = pass == 0 ? run_ypass<T>(a, tx, 0, stream, true) : run_zgreen<T>(a, tx, stream, true);
+      int& sc = (pass == 0 ? G.txy : G.txz)[phys];
+      LaunchInfo li = pass == 0 ? run_ypass<T>(a, sc, 0, stream, true) : run_zgreen<T>(a, sc, stream, true);
+      if (!launch_ok(li)) sc = schedule(2, 0);
+      li = pass == 0 ? run_ypass<T>(a, sc, 0, stream, true) : run_zgreen<T>(a, sc, stream, true);
       if (!launch_ok(li)) fail(HOM_E_UNSUPPORTED, "no valid tile for this grid");
     }
     LaunchInfo lx = run_xfwd<T>(a, stream, true);
@@ -1332,7 +1347,7 @@ std::unique_ptr<BatchImpl> make_batch(int nprob, const hom_grid* grids, const ui
 // ---------------------------------------------------------------------------
 template <typename T>
 static void apply_operator_t(const hom_grid& g, int ncomp, int op, double p0, double p1, const double* in,
-                             double* out) {
+                             double* out, int sched) {
   Group<T> G;
   G.nx = g.n[0];
   G.ny = g.n[1];
@@ -1359,8 +1374,13 @@ static void apply_operator_t(const hom_grid& g, int ncomp, int op, double p0, do
   a.C = ncomp;
   a.ctl = G.ctl_m;
   hipStream_t s = nullptr;
-  int tx = 4;
-  if (!launch_ok(run_zgreen<T>(a, tx, s, true))) tx = 2;
+  int tx = sched;
+  if (sched < 0) {
+    tx = schedule(4, 0);
+    if (!launch_ok(run_zgreen<T>(a, tx, s, true))) tx = schedule(2, 0);
+  } else if (!launch_ok(run_zgreen<T>(a, tx, s, true)) || !launch_ok(run_ypass<T>(a, tx, 0, s, true))) {
+    fail(HOM_E_UNSUPPORTED, "schedule does not fit the work-group limits on this grid");
+  }
   (void)hipGetLastError();
   run_xfwd<T>(a, s);
   hip_check(hipGetLastError(), "xfwd launch");
@@ -1377,7 +1397,12 @@ static void apply_operator_t(const hom_grid& g, int ncomp, int op, double p0, do
 }
 
 void apply_operator(const hom_grid& g, int ncomp, int op, double p0, double p1, int precision, const double* in,
-                    double* out) {
+                    double* out, int sched) {
+  if (sched >= 0) {
+    bool known = false;
+    for (int sc : kScheduleChoices) known = known || sc == sched;
+    if (!known) fail(HOM_E_ARG, "unknown schedule");
+  }
   for (int d = 0; d < 3; ++d)
     if (!supported_n(g.n[d])) fail(HOM_E_UNSUPPORTED, "unsupported grid size");
   if (!((ncomp == 6 && (op == G_PROJ || op == G_GAMMA0 || op == G_PROJ_ROT)) ||
@@ -1386,9 +1411,9 @@ void apply_operator(const hom_grid& g, int ncomp, int op, double p0, double p1, 
   if (op == G_GAMMA0 && !(p1 > 0.0 && p0 + 2.0 * p1 > 0.0)) fail(HOM_E_ARG, "invalid reference medium");
   if (op == G_GAMMA_TH && !(p0 > 0.0)) fail(HOM_E_ARG, "invalid reference conductivity");
   if (precision == HOM_FP64)
-    apply_operator_t<double>(g, ncomp, op, p0, p1, in, out);
+    apply_operator_t<double>(g, ncomp, op, p0, p1, in, out, sched);
   else if (precision == HOM_FP32)
-    apply_operator_t<float>(g, ncomp, op, p0, p1, in, out);
+    apply_operator_t<float>(g, ncomp, op, p0, p1, in, out, sched);
   else
     fail(HOM_E_ARG, "unknown precision");
 }

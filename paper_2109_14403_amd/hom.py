@@ -212,7 +212,8 @@ EXPORTS = (
     "hom_set_laws", "hom_batch_set_laws",
     "hom_last_error", "hom_destroy",
     "hom_batch_setup", "hom_batch_solve_increment", "hom_batch_kernel_stats", "hom_batch_last_error",
-    "hom_batch_destroy", "hom_apply_operator", "hom_eval_law",
+    "hom_batch_destroy", "hom_batch_schedules", "hom_schedules", "hom_apply_operator", "hom_apply_operator_schedule",
+    "hom_eval_law",
     "hom_dmn_default_train_opts", "hom_dmn_create", "hom_dmn_get_params", "hom_dmn_set_params",
     "hom_dmn_homogenize", "hom_dmn_loss_grad", "hom_dmn_train", "hom_dmn_last_error", "hom_dmn_destroy",
     "hom_dmn_online_create", "hom_dmn_online_step", "hom_dmn_online_set_predictor", "hom_dmn_online_last_error",
@@ -284,6 +285,10 @@ def library(path: str | None = None):
     lib.hom_batch_destroy.restype = None
     lib.hom_apply_operator.argtypes = [ct.POINTER(Grid), ct.c_int32, ct.c_int32, ct.c_double, ct.c_double,
                                        ct.c_int32, dp, dp]
+    lib.hom_schedules.argtypes = [ct.c_void_p, ct.POINTER(ct.c_int32), ct.c_int32]
+    lib.hom_batch_schedules.argtypes = [ct.c_void_p, ct.POINTER(ct.c_int32), ct.c_int32]
+    lib.hom_apply_operator_schedule.argtypes = [ct.POINTER(Grid), ct.c_int32, ct.c_int32, ct.c_double, ct.c_double,
+                                                ct.c_int32, ct.c_int32, dp, dp]
     lib.hom_eval_law.argtypes = [ct.POINTER(Law), ct.c_int64, dp, dp, dp, ct.c_double, ct.c_double, ct.c_int32,
                                  dp, dp, dp, dp, dp, dp]
     lib.hom_dmn_default_train_opts.argtypes = [ct.POINTER(DmnTrainOpts)]
@@ -543,11 +548,30 @@ class Context(_Handle):
     def kernel_stats(self):
         return _stats(self._lib.hom_kernel_stats, self._h)
 
+    def schedules(self):
+        """The y / z pass schedules (tile width, FFT plan) the autotuner chose."""
+        return _schedules(self._lib.hom_schedules, self._h)
+
     def set_profiling(self, on: bool):
         _check(self._lib.hom_set_profiling(self._h, int(on)), self.error)
 
     def device_bytes(self):
         return int(self._lib.hom_device_bytes(self._h))
+
+
+def _schedules(fn, h):
+    cap = 16
+    buf = (ct.c_int32 * (7 * cap))()
+    n = fn(h, buf, cap)
+    if n < 0:
+        raise HomError(n, "schedule query failed")
+    keys = ("grid", "y_mech", "z_mech", "y_thermal", "z_thermal")
+    out = []
+    for g in range(min(n, cap)):
+        r = list(buf[7 * g: 7 * g + 7])
+        sched = {k: {"tile": v & 15, "plan": v >> 4} for k, v in zip(keys[1:], r[3:])}
+        out.append({"grid": r[:3], **sched})
+    return out
 
 
 def _stats(fn, h):
@@ -625,15 +649,28 @@ class Batch(_Handle):
     def kernel_stats(self):
         return _stats(self._lib.hom_batch_kernel_stats, self._h)
 
+    def schedules(self):
+        """The y / z pass schedules (tile width, FFT plan) per grid group."""
+        return _schedules(self._lib.hom_batch_schedules, self._h)
 
-def apply_operator(field, op, p0=0.0, p1=0.0, precision=FP64, lengths=(1.0, 1.0, 1.0)):
-    """IFFT(Op FFT(field)) on the GPU; field (C, nz, ny, nx) float64."""
+
+# schedules of the y and z passes: tile width + 16 x FFT plan variant
+SCHEDULES = (2, 4, 8, 18, 20, 24)
+
+
+def apply_operator(field, op, p0=0.0, p1=0.0, precision=FP64, lengths=(1.0, 1.0, 1.0), schedule=None):
+    """IFFT(Op FFT(field)) on the GPU; field (C, nz, ny, nx) float64;
+    schedule: one of SCHEDULES, or None for the default."""
     lib = library()
     f = _f64(field)
     C = f.shape[0]
     g = make_grid(f.shape[1:], lengths)
     out = np.empty_like(f)
-    rc = lib.hom_apply_operator(ct.byref(g), C, op, p0, p1, precision, _dptr(f), _dptr(out))
+    if schedule is None:
+        rc = lib.hom_apply_operator(ct.byref(g), C, op, p0, p1, precision, _dptr(f), _dptr(out))
+    else:
+        rc = lib.hom_apply_operator_schedule(ct.byref(g), C, op, p0, p1, precision, int(schedule), _dptr(f),
+                                             _dptr(out))
     _check(rc, lambda: lib.hom_last_error(None).decode())
     return out
 

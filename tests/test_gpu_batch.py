@@ -89,3 +89,29 @@ def test_full_batch_in_bench_configuration_matches_oracle():
             print(f"batch of 512, problem {i} (n={n}) inc {k}: stress err {err:.2e}", flush=True)
             assert err <= FP32_BOUND
             assert np.allclose(rb[i]["heat_flux"], o["heat_flux"], rtol=FP32_BOUND)
+
+
+def test_autotuned_schedules_are_reported_and_solve_alike():
+    """The autotuner times every y / z schedule (tile width, FFT plan) per grid
+    group and keeps the fastest; whatever it keeps, the batch solves as the
+    untuned one does (FP32 bound), and the chosen schedules are valid ones."""
+    wls = [w for w in problems(range(12)) if w.record["n"] == 24][:2]
+    wls += [w for w in problems(range(12)) if w.record["n"] == 32][:1]
+    laws = [W.pa66(), W.e_glass()]
+    opts = dict(scheme=hom.SCHEME_NEWTON_CG, precision=hom.FP32, tol=1e-6)
+    tuned = hom.Batch([w.phases for w in wls], laws, autotune=1, **opts)
+    plain = hom.Batch([w.phases for w in wls], laws, autotune=0, **opts)
+    sched = tuned.schedules()
+    print(f"autotuned schedules: {sched}", flush=True)
+    assert sorted(tuple(s["grid"]) for s in sched) == [(24, 24, 24), (32, 32, 32)]
+    for s in sched:
+        for k in ("y_mech", "z_mech", "y_thermal", "z_thermal"):
+            assert s[k]["tile"] in (2, 4, 8) and s[k]["plan"] in (0, 1)
+    for s in plain.schedules():
+        assert all(s[k] == {"tile": 4, "plan": 0} for k in ("y_mech", "z_mech", "y_thermal", "z_thermal"))
+    st = [w.history[0] for w in wls]
+    args = (np.array([h.strain for h in st]), [h.theta for h in st], [h.grad for h in st], [h.dt for h in st])
+    rt, rp = tuned.solve_increment(*args), plain.solve_increment(*args)
+    for a, b in zip(rt, rp):
+        assert a["status"] == 0 and b["status"] == 0
+        assert np.abs(a["stress"] - b["stress"]).max() <= 2 * FP32_BOUND * np.abs(b["stress"]).max()

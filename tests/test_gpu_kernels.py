@@ -63,6 +63,38 @@ def test_long_plans_match_oracle(shape, precision, op, p0, C):
     assert err <= TOL[precision]
 
 
+# every y / z schedule the autotuner may pick (tile width x FFT plan variant)
+# on every transform length, the length on the y and the z axis in turn
+PLAN_SHAPES = [(16, 24, 16), (24, 16, 16), (32, 48, 16), (48, 32, 16), (64, 96, 16), (96, 64, 16),
+               (128, 16, 24), (16, 128, 24), (256, 16, 16), (16, 256, 16)]
+
+
+@pytest.mark.parametrize("shape", PLAN_SHAPES)
+@pytest.mark.parametrize("precision", [hom.FP64, hom.FP32])
+def test_every_schedule_matches_oracle(shape, precision):
+    rng = np.random.default_rng(sum(shape) * 11 + precision)
+    lengths = (1.1, 0.9, 1.0)
+    for op, p0, C in ((hom.OP_PROJECTOR, 0, 6), (hom.OP_GAMMA_CONDUCTION, 0.6, 3)):
+        f = rng.normal(size=(C,) + shape) + 0.25
+        ref = oracle_apply(f, op, p0, 0.0, lengths)
+        for sc in hom.SCHEDULES:
+            try:
+                gpu = hom.apply_operator(f, op, p0, 0.0, precision=precision, lengths=lengths, schedule=sc)
+            except hom.HomError as e:  # a tile wider than the work-group limits allow on this grid
+                assert e.code == hom.HOM_E_UNSUPPORTED
+                continue
+            err = np.abs(gpu - ref).max() / np.abs(ref).max()
+            print(f"schedule {sc} {shape} op {op} precision {precision}: max rel err {err:.2e}", flush=True)
+            assert err <= TOL[precision]
+
+
+def test_schedule_argument_errors():
+    f = np.zeros((6, 16, 16, 16))
+    with pytest.raises(hom.HomError) as e:
+        hom.apply_operator(f, hom.OP_PROJECTOR, schedule=5)
+    assert e.value.code == hom.HOM_E_ARG
+
+
 def test_projector_output_is_compatible_and_idempotent():
     rng = np.random.default_rng(1)
     f = rng.normal(size=(6, 16, 24, 32))
