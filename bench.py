@@ -91,11 +91,14 @@ def solve_bytes(n, fp_bytes, matrix_fraction, n_state, n_eval, n_cg, n_first, in
         "ypass": 2 * launches * algorithmic_bytes("yfwd", n, fp_bytes, matrix_fraction)[0],
         "zgreen": launches * algorithmic_bytes("zgreen", n, fp_bytes, matrix_fraction)[0],
         "xinv": launches * algorithmic_bytes("xinv", n, fp_bytes, matrix_fraction)[0],
-        "eval": n_eval * ev,
+        # every evaluation after an increment's first applies the last CG step
+        # x += alpha p first: read p, write x
+        "eval": n_eval * ev + (n_eval - increments) * 2 * field,
         # x = x^n + dE: read x^n, write x
         "init": increments * 2 * field,
-        # read the viscous strains of the branches, write 8 FP64 slots
-        "history": increments * (mv * ((n_state - 7) * 8 + 8 * 8) + v),
+        # read the viscous strains of the branches, write 8 FP64 slots (the
+        # PA66 voxels' compacted arrays: no phase test)
+        "history": increments * (mv * ((n_state - 7) * 8 + 8 * 8)),
         # read x, x^n, phase, the state and the history sums; write the state, x^n, the stress
         "commit": increments * (4 * field + v + mv * (2 * n_state * 8 + 8 * 8)),
     }
@@ -122,14 +125,15 @@ def _host_info():
     return {"nproc": len(os.sched_getaffinity(0)), "cpu_model": model}
 
 
-def counter_solve_bytes(n, kstats):
-    """HBM GB that the counters measured over the replayed timed increments:
-    bytes per launch of each per-voxel kernel (profiles/<kind>_fibres<n>_pmc.json,
-    current kernel sources only) times its launches. None if one is missing."""
-    launches = {"xfwd": kstats.get("xfwd", [0])[0], "ypass": kstats.get("yfwd", [0])[0] + kstats.get("yinv", [0])[0],
-                "zgreen": kstats.get("zgreen", [0])[0], "xinv": kstats.get("xinv", [0])[0],
-                "eval": kstats.get("eval", [0])[0], "commit": kstats.get("commit", [0])[0],
-                "history": kstats.get("history", [0])[0], "init": kstats.get("init", [0])[0]}
+def counter_solve_bytes(n, n_eval, n_cg, increments):
+    """HBM GB that the counters measured, for the timed increments: bytes per
+    working launch of each mechanical kernel (profiles/<kind>_fibres<n>_pmc.json,
+    current kernel sources only) times its working launches (n_eval residual
+    evaluations, n_cg CG iterations; the evaluation launches of CG iterations
+    return at once). None if one is missing."""
+    it = n_eval + n_cg
+    launches = {"xfwd": it, "ypass": 2 * it, "zgreen": it, "xinv": it, "eval": n_eval, "commit": increments,
+                "history": increments, "init": increments}
     h = kernel_source_hash()
     tot = 0.0
     for kind, nl in launches.items():
@@ -375,16 +379,7 @@ def _per_kernel(rows, counter):
     return out
 
 
-def _timed_launches(log_path):
-    """Launches of each pipeline kernel in the timed increments of a bench run,
-    from the JSON line it printed."""
-    with open(log_path) as f:
-        line = [l for l in f if l.startswith("{") and '"metric"' in l][-1]
-    d = json.loads(line)
-    return int(round((d["newton_per_step"] + d["krylov_per_step"]) * d["steps"]))
-
-
-def pmc_summary(dirs, n, command, log_path=None):
+def pmc_summary(dirs, n, command):
     """Turn rocprofv3 --pmc runs into HBM bytes per launch of each mechanical
     pipeline kernel. dirs = (FETCH_SIZE run, WRITE_SIZE run[, request-size
     run]). Each counter is scaled by what it reads for the 1 GiB calibration
@@ -423,12 +418,10 @@ def pmc_summary(dirs, n, command, log_path=None):
     if req is not None:
         cn = calib_name(req["TCC_EA0_RDREQ_128B"])
         lines.append(f"calibration kernel read bytes by request size: {req_bytes(cn) / calib_bytes:.4f} x 1 GiB")
-    lines += ["", "MB per launch, averaged over the launches of the mechanical instance:", "",
+    lines += ["", "MB per working launch of the mechanical instance (launches that moved at least 5 % of the "
+              "kernel's largest launch; a launch of a problem that is not iterating returns at once):", "",
               "| kernel | launches | FETCH raw | WRITE raw | HBM (scaled FETCH + scaled WRITE) | reads by request size |",
               "|---|---|---|---|---|---|"]
-    last = _timed_launches(log_path) if log_path else None
-    if last:
-        lines.insert(5, f"averages over the last {last} launches of each kernel: the timed increments")
     for kind, name in PMC_KINDS.items():
         groups = [k for k in fetch if name in k and "hom::" in k]
         if not groups:
@@ -436,11 +429,12 @@ def pmc_summary(dirs, n, command, log_path=None):
         # the mechanical instance: the most launches, and the 6-component one
         # where the conduction instance has as many (init, commit)
         main_name = max(groups, key=lambda k: (len(fetch[k]), ", 6>" in k))
-        nl = last * (2 if kind == "ypass" else 1) if last else None   # the y kernel runs forward and inverse
+        fv = np.asarray(fetch[main_name], dtype=np.float64)
+        work = fv >= 0.05 * fv.max() if fv.size else fv > 0
 
         def avg(table, nm):
-            v = table.get(nm, [0.0])
-            return float(np.mean(v[-nl:] if nl else v))
+            v = np.asarray(table.get(nm, [0.0]), dtype=np.float64)
+            return float(np.mean(v[work])) if v.size == work.size else float(np.mean(v))
 
         f = avg(fetch, main_name) * 1024.0
         w = avg(write, main_name) * 1024.0
@@ -451,11 +445,13 @@ def pmc_summary(dirs, n, command, log_path=None):
                 + 128 * avg(req["TCC_EA0_RDREQ_128B"], main_name)
         rec = {"source_hash": h, "bytes_per_launch": tot, "fetch_bytes_raw": f, "write_bytes_raw": w,
                "fetch_scale": fscale, "write_scale": wscale, "read_bytes_by_request_size": rb,
-               "launches": len(fetch[main_name]), "kernel": main_name, "command": command}
+               "launches": len(fetch[main_name]), "working_launches": int(work.sum()), "kernel": main_name,
+               "command": command}
         with open(os.path.join(ROOT, "profiles", f"{kind}_fibres{n}_pmc.json"), "w") as fo:
             json.dump(rec, fo, indent=1)
         rbs = f"{rb / 1e6:.1f}" if rb is not None else "-"
-        lines.append(f"| {kind} | {len(fetch[main_name])} | {f / 1e6:.1f} | {w / 1e6:.1f} | {tot / 1e6:.1f} | {rbs} |")
+        lines.append(f"| {kind} | {int(work.sum())} of {len(fetch[main_name])} | {f / 1e6:.1f} | {w / 1e6:.1f} | "
+                     f"{tot / 1e6:.1f} | {rbs} |")
     with open(os.path.join(ROOT, "profiles", f"pipeline_fibres{n}_hbm_traffic.md"), "w") as fo:
         fo.write("\n".join(lines) + "\n")
     print("\n".join(lines))
@@ -530,6 +526,28 @@ def trace_summary(folder, log_path, n, command):
               "of the control words). The rest are the checkpoint download before the per-kernel replay "
               "and its restore, outside the timed increments."]
     with open(os.path.join(ROOT, "profiles", f"pipeline_fibres{n}_kernel_trace.md"), "w") as fo:
+        fo.write("\n".join(lines) + "\n")
+    print("\n".join(lines))
+
+
+def kernel_table(folder, out_name, title, command, note="", top=20):
+    """Top kernels of a rocprofv3 --kernel-trace --stats run as a markdown
+    table under profiles/ (calls, total, average and largest launch)."""
+    import csv
+    import glob
+    stats = list(csv.DictReader(open(glob.glob(os.path.join(folder, "**", "*kernel_stats.csv"), recursive=True)[0])))
+    homk = [r for r in stats if "hom::" in r["Name"]]
+    tot = sum(float(r["TotalDurationNs"]) for r in homk) / 1e6
+    lines = [f"# {title}", "", f"command: {command}", ""]
+    if note:
+        lines += [note, ""]
+    lines += [f"hom kernels in total: {tot:.1f} ms ({len(homk)} kernel instances); the {min(top, len(homk))} largest:",
+              "", "| kernel | calls | total ms | average us | max us |", "|---|---|---|---|---|"]
+    for r in homk[:top]:
+        name = r["Name"].replace("void ", "").replace("hom::", "").split("(")[0]
+        lines.append(f"| `{name}` | {r['Calls']} | {float(r['TotalDurationNs']) / 1e6:.1f} | "
+                     f"{float(r['AverageNs']) / 1e3:.1f} | {float(r['MaxNs']) / 1e3:.1f} |")
+    with open(os.path.join(ROOT, "profiles", out_name), "w") as fo:
         fo.write("\n".join(lines) + "\n")
     print("\n".join(lines))
 
@@ -823,19 +841,25 @@ def main():
                     help="summarize rocprofv3 --pmc output folders (FETCH_SIZE, WRITE_SIZE[, request sizes]) "
                          "into profiles/ (no GPU needed)")
     ap.add_argument("--mfma-summary", metavar="DIR", help="summarize an MFMA --pmc run into profiles/")
+    ap.add_argument("--kernel-table", nargs=3, metavar=("DIR", "OUT", "TITLE"),
+                    help="top kernels of a --kernel-trace --stats run as profiles/OUT")
+    ap.add_argument("--table-note", default="", help="paragraph under the command line of --kernel-table")
     ap.add_argument("--pass-counter-summary", metavar="DIR",
                     help="summarize a --pmc run with the LDS/VALU counters of the FFT passes into profiles/")
     ap.add_argument("--pmc-command", default="", help="command line recorded in the summary")
-    ap.add_argument("--pmc-log", help="stdout of the profiled bench run (restricts averages to its timed launches)")
     ap.add_argument("--trace-summary", nargs=2, metavar=("TRACE_DIR", "LOG"),
                     help="summarize a rocprofv3 --kernel-trace --stats run of bench.py into profiles/")
     ap.add_argument("--network-only", action="store_true", help="time the surrogate network inference alone")
     args = ap.parse_args()
     if args.pmc_summary:
-        pmc_summary(args.pmc_summary, args.n, args.pmc_command, args.pmc_log)
+        pmc_summary(args.pmc_summary, args.n, args.pmc_command)
         return
     if args.trace_summary:
         trace_summary(args.trace_summary[0], args.trace_summary[1], args.n, args.pmc_command)
+        return
+    if args.kernel_table:
+        kernel_table(args.kernel_table[0], args.kernel_table[1], args.kernel_table[2], args.pmc_command,
+                     args.table_note)
         return
     if args.mfma_summary:
         mfma_summary(args.mfma_summary, args.pmc_command)
@@ -963,7 +987,7 @@ def main():
             # (profiles/*_pmc.json of the current kernel sources), where every
             # per-voxel kernel of the increment has them; the conduction solve
             # keeps its algorithmic bytes
-            cb = counter_solve_bytes(n, kstats)
+            cb = counter_solve_bytes(n, n_eval, n_cg, args.steps)
             if cb is not None:
                 per_step = (cb + sb["conduction"]) / args.steps
                 roof["solve_frac_counters"] = round(per_step * args.steps / elapsed / HBM_PEAK_GBS, 4)
