@@ -94,6 +94,7 @@ struct Pipe {
   int PS;                   // row pitch of the spectra in kx entries: P rounded up so that a
                             // row of PS * C complex values is a whole number of 128-byte lines
   long long nvox;
+  long long vs;             // stride of the per-voxel arrays: [prob][comp][vs], vs >= nvox
   int nprob;
   int C;
   const uint8_t* phase;     // [prob][nvox]

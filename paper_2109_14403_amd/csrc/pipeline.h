@@ -294,7 +294,7 @@ __global__ void __launch_bounds__((xfwd_threads<N, NL, C>())) k_xfwd(Pipe<T> a) 
   for (int i = tid; i < N; i += nth) tw[i] = a.twx[i];
   double pcp = 0.0;  // CG: partial sum of p . C p  (= p . A p, p being compatible)
 
-  const long long nv = a.nvox;
+  const long long nv = a.vs;  // stride of the per-voxel arrays (component, problem)
   const long long fo = (long long)prob * C * nv;
   const uint8_t* phase = a.phase + (long long)prob * nv;
   const ProbInc& inc = a.inc[prob];
@@ -774,7 +774,7 @@ __global__ void __launch_bounds__((N / Plan<N>::M) * NL * ((C + 1) / 2)) k_xinv(
   for (int m = 0; m < M; ++m) buf[l * SP + t + G * m] = conjg(r[m]);
   __syncthreads();
 
-  const long long nv = a.nvox;
+  const long long nv = a.vs;  // stride of the per-voxel arrays (component, problem)
   const long long fo = (long long)prob * C * nv;
   const T scale = T(1.0 / ((double)a.nx * a.ny * a.nz));
   double s0 = 0.0, s1 = 0.0;

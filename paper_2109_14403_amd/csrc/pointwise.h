@@ -14,6 +14,7 @@ constexpr int HIST_SLOTS = 8;
 template <typename T>
 struct Pt {
   long long nvox;
+  long long vs;             // stride of the per-voxel arrays: [prob][comp][vs], vs >= nvox
   int nprob;
   int bpp;                  // blocks per problem
   const uint8_t* phase;

@@ -43,7 +43,8 @@ __global__ void __launch_bounds__(PT_THREADS) k_init(Pt<T> a, int basic, int kee
   }
   if (keep_x) return;
   const long long nv = a.nvox;
-  const long long fo = (long long)prob * C * nv;
+  const long long vs = a.vs;  // stride of the per-voxel arrays (component, problem)
+  const long long fo = (long long)prob * C * vs;
   // predictor: add s times the fluctuation that the last committed increment added
   const bool pred = C == 6 && a.dx && in.pred_s != 0.0;
   const T ps = T(in.pred_s);
@@ -52,15 +53,15 @@ __global__ void __launch_bounds__(PT_THREADS) k_init(Pt<T> a, int basic, int kee
       if (pred) {
 #pragma unroll
         for (int c = 0; c < 6; ++c)
-          a.x[fo + c * nv + v] =
-              a.xn[fo + c * nv + v] + T(in.dE[c]) + ps * (a.dx[fo + c * nv + v] - T(in.dEp[c]));
+          a.x[fo + c * vs + v] =
+              a.xn[fo + c * vs + v] + T(in.dE[c]) + ps * (a.dx[fo + c * vs + v] - T(in.dEp[c]));
       } else {
 #pragma unroll
-        for (int c = 0; c < 6; ++c) a.x[fo + c * nv + v] = a.xn[fo + c * nv + v] + T(in.dE[c]);
+        for (int c = 0; c < 6; ++c) a.x[fo + c * vs + v] = a.xn[fo + c * vs + v] + T(in.dE[c]);
       }
     } else {
 #pragma unroll
-      for (int c = 0; c < 3; ++c) a.x[fo + c * nv + v] += T(in.dG[c]);
+      for (int c = 0; c < 3; ++c) a.x[fo + c * vs + v] += T(in.dG[c]);
     }
   }
 }
@@ -77,16 +78,17 @@ __global__ void __launch_bounds__(PT_THREADS) k_eval(Pt<T> a) {
   const bool want_tan = (mode == M_EVAL);
   const ProbInc& in = a.inc[prob];
   const long long nv = a.nvox;
-  const long long fo = (long long)prob * C * nv;
-  const uint8_t* phase = a.phase + (long long)prob * nv;
+  const long long vs = a.vs;  // stride of the per-voxel arrays (component, problem)
+  const long long fo = (long long)prob * C * vs;
+  const uint8_t* phase = a.phase + (long long)prob * vs;
   for (long long v = (long long)blk * PT_THREADS + threadIdx.x; v < nv; v += (long long)a.bpp * PT_THREADS) {
     T e[C];
 #pragma unroll
     for (int c = 0; c < C; ++c) {
-      T xv = ldnt(a.x + fo + c * nv + v);
+      T xv = ldnt(a.x + fo + c * vs + v);
       if (pending) {
-        xv += alpha * ldnt(a.p + fo + c * nv + v);
-        stnt(a.x + fo + c * nv + v, xv);
+        xv += alpha * ldnt(a.p + fo + c * vs + v);
+        stnt(a.x + fo + c * vs + v, xv);
       }
       e[c] = xv;
     }
@@ -94,7 +96,7 @@ __global__ void __launch_bounds__(PT_THREADS) k_eval(Pt<T> a) {
     if constexpr (C == 6) {
       double sg[6];
       double ca, cb = 0.0;
-      const long long to = (long long)prob * 2 * nv;
+      const long long to = (long long)prob * 2 * vs;
       const bool isp = ph == in.pa_phase;
       const unsigned q = a.state ? pa_index(a.cbase + (long long)prob * ((nv + 63) >> 6), v, isp) : 0u;
       if (isp) {
@@ -110,9 +112,9 @@ __global__ void __launch_bounds__(PT_THREADS) k_eval(Pt<T> a) {
         ca = o.a;
         cb = o.b;
         if (want_tan && cb != 0.0) {
-          const long long no = (long long)prob * 6 * nv;
+          const long long no = (long long)prob * 6 * vs;
 #pragma unroll
-          for (int c = 0; c < 6; ++c) stnt(a.tn + no + c * nv + v, T(o.nd[c]));
+          for (int c = 0; c < 6; ++c) stnt(a.tn + no + c * vs + v, T(o.nd[c]));
         }
       } else {
         const PhaseInc& pi = in.ph[ph];
@@ -126,15 +128,15 @@ __global__ void __launch_bounds__(PT_THREADS) k_eval(Pt<T> a) {
         ca = pi.G2;
       }
 #pragma unroll
-      for (int c = 0; c < 6; ++c) stnt(a.f + fo + c * nv + v, T(sg[c]));
+      for (int c = 0; c < 6; ++c) stnt(a.f + fo + c * vs + v, T(sg[c]));
       if (want_tan) {
         stnt(a.tab + to + v, T(ca));
-        stnt(a.tab + to + nv + v, T(cb));
+        stnt(a.tab + to + vs + v, T(cb));
       }
     } else {
       const T kap = T(in.ph[ph].kappa);
 #pragma unroll
-      for (int c = 0; c < C; ++c) stnt(a.f + fo + c * nv + v, kap * e[c]);
+      for (int c = 0; c < C; ++c) stnt(a.f + fo + c * vs + v, kap * e[c]);
     }
   }
 }
@@ -176,8 +178,9 @@ __global__ void __launch_bounds__(PT_THREADS) k_commit(Pt<T> a) {
   if (ctl.status != 1) return;
   const ProbInc& in = a.inc[prob];
   const long long nv = a.nvox;
-  const long long fo = (long long)prob * C * nv;
-  const uint8_t* phase = a.phase + (long long)prob * nv;
+  const long long vs = a.vs;  // stride of the per-voxel arrays (component, problem)
+  const long long fo = (long long)prob * C * vs;
+  const uint8_t* phase = a.phase + (long long)prob * vs;
   const bool commit = a.commit != 0;
   double acc[NS];
 #pragma unroll
@@ -188,8 +191,8 @@ __global__ void __launch_bounds__(PT_THREADS) k_commit(Pt<T> a) {
       double e[6], en[6];
 #pragma unroll
       for (int c = 0; c < 6; ++c) {
-        e[c] = (double)a.x[fo + c * nv + v];
-        en[c] = (double)a.xn[fo + c * nv + v];
+        e[c] = (double)a.x[fo + c * vs + v];
+        en[c] = (double)a.xn[fo + c * vs + v];
       }
       double sg[6], dis = 0.0, cpl;
       const bool isp = ph == in.pa_phase;
@@ -227,20 +230,20 @@ __global__ void __launch_bounds__(PT_THREADS) k_commit(Pt<T> a) {
       if (!commit) continue;
 #pragma unroll
       for (int c = 0; c < 6; ++c) {
-        a.xn[fo + c * nv + v] = T(e[c]);  // the committed strain (exact: e was read from T)
-        a.f[fo + c * nv + v] = T(sg[c]);
+        a.xn[fo + c * vs + v] = T(e[c]);  // the committed strain (exact: e was read from T)
+        a.f[fo + c * vs + v] = T(sg[c]);
       }
       if (a.dx)
 #pragma unroll
-        for (int c = 0; c < 6; ++c) a.dx[fo + c * nv + v] = T(e[c] - en[c]);
+        for (int c = 0; c < 6; ++c) a.dx[fo + c * vs + v] = T(e[c] - en[c]);
       if (a.pv_diss) {
-        a.pv_diss[(long long)prob * nv + v] = dis;
-        a.pv_coup[(long long)prob * nv + v] = cpl;
+        a.pv_diss[(long long)prob * vs + v] = dis;
+        a.pv_coup[(long long)prob * vs + v] = cpl;
       }
     } else {
       const double kap = in.ph[ph].kappa;
 #pragma unroll
-      for (int c = 0; c < 3; ++c) acc[c] -= kap * (double)a.x[fo + c * nv + v];
+      for (int c = 0; c < 3; ++c) acc[c] -= kap * (double)a.x[fo + c * vs + v];
     }
   }
   block_sum<NS>(acc, red);
@@ -270,8 +273,9 @@ __global__ void __launch_bounds__(PT_THREADS) k_commit_vox(Pt<T> a) {
   if (ctl.status != 1) return;
   const ProbInc& in = a.inc[prob];
   const long long nv = a.nvox;
-  const long long fo = (long long)prob * 6 * nv;
-  const uint8_t* phase = a.phase + (long long)prob * nv;
+  const long long vs = a.vs;  // stride of the per-voxel arrays (component, problem)
+  const long long fo = (long long)prob * 6 * vs;
+  const uint8_t* phase = a.phase + (long long)prob * vs;
   const double k3 = pa66_k3_total(in);
   const bool commit = a.commit != 0;
   // uniform bases; the voxel is a 32-bit offset
@@ -283,8 +287,8 @@ __global__ void __launch_bounds__(PT_THREADS) k_commit_vox(Pt<T> a) {
   const double* hs = a.hist + (long long)prob * HIST_SLOTS * a.ss;
   const long long ss = a.ss;
   const int* cbase = a.cbase + (long long)prob * ((nv + 63) >> 6);
-  double* pvd = commit && a.pv_diss ? a.pv_diss + (long long)prob * nv : nullptr;
-  double* pvc = commit && a.pv_coup ? a.pv_coup + (long long)prob * nv : nullptr;
+  double* pvd = commit && a.pv_diss ? a.pv_diss + (long long)prob * vs : nullptr;
+  double* pvc = commit && a.pv_coup ? a.pv_coup + (long long)prob * vs : nullptr;
   double acc[MECH_SUMS];
 #pragma unroll
   for (int k = 0; k < MECH_SUMS; ++k) acc[k] = 0.0;
@@ -295,8 +299,8 @@ __global__ void __launch_bounds__(PT_THREADS) k_commit_vox(Pt<T> a) {
     double e[6], en[6];
 #pragma unroll
     for (int c = 0; c < 6; ++c) {
-      e[c] = (double)*pa_at(xb + c * nv, v);
-      en[c] = (double)*pa_at(xnb + c * nv, v);
+      e[c] = (double)*pa_at(xb + c * vs, v);
+      en[c] = (double)*pa_at(xnb + c * vs, v);
     }
     double sg[6], dis = 0.0, cpl;
     const double trd = (e[0] - en[0]) + (e[1] - en[1]) + (e[2] - en[2]);
@@ -345,12 +349,12 @@ __global__ void __launch_bounds__(PT_THREADS) k_commit_vox(Pt<T> a) {
     if (commit) {
 #pragma unroll
       for (int c = 0; c < 6; ++c) {
-        *pa_at(xnb + c * nv, v) = T(e[c]);  // the committed strain (exact: e was read from T)
-        *pa_at(fb + c * nv, v) = T(sg[c]);
+        *pa_at(xnb + c * vs, v) = T(e[c]);  // the committed strain (exact: e was read from T)
+        *pa_at(fb + c * vs, v) = T(sg[c]);
       }
       if (dxb)
 #pragma unroll
-        for (int c = 0; c < 6; ++c) *pa_at(dxb + c * nv, v) = T(e[c] - en[c]);
+        for (int c = 0; c < 6; ++c) *pa_at(dxb + c * vs, v) = T(e[c] - en[c]);
       if (pvd) {
         *pa_at(pvd, v) = dis;
         *pa_at(pvc, v) = cpl;
@@ -386,14 +390,15 @@ __global__ void __launch_bounds__(PT_THREADS) k_init_linear(Pt<T> a) {
     c.rr = c.alpha = c.beta = c.res = c.fnorm = c.cg_target = 0.0;
   }
   const long long nv = a.nvox;
-  const long long fo = (long long)prob * 6 * nv;
+  const long long vs = a.vs;  // stride of the per-voxel arrays (component, problem)
+  const long long fo = (long long)prob * 6 * vs;
   for (long long v = (long long)blk * PT_THREADS + threadIdx.x; v < nv; v += (long long)a.bpp * PT_THREADS) {
     if (a.x0) {  // an earlier solution of the same column: same mean, close fluctuation
 #pragma unroll
-      for (int c = 0; c < 6; ++c) stnt(a.x + fo + c * nv + v, ldnt(a.x0 + fo + c * nv + v));
+      for (int c = 0; c < 6; ++c) stnt(a.x + fo + c * vs + v, ldnt(a.x0 + fo + c * vs + v));
     } else {
 #pragma unroll
-      for (int c = 0; c < 6; ++c) stnt(a.x + fo + c * nv + v, T(in.dE[c]));
+      for (int c = 0; c < 6; ++c) stnt(a.x + fo + c * vs + v, T(in.dE[c]));
     }
   }
 }
@@ -410,22 +415,23 @@ __global__ void __launch_bounds__(PT_THREADS) k_eval_linear(Pt<T> a) {
   const T alpha = T(ctl.alpha);
   const ProbInc& in = a.inc[prob];
   const long long nv = a.nvox;
-  const long long fo = (long long)prob * 6 * nv;
-  const long long to = (long long)prob * 2 * nv;
-  const uint8_t* phase = a.phase + (long long)prob * nv;
+  const long long vs = a.vs;  // stride of the per-voxel arrays (component, problem)
+  const long long fo = (long long)prob * 6 * vs;
+  const long long to = (long long)prob * 2 * vs;
+  const uint8_t* phase = a.phase + (long long)prob * vs;
   for (long long v = (long long)blk * PT_THREADS + threadIdx.x; v < nv; v += (long long)a.bpp * PT_THREADS) {
     double e[6];
 #pragma unroll
     for (int c = 0; c < 6; ++c) {
-      T xv = ldnt(a.x + fo + c * nv + v);
+      T xv = ldnt(a.x + fo + c * vs + v);
       if (pending) {
-        xv += alpha * ldnt(a.p + fo + c * nv + v);
-        stnt(a.x + fo + c * nv + v, xv);
+        xv += alpha * ldnt(a.p + fo + c * vs + v);
+        stnt(a.x + fo + c * vs + v, xv);
       }
       e[c] = (double)xv;
     }
     const double ca = (double)ldnt(a.tab + to + v);
-    const double cb = (double)ldnt(a.tab + to + nv + v);
+    const double cb = (double)ldnt(a.tab + to + vs + v);
     const double K3 = in.ph[phase[v]].K3;
     const double tr3 = (e[0] + e[1] + e[2]) * (1.0 / 3.0);
     const double sph = (K3 - ca) * tr3;
@@ -436,7 +442,7 @@ __global__ void __launch_bounds__(PT_THREADS) k_eval_linear(Pt<T> a) {
       double nd[6], dot = 0.0;
 #pragma unroll
       for (int c = 0; c < 6; ++c) {
-        nd[c] = (double)ldnt(a.tn + fo + c * nv + v);
+        nd[c] = (double)ldnt(a.tn + fo + c * vs + v);
         dot += nd[c] * e[c];
       }
 #pragma unroll
@@ -444,10 +450,10 @@ __global__ void __launch_bounds__(PT_THREADS) k_eval_linear(Pt<T> a) {
     }
     if (a.s0) {
 #pragma unroll
-      for (int c = 0; c < 6; ++c) sg[c] += (double)ldnt(a.s0 + fo + c * nv + v);
+      for (int c = 0; c < 6; ++c) sg[c] += (double)ldnt(a.s0 + fo + c * vs + v);
     }
 #pragma unroll
-    for (int c = 0; c < 6; ++c) stnt(a.f + fo + c * nv + v, T(sg[c]));
+    for (int c = 0; c < 6; ++c) stnt(a.f + fo + c * vs + v, T(sg[c]));
   }
 }
 
@@ -465,15 +471,16 @@ __global__ void __launch_bounds__(PT_THREADS) k_partials(Pt<T> a) {
   if (a.ctl[prob].status != 1) return;
   const ProbInc& in = a.inc[prob];
   const long long nv = a.nvox;
-  const long long fo = (long long)prob * 6 * nv;
-  const uint8_t* phase = a.phase + (long long)prob * nv;
+  const long long vs = a.vs;  // stride of the per-voxel arrays (component, problem)
+  const long long fo = (long long)prob * 6 * vs;
+  const uint8_t* phase = a.phase + (long long)prob * vs;
   for (long long v = (long long)blk * PT_THREADS + threadIdx.x; v < nv; v += (long long)a.bpp * PT_THREADS) {
     const int ph = phase[v];
     double e[6], en[6];
 #pragma unroll
     for (int c = 0; c < 6; ++c) {
-      e[c] = (double)a.x[fo + c * nv + v];
-      en[c] = (double)a.xn[fo + c * nv + v];
+      e[c] = (double)a.x[fo + c * vs + v];
+      en[c] = (double)a.xn[fo + c * vs + v];
     }
     double st_[6], gd[6], hd;
     const bool isp = ph == in.pa_phase;
@@ -518,10 +525,10 @@ __global__ void __launch_bounds__(PT_THREADS) k_partials(Pt<T> a) {
     }
 #pragma unroll
     for (int c = 0; c < 6; ++c) {
-      a.dsdt[fo + c * nv + v] = T(st_[c]);
-      a.dDde[fo + c * nv + v] = T(gd[c]);
+      a.dsdt[fo + c * vs + v] = T(st_[c]);
+      a.dDde[fo + c * vs + v] = T(gd[c]);
     }
-    a.dDdt[(long long)prob * nv + v] = T(hd);
+    a.dDdt[(long long)prob * vs + v] = T(hd);
   }
 }
 
@@ -534,18 +541,19 @@ __global__ void __launch_bounds__(PT_THREADS) k_tangent_sum(Pt<T> a) {
   const int blk = blockIdx.x % a.bpp;
   if (a.ctl[prob].status != 1) return;
   const long long nv = a.nvox;
-  const long long fo = (long long)prob * 6 * nv;
+  const long long vs = a.vs;  // stride of the per-voxel arrays (component, problem)
+  const long long fo = (long long)prob * 6 * vs;
   double acc[8];
 #pragma unroll
   for (int k = 0; k < 8; ++k) acc[k] = 0.0;
   for (long long v = (long long)blk * PT_THREADS + threadIdx.x; v < nv; v += (long long)a.bpp * PT_THREADS) {
 #pragma unroll
-    for (int c = 0; c < 6; ++c) acc[c] += (double)ldnt(a.f + fo + c * nv + v);
+    for (int c = 0; c < 6; ++c) acc[c] += (double)ldnt(a.f + fo + c * vs + v);
     if (a.dDde) {
 #pragma unroll
       for (int c = 0; c < 6; ++c)
-        acc[6] += (double)ldnt(a.dDde + fo + c * nv + v) * (double)ldnt(a.x + fo + c * nv + v);
-      acc[7] += (double)ldnt(a.dDdt + (long long)prob * nv + v);
+        acc[6] += (double)ldnt(a.dDde + fo + c * vs + v) * (double)ldnt(a.x + fo + c * vs + v);
+      acc[7] += (double)ldnt(a.dDdt + (long long)prob * vs + v);
     }
   }
   block_sum<8>(acc, red);
