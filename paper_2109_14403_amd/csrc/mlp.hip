@@ -220,6 +220,50 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) k
         acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(xh, bl, acc, 0, 0, 0);
       }
     }
+    // gated cubic skip, sk = c + sum_g s_g(x) (G_g . x), on the matrix cores:
+    // for every gate polynomial s_g the 16 rows x 16 outputs of G_g . x in one
+    // tile whose layout matches acc (x and G split into bf16 hi + lo parts,
+    // three products: about 16 significant bits)
+    floatx4_t sk = floatx4_t{0.f, 0.f, 0.f, 0.f};
+    if (a.y) {  // uniform over the work-group
+      bf16x8_t xh, xl;
+#pragma unroll
+      for (int j = 0; j < 8; ++j) {
+        const float v = xin[(wave * 16 + lrow) * (MLP_IN + 1) + kq + j];
+        xh[j] = (__bf16)v;
+        xl[j] = (__bf16)(v - (float)xh[j]);
+      }
+      float sg[4][MLP_GATES];  // the gate polynomials of this lane's four rows
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const float* xr = xin + (wave * 16 + (lane >> 4) * 4 + i) * (MLP_IN + 1);
+        const float va = xr[a.g0], vb = xr[a.g1], vc = xr[a.g2];
+        const float s[MLP_GATES] = {1.f, va, va * va, va * va * va, vb, vb * vb, vb * vb * vb,
+                                    vc, vc * vc, vc * vc * vc};
+#pragma unroll
+        for (int gi = 0; gi < MLP_GATES; ++gi) sg[i][gi] = s[gi];
+      }
+      const float* Gb = a.skip + (size_t)lrow * MLP_GATES * MLP_IN + kq;  // output lrow, inputs kq ..
+#pragma unroll
+      for (int gi = 0; gi < MLP_GATES; ++gi) {
+        bf16x8_t gh, gl;
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+          const float g = Gb[gi * MLP_IN + j];
+          gh[j] = (__bf16)g;
+          gl[j] = (__bf16)(g - (float)gh[j]);
+        }
+        floatx4_t t = floatx4_t{0.f, 0.f, 0.f, 0.f};
+        t = __builtin_amdgcn_mfma_f32_16x16x32_bf16(xh, gh, t, 0, 0, 0);
+        t = __builtin_amdgcn_mfma_f32_16x16x32_bf16(xl, gh, t, 0, 0, 0);
+        t = __builtin_amdgcn_mfma_f32_16x16x32_bf16(xh, gl, t, 0, 0, 0);
+#pragma unroll
+        for (int i = 0; i < 4; ++i) sk[i] += sg[i][gi] * t[i];
+      }
+      const float c = a.skip[MLP_OUT * MLP_GATES * MLP_IN + lrow];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) sk[i] += c;
+    }
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
       const int m = wave * 16 + (lane >> 4) * 4 + i;
@@ -227,21 +271,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) k
       if (gr >= a.n) continue;
       const float z = acc[i] + a.bias[l][lrow];
       if (SAVE) a.yhat[gr * MLP_OUT + lrow] = z;
-      if (a.y && lrow < a.n_out) {
-        const float* xr = xin + m * (MLP_IN + 1);
-        const float va = xr[a.g0], vb = xr[a.g1], vc = xr[a.g2];
-        const float s[MLP_GATES] = {1.f, va, va * va, va * va * va, vb, vb * vb, vb * vb * vb,
-                                    vc, vc * vc, vc * vc * vc};
-        float sk = a.skip[MLP_OUT * MLP_GATES * MLP_IN + lrow];
-        const float* G = a.skip + (size_t)lrow * MLP_GATES * MLP_IN;
-#pragma unroll
-        for (int gi = 0; gi < MLP_GATES; ++gi) {
-          float t = 0.f;
-          for (int k = 0; k < MLP_IN; ++k) t += G[gi * MLP_IN + k] * xr[k];
-          sk += s[gi] * t;
-        }
-        a.y[gr * a.n_out + lrow] = z * a.ystd[lrow] + a.ymean[lrow] + sk;
-      }
+      if (a.y && lrow < a.n_out) a.y[gr * a.n_out + lrow] = z * a.ystd[lrow] + a.ymean[lrow] + sk[i];
     }
   }
 }
