@@ -1,8 +1,8 @@
 // Surrogate network: n_in (<= 32) -> 4 x 256 (GELU) -> n_out (<= 16).
 //
-// Forward: one work-group of 4 waves per 64 rows; every layer is a
-// [64 x K] x [K x 256] product on the bf16 matrix cores
-// (v_mfma_f32_16x16x32_bf16, FP32 accumulation). Weights are bf16; the
+// Forward: one work-group of 8 waves per 64 rows (each wave all 64 rows x
+// 32 output columns); every layer is a [64 x K] x [K x 256] product on the
+// bf16 matrix cores (v_mfma_f32_16x16x32_bf16, FP32 accumulation). Weights are bf16; the
 // activations are kept in LDS split into bf16 hi + lo parts (two MFMAs per
 // tile), so the product sees the activations to ~16 significant bits. In "precise" mode the
 // weights are split as well (three MFMAs: a_hi w_hi + a_lo w_hi + a_hi w_lo),
@@ -33,10 +33,14 @@ namespace hom {
 
 typedef __bf16 bf16x8_t __attribute__((ext_vector_type(8)));
 typedef __bf16 bf16x4_t __attribute__((ext_vector_type(4)));
+typedef __bf16 bf16x2_t __attribute__((ext_vector_type(2)));
 typedef float floatx4_t __attribute__((ext_vector_type(4)));
 
-constexpr int MROWS = 64;  // rows per forward work-group
-constexpr int AST = 264;   // LDS row stride of the bf16 activation tiles (16-byte aligned rows)
+constexpr int MROWS = 64;             // rows per forward work-group
+constexpr int FWD_WAVES = 8;          // waves per forward work-group
+constexpr int NRB = MROWS / 16;       // 16-row tiles per wave (every wave spans all rows)
+constexpr int NCB = MLP_W / (16 * FWD_WAVES);  // 16-column tiles per wave
+constexpr int AST = 264;              // LDS row stride of the bf16 activation tiles (16-byte aligned rows)
 
 // erf by Abramowitz and Stegun's rational approximation 7.1.26 (Handbook of
 // Mathematical Functions, 1964): erf(x) = 1 - t (a1 + t (a2 + ... + t a5))
@@ -54,9 +58,23 @@ __device__ __forceinline__ float erf_as(float x) {
   const float e = __expf(-ax * ax);
   return copysignf(fmaf(-p * t, e, 1.0f), x);
 }
-__device__ __forceinline__ float gelu_f(float z) { return 0.5f * z * (1.0f + erf_as(z * 0.70710678118654752f)); }
 __device__ __forceinline__ float gelu_prime_f(float z) {
   return 0.5f * (1.0f + erf_as(z * 0.70710678118654752f)) + z * __expf(-0.5f * z * z) * 0.39894228040143268f;
+}
+
+// The same approximation arranged for the forward pass: with x = z / sqrt 2,
+// Phi(z) = 1 - q / 2 for z >= 0 and q / 2 below, q = p(t) t exp(-x^2), so
+// GELU(z) = z Phi(z) = max(z, 0) - |z| q / 2 (no cancellation for negative z);
+// the 1 / sqrt 2 and the 1 / 2 are folded into the constants.
+__device__ __forceinline__ float gelu_fwd(float z) {
+  const float az = fabsf(z);
+  const float t = __builtin_amdgcn_rcpf(fmaf(0.2316418883f, az, 1.0f));
+  float p = fmaf(0.5307027145f, t, -0.7265760135f);
+  p = fmaf(p, t, 0.7107068705f);
+  p = fmaf(p, t, -0.142248368f);
+  p = fmaf(p, t, 0.127414796f);
+  const float e = __builtin_amdgcn_exp2f(z * z * -0.7213475204f);  // exp(-z^2 / 2)
+  return fmaf(-az, p * t * e, fmaxf(z, 0.0f));
 }
 
 struct FwdArgs {
@@ -82,7 +100,7 @@ struct FwdArgs {
 // SAVE: keep the normalized inputs, pre-activations, activations and
 // normalized outputs for the backward pass (training); inference writes y only
 template <int PRECISE, bool SAVE>
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) k_mlp_fwd(FwdArgs a) {
+__global__ void __launch_bounds__(FWD_WAVES * 64) __attribute__((amdgpu_waves_per_eu(4))) k_mlp_fwd(FwdArgs a) {
   // The tile's activations live in LDS already split into bf16 hi + lo: each
   // value is split once, by the lane that produced it, and every wave reads
   // its MFMA fragments directly.
@@ -93,7 +111,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) k
   const int wave = tid >> 6;
   const int lane = tid & 63;
   const long long row0 = (long long)blockIdx.x * MROWS;
-  for (int i = tid; i < MROWS * MLP_IN; i += 256) {
+  for (int i = tid; i < MROWS * MLP_IN; i += FWD_WAVES * 64) {
     const int r = i / MLP_IN, k = i % MLP_IN;
     const long long gr = row0 + r;
     float v = 0.0f;
@@ -112,86 +130,93 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) k
     const int K = l == 0 ? MLP_IN : MLP_W;
     const __bf16* whi = a.whi[l];
     const __bf16* wlo = a.wlo[l];
-    floatx4_t acc[4][4];
+    floatx4_t acc[NRB][NCB];
 #pragma unroll
-    for (int i = 0; i < 4; ++i)
+    for (int i = 0; i < NRB; ++i)
 #pragma unroll
-      for (int j = 0; j < 4; ++j) acc[i][j] = floatx4_t{0.f, 0.f, 0.f, 0.f};
-    bf16x8_t bh[4], bl[4];
+      for (int j = 0; j < NCB; ++j) acc[i][j] = floatx4_t{0.f, 0.f, 0.f, 0.f};
+    bf16x8_t bh[NCB], bl[NCB];
 #pragma unroll
-    for (int cb = 0; cb < 4; ++cb) {
-      const long long nn = wave * 64 + cb * 16 + lrow;
+    for (int cb = 0; cb < NCB; ++cb) {
+      const long long nn = wave * (16 * NCB) + cb * 16 + lrow;
       bh[cb] = *reinterpret_cast<const bf16x8_t*>(whi + nn * K + kq);
       if constexpr (PRECISE) bl[cb] = *reinterpret_cast<const bf16x8_t*>(wlo + nn * K + kq);
     }
     for (int k0 = 0; k0 < K; k0 += 32) {
-      bf16x8_t xh[4], xl[4];
+      bf16x8_t xh[NRB], xl[NRB];
 #pragma unroll
-      for (int rb = 0; rb < 4; ++rb) {
+      for (int rb = 0; rb < NRB; ++rb) {
         const int o = (rb * 16 + lrow) * AST + k0 + kq;
         xh[rb] = *reinterpret_cast<const bf16x8_t*>(ahi + o);
         xl[rb] = *reinterpret_cast<const bf16x8_t*>(alo + o);
       }
       // weights of the next k-step in flight during this step's products
       const int k1 = k0 + 32 < K ? k0 + 32 : k0;
-      bf16x8_t nh[4], nl[4];
+      bf16x8_t nh[NCB], nl[NCB];
 #pragma unroll
-      for (int cb = 0; cb < 4; ++cb) {
-        const long long nn = wave * 64 + cb * 16 + lrow;
+      for (int cb = 0; cb < NCB; ++cb) {
+        const long long nn = wave * (16 * NCB) + cb * 16 + lrow;
         nh[cb] = *reinterpret_cast<const bf16x8_t*>(whi + nn * K + k1 + kq);
         if constexpr (PRECISE) nl[cb] = *reinterpret_cast<const bf16x8_t*>(wlo + nn * K + k1 + kq);
       }
       // the transposed tile Z^T = W A^T (weights as the first operand): each
       // lane's four accumulator values are four consecutive outputs of one
       // row, stored as one 8-byte LDS write per part in the epilogue. hi and
-      // lo passes over all 16 tiles: no product waits on the previous one into
+      // lo passes over all of the wave's tiles: no product waits on the previous one into
       // the same accumulator
 #pragma unroll
-      for (int rb = 0; rb < 4; ++rb)
+      for (int rb = 0; rb < NRB; ++rb)
 #pragma unroll
-        for (int cb = 0; cb < 4; ++cb)
+        for (int cb = 0; cb < NCB; ++cb)
           acc[rb][cb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(bh[cb], xh[rb], acc[rb][cb], 0, 0, 0);
 #pragma unroll
-      for (int rb = 0; rb < 4; ++rb)
+      for (int rb = 0; rb < NRB; ++rb)
 #pragma unroll
-        for (int cb = 0; cb < 4; ++cb)
+        for (int cb = 0; cb < NCB; ++cb)
           acc[rb][cb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(bh[cb], xl[rb], acc[rb][cb], 0, 0, 0);
       if constexpr (PRECISE) {
 #pragma unroll
-        for (int rb = 0; rb < 4; ++rb)
+        for (int rb = 0; rb < NRB; ++rb)
 #pragma unroll
-          for (int cb = 0; cb < 4; ++cb)
+          for (int cb = 0; cb < NCB; ++cb)
             acc[rb][cb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(bl[cb], xh[rb], acc[rb][cb], 0, 0, 0);
       }
 #pragma unroll
-      for (int cb = 0; cb < 4; ++cb) {
+      for (int cb = 0; cb < NCB; ++cb) {
         bh[cb] = nh[cb];
         if constexpr (PRECISE) bl[cb] = nl[cb];
       }
     }
     __syncthreads();  // all waves done reading this layer's input
     // lane: row m = rb 16 + lrow, outputs nn0 .. nn0 + 3 of tile cb
-    floatx4_t bv[4];
+    floatx4_t bv[NCB];
 #pragma unroll
-    for (int cb = 0; cb < 4; ++cb)
-      bv[cb] = *reinterpret_cast<const floatx4_t*>(a.bias[l] + wave * 64 + cb * 16 + (lane >> 4) * 4);
+    for (int cb = 0; cb < NCB; ++cb)
+      bv[cb] = *reinterpret_cast<const floatx4_t*>(a.bias[l] + wave * (16 * NCB) + cb * 16 + (lane >> 4) * 4);
 #pragma unroll
-    for (int rb = 0; rb < 4; ++rb)
+    for (int rb = 0; rb < NRB; ++rb)
 #pragma unroll
-      for (int cb = 0; cb < 4; ++cb) {
+      for (int cb = 0; cb < NCB; ++cb) {
         const int m = rb * 16 + lrow;
-        const int nn0 = wave * 64 + cb * 16 + (lane >> 4) * 4;
+        const int nn0 = wave * (16 * NCB) + cb * 16 + (lane >> 4) * 4;
         floatx4_t z, g;
-        bf16x4_t h, lo;
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
           z[i] = acc[rb][cb][i] + bv[cb][i];
-          g[i] = gelu_f(z[i]);
-          h[i] = (__bf16)g[i];
-          lo[i] = (__bf16)(g[i] - (float)h[i]);
+          g[i] = gelu_fwd(z[i]);
         }
-        *reinterpret_cast<bf16x4_t*>(ahi + m * AST + nn0) = h;
-        *reinterpret_cast<bf16x4_t*>(alo + m * AST + nn0) = lo;
+        unsigned hp[2], lp[2];
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+          const bf16x2_t hh = {(__bf16)g[2 * j], (__bf16)g[2 * j + 1]};
+          hp[j] = __builtin_bit_cast(unsigned, hh);
+          const float h0 = __builtin_bit_cast(float, hp[j] << 16);
+          const float h1 = __builtin_bit_cast(float, hp[j] & 0xffff0000u);
+          const bf16x2_t ll = {(__bf16)(g[2 * j] - h0), (__bf16)(g[2 * j + 1] - h1)};
+          lp[j] = __builtin_bit_cast(unsigned, ll);
+        }
+        *reinterpret_cast<uint2*>(ahi + m * AST + nn0) = make_uint2(hp[0], hp[1]);
+        *reinterpret_cast<uint2*>(alo + m * AST + nn0) = make_uint2(lp[0], lp[1]);
         if constexpr (SAVE) {
           const long long gr = row0 + m;
           if (gr < a.n) {
@@ -203,7 +228,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) k
     __syncthreads();
   }
   // output layer: each wave 16 rows x 16 outputs
-  {
+  if (wave < MROWS / 16) {
     const int l = MLP_LAYERS - 1;
     const __bf16* whi = a.whi[l];
     const __bf16* wlo = a.wlo[l];
@@ -780,14 +805,14 @@ void Mlp::forward(const float* x, float* y, long long n, bool precise, bool save
   const unsigned blocks = (unsigned)((n + MROWS - 1) / MROWS);
   if (save) {
     if (precise)
-      hipLaunchKernelGGL((k_mlp_fwd<1, true>), dim3(blocks), dim3(256), 0, s, a);
+      hipLaunchKernelGGL((k_mlp_fwd<1, true>), dim3(blocks), dim3(FWD_WAVES * 64), 0, s, a);
     else
-      hipLaunchKernelGGL((k_mlp_fwd<0, true>), dim3(blocks), dim3(256), 0, s, a);
+      hipLaunchKernelGGL((k_mlp_fwd<0, true>), dim3(blocks), dim3(FWD_WAVES * 64), 0, s, a);
   } else {
     if (precise)
-      hipLaunchKernelGGL((k_mlp_fwd<1, false>), dim3(blocks), dim3(256), 0, s, a);
+      hipLaunchKernelGGL((k_mlp_fwd<1, false>), dim3(blocks), dim3(FWD_WAVES * 64), 0, s, a);
     else
-      hipLaunchKernelGGL((k_mlp_fwd<0, false>), dim3(blocks), dim3(256), 0, s, a);
+      hipLaunchKernelGGL((k_mlp_fwd<0, false>), dim3(blocks), dim3(FWD_WAVES * 64), 0, s, a);
   }
 }
 
