@@ -19,6 +19,7 @@
 #include <cstring>
 #include <mutex>
 #include <random>
+#include <type_traits>
 #include <vector>
 
 #include "mlp.h"
@@ -86,6 +87,8 @@ struct FwdArgs {
   const float* ymean;
   const float* ystd;
   const float* skip;  // G [16][MLP_GATES][32], c [16]
+  const __bf16* skip_hi;  // G rounded to bf16
+  const __bf16* skip_lo;  // the remainder G - hi, rounded to bf16
   int g0, g1, g2;     // gate input indices
   const __bf16* whi[MLP_LAYERS];
   const __bf16* wlo[MLP_LAYERS];
@@ -130,11 +133,13 @@ __global__ void __launch_bounds__(FWD_WAVES * 64) __attribute__((amdgpu_waves_pe
     const int K = l == 0 ? MLP_IN : MLP_W;
     const __bf16* whi = a.whi[l];
     const __bf16* wlo = a.wlo[l];
+    // lane: row m = rb 16 + lrow, outputs nn0 .. nn0 + 3 of tile cb; the
+    // bias enters as the first product's accumulator input
+    floatx4_t bv[NCB];
+#pragma unroll
+    for (int cb = 0; cb < NCB; ++cb)
+      bv[cb] = *reinterpret_cast<const floatx4_t*>(a.bias[l] + wave * (16 * NCB) + cb * 16 + (lane >> 4) * 4);
     floatx4_t acc[NRB][NCB];
-#pragma unroll
-    for (int i = 0; i < NRB; ++i)
-#pragma unroll
-      for (int j = 0; j < NCB; ++j) acc[i][j] = floatx4_t{0.f, 0.f, 0.f, 0.f};
     bf16x8_t bh[NCB], bl[NCB];
 #pragma unroll
     for (int cb = 0; cb < NCB; ++cb) {
@@ -142,7 +147,8 @@ __global__ void __launch_bounds__(FWD_WAVES * 64) __attribute__((amdgpu_waves_pe
       bh[cb] = *reinterpret_cast<const bf16x8_t*>(whi + nn * K + kq);
       if constexpr (PRECISE) bl[cb] = *reinterpret_cast<const bf16x8_t*>(wlo + nn * K + kq);
     }
-    for (int k0 = 0; k0 < K; k0 += 32) {
+    const auto step = [&](int k0, auto first) {
+      constexpr bool FIRST = decltype(first)::value;
       bf16x8_t xh[NRB], xl[NRB];
 #pragma unroll
       for (int rb = 0; rb < NRB; ++rb) {
@@ -162,13 +168,17 @@ __global__ void __launch_bounds__(FWD_WAVES * 64) __attribute__((amdgpu_waves_pe
       // the transposed tile Z^T = W A^T (weights as the first operand): each
       // lane's four accumulator values are four consecutive outputs of one
       // row, stored as one 8-byte LDS write per part in the epilogue. hi and
-      // lo passes over all of the wave's tiles: no product waits on the previous one into
-      // the same accumulator
+      // lo passes over all of the wave's tiles: no product waits on the
+      // previous one into the same accumulator
 #pragma unroll
       for (int rb = 0; rb < NRB; ++rb)
 #pragma unroll
-        for (int cb = 0; cb < NCB; ++cb)
-          acc[rb][cb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(bh[cb], xh[rb], acc[rb][cb], 0, 0, 0);
+        for (int cb = 0; cb < NCB; ++cb) {
+          if constexpr (FIRST)
+            acc[rb][cb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(bh[cb], xh[rb], bv[cb], 0, 0, 0);
+          else
+            acc[rb][cb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(bh[cb], xh[rb], acc[rb][cb], 0, 0, 0);
+        }
 #pragma unroll
       for (int rb = 0; rb < NRB; ++rb)
 #pragma unroll
@@ -186,13 +196,10 @@ __global__ void __launch_bounds__(FWD_WAVES * 64) __attribute__((amdgpu_waves_pe
         bh[cb] = nh[cb];
         if constexpr (PRECISE) bl[cb] = nl[cb];
       }
-    }
+    };
+    step(0, std::true_type{});
+    for (int k0 = 32; k0 < K; k0 += 32) step(k0, std::false_type{});
     __syncthreads();  // all waves done reading this layer's input
-    // lane: row m = rb 16 + lrow, outputs nn0 .. nn0 + 3 of tile cb
-    floatx4_t bv[NCB];
-#pragma unroll
-    for (int cb = 0; cb < NCB; ++cb)
-      bv[cb] = *reinterpret_cast<const floatx4_t*>(a.bias[l] + wave * (16 * NCB) + cb * 16 + (lane >> 4) * 4);
 #pragma unroll
     for (int rb = 0; rb < NRB; ++rb)
 #pragma unroll
@@ -202,7 +209,7 @@ __global__ void __launch_bounds__(FWD_WAVES * 64) __attribute__((amdgpu_waves_pe
         floatx4_t z, g;
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
-          z[i] = acc[rb][cb][i] + bv[cb][i];
+          z[i] = acc[rb][cb][i];
           g[i] = gelu_fwd(z[i]);
         }
         unsigned hp[2], lp[2];
@@ -268,16 +275,11 @@ __global__ void __launch_bounds__(FWD_WAVES * 64) __attribute__((amdgpu_waves_pe
 #pragma unroll
         for (int gi = 0; gi < MLP_GATES; ++gi) sg[i][gi] = s[gi];
       }
-      const float* Gb = a.skip + (size_t)lrow * MLP_GATES * MLP_IN + kq;  // output lrow, inputs kq ..
+      const size_t gb = (size_t)lrow * MLP_GATES * MLP_IN + kq;  // output lrow, inputs kq ..
 #pragma unroll
       for (int gi = 0; gi < MLP_GATES; ++gi) {
-        bf16x8_t gh, gl;
-#pragma unroll
-        for (int j = 0; j < 8; ++j) {
-          const float g = Gb[gi * MLP_IN + j];
-          gh[j] = (__bf16)g;
-          gl[j] = (__bf16)(g - (float)gh[j]);
-        }
+        const bf16x8_t gh = *reinterpret_cast<const bf16x8_t*>(a.skip_hi + gb + gi * MLP_IN);
+        const bf16x8_t gl = *reinterpret_cast<const bf16x8_t*>(a.skip_lo + gb + gi * MLP_IN);
         floatx4_t t = floatx4_t{0.f, 0.f, 0.f, 0.f};
         t = __builtin_amdgcn_mfma_f32_16x16x32_bf16(xh, gh, t, 0, 0, 0);
         t = __builtin_amdgcn_mfma_f32_16x16x32_bf16(xl, gh, t, 0, 0, 0);
@@ -516,7 +518,8 @@ Mlp::Mlp(int n_in_, int n_out_, uint64_t seed) : n_in(n_in_), n_out(n_out_) {
   alloc((void**)&hi, npad * 2);
   alloc((void**)&lo, npad * 2);
   alloc((void**)&scal, 5 * MLP_OUT * 4 + 2 * MLP_IN * 4);
-  alloc((void**)&skip, (MLP_OUT * MLP_GATES * MLP_IN + MLP_OUT) * 4);
+  // G and c in FP32, then G's bf16 hi and lo parts
+  alloc((void**)&skip, (MLP_OUT * MLP_GATES * MLP_IN + MLP_OUT) * 4 + 2 * MLP_OUT * MLP_GATES * MLP_IN * 2);
   // He initialization (normal, std sqrt(2 / fan_in)), seeded; biases zero
   std::vector<float> hw(npad, 0.f);
   std::mt19937_64 gen(seed);
@@ -618,6 +621,22 @@ void Mlp::set_skip(const int* gates, const float* G, const float* c) {
     hskip[(size_t)n_out * MLP_GATES * n_in + j] = c[j];
   }
   HIPCHK(hipMemcpy(skip, f.data(), f.size() * 4, hipMemcpyHostToDevice));
+  // bf16 hi + lo parts of G (round to nearest even; G is finite)
+  const auto bf16_bits = [](float x) {
+    uint32_t u;
+    std::memcpy(&u, &x, 4);
+    return (uint16_t)((u + 0x7fffu + ((u >> 16) & 1u)) >> 16);
+  };
+  constexpr size_t NG = (size_t)MLP_OUT * MLP_GATES * MLP_IN;
+  std::vector<uint16_t> parts(2 * NG);
+  for (size_t i = 0; i < NG; ++i) {
+    parts[i] = bf16_bits(f[i]);
+    const uint32_t hu = (uint32_t)parts[i] << 16;
+    float h;
+    std::memcpy(&h, &hu, 4);
+    parts[NG + i] = bf16_bits(f[i] - h);
+  }
+  HIPCHK(hipMemcpy(skip + f.size(), parts.data(), parts.size() * 2, hipMemcpyHostToDevice));
 }
 
 void Mlp::normalize_row(const float* x, double* xn) const {
@@ -785,6 +804,8 @@ void Mlp::forward(const float* x, float* y, long long n, bool precise, bool save
   a.ymean = scal + 2 * MLP_IN;
   a.ystd = scal + 2 * MLP_IN + MLP_OUT;
   a.skip = skip;
+  a.skip_hi = reinterpret_cast<const __bf16*>(skip + MLP_OUT * MLP_GATES * MLP_IN + MLP_OUT);
+  a.skip_lo = a.skip_hi + MLP_OUT * MLP_GATES * MLP_IN;
   a.g0 = gate[0];
   a.g1 = gate[1];
   a.g2 = gate[2];
