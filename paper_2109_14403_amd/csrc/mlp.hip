@@ -78,6 +78,16 @@ __device__ __forceinline__ float gelu_fwd(float z) {
   return fmaf(-az, p * t * e, fmaxf(z, 0.0f));
 }
 
+// bf16 weight copies in fragment order: the 16 x 32 block of output rows
+// 16 cb .. 16 cb + 15 and inputs 32 s .. 32 s + 31 is one contiguous 1 KiB
+// fragment, lane-major (lane = 16 (k / 8 mod 4) + output mod 16, then 8
+// consecutive inputs), so a wave's B operand of one k-step is a single
+// coalesced 1 KiB load. Offset of the lane's 8 values in a layer with inner
+// dimension K:
+__host__ __device__ __forceinline__ long long frag_offset(int cb, int s, int K, int lane) {
+  return (((long long)cb * (K / 32) + s) * 64 + lane) * 8;
+}
+
 struct FwdArgs {
   const float* x;
   long long n;
@@ -143,9 +153,9 @@ __global__ void __launch_bounds__(FWD_WAVES * 64) __attribute__((amdgpu_waves_pe
     bf16x8_t bh[NCB], bl[NCB];
 #pragma unroll
     for (int cb = 0; cb < NCB; ++cb) {
-      const long long nn = wave * (16 * NCB) + cb * 16 + lrow;
-      bh[cb] = *reinterpret_cast<const bf16x8_t*>(whi + nn * K + kq);
-      if constexpr (PRECISE) bl[cb] = *reinterpret_cast<const bf16x8_t*>(wlo + nn * K + kq);
+      const long long f = frag_offset(wave * NCB + cb, 0, K, lane);
+      bh[cb] = *reinterpret_cast<const bf16x8_t*>(whi + f);
+      if constexpr (PRECISE) bl[cb] = *reinterpret_cast<const bf16x8_t*>(wlo + f);
     }
     const auto step = [&](int k0, auto first) {
       constexpr bool FIRST = decltype(first)::value;
@@ -161,9 +171,9 @@ __global__ void __launch_bounds__(FWD_WAVES * 64) __attribute__((amdgpu_waves_pe
       bf16x8_t nh[NCB], nl[NCB];
 #pragma unroll
       for (int cb = 0; cb < NCB; ++cb) {
-        const long long nn = wave * (16 * NCB) + cb * 16 + lrow;
-        nh[cb] = *reinterpret_cast<const bf16x8_t*>(whi + nn * K + k1 + kq);
-        if constexpr (PRECISE) nl[cb] = *reinterpret_cast<const bf16x8_t*>(wlo + nn * K + k1 + kq);
+        const long long f = frag_offset(wave * NCB + cb, k1 / 32, K, lane);
+        nh[cb] = *reinterpret_cast<const bf16x8_t*>(whi + f);
+        if constexpr (PRECISE) nl[cb] = *reinterpret_cast<const bf16x8_t*>(wlo + f);
       }
       // the transposed tile Z^T = W A^T (weights as the first operand): each
       // lane's four accumulator values are four consecutive outputs of one
@@ -244,11 +254,11 @@ __global__ void __launch_bounds__(FWD_WAVES * 64) __attribute__((amdgpu_waves_pe
       const int o = (wave * 16 + lrow) * AST + k0 + kq;
       const bf16x8_t xh = *reinterpret_cast<const bf16x8_t*>(ahi + o);
       const bf16x8_t xl = *reinterpret_cast<const bf16x8_t*>(alo + o);
-      const bf16x8_t bh = *reinterpret_cast<const bf16x8_t*>(whi + (long long)lrow * MLP_W + k0 + kq);
+      const bf16x8_t bh = *reinterpret_cast<const bf16x8_t*>(whi + frag_offset(0, k0 / 32, MLP_W, lane));
       acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(xh, bh, acc, 0, 0, 0);
       acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(xl, bh, acc, 0, 0, 0);
       if constexpr (PRECISE) {
-        const bf16x8_t bl = *reinterpret_cast<const bf16x8_t*>(wlo + (long long)lrow * MLP_W + k0 + kq);
+        const bf16x8_t bl = *reinterpret_cast<const bf16x8_t*>(wlo + frag_offset(0, k0 / 32, MLP_W, lane));
         acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(xh, bl, acc, 0, 0, 0);
       }
     }
@@ -439,16 +449,32 @@ __global__ void k_adam(float* w, const float* g, float* m, float* v, long long c
   w[i] -= lr * (mi / c1) / (sqrtf(vi / c2) + eps);
 }
 
-// master FP32 weights -> bf16 hi / lo copies and the effective FP32 weights
-// the forward pass uses (hi, or hi + lo in precise mode)
-__global__ void k_split(const float* w, __bf16* hi, __bf16* lo, float* eff_bf, float* eff_pr, long long count) {
+struct LayerSpans {
+  long long off[MLP_LAYERS];
+  int n[MLP_LAYERS], k[MLP_LAYERS];
+};
+
+// master FP32 weights -> bf16 hi / lo copies (weight matrices in fragment
+// order) and the effective FP32 weights the forward pass uses (hi, or hi + lo
+// in precise mode)
+__global__ void k_split(const float* w, __bf16* hi, __bf16* lo, float* eff_bf, float* eff_pr, long long count,
+                        LayerSpans ls) {
   const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= count) return;
   const float v = w[i];
   const __bf16 h = (__bf16)v;
   const __bf16 l = (__bf16)(v - (float)h);
-  hi[i] = h;
-  lo[i] = l;
+  long long d = i;  // biases and padding keep their place
+#pragma unroll
+  for (int L = 0; L < MLP_LAYERS; ++L) {
+    const long long r = i - ls.off[L];
+    if (r >= 0 && r < (long long)ls.n[L] * ls.k[L]) {
+      const int nn = (int)(r / ls.k[L]), k = (int)(r % ls.k[L]);
+      d = ls.off[L] + frag_offset(nn >> 4, k >> 5, ls.k[L], ((k & 31) >> 3) * 16 + (nn & 15)) + (k & 7);
+    }
+  }
+  hi[d] = h;
+  lo[d] = l;
   eff_bf[i] = (float)h;
   eff_pr[i] = (float)h + (float)l;
 }
@@ -560,7 +586,13 @@ void Mlp::free_work() {
 
 void Mlp::refresh(hipStream_t s) {
   const long long n = (long long)npad;
-  hipLaunchKernelGGL(k_split, dim3((n + 255) / 256), dim3(256), 0, s, w, hi, lo, eff_bf, eff_pr, n);
+  LayerSpans ls;
+  for (int l = 0; l < MLP_LAYERS; ++l) {
+    ls.off[l] = (long long)woff[l];
+    ls.n[l] = lay_n(l);
+    ls.k[l] = lay_k(l);
+  }
+  hipLaunchKernelGGL(k_split, dim3((n + 255) / 256), dim3(256), 0, s, w, hi, lo, eff_bf, eff_pr, n, ls);
 }
 
 void Mlp::set_scaling(const float* xmean, const float* xstd, const float* ymean, const float* ystd,
