@@ -9,8 +9,8 @@
 // which reproduces FP32 weights for gradient checks. Bias and GELU are fused
 // into the epilogue; the layer output stays in LDS for the next layer.
 //
-// Training: FP32 backward (tiled GEMMs for dA = dZ W and dW = dZ^T A,
-// column sums for db), weighted MSE on normalized outputs, Adam on FP32
+// Training: FP32 backward (64 x 64-tiled GEMMs on the FP32 matrix cores for
+// dA = dZ W and dW = dZ^T A, column sums for db), weighted MSE on normalized outputs, Adam on FP32
 // master weights with refreshed bf16 copies after each step.
 #include <hip/hip_runtime.h>
 #include <math.h>
@@ -333,9 +333,17 @@ __global__ void __launch_bounds__(256) k_gemm(int M, int N, int K, const float* 
     C += (long long)blockIdx.z * M * ldc;
   }
   const int tid = threadIdx.x;
-  const int tm = tid / 16, tn = tid % 16;
+  const int lane = tid & 63, wave = tid >> 6;
+  const int wm = (wave >> 1) * 32, wn = (wave & 1) * 32;  // the wave's 32 x 32 quarter of the tile
   const int m0 = blockIdx.y * 64, n0 = blockIdx.x * 64;
-  float acc[4][4] = {};
+  // FP32 matrix cores (v_mfma_f32_16x16x4_f32: exact products, FP32
+  // accumulation): lane l feeds A[l % 16][l / 16] and B[l / 16][l % 16] of a
+  // 16 x 4 x 16 step and holds C rows 4 (l / 16) .. + 3 of column l % 16
+  floatx4_t acc[2][2];
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) acc[i][j] = floatx4_t{0.f, 0.f, 0.f, 0.f};
   for (int k0 = 0; k0 < K; k0 += 16) {
     for (int i = tid; i < 16 * 64; i += 256) {
       const int kk = i / 64, mm = i % 64;
@@ -350,30 +358,33 @@ __global__ void __launch_bounds__(256) k_gemm(int M, int N, int K, const float* 
     }
     __syncthreads();
 #pragma unroll
-    for (int kk = 0; kk < 16; ++kk) {
-      float av[4], bv[4];
+    for (int ks = 0; ks < 4; ++ks) {
+      const int kk = ks * 4 + (lane >> 4);
+      float av[2], bv[2];
 #pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        av[i] = As[kk][tm * 4 + i];
-        bv[i] = Bs[kk][tn * 4 + i];
+      for (int t = 0; t < 2; ++t) {
+        av[t] = As[kk][wm + t * 16 + (lane & 15)];
+        bv[t] = Bs[kk][wn + t * 16 + (lane & 15)];
       }
 #pragma unroll
-      for (int i = 0; i < 4; ++i)
+      for (int i = 0; i < 2; ++i)
 #pragma unroll
-        for (int j = 0; j < 4; ++j) acc[i][j] += av[i] * bv[j];
+        for (int j = 0; j < 2; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[i], bv[j], acc[i][j], 0, 0, 0);
     }
     __syncthreads();
   }
 #pragma unroll
-  for (int i = 0; i < 4; ++i)
+  for (int i = 0; i < 2; ++i)
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      const int gm = m0 + tm * 4 + i, gn = n0 + tn * 4 + j;
-      if (gm < M && gn < N) {
-        float* c = C + (long long)gm * ldc + gn;
-        *c = beta == 0.f ? acc[i][j] : beta * *c + acc[i][j];
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int gm = m0 + wm + i * 16 + (lane >> 4) * 4 + r, gn = n0 + wn + j * 16 + (lane & 15);
+        if (gm < M && gn < N) {
+          float* c = C + (long long)gm * ldc + gn;
+          *c = beta == 0.f ? acc[i][j][r] : beta * *c + acc[i][j][r];
+        }
       }
-    }
 }
 
 // column sums: out[j] = sum_r in[r][j], one thread per column (fixed order)
