@@ -67,7 +67,7 @@ __global__ void __launch_bounds__(PT_THREADS) k_init(Pt<T> a, int basic, int kee
 }
 
 template <typename T, int C>
-__global__ void __launch_bounds__(PT_THREADS) k_eval(Pt<T> a) {
+__global__ void __launch_bounds__(PT_THREADS) __attribute__((amdgpu_waves_per_eu(4))) k_eval(Pt<T> a) {
   const int prob = blockIdx.x / a.bpp;
   const int blk = blockIdx.x % a.bpp;
   const Ctl& ctl = a.ctl[prob];
@@ -81,18 +81,34 @@ __global__ void __launch_bounds__(PT_THREADS) k_eval(Pt<T> a) {
   const long long vs = a.vs;  // stride of the per-voxel arrays (component, problem)
   const long long fo = (long long)prob * C * vs;
   const uint8_t* phase = a.phase + (long long)prob * vs;
-  for (long long v = (long long)blk * PT_THREADS + threadIdx.x; v < nv; v += (long long)a.bpp * PT_THREADS) {
+  const long long step = (long long)a.bpp * PT_THREADS;
+  // the next voxel's strain, CG step and phase are loaded while this voxel's
+  // internal variables are read and its law is evaluated
+  T xn[C], pn[C];
+  int phn = 0;
+  const auto fetch = [&](long long w) {
+#pragma unroll
+    for (int c = 0; c < C; ++c) {
+      xn[c] = ldnt(a.x + fo + c * vs + w);
+      pn[c] = pending ? ldnt(a.p + fo + c * vs + w) : T(0);
+    }
+    phn = phase[w];
+  };
+  long long v = (long long)blk * PT_THREADS + threadIdx.x;
+  if (v < nv) fetch(v);
+  for (; v < nv; v += step) {
     T e[C];
 #pragma unroll
     for (int c = 0; c < C; ++c) {
-      T xv = ldnt(a.x + fo + c * vs + v);
+      T xv = xn[c];
       if (pending) {
-        xv += alpha * ldnt(a.p + fo + c * vs + v);
+        xv += alpha * pn[c];
         stnt(a.x + fo + c * vs + v, xv);
       }
       e[c] = xv;
     }
-    const int ph = phase[v];
+    const int ph = phn;
+    if (v + step < nv) fetch(v + step);
     if constexpr (C == 6) {
       double sg[6];
       double ca, cb = 0.0;
