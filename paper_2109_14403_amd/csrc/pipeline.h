@@ -267,8 +267,11 @@ constexpr int xfwd_threads() {
   return items > ft ? items : ft;
 }
 
+// FP32: at most 128 VGPRs, four waves per SIMD (a few spilled values are
+// cheaper than the third of the occupancy the unbounded build gives up)
 template <typename T, int C, int N, int NL>
-__global__ void __launch_bounds__((xfwd_threads<N, NL, C>())) k_xfwd(Pipe<T> a) {
+__global__ void __launch_bounds__((xfwd_threads<N, NL, C>()))
+    __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 4 : 1))) k_xfwd(Pipe<T> a) {
   constexpr int M = Plan<N>::M;
   constexpr int G = N / M;
   constexpr int NP = (C + 1) / 2;
