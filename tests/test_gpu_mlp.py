@@ -69,6 +69,18 @@ def test_forward_bf16_matches_rounded_weight_oracle(net_and_data):
     assert err < 1e-4
 
 
+@pytest.mark.parametrize("precise", [False, True])
+def test_forward_rows_are_independent(net_and_data, precise):
+    """Each row's output depends on that row alone: the same rows give the
+    same bits whatever the batch length and wherever the 64-row tiles fall
+    (a full tile, a ragged tail, a single row, an offset start)."""
+    net, x, _, _ = net_and_data
+    full = net.forward(x, precise=precise)
+    for lo, hi in [(0, 64), (0, 70), (5, 6), (17, 333), (300, 333)]:
+        part = net.forward(np.ascontiguousarray(x[lo:hi]), precise=precise)
+        np.testing.assert_array_equal(part, full[lo:hi], err_msg=f"rows {lo}:{hi}")
+
+
 def test_gated_skip_matches_numpy(net_and_data):
     net, x, _, scal = net_and_data
     xm, xs, ym, ys, _ = scal
