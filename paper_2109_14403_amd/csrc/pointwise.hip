@@ -67,7 +67,7 @@ __global__ void __launch_bounds__(PT_THREADS) k_init(Pt<T> a, int basic, int kee
 }
 
 template <typename T, int C>
-__global__ void __launch_bounds__(PT_THREADS) __attribute__((amdgpu_waves_per_eu(4))) k_eval(Pt<T> a) {
+__global__ void __launch_bounds__(PT_THREADS) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 4 : 1))) k_eval(Pt<T> a) {
   const int prob = blockIdx.x / a.bpp;
   const int blk = blockIdx.x % a.bpp;
   const Ctl& ctl = a.ctl[prob];
